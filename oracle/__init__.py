@@ -1,0 +1,388 @@
+"""Serial CPU oracle for the parallel Glauber sweep (arXiv:1804.07250).
+
+TEST INFRASTRUCTURE ONLY: the product package never imports this module.  Only
+``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may use it.  It shares no code with the HIP path.
+
+Parts:
+  * ``liboracle.so`` (plain C, built with gcc from the ``*.c`` files here): the
+    Philox4x32-10 generator, the per-site uniform and one serial chain per model
+    (domino: the paper's T_b / T_w tilestate arrays with Rotate + Update of
+    Section 2.2; lozenge and six-vertex: full int32 heights, Section 1.2);
+  * exact threshold tables (``fractions.Fraction``): T = floor(2^32 p) with
+    p = W_up / (W_up + W_down) (heat-bath) or the lazy Metropolis pair, from the
+    weights of Section 1.1.1 (edge and volume weights) and Section 1.2 (vertex
+    weights a, b, c);
+  * the canonical hash (row digests, then one digest over them).
+"""
+from __future__ import annotations
+
+import ctypes
+import hashlib
+import os
+import subprocess
+from fractions import Fraction
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+SOURCES = ["philox.c", "domino.c", "lozenge.c", "sixvertex.c"]
+TWO32 = 1 << 32
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (-O2, serial, no OpenMP)."""
+    if not force and os.path.exists(LIB_PATH):
+        return LIB_PATH
+    srcs = [os.path.join(HERE, s) for s in SOURCES]
+    tmp = LIB_PATH + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-o", tmp] + srcs)
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = ctypes.CDLL(LIB_PATH)
+        u8p = ctypes.POINTER(ctypes.c_uint8)
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        L.or_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        L.or_site_uniform.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                      ctypes.c_uint32, ctypes.c_uint32]
+        L.or_site_uniform.restype = ctypes.c_uint32
+        L.or_set_reverse_order.argtypes = [ctypes.c_int]
+        L.or_domino_array_len.argtypes = [ctypes.c_int]
+        L.or_domino_vertex_state.argtypes = [ctypes.c_int, u8p, u8p, ctypes.c_int, ctypes.c_int]
+        L.or_domino_brick.argtypes = [ctypes.c_int, u8p, u8p]
+        L.or_domino_from_faces.argtypes = [ctypes.c_int, u8p, u8p, u8p]
+        L.or_domino_to_faces.argtypes = [ctypes.c_int, u8p, u8p, u8p]
+        L.or_domino_flip.argtypes = [ctypes.c_int, u8p, u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.or_domino_sweeps.argtypes = [ctypes.c_int, u8p, u8p, u32p, ctypes.c_int, ctypes.c_uint64,
+                                       ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p]
+        L.or_domino_observe.argtypes = [ctypes.c_int, u8p, u8p, ctypes.c_uint32, ctypes.c_void_p]
+        L.or_domino_observe.restype = ctypes.c_int64
+        L.or_lozenge_min.argtypes = [ctypes.c_int] * 3 + [i32p]
+        L.or_lozenge_max.argtypes = [ctypes.c_int] * 3 + [i32p]
+        L.or_lozenge_flip.argtypes = [ctypes.c_int] * 3 + [i32p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.or_lozenge_sweeps.argtypes = [ctypes.c_int] * 3 + [i32p, u32p, ctypes.c_int, ctypes.c_uint64,
+                                                             ctypes.c_uint32, ctypes.c_uint32,
+                                                             ctypes.c_void_p]
+        L.or_lozenge_observe.argtypes = [ctypes.c_int] * 3 + [i32p, ctypes.c_uint32, ctypes.c_void_p]
+        L.or_lozenge_observe.restype = ctypes.c_int64
+        L.or_sixv_min.argtypes = [ctypes.c_int, i32p]
+        L.or_sixv_max.argtypes = [ctypes.c_int, i32p]
+        L.or_sixv_flip.argtypes = [ctypes.c_int, i32p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.or_sixv_sweeps.argtypes = [ctypes.c_int, i32p, u32p, ctypes.c_int, ctypes.c_uint64,
+                                     ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p]
+        L.or_sixv_observe.argtypes = [ctypes.c_int, i32p, ctypes.c_uint32, ctypes.c_void_p]
+        L.or_sixv_observe.restype = ctypes.c_int64
+        _lib = L
+    return _lib
+
+
+def _p(arr, ctype):
+    return arr.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+class _Obs(ctypes.Structure):
+    _fields_ = [("obs_every", ctypes.c_uint32), ("bin", ctypes.c_uint32),
+                ("bin_sum", ctypes.POINTER(ctypes.c_uint64)),
+                ("scalar_sum", ctypes.POINTER(ctypes.c_int64)),
+                ("samples", ctypes.POINTER(ctypes.c_uint64))]
+
+
+# --------------------------------------------------------------------------- RNG
+
+def philox4x32_10(ctr, key):
+    """Philox4x32-10 (Salmon et al., SC'11) of a 4-word counter and 2-word key."""
+    c = np.asarray(ctr, dtype=np.uint32)
+    k = np.asarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().or_philox4x32_10(_p(c, ctypes.c_uint32), _p(k, ctypes.c_uint32), _p(out, ctypes.c_uint32))
+    return [int(v) for v in out]
+
+
+def set_reverse_order(rev: bool):
+    lib().or_set_reverse_order(int(rev))
+
+
+def site_uniform(seed, r, k, t, c):
+    return int(lib().or_site_uniform(seed, r, k, t, c))
+
+
+# --------------------------------------------------------------------- thresholds
+
+def _floor32(p: Fraction) -> int:
+    v = (p.numerator * TWO32) // p.denominator
+    if not 0 <= v < TWO32:
+        raise ValueError("threshold out of range")
+    return v
+
+
+def table_from_ratios(ratios, metropolis: bool):
+    """Thresholds from exact up/down weight ratios R per context.
+
+    heat-bath:        T = floor(2^32 R / (1 + R))            (new state up iff u < T)
+    lazy Metropolis:  current down: T = floor(2^32 min(1, R) / 2)
+                      current up:   T = 2^32 - floor(2^32 min(1, 1/R) / 2)
+                      laid out as [ctx*2 + current_is_up].
+    """
+    out = []
+    for R in ratios:
+        R = Fraction(R)
+        if R <= 0:
+            raise ValueError("weights must be positive")
+        if not metropolis:
+            out.append(_floor32(R / (1 + R)))
+        else:
+            out.append(_floor32(min(Fraction(1), R) / 2))
+            out.append(TWO32 - _floor32(min(Fraction(1), 1 / R) / 2))
+    return out
+
+
+def domino_ratios(kind="uniform", a=1, b=1):
+    """Up (vertical pair) / down (horizontal pair) weight ratio per context
+    2c + (x mod 2).  Two-periodic edge weights: a crossed edge weighs a when its
+    even (x+y even) endpoint has x even, b otherwise.  At an even vertex all four
+    of its edges share one weight (ratio 1); at an odd vertex with x even the
+    vertical pair crosses its E/W edges (even endpoints at odd x: weight b) and
+    the horizontal pair its N/S edges (weight a), so R = b^2/a^2; x odd: a^2/b^2."""
+    if kind == "uniform":
+        return [Fraction(1)] * 4
+    a, b = Fraction(a), Fraction(b)
+    return [Fraction(1), Fraction(1), (b * b) / (a * a), (a * a) / (b * b)]
+
+
+def lozenge_ratios(q):
+    """Volume weight q^volume: adding one cube multiplies the weight by q."""
+    return [Fraction(q)]
+
+
+def sixv_ratios(a, b, c_squared):
+    """W_up / W_down for each mask of diagonal faces at height m+1 (NE=1, NW=2,
+    SW=4, SE=8).  Corners NE and SW carry a, NW and SE carry b when not of type
+    c; a corner whose diagonal face is high is of type c in the up state only.
+    Only c^2 enters because exactly four corners change."""
+    a, b, c2 = Fraction(a), Fraction(b), Fraction(c_squared)
+    wts = [a, b, a, b]  # NE, NW, SW, SE
+    out = []
+    for mask in range(16):
+        R = Fraction(1)
+        nhigh = 0
+        for bit, w in enumerate(wts):
+            if mask >> bit & 1:
+                R /= w
+                nhigh += 1
+            else:
+                R *= w
+        # c^(nhigh - (4 - nhigh)) = (c^2)^(nhigh - 2)
+        e = nhigh - 2
+        R *= c2 ** e
+        out.append(R)
+    return out
+
+
+# --------------------------------------------------------------------- hashing
+
+def canonical_hash(arr2d: np.ndarray) -> str:
+    """SHA-256 over the concatenated SHA-256 digests of the rows of the
+    canonical export (little-endian bytes)."""
+    a = np.ascontiguousarray(arr2d)
+    h = hashlib.sha256()
+    for row in a:
+        h.update(hashlib.sha256(row.tobytes()).digest())
+    return h.hexdigest()
+
+
+# ----------------------------------------------------------------------- models
+
+class _Chain:
+    metropolis = False
+
+    def _obs(self, obs_every, bin_, nbins):
+        self.bin_sum = np.zeros(nbins, dtype=np.uint64)
+        self.scalar_sum = np.zeros(1, dtype=np.int64)
+        self.samples = np.zeros(1, dtype=np.uint64)
+        self.obs_every = obs_every
+        self.bin = bin_
+        self._o = _Obs(obs_every, bin_, _p(self.bin_sum, ctypes.c_uint64),
+                       _p(self.scalar_sum, ctypes.c_int64), _p(self.samples, ctypes.c_uint64))
+
+
+class DominoOracle(_Chain):
+    """Aztec diamond of order n; state = the paper's split tilestate arrays."""
+
+    def __init__(self, n, thr, metropolis=False, seed=0, obs_every=0, bin_=1):
+        self.n = n
+        L = lib()
+        m = L.or_domino_array_len(n)
+        self.Tb = np.zeros(m, dtype=np.uint8)
+        self.Tw = np.zeros(m, dtype=np.uint8)
+        L.or_domino_brick(n, _p(self.Tb, ctypes.c_uint8), _p(self.Tw, ctypes.c_uint8))
+        self.thr = np.asarray(thr, dtype=np.uint32)
+        self.metropolis = metropolis
+        self.seed = seed
+        self.t = 0
+        self.cells = (2 * n, 2 * n)
+        nb = -(-2 * n // bin_)
+        self._obs(obs_every, bin_, nb * nb)
+
+    def sweep(self, nsweeps):
+        lib().or_domino_sweeps(self.n, _p(self.Tb, ctypes.c_uint8), _p(self.Tw, ctypes.c_uint8),
+                               _p(self.thr, ctypes.c_uint32), int(self.metropolis), self.seed,
+                               self.t, nsweeps, ctypes.byref(self._o))
+        self.t += nsweeps
+
+    def export(self):
+        f = np.zeros((2 * self.n, 2 * self.n), dtype=np.uint8)
+        lib().or_domino_to_faces(self.n, _p(self.Tb, ctypes.c_uint8), _p(self.Tw, ctypes.c_uint8),
+                                 _p(f, ctypes.c_uint8))
+        return f
+
+    def load(self, faces):
+        f = np.ascontiguousarray(faces, dtype=np.uint8)
+        rc = lib().or_domino_from_faces(self.n, _p(f, ctypes.c_uint8), _p(self.Tb, ctypes.c_uint8),
+                                        _p(self.Tw, ctypes.c_uint8))
+        if rc != 0:
+            raise ValueError("not a domino tiling of the Aztec diamond")
+
+    def vertex_state(self, X, Y):
+        return int(lib().or_domino_vertex_state(self.n, _p(self.Tb, ctypes.c_uint8),
+                                                _p(self.Tw, ctypes.c_uint8), X, Y))
+
+    def flip(self, X, Y, up):
+        return lib().or_domino_flip(self.n, _p(self.Tb, ctypes.c_uint8), _p(self.Tw, ctypes.c_uint8),
+                                    X, Y, int(up))
+
+    def observe(self, bin_=None):
+        b = bin_ or self.bin
+        nb = -(-2 * self.n // b)
+        bs = np.zeros(nb * nb, dtype=np.uint64)
+        v = lib().or_domino_observe(self.n, _p(self.Tb, ctypes.c_uint8), _p(self.Tw, ctypes.c_uint8),
+                                    b, bs.ctypes.data)
+        return int(v), bs
+
+    def in_domain_cells(self):
+        n = self.n
+        Y, X = np.mgrid[0:2 * n, 0:2 * n]
+        return (np.abs(2 * X - 2 * n + 1) + np.abs(2 * Y - 2 * n + 1) <= 2 * n)
+
+    def sites(self):
+        """Box vertices (X, Y) that are interior (the rotation sites)."""
+        n = self.n
+        return [(X, Y) for Y in range(2 * n + 1) for X in range(2 * n + 1)
+                if abs(X - n) + abs(Y - n) <= n - 1]
+
+
+class LozengeOracle(_Chain):
+    def __init__(self, a, b, c, thr, metropolis=False, seed=0, obs_every=0, bin_=1, init="min"):
+        self.a, self.b, self.c = a, b, c
+        self.W, self.H = a + c + 1, b + c + 1
+        self.Hs = np.zeros(self.W * self.H, dtype=np.int32)
+        f = lib().or_lozenge_min if init == "min" else lib().or_lozenge_max
+        f(a, b, c, _p(self.Hs, ctypes.c_int32))
+        self.thr = np.asarray(thr, dtype=np.uint32)
+        self.metropolis = metropolis
+        self.seed = seed
+        self.t = 0
+        self.cells = (self.H, self.W)
+        self._obs(obs_every, bin_, (-(-self.W // bin_)) * (-(-self.H // bin_)))
+
+    def sweep(self, nsweeps):
+        lib().or_lozenge_sweeps(self.a, self.b, self.c, _p(self.Hs, ctypes.c_int32),
+                                _p(self.thr, ctypes.c_uint32), int(self.metropolis), self.seed,
+                                self.t, nsweeps, ctypes.byref(self._o))
+        self.t += nsweeps
+
+    def export(self):
+        return self.Hs.reshape(self.H, self.W).copy()
+
+    def load(self, Hs):
+        self.Hs[:] = np.asarray(Hs, dtype=np.int32).reshape(-1)
+
+    def flip(self, X, Y, up):
+        return lib().or_lozenge_flip(self.a, self.b, self.c, _p(self.Hs, ctypes.c_int32), X, Y, int(up))
+
+    def observe(self, bin_=None):
+        b = bin_ or self.bin
+        bs = np.zeros((-(-self.W // b)) * (-(-self.H // b)), dtype=np.uint64)
+        v = lib().or_lozenge_observe(self.a, self.b, self.c, _p(self.Hs, ctypes.c_int32), b,
+                                     bs.ctypes.data)
+        return int(v), bs
+
+    def in_domain_cells(self):
+        return self.export() != np.iinfo(np.int32).min
+
+    def sites(self):
+        a, b, c = self.a, self.b, self.c
+        out = []
+        for Y in range(self.H):
+            for X in range(self.W):
+                x, y = X - c, Y - c
+                if -c < x < a and -c < y < b and -b < x - y < a:
+                    out.append((X, Y))
+        return out
+
+
+class SixVertexOracle(_Chain):
+    def __init__(self, N, thr, metropolis=False, seed=0, obs_every=0, bin_=1, init="min"):
+        self.N = N
+        self.h = np.zeros((N + 1) * (N + 1), dtype=np.int32)
+        f = lib().or_sixv_min if init == "min" else lib().or_sixv_max
+        f(N, _p(self.h, ctypes.c_int32))
+        self.thr = np.asarray(thr, dtype=np.uint32)
+        self.metropolis = metropolis
+        self.seed = seed
+        self.t = 0
+        self.cells = (N, N)
+        self._obs(obs_every, bin_, (-(-N // bin_)) ** 2)
+
+    def sweep(self, nsweeps):
+        lib().or_sixv_sweeps(self.N, _p(self.h, ctypes.c_int32), _p(self.thr, ctypes.c_uint32),
+                             int(self.metropolis), self.seed, self.t, nsweeps, ctypes.byref(self._o))
+        self.t += nsweeps
+
+    def export(self):
+        return self.h.reshape(self.N + 1, self.N + 1).copy()
+
+    def load(self, h):
+        self.h[:] = np.asarray(h, dtype=np.int32).reshape(-1)
+
+    def flip(self, I, J, up):
+        return lib().or_sixv_flip(self.N, _p(self.h, ctypes.c_int32), I, J, int(up))
+
+    def observe(self, bin_=None):
+        b = bin_ or self.bin
+        bs = np.zeros((-(-self.N // b)) ** 2, dtype=np.uint64)
+        v = lib().or_sixv_observe(self.N, _p(self.h, ctypes.c_int32), b, bs.ctypes.data)
+        return int(v), bs
+
+    def in_domain_cells(self):
+        return np.ones((self.N, self.N), dtype=bool)
+
+    def sites(self):
+        return [(I, J) for J in range(1, self.N) for I in range(1, self.N)]
+
+
+def bin_density(bin_sum, samples, in_domain, bin_):
+    """density[bin] = bin_sum / (samples * in-domain cells of the bin); 0 for
+    bins without in-domain cells or before any sample (fp64, one division)."""
+    Hc, Wc = in_domain.shape
+    by, bx = -(-Hc // bin_), -(-Wc // bin_)
+    cnt = np.zeros((by, bx), dtype=np.float64)
+    for y in range(by):
+        for x in range(bx):
+            cnt[y, x] = in_domain[y * bin_:(y + 1) * bin_, x * bin_:(x + 1) * bin_].sum()
+    out = np.zeros((by, bx), dtype=np.float64)
+    s = np.asarray(bin_sum, dtype=np.float64).reshape(by, bx)
+    m = (cnt > 0) & (samples > 0)
+    out[m] = s[m] / (float(samples) * cnt[m])
+    return out
