@@ -1,0 +1,170 @@
+/*
+ * tilings.h -- C-ABI of the MI355X (gfx950) Glauber-sweep library for random
+ * tilings: domino tilings of Aztec diamonds, lozenge tilings of hexagons and the
+ * six-vertex model with domain-wall boundary (Keating & Sridhar, "Random Tilings
+ * with the GPU", arXiv:1804.07250).
+ *
+ * The library implements the domain-decomposed Markov chain of Section 1.1.3,
+ * eq. (1.1): the sites are coloured so that sites of one colour never
+ * interact, and one colour step applies the local move of every site of that
+ * colour at once (Section 1.1.2 "admissible clusters"; Section 1.2 for the
+ * lozenge 3-colouring and the six-vertex 4-colouring).  A sweep visits the
+ * colours 0..K-1 in order.  Every random draw is a pure function of
+ * (seed, sweep, colour, site) through Philox4x32-10, so results do not depend
+ * on how the work is tiled, launched or batched.
+ *
+ * Conventions shared by every entry point:
+ *   - all functions return a tl_status (TL_OK == 0, errors < 0) and never
+ *     throw; tl_last_error() returns a thread-local message for the last error;
+ *   - handles are not thread-safe; each sampler owns one HIP stream (its own,
+ *     or the caller's through tl_options.stream);
+ *   - sweeps are asynchronous (stream ordered); observables, export, import,
+ *     hash and sync synchronise the sampler's stream;
+ *   - host buffers are owned by the caller; device state is owned by the
+ *     library and freed by tl_sampler_destroy.
+ */
+#ifndef TILINGS_H
+#define TILINGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TL_OK = 0,
+    TL_EINVAL = -1,       /* invalid argument: shape, size, weights <= 0 or NaN, buffer size */
+    TL_EUNTILEABLE = -2,  /* the domain has no tiling */
+    TL_ENOMEM = -3,       /* device or host allocation failed */
+    TL_EBUDGET = -4,      /* request exceeds the memory budget of a server */
+    TL_EDEVICE = -5,      /* a HIP call failed (message in tl_last_error) */
+    TL_EBUSY = -6         /* result not ready yet */
+} tl_status;
+
+typedef enum { TL_DOMINO = 0, TL_LOZENGE = 1, TL_SIXVERTEX = 2 } tl_model;
+typedef enum { TL_AZTEC = 0, TL_HEXAGON = 1, TL_DWBC_SQUARE = 2 } tl_shape;
+/* Extremal start: domino MIN = all-horizontal brick tiling, MAX = all-vertical;
+ * lozenge MIN = empty box, MAX = full box; six-vertex MIN = |I-J|, MAX = N-|I+J-N|. */
+typedef enum { TL_INIT_MIN = 0, TL_INIT_MAX = 1 } tl_init;
+typedef enum { TL_HEATBATH = 0, TL_METROPOLIS = 1 } tl_rule;
+typedef enum {
+    TL_W_UNIFORM = 0,       /* all weights 1 (Section 1.1.1, last sentence) */
+    TL_W_TWO_PERIODIC = 1,  /* domino edge weights: w[0] = a, w[1] = b (see below) */
+    TL_W_VOLUME = 2,        /* lozenge volume weight q^volume: q = w[0], or w[0]/w[1] if w[1] > 0 */
+    TL_W_SIXVERTEX = 3      /* six-vertex vertex weights, squared: w[0] = a^2, w[1] = b^2, w[2] = c^2 */
+} tl_weight_kind;
+
+/* Domain (Section 1.1 "domain"; Section 1.2):
+ *   TL_DOMINO    + TL_AZTEC:       Aztec diamond of order n (faces [x,x+1]x[y,y+1]
+ *                                  with |2x+1|+|2y+1| <= 2n), 1 <= n <= 16384;
+ *   TL_LOZENGE   + TL_HEXAGON:     hexagon with sides a, b, c >= 1, a+c and b+c <= 32767;
+ *   TL_SIXVERTEX + TL_DWBC_SQUARE: N x N vertices, domain-wall boundary, 1 <= n <= 32767. */
+typedef struct {
+    int32_t model;   /* tl_model */
+    int32_t shape;   /* tl_shape */
+    int32_t n;       /* Aztec order / six-vertex N */
+    int32_t a, b, c; /* hexagon sides */
+    int32_t init;    /* tl_init */
+} tl_domain;
+
+/* Weights (Section 1.1.1 edge and volume weights; Section 1.2 vertex weights).
+ * Two-periodic: a crossed edge weighs a when its even endpoint (x+y even in
+ * centred coordinates) has x even, b otherwise.  Six-vertex: corners NE/SW of a
+ * flipped face carry a, NW/SE carry b, type-c corners carry c; a flip changes
+ * four corners, a and b each at two of them, so the chain depends on a^2, b^2
+ * and c^2 only, which are passed exactly (c = sqrt(2) as c^2 = 2).  Acceptance uses
+ * uint32 thresholds T = floor(2^32 p) (rule TL_HEATBATH: p = W_up/(W_up+W_down);
+ * TL_METROPOLIS: lazy Metropolis, p = min(1, W_new/W_old)/2). */
+typedef struct {
+    int32_t kind;  /* tl_weight_kind */
+    int32_t rule;  /* tl_rule */
+    double w[6];
+} tl_weights;
+
+typedef struct {
+    void *stream;                /* hipStream_t to run on; NULL = a stream owned by the sampler */
+    uint32_t obs_every;          /* accumulate observables after sweep t when (t+1) % obs_every == 0; 0 = never */
+    uint32_t obs_bin;            /* observable bin edge in cells (0 or 1 = per cell) */
+    uint32_t sweeps_per_launch;  /* sweeps fused in one launch of the tiled kernel; 0 = automatic */
+    uint32_t tile_rows;          /* tile height of the tiled kernel; 0 = automatic */
+    uint32_t kernel;             /* 0 = automatic, 1 = one launch per colour step, 2 = tiled multi-sweep */
+} tl_options;
+
+typedef struct tl_sampler tl_sampler;
+
+/* Observables (cells: domino faces of the 2n x 2n box, lozenge vertices of the
+ * (a+c+1) x (b+c+1) box, six-vertex vertices of the N x N grid).  Per-cell
+ * quantity: domino = face covered by a horizontal domino; lozenge = H - H_min;
+ * six-vertex = vertex of type c.  Buffers are caller-owned and may be NULL. */
+typedef struct {
+    uint64_t sweeps;        /* out: sweeps done so far */
+    uint64_t samples;       /* out: samples accumulated */
+    int64_t scalar_now;     /* out: whole-domain quantity of the current state */
+    int64_t scalar_sum;     /* out: sum of the whole-domain quantity over samples */
+    uint32_t bins_x, bins_y;/* out: bin grid */
+    uint64_t *bin_sum;      /* in/out: bins_x*bins_y sums over samples, or NULL */
+    uint64_t *bin_now;      /* in/out: bins_x*bins_y sums of the current state, or NULL */
+    double *bin_density;    /* in/out: bin_sum / (samples * in-domain cells of the bin), or NULL */
+    size_t bin_capacity;    /* in: entries available in each non-NULL buffer */
+} tl_observables;
+
+/* Create a sampler in the extremal state of dom->init, with sweep counter 0.
+ * The seed keys every draw (Philox key = (seed mod 2^32, seed >> 32)).
+ * opt may be NULL.  Errors: TL_EINVAL, TL_ENOMEM, TL_EDEVICE. */
+tl_status tl_sampler_create(const tl_domain *dom, const tl_weights *w, uint64_t seed,
+                            const tl_options *opt, tl_sampler **out);
+
+/* Enqueue n sweeps (sweeps t .. t+n-1) on the sampler's stream; returns without
+ * waiting.  sweep(a); sweep(b) gives the same state as sweep(a+b). */
+tl_status tl_sampler_sweep(tl_sampler *s, uint64_t n);
+
+/* Wait for the sampler's stream. */
+tl_status tl_sampler_sync(tl_sampler *s);
+
+/* Observables of the current state and the accumulated samples (synchronous). */
+tl_status tl_sampler_observables(tl_sampler *s, tl_observables *out);
+
+/* Size in bytes of the canonical export, and its row layout (rows x row_bytes):
+ * domino uint8 per face of the 2n x 2n box (partner 0:N 1:S 2:E 3:W, 0xFF
+ * outside); lozenge int32 H per vertex of the sheared box (INT32_MIN outside);
+ * six-vertex int32 h per face of the (N+1)^2 box.  Row 0 is the southmost. */
+tl_status tl_sampler_export_size(const tl_sampler *s, size_t *bytes, uint32_t *rows, uint32_t *row_bytes);
+
+/* Copy the canonical export of the current state into a host buffer of at
+ * least export_size bytes (synchronous); *sweep_out (nullable) = sweeps done. */
+tl_status tl_sampler_export(tl_sampler *s, void *host, size_t bytes, uint64_t *sweep_out);
+
+/* Canonical hash of the current state: SHA-256 over the SHA-256 digests of the
+ * export's rows, computed on the device except for the last 32*rows bytes. */
+tl_status tl_sampler_hash(tl_sampler *s, uint8_t digest[32]);
+
+/* Replace the state by a canonical export (validated on the host: TL_EINVAL if
+ * it is not a state of the domain) and set the sweep counter. */
+tl_status tl_sampler_import(tl_sampler *s, const void *host, size_t bytes, uint64_t sweep);
+
+/* Free the sampler and its device memory. */
+tl_status tl_sampler_destroy(tl_sampler *s);
+
+/* Number of sites (rotation locations) and colour classes of the sampler. */
+tl_status tl_sampler_info(const tl_sampler *s, uint64_t *sites, uint32_t *colours);
+
+/* Threshold table the sampler uses (for checks against exact rationals):
+ * writes up to cap entries, returns the count in *count. */
+tl_status tl_sampler_thresholds(const tl_sampler *s, uint32_t *out, uint32_t cap, uint32_t *count);
+
+/* Threshold table of a (domain, weights) pair without creating a sampler (host
+ * only, no device work): heat-bath tables have one entry per context, lazy
+ * Metropolis tables two ([ctx*2 + current state is up]).  Contexts: domino
+ * 2c + (x mod 2); lozenge 0; six-vertex the mask of high diagonal faces
+ * NE=1, NW=2, SW=4, SE=8.  Writes up to cap entries, the count in *count. */
+tl_status tl_thresholds(const tl_domain *dom, const tl_weights *w, uint32_t *out, uint32_t cap, uint32_t *count);
+
+const char *tl_status_str(tl_status st);
+const char *tl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TILINGS_H */

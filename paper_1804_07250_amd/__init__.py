@@ -1,0 +1,208 @@
+"""Python binding of the MI355X Glauber-sweep library ``libtilings.so``.
+
+Argument marshalling only: every step of the sweep, the observables, the export
+and the row hashing run in the library's HIP kernels.  The names follow the
+C-ABI of ``include/tilings.h``.  Importing this module loads the library and
+raises if it has not been built (``python -m paper_1804_07250_amd.build`` or
+``__graft_entry__.build()``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtilings.so")
+
+TL_OK, TL_EINVAL, TL_EUNTILEABLE, TL_ENOMEM, TL_EBUDGET, TL_EDEVICE, TL_EBUSY = 0, -1, -2, -3, -4, -5, -6
+TL_DOMINO, TL_LOZENGE, TL_SIXVERTEX = 0, 1, 2
+TL_AZTEC, TL_HEXAGON, TL_DWBC_SQUARE = 0, 1, 2
+TL_INIT_MIN, TL_INIT_MAX = 0, 1
+TL_HEATBATH, TL_METROPOLIS = 0, 1
+TL_W_UNIFORM, TL_W_TWO_PERIODIC, TL_W_VOLUME, TL_W_SIXVERTEX = 0, 1, 2, 3
+
+
+class TlError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s (status %d): %s" % (_status_name(status), status, message))
+        self.status = status
+
+
+def _status_name(st):
+    return {0: "TL_OK", -1: "TL_EINVAL", -2: "TL_EUNTILEABLE", -3: "TL_ENOMEM", -4: "TL_EBUDGET",
+            -5: "TL_EDEVICE", -6: "TL_EBUSY"}.get(st, "TL_?")
+
+
+class tl_domain(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int32), ("shape", ctypes.c_int32), ("n", ctypes.c_int32),
+                ("a", ctypes.c_int32), ("b", ctypes.c_int32), ("c", ctypes.c_int32),
+                ("init", ctypes.c_int32)]
+
+
+class tl_weights(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("rule", ctypes.c_int32), ("w", ctypes.c_double * 6)]
+
+
+class tl_options(ctypes.Structure):
+    _fields_ = [("stream", ctypes.c_void_p), ("obs_every", ctypes.c_uint32), ("obs_bin", ctypes.c_uint32),
+                ("sweeps_per_launch", ctypes.c_uint32), ("tile_rows", ctypes.c_uint32),
+                ("kernel", ctypes.c_uint32)]
+
+
+class tl_observables(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_uint64), ("samples", ctypes.c_uint64), ("scalar_now", ctypes.c_int64),
+                ("scalar_sum", ctypes.c_int64), ("bins_x", ctypes.c_uint32), ("bins_y", ctypes.c_uint32),
+                ("bin_sum", ctypes.POINTER(ctypes.c_uint64)), ("bin_now", ctypes.POINTER(ctypes.c_uint64)),
+                ("bin_density", ctypes.POINTER(ctypes.c_double)), ("bin_capacity", ctypes.c_size_t)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libtilings.so (raises if it is missing: no fallback path exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libtilings.so is not built: run __graft_entry__.build() or "
+                              "python -m paper_1804_07250_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32
+        L.tl_sampler_create.argtypes = [ctypes.POINTER(tl_domain), ctypes.POINTER(tl_weights), u64,
+                                        ctypes.POINTER(tl_options), ctypes.POINTER(vp)]
+        L.tl_sampler_sweep.argtypes = [vp, u64]
+        L.tl_sampler_sync.argtypes = [vp]
+        L.tl_sampler_observables.argtypes = [vp, ctypes.POINTER(tl_observables)]
+        L.tl_sampler_export_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(u32),
+                                             ctypes.POINTER(u32)]
+        L.tl_sampler_export.argtypes = [vp, vp, ctypes.c_size_t, ctypes.POINTER(u64)]
+        L.tl_sampler_hash.argtypes = [vp, ctypes.POINTER(ctypes.c_uint8)]
+        L.tl_sampler_import.argtypes = [vp, vp, ctypes.c_size_t, u64]
+        L.tl_sampler_destroy.argtypes = [vp]
+        L.tl_sampler_info.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(u32)]
+        L.tl_sampler_thresholds.argtypes = [vp, ctypes.POINTER(u32), u32, ctypes.POINTER(u32)]
+        L.tl_thresholds.argtypes = [ctypes.POINTER(tl_domain), ctypes.POINTER(tl_weights),
+                                    ctypes.POINTER(u32), u32, ctypes.POINTER(u32)]
+        L.tl_thresholds.restype = i32
+        L.tl_status_str.argtypes = [i32]
+        L.tl_status_str.restype = ctypes.c_char_p
+        L.tl_last_error.restype = ctypes.c_char_p
+        for name in ("tl_sampler_create", "tl_sampler_sweep", "tl_sampler_sync", "tl_sampler_observables",
+                     "tl_sampler_export_size", "tl_sampler_export", "tl_sampler_hash", "tl_sampler_import",
+                     "tl_sampler_destroy", "tl_sampler_info", "tl_sampler_thresholds"):
+            getattr(L, name).restype = i32
+        _lib = L
+    return _lib
+
+
+def _check(st):
+    if st != TL_OK:
+        raise TlError(st, lib().tl_last_error().decode())
+
+
+def domain(model, n=0, a=0, b=0, c=0, init=TL_INIT_MIN):
+    shape = {TL_DOMINO: TL_AZTEC, TL_LOZENGE: TL_HEXAGON, TL_SIXVERTEX: TL_DWBC_SQUARE}[model]
+    return tl_domain(model, shape, n, a, b, c, init)
+
+
+def weights(kind=TL_W_UNIFORM, *w, rule=TL_HEATBATH):
+    arr = (ctypes.c_double * 6)(*([float(v) for v in w] + [0.0] * (6 - len(w))))
+    return tl_weights(kind, rule, arr)
+
+
+def options(stream=None, obs_every=0, obs_bin=1, sweeps_per_launch=0, tile_rows=0, kernel=0):
+    return tl_options(stream, obs_every, obs_bin, sweeps_per_launch, tile_rows, kernel)
+
+
+def thresholds(dom: tl_domain, w: tl_weights):
+    """The library's threshold table for (dom, w) (host only)."""
+    cnt = ctypes.c_uint32()
+    _check(lib().tl_thresholds(ctypes.byref(dom), ctypes.byref(w), None, 0, ctypes.byref(cnt)))
+    buf = (ctypes.c_uint32 * max(1, cnt.value))()
+    _check(lib().tl_thresholds(ctypes.byref(dom), ctypes.byref(w), buf, cnt.value, ctypes.byref(cnt)))
+    return [int(v) for v in buf[:cnt.value]]
+
+
+class Sampler:
+    """One chain: ``tl_sampler_create`` / ``sweep`` / ``observables`` / ``export`` /
+    ``hash`` / ``import_`` / ``destroy``."""
+
+    def __init__(self, dom: tl_domain, w: tl_weights, seed: int, opt: tl_options | None = None):
+        self._h = ctypes.c_void_p()
+        self._opt = opt
+        _check(lib().tl_sampler_create(ctypes.byref(dom), ctypes.byref(w), seed,
+                                       ctypes.byref(opt) if opt is not None else None, ctypes.byref(self._h)))
+        self.dom = dom
+        size = ctypes.c_size_t()
+        rows, rb = ctypes.c_uint32(), ctypes.c_uint32()
+        _check(lib().tl_sampler_export_size(self._h, ctypes.byref(size), ctypes.byref(rows), ctypes.byref(rb)))
+        self.export_bytes, self.rows, self.row_bytes = size.value, rows.value, rb.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def sweep(self, n: int):
+        _check(lib().tl_sampler_sweep(self._h, n))
+
+    def sync(self):
+        _check(lib().tl_sampler_sync(self._h))
+
+    def info(self):
+        s, c = ctypes.c_uint64(), ctypes.c_uint32()
+        _check(lib().tl_sampler_info(self._h, ctypes.byref(s), ctypes.byref(c)))
+        return s.value, c.value
+
+    def thresholds(self):
+        cnt = ctypes.c_uint32()
+        _check(lib().tl_sampler_thresholds(self._h, None, 0, ctypes.byref(cnt)))
+        buf = (ctypes.c_uint32 * max(1, cnt.value))()
+        _check(lib().tl_sampler_thresholds(self._h, buf, cnt.value, ctypes.byref(cnt)))
+        return [int(v) for v in buf[:cnt.value]]
+
+    def observables(self):
+        o = tl_observables()
+        _check(lib().tl_sampler_observables(self._h, ctypes.byref(o)))
+        nb = o.bins_x * o.bins_y
+        bs = np.zeros(nb, dtype=np.uint64)
+        bn = np.zeros(nb, dtype=np.uint64)
+        bd = np.zeros(nb, dtype=np.float64)
+        o.bin_sum = bs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+        o.bin_now = bn.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+        o.bin_density = bd.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        o.bin_capacity = nb
+        _check(lib().tl_sampler_observables(self._h, ctypes.byref(o)))
+        shape = (o.bins_y, o.bins_x)
+        return {"sweeps": o.sweeps, "samples": o.samples, "scalar_now": o.scalar_now,
+                "scalar_sum": o.scalar_sum, "bin_sum": bs.reshape(shape), "bin_now": bn.reshape(shape),
+                "bin_density": bd.reshape(shape)}
+
+    def export(self) -> np.ndarray:
+        buf = np.empty(self.export_bytes, dtype=np.uint8)
+        t = ctypes.c_uint64()
+        _check(lib().tl_sampler_export(self._h, buf.ctypes.data, buf.nbytes, ctypes.byref(t)))
+        if self.dom.model == TL_DOMINO:
+            return buf.reshape(self.rows, self.row_bytes)
+        return buf.view(np.int32).reshape(self.rows, self.row_bytes // 4)
+
+    def hash(self) -> str:
+        d = (ctypes.c_uint8 * 32)()
+        _check(lib().tl_sampler_hash(self._h, d))
+        return bytes(d).hex()
+
+    def import_(self, arr: np.ndarray, sweep: int):
+        a = np.ascontiguousarray(arr)
+        _check(lib().tl_sampler_import(self._h, a.ctypes.data, a.nbytes, sweep))
+
+    def destroy(self):
+        if self._h:
+            lib().tl_sampler_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

@@ -1,0 +1,405 @@
+// C-ABI of the Glauber-sweep library (include/tilings.h): sampler objects,
+// threshold tables, sweep scheduling, observables, export, import and hashing.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/tilings.h"
+#include "internal.hpp"
+#include "models.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+tl_status fail(tl_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+#define TL_HIP(call)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(TL_EDEVICE, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),    \
+                        __FILE__, __LINE__);                                                  \
+    } while (0)
+
+bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
+
+}  // namespace
+
+namespace tl {
+
+// Thresholds T = floor(2^32 p) in 80-bit extended precision from up/down weight
+// ratios R (heat-bath p = R/(1+R); lazy Metropolis pairs [down, up]).
+std::vector<uint32_t> thresholds_from_ratios(const std::vector<long double> &R, bool metropolis)
+{
+    auto fl = [](long double p) -> uint32_t {
+        long double v = floorl(ldexpl(p, 32));
+        if (v < 0) v = 0;
+        if (v > 4294967295.0L) v = 4294967295.0L;
+        return (uint32_t)v;
+    };
+    std::vector<uint32_t> out;
+    for (long double r : R) {
+        if (!metropolis) {
+            out.push_back(fl(r / (1.0L + r)));
+        } else {
+            const long double up = r < 1.0L ? r : 1.0L;
+            const long double dn = r > 1.0L ? 1.0L / r : 1.0L;
+            out.push_back(fl(up / 2.0L));
+            const uint64_t f = fl(dn / 2.0L);
+            out.push_back((uint32_t)((1ull << 32) - f));
+        }
+    }
+    return out;
+}
+
+}  // namespace tl
+
+struct tl_sampler {
+    tl_domain dom{};
+    tl_weights w{};
+    uint64_t seed = 0;
+    tl_options opt{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    uint64_t t = 0;
+    uint64_t samples = 0;
+    std::vector<uint32_t> thr;
+    std::unique_ptr<tl::Model> model;
+    unsigned long long *bin_sum = nullptr;  // device accumulators
+    unsigned long long *bin_tmp = nullptr;
+    uint32_t bins_x = 0, bins_y = 0, B = 1;
+    std::vector<uint32_t> cells_per_bin;    // lazily computed on the host
+};
+
+namespace {
+
+tl_status make_thresholds(const tl_domain &d, const tl_weights &w, std::vector<uint32_t> &thr)
+{
+    const bool metro = w.rule == TL_METROPOLIS;
+    if (w.rule != TL_HEATBATH && w.rule != TL_METROPOLIS) return fail(TL_EINVAL, "unknown rule %d", w.rule);
+    std::vector<long double> R;
+    switch (d.model) {
+    case TL_DOMINO:
+        if (w.kind == TL_W_UNIFORM) {
+            R.assign(4, 1.0L);
+        } else if (w.kind == TL_W_TWO_PERIODIC) {
+            if (!finite_pos(w.w[0]) || !finite_pos(w.w[1])) return fail(TL_EINVAL, "two-periodic weights must be > 0");
+            const long double a = w.w[0], b = w.w[1];
+            R = {1.0L, 1.0L, (b * b) / (a * a), (a * a) / (b * b)};
+        } else {
+            return fail(TL_EINVAL, "weight kind %d does not apply to dominoes", w.kind);
+        }
+        break;
+    case TL_LOZENGE:
+        if (w.kind == TL_W_UNIFORM) {
+            R = {1.0L};
+        } else if (w.kind == TL_W_VOLUME) {
+            if (!finite_pos(w.w[0])) return fail(TL_EINVAL, "volume weight q must be > 0");
+            if (w.w[1] != 0.0 && !finite_pos(w.w[1])) return fail(TL_EINVAL, "volume weight denominator must be > 0");
+            R = {w.w[1] > 0.0 ? (long double)w.w[0] / (long double)w.w[1] : (long double)w.w[0]};
+        } else {
+            return fail(TL_EINVAL, "weight kind %d does not apply to lozenges", w.kind);
+        }
+        break;
+    case TL_SIXVERTEX: {
+        long double a2 = 1, b2 = 1, c2 = 1;
+        if (w.kind == TL_W_SIXVERTEX) {
+            if (!finite_pos(w.w[0]) || !finite_pos(w.w[1]) || !finite_pos(w.w[2]))
+                return fail(TL_EINVAL, "six-vertex weights must be > 0");
+            a2 = w.w[0];
+            b2 = w.w[1];
+            c2 = w.w[2];
+        } else if (w.kind != TL_W_UNIFORM) {
+            return fail(TL_EINVAL, "weight kind %d does not apply to the six-vertex model", w.kind);
+        }
+        // W_up / W_down = prod over the corners (c/w)^(+1 if the corner's diagonal
+        // face is high, -1 otherwise), w = a at NE and SW, b at NW and SE; the
+        // exponents of a, b and c are even, so squares suffice.
+        for (int mask = 0; mask < 16; ++mask) {
+            const int hNE = mask & 1, hNW = (mask >> 1) & 1, hSW = (mask >> 2) & 1, hSE = (mask >> 3) & 1;
+            const int ea = 1 - hNE - hSW;   // exponent of a^2
+            const int eb = 1 - hNW - hSE;   // exponent of b^2
+            const int ec = hNE + hNW + hSW + hSE - 2;   // exponent of c^2
+            long double r = 1.0L;
+            for (int i = 0; i < (ea > 0 ? ea : -ea); ++i) r = ea > 0 ? r * a2 : r / a2;
+            for (int i = 0; i < (eb > 0 ? eb : -eb); ++i) r = eb > 0 ? r * b2 : r / b2;
+            for (int i = 0; i < (ec > 0 ? ec : -ec); ++i) r = ec > 0 ? r * c2 : r / c2;
+            R.push_back(r);
+        }
+        break;
+    }
+    default:
+        return fail(TL_EINVAL, "unknown model %d", d.model);
+    }
+    thr = tl::thresholds_from_ratios(R, metro);
+    return TL_OK;
+}
+
+tl_status enqueue_sample(tl_sampler *s)
+{
+    TL_HIP(s->model->observe(s->B, s->bins_x, s->bin_sum, s->stream));
+    s->samples += 1;
+    return TL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *tl_status_str(tl_status st)
+{
+    switch (st) {
+    case TL_OK: return "ok";
+    case TL_EINVAL: return "invalid argument";
+    case TL_EUNTILEABLE: return "domain not tileable";
+    case TL_ENOMEM: return "out of memory";
+    case TL_EBUDGET: return "over memory budget";
+    case TL_EDEVICE: return "device error";
+    case TL_EBUSY: return "busy";
+    }
+    return "unknown status";
+}
+
+const char *tl_last_error(void) { return g_last_error.c_str(); }
+
+tl_status tl_thresholds(const tl_domain *dom, const tl_weights *w, uint32_t *out, uint32_t cap, uint32_t *count)
+{
+    if (!dom || !w) return fail(TL_EINVAL, "null argument");
+    std::vector<uint32_t> thr;
+    tl_status st = make_thresholds(*dom, *w, thr);
+    if (st != TL_OK) return st;
+    if (count) *count = (uint32_t)thr.size();
+    if (out)
+        for (uint32_t i = 0; i < cap && i < thr.size(); ++i) out[i] = thr[i];
+    return TL_OK;
+}
+
+tl_status tl_sampler_create(const tl_domain *dom, const tl_weights *w, uint64_t seed, const tl_options *opt,
+                            tl_sampler **out)
+{
+    if (!dom || !w || !out) return fail(TL_EINVAL, "null argument");
+    *out = nullptr;
+    std::unique_ptr<tl_sampler> s(new (std::nothrow) tl_sampler());
+    if (!s) return fail(TL_ENOMEM, "host allocation failed");
+    s->dom = *dom;
+    s->w = *w;
+    s->seed = seed;
+    if (opt) s->opt = *opt;
+    if (dom->init != TL_INIT_MIN && dom->init != TL_INIT_MAX) return fail(TL_EINVAL, "unknown init %d", dom->init);
+    tl_status st = make_thresholds(*dom, *w, s->thr);
+    if (st != TL_OK) return st;
+    std::string why;
+    s->model = tl::make_model(*dom, why);
+    if (!s->model) return fail(TL_EINVAL, "%s", why.c_str());
+    if (s->opt.stream) {
+        s->stream = (hipStream_t)s->opt.stream;
+    } else {
+        TL_HIP(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
+        s->own_stream = true;
+    }
+    hipError_t e = s->model->allocate();
+    if (e != hipSuccess) {
+        if (s->own_stream) (void)hipStreamDestroy(s->stream);
+        return fail(e == hipErrorOutOfMemory ? TL_ENOMEM : TL_EDEVICE, "state allocation: %s", hipGetErrorString(e));
+    }
+    s->B = s->opt.obs_bin ? s->opt.obs_bin : 1u;
+    uint32_t cw, ch;
+    s->model->cell_box(&cw, &ch);
+    s->bins_x = (cw + s->B - 1) / s->B;
+    s->bins_y = (ch + s->B - 1) / s->B;
+    const size_t nb = (size_t)s->bins_x * s->bins_y;
+    if (hipMalloc(&s->bin_sum, nb * sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc(&s->bin_tmp, nb * sizeof(unsigned long long)) != hipSuccess) {
+        if (s->bin_sum) (void)hipFree(s->bin_sum);
+        s->bin_sum = nullptr;
+        s->model->release();
+        if (s->own_stream) (void)hipStreamDestroy(s->stream);
+        return fail(TL_ENOMEM, "observable buffers");
+    }
+    TL_HIP(hipMemsetAsync(s->bin_sum, 0, nb * sizeof(unsigned long long), s->stream));
+    TL_HIP(s->model->init(dom->init == TL_INIT_MAX, s->stream));
+    *out = s.release();
+    return TL_OK;
+}
+
+tl_status tl_sampler_sweep(tl_sampler *s, uint64_t n)
+{
+    if (!s) return fail(TL_EINVAL, "null sampler");
+    if (s->t + n > 0xFFFFFFFFull) return fail(TL_EINVAL, "sweep counter would exceed 2^32");
+    tl::Thr T{};
+    for (size_t i = 0; i < s->thr.size() && i < 32; ++i) T.v[i] = s->thr[i];
+    const bool metro = s->w.rule == TL_METROPOLIS;
+    const uint32_t every = s->opt.obs_every;
+    uint64_t done = 0;
+    while (done < n) {
+        const uint32_t t = (uint32_t)(s->t + done);
+        // sweeps until the next sample point (or the end)
+        uint64_t chunk = n - done;
+        if (every) {
+            const uint64_t to_sample = every - (t % every);
+            if (to_sample < chunk) chunk = to_sample;
+        }
+        TL_HIP(s->model->sweeps(t, (uint32_t)chunk, T, metro, s->seed, s->opt, s->stream));
+        done += chunk;
+        if (every && ((uint64_t)t + chunk) % every == 0) {
+            tl_status st = enqueue_sample(s);
+            if (st != TL_OK) return st;
+        }
+    }
+    s->t += n;
+    return TL_OK;
+}
+
+tl_status tl_sampler_sync(tl_sampler *s)
+{
+    if (!s) return fail(TL_EINVAL, "null sampler");
+    TL_HIP(hipStreamSynchronize(s->stream));
+    return TL_OK;
+}
+
+tl_status tl_sampler_observables(tl_sampler *s, tl_observables *o)
+{
+    if (!s || !o) return fail(TL_EINVAL, "null argument");
+    const size_t nb = (size_t)s->bins_x * s->bins_y;
+    if ((o->bin_sum || o->bin_now || o->bin_density) && o->bin_capacity < nb)
+        return fail(TL_EINVAL, "bin buffers hold %zu entries, %zu needed", o->bin_capacity, nb);
+    TL_HIP(hipMemsetAsync(s->bin_tmp, 0, nb * sizeof(unsigned long long), s->stream));
+    TL_HIP(s->model->observe(s->B, s->bins_x, s->bin_tmp, s->stream));
+    std::vector<unsigned long long> sum(nb), now(nb);
+    TL_HIP(hipMemcpyAsync(sum.data(), s->bin_sum, nb * sizeof(unsigned long long), hipMemcpyDeviceToHost, s->stream));
+    TL_HIP(hipMemcpyAsync(now.data(), s->bin_tmp, nb * sizeof(unsigned long long), hipMemcpyDeviceToHost, s->stream));
+    TL_HIP(hipStreamSynchronize(s->stream));
+    o->sweeps = s->t;
+    o->samples = s->samples;
+    o->bins_x = s->bins_x;
+    o->bins_y = s->bins_y;
+    int64_t a = 0, b = 0;
+    for (size_t i = 0; i < nb; ++i) {
+        a += (int64_t)sum[i];
+        b += (int64_t)now[i];
+    }
+    o->scalar_sum = a;
+    o->scalar_now = b;
+    if (o->bin_sum) memcpy(o->bin_sum, sum.data(), nb * sizeof(uint64_t));
+    if (o->bin_now) memcpy(o->bin_now, now.data(), nb * sizeof(uint64_t));
+    if (o->bin_density) {
+        if (s->cells_per_bin.empty()) s->cells_per_bin = s->model->cells_per_bin(s->B, s->bins_x, s->bins_y);
+        for (size_t i = 0; i < nb; ++i) {
+            const uint32_t c = s->cells_per_bin[i];
+            o->bin_density[i] = (c && s->samples) ? (double)sum[i] / ((double)s->samples * (double)c) : 0.0;
+        }
+    }
+    return TL_OK;
+}
+
+tl_status tl_sampler_export_size(const tl_sampler *s, size_t *bytes, uint32_t *rows, uint32_t *row_bytes)
+{
+    if (!s) return fail(TL_EINVAL, "null sampler");
+    uint32_t r, rb;
+    s->model->export_layout(&r, &rb);
+    if (bytes) *bytes = (size_t)r * rb;
+    if (rows) *rows = r;
+    if (row_bytes) *row_bytes = rb;
+    return TL_OK;
+}
+
+tl_status tl_sampler_export(tl_sampler *s, void *host, size_t bytes, uint64_t *sweep_out)
+{
+    if (!s || !host) return fail(TL_EINVAL, "null argument");
+    uint32_t r, rb;
+    s->model->export_layout(&r, &rb);
+    const size_t need = (size_t)r * rb;
+    if (bytes < need) return fail(TL_EINVAL, "export buffer has %zu bytes, %zu needed", bytes, need);
+    uint8_t *dev = nullptr;
+    TL_HIP(hipMallocAsync((void **)&dev, need, s->stream));
+    hipError_t e = s->model->export_canonical(dev, s->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(host, dev, need, hipMemcpyDeviceToHost, s->stream);
+    (void)hipFreeAsync(dev, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return fail(TL_EDEVICE, "export: %s", hipGetErrorString(e));
+    if (sweep_out) *sweep_out = s->t;
+    return TL_OK;
+}
+
+tl_status tl_sampler_hash(tl_sampler *s, uint8_t digest[32])
+{
+    if (!s || !digest) return fail(TL_EINVAL, "null argument");
+    uint32_t r, rb;
+    s->model->export_layout(&r, &rb);
+    const size_t need = (size_t)r * rb;
+    uint8_t *dev = nullptr;
+    TL_HIP(hipMallocAsync((void **)&dev, need + 32 * (size_t)r, s->stream));
+    std::vector<uint8_t> rowd(32 * (size_t)r);
+    hipError_t e = s->model->export_canonical(dev, s->stream);
+    if (e == hipSuccess) e = tl::hash_rows(dev, r, rb, dev + need, s->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(rowd.data(), dev + need, rowd.size(), hipMemcpyDeviceToHost, s->stream);
+    (void)hipFreeAsync(dev, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return fail(TL_EDEVICE, "hash: %s", hipGetErrorString(e));
+    tl::sha256_host(rowd.data(), rowd.size(), digest);
+    return TL_OK;
+}
+
+tl_status tl_sampler_import(tl_sampler *s, const void *host, size_t bytes, uint64_t sweep)
+{
+    if (!s || !host) return fail(TL_EINVAL, "null argument");
+    uint32_t r, rb;
+    s->model->export_layout(&r, &rb);
+    if (bytes != (size_t)r * rb) return fail(TL_EINVAL, "import needs exactly %zu bytes", (size_t)r * rb);
+    if (sweep > 0xFFFFFFFFull) return fail(TL_EINVAL, "sweep counter exceeds 2^32");
+    std::string why;
+    hipError_t e = hipSuccess;
+    if (!s->model->import_canonical((const uint8_t *)host, s->stream, why, &e)) {
+        if (e != hipSuccess) return fail(TL_EDEVICE, "import: %s", hipGetErrorString(e));
+        return fail(TL_EINVAL, "import: %s", why.c_str());
+    }
+    TL_HIP(hipStreamSynchronize(s->stream));
+    s->t = sweep;
+    return TL_OK;
+}
+
+tl_status tl_sampler_destroy(tl_sampler *s)
+{
+    if (!s) return TL_OK;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    if (s->model) s->model->release();
+    if (s->bin_sum) (void)hipFree(s->bin_sum);
+    if (s->bin_tmp) (void)hipFree(s->bin_tmp);
+    if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+    return TL_OK;
+}
+
+tl_status tl_sampler_info(const tl_sampler *s, uint64_t *sites, uint32_t *colours)
+{
+    if (!s) return fail(TL_EINVAL, "null sampler");
+    if (sites) *sites = s->model->sites();
+    if (colours) *colours = (uint32_t)s->model->colours();
+    return TL_OK;
+}
+
+tl_status tl_sampler_thresholds(const tl_sampler *s, uint32_t *out, uint32_t cap, uint32_t *count)
+{
+    if (!s) return fail(TL_EINVAL, "null sampler");
+    if (count) *count = (uint32_t)s->thr.size();
+    if (out)
+        for (uint32_t i = 0; i < cap && i < s->thr.size(); ++i) out[i] = s->thr[i];
+    return TL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,115 @@
+// Device-side building blocks shared by the three models: the Philox4x32-10
+// generator, the bit-serial acceptance test "u < T" over 128 sites, and the
+// observable bin reduction.  gfx950 only; wavefront size 64.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tl {
+
+constexpr uint32_t kPhiloxM0 = 0xD2511F53u;
+constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
+constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
+constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 32x32->64 products; the key (uniform across the wavefront, so it lives in
+// scalar registers) is bumped by the Weyl constants between rounds.
+__device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                              uint32_t k0, uint32_t k1, uint32_t out[4])
+{
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        if (i) {
+            k0 += kPhiloxW0;
+            k1 += kPhiloxW1;
+        }
+        const uint32_t hi0 = __umulhi(kPhiloxM0, c0), lo0 = kPhiloxM0 * c0;
+        const uint32_t hi1 = __umulhi(kPhiloxM1, c2), lo1 = kPhiloxM1 * c2;
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+// Acceptance decisions for the 128 sites k = 128 g + 32 w + b (w = 0..3,
+// b = 0..31) of class row r in colour step (t, c): bit b of D[w] is 1 iff the
+// site's uniform u is below the threshold of its context.
+//
+// u is defined plane by plane from its most significant bit: bit 31-j of u is
+// bit b of word w of Philox(ctr = (g, r, t, 4j + c)).  The comparison runs
+// bit-serially from plane 0; a site leaves the loop as soon as its prefix of u
+// differs from the prefix of its threshold, or when the threshold has no 1 bit
+// left below the current plane.  Only the sites in `live` need a decision
+// (the others are not flippable), so with T = 2^31 a single Philox call decides
+// 128 sites.
+//
+// Contexts: site (w, b) is in context i iff bit b of cm[i][w] is set; the masks
+// of one word partition (at least) the live sites.
+template <int NC>
+__device__ __forceinline__ void decide128(uint32_t key0, uint32_t key1, uint32_t g, uint32_t r,
+                                          uint32_t t, uint32_t c, const uint32_t (&T)[NC],
+                                          const uint32_t (&cm)[NC][4], const uint32_t (&live)[4],
+                                          uint32_t (&D)[4])
+{
+    uint32_t eq[4], lt[4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        eq[w] = live[w];
+        lt[w] = 0u;
+    }
+    for (uint32_t j = 0; j < 32u; ++j) {
+        if ((eq[0] | eq[1] | eq[2] | eq[3]) == 0u) break;
+        uint32_t R[4];
+        philox4x32_10(g, r, t, (j << 2) | c, key0, key1, R);
+        const uint32_t b = 31u - j;
+        const uint32_t below = (b == 0u) ? 0u : ((1u << b) - 1u);
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            uint32_t tb = 0u, nz = 0u;
+#pragma unroll
+            for (int i = 0; i < NC; ++i) {
+                if ((T[i] >> b) & 1u) tb |= cm[i][w];
+                if (T[i] & below) nz |= cm[i][w];
+            }
+            lt[w] |= eq[w] & tb & ~R[w];
+            eq[w] &= ~(tb ^ R[w]) & nz;
+        }
+    }
+#pragma unroll
+    for (int w = 0; w < 4; ++w) D[w] = lt[w];
+}
+
+// Adds the per-cell quantity q of the calling thread to bin (X / B, Y / B).
+// Launch shape: 16 x 16 threads per block over a 16 x 16 tile of cells.  When
+// B is a multiple of 16 the whole tile falls in one bin and is reduced in the
+// block first.
+__device__ __forceinline__ void bin_add(uint64_t q, int X, int Y, bool valid, uint32_t B,
+                                        uint32_t bins_x, unsigned long long *bin_sum)
+{
+    if ((B & 15u) == 0u) {
+        __shared__ unsigned long long part[4];
+        uint64_t v = valid ? q : 0ull;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+        const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+        if ((tid & 63) == 0) part[tid >> 6] = v;
+        __syncthreads();
+        if (tid == 0) {
+            const uint64_t s = part[0] + part[1] + part[2] + part[3];
+            const int X0 = blockIdx.x * 16, Y0 = blockIdx.y * 16;
+            if (s) atomicAdd(&bin_sum[(size_t)(Y0 / B) * bins_x + X0 / B], (unsigned long long)s);
+        }
+    } else if (valid && q) {
+        atomicAdd(&bin_sum[(size_t)(Y / (int)B) * bins_x + X / (int)B], (unsigned long long)q);
+    }
+}
+
+}  // namespace tl

@@ -1,0 +1,38 @@
+// Per-model state objects behind the C-ABI: each owns its device bit-planes and
+// knows how to initialise, sweep, observe, export and import its state.
+#pragma once
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/tilings.h"
+#include "internal.hpp"
+
+namespace tl {
+
+class Model {
+public:
+    virtual ~Model() {}
+    virtual hipError_t allocate() = 0;
+    virtual void release() = 0;
+    virtual hipError_t init(bool init_max, hipStream_t s) = 0;
+    // Sweeps t0 .. t0+n-1, every colour in order 0..K-1 within a sweep.
+    virtual hipError_t sweeps(uint32_t t0, uint32_t n, const Thr &T, bool metropolis, uint64_t seed,
+                              const tl_options &opt, hipStream_t s) = 0;
+    // Add the per-cell observable of the current state to bins of B x B cells.
+    virtual hipError_t observe(uint32_t B, uint32_t bins_x, unsigned long long *bins, hipStream_t s) = 0;
+    virtual void cell_box(uint32_t *w, uint32_t *h) const = 0;
+    virtual std::vector<uint32_t> cells_per_bin(uint32_t B, uint32_t bins_x, uint32_t bins_y) const = 0;
+    virtual void export_layout(uint32_t *rows, uint32_t *row_bytes) const = 0;
+    virtual hipError_t export_canonical(uint8_t *dev, hipStream_t s) = 0;
+    // Validate a canonical export on the host and upload it; false on error
+    // (why set for invalid input, *err set for HIP failures).
+    virtual bool import_canonical(const uint8_t *host, hipStream_t s, std::string &why, hipError_t *err) = 0;
+    virtual uint64_t sites() const = 0;
+    virtual int colours() const = 0;
+};
+
+std::unique_ptr<Model> make_model(const tl_domain &d, std::string &why);
+std::vector<uint32_t> thresholds_from_ratios(const std::vector<long double> &R, bool metropolis);
+
+}  // namespace tl

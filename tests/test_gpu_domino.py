@@ -1,0 +1,154 @@
+"""GPU parity for the domino sampler: the HIP path against the oracle, bit for
+bit on the canonical export and the integer observables (Aztec diamonds)."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import need_gpu, say, vertical_brick_faces
+
+pytestmark = pytest.mark.gpu
+
+
+def thr_uniform(metro=False):
+    return oracle.table_from_ratios(oracle.domino_ratios(), metro)
+
+
+def thr_two(a, b, metro=False):
+    return oracle.table_from_ratios(oracle.domino_ratios("two", a, b), metro)
+
+
+def gpu_sampler(tl, n, seed, kind="uniform", a=1.0, b=1.0, metro=False, init=0, obs_every=0, obs_bin=1, **kw):
+    w = tl.weights(tl.TL_W_UNIFORM) if kind == "uniform" else tl.weights(tl.TL_W_TWO_PERIODIC, a, b)
+    w.rule = tl.TL_METROPOLIS if metro else tl.TL_HEATBATH
+    return tl.Sampler(tl.domain(tl.TL_DOMINO, n=n, init=init), w, seed,
+                      tl.options(obs_every=obs_every, obs_bin=obs_bin, **kw))
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 7, 8, 31, 32, 33, 65, 130, 257])
+def test_uniform_parity_small(n):
+    tl = need_gpu()
+    say("domino uniform parity n=%d" % n)
+    s = gpu_sampler(tl, n, seed=1234 + n)
+    o = oracle.DominoOracle(n, thr_uniform(), seed=1234 + n)
+    assert (s.export() == o.export()).all()
+    for steps in (1, 2, 9):
+        s.sweep(steps)
+        o.sweep(steps)
+        assert (s.export() == o.export()).all(), "n=%d after %d sweeps" % (n, o.t)
+
+
+@pytest.mark.parametrize("metro", [False, True])
+@pytest.mark.parametrize("n", [5, 40, 133])
+def test_two_periodic_parity(n, metro):
+    tl = need_gpu()
+    say("domino two-periodic parity n=%d metro=%s" % (n, metro))
+    s = gpu_sampler(tl, n, seed=77, kind="two", a=1.0, b=0.5, metro=metro)
+    o = oracle.DominoOracle(n, thr_two(1, oracle.Fraction(1, 2), metro), metropolis=metro, seed=77)
+    assert s.thresholds() == list(o.thr)
+    s.sweep(15)
+    o.sweep(15)
+    assert (s.export() == o.export()).all()
+
+
+def test_uniform_metropolis_parity():
+    tl = need_gpu()
+    s = gpu_sampler(tl, 50, seed=5, metro=True)
+    o = oracle.DominoOracle(50, thr_uniform(True), metropolis=True, seed=5)
+    s.sweep(12)
+    o.sweep(12)
+    assert (s.export() == o.export()).all()
+
+
+def test_config1_aztec64_1000_sweeps_with_face_density():
+    # Aztec n=64, uniform, brick start, 1000 sweeps, seed 1, per-face
+    # horizontal counts sampled after every sweep.
+    tl = need_gpu()
+    say("domino config n=64 1000 sweeps")
+    s = gpu_sampler(tl, 64, seed=1, obs_every=1, obs_bin=1)
+    o = oracle.DominoOracle(64, thr_uniform(), seed=1, obs_every=1, bin_=1)
+    s.sweep(1000)
+    o.sweep(1000)
+    assert (s.export() == o.export()).all()
+    obs = s.observables()
+    assert obs["samples"] == int(o.samples[0]) == 1000
+    assert (obs["bin_sum"].reshape(-1) == o.bin_sum).all()
+    assert obs["scalar_sum"] == int(o.scalar_sum[0])
+    v, _ = o.observe(1)
+    assert obs["scalar_now"] == v
+    dens = oracle.bin_density(o.bin_sum, int(o.samples[0]), o.in_domain_cells(), 1)
+    assert np.allclose(obs["bin_density"], dens, rtol=1e-12, atol=0)
+    assert s.hash() == oracle.canonical_hash(o.export())
+
+
+def test_binned_density_and_ragged_bins():
+    tl = need_gpu()
+    n, B = 45, 16   # 90 x 90 faces -> 6 x 6 bins, last ones ragged
+    s = gpu_sampler(tl, n, seed=9, obs_every=3, obs_bin=B)
+    o = oracle.DominoOracle(n, thr_uniform(), seed=9, obs_every=3, bin_=B)
+    s.sweep(31)
+    o.sweep(31)
+    obs = s.observables()
+    assert (obs["bin_sum"].reshape(-1) == o.bin_sum).all()
+    dens = oracle.bin_density(o.bin_sum, int(o.samples[0]), o.in_domain_cells(), B)
+    assert np.allclose(obs["bin_density"], dens, rtol=1e-6, atol=0)
+    s2 = gpu_sampler(tl, n, seed=9, obs_every=3, obs_bin=5)
+    o2 = oracle.DominoOracle(n, thr_uniform(), seed=9, obs_every=3, bin_=5)
+    s2.sweep(7)
+    o2.sweep(7)
+    assert (s2.observables()["bin_sum"].reshape(-1) == o2.bin_sum).all()
+
+
+def test_init_max_and_import_resume():
+    tl = need_gpu()
+    n = 37
+    s = gpu_sampler(tl, n, seed=3, init=tl.TL_INIT_MAX)
+    vb = vertical_brick_faces(n)
+    assert (s.export() == vb).all()
+    o = oracle.DominoOracle(n, thr_uniform(), seed=3)
+    o.load(vb)
+    s.sweep(11)
+    o.sweep(11)
+    assert (s.export() == o.export()).all()
+    # resume: export at t=11, import into a fresh sampler, continue
+    mid = s.export()
+    s.sweep(6)
+    r = gpu_sampler(tl, n, seed=3)
+    r.import_(mid, 11)
+    r.sweep(6)
+    assert (r.export() == s.export()).all()
+    # split sweeps
+    a = gpu_sampler(tl, n, seed=3)
+    a.sweep(4)
+    a.sweep(13)
+    b = gpu_sampler(tl, n, seed=3)
+    b.sweep(17)
+    assert (a.export() == b.export()).all()
+
+
+def test_import_rejects_invalid():
+    tl = need_gpu()
+    s = gpu_sampler(tl, 6, seed=1)
+    bad = s.export().copy()
+    bad[5, 5] = 0 if bad[5, 5] != 0 else 1
+    with pytest.raises(tl.TlError) as e:
+        s.import_(bad, 0)
+    assert e.value.status == tl.TL_EINVAL
+
+
+def test_full_size_order_2048_one_sweep_sampled():
+    # Order 2048 (the large plain-path workload): after a few sweeps from the
+    # brick tiling the GPU state is loaded into the oracle, both run one more
+    # sweep at a late sweep index, and the exports must agree bit for bit.
+    tl = need_gpu()
+    say("domino order 2048 one-sweep parity")
+    n = 2048
+    s = gpu_sampler(tl, n, seed=7)
+    s.sweep(3)
+    mid = s.export()
+    o = oracle.DominoOracle(n, thr_uniform(), seed=7)
+    o.load(mid)
+    o.t = 3
+    s.sweep(1)
+    o.sweep(1)
+    assert (s.export() == o.export()).all()
+    assert s.hash() == oracle.canonical_hash(o.export())
