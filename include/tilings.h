@@ -90,6 +90,7 @@ typedef struct {
     uint32_t sweeps_per_launch;  /* sweeps fused in one launch of the tiled kernel; 0 = automatic */
     uint32_t tile_rows;          /* tile height of the tiled kernel; 0 = automatic */
     uint32_t kernel;             /* 0 = automatic, 1 = one launch per colour step, 2 = tiled multi-sweep */
+    uint32_t tile_groups;        /* tile width in groups of 128 sites; 0 = automatic */
 } tl_options;
 
 typedef struct tl_sampler tl_sampler;
@@ -146,6 +147,21 @@ tl_status tl_sampler_import(tl_sampler *s, const void *host, size_t bytes, uint6
 
 /* Free the sampler and its device memory. */
 tl_status tl_sampler_destroy(tl_sampler *s);
+
+/* Return the sampler to the extremal start of its domain with sweep counter 0,
+ * no accumulated samples and a new seed (device work only, asynchronous). */
+tl_status tl_sampler_reset(tl_sampler *s, uint64_t seed);
+
+/* Per-launch timing of the sweep kernels: with period p > 0, every p-th sweep
+ * kernel launch carries a start/stop event pair recorded by its own dispatch
+ * (p = 1 times every launch); p = 0 switches timing off. */
+tl_status tl_sampler_set_timing(tl_sampler *s, int period);
+
+/* Synchronise and report (then clear) the timed launches: total kernel time in
+ * ms, number of launches, colour steps they performed, and the algorithmic
+ * bytes of one colour step (the packed state read and written once). */
+tl_status tl_sampler_kernel_time(tl_sampler *s, double *ms, uint64_t *launches, uint64_t *colour_steps,
+                                 double *bytes_per_colour_step);
 
 /* Number of sites (rotation locations) and colour classes of the sampler. */
 tl_status tl_sampler_info(const tl_sampler *s, uint64_t *sites, uint32_t *colours);

@@ -48,7 +48,7 @@ class tl_weights(ctypes.Structure):
 class tl_options(ctypes.Structure):
     _fields_ = [("stream", ctypes.c_void_p), ("obs_every", ctypes.c_uint32), ("obs_bin", ctypes.c_uint32),
                 ("sweeps_per_launch", ctypes.c_uint32), ("tile_rows", ctypes.c_uint32),
-                ("kernel", ctypes.c_uint32)]
+                ("kernel", ctypes.c_uint32), ("tile_groups", ctypes.c_uint32)]
 
 
 class tl_observables(ctypes.Structure):
@@ -82,6 +82,10 @@ def lib():
         L.tl_sampler_import.argtypes = [vp, vp, ctypes.c_size_t, u64]
         L.tl_sampler_destroy.argtypes = [vp]
         L.tl_sampler_info.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(u32)]
+        L.tl_sampler_reset.argtypes = [vp, u64]
+        L.tl_sampler_set_timing.argtypes = [vp, i32]
+        L.tl_sampler_kernel_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(u64),
+                                             ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_double)]
         L.tl_sampler_thresholds.argtypes = [vp, ctypes.POINTER(u32), u32, ctypes.POINTER(u32)]
         L.tl_thresholds.argtypes = [ctypes.POINTER(tl_domain), ctypes.POINTER(tl_weights),
                                     ctypes.POINTER(u32), u32, ctypes.POINTER(u32)]
@@ -91,7 +95,8 @@ def lib():
         L.tl_last_error.restype = ctypes.c_char_p
         for name in ("tl_sampler_create", "tl_sampler_sweep", "tl_sampler_sync", "tl_sampler_observables",
                      "tl_sampler_export_size", "tl_sampler_export", "tl_sampler_hash", "tl_sampler_import",
-                     "tl_sampler_destroy", "tl_sampler_info", "tl_sampler_thresholds"):
+                     "tl_sampler_destroy", "tl_sampler_info", "tl_sampler_thresholds", "tl_sampler_reset",
+                     "tl_sampler_set_timing", "tl_sampler_kernel_time"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -112,8 +117,8 @@ def weights(kind=TL_W_UNIFORM, *w, rule=TL_HEATBATH):
     return tl_weights(kind, rule, arr)
 
 
-def options(stream=None, obs_every=0, obs_bin=1, sweeps_per_launch=0, tile_rows=0, kernel=0):
-    return tl_options(stream, obs_every, obs_bin, sweeps_per_launch, tile_rows, kernel)
+def options(stream=None, obs_every=0, obs_bin=1, sweeps_per_launch=0, tile_rows=0, kernel=0, tile_groups=0):
+    return tl_options(stream, obs_every, obs_bin, sweeps_per_launch, tile_rows, kernel, tile_groups)
 
 
 def thresholds(dom: tl_domain, w: tl_weights):
@@ -149,6 +154,20 @@ class Sampler:
 
     def sync(self):
         _check(lib().tl_sampler_sync(self._h))
+
+    def reset(self, seed: int):
+        _check(lib().tl_sampler_reset(self._h, seed))
+
+    def set_timing(self, period: int):
+        """Time every `period`-th sweep launch with dispatch events (0 = off)."""
+        _check(lib().tl_sampler_set_timing(self._h, int(period)))
+
+    def kernel_time(self):
+        """(total kernel ms, launches, colour steps, algorithmic bytes per colour step)."""
+        ms, la, st, bp = ctypes.c_double(), ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_double()
+        _check(lib().tl_sampler_kernel_time(self._h, ctypes.byref(ms), ctypes.byref(la), ctypes.byref(st),
+                                            ctypes.byref(bp)))
+        return ms.value, la.value, st.value, bp.value
 
     def info(self):
         s, c = ctypes.c_uint64(), ctypes.c_uint32()

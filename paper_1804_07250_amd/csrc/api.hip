@@ -243,6 +243,7 @@ tl_status tl_sampler_sweep(tl_sampler *s, uint64_t n)
     if (s->t + n > 0xFFFFFFFFull) return fail(TL_EINVAL, "sweep counter would exceed 2^32");
     tl::Thr T{};
     for (size_t i = 0; i < s->thr.size() && i < 32; ++i) T.v[i] = s->thr[i];
+    T.count = (uint32_t)(s->thr.size() < 32 ? s->thr.size() : 32);
     const bool metro = s->w.rule == TL_METROPOLIS;
     const uint32_t every = s->opt.obs_every;
     uint64_t done = 0;
@@ -382,6 +383,44 @@ tl_status tl_sampler_destroy(tl_sampler *s)
     if (s->bin_tmp) (void)hipFree(s->bin_tmp);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
+    return TL_OK;
+}
+
+tl_status tl_sampler_reset(tl_sampler *s, uint64_t seed)
+{
+    if (!s) return fail(TL_EINVAL, "null sampler");
+    s->seed = seed;
+    s->t = 0;
+    s->samples = 0;
+    const size_t nb = (size_t)s->bins_x * s->bins_y;
+    TL_HIP(hipMemsetAsync(s->bin_sum, 0, nb * sizeof(unsigned long long), s->stream));
+    TL_HIP(s->model->init(s->dom.init == TL_INIT_MAX, s->stream));
+    return TL_OK;
+}
+
+tl_status tl_sampler_set_timing(tl_sampler *s, int enable)
+{
+    if (!s) return fail(TL_EINVAL, "null sampler");
+    if (enable < 0) return fail(TL_EINVAL, "timing period must be >= 0");
+    s->model->timing.on = enable != 0;
+    s->model->timing.every = enable > 0 ? (uint32_t)enable : 1u;
+    s->model->timing.counter = 0;
+    return TL_OK;
+}
+
+tl_status tl_sampler_kernel_time(tl_sampler *s, double *ms, uint64_t *launches, uint64_t *colour_steps,
+                                 double *bytes_per_colour_step)
+{
+    if (!s) return fail(TL_EINVAL, "null sampler");
+    TL_HIP(hipStreamSynchronize(s->stream));
+    TL_HIP(s->model->timing.collect());
+    if (ms) *ms = s->model->timing.ms;
+    if (launches) *launches = s->model->timing.launches;
+    if (colour_steps) *colour_steps = s->model->timing.steps;
+    if (bytes_per_colour_step) *bytes_per_colour_step = s->model->bytes_per_colour_step();
+    s->model->timing.ms = 0.0;
+    s->model->timing.launches = 0;
+    s->model->timing.steps = 0;
     return TL_OK;
 }
 

@@ -17,6 +17,14 @@
 // horizontal otherwise; flipping toggles its four edge bits.  Owner steps touch
 // only the owner's own bits; the other colour's step reads and writes bits of
 // four owners, two of them shifted by one bit position.
+//
+// Two kernels run the same group update (128 sites of one row):
+//   * a streaming kernel, one launch per colour step, on the state in HBM;
+//   * a tiled kernel that loads a tile plus halo into LDS, runs S whole sweeps
+//     there and writes the tile interior back (ping-pong buffers).  The halo is
+//     recomputed redundantly with the same keyed draws, so results are
+//     independent of the tiling.  In the owner frame one sweep invalidates one
+//     row and one column of the halo on each side.
 #include "device_common.hpp"
 #include "internal.hpp"
 
@@ -45,41 +53,46 @@ __device__ __forceinline__ uint32_t brick_pair(int n, int x, int y)
     return (m > 0 && x - 1 >= -m && x <= m - 1 && ((x - 1 + m) & 1) == 0) ? 1u : 0u;
 }
 
-__global__ void domino_init_kernel(uint32_t *planes, size_t PS, uint32_t RS, int n, int init_max)
+// Writes the initial state into both buffers (a and, if non-null, b),
+// including the zero padding.
+__global__ void domino_init_kernel(uint32_t *a, uint32_t *b, size_t PS, uint32_t RS, int n, int init_max)
 {
     const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t r = blockIdx.y;
     if (w >= RS || r > (uint32_t)n) return;
     uint32_t bits[4] = {0u, 0u, 0u, 0u};
     if (r < (uint32_t)n) {
-        for (int b = 0; b < 32; ++b) {
-            const int k = (int)(w * 32u) + b;
+        for (int bb = 0; bb < 32; ++bb) {
+            const int k = (int)(w * 32u) + bb;
             if (k >= n) break;
             const int x = (int)r - k, y = (int)r + k + 1 - n;
             if (!init_max) {        // horizontal brick: N and S edges
-                bits[0] |= brick_pair(n, x, y) << b;
-                bits[1] |= brick_pair(n, x, y - 1) << b;
+                bits[0] |= brick_pair(n, x, y) << bb;
+                bits[1] |= brick_pair(n, x, y - 1) << bb;
             } else {                // vertical brick (the transpose): E and W edges
-                bits[2] |= brick_pair(n, y, x) << b;
-                bits[3] |= brick_pair(n, y, x - 1) << b;
+                bits[2] |= brick_pair(n, y, x) << bb;
+                bits[3] |= brick_pair(n, y, x - 1) << bb;
             }
         }
     }
 #pragma unroll
-    for (int p = 0; p < 4; ++p) planes[p * PS + (size_t)r * RS + w] = bits[p];
+    for (int p = 0; p < 4; ++p) {
+        a[p * PS + (size_t)r * RS + w] = bits[p];
+        if (b) b[p * PS + (size_t)r * RS + w] = bits[p];
+    }
 }
 
-__device__ __forceinline__ uint4 ld4(const uint32_t *p) { return *reinterpret_cast<const uint4 *>(p); }
-__device__ __forceinline__ void st4(uint32_t *p, const uint32_t (&v)[4])
+__device__ __forceinline__ void ld4(const uint32_t *p, uint32_t (&v)[4])
 {
-    *reinterpret_cast<uint4 *>(p) = make_uint4(v[0], v[1], v[2], v[3]);
-}
-__device__ __forceinline__ void unpack(uint4 q, uint32_t (&v)[4])
-{
+    const uint4 q = *reinterpret_cast<const uint4 *>(p);
     v[0] = q.x;
     v[1] = q.y;
     v[2] = q.z;
     v[3] = q.w;
+}
+__device__ __forceinline__ void st4(uint32_t *p, const uint32_t (&v)[4])
+{
+    *reinterpret_cast<uint4 *>(p) = make_uint4(v[0], v[1], v[2], v[3]);
 }
 
 // Contexts of the domino tables: ctx = 2c + (x mod 2) (heat-bath) and
@@ -124,22 +137,42 @@ struct DomCtx<true> {
     }
 };
 
-// One colour step of the owner colour: all bits local to the owner.
-template <bool METRO>
-__global__ void __launch_bounds__(256) domino_owner_step(uint32_t *planes, size_t PS, uint32_t RS,
-                                                         uint32_t ng, uint32_t n, uint32_t c,
-                                                         uint32_t t, Thr Tall, uint32_t key0,
-                                                         uint32_t key1)
+// Rule variants: general heat-bath, general lazy Metropolis, and uniform
+// weights (every threshold 2^31: a site goes up iff the top bit of its uniform
+// is 0, so one Philox call decides all 128 sites and does not depend on the
+// state; it is issued first to overlap the memory latency).
+enum { kHeatBath = 0, kMetropolis = 1, kUniform = 2 };
+
+template <int MODE>
+__device__ __forceinline__ void decide_group(uint32_t key0, uint32_t key1, uint32_t g, uint32_t r, uint32_t t,
+                                             uint32_t c, const Thr &Tall, const uint32_t (&R0)[4],
+                                             const uint32_t (&vert)[4], const uint32_t (&live)[4], uint32_t (&D)[4])
 {
-    const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t g = gid % ng, r = gid / ng;
-    if (r >= n) return;
-    uint32_t *base = planes + (size_t)r * RS + 4u * g;
+    if (MODE == kUniform) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w) D[w] = ~R0[w];
+    } else {
+        constexpr int NC = DomCtx<MODE == kMetropolis>::NC;
+        uint32_t T[NC], cm[NC][4];
+        DomCtx<MODE == kMetropolis>::build(r, c, Tall, vert, T, cm);
+        decide128<NC>(key0, key1, g, r, t, c, T, cm, live, D);
+    }
+}
+
+// Owner colour step on the 128 owner sites of group g of row r.  pN..pW point at
+// word 4g of row r in the four planes (global memory or LDS).
+template <int MODE>
+__device__ __forceinline__ void owner_group(uint32_t *pN, uint32_t *pS, uint32_t *pE, uint32_t *pW, uint32_t r,
+                                            uint32_t g, uint32_t c, uint32_t t, const Thr &Tall, uint32_t key0,
+                                            uint32_t key1)
+{
+    uint32_t R0[4] = {0u, 0u, 0u, 0u};
+    if (MODE == kUniform) philox4x32_10(g, r, t, c, key0, key1, R0);
     uint32_t N[4], S[4], E[4], W[4];
-    unpack(ld4(base), N);
-    unpack(ld4(base + PS), S);
-    unpack(ld4(base + 2 * PS), E);
-    unpack(ld4(base + 3 * PS), W);
+    ld4(pN, N);
+    ld4(pS, S);
+    ld4(pE, E);
+    ld4(pW, W);
     uint32_t horiz[4], vert[4], live[4];
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
@@ -148,70 +181,55 @@ __global__ void __launch_bounds__(256) domino_owner_step(uint32_t *planes, size_
         live[w] = horiz[w] | vert[w];
     }
     if ((live[0] | live[1] | live[2] | live[3]) == 0u) return;
-    constexpr int NC = DomCtx<METRO>::NC;
-    uint32_t T[NC], cm[NC][4], D[4];
-    DomCtx<METRO>::build(r, c, Tall, vert, T, cm);
-    decide128<NC>(key0, key1, g, r, t, c, T, cm, live, D);
-    uint32_t F[4];
+    uint32_t D[4];
+    decide_group<MODE>(key0, key1, g, r, t, c, Tall, R0, vert, live, D);
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
-        F[w] = (horiz[w] & D[w]) | (vert[w] & ~D[w]);
-        N[w] ^= F[w];
-        S[w] ^= F[w];
-        E[w] ^= F[w];
-        W[w] ^= F[w];
+        const uint32_t F = (horiz[w] & D[w]) | (vert[w] & ~D[w]);
+        N[w] ^= F;
+        S[w] ^= F;
+        E[w] ^= F;
+        W[w] ^= F;
     }
-    st4(base, N);
-    st4(base + PS, S);
-    st4(base + 2 * PS, E);
-    st4(base + 3 * PS, W);
+    st4(pN, N);
+    st4(pS, S);
+    st4(pE, E);
+    st4(pW, W);
 }
 
-// One colour step of the other colour.  Its site (r, k) uses bits N(r,k),
-// W(r+1,k) (aligned) and S(r+1,k+1), E(r,k+1) (shifted by one bit).  Bit 0 of
+// Other-colour step on the 128 sites of group g of row r.  rowN, rowE point at
+// word 4g of owner row r (planes N, E); rowS1, rowW1 at word 4g of owner row r+1
+// (planes S, W).  Word 4g+4 of rowE and rowS1 must exist (padding).  Bit 0 of
 // the first word of a group in the shifted planes belongs to the previous
-// group's last site, so the first and carry words are updated atomically.
-template <bool METRO>
-__global__ void __launch_bounds__(256) domino_other_step(uint32_t *planes, size_t PS, uint32_t RS,
-                                                         uint32_t ng, uint32_t n, uint32_t c,
-                                                         uint32_t t, Thr Tall, uint32_t key0,
-                                                         uint32_t key1)
+// group's last site, so the first and the carry words are updated atomically.
+template <int MODE>
+__device__ __forceinline__ void other_group(uint32_t *rowN, uint32_t *rowE, uint32_t *rowS1, uint32_t *rowW1,
+                                            uint32_t r, uint32_t g, uint32_t c, uint32_t t, const Thr &Tall,
+                                            uint32_t key0, uint32_t key1)
 {
-    const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t g = gid % ng, r = gid / ng;
-    if (r + 1u >= n) return;   // the other colour has rows 0 .. n-2
-    uint32_t *rowN = planes + (size_t)r * RS + 4u * g;
-    uint32_t *rowE = planes + 2 * PS + (size_t)r * RS + 4u * g;
-    uint32_t *rowS1 = planes + PS + (size_t)(r + 1) * RS + 4u * g;
-    uint32_t *rowW1 = planes + 3 * PS + (size_t)(r + 1) * RS + 4u * g;
+    uint32_t R0[4] = {0u, 0u, 0u, 0u};
+    if (MODE == kUniform) philox4x32_10(g, r, t, c, key0, key1, R0);
     uint32_t oN[4], oE[4], oS1[4], oW1[4];
-    unpack(ld4(rowN), oN);
-    unpack(ld4(rowE), oE);
-    unpack(ld4(rowS1), oS1);
-    unpack(ld4(rowW1), oW1);
+    ld4(rowN, oN);
+    ld4(rowE, oE);
+    ld4(rowS1, oS1);
+    ld4(rowW1, oW1);
     const uint32_t eNext = rowE[4], sNext = rowS1[4];
-    uint32_t sN[4], sS[4], sE[4], sW[4];
+    uint32_t horiz[4], vert[4], live[4];
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
         const uint32_t eHi = (w < 3) ? oE[w + 1] : eNext;
         const uint32_t sHi = (w < 3) ? oS1[w + 1] : sNext;
-        sS[w] = oN[w];
-        sE[w] = oW1[w];
-        sN[w] = (oS1[w] >> 1) | (sHi << 31);
-        sW[w] = (oE[w] >> 1) | (eHi << 31);
-    }
-    uint32_t horiz[4], vert[4], live[4];
-#pragma unroll
-    for (int w = 0; w < 4; ++w) {
-        horiz[w] = sN[w] & sS[w];
-        vert[w] = sE[w] & sW[w];
+        const uint32_t sS = oN[w], sE = oW1[w];
+        const uint32_t sN = (oS1[w] >> 1) | (sHi << 31);
+        const uint32_t sW = (oE[w] >> 1) | (eHi << 31);
+        horiz[w] = sN & sS;
+        vert[w] = sE & sW;
         live[w] = horiz[w] | vert[w];
     }
     if ((live[0] | live[1] | live[2] | live[3]) == 0u) return;
-    constexpr int NC = DomCtx<METRO>::NC;
-    uint32_t T[NC], cm[NC][4], D[4];
-    DomCtx<METRO>::build(r, c, Tall, vert, T, cm);
-    decide128<NC>(key0, key1, g, r, t, c, T, cm, live, D);
+    uint32_t D[4];
+    decide_group<MODE>(key0, key1, g, r, t, c, Tall, R0, vert, live, D);
     uint32_t F[4];
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
@@ -236,9 +254,96 @@ __global__ void __launch_bounds__(256) domino_other_step(uint32_t *planes, size_
     }
 }
 
+// ---------------------------------------------------------- streaming kernels
+template <int MODE>
+__global__ void __launch_bounds__(256) domino_owner_step(uint32_t *planes, size_t PS, uint32_t RS, uint32_t ng,
+                                                         uint32_t n, uint32_t c, uint32_t t, Thr Tall,
+                                                         uint32_t key0, uint32_t key1)
+{
+    const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t g = gid % ng, r = gid / ng;
+    if (r >= n) return;
+    uint32_t *base = planes + (size_t)r * RS + 4u * g;
+    owner_group<MODE>(base, base + PS, base + 2 * PS, base + 3 * PS, r, g, c, t, Tall, key0, key1);
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(256) domino_other_step(uint32_t *planes, size_t PS, uint32_t RS, uint32_t ng,
+                                                         uint32_t n, uint32_t c, uint32_t t, Thr Tall,
+                                                         uint32_t key0, uint32_t key1)
+{
+    const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t g = gid % ng, r = gid / ng;
+    if (r + 1u >= n) return;   // the other colour has rows 0 .. n-2
+    uint32_t *row = planes + (size_t)r * RS + 4u * g;
+    other_group<MODE>(row, row + 2 * PS, row + PS + RS, row + 3 * PS + RS, r, g, c, t, Tall, key0, key1);
+}
+
+// -------------------------------------------------------------- tiled kernel
+// Block = one tile.  Local (lr, lg) is global row R0 + lr, group G0 + lg.  LDS:
+// 4 planes x LR rows x LRS words (LRS = 4*LG + 4: one zero pad group per row).
+// One thread per (row, group) task; blockDim >= LR * LG.
+template <int MODE>
+__global__ void __launch_bounds__(1024) domino_tiled_kernel(const uint32_t *__restrict__ in,
+                                                            uint32_t *__restrict__ out, size_t PS, uint32_t RS,
+                                                            uint32_t ng, uint32_t n, uint32_t omega, uint32_t t0,
+                                                            uint32_t nsweeps, uint32_t TR, uint32_t TG,
+                                                            uint32_t HR, uint32_t HG, uint32_t tiles_x,
+                                                            Thr Tall, uint32_t key0, uint32_t key1)
+{
+    extern __shared__ uint32_t lds[];
+    const uint32_t LR = TR + 2 * HR, LG = TG + 2 * HG, LRS = 4 * LG + 4;
+    const uint32_t LPS = LR * LRS;
+    const uint32_t tile_r = blockIdx.x / tiles_x, tile_g = blockIdx.x % tiles_x;
+    const int R0 = (int)(tile_r * TR) - (int)HR, G0 = (int)(tile_g * TG) - (int)HG;
+    const uint32_t tid = threadIdx.x;
+
+    // load tile + halo (zero outside the state), one uint4 per item
+    const uint32_t items = 4 * LR * (LG + 1);
+    for (uint32_t i = tid; i < items; i += blockDim.x) {
+        const uint32_t lg = i % (LG + 1), lr = (i / (LG + 1)) % LR, p = i / ((LG + 1) * LR);
+        const int gr = R0 + (int)lr, gg = G0 + (int)lg;
+        uint32_t v[4] = {0u, 0u, 0u, 0u};
+        if (lg < LG && gr >= 0 && gr < (int)n && gg >= 0 && gg < (int)ng)
+            ld4(in + p * PS + (size_t)gr * RS + 4 * gg, v);
+        st4(lds + p * LPS + lr * LRS + 4 * lg, v);
+    }
+    __syncthreads();
+
+    const uint32_t lr = tid / LG, lg = tid % LG;
+    const int gr = R0 + (int)lr, gg = G0 + (int)lg;
+    const bool active = tid < LR * LG && gr >= 0 && gr < (int)n && gg >= 0 && gg < (int)ng;
+    uint32_t *pN = lds + lr * LRS + 4 * lg;
+    for (uint32_t s = 0; s < nsweeps; ++s) {
+        const uint32_t t = t0 + s;
+        for (uint32_t c = 0; c < 2; ++c) {
+            if (active) {
+                if (c == omega)
+                    owner_group<MODE>(pN, pN + LPS, pN + 2 * LPS, pN + 3 * LPS, (uint32_t)gr, (uint32_t)gg, c, t,
+                                       Tall, key0, key1);
+                else if (lr + 1 < LR)
+                    other_group<MODE>(pN, pN + 2 * LPS, pN + LPS + LRS, pN + 3 * LPS + LRS, (uint32_t)gr,
+                                       (uint32_t)gg, c, t, Tall, key0, key1);
+            }
+            __syncthreads();
+        }
+    }
+
+    // store the interior
+    const uint32_t oitems = 4 * TR * TG;
+    for (uint32_t i = tid; i < oitems; i += blockDim.x) {
+        const uint32_t ig = i % TG, ir = (i / TG) % TR, p = i / (TG * TR);
+        const uint32_t orow = tile_r * TR + ir, og = tile_g * TG + ig;
+        if (orow >= n || og >= ng) continue;
+        uint32_t v[4];
+        ld4(lds + p * LPS + (ir + HR) * LRS + 4 * (ig + HG), v);
+        st4(out + p * PS + (size_t)orow * RS + 4 * og, v);
+    }
+}
+
 // Crossing bit of an owner's edge plane p at box vertex (P, Q) (0 outside).
-__device__ __forceinline__ uint32_t owner_bit(const uint32_t *planes, size_t PS, uint32_t RS, int n,
-                                              int p, int P, int Q)
+__device__ __forceinline__ uint32_t owner_bit(const uint32_t *planes, size_t PS, uint32_t RS, int n, int p, int P,
+                                              int Q)
 {
     const int r2 = P + Q - n - 1, k2 = Q - P + n - 1;
     if (r2 < 0 || k2 < 0) return 0u;
@@ -248,13 +353,11 @@ __device__ __forceinline__ uint32_t owner_bit(const uint32_t *planes, size_t PS,
 }
 
 // Horizontal segment (P,Q)-(P+1,Q) and vertical segment (P,Q)-(P,Q+1).
-__device__ __forceinline__ uint32_t hseg(const uint32_t *pl, size_t PS, uint32_t RS, int n, int om, int P,
-                                         int Q)
+__device__ __forceinline__ uint32_t hseg(const uint32_t *pl, size_t PS, uint32_t RS, int n, int om, int P, int Q)
 {
     return (((P + Q) & 1) == om) ? owner_bit(pl, PS, RS, n, 2, P, Q) : owner_bit(pl, PS, RS, n, 3, P + 1, Q);
 }
-__device__ __forceinline__ uint32_t vseg(const uint32_t *pl, size_t PS, uint32_t RS, int n, int om, int P,
-                                         int Q)
+__device__ __forceinline__ uint32_t vseg(const uint32_t *pl, size_t PS, uint32_t RS, int n, int om, int P, int Q)
 {
     return (((P + Q) & 1) == om) ? owner_bit(pl, PS, RS, n, 0, P, Q) : owner_bit(pl, PS, RS, n, 1, P, Q + 1);
 }
@@ -264,8 +367,7 @@ __device__ __forceinline__ bool face_in(int n, int X, int Y)
     return abs(2 * X - 2 * n + 1) + abs(2 * Y - 2 * n + 1) <= 2 * n;
 }
 
-__global__ void domino_export_kernel(const uint32_t *pl, size_t PS, uint32_t RS, int n, int om,
-                                     uint8_t *faces)
+__global__ void domino_export_kernel(const uint32_t *pl, size_t PS, uint32_t RS, int n, int om, uint8_t *faces)
 {
     const int X = blockIdx.x * 16 + threadIdx.x, Y = blockIdx.y * 16 + threadIdx.y;
     if (X >= 2 * n || Y >= 2 * n) return;
@@ -279,15 +381,51 @@ __global__ void domino_export_kernel(const uint32_t *pl, size_t PS, uint32_t RS,
     faces[(size_t)Y * (2 * n) + X] = d;
 }
 
-// Per face: covered by a horizontal domino (one of its vertical sides crossed).
-__global__ void domino_observe_kernel(const uint32_t *pl, size_t PS, uint32_t RS, int n, int om,
-                                      uint32_t B, uint32_t bins_x, unsigned long long *bins)
+// Faces covered by horizontal dominoes = the two faces beside every crossed
+// vertical edge, i.e. beside the crossed N and S edges of the owners.  One
+// thread per owner word; owner (r, k) is box vertex (X, Y) = (r-k+n, r+k+1):
+// a crossed N edge covers faces (X-1, Y) and (X, Y), a crossed S edge faces
+// (X-1, Y-1) and (X, Y-1).  Counts go to a block-local copy of the bins in LDS
+// (when they fit) and are flushed with one global atomic per touched bin.
+constexpr uint32_t kLdsBins = 8192;
+
+__global__ void __launch_bounds__(256) domino_observe_kernel(const uint32_t *pl, size_t PS, uint32_t RS, int n,
+                                                             uint32_t nw, uint32_t B, uint32_t bins_x,
+                                                             uint32_t nbins, unsigned long long *bins)
 {
-    const int X = blockIdx.x * 16 + threadIdx.x, Y = blockIdx.y * 16 + threadIdx.y;
-    const bool valid = X < 2 * n && Y < 2 * n && face_in(n, X, Y);
-    uint64_t q = 0;
-    if (valid) q = vseg(pl, PS, RS, n, om, X, Y) | vseg(pl, PS, RS, n, om, X + 1, Y);
-    bin_add(q, X, Y, valid, B, bins_x, bins);
+    extern __shared__ uint32_t lbin[];
+    const bool local = nbins <= kLdsBins;
+    if (local) {
+        for (uint32_t i = threadIdx.x; i < nbins; i += blockDim.x) lbin[i] = 0u;
+        __syncthreads();
+    }
+    const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t r = gid / nw, w = gid % nw;
+    if (r < (uint32_t)n) {
+        for (int p = 0; p < 2; ++p) {
+            uint32_t m = pl[(size_t)p * PS + (size_t)r * RS + w];
+            while (m) {
+                const int b = __builtin_ctz(m);
+                m &= m - 1u;
+                const int k = (int)(w * 32u) + b;
+                const int X = (int)r - k + n, Y = (int)r + k + 1 - p;   // face row of the crossed edge
+                const uint32_t i0 = (uint32_t)(Y / (int)B) * bins_x + (uint32_t)((X - 1) / (int)B);
+                const uint32_t i1 = (uint32_t)(Y / (int)B) * bins_x + (uint32_t)(X / (int)B);
+                if (local) {
+                    atomicAdd(&lbin[i0], 1u);
+                    atomicAdd(&lbin[i1], 1u);
+                } else {
+                    atomicAdd(&bins[i0], 1ull);
+                    atomicAdd(&bins[i1], 1ull);
+                }
+            }
+        }
+    }
+    if (local) {
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < nbins; i += blockDim.x)
+            if (lbin[i]) atomicAdd(&bins[i], (unsigned long long)lbin[i]);
+    }
 }
 
 }  // namespace
@@ -295,33 +433,89 @@ __global__ void domino_observe_kernel(const uint32_t *pl, size_t PS, uint32_t RS
 hipError_t domino_init(const DominoDev &d, int init_max, hipStream_t s)
 {
     dim3 block(64), grid((d.RS + 63) / 64, d.n + 1);
-    hipLaunchKernelGGL(domino_init_kernel, grid, block, 0, s, d.planes, d.PS, d.RS, d.n, init_max);
+    hipLaunchKernelGGL(domino_init_kernel, grid, block, 0, s, d.planes, d.spare, d.PS, d.RS, d.n, init_max);
     return hipGetLastError();
 }
 
 hipError_t domino_colour_step(const DominoDev &d, int colour, uint32_t t, const Thr &T, int metropolis,
-                              uint64_t seed, hipStream_t s)
+                              uint64_t seed, hipStream_t s, Timing *tm)
 {
     const uint32_t key0 = (uint32_t)seed, key1 = (uint32_t)(seed >> 32);
     const uint32_t threads = d.ng * (uint32_t)d.n;
     dim3 block(256), grid((threads + 255) / 256);
     const bool owner = colour == d.omega;
-    if (owner) {
-        if (metropolis)
-            hipLaunchKernelGGL(domino_owner_step<true>, grid, block, 0, s, d.planes, d.PS, d.RS, d.ng,
-                               (uint32_t)d.n, (uint32_t)colour, t, T, key0, key1);
-        else
-            hipLaunchKernelGGL(domino_owner_step<false>, grid, block, 0, s, d.planes, d.PS, d.RS, d.ng,
-                               (uint32_t)d.n, (uint32_t)colour, t, T, key0, key1);
-    } else {
-        if (metropolis)
-            hipLaunchKernelGGL(domino_other_step<true>, grid, block, 0, s, d.planes, d.PS, d.RS, d.ng,
-                               (uint32_t)d.n, (uint32_t)colour, t, T, key0, key1);
-        else
-            hipLaunchKernelGGL(domino_other_step<false>, grid, block, 0, s, d.planes, d.PS, d.RS, d.ng,
-                               (uint32_t)d.n, (uint32_t)colour, t, T, key0, key1);
+    const uint32_t n = (uint32_t)d.n, c = (uint32_t)colour;
+    if (owner)
+    {
+        auto k = T.uniform() ? domino_owner_step<kUniform>
+                             : (metropolis ? domino_owner_step<kMetropolis> : domino_owner_step<kHeatBath>);
+        return launch(tm, 1, k, grid, block, 0, s, d.planes, d.PS, d.RS, d.ng, n, c, t, T, key0, key1);
     }
-    return hipGetLastError();
+    auto k = T.uniform() ? domino_other_step<kUniform>
+                         : (metropolis ? domino_other_step<kMetropolis> : domino_other_step<kHeatBath>);
+    return launch(tm, 1, k, grid, block, 0, s, d.planes, d.PS, d.RS, d.ng, n, c, t, T, key0, key1);
+}
+
+DominoTile domino_auto_tile(int n)
+{
+    DominoTile t;
+    uint32_t ng, RS;
+    size_t PS;
+    domino_words(n, &ng, &RS, &PS);
+    if ((uint32_t)n <= 128 && ng <= 4) {   // whole domain in one tile, no halo
+        t.TR = (uint32_t)n;
+        t.TG = ng;
+        t.S = 1u << 30;
+        return t;
+    }
+    t.TR = 32;
+    t.TG = ng < 4 ? ng : 4;
+    t.S = 16;   // measured best on MI355X for order 2048 (tile 32 rows x 4 groups)
+    return t;
+}
+
+hipError_t domino_tiled_sweeps(DominoDev &d, const DominoTile &tile, uint32_t t0, uint32_t nsw, const Thr &T,
+                               int metropolis, uint64_t seed, hipStream_t s, Timing *tm)
+{
+    const uint32_t key0 = (uint32_t)seed, key1 = (uint32_t)(seed >> 32);
+    const uint32_t n = (uint32_t)d.n;
+    const uint32_t TG = tile.TG == 0 ? 1u : (tile.TG < d.ng ? tile.TG : d.ng);
+    const uint32_t tiles_x = (d.ng + TG - 1) / TG;
+    const uint32_t LG0 = TG + (tiles_x > 1 ? 2u : 0u);
+    const uint32_t max_rows = 1024u / LG0;   // one thread per (row, group) task
+    if (max_rows < 3u) return hipErrorInvalidConfiguration;
+    uint32_t TR = tile.TR == 0 ? 1u : (tile.TR < n ? tile.TR : n);
+    if (TR < n && TR > max_rows - 2u) TR = max_rows - 2u;   // leave room for a halo
+    if (TR >= n && n > max_rows) TR = max_rows - 2u;
+    const uint32_t tiles_y = (n + TR - 1) / TR;
+    uint32_t done = 0;
+    while (done < nsw) {
+        uint32_t S = nsw - done;
+        if (S > tile.S) S = tile.S;
+        if (tiles_x > 1 && S > 128u) S = 128u;   // the one-group column halo covers 128 sweeps
+        if (tiles_y > 1 && S > (max_rows - TR) / 2u) S = (max_rows - TR) / 2u;
+        if (S == 0u) S = 1u;
+        const uint32_t HR = tiles_y > 1 ? S : 0u;
+        const uint32_t HG = tiles_x > 1 ? 1u : 0u;
+        const uint32_t LR = TR + 2 * HR, LG = TG + 2 * HG;
+        const uint32_t tasks = LR * LG;
+        if (tasks > 1024) return hipErrorInvalidConfiguration;
+        const uint32_t threads = (tasks + 63) / 64 * 64;
+        const uint32_t shmem = 4u * LR * (4u * LG + 4u) * 4u;
+        if (shmem > 160u * 1024u) return hipErrorInvalidConfiguration;
+        dim3 grid(tiles_x * tiles_y), block(threads);
+        hipError_t e;
+        auto k = T.uniform() ? domino_tiled_kernel<kUniform>
+                             : (metropolis ? domino_tiled_kernel<kMetropolis> : domino_tiled_kernel<kHeatBath>);
+        e = launch(tm, 2 * S, k, grid, block, shmem, s, (const uint32_t *)d.planes, d.spare, d.PS, d.RS, d.ng, n,
+                   (uint32_t)d.omega, t0 + done, S, TR, TG, HR, HG, tiles_x, T, key0, key1);
+        if (e != hipSuccess) return e;
+        uint32_t *tmp = d.planes;
+        d.planes = d.spare;
+        d.spare = tmp;
+        done += S;
+    }
+    return hipSuccess;
 }
 
 hipError_t domino_export(const DominoDev &d, uint8_t *faces, hipStream_t s)
@@ -331,12 +525,16 @@ hipError_t domino_export(const DominoDev &d, uint8_t *faces, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t domino_observe(const DominoDev &d, uint32_t B, uint32_t bins_x, unsigned long long *bins,
-                          hipStream_t s)
+hipError_t domino_observe(const DominoDev &d, uint32_t B, uint32_t bins_x, unsigned long long *bins, hipStream_t s)
 {
-    dim3 block(16, 16), grid((2 * d.n + 15) / 16, (2 * d.n + 15) / 16);
-    hipLaunchKernelGGL(domino_observe_kernel, grid, block, 0, s, d.planes, d.PS, d.RS, d.n, d.omega, B,
-                       bins_x, bins);
+    const uint32_t nw = (uint32_t)((d.n + 31) / 32);
+    const uint32_t bins_y = (2u * (uint32_t)d.n + B - 1) / B;
+    const uint32_t nbins = bins_x * bins_y;
+    const uint32_t threads = nw * (uint32_t)d.n;
+    dim3 block(256), grid((threads + 255) / 256);
+    const uint32_t shmem = nbins <= kLdsBins ? nbins * 4u : 0u;
+    hipLaunchKernelGGL(domino_observe_kernel, grid, block, shmem, s, d.planes, d.PS, d.RS, d.n, nw, B, bins_x, nbins,
+                       bins);
     return hipGetLastError();
 }
 

@@ -2,16 +2,97 @@
 // kernel launchers.  Every launcher enqueues on the given stream and returns the
 // HIP status of the launch.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
+
+#include <vector>
 
 namespace tl {
 
 // Threshold values handed to a colour-step kernel by value.
 struct Thr {
     uint32_t v[32];
+    uint32_t count;
+    // every threshold is 2^31: one random bit per site decides
+    bool uniform() const
+    {
+        for (uint32_t i = 0; i < count; ++i)
+            if (v[i] != 0x80000000u) return false;
+        return count > 0;
+    }
 };
+
+// Optional per-launch kernel timing: when enabled, sweep kernels are launched
+// with hipExtLaunchKernelGGL and a start/stop event pair recorded by the
+// dispatch itself; collect() (after the stream has been synchronised) adds the
+// elapsed times.  `steps` counts the colour steps each launch performed.
+struct Timing {
+    bool on = false;
+    uint32_t every = 1;       // time one launch in `every`
+    uint64_t counter = 0;
+    std::vector<hipEvent_t> pool;
+    std::vector<hipEvent_t> pending;      // start, stop, start, stop, ...
+    std::vector<uint32_t> pending_steps;
+    double ms = 0.0;
+    uint64_t launches = 0, steps = 0;
+
+    hipError_t events(hipEvent_t *a, hipEvent_t *b)
+    {
+        for (hipEvent_t *e : {a, b}) {
+            if (!pool.empty()) {
+                *e = pool.back();
+                pool.pop_back();
+            } else {
+                hipError_t err = hipEventCreate(e);
+                if (err != hipSuccess) return err;
+            }
+        }
+        return hipSuccess;
+    }
+    hipError_t collect()
+    {
+        for (size_t i = 0; i + 1 < pending.size(); i += 2) {
+            float t = 0.f;
+            hipError_t e = hipEventElapsedTime(&t, pending[i], pending[i + 1]);
+            if (e != hipSuccess) return e;
+            ms += t;
+            launches += 1;
+            steps += pending_steps[i / 2];
+            pool.push_back(pending[i]);
+            pool.push_back(pending[i + 1]);
+        }
+        pending.clear();
+        pending_steps.clear();
+        return hipSuccess;
+    }
+    void release()
+    {
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+        for (hipEvent_t e : pending) (void)hipEventDestroy(e);
+        pool.clear();
+        pending.clear();
+    }
+};
+
+template <typename F, typename... Args>
+hipError_t launch(Timing *tm, uint32_t steps, F kernel, dim3 grid, dim3 block, uint32_t shmem, hipStream_t s,
+                  Args... args)
+{
+    if (tm && tm->on && (tm->counter++ % tm->every) == 0) {
+        hipEvent_t a, b;
+        hipError_t e = tm->events(&a, &b);
+        if (e != hipSuccess) return e;
+        hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, a, b, 0, args...);
+        tm->pending.push_back(a);
+        tm->pending.push_back(b);
+        tm->pending_steps.push_back(steps);
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, shmem, s, args...);
+    }
+    return hipGetLastError();
+}
 
 // ---------------------------------------------------------------- domino
 // Aztec diamond of order n in the owner frame: the owner colour
@@ -27,12 +108,23 @@ struct DominoDev {
     uint32_t ng = 0;   // groups of 128 sites per row
     uint32_t RS = 0;   // row stride in words
     size_t PS = 0;     // plane stride in words
-    uint32_t *planes = nullptr;
+    uint32_t *planes = nullptr;   // current state
+    uint32_t *spare = nullptr;    // second buffer of the tiled kernel (same layout)
+};
+// Tile of the multi-sweep kernel: TR owner rows x TG groups of 4 words, run for
+// up to S sweeps per launch with an S-row halo above and below and a one-group
+// halo left and right (a dimension covered by one tile needs no halo).
+struct DominoTile {
+    uint32_t TR = 32, TG = 4, S = 8;
 };
 size_t domino_words(int n, uint32_t *ng, uint32_t *RS, size_t *PS);
 hipError_t domino_init(const DominoDev &d, int init_max, hipStream_t s);
 hipError_t domino_colour_step(const DominoDev &d, int colour, uint32_t t, const Thr &T, int metropolis,
-                              uint64_t seed, hipStream_t s);
+                              uint64_t seed, hipStream_t s, Timing *tm = nullptr);
+// Sweeps t0 .. t0+n-1 with the tiled kernel; swaps d.planes / d.spare.
+hipError_t domino_tiled_sweeps(DominoDev &d, const DominoTile &tile, uint32_t t0, uint32_t n, const Thr &T,
+                               int metropolis, uint64_t seed, hipStream_t s, Timing *tm = nullptr);
+DominoTile domino_auto_tile(int n);
 hipError_t domino_export(const DominoDev &d, uint8_t *faces, hipStream_t s);
 hipError_t domino_observe(const DominoDev &d, uint32_t B, uint32_t bins_x, unsigned long long *bins,
                           hipStream_t s);

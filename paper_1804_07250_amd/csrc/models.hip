@@ -17,24 +17,35 @@ public:
     hipError_t allocate() override
     {
         const size_t words = domino_words(d_.n, &d_.ng, &d_.RS, &d_.PS);
-        return hipMalloc(&d_.planes, words * sizeof(uint32_t));
+        hipError_t e = hipMalloc(&d_.planes, words * sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMalloc(&d_.spare, words * sizeof(uint32_t));
+        return e;
     }
     void release() override
     {
         if (d_.planes) (void)hipFree(d_.planes);
-        d_.planes = nullptr;
+        if (d_.spare) (void)hipFree(d_.spare);
+        d_.planes = d_.spare = nullptr;
+        timing.release();
     }
     hipError_t init(bool init_max, hipStream_t s) override { return domino_init(d_, init_max ? 1 : 0, s); }
 
-    hipError_t sweeps(uint32_t t0, uint32_t n, const Thr &T, bool metro, uint64_t seed, const tl_options &,
+    hipError_t sweeps(uint32_t t0, uint32_t n, const Thr &T, bool metro, uint64_t seed, const tl_options &opt,
                       hipStream_t s) override
     {
-        for (uint32_t i = 0; i < n; ++i)
-            for (int c = 0; c < 2; ++c) {
-                hipError_t e = domino_colour_step(d_, c, t0 + i, T, metro ? 1 : 0, seed, s);
-                if (e != hipSuccess) return e;
-            }
-        return hipSuccess;
+        if (opt.kernel == 1) {   // one launch per colour step
+            for (uint32_t i = 0; i < n; ++i)
+                for (int c = 0; c < 2; ++c) {
+                    hipError_t e = domino_colour_step(d_, c, t0 + i, T, metro ? 1 : 0, seed, s, &timing);
+                    if (e != hipSuccess) return e;
+                }
+            return hipSuccess;
+        }
+        DominoTile tile = domino_auto_tile(d_.n);
+        if (opt.tile_rows) tile.TR = opt.tile_rows;
+        if (opt.tile_groups) tile.TG = opt.tile_groups;
+        if (opt.sweeps_per_launch) tile.S = opt.sweeps_per_launch;
+        return domino_tiled_sweeps(d_, tile, t0, n, T, metro ? 1 : 0, seed, s, &timing);
     }
     hipError_t observe(uint32_t B, uint32_t bins_x, unsigned long long *bins, hipStream_t s) override
     {
@@ -100,6 +111,8 @@ public:
     }
     uint64_t sites() const override { return 2ull * d_.n * d_.n - 2ull * d_.n + 1ull; }
     int colours() const override { return 2; }
+    // 4 bits per owner site (n^2 owners), read and written: n^2 bytes
+    double bytes_per_colour_step() const override { return 2.0 * 4.0 * (double)d_.n * d_.n / 8.0; }
 
 private:
     DominoDev d_;

@@ -30,6 +30,9 @@ public:
     virtual bool import_canonical(const uint8_t *host, hipStream_t s, std::string &why, hipError_t *err) = 0;
     virtual uint64_t sites() const = 0;
     virtual int colours() const = 0;
+    // Algorithmic bytes of one colour step: the packed state read and written once.
+    virtual double bytes_per_colour_step() const = 0;
+    Timing timing;
 };
 
 std::unique_ptr<Model> make_model(const tl_domain &d, std::string &why);

@@ -136,19 +136,68 @@ def test_import_rejects_invalid():
 
 
 def test_full_size_order_2048_one_sweep_sampled():
-    # Order 2048 (the large plain-path workload): after a few sweeps from the
-    # brick tiling the GPU state is loaded into the oracle, both run one more
-    # sweep at a late sweep index, and the exports must agree bit for bit.
+    # Order 2048 (the large plain-path workload): after 1500 sweeps from the
+    # brick tiling (a wide disordered band) the GPU state is loaded into the
+    # oracle, both run one more sweep, and the exports must agree bit for bit.
     tl = need_gpu()
     say("domino order 2048 one-sweep parity")
     n = 2048
     s = gpu_sampler(tl, n, seed=7)
-    s.sweep(3)
+    s.sweep(1500)
     mid = s.export()
     o = oracle.DominoOracle(n, thr_uniform(), seed=7)
     o.load(mid)
-    o.t = 3
+    o.t = 1500
     s.sweep(1)
     o.sweep(1)
     assert (s.export() == o.export()).all()
     assert s.hash() == oracle.canonical_hash(o.export())
+
+
+@pytest.mark.parametrize("n,tile_rows,spl", [(100, 8, 3), (257, 16, 5), (700, 32, 8), (700, 24, 130), (333, 40, 1)])
+def test_tiled_kernel_parity(n, tile_rows, spl):
+    # multi-tile launches with row and column halos, several sweeps per launch
+    tl = need_gpu()
+    say("domino tiled parity n=%d tile_rows=%d sweeps_per_launch=%d" % (n, tile_rows, spl))
+    s = gpu_sampler(tl, n, seed=21, kernel=2, tile_rows=tile_rows, sweeps_per_launch=spl)
+    o = oracle.DominoOracle(n, thr_uniform(), seed=21)
+    s.sweep(13)
+    o.sweep(13)
+    assert (s.export() == o.export()).all()
+
+
+@pytest.mark.parametrize("n", [9, 130, 700])
+def test_streaming_kernel_parity(n):
+    tl = need_gpu()
+    s = gpu_sampler(tl, n, seed=4, kernel=1)
+    o = oracle.DominoOracle(n, thr_uniform(), seed=4)
+    s.sweep(10)
+    o.sweep(10)
+    assert (s.export() == o.export()).all()
+
+
+def test_streaming_equals_tiled_order_2048():
+    tl = need_gpu()
+    say("domino order 2048 streaming vs tiled")
+    a = gpu_sampler(tl, 2048, seed=7, kernel=1)
+    b = gpu_sampler(tl, 2048, seed=7, kernel=2)
+    a.sweep(300)
+    b.sweep(300)
+    assert a.hash() == b.hash()
+    assert (a.export() == b.export()).all()
+
+
+def test_reset_and_timing():
+    tl = need_gpu()
+    s = gpu_sampler(tl, 300, seed=2, obs_every=5, obs_bin=64)
+    s.set_timing(True)
+    s.sweep(20)
+    h1 = s.hash()
+    o1 = s.observables()
+    ms, launches, steps, bpc = s.kernel_time()
+    assert launches > 0 and steps == 40 and ms > 0 and bpc == 300 * 300
+    s.reset(2)
+    s.sweep(20)
+    assert s.hash() == h1
+    o2 = s.observables()
+    assert (o1["bin_sum"] == o2["bin_sum"]).all() and o2["samples"] == 4
