@@ -1,0 +1,548 @@
+// Lozenge tilings of the a x b x c hexagon and the six-vertex model with
+// domain-wall boundary: the two height-function models (Section 1.2).
+//
+// Both store one bit per height site (a 1-bit residual of the height):
+//   lozenge    H(X, Y) mod 2 per triangular vertex; along (1,0), (0,1), (1,1) H
+//              changes by 0 or -1, so the parity of two neighbours fixes their
+//              difference.  Plane s = X mod 3 holds the vertices X = 3k + s of a
+//              row, so one plane of a row is exactly one colour class (colour
+//              (X + Y) mod 3).
+//   six-vertex floor(h/2) mod 2 per face; neighbouring faces differ by +-1 and
+//              h = (I + J) mod 2 + 2 floor(h/2), so the bit fixes the sign.
+//              Plane p = I mod 2; colour (I mod 2) + 2 (J mod 2).
+// A colour step updates one plane of every other row (six-vertex) or one plane
+// of every row (lozenge); each site writes only its own bit, reading the other
+// planes of its row and of the rows above and below.
+//
+// Lozenge move (Section 1.2, lozenge rotations): a vertex is rotateable iff its
+// forward neighbours (X+1,Y), (X,Y+1), (X+1,Y+1) share a height f and its
+// backward neighbours share f+1; up (add a cube) sets H = f+1, which has the
+// parity of the backward neighbours, down sets H = f.
+// Six-vertex move (c-flip): a face is flippable iff its four edge neighbours
+// share a height m; up sets m+1.  A diagonal face is "high" iff it is at m+1.
+// Context of the weights: sA = #high among NE, SW (corners carrying a) and
+// sB = #high among NW, SE (corners carrying b); W_up/W_down depends on (sA, sB)
+// only.
+#include "../../include/tilings.h"
+#include "height_common.hpp"
+#include "internal.hpp"
+
+namespace tl {
+
+size_t height_words(HeightDev &d)
+{
+    if (d.model == TL_LOZENGE) {
+        d.P = 3;
+        d.rows = (uint32_t)(d.b + d.c + 1);
+        d.K = (uint32_t)((d.a + d.c + 3) / 3);
+    } else {
+        d.P = 2;
+        d.rows = (uint32_t)(d.N + 1);
+        d.K = (uint32_t)((d.N + 2) / 2);
+    }
+    const uint32_t nw = (d.K + 31u) / 32u;
+    d.ng = (nw + 3u) / 4u;
+    d.RS = 4u * (d.ng + 2u);
+    d.PS = (size_t)d.rows * d.RS;
+    return d.P * d.PS;
+}
+
+namespace {
+
+enum { kHeatBath = 0, kMetropolis = 1, kUniform = 2 };
+
+struct Geo {
+    int model, a, b, c, N;
+};
+
+__device__ __forceinline__ int imax(int p, int q) { return p > q ? p : q; }
+__device__ __forceinline__ int imin(int p, int q) { return p < q ? p : q; }
+
+// Lozenge: H_min / H_max at (X, Y) = (x + c, y + c).
+__device__ __forceinline__ int loz_hmin(const Geo &g, int X, int Y) { return imax(0, imax(g.c - X, g.c - Y)); }
+__device__ __forceinline__ int loz_hmax(const Geo &g, int X, int Y)
+{
+    return imin(g.c, imin(g.a + g.c - X, g.b + g.c - Y));
+}
+// Vertices of row Y inside the hexagon: X in [loz_xs, loz_xe].
+__device__ __forceinline__ int loz_xs(const Geo &g, int Y) { return imax(0, Y - g.b); }
+__device__ __forceinline__ int loz_xe(const Geo &g, int Y) { return imin(g.a + g.c, Y + g.a); }
+
+__global__ void height_init_kernel(uint32_t *pa, uint32_t *pb, size_t PS, uint32_t RS, uint32_t rows, uint32_t P,
+                                   Geo geo, int init_max)
+{
+    const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t y = blockIdx.y, p = blockIdx.z;
+    if (w >= RS || y >= rows || p >= P) return;
+    uint32_t bits = 0u;
+    if (w >= 4u) {
+        const int dw = (int)w - 4;
+        for (int bb = 0; bb < 32; ++bb) {
+            const int k = dw * 32 + bb;
+            if (geo.model == TL_LOZENGE) {
+                const int X = 3 * k + (int)p, Y = (int)y;
+                if (X > geo.a + geo.c || X < loz_xs(geo, Y) || X > loz_xe(geo, Y)) continue;
+                const int H = init_max ? loz_hmax(geo, X, Y) : loz_hmin(geo, X, Y);
+                bits |= (uint32_t)(H & 1) << bb;
+            } else {
+                const int I = 2 * k + (int)p, J = (int)y;
+                if (I > geo.N) continue;
+                const int h = init_max ? geo.N - abs(I + J - geo.N) : abs(I - J);
+                bits |= (uint32_t)((h >> 1) & 1) << bb;
+            }
+        }
+    }
+    pa[p * PS + (size_t)y * RS + w] = bits;
+    if (pb) pb[p * PS + (size_t)y * RS + w] = bits;
+}
+
+// Contexts: lozenge heat-bath 1, Metropolis 2 (current up); six-vertex
+// heat-bath 9 classes 3*sA + sB, Metropolis 18 (2*class + current up).
+template <int MODE>
+__device__ __forceinline__ void loz_decide(uint32_t k0, uint32_t k1, uint32_t g, uint32_t r, uint32_t t, uint32_t c,
+                                           const Thr &Tall, const uint32_t (&R0)[4], const uint32_t (&cur)[4],
+                                           const uint32_t (&live)[4], uint32_t (&D)[4])
+{
+    if (MODE == kUniform) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w) D[w] = ~R0[w];
+    } else if (MODE == kHeatBath) {
+        uint32_t T[1] = {Tall.v[0]}, cm[1][4] = {{~0u, ~0u, ~0u, ~0u}};
+        decide128<1>(k0, k1, g, r, t, c, T, cm, live, D);
+    } else {
+        uint32_t T[2] = {Tall.v[0], Tall.v[1]}, cm[2][4];
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            cm[0][w] = ~cur[w];
+            cm[1][w] = cur[w];
+        }
+        decide128<2>(k0, k1, g, r, t, c, T, cm, live, D);
+    }
+}
+
+template <int MODE>
+__device__ __forceinline__ void sixv_decide(uint32_t k0, uint32_t k1, uint32_t g, uint32_t r, uint32_t t, uint32_t c,
+                                            const Thr &Tall, const uint32_t (&R0)[4], const uint32_t (&hNE)[4],
+                                            const uint32_t (&hNW)[4], const uint32_t (&hSW)[4],
+                                            const uint32_t (&hSE)[4], const uint32_t (&cur)[4],
+                                            const uint32_t (&live)[4], uint32_t (&D)[4])
+{
+    if (MODE == kUniform) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w) D[w] = ~R0[w];
+        return;
+    }
+    constexpr int NC = MODE == kMetropolis ? 18 : 9;
+    uint32_t T[NC], cm[NC][4];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) T[i] = Tall.v[i];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const uint32_t A[3] = {~hNE[w] & ~hSW[w], hNE[w] ^ hSW[w], hNE[w] & hSW[w]};
+        const uint32_t B[3] = {~hNW[w] & ~hSE[w], hNW[w] ^ hSE[w], hNW[w] & hSE[w]};
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const uint32_t m = A[i] & B[j];
+                if (MODE == kMetropolis) {
+                    cm[2 * (3 * i + j)][w] = m & ~cur[w];
+                    cm[2 * (3 * i + j) + 1][w] = m & cur[w];
+                } else {
+                    cm[3 * i + j][w] = m;
+                }
+            }
+    }
+    decide128<NC>(k0, k1, g, r, t, c, T, cm, live, D);
+}
+
+// One lozenge group: sites k = 128 g + (0..127) of plane s0 in row Y.
+// base(p, row) -> pointer to word 4 lg of that plane row (data words, pads
+// around it).  lrow is the row index in the addressed array.
+template <int MODE>
+__device__ __forceinline__ void loz_group(uint32_t *base, size_t ps, uint32_t rs, uint32_t lrow, uint32_t lgrp,
+                                          const Geo &geo, int Y, uint32_t g, uint32_t s0, uint32_t colour, uint32_t t,
+                                          const Thr &Tall, uint32_t k0, uint32_t k1)
+{
+    uint32_t R0[4] = {0u, 0u, 0u, 0u};
+    if (MODE == kUniform) philox4x32_10(g, (uint32_t)Y, t, colour, k0, k1, R0);
+    auto P = [&](uint32_t p, uint32_t r) { return base + p * ps + (size_t)r * rs + 4u + 4u * lgrp; };
+    uint32_t O[4], f1[4], f2[4], f3[4], b1[4], b2[4], b3[4];
+    hld4(P(s0, lrow), O);
+    hld4(P(s0, lrow + 1), f2);
+    hld4(P(s0, lrow - 1), b2);
+    if (s0 < 2) {
+        hld4(P(s0 + 1, lrow), f1);
+        hld4(P(s0 + 1, lrow + 1), f3);
+    } else {
+        hld4_plus1(P(0, lrow), f1);
+        hld4_plus1(P(0, lrow + 1), f3);
+    }
+    if (s0 > 0) {
+        hld4(P(s0 - 1, lrow), b1);
+        hld4(P(s0 - 1, lrow - 1), b3);
+    } else {
+        hld4_minus1(P(2, lrow), b1);
+        hld4_minus1(P(2, lrow - 1), b3);
+    }
+    // interior of row Y: X in (max(0, Y-b), min(a+c, Y+a)), X = 3k + s0
+    const int xlo = imax(0, Y - geo.b), xhi = imin(geo.a + geo.c, Y + geo.a);
+    const int klo = floordiv(xlo - (int)s0, 3) + 1, khi = floordiv(xhi - (int)s0 - 1, 3);
+    uint32_t live[4], cur[4];
+    uint32_t any = 0u;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const uint32_t m = range_mask((int)(4 * g) + w, klo, khi);
+        live[w] = ~(f1[w] ^ f2[w]) & ~(f1[w] ^ f3[w]) & ~(b1[w] ^ b2[w]) & ~(b1[w] ^ b3[w]) & (f1[w] ^ b1[w]) & m;
+        cur[w] = ~(O[w] ^ b1[w]);
+        any |= live[w];
+    }
+    if (!any) return;
+    uint32_t D[4];
+    loz_decide<MODE>(k0, k1, g, (uint32_t)Y, t, colour, Tall, R0, cur, live, D);
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const uint32_t nw = (D[w] & b1[w]) | (~D[w] & f1[w]);
+        O[w] = (O[w] & ~live[w]) | (nw & live[w]);
+    }
+    hst4(P(s0, lrow), O);
+}
+
+// One six-vertex group: faces I = 2k + p, k = 128 g + (0..127), of row J.
+template <int MODE>
+__device__ __forceinline__ void sixv_group(uint32_t *base, size_t ps, uint32_t rs, uint32_t lrow, uint32_t lgrp,
+                                           const Geo &geo, int J, uint32_t g, uint32_t p, uint32_t colour, uint32_t t,
+                                           const Thr &Tall, uint32_t k0, uint32_t k1)
+{
+    uint32_t R0[4] = {0u, 0u, 0u, 0u};
+    if (MODE == kUniform) philox4x32_10(g, (uint32_t)J, t, colour, k0, k1, R0);
+    auto P = [&](uint32_t q, uint32_t r) { return base + q * ps + (size_t)r * rs + 4u + 4u * lgrp; };
+    uint32_t O[4], Nn[4], Sn[4], E[4], W[4], NE[4], NW[4], SE[4], SW[4];
+    hld4(P(p, lrow), O);
+    hld4(P(p, lrow + 1), Nn);
+    hld4(P(p, lrow - 1), Sn);
+    if (p == 0) {
+        hld4(P(1, lrow), E);
+        hld4_minus1(P(1, lrow), W);
+        hld4(P(1, lrow + 1), NE);
+        hld4_minus1(P(1, lrow + 1), NW);
+        hld4(P(1, lrow - 1), SE);
+        hld4_minus1(P(1, lrow - 1), SW);
+    } else {
+        hld4_plus1(P(0, lrow), E);
+        hld4(P(0, lrow), W);
+        hld4_plus1(P(0, lrow + 1), NE);
+        hld4(P(0, lrow + 1), NW);
+        hld4_plus1(P(0, lrow - 1), SE);
+        hld4(P(0, lrow - 1), SW);
+    }
+    // interior faces 1 <= I <= N-1
+    const int klo = p == 0 ? 1 : 0, khi = (geo.N - 1 - (int)p) >> 1;
+    const bool podd = ((p + (uint32_t)J) & 1u) != 0u;   // parity of I + J
+    uint32_t live[4], up[4], hNE[4], hNW[4], hSW[4], hSE[4], cur[4];
+    uint32_t any = 0u;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const uint32_t m = range_mask((int)(4 * g) + w, klo, khi);
+        live[w] = ~(E[w] ^ W[w]) & ~(E[w] ^ Nn[w]) & ~(E[w] ^ Sn[w]) & m;
+        up[w] = podd ? E[w] : ~E[w];      // residual bit of m+1
+        hNE[w] = ~(NE[w] ^ up[w]);
+        hNW[w] = ~(NW[w] ^ up[w]);
+        hSW[w] = ~(SW[w] ^ up[w]);
+        hSE[w] = ~(SE[w] ^ up[w]);
+        cur[w] = ~(O[w] ^ up[w]);
+        any |= live[w];
+    }
+    if (!any) return;
+    uint32_t D[4];
+    sixv_decide<MODE>(k0, k1, g, (uint32_t)J, t, colour, Tall, R0, hNE, hNW, hSW, hSE, cur, live, D);
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const uint32_t nw = ~(D[w] ^ up[w]);
+        O[w] = (O[w] & ~live[w]) | (nw & live[w]);
+    }
+    hst4(P(p, lrow), O);
+}
+
+// Which plane of row y holds the sites of colour c (-1: none in this row).
+__device__ __forceinline__ int colour_plane(const Geo &geo, int y, uint32_t c)
+{
+    if (geo.model == TL_LOZENGE) return (int)((c + 3u * 1024u - (uint32_t)y % 3u) % 3u);
+    return ((c >> 1) == ((uint32_t)y & 1u)) ? (int)(c & 1u) : -1;
+}
+
+// Site rows: lozenge 1 .. b+c-1, six-vertex 1 .. N-1.
+__device__ __forceinline__ bool site_row(const Geo &geo, int y, uint32_t rows)
+{
+    return y >= 1 && y <= (int)rows - 2;
+}
+
+template <int MODE>
+__device__ __forceinline__ void height_group(uint32_t *base, size_t ps, uint32_t rs, uint32_t lrow, uint32_t lgrp,
+                                             const Geo &geo, int y, uint32_t g, uint32_t colour, uint32_t t,
+                                             const Thr &T, uint32_t k0, uint32_t k1)
+{
+    const int pl = colour_plane(geo, y, colour);
+    if (pl < 0) return;
+    if (geo.model == TL_LOZENGE)
+        loz_group<MODE>(base, ps, rs, lrow, lgrp, geo, y, g, (uint32_t)pl, colour, t, T, k0, k1);
+    else
+        sixv_group<MODE>(base, ps, rs, lrow, lgrp, geo, y, g, (uint32_t)pl, colour, t, T, k0, k1);
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(256) height_step_kernel(uint32_t *planes, size_t PS, uint32_t RS, uint32_t ng,
+                                                          uint32_t rows, Geo geo, uint32_t colour, uint32_t t, Thr T,
+                                                          uint32_t k0, uint32_t k1)
+{
+    const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t g = gid % ng, y = gid / ng;
+    if (!site_row(geo, (int)y, rows)) return;
+    height_group<MODE>(planes, PS, RS, y, g, geo, (int)y, g, colour, t, T, k0, k1);
+}
+
+// Tiled multi-sweep kernel.  LDS: P planes x LR rows x LRS words, LRS =
+// 4*(LG+2) (the pad groups hold the neighbouring groups, or zero).  Local row
+// lr is global row R0 + lr, local group lg is global group G0 + lg.
+template <int MODE>
+__global__ void __launch_bounds__(1024) height_tiled_kernel(const uint32_t *__restrict__ in,
+                                                            uint32_t *__restrict__ out, size_t PS, uint32_t RS,
+                                                            uint32_t ng, uint32_t rows, uint32_t P, Geo geo,
+                                                            uint32_t K, uint32_t t0, uint32_t nsweeps, uint32_t TR,
+                                                            uint32_t TG, uint32_t HR, uint32_t HG, uint32_t tiles_x,
+                                                            Thr T, uint32_t k0, uint32_t k1)
+{
+    extern __shared__ uint32_t lds[];
+    const uint32_t LR = TR + 2 * HR, LG = TG + 2 * HG, LRS = 4 * (LG + 2);
+    const uint32_t LPS = LR * LRS;
+    const uint32_t tile_r = blockIdx.x / tiles_x, tile_g = blockIdx.x % tiles_x;
+    const int R0 = (int)(tile_r * TR) - (int)HR, G0 = (int)(tile_g * TG) - (int)HG;
+    const uint32_t tid = threadIdx.x;
+
+    // load LR rows x (LG + 2) groups (including the pad groups) per plane
+    const uint32_t items = P * LR * (LG + 2);
+    for (uint32_t i = tid; i < items; i += blockDim.x) {
+        const uint32_t lg = i % (LG + 2), lr = (i / (LG + 2)) % LR, p = i / ((LG + 2) * LR);
+        const int gr = R0 + (int)lr, gg = G0 - 1 + (int)lg;   // global group, -1 .. ng = pads
+        uint32_t v[4] = {0u, 0u, 0u, 0u};
+        if (gr >= 0 && gr < (int)rows && gg >= -1 && gg <= (int)ng)
+            hld4(in + p * PS + (size_t)gr * RS + 4 + 4 * gg, v);
+        hst4(lds + p * LPS + lr * LRS + 4 * lg, v);
+    }
+    __syncthreads();
+
+    const uint32_t lr = tid / LG, lg = tid % LG;
+    const int gr = R0 + (int)lr, gg = G0 + (int)lg;
+    const bool active = tid < LR * LG && lr >= 1 && lr + 1 < LR && gg >= 0 && gg < (int)ng &&
+                        site_row(geo, gr, rows);
+    const uint32_t K_colours = geo.model == TL_LOZENGE ? 3u : 4u;
+    for (uint32_t s = 0; s < nsweeps; ++s) {
+        const uint32_t t = t0 + s;
+        for (uint32_t c = 0; c < K_colours; ++c) {
+            if (active) height_group<MODE>(lds, LPS, LRS, lr, lg, geo, gr, (uint32_t)gg, c, t, T, k0, k1);
+            __syncthreads();
+        }
+    }
+
+    const uint32_t oitems = P * TR * TG;
+    for (uint32_t i = tid; i < oitems; i += blockDim.x) {
+        const uint32_t ig = i % TG, ir = (i / TG) % TR, p = i / (TG * TR);
+        const uint32_t orow = tile_r * TR + ir, og = tile_g * TG + ig;
+        if (orow >= rows || og >= ng) continue;
+        uint32_t v[4];
+        hld4(lds + p * LPS + (ir + HR) * LRS + 4 * (ig + HG + 1), v);
+        hst4(out + p * PS + (size_t)orow * RS + 4 + 4 * og, v);
+    }
+}
+
+__device__ __forceinline__ uint32_t hbit(const uint32_t *pl, size_t PS, uint32_t RS, uint32_t p, uint32_t y,
+                                         uint32_t k)
+{
+    return (pl[p * PS + (size_t)y * RS + 4 + (k >> 5)] >> (k & 31u)) & 1u;
+}
+
+// Height of every site of row y, one thread per row, and the per-cell
+// observable (lozenge H - H_min per vertex; six-vertex: type-c vertices, done
+// separately below).
+__global__ void height_export_kernel(const uint32_t *pl, size_t PS, uint32_t RS, uint32_t rows, Geo geo,
+                                     int32_t *out)
+{
+    const uint32_t y = blockIdx.x * blockDim.x + threadIdx.x;
+    if (y >= rows) return;
+    if (geo.model == TL_LOZENGE) {
+        const int W = geo.a + geo.c + 1, Y = (int)y;
+        const int xs = loz_xs(geo, Y), xe = loz_xe(geo, Y);
+        int H = loz_hmin(geo, xs, Y);
+        uint32_t prev = hbit(pl, PS, RS, (uint32_t)xs % 3u, y, (uint32_t)xs / 3u);
+        for (int X = 0; X < W; ++X) {
+            int32_t v = INT32_MIN;
+            if (X >= xs && X <= xe) {
+                if (X > xs) {
+                    const uint32_t bx = hbit(pl, PS, RS, (uint32_t)X % 3u, y, (uint32_t)X / 3u);
+                    H -= (int)(bx ^ prev);
+                    prev = bx;
+                }
+                v = H;
+            }
+            out[(size_t)y * W + X] = v;
+        }
+    } else {
+        const int N = geo.N;
+        int h = (int)y;    // h(0, J) = J
+        out[(size_t)y * (N + 1)] = h;
+        for (int I = 1; I <= N; ++I) {
+            const uint32_t bx = hbit(pl, PS, RS, (uint32_t)I & 1u, y, (uint32_t)I >> 1);
+            h = ((uint32_t)(((h + 1) >> 1) & 1) == bx) ? h + 1 : h - 1;
+            out[(size_t)y * (N + 1) + I] = h;
+        }
+    }
+}
+
+// Per-cell observables summed into bins of B x B cells, one thread per cell
+// row; counts are flushed with one atomic per bin run.
+__global__ void height_observe_kernel(const uint32_t *pl, size_t PS, uint32_t RS, uint32_t rows, Geo geo, uint32_t B,
+                                      uint32_t bins_x, unsigned long long *bins)
+{
+    const uint32_t y = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long acc = 0;
+    int cur_bin = -1;
+    auto add = [&](int X, int Y, unsigned long long q) {
+        const int b = (Y / (int)B) * (int)bins_x + X / (int)B;
+        if (b != cur_bin) {
+            if (cur_bin >= 0 && acc) atomicAdd(&bins[cur_bin], acc);
+            cur_bin = b;
+            acc = 0;
+        }
+        acc += q;
+    };
+    if (geo.model == TL_LOZENGE) {
+        if (y >= rows) return;
+        const int Y = (int)y;
+        const int xs = loz_xs(geo, Y), xe = loz_xe(geo, Y);
+        int H = loz_hmin(geo, xs, Y);
+        uint32_t prev = hbit(pl, PS, RS, (uint32_t)xs % 3u, y, (uint32_t)xs / 3u);
+        for (int X = xs; X <= xe; ++X) {
+            if (X > xs) {
+                const uint32_t bx = hbit(pl, PS, RS, (uint32_t)X % 3u, y, (uint32_t)X / 3u);
+                H -= (int)(bx ^ prev);
+                prev = bx;
+            }
+            add(X, Y, (unsigned long long)(H - loz_hmin(geo, X, Y)));
+        }
+    } else {
+        // vertex row j (1..N) between face rows j-1 and j; cell (i-1, j-1)
+        const int j = (int)y + 1, N = geo.N;
+        if (j > N) return;
+        for (int i = 1; i <= N; ++i) {
+            const uint32_t a00 = hbit(pl, PS, RS, (uint32_t)(i - 1) & 1u, (uint32_t)(j - 1), (uint32_t)(i - 1) >> 1);
+            const uint32_t a11 = hbit(pl, PS, RS, (uint32_t)i & 1u, (uint32_t)j, (uint32_t)i >> 1);
+            const uint32_t a10 = hbit(pl, PS, RS, (uint32_t)i & 1u, (uint32_t)(j - 1), (uint32_t)i >> 1);
+            const uint32_t a01 = hbit(pl, PS, RS, (uint32_t)(i - 1) & 1u, (uint32_t)j, (uint32_t)(i - 1) >> 1);
+            // both diagonal pairs equal (same parity => equal residual bit <=> equal height)
+            add(i - 1, j - 1, (a00 == a11 && a10 == a01) ? 1ull : 0ull);
+        }
+    }
+    if (cur_bin >= 0 && acc) atomicAdd(&bins[cur_bin], acc);
+}
+
+Geo geo_of(const HeightDev &d) { return Geo{d.model, d.a, d.b, d.c, d.N}; }
+
+}  // namespace
+
+hipError_t height_init(const HeightDev &d, int init_max, hipStream_t s)
+{
+    dim3 block(64), grid((d.RS + 63) / 64, d.rows, d.P);
+    hipLaunchKernelGGL(height_init_kernel, grid, block, 0, s, d.planes, d.spare, d.PS, d.RS, d.rows, d.P, geo_of(d),
+                       init_max);
+    return hipGetLastError();
+}
+
+hipError_t height_colour_step(const HeightDev &d, int colour, uint32_t t, const Thr &T, int metropolis, uint64_t seed,
+                              hipStream_t s, Timing *tm)
+{
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    const uint32_t threads = d.ng * d.rows;
+    dim3 block(256), grid((threads + 255) / 256);
+    auto k = T.uniform() ? height_step_kernel<kUniform>
+                         : (metropolis ? height_step_kernel<kMetropolis> : height_step_kernel<kHeatBath>);
+    return launch(tm, 1, k, grid, block, 0, s, d.planes, d.PS, d.RS, d.ng, d.rows, geo_of(d), (uint32_t)colour, t, T,
+                  k0, k1);
+}
+
+HeightTile height_auto_tile(const HeightDev &d)
+{
+    HeightTile t;
+    if (d.rows <= 96 && d.ng <= 4) {   // whole domain in one tile, no halo
+        t.TR = d.rows;
+        t.TG = d.ng;
+        t.S = 1u << 30;
+        return t;
+    }
+    t.TR = 32;
+    t.TG = d.ng < 4 ? d.ng : 4;
+    t.S = 8;
+    return t;
+}
+
+hipError_t height_tiled_sweeps(HeightDev &d, const HeightTile &tile, uint32_t t0, uint32_t nsw, const Thr &T,
+                               int metropolis, uint64_t seed, hipStream_t s, Timing *tm)
+{
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    const uint32_t rows_per_sweep = d.model == TL_LOZENGE ? 3u : 2u;   // halo rows invalidated per sweep
+    const uint32_t cols_per_sweep = d.model == TL_LOZENGE ? 1u : 2u;   // halo sites (per plane) per sweep
+    const uint32_t colours = d.model == TL_LOZENGE ? 3u : 4u;
+    const uint32_t TG = tile.TG == 0 ? 1u : (tile.TG < d.ng ? tile.TG : d.ng);
+    const uint32_t tiles_x = (d.ng + TG - 1) / TG;
+    const uint32_t LG0 = TG + (tiles_x > 1 ? 2u : 0u);
+    const uint32_t max_rows = 1024u / LG0;
+    if (max_rows < 2u * rows_per_sweep + 3u) return hipErrorInvalidConfiguration;
+    uint32_t TR = tile.TR == 0 ? 1u : (tile.TR < d.rows ? tile.TR : d.rows);
+    if (TR < d.rows && TR > max_rows - 2u * rows_per_sweep) TR = max_rows - 2u * rows_per_sweep;
+    if (TR >= d.rows && d.rows > max_rows) TR = max_rows - 2u * rows_per_sweep;
+    const uint32_t tiles_y = (d.rows + TR - 1) / TR;
+    uint32_t done = 0;
+    while (done < nsw) {
+        uint32_t S = nsw - done;
+        if (S > tile.S) S = tile.S;
+        if (tiles_x > 1 && S > 128u / cols_per_sweep) S = 128u / cols_per_sweep;
+        if (tiles_y > 1 && S > (max_rows - TR) / (2u * rows_per_sweep)) S = (max_rows - TR) / (2u * rows_per_sweep);
+        if (S == 0u) S = 1u;
+        const uint32_t HR = tiles_y > 1 ? rows_per_sweep * S : 0u;
+        const uint32_t HG = tiles_x > 1 ? 1u : 0u;
+        const uint32_t LR = TR + 2 * HR, LG = TG + 2 * HG;
+        const uint32_t tasks = LR * LG;
+        if (tasks > 1024u) return hipErrorInvalidConfiguration;
+        const uint32_t threads = (tasks + 63) / 64 * 64;
+        const uint32_t shmem = d.P * LR * 4u * (LG + 2u) * 4u;
+        if (shmem > 160u * 1024u) return hipErrorInvalidConfiguration;
+        dim3 grid(tiles_x * tiles_y), block(threads);
+        auto k = T.uniform() ? height_tiled_kernel<kUniform>
+                             : (metropolis ? height_tiled_kernel<kMetropolis> : height_tiled_kernel<kHeatBath>);
+        hipError_t e = launch(tm, colours * S, k, grid, block, shmem, s, (const uint32_t *)d.planes, d.spare, d.PS,
+                              d.RS, d.ng, d.rows, d.P, geo_of(d), d.K, t0 + done, S, TR, TG, HR, HG, tiles_x, T, k0,
+                              k1);
+        if (e != hipSuccess) return e;
+        uint32_t *tmp = d.planes;
+        d.planes = d.spare;
+        d.spare = tmp;
+        done += S;
+    }
+    return hipSuccess;
+}
+
+hipError_t height_export(const HeightDev &d, int32_t *dev, hipStream_t s)
+{
+    dim3 block(64), grid((d.rows + 63) / 64);
+    hipLaunchKernelGGL(height_export_kernel, grid, block, 0, s, d.planes, d.PS, d.RS, d.rows, geo_of(d), dev);
+    return hipGetLastError();
+}
+
+hipError_t height_observe(const HeightDev &d, uint32_t B, uint32_t bins_x, unsigned long long *bins, hipStream_t s)
+{
+    dim3 block(64), grid((d.rows + 63) / 64);
+    hipLaunchKernelGGL(height_observe_kernel, grid, block, 0, s, d.planes, d.PS, d.RS, d.rows, geo_of(d), B, bins_x,
+                       bins);
+    return hipGetLastError();
+}
+
+}  // namespace tl

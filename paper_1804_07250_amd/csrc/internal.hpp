@@ -129,6 +129,34 @@ hipError_t domino_export(const DominoDev &d, uint8_t *faces, hipStream_t s);
 hipError_t domino_observe(const DominoDev &d, uint32_t B, uint32_t bins_x, unsigned long long *bins,
                           hipStream_t s);
 
+// ------------------------------------------------------ height-function models
+// Bit-planes of a 1-bit height residual: plane p, row y, word w at
+// planes[p*PS + y*RS + 4 + w] (a zero pad group before and after each row).
+struct HeightDev {
+    int model = 0;          // TL_LOZENGE or TL_SIXVERTEX
+    int a = 0, b = 0, c = 0;  // hexagon sides (lozenge)
+    int N = 0;              // grid size (six-vertex)
+    uint32_t P = 0;         // planes: 3 (lozenge, X mod 3) or 2 (six-vertex, I mod 2)
+    uint32_t rows = 0;      // b+c+1 or N+1
+    uint32_t K = 0;         // sites per plane row
+    uint32_t ng = 0, RS = 0;
+    size_t PS = 0;
+    uint32_t *planes = nullptr, *spare = nullptr;
+};
+struct HeightTile {
+    uint32_t TR = 32, TG = 4, S = 8;
+};
+size_t height_words(HeightDev &d);
+hipError_t height_init(const HeightDev &d, int init_max, hipStream_t s);
+hipError_t height_colour_step(const HeightDev &d, int colour, uint32_t t, const Thr &T, int metropolis,
+                              uint64_t seed, hipStream_t s, Timing *tm = nullptr);
+hipError_t height_tiled_sweeps(HeightDev &d, const HeightTile &tile, uint32_t t0, uint32_t n, const Thr &T,
+                               int metropolis, uint64_t seed, hipStream_t s, Timing *tm = nullptr);
+HeightTile height_auto_tile(const HeightDev &d);
+// int32 canonical export into dev (rows x (row length) values)
+hipError_t height_export(const HeightDev &d, int32_t *dev, hipStream_t s);
+hipError_t height_observe(const HeightDev &d, uint32_t B, uint32_t bins_x, unsigned long long *bins, hipStream_t s);
+
 // ----------------------------------------------------------------- hashing
 // SHA-256 of each of `rows` rows of `row_bytes` bytes at `data` (device), into
 // 32-byte digests at `digests` (device).

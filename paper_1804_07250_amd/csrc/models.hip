@@ -1,6 +1,9 @@
 // Host-side model objects: device allocation, sweep scheduling per model and
 // the host conversion of canonical exports for import.
+#include <limits.h>
 #include <stdlib.h>
+
+#include <algorithm>
 #include <string.h>
 
 #include "models.hpp"
@@ -118,6 +121,185 @@ private:
     DominoDev d_;
 };
 
+// ------------------------------------------------------- lozenge / six-vertex
+class HeightModel : public Model {
+public:
+    explicit HeightModel(const tl_domain &dom)
+    {
+        d_.model = dom.model;
+        d_.a = dom.a;
+        d_.b = dom.b;
+        d_.c = dom.c;
+        d_.N = dom.n;
+        height_words(d_);
+    }
+    bool loz() const { return d_.model == TL_LOZENGE; }
+    int width() const { return loz() ? d_.a + d_.c + 1 : d_.N + 1; }   // export row length
+
+    hipError_t allocate() override
+    {
+        const size_t words = height_words(d_);
+        hipError_t e = hipMalloc(&d_.planes, words * sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMalloc(&d_.spare, words * sizeof(uint32_t));
+        return e;
+    }
+    void release() override
+    {
+        if (d_.planes) (void)hipFree(d_.planes);
+        if (d_.spare) (void)hipFree(d_.spare);
+        d_.planes = d_.spare = nullptr;
+        timing.release();
+    }
+    hipError_t init(bool init_max, hipStream_t s) override { return height_init(d_, init_max ? 1 : 0, s); }
+
+    // Six-vertex kernels take one threshold per weight class (sA, sB) (and
+    // current state for Metropolis): class 3*sA + sB <-> mask with NE = sA>=1,
+    // SW = sA>=2, NW = sB>=1, SE = sB>=2.
+    Thr kernel_table(const Thr &T, bool metro) const
+    {
+        if (loz()) return T;
+        Thr K{};
+        uint32_t n = 0;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                const uint32_t mask = (i >= 1 ? 1u : 0u) | (j >= 1 ? 2u : 0u) | (i >= 2 ? 4u : 0u) | (j >= 2 ? 8u : 0u);
+                if (metro) {
+                    K.v[n++] = T.v[2 * mask];
+                    K.v[n++] = T.v[2 * mask + 1];
+                } else {
+                    K.v[n++] = T.v[mask];
+                }
+            }
+        K.count = n;
+        return K;
+    }
+    hipError_t sweeps(uint32_t t0, uint32_t n, const Thr &T, bool metro, uint64_t seed, const tl_options &opt,
+                      hipStream_t s) override
+    {
+        const Thr K = kernel_table(T, metro);
+        if (opt.kernel == 1) {
+            const int colours = loz() ? 3 : 4;
+            for (uint32_t i = 0; i < n; ++i)
+                for (int c = 0; c < colours; ++c) {
+                    hipError_t e = height_colour_step(d_, c, t0 + i, K, metro ? 1 : 0, seed, s, &timing);
+                    if (e != hipSuccess) return e;
+                }
+            return hipSuccess;
+        }
+        HeightTile tile = height_auto_tile(d_);
+        if (opt.tile_rows) tile.TR = opt.tile_rows;
+        if (opt.tile_groups) tile.TG = opt.tile_groups;
+        if (opt.sweeps_per_launch) tile.S = opt.sweeps_per_launch;
+        return height_tiled_sweeps(d_, tile, t0, n, K, metro ? 1 : 0, seed, s, &timing);
+    }
+    hipError_t observe(uint32_t B, uint32_t bins_x, unsigned long long *bins, hipStream_t s) override
+    {
+        return height_observe(d_, B, bins_x, bins, s);
+    }
+    void cell_box(uint32_t *w, uint32_t *h) const override
+    {
+        if (loz()) {
+            *w = (uint32_t)(d_.a + d_.c + 1);
+            *h = (uint32_t)(d_.b + d_.c + 1);
+        } else {
+            *w = *h = (uint32_t)d_.N;
+        }
+    }
+    bool in_hex(int X, int Y) const
+    {
+        const int x = X - d_.c, y = Y - d_.c;
+        return x >= -d_.c && x <= d_.a && y >= -d_.c && y <= d_.b && x - y >= -d_.b && x - y <= d_.a;
+    }
+    int hmin(int X, int Y) const { return std::max(0, std::max(d_.c - X, d_.c - Y)); }
+    int hmax(int X, int Y) const { return std::min(d_.c, std::min(d_.a + d_.c - X, d_.b + d_.c - Y)); }
+    std::vector<uint32_t> cells_per_bin(uint32_t B, uint32_t bx, uint32_t by) const override
+    {
+        std::vector<uint32_t> cnt((size_t)bx * by, 0u);
+        uint32_t w, h;
+        cell_box(&w, &h);
+        for (uint32_t Y = 0; Y < h; ++Y)
+            for (uint32_t X = 0; X < w; ++X)
+                if (!loz() || in_hex((int)X, (int)Y)) cnt[(size_t)(Y / B) * bx + X / B] += 1;
+        return cnt;
+    }
+    void export_layout(uint32_t *rows, uint32_t *row_bytes) const override
+    {
+        *rows = d_.rows;
+        *row_bytes = 4u * (uint32_t)width();
+    }
+    hipError_t export_canonical(uint8_t *dev, hipStream_t s) override
+    {
+        return height_export(d_, reinterpret_cast<int32_t *>(dev), s);
+    }
+    bool import_canonical(const uint8_t *raw, hipStream_t s, std::string &why, hipError_t *err) override
+    {
+        const int W = width(), R = (int)d_.rows;
+        std::vector<int32_t> h((size_t)W * R);
+        memcpy(h.data(), raw, h.size() * sizeof(int32_t));
+        auto at = [&](int X, int Y) { return h[(size_t)Y * W + X]; };
+        std::vector<uint32_t> host(d_.P * d_.PS, 0u);
+        auto setbit = [&](uint32_t p, uint32_t y, uint32_t k) {
+            host[p * d_.PS + (size_t)y * d_.RS + 4 + (k >> 5)] |= 1u << (k & 31u);
+        };
+        if (loz()) {
+            for (int Y = 0; Y < R; ++Y)
+                for (int X = 0; X < W; ++X) {
+                    const int32_t v = at(X, Y);
+                    if (!in_hex(X, Y)) {
+                        if (v != INT32_MIN) { why = "vertex outside the hexagon is not INT32_MIN"; return false; }
+                        continue;
+                    }
+                    if (v < hmin(X, Y) || v > hmax(X, Y)) { why = "height outside [H_min, H_max]"; return false; }
+                    const int dx[3] = {1, 0, 1}, dy[3] = {0, 1, 1};
+                    for (int q = 0; q < 3; ++q) {
+                        const int X2 = X + dx[q], Y2 = Y + dy[q];
+                        if (X2 < W && Y2 < R && in_hex(X2, Y2)) {
+                            const int dlt = at(X2, Y2) - v;
+                            if (dlt != 0 && dlt != -1) { why = "height step not in {0, -1}"; return false; }
+                        }
+                    }
+                    if (v & 1) setbit((uint32_t)(X % 3), (uint32_t)Y, (uint32_t)(X / 3));
+                }
+        } else {
+            const int N = d_.N;
+            for (int J = 0; J <= N; ++J)
+                for (int I = 0; I <= N; ++I) {
+                    const int32_t v = at(I, J);
+                    const bool edge = I == 0 || J == 0 || I == N || J == N;
+                    if (edge) {
+                        const int want = J == 0 ? I : (I == 0 ? J : (J == N ? N - I : N - J));
+                        if (v != want) { why = "domain-wall boundary heights violated"; return false; }
+                    }
+                    if (I < N && std::abs(at(I + 1, J) - v) != 1) { why = "ice rule violated"; return false; }
+                    if (J < N && std::abs(at(I, J + 1) - v) != 1) { why = "ice rule violated"; return false; }
+                    if (v < 0) { why = "negative height"; return false; }
+                    if ((v >> 1) & 1) setbit((uint32_t)(I & 1), (uint32_t)J, (uint32_t)(I >> 1));
+                }
+        }
+        hipError_t e = hipMemcpyAsync(d_.planes, host.data(), host.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) { *err = e; return false; }
+        return true;
+    }
+    uint64_t sites() const override
+    {
+        if (loz()) {
+            uint64_t n = 0;
+            for (int Y = 1; Y < (int)d_.rows - 1; ++Y) {
+                const int lo = std::max(0, Y - d_.b), hi = std::min(d_.a + d_.c, Y + d_.a);
+                if (hi - lo - 1 > 0) n += (uint64_t)(hi - lo - 1);
+            }
+            return n;
+        }
+        return (uint64_t)(d_.N - 1) * (uint64_t)(d_.N - 1);
+    }
+    int colours() const override { return loz() ? 3 : 4; }
+    double bytes_per_colour_step() const override { return 2.0 * d_.P * (double)d_.rows * d_.K / 8.0; }
+
+private:
+    HeightDev d_;
+};
+
 }  // namespace
 
 std::unique_ptr<Model> make_model(const tl_domain &d, std::string &why)
@@ -127,7 +309,20 @@ std::unique_ptr<Model> make_model(const tl_domain &d, std::string &why)
         if (d.n < 1 || d.n > 16384) { why = "Aztec order must be in [1, 16384]"; return nullptr; }
         return std::unique_ptr<Model>(new DominoModel(d.n));
     }
-    why = "model not supported";
+    if (d.model == TL_LOZENGE) {
+        if (d.shape != TL_HEXAGON) { why = "lozenges support the hexagon shape"; return nullptr; }
+        if (d.a < 1 || d.b < 1 || d.c < 1 || d.a + d.c > 32767 || d.b + d.c > 32767) {
+            why = "hexagon sides must be >= 1 with a+c, b+c <= 32767";
+            return nullptr;
+        }
+        return std::unique_ptr<Model>(new HeightModel(d));
+    }
+    if (d.model == TL_SIXVERTEX) {
+        if (d.shape != TL_DWBC_SQUARE) { why = "the six-vertex model supports the domain-wall square"; return nullptr; }
+        if (d.n < 1 || d.n > 32767) { why = "six-vertex N must be in [1, 32767]"; return nullptr; }
+        return std::unique_ptr<Model>(new HeightModel(d));
+    }
+    why = "unknown model";
     return nullptr;
 }
 

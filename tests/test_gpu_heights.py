@@ -1,0 +1,177 @@
+"""GPU parity for the height-function models (lozenge tilings of hexagons,
+six-vertex model with domain-wall boundary): the HIP path against the oracle,
+bit for bit on the canonical height export and the integer observables."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import need_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+
+def loz_sampler(tl, a, b, c, seed, q=None, metro=False, init=0, **kw):
+    w = tl.weights(tl.TL_W_UNIFORM) if q is None else tl.weights(tl.TL_W_VOLUME, q.numerator, q.denominator)
+    w.rule = tl.TL_METROPOLIS if metro else tl.TL_HEATBATH
+    return tl.Sampler(tl.domain(tl.TL_LOZENGE, a=a, b=b, c=c, init=init), w, seed, tl.options(**kw))
+
+
+def loz_oracle(a, b, c, seed, q=None, metro=False, init="min", **kw):
+    thr = oracle.table_from_ratios(oracle.lozenge_ratios(q if q is not None else 1), metro)
+    return oracle.LozengeOracle(a, b, c, thr, metropolis=metro, seed=seed, init=init, **kw)
+
+
+def sixv_sampler(tl, N, seed, w2=None, metro=False, init=0, **kw):
+    w = tl.weights(tl.TL_W_UNIFORM) if w2 is None else tl.weights(tl.TL_W_SIXVERTEX, *w2)
+    w.rule = tl.TL_METROPOLIS if metro else tl.TL_HEATBATH
+    return tl.Sampler(tl.domain(tl.TL_SIXVERTEX, n=N, init=init), w, seed, tl.options(**kw))
+
+
+def sixv_oracle(N, seed, w2=None, metro=False, init="min", **kw):
+    a2, b2, c2 = w2 if w2 is not None else (1, 1, 1)
+    # the oracle takes a, b and c^2 (the squares used here are of integers)
+    ratios = oracle.sixv_ratios(int(round(a2 ** 0.5)), int(round(b2 ** 0.5)), c2)
+    thr = oracle.table_from_ratios(ratios, metro)
+    return oracle.SixVertexOracle(N, thr, metropolis=metro, seed=seed, init=init, **kw)
+
+
+@pytest.mark.parametrize("abc", [(1, 1, 1), (2, 3, 4), (5, 5, 5), (7, 3, 11), (40, 37, 45), (130, 120, 140)])
+@pytest.mark.parametrize("kind", ["uniform", "q", "qmetro"])
+def test_lozenge_parity(abc, kind):
+    tl = need_gpu()
+    say("lozenge parity %s %s" % (abc, kind))
+    q = None if kind == "uniform" else Fraction(1999, 2000) if kind == "q" else Fraction(1, 2)
+    metro = kind == "qmetro"
+    s = loz_sampler(tl, *abc, seed=11, q=q, metro=metro)
+    o = loz_oracle(*abc, seed=11, q=q, metro=metro)
+    assert (s.export() == o.export()).all()
+    for k in (1, 3, 8):
+        s.sweep(k)
+        o.sweep(k)
+        assert (s.export() == o.export()).all(), "%s %s after %d sweeps" % (abc, kind, o.t)
+
+
+@pytest.mark.parametrize("abc,tile_rows,spl,kernel", [((60, 70, 80), 16, 3, 2), ((130, 120, 140), 24, 5, 2),
+                                                       ((200, 90, 300), 32, 40, 2), ((33, 44, 55), 0, 0, 1)])
+def test_lozenge_tiles_and_streaming(abc, tile_rows, spl, kernel):
+    tl = need_gpu()
+    s = loz_sampler(tl, *abc, seed=5, q=Fraction(3, 4), kernel=kernel, tile_rows=tile_rows, sweeps_per_launch=spl)
+    o = loz_oracle(*abc, seed=5, q=Fraction(3, 4))
+    s.sweep(11)
+    o.sweep(11)
+    assert (s.export() == o.export()).all()
+
+
+def test_lozenge_init_max_observables_hash_import():
+    tl = need_gpu()
+    a, b, c = 23, 17, 29
+    s = loz_sampler(tl, a, b, c, seed=3, q=Fraction(7, 8), init=tl.TL_INIT_MAX, obs_every=2, obs_bin=8)
+    o = loz_oracle(a, b, c, seed=3, q=Fraction(7, 8), init="max", obs_every=2, bin_=8)
+    assert (s.export() == o.export()).all()
+    s.sweep(9)
+    o.sweep(9)
+    assert (s.export() == o.export()).all()
+    obs = s.observables()
+    assert obs["samples"] == int(o.samples[0]) == 4
+    assert (obs["bin_sum"].reshape(-1) == o.bin_sum).all()
+    assert obs["scalar_now"] == o.observe(1)[0]
+    dens = oracle.bin_density(o.bin_sum, 4, o.in_domain_cells(), 8)
+    assert np.allclose(obs["bin_density"], dens, rtol=1e-12, atol=0)
+    assert s.hash() == oracle.canonical_hash(o.export())
+    mid = s.export()
+    s.sweep(5)
+    r = loz_sampler(tl, a, b, c, seed=3, q=Fraction(7, 8))
+    r.import_(mid, 9)
+    r.sweep(5)
+    assert (r.export() == s.export()).all()
+    bad = mid.copy()
+    bad[10, 10] += 3
+    with pytest.raises(tl.TlError):
+        r.import_(bad, 0)
+
+
+def test_lozenge_hexagon_1024_one_sweep_sampled():
+    # a = b = c = 1024, q = 1999/2000: after 300 GPU sweeps from the empty box the
+    # state is loaded into the oracle, both run one more sweep, exports agree.
+    tl = need_gpu()
+    say("lozenge 1024^3 one-sweep parity")
+    q = Fraction(1999, 2000)
+    s = loz_sampler(tl, 1024, 1024, 1024, seed=11, q=q)
+    s.sweep(300)
+    mid = s.export()
+    o = loz_oracle(1024, 1024, 1024, seed=11, q=q)
+    o.load(mid)
+    o.t = 300
+    s.sweep(1)
+    o.sweep(1)
+    assert (s.export() == o.export()).all()
+    assert s.hash() == oracle.canonical_hash(o.export())
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 8, 9, 33, 64, 130, 257])
+@pytest.mark.parametrize("kind", ["uniform", "sqrt2", "sqrt2metro", "a2"])
+def test_sixvertex_parity(N, kind):
+    tl = need_gpu()
+    say("six-vertex parity N=%d %s" % (N, kind))
+    w2 = {"uniform": None, "sqrt2": (1, 1, 2), "sqrt2metro": (1, 1, 2), "a2": (4, 1, 4)}[kind]
+    metro = kind == "sqrt2metro"
+    s = sixv_sampler(tl, N, seed=17, w2=w2, metro=metro)
+    o = sixv_oracle(N, seed=17, w2=w2, metro=metro)
+    assert (s.export() == o.export()).all()
+    for k in (1, 2, 7):
+        s.sweep(k)
+        o.sweep(k)
+        assert (s.export() == o.export()).all(), "N=%d %s after %d sweeps" % (N, kind, o.t)
+
+
+@pytest.mark.parametrize("N,tile_rows,spl,kernel", [(100, 16, 3, 2), (300, 20, 6, 2), (513, 32, 30, 2),
+                                                     (77, 0, 0, 1)])
+def test_sixvertex_tiles_and_streaming(N, tile_rows, spl, kernel):
+    tl = need_gpu()
+    s = sixv_sampler(tl, N, seed=8, w2=(1, 1, 2), kernel=kernel, tile_rows=tile_rows, sweeps_per_launch=spl)
+    o = sixv_oracle(N, seed=8, w2=(1, 1, 2))
+    s.sweep(13)
+    o.sweep(13)
+    assert (s.export() == o.export()).all()
+
+
+def test_sixvertex_init_max_observables_hash_import():
+    tl = need_gpu()
+    N = 45
+    s = sixv_sampler(tl, N, seed=2, w2=(1, 1, 2), init=tl.TL_INIT_MAX, obs_every=3, obs_bin=4)
+    o = sixv_oracle(N, seed=2, w2=(1, 1, 2), init="max", obs_every=3, bin_=4)
+    assert (s.export() == o.export()).all()
+    s.sweep(10)
+    o.sweep(10)
+    assert (s.export() == o.export()).all()
+    obs = s.observables()
+    assert obs["samples"] == int(o.samples[0]) == 3
+    assert (obs["bin_sum"].reshape(-1) == o.bin_sum).all()
+    assert obs["scalar_now"] == o.observe(1)[0]
+    assert s.hash() == oracle.canonical_hash(o.export())
+    mid = s.export()
+    s.sweep(4)
+    r = sixv_sampler(tl, N, seed=2, w2=(1, 1, 2))
+    r.import_(mid, 10)
+    r.sweep(4)
+    assert (r.export() == s.export()).all()
+    bad = mid.copy()
+    bad[5, 5] += 2
+    with pytest.raises(tl.TlError):
+        r.import_(bad, 0)
+
+
+def test_sixvertex_1024_one_sweep_sampled():
+    tl = need_gpu()
+    say("six-vertex N=1024 one-sweep parity")
+    s = sixv_sampler(tl, 1024, seed=3, w2=(1, 1, 2))
+    s.sweep(500)
+    mid = s.export()
+    o = sixv_oracle(1024, seed=3, w2=(1, 1, 2))
+    o.load(mid)
+    o.t = 500
+    s.sweep(1)
+    o.sweep(1)
+    assert (s.export() == o.export()).all()
