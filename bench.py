@@ -21,6 +21,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -51,7 +53,89 @@ def parse():
                    help="time only the sweeps (for profiler runs); no JSON contract line")
     p.add_argument("--copy-calibration", type=int, default=0,
                    help="run a plain device copy of this many MiB (profiler calibration) and exit")
+    p.add_argument("--no-batched", action="store_true")
+    p.add_argument("--no-served", action="store_true")
+    p.add_argument("--batched-chains", type=int, default=4096)
+    p.add_argument("--batched-sweeps", type=int, default=5000)
+    p.add_argument("--served-requests", type=int, default=400)
+    p.add_argument("--served-rate", type=float, default=200.0)
+    p.add_argument("--served-sweeps", type=int, default=2000)
+    p.add_argument("--served-budget-mib", type=int, default=1024)
+    p.add_argument("--served-slots", type=int, default=64)
     return p.parse_args()
+
+
+def run_batched(tl, args):
+    """Batched form: Aztec chains of orders uniform in [16, 512], two-periodic
+    weights a = 1, b = 1/2, seeds 0..count-1, args.batched_sweeps sweeps in one
+    graph-replayed persistent launch; work-group size from the autotuner."""
+    from paper_1804_07250_amd import workloads
+    from paper_1804_07250_amd.serving import Batch
+    orders = workloads.batch_orders(args.batched_chains)
+    doms = [tl.domain(tl.TL_DOMINO, n=n) for n in orders]
+    w = tl.weights(tl.TL_W_TWO_PERIODIC, 1.0, 0.5)
+    b = Batch(doms, w, list(range(len(orders))))
+    threads, probe_ms = b.autotune(4)
+    info = b.info()
+    b.sweep(args.batched_sweeps)   # warm-up (captures the graph)
+    b.sync()
+    b.reset()
+    b.sync()
+    b.set_timing(True)
+    t0 = time.perf_counter()
+    b.sweep(args.batched_sweeps)
+    b.sync()
+    el = time.perf_counter() - t0
+    kms, launches, steps = b.kernel_time()
+    updates = info["sites"] * args.batched_sweeps
+    h0 = b.hash(0)
+    b.destroy()
+    # algorithmic bytes: the packed state of every chain read and written per colour step
+    alg = 2.0 * info["state_bytes"] * 2 * args.batched_sweeps
+    return {"value": updates / el, "unit": "site-updates/s", "ms_per_step": el * 1e3,
+            "chains": len(orders), "sweeps": args.batched_sweeps, "sites": info["sites"],
+            "state_bytes": info["state_bytes"], "threads": threads, "workgroups": info["workgroups"],
+            "autotune_probe_ms": round(probe_ms, 3), "launch_ms": round(kms, 3),
+            "roofline": {"bound": "hbm", "achieved": round(alg / (kms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(alg / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+            "chain0_hash": h0,
+            "workload": "batched: %d domino chains, Aztec orders uniform in [16,512] (PCG64 seed 0x5EED), "
+                        "two-periodic a=1 b=1/2, %d sweeps, seeds 0..%d, one graph-replayed persistent launch"
+                        % (len(orders), args.batched_sweeps, len(orders) - 1)}
+
+
+def run_served(tl, args):
+    """Served form: six-vertex domain-wall requests, N uniform over
+    {64,...,1024}, weights (1,1,sqrt 2) heat-bath / (1,1,1) alternating, 2000
+    sweeps, Poisson arrivals; admitted by a device-memory budget."""
+    from paper_1804_07250_amd import workloads
+    from paper_1804_07250_amd.serving import Server
+    reqs = workloads.serve_requests(args.served_requests, args.served_rate)
+    sv = Server(args.served_budget_mib << 20, args.served_slots, tl.options(sweeps_per_launch=250))
+    start = time.perf_counter()
+    tickets = []
+    for r in reqs:
+        delay = r["arrival"] - (time.perf_counter() - start)
+        if delay > 0:
+            time.sleep(delay)
+        dom = tl.domain(tl.TL_SIXVERTEX, n=r["N"])
+        w = tl.weights(tl.TL_W_SIXVERTEX, *r["w2"])
+        tickets.append((sv.submit(dom, w, r["seed"], args.served_sweeps), r))
+    res = [(sv.wait(t, 600.0), r) for t, r in tickets]
+    end = time.perf_counter()
+    st = sv.stats()
+    sv.destroy()
+    lat = np.array([x["t_done"] - x["t_submit"] for x, _ in res]) * 1e3
+    ok = all(x["status"] == tl.TL_OK for x, _ in res)
+    updates = sum((r["N"] - 1) ** 2 * args.served_sweeps for _, r in res)
+    return {"value": updates / (end - start), "unit": "site-updates/s", "requests": len(res), "all_ok": ok,
+            "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "max_ms": round(float(lat.max()), 3), "span_s": round(end - start, 3),
+            "peak_active": st["peak_active"], "peak_bytes": st["peak_bytes"],
+            "workload": "served: six-vertex DWBC, N uniform over {64,128,256,512,1024}, weights (1,1,sqrt2) and "
+                        "(1,1,1) alternating, %d sweeps per request, Poisson %.0f/s, %d requests, budget %d MiB, "
+                        "%d slots, quanta of 250 sweeps" % (args.served_sweeps, args.served_rate, len(res),
+                                                           args.served_budget_mib, args.served_slots)}
 
 
 def make_sampler(tl, wl, args):
@@ -182,6 +266,13 @@ def main():
     if args.sweeps_only:
         print(json.dumps({"sweeps_only_s_per_step": el / args.steps, "kernel_ms": kms, "launches": launches}))
         return
+    s.destroy()
+    if not args.no_batched:
+        out["batched"] = run_batched(tl, args)
+        print("batched done", file=sys.stderr, flush=True)
+    if not args.no_served:
+        out["served"] = run_served(tl, args)
+        print("served done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(out))

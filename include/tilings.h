@@ -170,6 +170,80 @@ tl_status tl_sampler_info(const tl_sampler *s, uint64_t *sites, uint32_t *colour
  * writes up to cap entries, returns the count in *count. */
 tl_status tl_sampler_thresholds(const tl_sampler *s, uint32_t *out, uint32_t cap, uint32_t *count);
 
+/* ------------------------------------------------------------------ batched
+ * Many independent domino chains on Aztec diamonds of uneven orders (1..512),
+ * advanced together: each tl_batch_sweep call is one persistent kernel launch
+ * (replayed from a captured hipGraph) in which work-groups take whole chains,
+ * longest first, and keep them in LDS for all the call's sweeps.  Chain i is
+ * keyed by seeds[i], so its tiling equals the tiling of a tl_sampler with the
+ * same domain, weights and seed.  One weight set for all chains. */
+typedef struct tl_batch tl_batch;
+
+/* doms[0..n) (domino, Aztec, order <= 512), seeds[0..n).  Errors: TL_EINVAL,
+ * TL_ENOMEM, TL_EDEVICE. */
+tl_status tl_batch_create(int32_t n, const tl_domain *doms, const tl_weights *w, const uint64_t *seeds,
+                          const tl_options *opt, tl_batch **out);
+/* Pick the work-group size (256, 512 or 1024 threads) with the shortest probe
+ * of probe_sweeps sweeps; only before the first sweep (the chains are then
+ * returned to their start).  Outputs are nullable. */
+tl_status tl_batch_autotune(tl_batch *b, uint32_t probe_sweeps, uint32_t *threads_out, float *ms_out);
+/* Advance every chain by n sweeps (asynchronous). */
+tl_status tl_batch_sweep(tl_batch *b, uint64_t n);
+tl_status tl_batch_sync(tl_batch *b);
+/* Return every chain to its start (sweep counter 0). */
+tl_status tl_batch_reset(tl_batch *b);
+/* Total sites, packed state bytes, work-group size and resident work-groups. */
+tl_status tl_batch_info(const tl_batch *b, uint64_t *sites, uint64_t *state_bytes, uint32_t *threads,
+                        uint32_t *workgroups);
+/* Time each batch launch with events (enable != 0); report and clear. */
+tl_status tl_batch_set_timing(tl_batch *b, int enable);
+tl_status tl_batch_kernel_time(tl_batch *b, double *ms, uint64_t *launches, uint64_t *colour_steps);
+/* Canonical export / hash of one chain (same formats as the sampler's). */
+tl_status tl_batch_export(tl_batch *b, int32_t chain, void *host, size_t bytes);
+tl_status tl_batch_hash(tl_batch *b, int32_t chain, uint8_t digest[32]);
+tl_status tl_batch_destroy(tl_batch *b);
+
+/* -------------------------------------------------------------------- served
+ * A request loop with continuous batching: jobs (any model and domain) are
+ * queued by tl_server_submit and admitted in arrival order by a scheduler
+ * thread while the device-memory budget and the slot count allow; admitted
+ * chains stay resident on the device and advance in quanta of
+ * tl_options.sweeps_per_launch sweeps (default 250) on their own streams, so
+ * jobs that arrive while others run overlap with them on the GPU.  A finished
+ * job's result is its canonical hash and whole-domain observable; its memory
+ * is released at once.  A job gives the same result alone and in a mix. */
+typedef struct tl_server tl_server;
+typedef struct {
+    uint64_t ticket;
+    int32_t status;          /* TL_OK, or the error that ended the job */
+    uint64_t sweeps;         /* sweeps performed */
+    double t_submit;         /* seconds since server creation: submission, */
+    double t_start;          /*   admission (device state created) */
+    double t_done;           /*   and completion */
+    uint8_t hash[32];        /* canonical hash of the final state */
+    int64_t scalar_now;      /* whole-domain observable of the final state */
+} tl_result;
+typedef struct {
+    uint64_t queued, active, admitted, completed;
+    uint64_t bytes_in_use, peak_bytes;
+    uint32_t peak_active;
+} tl_server_counters;
+
+/* Budget in bytes of device state (sum over resident jobs), at most max_slots
+ * resident jobs; opt (nullable): sweeps_per_launch = quantum, obs_bin. */
+tl_status tl_server_create(size_t hbm_budget_bytes, int32_t max_slots, const tl_options *opt, tl_server **out);
+/* Queue a job; TL_EBUDGET if it can never fit the budget, TL_EINVAL for an
+ * invalid domain or weights.  *ticket identifies it. */
+tl_status tl_server_submit(tl_server *sv, const tl_domain *dom, const tl_weights *w, uint64_t seed,
+                           uint64_t n_sweeps, uint64_t *ticket);
+/* Result of a finished job, TL_EBUSY while it is queued or running. */
+tl_status tl_server_poll(tl_server *sv, uint64_t ticket, tl_result *out);
+/* Block until the job finishes or timeout_s passes (TL_EBUSY). */
+tl_status tl_server_wait(tl_server *sv, uint64_t ticket, double timeout_s, tl_result *out);
+tl_status tl_server_stats(tl_server *sv, tl_server_counters *out);
+/* Stop the scheduler; jobs still queued or running end with TL_EBUSY. */
+tl_status tl_server_destroy(tl_server *sv);
+
 /* Threshold table of a (domain, weights) pair without creating a sampler (host
  * only, no device work): heat-bath tables have one entry per context, lazy
  * Metropolis tables two ([ctx*2 + current state is up]).  Contexts: domino

@@ -10,13 +10,15 @@
 #include <vector>
 
 #include "../../include/tilings.h"
+#include "errors.hpp"
 #include "internal.hpp"
 #include "models.hpp"
 
 namespace {
-
 thread_local std::string g_last_error;
+}  // namespace
 
+namespace tl {
 tl_status fail(tl_status st, const char *fmt, ...)
 {
     char buf[512];
@@ -27,14 +29,11 @@ tl_status fail(tl_status st, const char *fmt, ...)
     g_last_error = buf;
     return st;
 }
+}  // namespace tl
 
-#define TL_HIP(call)                                                                          \
-    do {                                                                                      \
-        hipError_t e_ = (call);                                                               \
-        if (e_ != hipSuccess)                                                                 \
-            return fail(TL_EDEVICE, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),    \
-                        __FILE__, __LINE__);                                                  \
-    } while (0)
+using tl::fail;
+
+namespace {
 
 bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
 
@@ -158,6 +157,14 @@ tl_status enqueue_sample(tl_sampler *s)
 }
 
 }  // namespace
+
+namespace tl {
+hipStream_t sampler_stream(const tl_sampler *s) { return s->stream; }
+tl_status make_table(const tl_domain &d, const tl_weights &w, std::vector<uint32_t> &thr)
+{
+    return make_thresholds(d, w, thr);
+}
+}  // namespace tl
 
 extern "C" {
 

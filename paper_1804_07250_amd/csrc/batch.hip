@@ -1,0 +1,354 @@
+// Batched form: thousands of independent domino chains (Aztec diamonds of
+// uneven orders) advanced together by one persistent launch per call, replayed
+// from a captured hipGraph.  Chains are handed to work-groups longest first
+// (LPT order) through an atomic counter; each chain lives in LDS for the whole
+// call.  Every draw is keyed by (chain seed, sweep, colour, site), so a chain
+// gives the same tiling in the batch as alone.
+#include <algorithm>
+#include <memory>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "errors.hpp"
+#include "internal.hpp"
+
+struct tl_batch {
+    int32_t count = 0;
+    std::vector<tl_domain> doms;
+    std::vector<uint64_t> seeds;
+    tl_weights w{};
+    tl::Thr T{};
+    bool metro = false;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    uint32_t *planes = nullptr;
+    std::vector<tl::BatchChain> chains;
+    tl::BatchChain *d_chains = nullptr;
+    uint32_t *d_order = nullptr;
+    uint32_t *d_counter = nullptr;
+    uint32_t lds_max = 0;
+    uint32_t threads = 256;
+    uint32_t workgroups = 0;
+    uint32_t cus = 0;
+    uint64_t t = 0;
+    uint64_t sites = 0;
+    uint64_t owner_bits = 0;
+    hipGraphExec_t graph = nullptr;
+    hipGraph_t graph_def = nullptr;
+    uint32_t graph_q = 0;
+    tl::Timing timing;
+    std::vector<hipEvent_t> ev;   // start/stop around graph launches when timing
+};
+
+namespace {
+
+tl::DominoDev chain_dev(const tl_batch *b, int32_t i)
+{
+    const tl::BatchChain &c = b->chains[i];
+    tl::DominoDev d;
+    d.n = (int)c.n;
+    d.omega = ((int)c.n + 1) & 1;
+    d.ng = c.ng;
+    d.RS = c.RS;
+    d.PS = c.PS;
+    d.planes = b->planes + c.offset;
+    d.spare = nullptr;
+    return d;
+}
+
+tl_status drop_graph(tl_batch *b)
+{
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    if (b->graph_def) (void)hipGraphDestroy(b->graph_def);
+    b->graph = nullptr;
+    b->graph_def = nullptr;
+    b->graph_q = 0;
+    return TL_OK;
+}
+
+uint32_t workgroups_for(const tl_batch *b, uint32_t threads)
+{
+    // as many resident work-groups per CU as LDS and threads allow
+    uint32_t per_cu = (160u * 1024u) / (b->lds_max + 64u);
+    const uint32_t by_threads = 2048u / threads;
+    if (per_cu > by_threads) per_cu = by_threads;
+    if (per_cu < 1u) per_cu = 1u;
+    uint32_t wg = b->cus * per_cu;
+    if (wg > (uint32_t)b->count) wg = (uint32_t)b->count;
+    return wg;
+}
+
+tl_status init_all(tl_batch *b)
+{
+    for (int32_t i = 0; i < b->count; ++i) {
+        const tl::DominoDev d = chain_dev(b, i);
+        TL_HIP(tl::domino_init(d, b->doms[i].init == TL_INIT_MAX ? 1 : 0, b->stream));
+    }
+    for (auto &c : b->chains) c.t = 0;
+    TL_HIP(hipMemcpyAsync(b->d_chains, b->chains.data(), b->chains.size() * sizeof(tl::BatchChain),
+                          hipMemcpyHostToDevice, b->stream));
+    b->t = 0;
+    return TL_OK;
+}
+
+tl_status launch_direct(tl_batch *b, uint32_t nsweeps, uint32_t threads, tl::Timing *tm)
+{
+    TL_HIP(tl::domino_batch_sweeps(b->d_chains, b->d_order, (uint32_t)b->count, b->d_counter, b->planes, nsweeps,
+                                   b->T, b->metro ? 1 : 0, threads, workgroups_for(b, threads), b->lds_max,
+                                   b->stream, tm));
+    return TL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tl_status tl_batch_create(int32_t n, const tl_domain *doms, const tl_weights *w, const uint64_t *seeds,
+                          const tl_options *opt, tl_batch **out)
+{
+    if (!doms || !w || !seeds || !out || n <= 0) return tl::fail(TL_EINVAL, "invalid batch arguments");
+    *out = nullptr;
+    std::unique_ptr<tl_batch> b(new (std::nothrow) tl_batch());
+    if (!b) return tl::fail(TL_ENOMEM, "host allocation failed");
+    b->count = n;
+    b->doms.assign(doms, doms + n);
+    b->seeds.assign(seeds, seeds + n);
+    b->w = *w;
+    b->metro = w->rule == TL_METROPOLIS;
+    std::vector<uint32_t> thr;
+    for (int32_t i = 0; i < n; ++i) {
+        const tl_domain &d = doms[i];
+        if (d.model != TL_DOMINO || d.shape != TL_AZTEC)
+            return tl::fail(TL_EINVAL, "batches hold domino chains on Aztec diamonds (chain %d)", i);
+        if (d.n < 1 || d.n > 512) return tl::fail(TL_EINVAL, "batched Aztec orders must be in [1, 512] (chain %d)", i);
+        if (d.init != TL_INIT_MIN && d.init != TL_INIT_MAX) return tl::fail(TL_EINVAL, "unknown init (chain %d)", i);
+    }
+    tl_status st = tl::make_table(doms[0], *w, thr);
+    if (st != TL_OK) return st;
+    for (size_t i = 0; i < thr.size() && i < 32; ++i) b->T.v[i] = thr[i];
+    b->T.count = (uint32_t)std::min<size_t>(thr.size(), 32);
+    // layout: chains back to back, each in the single-chain layout
+    uint64_t words = 0;
+    b->chains.resize(n);
+    for (int32_t i = 0; i < n; ++i) {
+        tl::BatchChain &c = b->chains[i];
+        uint32_t ng, RS;
+        size_t PS;
+        const size_t wds = tl::domino_words(doms[i].n, &ng, &RS, &PS);
+        c.offset = words;
+        c.PS = PS;
+        c.n = (uint32_t)doms[i].n;
+        c.ng = ng;
+        c.RS = RS;
+        c.key0 = (uint32_t)seeds[i];
+        c.key1 = (uint32_t)(seeds[i] >> 32);
+        c.t = 0;
+        c.lds_bytes = 4u * c.n * 4u * ng * 4u;
+        c.pad = 0;
+        words += (wds + 63) / 64 * 64;   // 256-byte aligned chains
+        b->lds_max = std::max(b->lds_max, c.lds_bytes);
+        b->sites += 2ull * c.n * c.n - 2ull * c.n + 1ull;
+        b->owner_bits += 4ull * c.n * c.n;
+    }
+    if (opt && opt->stream) {
+        b->stream = (hipStream_t)opt->stream;
+    } else {
+        TL_HIP(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+        b->own_stream = true;
+    }
+    int dev = 0, cus = 0;
+    TL_HIP(hipGetDevice(&dev));
+    TL_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    b->cus = (uint32_t)cus;
+    if (hipMalloc(&b->planes, words * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&b->d_chains, n * sizeof(tl::BatchChain)) != hipSuccess ||
+        hipMalloc(&b->d_order, n * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&b->d_counter, sizeof(uint32_t)) != hipSuccess) {
+        tl_batch_destroy(b.release());
+        return tl::fail(TL_ENOMEM, "batch state allocation (%zu MB)", (size_t)(words * 4 >> 20));
+    }
+    // longest chains first
+    std::vector<uint32_t> order(n);
+    std::iota(order.begin(), order.end(), 0u);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](uint32_t x, uint32_t y) { return b->chains[x].n > b->chains[y].n; });
+    TL_HIP(hipMemcpyAsync(b->d_order, order.data(), n * sizeof(uint32_t), hipMemcpyHostToDevice, b->stream));
+    if (opt && opt->tile_rows) b->threads = opt->tile_rows;   // work-group size override
+    st = init_all(b.get());
+    if (st != TL_OK) {
+        tl_batch_destroy(b.release());
+        return st;
+    }
+    TL_HIP(hipStreamSynchronize(b->stream));
+    *out = b.release();
+    return TL_OK;
+}
+
+tl_status tl_batch_autotune(tl_batch *b, uint32_t probe_sweeps, uint32_t *threads_out, float *ms_out)
+{
+    if (!b) return tl::fail(TL_EINVAL, "null batch");
+    if (b->t != 0) return tl::fail(TL_EINVAL, "autotune runs before the first sweep");
+    if (probe_sweeps == 0) probe_sweeps = 1;
+    const uint32_t cand[3] = {256u, 512u, 1024u};
+    float best = 1e30f;
+    uint32_t best_th = b->threads;
+    hipEvent_t e0, e1;
+    TL_HIP(hipEventCreate(&e0));
+    TL_HIP(hipEventCreate(&e1));
+    for (uint32_t th : cand) {
+        TL_HIP(hipEventRecord(e0, b->stream));
+        tl_status st = launch_direct(b, probe_sweeps, th, nullptr);
+        if (st != TL_OK) return st;
+        TL_HIP(hipEventRecord(e1, b->stream));
+        TL_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        TL_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+            best = ms;
+            best_th = th;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->threads = best_th;
+    drop_graph(b);
+    tl_status st = init_all(b);   // the probes advanced the chains: start again
+    if (st != TL_OK) return st;
+    TL_HIP(hipStreamSynchronize(b->stream));
+    if (threads_out) *threads_out = best_th;
+    if (ms_out) *ms_out = best;
+    return TL_OK;
+}
+
+tl_status tl_batch_sweep(tl_batch *b, uint64_t n)
+{
+    if (!b) return tl::fail(TL_EINVAL, "null batch");
+    if (n == 0) return TL_OK;
+    if (b->t + n > 0xFFFFFFFFull) return tl::fail(TL_EINVAL, "sweep counter would exceed 2^32");
+    if (b->graph_q != (uint32_t)n) {
+        drop_graph(b);
+        TL_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        tl_status st = launch_direct(b, (uint32_t)n, b->threads, nullptr);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(b->stream, &g);
+        if (st != TL_OK) return st;
+        if (e != hipSuccess) return tl::fail(TL_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+        b->graph_def = g;
+        TL_HIP(hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0));
+        b->graph_q = (uint32_t)n;
+    }
+    if (b->timing.on) {
+        hipEvent_t a, c;
+        TL_HIP(b->timing.events(&a, &c));
+        TL_HIP(hipEventRecord(a, b->stream));
+        TL_HIP(hipGraphLaunch(b->graph, b->stream));
+        TL_HIP(hipEventRecord(c, b->stream));
+        b->timing.pending.push_back(a);
+        b->timing.pending.push_back(c);
+        b->timing.pending_steps.push_back(2u * (uint32_t)n);
+    } else {
+        TL_HIP(hipGraphLaunch(b->graph, b->stream));
+    }
+    b->t += n;
+    return TL_OK;
+}
+
+tl_status tl_batch_sync(tl_batch *b)
+{
+    if (!b) return tl::fail(TL_EINVAL, "null batch");
+    TL_HIP(hipStreamSynchronize(b->stream));
+    return TL_OK;
+}
+
+tl_status tl_batch_reset(tl_batch *b)
+{
+    if (!b) return tl::fail(TL_EINVAL, "null batch");
+    return init_all(b);
+}
+
+tl_status tl_batch_info(const tl_batch *b, uint64_t *sites, uint64_t *state_bytes, uint32_t *threads,
+                        uint32_t *workgroups)
+{
+    if (!b) return tl::fail(TL_EINVAL, "null batch");
+    if (sites) *sites = b->sites;
+    if (state_bytes) *state_bytes = b->owner_bits / 8;
+    if (threads) *threads = b->threads;
+    if (workgroups) *workgroups = workgroups_for(b, b->threads);
+    return TL_OK;
+}
+
+tl_status tl_batch_set_timing(tl_batch *b, int enable)
+{
+    if (!b) return tl::fail(TL_EINVAL, "null batch");
+    b->timing.on = enable != 0;
+    return TL_OK;
+}
+
+tl_status tl_batch_kernel_time(tl_batch *b, double *ms, uint64_t *launches, uint64_t *colour_steps)
+{
+    if (!b) return tl::fail(TL_EINVAL, "null batch");
+    TL_HIP(hipStreamSynchronize(b->stream));
+    TL_HIP(b->timing.collect());
+    if (ms) *ms = b->timing.ms;
+    if (launches) *launches = b->timing.launches;
+    if (colour_steps) *colour_steps = b->timing.steps;
+    b->timing.ms = 0.0;
+    b->timing.launches = b->timing.steps = 0;
+    return TL_OK;
+}
+
+tl_status tl_batch_export(tl_batch *b, int32_t chain, void *host, size_t bytes)
+{
+    if (!b || !host) return tl::fail(TL_EINVAL, "null argument");
+    if (chain < 0 || chain >= b->count) return tl::fail(TL_EINVAL, "chain %d out of range", chain);
+    const tl::DominoDev d = chain_dev(b, chain);
+    const size_t need = (size_t)(2 * d.n) * (2 * d.n);
+    if (bytes < need) return tl::fail(TL_EINVAL, "export buffer has %zu bytes, %zu needed", bytes, need);
+    uint8_t *dev = nullptr;
+    TL_HIP(hipMalloc(&dev, need));
+    hipError_t e = tl::domino_export(d, dev, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(host, dev, need, hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    (void)hipFree(dev);
+    if (e != hipSuccess) return tl::fail(TL_EDEVICE, "batch export: %s", hipGetErrorString(e));
+    return TL_OK;
+}
+
+tl_status tl_batch_hash(tl_batch *b, int32_t chain, uint8_t digest[32])
+{
+    if (!b || !digest) return tl::fail(TL_EINVAL, "null argument");
+    if (chain < 0 || chain >= b->count) return tl::fail(TL_EINVAL, "chain %d out of range", chain);
+    const tl::DominoDev d = chain_dev(b, chain);
+    const uint32_t rows = 2u * (uint32_t)d.n, rb = 2u * (uint32_t)d.n;
+    const size_t need = (size_t)rows * rb;
+    uint8_t *dev = nullptr;
+    TL_HIP(hipMalloc(&dev, need + 32 * (size_t)rows));
+    std::vector<uint8_t> rowd(32 * (size_t)rows);
+    hipError_t e = tl::domino_export(d, dev, b->stream);
+    if (e == hipSuccess) e = tl::hash_rows(dev, rows, rb, dev + need, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(rowd.data(), dev + need, rowd.size(), hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    (void)hipFree(dev);
+    if (e != hipSuccess) return tl::fail(TL_EDEVICE, "batch hash: %s", hipGetErrorString(e));
+    tl::sha256_host(rowd.data(), rowd.size(), digest);
+    return TL_OK;
+}
+
+tl_status tl_batch_destroy(tl_batch *b)
+{
+    if (!b) return TL_OK;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    drop_graph(b);
+    b->timing.release();
+    if (b->planes) (void)hipFree(b->planes);
+    if (b->d_chains) (void)hipFree(b->d_chains);
+    if (b->d_order) (void)hipFree(b->d_order);
+    if (b->d_counter) (void)hipFree(b->d_counter);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+    return TL_OK;
+}
+
+}  // extern "C"

@@ -205,8 +205,11 @@ __device__ __forceinline__ void owner_group(uint32_t *pN, uint32_t *pS, uint32_t
 template <int MODE>
 __device__ __forceinline__ void other_group(uint32_t *rowN, uint32_t *rowE, uint32_t *rowS1, uint32_t *rowW1,
                                             uint32_t r, uint32_t g, uint32_t c, uint32_t t, const Thr &Tall,
-                                            uint32_t key0, uint32_t key1)
+                                            uint32_t key0, uint32_t key1, bool has_next = true)
 {
+    // has_next = false: the group is the last of its row and the row has no pad
+    // group after it (compact LDS rows); its word 4 reads as zero and its carry
+    // bit (site k = 128 g + 127 >= n - 1, never a site of this colour) is zero.
     uint32_t R0[4] = {0u, 0u, 0u, 0u};
     if (MODE == kUniform) philox4x32_10(g, r, t, c, key0, key1, R0);
     uint32_t oN[4], oE[4], oS1[4], oW1[4];
@@ -214,7 +217,7 @@ __device__ __forceinline__ void other_group(uint32_t *rowN, uint32_t *rowE, uint
     ld4(rowE, oE);
     ld4(rowS1, oS1);
     ld4(rowW1, oW1);
-    const uint32_t eNext = rowE[4], sNext = rowS1[4];
+    const uint32_t eNext = has_next ? rowE[4] : 0u, sNext = has_next ? rowS1[4] : 0u;
     uint32_t horiz[4], vert[4], live[4];
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
@@ -248,7 +251,7 @@ __device__ __forceinline__ void other_group(uint32_t *rowN, uint32_t *rowE, uint
         rowE[w] = oE[w] ^ m;
         rowS1[w] = oS1[w] ^ m;
     }
-    if (F[3] >> 31) {
+    if (has_next && (F[3] >> 31)) {
         atomicXor(&rowE[4], 1u);
         atomicXor(&rowS1[4], 1u);
     }
@@ -338,6 +341,69 @@ __global__ void __launch_bounds__(1024) domino_tiled_kernel(const uint32_t *__re
         uint32_t v[4];
         ld4(lds + p * LPS + (ir + HR) * LRS + 4 * (ig + HG), v);
         st4(out + p * PS + (size_t)orow * RS + 4 * og, v);
+    }
+}
+
+// ------------------------------------------------------------ batched chains
+// Persistent kernel over a list of independent chains (longest first).  A
+// work-group takes the next chain from an atomic counter, copies its whole
+// state into LDS (compact rows of 4*ng words, n rows, no padding), runs all
+// nsweeps sweeps there and writes it back.  Every work-group leaves the loop
+// once the counter passes the end of the list.
+__global__ void batch_reset_kernel(uint32_t *counter) { *counter = 0u; }
+
+template <int MODE>
+__global__ void __launch_bounds__(1024) domino_batch_kernel(BatchChain *chains, const uint32_t *order, uint32_t count,
+                                                            uint32_t *counter, uint32_t *planes, uint32_t nsweeps,
+                                                            Thr Tall)
+{
+    extern __shared__ uint32_t lds[];
+    __shared__ uint32_t s_next;
+    const uint32_t tid = threadIdx.x, nt = blockDim.x;
+    for (;;) {
+        if (tid == 0) s_next = atomicAdd(counter, 1u);
+        __syncthreads();
+        const uint32_t i = s_next;
+        __syncthreads();
+        if (i >= count) return;
+        const uint32_t ci = order[i];
+        const BatchChain ch = chains[ci];
+        const uint32_t n = ch.n, ng = ch.ng, LRS = 4 * ng, LPS = n * LRS;
+        const uint32_t omega = (n + 1) & 1u;
+        uint32_t *g = planes + ch.offset;
+        const uint32_t items = 4 * n * ng;
+        for (uint32_t j = tid; j < items; j += nt) {
+            const uint32_t gg = j % ng, r = (j / ng) % n, p = j / (ng * n);
+            uint32_t v[4];
+            ld4(g + p * ch.PS + (size_t)r * ch.RS + 4 * gg, v);
+            st4(lds + p * LPS + r * LRS + 4 * gg, v);
+        }
+        __syncthreads();
+        const uint32_t tasks = n * ng;
+        for (uint32_t s = 0; s < nsweeps; ++s) {
+            const uint32_t t = ch.t + s;
+            for (uint32_t c = 0; c < 2; ++c) {
+                for (uint32_t task = tid; task < tasks; task += nt) {
+                    const uint32_t r = task / ng, gg = task % ng;
+                    uint32_t *pN = lds + r * LRS + 4 * gg;
+                    if (c == omega)
+                        owner_group<MODE>(pN, pN + LPS, pN + 2 * LPS, pN + 3 * LPS, r, gg, c, t, Tall, ch.key0,
+                                          ch.key1);
+                    else if (r + 1 < n)
+                        other_group<MODE>(pN, pN + 2 * LPS, pN + LPS + LRS, pN + 3 * LPS + LRS, r, gg, c, t, Tall,
+                                          ch.key0, ch.key1, gg + 1 < ng);
+                }
+                __syncthreads();
+            }
+        }
+        for (uint32_t j = tid; j < items; j += nt) {
+            const uint32_t gg = j % ng, r = (j / ng) % n, p = j / (ng * n);
+            uint32_t v[4];
+            ld4(lds + p * LPS + r * LRS + 4 * gg, v);
+            st4(g + p * ch.PS + (size_t)r * ch.RS + 4 * gg, v);
+        }
+        if (tid == 0) chains[ci].t = ch.t + nsweeps;
+        __syncthreads();
     }
 }
 
@@ -516,6 +582,21 @@ hipError_t domino_tiled_sweeps(DominoDev &d, const DominoTile &tile, uint32_t t0
         done += S;
     }
     return hipSuccess;
+}
+
+hipError_t domino_batch_sweeps(BatchChain *chains, const uint32_t *order, uint32_t count, uint32_t *counter,
+                               uint32_t *planes, uint32_t nsweeps, const Thr &T, int metropolis, uint32_t threads,
+                               uint32_t workgroups, uint32_t lds_bytes, hipStream_t s, Timing *tm)
+{
+    if (threads == 0 || threads > 1024 || (threads & 63) || lds_bytes > 160u * 1024u - 64u)
+        return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(1), 0, s, counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    auto k = T.uniform() ? domino_batch_kernel<kUniform>
+                         : (metropolis ? domino_batch_kernel<kMetropolis> : domino_batch_kernel<kHeatBath>);
+    return launch(tm, 2 * nsweeps, k, dim3(workgroups), dim3(threads), lds_bytes, s, chains, order, count, counter,
+                  planes, nsweeps, T);
 }
 
 hipError_t domino_export(const DominoDev &d, uint8_t *faces, hipStream_t s)

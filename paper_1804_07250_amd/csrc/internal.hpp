@@ -129,6 +129,25 @@ hipError_t domino_export(const DominoDev &d, uint8_t *faces, hipStream_t s);
 hipError_t domino_observe(const DominoDev &d, uint32_t B, uint32_t bins_x, unsigned long long *bins,
                           hipStream_t s);
 
+// ------------------------------------------------------------ batched chains
+// One entry per domino chain of a batch; planes of chain i start at word
+// `offset` of the batch buffer and use the DominoDev layout of its order n.
+struct BatchChain {
+    uint64_t offset;
+    uint64_t PS;
+    uint32_t n, ng, RS;
+    uint32_t key0, key1;
+    uint32_t t;        // sweeps done, advanced by the kernel
+    uint32_t lds_bytes;
+    uint32_t pad;
+};
+// Advance every chain listed in order[0..count) by nsweeps sweeps: one
+// persistent launch; work-groups take chains from an atomic counter (reset by
+// a small kernel first, so the pair can be captured in a graph).
+hipError_t domino_batch_sweeps(BatchChain *chains, const uint32_t *order, uint32_t count, uint32_t *counter,
+                               uint32_t *planes, uint32_t nsweeps, const Thr &T, int metropolis, uint32_t threads,
+                               uint32_t workgroups, uint32_t lds_bytes, hipStream_t s, Timing *tm = nullptr);
+
 // ------------------------------------------------------ height-function models
 // Bit-planes of a 1-bit height residual: plane p, row y, word w at
 // planes[p*PS + y*RS + 4 + w] (a zero pad group before and after each row).

@@ -327,3 +327,33 @@ std::unique_ptr<Model> make_model(const tl_domain &d, std::string &why)
 }
 
 }  // namespace tl
+
+namespace tl {
+
+size_t sampler_device_bytes(const tl_domain &d, uint32_t obs_bin)
+{
+    std::string why;
+    if (!make_model(d, why)) return 0;
+    const uint32_t B = obs_bin ? obs_bin : 1u;
+    size_t words = 0, cells_w = 0, cells_h = 0;
+    if (d.model == TL_DOMINO) {
+        uint32_t ng, RS;
+        size_t PS;
+        words = domino_words(d.n, &ng, &RS, &PS);
+        cells_w = cells_h = 2u * (uint32_t)d.n;
+    } else {
+        HeightDev h;
+        h.model = d.model;
+        h.a = d.a;
+        h.b = d.b;
+        h.c = d.c;
+        h.N = d.n;
+        words = height_words(h);
+        cells_w = d.model == TL_LOZENGE ? (size_t)(d.a + d.c + 1) : (size_t)d.n;
+        cells_h = d.model == TL_LOZENGE ? (size_t)(d.b + d.c + 1) : (size_t)d.n;
+    }
+    const size_t bins = ((cells_w + B - 1) / B) * ((cells_h + B - 1) / B);
+    return 2 * words * sizeof(uint32_t) + 2 * bins * sizeof(unsigned long long);
+}
+
+}  // namespace tl
