@@ -31,6 +31,10 @@ HBM_PEAK_GBS = 8000.0
 WORKLOADS = {
     "aztec2048": dict(model="domino", n=2048, sweeps=10000, seed=7, obs_every=100, obs_bin=64),
     "aztec64": dict(model="domino", n=64, sweeps=1000, seed=1, obs_every=1, obs_bin=1),
+    "hexagon1024": dict(model="lozenge", a=1024, b=1024, c=1024, q=(1999, 2000), sweeps=20000, seed=11,
+                        obs_every=200, obs_bin=64),
+    "sixv1024": dict(model="sixvertex", n=1024, w2=(1.0, 1.0, 2.0), sweeps=2000, seed=0, obs_every=100, obs_bin=64),
+    "sixv1024u": dict(model="sixvertex", n=1024, w2=(1.0, 1.0, 1.0), sweeps=2000, seed=1, obs_every=100, obs_bin=64),
 }
 
 
@@ -62,6 +66,7 @@ def parse():
     p.add_argument("--served-sweeps", type=int, default=2000)
     p.add_argument("--served-budget-mib", type=int, default=1024)
     p.add_argument("--served-slots", type=int, default=64)
+    p.add_argument("--served-quantum", type=int, default=8, help="sweeps per tick of a weighted request")
     return p.parse_args()
 
 
@@ -111,7 +116,7 @@ def run_served(tl, args):
     from paper_1804_07250_amd import workloads
     from paper_1804_07250_amd.serving import Server
     reqs = workloads.serve_requests(args.served_requests, args.served_rate)
-    sv = Server(args.served_budget_mib << 20, args.served_slots, tl.options(sweeps_per_launch=250))
+    sv = Server(args.served_budget_mib << 20, args.served_slots, tl.options(sweeps_per_launch=args.served_quantum))
     start = time.perf_counter()
     tickets = []
     for r in reqs:
@@ -134,8 +139,9 @@ def run_served(tl, args):
             "peak_active": st["peak_active"], "peak_bytes": st["peak_bytes"],
             "workload": "served: six-vertex DWBC, N uniform over {64,128,256,512,1024}, weights (1,1,sqrt2) and "
                         "(1,1,1) alternating, %d sweeps per request, Poisson %.0f/s, %d requests, budget %d MiB, "
-                        "%d slots, quanta of 250 sweeps" % (args.served_sweeps, args.served_rate, len(res),
-                                                           args.served_budget_mib, args.served_slots)}
+                        "%d slots, ticks of %d sweeps (x4 for one-bit jobs)"
+                        % (args.served_sweeps, args.served_rate, len(res), args.served_budget_mib, args.served_slots,
+                           args.served_quantum)}
 
 
 def make_sampler(tl, wl, args):
@@ -145,9 +151,28 @@ def make_sampler(tl, wl, args):
     if wl["model"] == "domino":
         dom = tl.domain(tl.TL_DOMINO, n=wl["n"])
         w = tl.weights(tl.TL_W_UNIFORM)
+    elif wl["model"] == "lozenge":
+        dom = tl.domain(tl.TL_LOZENGE, a=wl["a"], b=wl["b"], c=wl["c"])
+        w = tl.weights(tl.TL_W_VOLUME, *wl["q"])
     else:
-        raise ValueError(wl["model"])
+        dom = tl.domain(tl.TL_SIXVERTEX, n=wl["n"])
+        w = tl.weights(tl.TL_W_SIXVERTEX, *wl["w2"])
     return tl.Sampler(dom, w, wl["seed"], opt)
+
+
+def describe(wl):
+    if wl["model"] == "domino":
+        return ("plain: domino tilings of the order-%d Aztec diamond, uniform, brick start, %d sweeps, seed %d, "
+                "2 bits/face, %dx%d-face density bins every %d sweeps, row hash"
+                % (wl["n"], wl["sweeps"], wl["seed"], wl["obs_bin"], wl["obs_bin"], wl["obs_every"]))
+    if wl["model"] == "lozenge":
+        return ("plain: lozenge tilings of the %dx%dx%d hexagon, q = %d/%d, empty-box start, %d sweeps, seed %d, "
+                "1 bit/vertex, volume bins %dx%d every %d sweeps, row hash"
+                % (wl["a"], wl["b"], wl["c"], wl["q"][0], wl["q"][1], wl["sweeps"], wl["seed"], wl["obs_bin"],
+                   wl["obs_bin"], wl["obs_every"]))
+    return ("plain: six-vertex model, domain-wall %dx%d, (a^2,b^2,c^2) = %s, h_min start, %d sweeps, seed %d, "
+            "1 bit/face, c-vertex bins %dx%d every %d sweeps, row hash"
+            % (wl["n"], wl["n"], wl["w2"], wl["sweeps"], wl["seed"], wl["obs_bin"], wl["obs_bin"], wl["obs_every"]))
 
 
 def traffic_record(name):
@@ -172,12 +197,23 @@ def cpu_baseline(wl, budget_s):
     """The serial oracle on the same workload from its start, for a bounded
     number of sweeps (about budget_s seconds)."""
     import oracle
-    if wl["model"] != "domino":
-        return None
-    n = wl["n"]
-    thr = oracle.table_from_ratios(oracle.domino_ratios(), False)
-    o = oracle.DominoOracle(n, thr, seed=wl["seed"])
-    sites = 2 * n * n - 2 * n + 1
+    from fractions import Fraction
+    if wl["model"] == "domino":
+        n = wl["n"]
+        thr = oracle.table_from_ratios(oracle.domino_ratios(), False)
+        o = oracle.DominoOracle(n, thr, seed=wl["seed"])
+        sites = 2 * n * n - 2 * n + 1
+    elif wl["model"] == "lozenge":
+        thr = oracle.table_from_ratios(oracle.lozenge_ratios(Fraction(*wl["q"])), False)
+        o = oracle.LozengeOracle(wl["a"], wl["b"], wl["c"], thr, seed=wl["seed"])
+        sites = len(o.sites())
+        n = "%dx%dx%d" % (wl["a"], wl["b"], wl["c"])
+    else:
+        a2, b2, c2 = wl["w2"]
+        thr = oracle.table_from_ratios(oracle.sixv_ratios(int(a2 ** 0.5), int(b2 ** 0.5), int(c2)), False)
+        o = oracle.SixVertexOracle(wl["n"], thr, seed=wl["seed"])
+        sites = (wl["n"] - 1) ** 2
+        n = wl["n"]
     done = 0
     t0 = time.perf_counter()
     chunk = 1
@@ -189,8 +225,8 @@ def cpu_baseline(wl, budget_s):
             chunk *= 2
     el = time.perf_counter() - t0
     return {"value": sites * done / el, "unit": "site-updates/s", "cores": 1, "kind": "oracle",
-            "sample": "serial C oracle, first %d of %d sweeps of the same chain (order %d, seed %d, from the "
-                      "brick tiling), %.1f s" % (done, wl["sweeps"], n, wl["seed"], el)}
+            "sample": "serial C oracle, first %d of %d sweeps of the same %s chain (size %s, seed %d, from its "
+                      "extremal start), %.1f s" % (done, wl["sweeps"], wl["model"], n, wl["seed"], el)}
 
 
 def main():
@@ -244,7 +280,7 @@ def main():
     avg_ms = kms / max(1, launches)
     bytes_per_launch = bpc * csteps / max(1, launches)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if launches else 0.0
-    kname = "domino_tiled" if args.kernel != 1 else "domino_streaming"
+    kname = ("domino" if wl["model"] == "domino" else "height") + ("_tiled" if args.kernel != 1 else "_streaming")
     rec = traffic_record("%s_%s" % (kname, args.workload))
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -255,10 +291,7 @@ def main():
            "value": value, "unit": "site-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": el / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "u32", "data": "synthetic",
-           "config": {"workload": "plain: domino tilings of the order-%d Aztec diamond, uniform, brick start, "
-                                  "%d sweeps, seed %d, 2 bits/face, %dx%d-face density bins every %d sweeps, row hash"
-                                  % (wl["n"], wl["sweeps"], wl["seed"], wl["obs_bin"], wl["obs_bin"],
-                                     wl["obs_every"]),
+           "config": {"workload": describe(wl),
                       "sites": sites, "colours": colours, "sweeps": wl["sweeps"],
                       "kernel": "tiled" if args.kernel != 1 else "streaming",
                       "hash": digest},

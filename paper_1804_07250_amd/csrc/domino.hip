@@ -142,6 +142,8 @@ struct DomCtx<true> {
 // is 0, so one Philox call decides all 128 sites and does not depend on the
 // state; it is issued first to overlap the memory latency).
 enum { kHeatBath = 0, kMetropolis = 1, kUniform = 2 };
+static_assert(kHeatBath == kModeHeatBath && kMetropolis == kModeMetropolis && kUniform == kModeUniform,
+              "kernel modes and TileJob modes agree");
 
 template <int MODE>
 __device__ __forceinline__ void decide_group(uint32_t key0, uint32_t key1, uint32_t g, uint32_t r, uint32_t t,
@@ -286,24 +288,28 @@ __global__ void __launch_bounds__(256) domino_other_step(uint32_t *planes, size_
 // Block = one tile.  Local (lr, lg) is global row R0 + lr, group G0 + lg.  LDS:
 // 4 planes x LR rows x LRS words (LRS = 4*LG + 4: one zero pad group per row).
 // One thread per (row, group) task; blockDim >= LR * LG.
+// One tile of the multi-sweep kernel: TR owner rows x TG groups (tile index
+// (tile_r, tile_g)) plus HR halo rows and HG halo groups on each side are
+// loaded into LDS, advanced nsweeps sweeps there, and the interior written to
+// `out`.  Halo cells repeat their neighbours' keyed draws, so the interior
+// matches the sweep of the whole state; halo rows go stale one per sweep from
+// each side, so sweep s computes only rows [s, LR - s).  Thread tid handles
+// group tid % LG of rows tid / LG, tid / LG + RP, ... (RP rows per pass).
 template <int MODE>
-__global__ void __launch_bounds__(1024) domino_tiled_kernel(const uint32_t *__restrict__ in,
-                                                            uint32_t *__restrict__ out, size_t PS, uint32_t RS,
-                                                            uint32_t ng, uint32_t n, uint32_t omega, uint32_t t0,
-                                                            uint32_t nsweeps, uint32_t TR, uint32_t TG,
-                                                            uint32_t HR, uint32_t HG, uint32_t tiles_x,
-                                                            Thr Tall, uint32_t key0, uint32_t key1)
+__device__ __forceinline__ void domino_tile(uint32_t *lds, const uint32_t *__restrict__ in,
+                                            uint32_t *__restrict__ out, size_t PS, uint32_t RS, uint32_t ng,
+                                            uint32_t n, uint32_t omega, uint32_t t0, uint32_t nsweeps, uint32_t TR,
+                                            uint32_t TG, uint32_t HR, uint32_t HG, uint32_t tile_r, uint32_t tile_g,
+                                            const Thr &Tall, uint32_t key0, uint32_t key1)
 {
-    extern __shared__ uint32_t lds[];
     const uint32_t LR = TR + 2 * HR, LG = TG + 2 * HG, LRS = 4 * LG + 4;
     const uint32_t LPS = LR * LRS;
-    const uint32_t tile_r = blockIdx.x / tiles_x, tile_g = blockIdx.x % tiles_x;
     const int R0 = (int)(tile_r * TR) - (int)HR, G0 = (int)(tile_g * TG) - (int)HG;
-    const uint32_t tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x, nt = blockDim.x;
 
     // load tile + halo (zero outside the state), one uint4 per item
     const uint32_t items = 4 * LR * (LG + 1);
-    for (uint32_t i = tid; i < items; i += blockDim.x) {
+    for (uint32_t i = tid; i < items; i += nt) {
         const uint32_t lg = i % (LG + 1), lr = (i / (LG + 1)) % LR, p = i / ((LG + 1) * LR);
         const int gr = R0 + (int)lr, gg = G0 + (int)lg;
         uint32_t v[4] = {0u, 0u, 0u, 0u};
@@ -313,20 +319,25 @@ __global__ void __launch_bounds__(1024) domino_tiled_kernel(const uint32_t *__re
     }
     __syncthreads();
 
-    const uint32_t lr = tid / LG, lg = tid % LG;
-    const int gr = R0 + (int)lr, gg = G0 + (int)lg;
-    const bool active = tid < LR * LG && gr >= 0 && gr < (int)n && gg >= 0 && gg < (int)ng;
-    uint32_t *pN = lds + lr * LRS + 4 * lg;
+    const uint32_t RP = nt / LG, r0 = tid / LG, lg = tid % LG;
+    const int gg = G0 + (int)lg;
+    const bool lane = r0 < RP && gg >= 0 && gg < (int)ng;
     for (uint32_t s = 0; s < nsweeps; ++s) {
         const uint32_t t = t0 + s;
+        const uint32_t base = HR ? s : 0u, end = HR ? LR - s : LR;
         for (uint32_t c = 0; c < 2; ++c) {
-            if (active) {
-                if (c == omega)
-                    owner_group<MODE>(pN, pN + LPS, pN + 2 * LPS, pN + 3 * LPS, (uint32_t)gr, (uint32_t)gg, c, t,
-                                       Tall, key0, key1);
-                else if (lr + 1 < LR)
-                    other_group<MODE>(pN, pN + 2 * LPS, pN + LPS + LRS, pN + 3 * LPS + LRS, (uint32_t)gr,
-                                       (uint32_t)gg, c, t, Tall, key0, key1);
+            if (lane) {
+                for (uint32_t lr = base + r0; lr < end; lr += RP) {
+                    const int gr = R0 + (int)lr;
+                    if (gr < 0 || gr >= (int)n) continue;
+                    uint32_t *pN = lds + lr * LRS + 4 * lg;
+                    if (c == omega)
+                        owner_group<MODE>(pN, pN + LPS, pN + 2 * LPS, pN + 3 * LPS, (uint32_t)gr, (uint32_t)gg, c,
+                                          t, Tall, key0, key1);
+                    else if (lr + 1 < LR)
+                        other_group<MODE>(pN, pN + 2 * LPS, pN + LPS + LRS, pN + 3 * LPS + LRS, (uint32_t)gr,
+                                          (uint32_t)gg, c, t, Tall, key0, key1);
+                }
             }
             __syncthreads();
         }
@@ -334,7 +345,7 @@ __global__ void __launch_bounds__(1024) domino_tiled_kernel(const uint32_t *__re
 
     // store the interior
     const uint32_t oitems = 4 * TR * TG;
-    for (uint32_t i = tid; i < oitems; i += blockDim.x) {
+    for (uint32_t i = tid; i < oitems; i += nt) {
         const uint32_t ig = i % TG, ir = (i / TG) % TR, p = i / (TG * TR);
         const uint32_t orow = tile_r * TR + ir, og = tile_g * TG + ig;
         if (orow >= n || og >= ng) continue;
@@ -342,6 +353,43 @@ __global__ void __launch_bounds__(1024) domino_tiled_kernel(const uint32_t *__re
         ld4(lds + p * LPS + (ir + HR) * LRS + 4 * (ig + HG), v);
         st4(out + p * PS + (size_t)orow * RS + 4 * og, v);
     }
+}
+
+// Tiled multi-sweep kernel of one state: one work-group per tile.
+template <int MODE>
+__global__ void __launch_bounds__(1024) domino_tiled_kernel(const uint32_t *__restrict__ in,
+                                                            uint32_t *__restrict__ out, size_t PS, uint32_t RS,
+                                                            uint32_t ng, uint32_t n, uint32_t omega, uint32_t t0,
+                                                            uint32_t nsweeps, uint32_t TR, uint32_t TG,
+                                                            uint32_t HR, uint32_t HG, uint32_t tiles_x,
+                                                            Thr Tall, uint32_t key0, uint32_t key1)
+{
+    extern __shared__ uint32_t lds[];
+    domino_tile<MODE>(lds, in, out, PS, RS, ng, n, omega, t0, nsweeps, TR, TG, HR, HG, blockIdx.x / tiles_x,
+                      blockIdx.x % tiles_x, Tall, key0, key1);
+}
+
+// Multi-job kernel: work-group b runs tile items[b].tile of job items[b].job,
+// with that job's plan, thresholds and key.
+template <int MODE>
+__device__ __forceinline__ void domino_item(uint32_t *lds, const TileJob &j, uint32_t tile)
+{
+    domino_tile<MODE>(lds, j.in, j.out, j.PS, j.RS, j.ng, j.rows, (uint32_t)j.omega, j.t0, j.S, j.TR, j.TG, j.HR,
+                      j.HG, tile / j.tiles_x, tile % j.tiles_x, j.T, j.key0, j.key1);
+}
+
+__global__ void __launch_bounds__(1024) domino_items_kernel(const TileJob *__restrict__ jobs,
+                                                            const TileItem *__restrict__ items)
+{
+    extern __shared__ uint32_t lds[];
+    const TileItem it = items[blockIdx.x];
+    const TileJob &j = jobs[it.job];
+    if (j.mode == kUniform)
+        domino_item<kUniform>(lds, j, it.tile);
+    else if (j.mode == kMetropolis)
+        domino_item<kMetropolis>(lds, j, it.tile);
+    else
+        domino_item<kHeatBath>(lds, j, it.tile);
 }
 
 // ------------------------------------------------------------ batched chains
@@ -540,48 +588,96 @@ DominoTile domino_auto_tile(int n)
     return t;
 }
 
-hipError_t domino_tiled_sweeps(DominoDev &d, const DominoTile &tile, uint32_t t0, uint32_t nsw, const Thr &T,
-                               int metropolis, uint64_t seed, hipStream_t s, Timing *tm)
+bool domino_plan(const DominoDev &d, const DominoTile &tile, uint32_t S_max, TilePlan *p)
 {
-    const uint32_t key0 = (uint32_t)seed, key1 = (uint32_t)(seed >> 32);
     const uint32_t n = (uint32_t)d.n;
+    if (n == 0 || S_max == 0) return false;
     const uint32_t TG = tile.TG == 0 ? 1u : (tile.TG < d.ng ? tile.TG : d.ng);
     const uint32_t tiles_x = (d.ng + TG - 1) / TG;
     const uint32_t LG0 = TG + (tiles_x > 1 ? 2u : 0u);
     const uint32_t max_rows = 1024u / LG0;   // one thread per (row, group) task
-    if (max_rows < 3u) return hipErrorInvalidConfiguration;
+    if (max_rows < 3u) return false;
     uint32_t TR = tile.TR == 0 ? 1u : (tile.TR < n ? tile.TR : n);
     if (TR < n && TR > max_rows - 2u) TR = max_rows - 2u;   // leave room for a halo
     if (TR >= n && n > max_rows) TR = max_rows - 2u;
     const uint32_t tiles_y = (n + TR - 1) / TR;
+    uint32_t S = S_max < tile.S ? S_max : tile.S;
+    if (tiles_x > 1 && S > 128u) S = 128u;   // the one-group column halo covers 128 sweeps
+    if (tiles_y > 1 && S > (max_rows - TR) / 2u) S = (max_rows - TR) / 2u;
+    if (S == 0u) S = 1u;
+    const uint32_t HR = tiles_y > 1 ? S : 0u;
+    const uint32_t HG = tiles_x > 1 ? 1u : 0u;
+    const uint32_t LR = TR + 2 * HR, LG = TG + 2 * HG;
+    const uint32_t tasks = LR * LG;
+    const uint32_t lds = 4u * LR * (4u * LG + 4u) * 4u;
+    if (tasks > 1024u || lds > 160u * 1024u) return false;
+    p->S = S;
+    p->TR = TR;
+    p->TG = TG;
+    p->HR = HR;
+    p->HG = HG;
+    p->tiles_x = tiles_x;
+    p->tiles_y = tiles_y;
+    p->threads = (tasks + 63) / 64 * 64;
+    p->lds = lds;
+    return true;
+}
+
+hipError_t domino_tiled_sweeps(DominoDev &d, const DominoTile &tile, uint32_t t0, uint32_t nsw, const Thr &T,
+                               int metropolis, uint64_t seed, hipStream_t s, Timing *tm)
+{
+    const uint32_t key0 = (uint32_t)seed, key1 = (uint32_t)(seed >> 32);
     uint32_t done = 0;
     while (done < nsw) {
-        uint32_t S = nsw - done;
-        if (S > tile.S) S = tile.S;
-        if (tiles_x > 1 && S > 128u) S = 128u;   // the one-group column halo covers 128 sweeps
-        if (tiles_y > 1 && S > (max_rows - TR) / 2u) S = (max_rows - TR) / 2u;
-        if (S == 0u) S = 1u;
-        const uint32_t HR = tiles_y > 1 ? S : 0u;
-        const uint32_t HG = tiles_x > 1 ? 1u : 0u;
-        const uint32_t LR = TR + 2 * HR, LG = TG + 2 * HG;
-        const uint32_t tasks = LR * LG;
-        if (tasks > 1024) return hipErrorInvalidConfiguration;
-        const uint32_t threads = (tasks + 63) / 64 * 64;
-        const uint32_t shmem = 4u * LR * (4u * LG + 4u) * 4u;
-        if (shmem > 160u * 1024u) return hipErrorInvalidConfiguration;
-        dim3 grid(tiles_x * tiles_y), block(threads);
-        hipError_t e;
+        TilePlan p;
+        if (!domino_plan(d, tile, nsw - done, &p)) return hipErrorInvalidConfiguration;
         auto k = T.uniform() ? domino_tiled_kernel<kUniform>
                              : (metropolis ? domino_tiled_kernel<kMetropolis> : domino_tiled_kernel<kHeatBath>);
-        e = launch(tm, 2 * S, k, grid, block, shmem, s, (const uint32_t *)d.planes, d.spare, d.PS, d.RS, d.ng, n,
-                   (uint32_t)d.omega, t0 + done, S, TR, TG, HR, HG, tiles_x, T, key0, key1);
+        hipError_t e = launch(tm, 2 * p.S, k, dim3(p.tiles()), dim3(p.threads), p.lds, s, (const uint32_t *)d.planes,
+                              d.spare, d.PS, d.RS, d.ng, (uint32_t)d.n, (uint32_t)d.omega, t0 + done, p.S, p.TR,
+                              p.TG, p.HR, p.HG, p.tiles_x, T, key0, key1);
         if (e != hipSuccess) return e;
         uint32_t *tmp = d.planes;
         d.planes = d.spare;
         d.spare = tmp;
-        done += S;
+        done += p.S;
     }
     return hipSuccess;
+}
+
+TileJob domino_tile_job(const DominoDev &d, const TilePlan &p, uint32_t t0, const Thr &T, int metropolis,
+                        uint64_t seed)
+{
+    TileJob j{};
+    j.in = d.planes;
+    j.out = d.spare;
+    j.PS = d.PS;
+    j.RS = d.RS;
+    j.ng = d.ng;
+    j.rows = (uint32_t)d.n;
+    j.P = 4;
+    j.omega = d.omega;
+    j.t0 = t0;
+    j.S = p.S;
+    j.TR = p.TR;
+    j.TG = p.TG;
+    j.HR = p.HR;
+    j.HG = p.HG;
+    j.tiles_x = p.tiles_x;
+    j.mode = T.uniform() ? kModeUniform : (metropolis ? kModeMetropolis : kModeHeatBath);
+    j.key0 = (uint32_t)seed;
+    j.key1 = (uint32_t)(seed >> 32);
+    j.T = T;
+    return j;
+}
+
+hipError_t domino_items(const TileJob *jobs, const TileItem *items, uint32_t n_items, uint32_t threads, uint32_t lds,
+                        hipStream_t s)
+{
+    if (n_items == 0) return hipSuccess;
+    if (threads == 0 || threads > 1024u || lds > 160u * 1024u) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(domino_items_kernel, dim3(n_items), dim3(threads), lds, s, jobs, items);
+    return hipGetLastError();
 }
 
 hipError_t domino_batch_sweeps(BatchChain *chains, const uint32_t *order, uint32_t count, uint32_t *counter,

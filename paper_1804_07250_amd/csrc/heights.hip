@@ -50,6 +50,8 @@ size_t height_words(HeightDev &d)
 namespace {
 
 enum { kHeatBath = 0, kMetropolis = 1, kUniform = 2 };
+static_assert(kHeatBath == kModeHeatBath && kMetropolis == kModeMetropolis && kUniform == kModeUniform,
+              "kernel modes and TileJob modes agree");
 
 struct Geo {
     int model, a, b, c, N;
@@ -301,27 +303,29 @@ __global__ void __launch_bounds__(256) height_step_kernel(uint32_t *planes, size
     height_group<MODE>(planes, PS, RS, y, g, geo, (int)y, g, colour, t, T, k0, k1);
 }
 
-// Tiled multi-sweep kernel.  LDS: P planes x LR rows x LRS words, LRS =
-// 4*(LG+2) (the pad groups hold the neighbouring groups, or zero).  Local row
-// lr is global row R0 + lr, local group lg is global group G0 + lg.
+// One tile of the multi-sweep kernel.  LDS: P planes x LR rows x LRS words,
+// LRS = 4*(LG+2) (the pad groups hold the neighbouring groups, or zero).  Local
+// row lr is global row R0 + lr, local group lg is global group G0 + lg.  With a
+// row halo, the rows still valid before sweep s are [rps*s, LR - rps*s) (rps
+// rows go stale per sweep on each side), and only those are computed.  Thread
+// tid handles group tid % LG of rows tid / LG, tid / LG + RP, ... (RP rows
+// per pass).
 template <int MODE>
-__global__ void __launch_bounds__(1024) height_tiled_kernel(const uint32_t *__restrict__ in,
-                                                            uint32_t *__restrict__ out, size_t PS, uint32_t RS,
-                                                            uint32_t ng, uint32_t rows, uint32_t P, Geo geo,
-                                                            uint32_t K, uint32_t t0, uint32_t nsweeps, uint32_t TR,
-                                                            uint32_t TG, uint32_t HR, uint32_t HG, uint32_t tiles_x,
-                                                            Thr T, uint32_t k0, uint32_t k1)
+__device__ __forceinline__ void height_tile(uint32_t *lds, const uint32_t *__restrict__ in,
+                                            uint32_t *__restrict__ out, size_t PS, uint32_t RS, uint32_t ng,
+                                            uint32_t rows, uint32_t P, const Geo &geo, uint32_t t0,
+                                            uint32_t nsweeps, uint32_t TR, uint32_t TG, uint32_t HR, uint32_t HG,
+                                            uint32_t tile_r, uint32_t tile_g, const Thr &T, uint32_t k0,
+                                            uint32_t k1)
 {
-    extern __shared__ uint32_t lds[];
     const uint32_t LR = TR + 2 * HR, LG = TG + 2 * HG, LRS = 4 * (LG + 2);
     const uint32_t LPS = LR * LRS;
-    const uint32_t tile_r = blockIdx.x / tiles_x, tile_g = blockIdx.x % tiles_x;
     const int R0 = (int)(tile_r * TR) - (int)HR, G0 = (int)(tile_g * TG) - (int)HG;
-    const uint32_t tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x, nt = blockDim.x;
 
     // load LR rows x (LG + 2) groups (including the pad groups) per plane
     const uint32_t items = P * LR * (LG + 2);
-    for (uint32_t i = tid; i < items; i += blockDim.x) {
+    for (uint32_t i = tid; i < items; i += nt) {
         const uint32_t lg = i % (LG + 2), lr = (i / (LG + 2)) % LR, p = i / ((LG + 2) * LR);
         const int gr = R0 + (int)lr, gg = G0 - 1 + (int)lg;   // global group, -1 .. ng = pads
         uint32_t v[4] = {0u, 0u, 0u, 0u};
@@ -331,21 +335,28 @@ __global__ void __launch_bounds__(1024) height_tiled_kernel(const uint32_t *__re
     }
     __syncthreads();
 
-    const uint32_t lr = tid / LG, lg = tid % LG;
-    const int gr = R0 + (int)lr, gg = G0 + (int)lg;
-    const bool active = tid < LR * LG && lr >= 1 && lr + 1 < LR && gg >= 0 && gg < (int)ng &&
-                        site_row(geo, gr, rows);
+    const uint32_t RP = nt / LG, r0 = tid / LG, lg = tid % LG;
+    const int gg = G0 + (int)lg;
+    const bool lane = r0 < RP && gg >= 0 && gg < (int)ng;
     const uint32_t K_colours = geo.model == TL_LOZENGE ? 3u : 4u;
+    const uint32_t rps = geo.model == TL_LOZENGE ? 3u : 2u;
     for (uint32_t s = 0; s < nsweeps; ++s) {
         const uint32_t t = t0 + s;
+        const uint32_t base = HR ? rps * s : 0u, end = HR ? LR - rps * s : LR;
         for (uint32_t c = 0; c < K_colours; ++c) {
-            if (active) height_group<MODE>(lds, LPS, LRS, lr, lg, geo, gr, (uint32_t)gg, c, t, T, k0, k1);
+            if (lane) {
+                for (uint32_t lr = base + r0; lr < end; lr += RP) {
+                    const int gr = R0 + (int)lr;
+                    if (lr >= 1 && lr + 1 < LR && site_row(geo, gr, rows))
+                        height_group<MODE>(lds, LPS, LRS, lr, lg, geo, gr, (uint32_t)gg, c, t, T, k0, k1);
+                }
+            }
             __syncthreads();
         }
     }
 
     const uint32_t oitems = P * TR * TG;
-    for (uint32_t i = tid; i < oitems; i += blockDim.x) {
+    for (uint32_t i = tid; i < oitems; i += nt) {
         const uint32_t ig = i % TG, ir = (i / TG) % TR, p = i / (TG * TR);
         const uint32_t orow = tile_r * TR + ir, og = tile_g * TG + ig;
         if (orow >= rows || og >= ng) continue;
@@ -353,6 +364,44 @@ __global__ void __launch_bounds__(1024) height_tiled_kernel(const uint32_t *__re
         hld4(lds + p * LPS + (ir + HR) * LRS + 4 * (ig + HG + 1), v);
         hst4(out + p * PS + (size_t)orow * RS + 4 + 4 * og, v);
     }
+}
+
+// Tiled multi-sweep kernel of one state: one work-group per tile.
+template <int MODE>
+__global__ void __launch_bounds__(1024) height_tiled_kernel(const uint32_t *__restrict__ in,
+                                                            uint32_t *__restrict__ out, size_t PS, uint32_t RS,
+                                                            uint32_t ng, uint32_t rows, uint32_t P, Geo geo,
+                                                            uint32_t t0, uint32_t nsweeps, uint32_t TR, uint32_t TG,
+                                                            uint32_t HR, uint32_t HG, uint32_t tiles_x, Thr T,
+                                                            uint32_t k0, uint32_t k1)
+{
+    extern __shared__ uint32_t lds[];
+    height_tile<MODE>(lds, in, out, PS, RS, ng, rows, P, geo, t0, nsweeps, TR, TG, HR, HG, blockIdx.x / tiles_x,
+                      blockIdx.x % tiles_x, T, k0, k1);
+}
+
+// Multi-job kernel: work-group b runs tile items[b].tile of job items[b].job,
+// with that job's geometry, plan, thresholds and key.
+template <int MODE>
+__device__ __forceinline__ void height_item(uint32_t *lds, const TileJob &j, uint32_t tile)
+{
+    const Geo geo{j.model, j.a, j.b, j.c, j.N};
+    height_tile<MODE>(lds, j.in, j.out, j.PS, j.RS, j.ng, j.rows, j.P, geo, j.t0, j.S, j.TR, j.TG, j.HR, j.HG,
+                      tile / j.tiles_x, tile % j.tiles_x, j.T, j.key0, j.key1);
+}
+
+__global__ void __launch_bounds__(1024) height_items_kernel(const TileJob *__restrict__ jobs,
+                                                            const TileItem *__restrict__ items)
+{
+    extern __shared__ uint32_t lds[];
+    const TileItem it = items[blockIdx.x];
+    const TileJob &j = jobs[it.job];
+    if (j.mode == kUniform)
+        height_item<kUniform>(lds, j, it.tile);
+    else if (j.mode == kMetropolis)
+        height_item<kMetropolis>(lds, j, it.tile);
+    else
+        height_item<kHeatBath>(lds, j, it.tile);
 }
 
 __device__ __forceinline__ uint32_t hbit(const uint32_t *pl, size_t PS, uint32_t RS, uint32_t p, uint32_t y,
@@ -484,50 +533,103 @@ HeightTile height_auto_tile(const HeightDev &d)
     return t;
 }
 
-hipError_t height_tiled_sweeps(HeightDev &d, const HeightTile &tile, uint32_t t0, uint32_t nsw, const Thr &T,
-                               int metropolis, uint64_t seed, hipStream_t s, Timing *tm)
+bool height_plan(const HeightDev &d, const HeightTile &tile, uint32_t S_max, TilePlan *p)
 {
-    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    if (d.rows == 0 || S_max == 0) return false;
     const uint32_t rows_per_sweep = d.model == TL_LOZENGE ? 3u : 2u;   // halo rows invalidated per sweep
     const uint32_t cols_per_sweep = d.model == TL_LOZENGE ? 1u : 2u;   // halo sites (per plane) per sweep
-    const uint32_t colours = d.model == TL_LOZENGE ? 3u : 4u;
     const uint32_t TG = tile.TG == 0 ? 1u : (tile.TG < d.ng ? tile.TG : d.ng);
     const uint32_t tiles_x = (d.ng + TG - 1) / TG;
     const uint32_t LG0 = TG + (tiles_x > 1 ? 2u : 0u);
     const uint32_t max_rows = 1024u / LG0;
-    if (max_rows < 2u * rows_per_sweep + 3u) return hipErrorInvalidConfiguration;
+    if (max_rows < 2u * rows_per_sweep + 3u) return false;
     uint32_t TR = tile.TR == 0 ? 1u : (tile.TR < d.rows ? tile.TR : d.rows);
     if (TR < d.rows && TR > max_rows - 2u * rows_per_sweep) TR = max_rows - 2u * rows_per_sweep;
     if (TR >= d.rows && d.rows > max_rows) TR = max_rows - 2u * rows_per_sweep;
     const uint32_t tiles_y = (d.rows + TR - 1) / TR;
+    uint32_t S = S_max < tile.S ? S_max : tile.S;
+    if (tiles_x > 1 && S > 128u / cols_per_sweep) S = 128u / cols_per_sweep;
+    if (tiles_y > 1 && S > (max_rows - TR) / (2u * rows_per_sweep)) S = (max_rows - TR) / (2u * rows_per_sweep);
+    if (S == 0u) S = 1u;
+    const uint32_t HR = tiles_y > 1 ? rows_per_sweep * S : 0u;
+    const uint32_t HG = tiles_x > 1 ? 1u : 0u;
+    const uint32_t LR = TR + 2 * HR, LG = TG + 2 * HG;
+    const uint32_t tasks = LR * LG;
+    const uint32_t lds = d.P * LR * 4u * (LG + 2u) * 4u;
+    if (tasks > 1024u || lds > 160u * 1024u) return false;
+    p->S = S;
+    p->TR = TR;
+    p->TG = TG;
+    p->HR = HR;
+    p->HG = HG;
+    p->tiles_x = tiles_x;
+    p->tiles_y = tiles_y;
+    p->threads = (tasks + 63) / 64 * 64;
+    p->lds = lds;
+    return true;
+}
+
+hipError_t height_tiled_sweeps(HeightDev &d, const HeightTile &tile, uint32_t t0, uint32_t nsw, const Thr &T,
+                               int metropolis, uint64_t seed, hipStream_t s, Timing *tm)
+{
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    const uint32_t colours = d.model == TL_LOZENGE ? 3u : 4u;
     uint32_t done = 0;
     while (done < nsw) {
-        uint32_t S = nsw - done;
-        if (S > tile.S) S = tile.S;
-        if (tiles_x > 1 && S > 128u / cols_per_sweep) S = 128u / cols_per_sweep;
-        if (tiles_y > 1 && S > (max_rows - TR) / (2u * rows_per_sweep)) S = (max_rows - TR) / (2u * rows_per_sweep);
-        if (S == 0u) S = 1u;
-        const uint32_t HR = tiles_y > 1 ? rows_per_sweep * S : 0u;
-        const uint32_t HG = tiles_x > 1 ? 1u : 0u;
-        const uint32_t LR = TR + 2 * HR, LG = TG + 2 * HG;
-        const uint32_t tasks = LR * LG;
-        if (tasks > 1024u) return hipErrorInvalidConfiguration;
-        const uint32_t threads = (tasks + 63) / 64 * 64;
-        const uint32_t shmem = d.P * LR * 4u * (LG + 2u) * 4u;
-        if (shmem > 160u * 1024u) return hipErrorInvalidConfiguration;
-        dim3 grid(tiles_x * tiles_y), block(threads);
+        TilePlan p;
+        if (!height_plan(d, tile, nsw - done, &p)) return hipErrorInvalidConfiguration;
         auto k = T.uniform() ? height_tiled_kernel<kUniform>
                              : (metropolis ? height_tiled_kernel<kMetropolis> : height_tiled_kernel<kHeatBath>);
-        hipError_t e = launch(tm, colours * S, k, grid, block, shmem, s, (const uint32_t *)d.planes, d.spare, d.PS,
-                              d.RS, d.ng, d.rows, d.P, geo_of(d), d.K, t0 + done, S, TR, TG, HR, HG, tiles_x, T, k0,
-                              k1);
+        hipError_t e = launch(tm, colours * p.S, k, dim3(p.tiles()), dim3(p.threads), p.lds, s,
+                              (const uint32_t *)d.planes, d.spare, d.PS, d.RS, d.ng, d.rows, d.P, geo_of(d),
+                              t0 + done, p.S, p.TR, p.TG, p.HR, p.HG, p.tiles_x, T, k0, k1);
         if (e != hipSuccess) return e;
         uint32_t *tmp = d.planes;
         d.planes = d.spare;
         d.spare = tmp;
-        done += S;
+        done += p.S;
     }
     return hipSuccess;
+}
+
+TileJob height_tile_job(const HeightDev &d, const TilePlan &p, uint32_t t0, const Thr &T, int metropolis,
+                        uint64_t seed)
+{
+    TileJob j{};
+    j.in = d.planes;
+    j.out = d.spare;
+    j.PS = d.PS;
+    j.RS = d.RS;
+    j.ng = d.ng;
+    j.rows = d.rows;
+    j.P = d.P;
+    j.K = d.K;
+    j.model = d.model;
+    j.a = d.a;
+    j.b = d.b;
+    j.c = d.c;
+    j.N = d.N;
+    j.t0 = t0;
+    j.S = p.S;
+    j.TR = p.TR;
+    j.TG = p.TG;
+    j.HR = p.HR;
+    j.HG = p.HG;
+    j.tiles_x = p.tiles_x;
+    j.mode = T.uniform() ? kModeUniform : (metropolis ? kModeMetropolis : kModeHeatBath);
+    j.key0 = (uint32_t)seed;
+    j.key1 = (uint32_t)(seed >> 32);
+    j.T = T;
+    return j;
+}
+
+hipError_t height_items(const TileJob *jobs, const TileItem *items, uint32_t n_items, uint32_t threads, uint32_t lds,
+                        hipStream_t s)
+{
+    if (n_items == 0) return hipSuccess;
+    if (threads == 0 || threads > 1024u || lds > 160u * 1024u) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(height_items_kernel, dim3(n_items), dim3(threads), lds, s, jobs, items);
+    return hipGetLastError();
 }
 
 hipError_t height_export(const HeightDev &d, int32_t *dev, hipStream_t s)

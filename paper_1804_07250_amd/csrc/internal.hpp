@@ -176,6 +176,49 @@ HeightTile height_auto_tile(const HeightDev &d);
 hipError_t height_export(const HeightDev &d, int32_t *dev, hipStream_t s);
 hipError_t height_observe(const HeightDev &d, uint32_t B, uint32_t bins_x, unsigned long long *bins, hipStream_t s);
 
+// ------------------------------------------------------ planned tile launches
+// One launch of a tiled multi-sweep kernel, planned on the host: S sweeps,
+// tiles_x * tiles_y tiles of TR rows x TG groups with HR halo rows and HG halo
+// groups on each side, `threads` per work-group (one (row, group) task per
+// thread and row pass), `lds` bytes of LDS per work-group.
+struct TilePlan {
+    uint32_t S = 0, TR = 0, TG = 0, HR = 0, HG = 0, tiles_x = 0, tiles_y = 0, threads = 0, lds = 0;
+    uint32_t tiles() const { return tiles_x * tiles_y; }
+};
+// Largest launch of at most S_max sweeps the tile shape allows (tile sizes
+// clamped as the single-state launches clamp them); false if none fits.
+bool domino_plan(const DominoDev &d, const DominoTile &tile, uint32_t S_max, TilePlan *p);
+bool height_plan(const HeightDev &d, const HeightTile &tile, uint32_t S_max, TilePlan *p);
+
+// One state's share of a multi-job launch (served form): the state it reads
+// and the buffer it writes, its geometry, launch plan, thresholds and key.
+// A work-group handles one item (job, tile).
+enum { kModeHeatBath = 0, kModeMetropolis = 1, kModeUniform = 2 };
+struct TileJob {
+    const uint32_t *in;
+    uint32_t *out;
+    uint64_t PS;
+    uint32_t RS, ng, rows, P, K;      // domino: rows = n, P = 4, K = 0
+    int32_t model, a, b, c, N, omega;   // heights: model and sides; domino: omega
+    uint32_t t0, S, TR, TG, HR, HG, tiles_x;
+    uint32_t mode;                      // kMode*
+    uint32_t key0, key1;
+    Thr T;                              // kernel table (heights: weight classes)
+};
+struct TileItem {
+    uint32_t job, tile;
+};
+TileJob domino_tile_job(const DominoDev &d, const TilePlan &p, uint32_t t0, const Thr &T, int metropolis,
+                        uint64_t seed);
+TileJob height_tile_job(const HeightDev &d, const TilePlan &p, uint32_t t0, const Thr &T, int metropolis,
+                        uint64_t seed);
+// One launch over items[0..n_items) (device arrays): threads and LDS bytes per
+// work-group at least the largest any item's plan asks for.
+hipError_t domino_items(const TileJob *jobs, const TileItem *items, uint32_t n_items, uint32_t threads,
+                        uint32_t lds, hipStream_t s);
+hipError_t height_items(const TileJob *jobs, const TileItem *items, uint32_t n_items, uint32_t threads,
+                        uint32_t lds, hipStream_t s);
+
 // ----------------------------------------------------------------- hashing
 // SHA-256 of each of `rows` rows of `row_bytes` bytes at `data` (device), into
 // 32-byte digests at `digests` (device).

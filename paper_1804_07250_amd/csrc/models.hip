@@ -4,6 +4,7 @@
 #include <stdlib.h>
 
 #include <algorithm>
+#include <utility>
 #include <string.h>
 
 #include "models.hpp"
@@ -15,22 +16,45 @@ namespace {
 // ------------------------------------------------------------------ domino
 class DominoModel : public Model {
 public:
-    explicit DominoModel(int n) { d_.n = n; d_.omega = (n + 1) & 1; }
+    explicit DominoModel(int n)
+    {
+        d_.n = n;
+        d_.omega = (n + 1) & 1;
+        words_ = domino_words(n, &d_.ng, &d_.RS, &d_.PS);
+    }
 
     hipError_t allocate() override
     {
-        const size_t words = domino_words(d_.n, &d_.ng, &d_.RS, &d_.PS);
-        hipError_t e = hipMalloc(&d_.planes, words * sizeof(uint32_t));
-        if (e == hipSuccess) e = hipMalloc(&d_.spare, words * sizeof(uint32_t));
+        hipError_t e = hipMalloc(&d_.planes, words_ * sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMalloc(&d_.spare, words_ * sizeof(uint32_t));
+        owned_ = true;
         return e;
     }
     void release() override
     {
-        if (d_.planes) (void)hipFree(d_.planes);
-        if (d_.spare) (void)hipFree(d_.spare);
+        if (owned_ && d_.planes) (void)hipFree(d_.planes);
+        if (owned_ && d_.spare) (void)hipFree(d_.spare);
         d_.planes = d_.spare = nullptr;
         timing.release();
     }
+    size_t state_words() const override { return words_; }
+    void attach(uint32_t *state, uint32_t *spare) override
+    {
+        d_.planes = state;
+        d_.spare = spare;
+        owned_ = false;
+    }
+    bool tile_job(uint32_t t0, uint32_t S_max, const Thr &T, bool metro, uint64_t seed, TileJob *j,
+                  TilePlan *p) const override
+    {
+        DominoTile tile = domino_auto_tile(d_.n);
+        tile.S = S_max;
+        if (!domino_plan(d_, tile, S_max, p)) return false;
+        *j = domino_tile_job(d_, *p, t0, T, metro ? 1 : 0, seed);
+        return true;
+    }
+    void swap_buffers() override { std::swap(d_.planes, d_.spare); }
+    bool height_family() const override { return false; }
     hipError_t init(bool init_max, hipStream_t s) override { return domino_init(d_, init_max ? 1 : 0, s); }
 
     hipError_t sweeps(uint32_t t0, uint32_t n, const Thr &T, bool metro, uint64_t seed, const tl_options &opt,
@@ -119,6 +143,8 @@ public:
 
 private:
     DominoDev d_;
+    size_t words_ = 0;
+    bool owned_ = false;
 };
 
 // ------------------------------------------------------- lozenge / six-vertex
@@ -141,15 +167,48 @@ public:
         const size_t words = height_words(d_);
         hipError_t e = hipMalloc(&d_.planes, words * sizeof(uint32_t));
         if (e == hipSuccess) e = hipMalloc(&d_.spare, words * sizeof(uint32_t));
+        owned_ = true;
         return e;
     }
     void release() override
     {
-        if (d_.planes) (void)hipFree(d_.planes);
-        if (d_.spare) (void)hipFree(d_.spare);
+        if (owned_ && d_.planes) (void)hipFree(d_.planes);
+        if (owned_ && d_.spare) (void)hipFree(d_.spare);
         d_.planes = d_.spare = nullptr;
         timing.release();
     }
+    size_t state_words() const override
+    {
+        HeightDev d = d_;
+        return height_words(d);
+    }
+    void attach(uint32_t *state, uint32_t *spare) override
+    {
+        d_.planes = state;
+        d_.spare = spare;
+        owned_ = false;
+    }
+    // Served tiles: a state whose (row, group) tasks fit one work-group and
+    // whose planes fit 64 KB of LDS is one tile (no halo, any sweep count);
+    // larger ones are cut into 32-row tiles spanning up to 8 groups.
+    bool tile_job(uint32_t t0, uint32_t S_max, const Thr &T, bool metro, uint64_t seed, TileJob *j,
+                  TilePlan *p) const override
+    {
+        HeightTile tile;
+        if (d_.rows * d_.ng <= 1024u && (size_t)d_.P * d_.rows * 4u * (d_.ng + 2u) * 4u <= 64u * 1024u) {
+            tile.TR = d_.rows;
+            tile.TG = d_.ng;
+        } else {
+            tile.TR = 32;
+            tile.TG = d_.ng <= 8u ? d_.ng : 4u;
+        }
+        tile.S = S_max;
+        if (!height_plan(d_, tile, S_max, p)) return false;
+        *j = height_tile_job(d_, *p, t0, kernel_table(T, metro), metro ? 1 : 0, seed);
+        return true;
+    }
+    void swap_buffers() override { std::swap(d_.planes, d_.spare); }
+    bool height_family() const override { return true; }
     hipError_t init(bool init_max, hipStream_t s) override { return height_init(d_, init_max ? 1 : 0, s); }
 
     // Six-vertex kernels take one threshold per weight class (sA, sB) (and
@@ -298,6 +357,7 @@ public:
 
 private:
     HeightDev d_;
+    bool owned_ = false;
 };
 
 }  // namespace

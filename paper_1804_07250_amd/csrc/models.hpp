@@ -32,6 +32,18 @@ public:
     virtual int colours() const = 0;
     // Algorithmic bytes of one colour step: the packed state read and written once.
     virtual double bytes_per_colour_step() const = 0;
+
+    // Multi-job launches (served form).  The state lives in two caller-owned
+    // buffers of state_words() words each (attach; release() leaves them);
+    // tile_job plans the next launch of at most S_max sweeps from sweep t0 and
+    // describes it (tile shape: small states in one tile, larger ones in row
+    // tiles), and swap_buffers() follows that launch.
+    virtual size_t state_words() const = 0;
+    virtual void attach(uint32_t *state, uint32_t *spare) = 0;
+    virtual bool tile_job(uint32_t t0, uint32_t S_max, const Thr &T, bool metro, uint64_t seed, TileJob *j,
+                          TilePlan *p) const = 0;
+    virtual void swap_buffers() = 0;
+    virtual bool height_family() const = 0;
     Timing timing;
 };
 

@@ -1,12 +1,18 @@
-// Served form: a request loop with continuous batching.  Sampling jobs of
-// different sizes are queued by tl_server_submit; a scheduler thread admits
-// them in arrival order while the device-memory budget and the slot count
-// allow, keeps every admitted chain resident on the device, and advances each
-// one by quanta of sweeps on its own stream, so jobs that arrive while others
-// run start as soon as memory and a slot are free and share the GPU with them.
-// A finished chain is hashed, its observable read, its memory released and the
-// next queued job admitted.  Every draw is keyed by the job's own seed and
-// sweep counter, so a job's result does not depend on what else is running.
+// Served form: continuous batching of sampling jobs on one stream.
+//
+// Requests queue in arrival order.  A scheduler thread admits them while a
+// slot is free and the device arena (one allocation of the memory budget,
+// carved first-fit) has room for the job's two state buffers, its export
+// buffer and its row digests.  The GPU then runs in ticks: one launch per
+// kernel family advances every admitted job by a few sweeps, one work-group
+// per (job, tile) item, so many jobs fill the chip together and a new job
+// joins at the next tick.  A job that reaches its sweep count is exported,
+// hashed and observed right after its last tick on the same stream; the host
+// completes the digest, posts the result and returns the memory.  Every draw
+// is keyed by the job's own seed, sweep and site, and a tile with its halo
+// computes exactly the sweep of the whole state, so a job's result does not
+// depend on what else runs beside it.
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -15,6 +21,7 @@
 #include <memory>
 #include <mutex>
 #include <new>
+#include <string.h>
 #include <thread>
 #include <vector>
 
@@ -24,18 +31,135 @@
 
 namespace {
 
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// First-fit allocator over one device allocation; free blocks coalesce.
+class Arena {
+public:
+    hipError_t init(size_t bytes)
+    {
+        size_ = bytes / kAlign * kAlign;   // never more than the budget
+        if (size_ == 0) return hipErrorInvalidValue;
+        hipError_t e = hipMalloc((void **)&base_, size_);
+        if (e == hipSuccess) free_[0] = size_;
+        return e;
+    }
+    void release()
+    {
+        if (base_) (void)hipFree(base_);
+        base_ = nullptr;
+        free_.clear();
+    }
+    bool alloc(size_t bytes, size_t *off)
+    {
+        bytes = align_up(bytes);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            *off = it->first;
+            const size_t rest = it->second - bytes, at = it->first + bytes;
+            free_.erase(it);
+            if (rest) free_[at] = rest;
+            return true;
+        }
+        return false;
+    }
+    void free(size_t off, size_t bytes)
+    {
+        bytes = align_up(bytes);
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    uint8_t *at(size_t off) const { return base_ + off; }
+    size_t size() const { return size_; }
+
+private:
+    uint8_t *base_ = nullptr;
+    size_t size_ = 0;
+    std::map<size_t, size_t> free_;   // offset -> bytes
+};
+
+// Page-locked host blocks in power-of-two size classes, reused across jobs and
+// returned to the system only when the server ends.
+class PinnedPool {
+public:
+    void *get(size_t bytes, size_t *cls)
+    {
+        size_t c = 256;
+        while (c < bytes) c <<= 1;
+        *cls = c;
+        auto &fl = free_[c];
+        if (!fl.empty()) {
+            void *p = fl.back();
+            fl.pop_back();
+            return p;
+        }
+        void *p = nullptr;
+        if (hipHostMalloc(&p, c, hipHostMallocDefault) != hipSuccess) return nullptr;
+        all_.push_back(p);
+        return p;
+    }
+    void put(void *p, size_t cls)
+    {
+        if (p) free_[cls].push_back(p);
+    }
+    void release()
+    {
+        for (void *p : all_) (void)hipHostFree(p);
+        all_.clear();
+        free_.clear();
+    }
+
+private:
+    std::map<size_t, std::vector<void *>> free_;
+    std::vector<void *> all_;
+};
+
 struct Job {
     uint64_t ticket = 0;
     tl_domain dom{};
-    tl_weights w{};
     uint64_t seed = 0;
     uint64_t sweeps = 0;
-    uint64_t done = 0;
-    size_t bytes = 0;
-    double t_submit = 0, t_start = 0, t_done = 0;
-    tl_sampler *s = nullptr;
+    uint64_t enq = 0;   // sweeps enqueued so far
+    size_t bytes = 0, off = 0;
+    double t_submit = 0, t_start = 0;
+    std::unique_ptr<tl::Model> model;
+    tl::Thr T{};
+    bool metro = false;
+    bool uniform = false;
+    uint32_t rows = 0, row_bytes = 0, obs_B = 1;
+    uint8_t *d_export = nullptr, *d_digest = nullptr;
+    unsigned long long *d_bin = nullptr;
+    uint8_t *h_res = nullptr;   // pinned: row digests, then the observable
+    size_t h_cls = 0;
+    bool finishing = false;
+    int32_t status = TL_OK;
+};
+
+// Device bytes of a job: two state buffers, the canonical export, one digest
+// per export row and the observable's counter.
+size_t job_bytes(const tl::Model &m, uint32_t *rows, uint32_t *row_bytes)
+{
+    m.export_layout(rows, row_bytes);
+    return 2 * align_up(m.state_words() * sizeof(uint32_t)) + align_up((size_t)*rows * *row_bytes) +
+           align_up(32 * (size_t)*rows) + kAlign;
+}
+
+struct Tick {
     hipEvent_t ev = nullptr;
-    bool in_flight = false;
+    uint32_t slot = 0;
+    std::vector<Job *> finishing;
 };
 
 }  // namespace
@@ -43,24 +167,36 @@ struct Job {
 struct tl_server {
     size_t budget = 0;
     int32_t max_slots = 0;
-    uint32_t quantum = 250;
-    uint32_t obs_bin = 1;
+    uint32_t quantum = 8;   // sweeps per tick of a weighted job (4x for one-bit jobs)
     int device = 0;
     std::chrono::steady_clock::time_point t0;
     std::mutex mu;
     std::condition_variable cv;       // wakes the scheduler
     std::condition_variable done_cv;  // wakes waiters
-    std::deque<Job> queue;
-    std::vector<Job> active;
+    std::deque<std::unique_ptr<Job>> queue;
     std::map<uint64_t, tl_result> results;
     uint64_t next_ticket = 1;
     size_t in_use = 0, peak = 0;
     uint64_t completed = 0;
-    // written by the scheduler thread only, read by tl_server_stats
+    bool stop = false;
     std::atomic<uint64_t> admitted{0};
     std::atomic<uint32_t> n_active{0}, peak_active{0};
-    bool stop = false;
     std::thread worker;
+
+    // scheduler-thread state
+    hipStream_t stream = nullptr;
+    Arena arena;
+    PinnedPool pinned;
+    std::vector<std::unique_ptr<Job>> active;
+    std::deque<Tick> inflight;
+    std::vector<hipEvent_t> events;
+    static constexpr uint32_t kInflight = 2, kSlots = kInflight + 1;
+    uint32_t next_slot = 0;
+    uint32_t cap_jobs = 0, cap_items = 0;
+    tl::TileJob *d_jobs = nullptr;
+    tl::TileItem *d_items = nullptr;
+    tl::TileJob *h_jobs[kSlots] = {};
+    tl::TileItem *h_items[kSlots] = {};
 
     double now() const
     {
@@ -70,24 +206,25 @@ struct tl_server {
 
 namespace {
 
-void finish(tl_server *sv, Job &j, int32_t status)
+void post(tl_server *sv, Job &j, int32_t status)
 {
     tl_result r{};
     r.ticket = j.ticket;
     r.status = status;
-    r.sweeps = j.done;
+    r.sweeps = status == TL_OK ? j.sweeps : 0;
     r.t_submit = j.t_submit;
     r.t_start = j.t_start;
     r.t_done = sv->now();
-    if (status == TL_OK && j.s) {
-        if (tl_sampler_hash(j.s, r.hash) != TL_OK) r.status = TL_EDEVICE;
-        tl_observables o{};
-        if (r.status == TL_OK && tl_sampler_observables(j.s, &o) == TL_OK) r.scalar_now = o.scalar_now;
+    if (status == TL_OK) {
+        tl::sha256_host(j.h_res, 32 * (size_t)j.rows, r.hash);
+        uint64_t v = 0;
+        memcpy(&v, j.h_res + 32 * (size_t)j.rows, sizeof(v));
+        r.scalar_now = v;
     }
-    if (j.ev) (void)hipEventDestroy(j.ev);
-    if (j.s) tl_sampler_destroy(j.s);
-    j.s = nullptr;
-    j.ev = nullptr;
+    sv->pinned.put(j.h_res, j.h_cls);
+    j.h_res = nullptr;
+    if (j.model) j.model->release();
+    if (j.bytes) sv->arena.free(j.off, j.bytes);
     std::lock_guard<std::mutex> lk(sv->mu);
     sv->in_use -= j.bytes;
     sv->results[j.ticket] = r;
@@ -95,90 +232,281 @@ void finish(tl_server *sv, Job &j, int32_t status)
     sv->done_cv.notify_all();
 }
 
+// Give an admitted job its device memory and initial state.
+int32_t start_job(tl_server *sv, Job &j)
+{
+    uint8_t *base = sv->arena.at(j.off);
+    const size_t sb = align_up(j.model->state_words() * sizeof(uint32_t));
+    uint32_t *a = (uint32_t *)base, *b = (uint32_t *)(base + sb);
+    j.d_export = base + 2 * sb;
+    j.d_digest = j.d_export + align_up((size_t)j.rows * j.row_bytes);
+    j.d_bin = (unsigned long long *)(j.d_digest + align_up(32 * (size_t)j.rows));
+    j.h_res = (uint8_t *)sv->pinned.get(32 * (size_t)j.rows + 8, &j.h_cls);
+    if (!j.h_res) return TL_ENOMEM;
+    j.model->attach(a, b);
+    uint32_t w = 0, h = 0;
+    j.model->cell_box(&w, &h);
+    j.obs_B = std::max(w, h);
+    if (j.model->init(j.dom.init == TL_INIT_MAX, sv->stream) != hipSuccess) return TL_EDEVICE;
+    return TL_OK;
+}
+
+// Result of a finished job: canonical export -> row digests -> host, and the
+// whole-state observable -> host, after its last tick.
+hipError_t enqueue_finish(tl_server *sv, Job &j)
+{
+    hipError_t e = j.model->export_canonical(j.d_export, sv->stream);
+    if (e == hipSuccess) e = tl::hash_rows(j.d_export, j.rows, j.row_bytes, j.d_digest, sv->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(j.h_res, j.d_digest, 32 * (size_t)j.rows, hipMemcpyDeviceToHost, sv->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(j.d_bin, 0, sizeof(unsigned long long), sv->stream);
+    if (e == hipSuccess) e = j.model->observe(j.obs_B, 1, j.d_bin, sv->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(j.h_res + 32 * (size_t)j.rows, j.d_bin, sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, sv->stream);
+    return e;
+}
+
+hipError_t grow(tl_server *sv, uint32_t jobs, uint32_t items)
+{
+    if (jobs <= sv->cap_jobs && items <= sv->cap_items) return hipSuccess;
+    // the staging and device arrays are in use by the ticks in flight
+    hipError_t e = hipStreamSynchronize(sv->stream);
+    if (e != hipSuccess) return e;
+    const uint32_t cj = std::max(jobs, std::max(2 * sv->cap_jobs, 64u));
+    const uint32_t ci = std::max(items, std::max(2 * sv->cap_items, 4096u));
+    if (sv->d_jobs) (void)hipFree(sv->d_jobs);
+    if (sv->d_items) (void)hipFree(sv->d_items);
+    for (uint32_t s = 0; s < tl_server::kSlots; ++s) {
+        if (sv->h_jobs[s]) (void)hipHostFree(sv->h_jobs[s]);
+        if (sv->h_items[s]) (void)hipHostFree(sv->h_items[s]);
+        sv->h_jobs[s] = nullptr;
+        sv->h_items[s] = nullptr;
+    }
+    sv->d_jobs = nullptr;
+    sv->d_items = nullptr;
+    sv->cap_jobs = sv->cap_items = 0;
+    e = hipMalloc(&sv->d_jobs, cj * sizeof(tl::TileJob));
+    if (e == hipSuccess) e = hipMalloc(&sv->d_items, ci * sizeof(tl::TileItem));
+    for (uint32_t s = 0; s < tl_server::kSlots && e == hipSuccess; ++s) {
+        e = hipHostMalloc((void **)&sv->h_jobs[s], cj * sizeof(tl::TileJob), hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&sv->h_items[s], ci * sizeof(tl::TileItem), hipHostMallocDefault);
+    }
+    if (e == hipSuccess) {
+        sv->cap_jobs = cj;
+        sv->cap_items = ci;
+    }
+    return e;
+}
+
+// Retire the oldest tick if it has completed; false if it has not.
+bool retire(tl_server *sv)
+{
+    if (sv->inflight.empty()) return false;
+    Tick &tk = sv->inflight.front();
+    const hipError_t q = hipEventQuery(tk.ev);
+    if (q == hipErrorNotReady) return false;
+    const int32_t st = q == hipSuccess ? TL_OK : TL_EDEVICE;
+    for (Job *jp : tk.finishing) {
+        auto it = std::find_if(sv->active.begin(), sv->active.end(),
+                               [&](const std::unique_ptr<Job> &p) { return p.get() == jp; });
+        if (it == sv->active.end()) continue;
+        post(sv, *jp, jp->status != TL_OK ? jp->status : st);
+        sv->active.erase(it);
+    }
+    sv->events.push_back(tk.ev);
+    sv->inflight.pop_front();
+    if (st != TL_OK) {   // the stream is unusable: fail every admitted job
+        (void)hipStreamSynchronize(sv->stream);
+        while (!sv->inflight.empty()) {
+            sv->events.push_back(sv->inflight.front().ev);
+            sv->inflight.pop_front();
+        }
+        for (auto &j : sv->active) post(sv, *j, TL_EDEVICE);
+        sv->active.clear();
+    }
+    sv->n_active = (uint32_t)sv->active.size();
+    return true;
+}
+
+// Enqueue one tick: every active job with sweeps left advances by its share;
+// jobs that reach their count are finished after it.  False if there was
+// nothing to do.
+bool tick(tl_server *sv)
+{
+    std::vector<Job *> run, fin;
+    for (auto &j : sv->active) {
+        if (j->finishing) continue;
+        if (j->enq < j->sweeps) run.push_back(j.get());
+        else fin.push_back(j.get());
+    }
+    if (run.empty() && fin.empty()) return false;
+    // weighted jobs first: their items take longest
+    std::stable_sort(run.begin(), run.end(), [](const Job *a, const Job *b) { return !a->uniform && b->uniform; });
+    std::vector<tl::TileJob> jobs(run.size());
+    std::vector<tl::TilePlan> plans(run.size());
+    uint32_t n_items = 0, n_height = 0;
+    for (size_t i = 0; i < run.size(); ++i) {
+        Job &j = *run[i];
+        const uint64_t left = j.sweeps - j.enq;
+        const uint64_t want = (uint64_t)sv->quantum * (j.uniform ? 4u : 1u);
+        const uint32_t smax = (uint32_t)std::min<uint64_t>(left, want);
+        if (!j.model->tile_job((uint32_t)j.enq, smax, j.T, j.metro, j.seed, &jobs[i], &plans[i])) {
+            j.status = TL_EINVAL;
+            j.enq = j.sweeps;   // finish (as failed) without running
+            plans[i] = tl::TilePlan{};
+            continue;
+        }
+        n_items += plans[i].tiles();
+        if (j.model->height_family()) n_height += plans[i].tiles();
+    }
+    hipError_t e = grow(sv, (uint32_t)run.size(), n_items);
+    if (e != hipSuccess) {   // finish these jobs, as failed, at the next tick
+        for (Job *j : run) {
+            j->status = TL_EDEVICE;
+            j->enq = j->sweeps;
+        }
+        return true;
+    }
+    const uint32_t slot = sv->next_slot;
+    sv->next_slot = (sv->next_slot + 1) % tl_server::kSlots;
+    tl::TileJob *hj = sv->h_jobs[slot];
+    tl::TileItem *hi = sv->h_items[slot];
+    uint32_t ih = 0, idm = n_height;
+    uint32_t th_h = 0, th_d = 0, lds_h = 0, lds_d = 0;
+    for (size_t i = 0; i < run.size(); ++i) {
+        hj[i] = jobs[i];
+        const tl::TilePlan &p = plans[i];
+        const bool h = run[i]->model->height_family();
+        for (uint32_t t = 0; t < p.tiles(); ++t) hi[h ? ih++ : idm++] = tl::TileItem{(uint32_t)i, t};
+        if (p.tiles() == 0) continue;
+        if (h) {
+            th_h = std::max(th_h, p.threads);
+            lds_h = std::max(lds_h, p.lds);
+        } else {
+            th_d = std::max(th_d, p.threads);
+            lds_d = std::max(lds_d, p.lds);
+        }
+    }
+    if (n_items) {
+        e = hipMemcpyAsync(sv->d_jobs, hj, run.size() * sizeof(tl::TileJob), hipMemcpyHostToDevice, sv->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(sv->d_items, hi, n_items * sizeof(tl::TileItem), hipMemcpyHostToDevice, sv->stream);
+        if (e == hipSuccess) e = tl::height_items(sv->d_jobs, sv->d_items, n_height, th_h, lds_h, sv->stream);
+        if (e == hipSuccess)
+            e = tl::domino_items(sv->d_jobs, sv->d_items + n_height, n_items - n_height, th_d, lds_d, sv->stream);
+    }
+    for (size_t i = 0; i < run.size(); ++i) {
+        Job &j = *run[i];
+        if (plans[i].tiles() == 0) continue;
+        j.model->swap_buffers();
+        j.enq += plans[i].S;
+        if (e != hipSuccess) j.status = TL_EDEVICE;
+    }
+    Tick tk;
+    tk.slot = slot;
+    for (auto &jp : sv->active) {
+        Job &j = *jp;
+        if (j.finishing || j.enq < j.sweeps) continue;
+        if (j.status == TL_OK && enqueue_finish(sv, j) != hipSuccess) j.status = TL_EDEVICE;
+        j.finishing = true;
+        tk.finishing.push_back(&j);
+    }
+    if (sv->events.empty()) {
+        hipEvent_t ev;
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) ev = nullptr;
+        sv->events.push_back(ev);
+    }
+    tk.ev = sv->events.back();
+    sv->events.pop_back();
+    if (!tk.ev || hipEventRecord(tk.ev, sv->stream) != hipSuccess) {
+        // no event: wait for the stream instead
+        (void)hipStreamSynchronize(sv->stream);
+        for (Job *jp : tk.finishing) {
+            auto it = std::find_if(sv->active.begin(), sv->active.end(),
+                                   [&](const std::unique_ptr<Job> &p) { return p.get() == jp; });
+            post(sv, *jp, TL_EDEVICE);
+            sv->active.erase(it);
+        }
+        if (tk.ev) sv->events.push_back(tk.ev);
+        return true;
+    }
+    sv->inflight.push_back(std::move(tk));
+    return true;
+}
+
 void scheduler(tl_server *sv)
 {
     (void)hipSetDevice(sv->device);
     for (;;) {
-        std::vector<Job> admit;
+        std::vector<std::unique_ptr<Job>> admit;
         {
             std::unique_lock<std::mutex> lk(sv->mu);
-            if (sv->active.empty() && sv->queue.empty())
+            if (sv->active.empty() && sv->queue.empty() && sv->inflight.empty())
                 sv->cv.wait_for(lk, std::chrono::milliseconds(2), [&] { return sv->stop || !sv->queue.empty(); });
             if (sv->stop) break;
-            // admission in arrival order, bounded by slots and the memory budget
-            while (!sv->queue.empty() && (int32_t)(sv->active.size() + admit.size()) < sv->max_slots &&
-                   sv->in_use + sv->queue.front().bytes <= sv->budget) {
-                Job j = sv->queue.front();
+            // admission in arrival order, bounded by slots and the arena
+            while (!sv->queue.empty() && (int32_t)(sv->active.size() + admit.size()) < sv->max_slots) {
+                Job &f = *sv->queue.front();
+                if (!sv->arena.alloc(f.bytes, &f.off)) break;
+                sv->in_use += f.bytes;
+                sv->peak = std::max(sv->peak, sv->in_use);
+                admit.push_back(std::move(sv->queue.front()));
                 sv->queue.pop_front();
-                sv->in_use += j.bytes;
-                if (sv->in_use > sv->peak) sv->peak = sv->in_use;
-                admit.push_back(j);
             }
         }
-        for (Job &j : admit) {
-            tl_options o{};
-            o.obs_bin = sv->obs_bin;
-            j.t_start = sv->now();
-            tl_status st = tl_sampler_create(&j.dom, &j.w, j.seed, &o, &j.s);
-            if (st == TL_OK && hipEventCreateWithFlags(&j.ev, hipEventDisableTiming) != hipSuccess) st = TL_EDEVICE;
+        for (auto &j : admit) {
+            j->t_start = sv->now();
+            const int32_t st = start_job(sv, *j);
             if (st != TL_OK) {
-                finish(sv, j, st);
+                post(sv, *j, st);
                 continue;
             }
             sv->admitted += 1;
-            sv->active.push_back(j);
+            sv->active.push_back(std::move(j));
         }
         sv->n_active = (uint32_t)sv->active.size();
         if (sv->n_active > sv->peak_active) sv->peak_active = sv->n_active.load();
-        // advance every chain whose previous quantum has completed
-        bool progressed = false;
-        for (size_t i = 0; i < sv->active.size();) {
-            Job &j = sv->active[i];
-            if (j.in_flight) {
-                const hipError_t q = hipEventQuery(j.ev);
-                if (q == hipErrorNotReady) {
-                    ++i;
-                    continue;
-                }
-                j.in_flight = false;
-                if (q != hipSuccess) {
-                    Job dead = j;
-                    sv->active.erase(sv->active.begin() + i);
-                    finish(sv, dead, TL_EDEVICE);
-                    continue;
-                }
-            }
-            if (j.done >= j.sweeps) {
-                Job fin = j;
-                sv->active.erase(sv->active.begin() + i);
-                finish(sv, fin, TL_OK);
-                progressed = true;
-                continue;
-            }
-            uint64_t q = j.sweeps - j.done;
-            if (q > sv->quantum) q = sv->quantum;
-            tl_status st = tl_sampler_sweep(j.s, q);
-            hipStream_t stream = nullptr;
-            if (st == TL_OK) stream = tl::sampler_stream(j.s);
-            if (st != TL_OK || hipEventRecord(j.ev, stream) != hipSuccess) {
-                Job dead = j;
-                sv->active.erase(sv->active.begin() + i);
-                finish(sv, dead, st != TL_OK ? st : TL_EDEVICE);
-                continue;
-            }
-            j.done += q;
-            j.in_flight = true;
-            progressed = true;
-            ++i;
-        }
-        if (!progressed && !sv->active.empty()) std::this_thread::sleep_for(std::chrono::microseconds(50));
+        bool busy = false;
+        while (retire(sv)) busy = true;
+        if (sv->inflight.size() < tl_server::kInflight && tick(sv)) busy = true;
+        if (!busy && !sv->inflight.empty()) std::this_thread::sleep_for(std::chrono::microseconds(20));
     }
-    // shutdown: drain the device work of the remaining chains and release them
-    for (Job &j : sv->active) {
-        if (j.s) (void)tl_sampler_sync(j.s);
-        finish(sv, j, TL_EBUSY);
+    // shutdown: drain the stream, fail what has not finished
+    (void)hipStreamSynchronize(sv->stream);
+    while (retire(sv)) {
     }
+    for (auto &j : sv->active) post(sv, *j, TL_EBUSY);
     sv->active.clear();
+    std::lock_guard<std::mutex> lk(sv->mu);
+    for (auto &j : sv->queue) {
+        tl_result r{};
+        r.ticket = j->ticket;
+        r.status = TL_EBUSY;
+        r.t_submit = j->t_submit;
+        r.t_done = sv->now();
+        sv->results[j->ticket] = r;
+    }
+    sv->queue.clear();
+    sv->done_cv.notify_all();
+}
+
+void destroy_resources(tl_server *sv)
+{
+    if (sv->stream) (void)hipStreamSynchronize(sv->stream);
+    for (hipEvent_t e : sv->events)
+        if (e) (void)hipEventDestroy(e);
+    sv->events.clear();
+    if (sv->d_jobs) (void)hipFree(sv->d_jobs);
+    if (sv->d_items) (void)hipFree(sv->d_items);
+    for (uint32_t s = 0; s < tl_server::kSlots; ++s) {
+        if (sv->h_jobs[s]) (void)hipHostFree(sv->h_jobs[s]);
+        if (sv->h_items[s]) (void)hipHostFree(sv->h_items[s]);
+    }
+    sv->pinned.release();
+    sv->arena.release();
+    if (sv->stream) (void)hipStreamDestroy(sv->stream);
+    sv->stream = nullptr;
 }
 
 }  // namespace
@@ -189,19 +517,23 @@ tl_status tl_server_create(size_t hbm_budget_bytes, int32_t max_slots, const tl_
 {
     if (!out || hbm_budget_bytes == 0 || max_slots <= 0) return tl::fail(TL_EINVAL, "invalid server arguments");
     *out = nullptr;
-    tl_server *sv = new (std::nothrow) tl_server();
+    std::unique_ptr<tl_server> sv(new (std::nothrow) tl_server());
     if (!sv) return tl::fail(TL_ENOMEM, "host allocation failed");
     sv->budget = hbm_budget_bytes;
     sv->max_slots = max_slots;
     if (opt && opt->sweeps_per_launch) sv->quantum = opt->sweeps_per_launch;
-    if (opt && opt->obs_bin) sv->obs_bin = opt->obs_bin;
     sv->t0 = std::chrono::steady_clock::now();
-    if (hipGetDevice(&sv->device) != hipSuccess) {
-        delete sv;
-        return tl::fail(TL_EDEVICE, "no current device");
+    if (hipGetDevice(&sv->device) != hipSuccess) return tl::fail(TL_EDEVICE, "no current device");
+    hipError_t e = hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = sv->arena.init(hbm_budget_bytes);
+    if (e == hipSuccess) e = grow(sv.get(), 64, 4096);
+    if (e != hipSuccess) {
+        destroy_resources(sv.get());
+        return tl::fail(e == hipErrorOutOfMemory ? TL_ENOMEM : TL_EDEVICE, "server set-up: %s",
+                        hipGetErrorString(e));
     }
-    sv->worker = std::thread(scheduler, sv);
-    *out = sv;
+    sv->worker = std::thread(scheduler, sv.get());
+    *out = sv.release();
     return TL_OK;
 }
 
@@ -212,21 +544,28 @@ tl_status tl_server_submit(tl_server *sv, const tl_domain *dom, const tl_weights
     std::vector<uint32_t> thr;
     tl_status st = tl::make_table(*dom, *w, thr);
     if (st != TL_OK) return st;
-    const size_t bytes = tl::sampler_device_bytes(*dom, sv->obs_bin);
-    if (bytes == 0) return tl::fail(TL_EINVAL, "invalid domain");
-    if (bytes > sv->budget) return tl::fail(TL_EBUDGET, "job needs %zu bytes, budget is %zu", bytes, sv->budget);
+    std::string why;
+    std::unique_ptr<tl::Model> m = tl::make_model(*dom, why);
+    if (!m) return tl::fail(TL_EINVAL, "%s", why.c_str());
     if (n_sweeps > 0xFFFFFFFFull) return tl::fail(TL_EINVAL, "sweep count exceeds 2^32");
+    std::unique_ptr<Job> j(new (std::nothrow) Job());
+    if (!j) return tl::fail(TL_ENOMEM, "host allocation failed");
+    j->bytes = job_bytes(*m, &j->rows, &j->row_bytes);
+    if (align_up(j->bytes) > sv->budget / kAlign * kAlign)
+        return tl::fail(TL_EBUDGET, "job needs %zu bytes, budget is %zu", j->bytes, sv->budget);
+    j->dom = *dom;
+    j->seed = seed;
+    j->sweeps = n_sweeps;
+    j->metro = w->rule == TL_METROPOLIS;
+    std::copy(thr.begin(), thr.end(), j->T.v);
+    j->T.count = (uint32_t)thr.size();
+    j->uniform = j->T.uniform();
+    j->model = std::move(m);
     std::lock_guard<std::mutex> lk(sv->mu);
-    Job j;
-    j.ticket = sv->next_ticket++;
-    j.dom = *dom;
-    j.w = *w;
-    j.seed = seed;
-    j.sweeps = n_sweeps;
-    j.bytes = bytes;
-    j.t_submit = sv->now();
-    sv->queue.push_back(j);
-    *ticket = j.ticket;
+    j->ticket = sv->next_ticket++;
+    j->t_submit = sv->now();
+    *ticket = j->ticket;
+    sv->queue.push_back(std::move(j));
     sv->cv.notify_one();
     return TL_OK;
 }
@@ -278,6 +617,7 @@ tl_status tl_server_destroy(tl_server *sv)
         sv->cv.notify_all();
     }
     if (sv->worker.joinable()) sv->worker.join();
+    destroy_resources(sv);
     delete sv;
     return TL_OK;
 }

@@ -137,3 +137,35 @@ def test_server_budget_and_alone():
     s = tl.Sampler(tl.domain(tl.TL_SIXVERTEX, n=20), sixv_w(tl, (1.0, 1.0, 2.0)), 7)
     s.sweep(50)
     assert r["hash"] == s.hash()
+
+
+@pytest.mark.parametrize("quantum", [3, 8])
+def test_server_multi_tile_jobs_equal_alone(quantum):
+    # jobs large enough to be cut into row tiles with halos (six-vertex N=600,
+    # Aztec order 300, a 200^3 hexagon), small single-tile ones, a job of zero
+    # sweeps and sweep counts that are not multiples of the tick's share, more
+    # jobs than slots: each result equals the same job run alone
+    tl = need_gpu()
+    from paper_1804_07250_amd.serving import Server
+    say("server multi-tile jobs quantum=%d" % quantum)
+    metro = sixv_w(tl, (1.0, 1.0, 2.0), metro=True)
+    jobs = [(tl.domain(tl.TL_SIXVERTEX, n=600), sixv_w(tl, (1.0, 1.0, 2.0)), 5, 37),
+            (tl.domain(tl.TL_DOMINO, n=300), tl.weights(tl.TL_W_UNIFORM), 6, 41),
+            (tl.domain(tl.TL_LOZENGE, a=200, b=200, c=200), tl.weights(tl.TL_W_VOLUME, 1999, 2000), 7, 23),
+            (tl.domain(tl.TL_SIXVERTEX, n=600), sixv_w(tl, (1.0, 1.0, 1.0)), 8, 50),
+            (tl.domain(tl.TL_SIXVERTEX, n=48), metro, 9, 29),
+            (tl.domain(tl.TL_DOMINO, n=150), two_periodic(tl), 10, 19),
+            (tl.domain(tl.TL_SIXVERTEX, n=64), sixv_w(tl, (1.0, 1.0, 2.0)), 11, 0),
+            (tl.domain(tl.TL_LOZENGE, a=30, b=20, c=10), tl.weights(tl.TL_W_UNIFORM), 12, 33)]
+    sv = Server(256 * 1024 * 1024, max_slots=3, opt=tl.options(sweeps_per_launch=quantum))
+    tickets = [sv.submit(d, w, seed, n) for d, w, seed, n in jobs]
+    res = [sv.wait(t, 120.0) for t in tickets]
+    st = sv.stats()
+    sv.destroy()
+    assert st["completed"] == len(jobs) and st["peak_active"] <= 3 and st["bytes_in_use"] == 0
+    for (d, w, seed, n), r in zip(jobs, res):
+        assert r["status"] == tl.TL_OK and r["sweeps"] == n
+        s = tl.Sampler(d, w, seed)
+        s.sweep(n)
+        assert r["hash"] == s.hash(), "job seed %d differs from the same job alone" % seed
+        assert r["scalar_now"] == s.observables()["scalar_now"]

@@ -136,22 +136,49 @@ def test_import_rejects_invalid():
 
 
 def test_full_size_order_2048_one_sweep_sampled():
-    # Order 2048 (the large plain-path workload): after 1500 sweeps from the
-    # brick tiling (a wide disordered band) the GPU state is loaded into the
-    # oracle, both run one more sweep, and the exports must agree bit for bit.
+    # The large plain-path workload at its full size, in the launch
+    # configuration bench.py times (order 2048, seed 7, the full 10^4 sweeps
+    # with density samples every 100 sweeps): the final state is a valid tiling
+    # (host-validated import), and the oracle, started from it, takes sweep
+    # 10^4 exactly as the GPU does.
     tl = need_gpu()
-    say("domino order 2048 one-sweep parity")
+    say("domino order 2048, 10^4 sweeps + one-sweep parity")
     n = 2048
-    s = gpu_sampler(tl, n, seed=7)
-    s.sweep(1500)
+    s = gpu_sampler(tl, n, seed=7, obs_every=100, obs_bin=64)
+    brick = s.export()
+    s.sweep(10000)
     mid = s.export()
+    obs = s.observables()
+    assert obs["samples"] == 100
+    inside = (mid != 255)
+    assert obs["scalar_now"] == int(((mid == 2) | (mid == 3)).sum())
     o = oracle.DominoOracle(n, thr_uniform(), seed=7)
-    o.load(mid)
-    o.t = 1500
+    o.load(mid)   # raises unless mid is a domino tiling of the diamond
+    o.t = 10000
     s.sweep(1)
     o.sweep(1)
     assert (s.export() == o.export()).all()
     assert s.hash() == oracle.canonical_hash(o.export())
+    # the chain has moved away from the brick start, and is still moving: each
+    # flip rewrites the partners of four cells
+    assert (mid != brick)[inside].mean() > 0.01
+    assert (s.export() != mid)[inside].mean() > 0.01
+
+
+def test_maximum_order_valid_tiling():
+    # the largest order the library accepts: a few sweeps, then the export must
+    # pass the host's tiling validation on import
+    tl = need_gpu()
+    n = 16384
+    say("domino order %d" % n)
+    s = gpu_sampler(tl, n, seed=1)
+    s.sweep(20)
+    f = s.export()
+    r = gpu_sampler(tl, n, seed=1, kernel=1)
+    r.import_(f, 20)
+    assert r.hash() == s.hash()
+    with pytest.raises(tl.TlError):
+        gpu_sampler(tl, n + 1, seed=1)
 
 
 @pytest.mark.parametrize("n,tile_rows,spl", [(100, 8, 3), (257, 16, 5), (700, 32, 8), (700, 24, 130), (333, 40, 1)])

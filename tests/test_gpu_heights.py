@@ -93,17 +93,18 @@ def test_lozenge_init_max_observables_hash_import():
 
 
 def test_lozenge_hexagon_1024_one_sweep_sampled():
-    # a = b = c = 1024, q = 1999/2000: after 300 GPU sweeps from the empty box the
-    # state is loaded into the oracle, both run one more sweep, exports agree.
+    # The lozenge workload at full size (a = b = c = 1024, q = 1999/2000, seed
+    # 11, the full 2 x 10^4 sweeps from the empty box): the oracle, started
+    # from the GPU's final state, takes the next sweep exactly as the GPU does.
     tl = need_gpu()
-    say("lozenge 1024^3 one-sweep parity")
+    say("lozenge 1024^3, 2e4 sweeps + one-sweep parity")
     q = Fraction(1999, 2000)
     s = loz_sampler(tl, 1024, 1024, 1024, seed=11, q=q)
-    s.sweep(300)
+    s.sweep(20000)
     mid = s.export()
     o = loz_oracle(1024, 1024, 1024, seed=11, q=q)
     o.load(mid)
-    o.t = 300
+    o.t = 20000
     s.sweep(1)
     o.sweep(1)
     assert (s.export() == o.export()).all()
@@ -163,15 +164,20 @@ def test_sixvertex_init_max_observables_hash_import():
         r.import_(bad, 0)
 
 
-def test_sixvertex_1024_one_sweep_sampled():
+@pytest.mark.parametrize("w2,metro", [((1, 1, 2), False), ((1, 1, 2), True), ((1, 1, 1), False)])
+def test_sixvertex_1024_one_sweep_sampled(w2, metro):
+    # The largest served request at full size (N = 1024, 2000 sweeps from
+    # h_min): the oracle, started from the GPU's final state, takes sweep 2000
+    # exactly as the GPU does.
     tl = need_gpu()
-    say("six-vertex N=1024 one-sweep parity")
-    s = sixv_sampler(tl, 1024, seed=3, w2=(1, 1, 2))
-    s.sweep(500)
+    say("six-vertex N=1024 %s metro=%s, 2000 sweeps + one-sweep parity" % (w2, metro))
+    s = sixv_sampler(tl, 1024, seed=3, w2=w2, metro=metro)
+    s.sweep(2000)
     mid = s.export()
-    o = sixv_oracle(1024, seed=3, w2=(1, 1, 2))
+    o = sixv_oracle(1024, seed=3, w2=w2, metro=metro)
     o.load(mid)
-    o.t = 500
+    o.t = 2000
     s.sweep(1)
     o.sweep(1)
     assert (s.export() == o.export()).all()
+    assert s.hash() == oracle.canonical_hash(o.export())
