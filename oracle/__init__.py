@@ -220,13 +220,15 @@ class _Chain:
 class DominoOracle(_Chain):
     """Aztec diamond of order n; state = the paper's split tilestate arrays."""
 
-    def __init__(self, n, thr, metropolis=False, seed=0, obs_every=0, bin_=1):
+    def __init__(self, n, thr, metropolis=False, seed=0, obs_every=0, bin_=1, init="min"):
         self.n = n
         L = lib()
         m = L.or_domino_array_len(n)
         self.Tb = np.zeros(m, dtype=np.uint8)
         self.Tw = np.zeros(m, dtype=np.uint8)
         L.or_domino_brick(n, _p(self.Tb, ctypes.c_uint8), _p(self.Tw, ctypes.c_uint8))
+        if init == "max":
+            self.load(domino_vertical_brick(self.export()))
         self.thr = np.asarray(thr, dtype=np.uint32)
         self.metropolis = metropolis
         self.seed = seed
@@ -370,6 +372,47 @@ class SixVertexOracle(_Chain):
 
     def sites(self):
         return [(I, J) for J in range(1, self.N) for I in range(1, self.N)]
+
+
+def domino_vertical_brick(horizontal):
+    """The all-vertical tiling of an Aztec diamond from the all-horizontal one
+    (canonical export, row 0 southmost): the mirror image in the diagonal X = Y,
+    under which a partner to the east (+X) becomes one to the north (+Y),
+    west -> south, north -> east and south -> west.  The two brick tilings are
+    the extremal tilings of Section 1.1.4: every rotation available from either
+    one moves the height function the same way."""
+    remap = np.array([2, 3, 0, 1] + [255] * 252, dtype=np.uint8)
+    return remap[np.ascontiguousarray(horizontal.T)]
+
+
+def cftp_segments(R):
+    """Sweeps from time -2^R to time 0 as (first sweep counter, count), in
+    time order.  The draws of each time step are fixed once for all rounds
+    (the reading of the seed list of the CFTP host function in Section 2.2):
+    time tau in [-2^r, -2^(r-1)), r >= 1, uses sweep counter tau + 3 * 2^(r-1),
+    so that segment r is the counters [2^(r-1), 2^r) in order, and time -1
+    uses counter 0."""
+    segs = [(1 << (r - 1), 1 << (r - 1)) for r in range(R, 0, -1)]
+    segs.append((0, 1))
+    return segs
+
+
+def cftp(make, max_log2=30, first_log2=1):
+    """Coupling from the past (Section 1.1.4; the CFTP host function of
+    Section 2.2).  make(init) returns a fresh chain started from the maximal
+    ("max") or minimal ("min") state.  For R = first_log2, first_log2 + 1, ...
+    both chains run the same sweeps from time -2^R to 0; the first R at which
+    they end equal gives the exact sample.  Returns (R, final export)."""
+    for R in range(first_log2, max_log2 + 1):
+        top, bottom = make("max"), make("min")
+        for t0, count in cftp_segments(R):
+            for ch in (top, bottom):
+                ch.t = t0
+                ch.sweep(count)
+        a, b = top.export(), bottom.export()
+        if np.array_equal(a, b):
+            return R, b
+    raise RuntimeError("no coalescence within 2^%d sweeps" % max_log2)
 
 
 def bin_density(bin_sum, samples, in_domain, bin_):
