@@ -293,8 +293,9 @@ __global__ void __launch_bounds__(256) domino_other_step(uint32_t *planes, size_
 // loaded into LDS, advanced nsweeps sweeps there, and the interior written to
 // `out`.  Halo cells repeat their neighbours' keyed draws, so the interior
 // matches the sweep of the whole state; halo rows go stale one per sweep from
-// each side, so sweep s computes only rows [s, LR - s).  Thread tid handles
-// group tid % LG of rows tid / LG, tid / LG + RP, ... (RP rows per pass).
+// each side, so sweep s computes only rows [s, LR - s).  The block has a
+// thread per (row, group) task (blockDim >= LR * LG, as every launch plan
+// gives): thread tid handles group tid % LG of row s + tid / LG.
 template <int MODE>
 __device__ __forceinline__ void domino_tile(uint32_t *lds, const uint32_t *__restrict__ in,
                                             uint32_t *__restrict__ out, size_t PS, uint32_t RS, uint32_t ng,
@@ -319,25 +320,23 @@ __device__ __forceinline__ void domino_tile(uint32_t *lds, const uint32_t *__res
     }
     __syncthreads();
 
-    const uint32_t RP = nt / LG, r0 = tid / LG, lg = tid % LG;
+    const uint32_t r0 = tid / LG, lg = tid % LG;
     const int gg = G0 + (int)lg;
-    const bool lane = r0 < RP && gg >= 0 && gg < (int)ng;
+    const bool lane = gg >= 0 && gg < (int)ng;
     for (uint32_t s = 0; s < nsweeps; ++s) {
         const uint32_t t = t0 + s;
         const uint32_t base = HR ? s : 0u, end = HR ? LR - s : LR;
         for (uint32_t c = 0; c < 2; ++c) {
-            if (lane) {
-                for (uint32_t lr = base + r0; lr < end; lr += RP) {
-                    const int gr = R0 + (int)lr;
-                    if (gr < 0 || gr >= (int)n) continue;
-                    uint32_t *pN = lds + lr * LRS + 4 * lg;
-                    if (c == omega)
-                        owner_group<MODE>(pN, pN + LPS, pN + 2 * LPS, pN + 3 * LPS, (uint32_t)gr, (uint32_t)gg, c,
-                                          t, Tall, key0, key1);
-                    else if (lr + 1 < LR)
-                        other_group<MODE>(pN, pN + 2 * LPS, pN + LPS + LRS, pN + 3 * LPS + LRS, (uint32_t)gr,
-                                          (uint32_t)gg, c, t, Tall, key0, key1);
-                }
+            const uint32_t lr = base + r0;
+            const int gr = R0 + (int)lr;
+            if (lane && lr < end && gr >= 0 && gr < (int)n) {
+                uint32_t *pN = lds + lr * LRS + 4 * lg;
+                if (c == omega)
+                    owner_group<MODE>(pN, pN + LPS, pN + 2 * LPS, pN + 3 * LPS, (uint32_t)gr, (uint32_t)gg, c, t,
+                                      Tall, key0, key1);
+                else if (lr + 1 < LR)
+                    other_group<MODE>(pN, pN + 2 * LPS, pN + LPS + LRS, pN + 3 * LPS + LRS, (uint32_t)gr,
+                                      (uint32_t)gg, c, t, Tall, key0, key1);
             }
             __syncthreads();
         }
@@ -518,6 +517,32 @@ __global__ void __launch_bounds__(256) domino_observe_kernel(const uint32_t *pl,
     if (r < (uint32_t)n) {
         for (int p = 0; p < 2; ++p) {
             uint32_t m = pl[(size_t)p * PS + (size_t)r * RS + w];
+            if (B >= 32u) {
+                // site k = 32w + b sits at X = X0 - b, Y = Y0 + b: with bins of
+                // at least 32 faces, the word's bits fall into at most three
+                // runs per face column (X - 1 and X), each one bin
+                if (!m) continue;
+                const int X0 = (int)r - (int)(w * 32u) + n, Y0 = (int)r + (int)(w * 32u) + 1 - p;
+                const uint32_t yb0 = (uint32_t)Y0 / B, ybrk = B - (uint32_t)Y0 % B;
+                for (int d = 1; d >= 0; --d) {
+                    const uint32_t c0 = (uint32_t)(X0 - d), xb0 = c0 / B, xbrk = c0 % B + 1u;
+                    const uint32_t s1 = ybrk < xbrk ? ybrk : xbrk, s2 = ybrk < xbrk ? xbrk : ybrk;
+                    const uint32_t cuts[4] = {0u, s1 < 32u ? s1 : 32u, s2 < 32u ? s2 : 32u, 32u};
+                    for (int q = 0; q < 3; ++q) {
+                        const uint32_t lo = cuts[q], hi = cuts[q + 1];
+                        if (lo >= hi) continue;
+                        const uint32_t mask = (hi >= 32u ? ~0u : ((1u << hi) - 1u)) & ~((1u << lo) - 1u);
+                        const uint32_t cnt = (uint32_t)__popc(m & mask);
+                        if (!cnt) continue;
+                        const uint32_t i = (yb0 + (lo >= ybrk ? 1u : 0u)) * bins_x + xb0 - (lo >= xbrk ? 1u : 0u);
+                        if (local)
+                            atomicAdd(&lbin[i], cnt);
+                        else
+                            atomicAdd(&bins[i], (unsigned long long)cnt);
+                    }
+                }
+                continue;
+            }
             while (m) {
                 const int b = __builtin_ctz(m);
                 m &= m - 1u;
@@ -584,7 +609,7 @@ DominoTile domino_auto_tile(int n)
     }
     t.TR = 32;
     t.TG = ng < 4 ? ng : 4;
-    t.S = 16;   // measured best on MI355X for order 2048 (tile 32 rows x 4 groups)
+    t.S = 25;   // measured best on MI355X for order 2048 (tile 32 rows x 4 groups)
     return t;
 }
 

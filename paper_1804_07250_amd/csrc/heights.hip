@@ -307,9 +307,10 @@ __global__ void __launch_bounds__(256) height_step_kernel(uint32_t *planes, size
 // LRS = 4*(LG+2) (the pad groups hold the neighbouring groups, or zero).  Local
 // row lr is global row R0 + lr, local group lg is global group G0 + lg.  With a
 // row halo, the rows still valid before sweep s are [rps*s, LR - rps*s) (rps
-// rows go stale per sweep on each side), and only those are computed.  Thread
-// tid handles group tid % LG of rows tid / LG, tid / LG + RP, ... (RP rows
-// per pass).
+// rows go stale per sweep on each side), and only those are computed.  The
+// block has a thread per (row, group) task (blockDim >= LR * LG, as every
+// launch plan gives): thread tid handles group tid % LG of row
+// rps*s + tid / LG.
 template <int MODE>
 __device__ __forceinline__ void height_tile(uint32_t *lds, const uint32_t *__restrict__ in,
                                             uint32_t *__restrict__ out, size_t PS, uint32_t RS, uint32_t ng,
@@ -335,22 +336,19 @@ __device__ __forceinline__ void height_tile(uint32_t *lds, const uint32_t *__res
     }
     __syncthreads();
 
-    const uint32_t RP = nt / LG, r0 = tid / LG, lg = tid % LG;
+    const uint32_t r0 = tid / LG, lg = tid % LG;
     const int gg = G0 + (int)lg;
-    const bool lane = r0 < RP && gg >= 0 && gg < (int)ng;
+    const bool lane = gg >= 0 && gg < (int)ng;
     const uint32_t K_colours = geo.model == TL_LOZENGE ? 3u : 4u;
     const uint32_t rps = geo.model == TL_LOZENGE ? 3u : 2u;
     for (uint32_t s = 0; s < nsweeps; ++s) {
         const uint32_t t = t0 + s;
         const uint32_t base = HR ? rps * s : 0u, end = HR ? LR - rps * s : LR;
         for (uint32_t c = 0; c < K_colours; ++c) {
-            if (lane) {
-                for (uint32_t lr = base + r0; lr < end; lr += RP) {
-                    const int gr = R0 + (int)lr;
-                    if (lr >= 1 && lr + 1 < LR && site_row(geo, gr, rows))
-                        height_group<MODE>(lds, LPS, LRS, lr, lg, geo, gr, (uint32_t)gg, c, t, T, k0, k1);
-                }
-            }
+            const uint32_t lr = base + r0;
+            const int gr = R0 + (int)lr;
+            if (lane && lr < end && lr >= 1 && lr + 1 < LR && site_row(geo, gr, rows))
+                height_group<MODE>(lds, LPS, LRS, lr, lg, geo, gr, (uint32_t)gg, c, t, T, k0, k1);
             __syncthreads();
         }
     }

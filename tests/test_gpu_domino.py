@@ -98,6 +98,19 @@ def test_binned_density_and_ragged_bins():
     assert (s2.observables()["bin_sum"].reshape(-1) == o2.bin_sum).all()
 
 
+@pytest.mark.parametrize("n,B", [(300, 32), (300, 64), (130, 48), (257, 100), (70, 200)])
+def test_large_bins(n, B):
+    # bins of 32 faces or more (runs of an owner word counted at once)
+    tl = need_gpu()
+    s = gpu_sampler(tl, n, seed=13, obs_every=2, obs_bin=B)
+    o = oracle.DominoOracle(n, thr_uniform(), seed=13, obs_every=2, bin_=B)
+    s.sweep(9)
+    o.sweep(9)
+    obs = s.observables()
+    assert obs["samples"] == int(o.samples[0]) == 4
+    assert (obs["bin_sum"].reshape(-1) == o.bin_sum).all()
+
+
 def test_init_max_and_import_resume():
     tl = need_gpu()
     n = 37
