@@ -170,6 +170,32 @@ tl_status tl_sampler_info(const tl_sampler *s, uint64_t *sites, uint32_t *colour
  * writes up to cap entries, returns the count in *count. */
 tl_status tl_sampler_thresholds(const tl_sampler *s, uint32_t *out, uint32_t cap, uint32_t *count);
 
+/* ------------------------------------------------------- coupling from the past
+ * Exact sampling (Section 1.1.4; the CFTP host function of Section 2.2): two
+ * chains, from the maximal and from the minimal state of the domain (domino:
+ * all-vertical and all-horizontal brick; lozenge: full and empty box;
+ * six-vertex: h_max and h_min), run the same sweeps from time -2^R to time 0
+ * for R = 1, 2, ..., max_log2 until they end equal (compared on the device).
+ * The draws of each time step stay fixed across rounds: time tau in
+ * [-2^r, -2^(r-1)) uses sweep counter tau + 3 * 2^(r-1), time -1 counter 0, so
+ * round R runs the counters [2^(R-1), 2^R), [2^(R-2), 2^(R-1)), ..., [1, 2),
+ * [0, 1) in that order, keyed by the sampler's seed.
+ * The moves must preserve the height order: heat-bath rule only, and for the
+ * six-vertex model a^2 <= c^2 and b^2 <= c^2 (Section 1.2.4); otherwise
+ * TL_EINVAL.  On success the sampler holds the sample, its sweep counter is
+ * 2^R (later sweeps use fresh draws), accumulated samples are cleared, and
+ * *out (nullable) reports R, the 2^R sweeps of the final round and the sweeps
+ * run over all rounds and both chains.  If the chains have not met at
+ * max_log2 (1..31), TL_EBUSY; the sampler then holds the minimal chain at time
+ * 0 of the last round.  Allocates a second state for the maximal chain while
+ * it runs; synchronous. */
+typedef struct {
+    uint32_t log2_sweeps;   /* R of the round whose chains met */
+    uint64_t sweeps;        /* 2^R */
+    uint64_t total_sweeps;  /* sweeps over all rounds, both chains */
+} tl_cftp_info;
+tl_status tl_sampler_cftp(tl_sampler *s, uint32_t max_log2, tl_cftp_info *out);
+
 /* ------------------------------------------------------------------ batched
  * Many independent domino chains on Aztec diamonds of uneven orders (1..512),
  * advanced together: each tl_batch_sweep call is one persistent kernel launch

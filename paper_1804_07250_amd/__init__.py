@@ -58,6 +58,10 @@ class tl_observables(ctypes.Structure):
                 ("bin_density", ctypes.POINTER(ctypes.c_double)), ("bin_capacity", ctypes.c_size_t)]
 
 
+class tl_cftp_info(ctypes.Structure):
+    _fields_ = [("log2_sweeps", ctypes.c_uint32), ("sweeps", ctypes.c_uint64), ("total_sweeps", ctypes.c_uint64)]
+
+
 _lib = None
 
 
@@ -83,6 +87,7 @@ def lib():
         L.tl_sampler_destroy.argtypes = [vp]
         L.tl_sampler_info.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(u32)]
         L.tl_sampler_reset.argtypes = [vp, u64]
+        L.tl_sampler_cftp.argtypes = [vp, u32, ctypes.POINTER(tl_cftp_info)]
         L.tl_sampler_set_timing.argtypes = [vp, i32]
         L.tl_sampler_kernel_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(u64),
                                              ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_double)]
@@ -96,7 +101,7 @@ def lib():
         for name in ("tl_sampler_create", "tl_sampler_sweep", "tl_sampler_sync", "tl_sampler_observables",
                      "tl_sampler_export_size", "tl_sampler_export", "tl_sampler_hash", "tl_sampler_import",
                      "tl_sampler_destroy", "tl_sampler_info", "tl_sampler_thresholds", "tl_sampler_reset",
-                     "tl_sampler_set_timing", "tl_sampler_kernel_time"):
+                     "tl_sampler_set_timing", "tl_sampler_kernel_time", "tl_sampler_cftp"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -157,6 +162,14 @@ class Sampler:
 
     def reset(self, seed: int):
         _check(lib().tl_sampler_reset(self._h, seed))
+
+    def cftp(self, max_log2: int = 24):
+        """Exact sample by coupling from the past (raises TlError TL_EBUSY if the
+        chains have not met within 2^max_log2 sweeps).  Returns
+        {"log2_sweeps", "sweeps", "total_sweeps"}."""
+        info = tl_cftp_info()
+        _check(lib().tl_sampler_cftp(self._h, int(max_log2), ctypes.byref(info)))
+        return {"log2_sweeps": info.log2_sweeps, "sweeps": info.sweeps, "total_sweeps": info.total_sweeps}
 
     def set_timing(self, period: int):
         """Time every `period`-th sweep launch with dispatch events (0 = off)."""

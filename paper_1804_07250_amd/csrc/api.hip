@@ -149,6 +149,24 @@ tl_status make_thresholds(const tl_domain &d, const tl_weights &w, std::vector<u
     return TL_OK;
 }
 
+tl::Thr table_of(const tl_sampler *s)
+{
+    tl::Thr T{};
+    for (size_t i = 0; i < s->thr.size() && i < 32; ++i) T.v[i] = s->thr[i];
+    T.count = (uint32_t)(s->thr.size() < 32 ? s->thr.size() : 32);
+    return T;
+}
+
+// Sets *flag when the word arrays a and b differ anywhere.
+__global__ void __launch_bounds__(256) words_differ_kernel(const uint32_t *a, const uint32_t *b, size_t n,
+                                                           uint32_t *flag)
+{
+    uint32_t acc = 0u;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) acc |= a[i] ^ b[i];
+    if (acc) atomicOr(flag, 1u);
+}
+
 tl_status enqueue_sample(tl_sampler *s)
 {
     TL_HIP(s->model->observe(s->B, s->bins_x, s->bin_sum, s->stream));
@@ -248,9 +266,7 @@ tl_status tl_sampler_sweep(tl_sampler *s, uint64_t n)
 {
     if (!s) return fail(TL_EINVAL, "null sampler");
     if (s->t + n > 0xFFFFFFFFull) return fail(TL_EINVAL, "sweep counter would exceed 2^32");
-    tl::Thr T{};
-    for (size_t i = 0; i < s->thr.size() && i < 32; ++i) T.v[i] = s->thr[i];
-    T.count = (uint32_t)(s->thr.size() < 32 ? s->thr.size() : 32);
+    const tl::Thr T = table_of(s);
     const bool metro = s->w.rule == TL_METROPOLIS;
     const uint32_t every = s->opt.obs_every;
     uint64_t done = 0;
@@ -402,6 +418,64 @@ tl_status tl_sampler_reset(tl_sampler *s, uint64_t seed)
     const size_t nb = (size_t)s->bins_x * s->bins_y;
     TL_HIP(hipMemsetAsync(s->bin_sum, 0, nb * sizeof(unsigned long long), s->stream));
     TL_HIP(s->model->init(s->dom.init == TL_INIT_MAX, s->stream));
+    return TL_OK;
+}
+
+tl_status tl_sampler_cftp(tl_sampler *s, uint32_t max_log2, tl_cftp_info *out)
+{
+    if (!s) return fail(TL_EINVAL, "null sampler");
+    if (max_log2 < 1 || max_log2 > 31) return fail(TL_EINVAL, "max_log2 must be in 1..31");
+    if (s->w.rule != TL_HEATBATH) return fail(TL_EINVAL, "coupling from the past needs the heat-bath rule");
+    if (s->dom.model == TL_SIXVERTEX && s->w.kind == TL_W_SIXVERTEX &&
+        (s->w.w[0] > s->w.w[2] || s->w.w[1] > s->w.w[2]))
+        return fail(TL_EINVAL, "coupling from the past needs a <= c and b <= c");
+    std::string why;
+    std::unique_ptr<tl::Model> top = tl::make_model(s->dom, why);
+    if (!top) return fail(TL_EINVAL, "%s", why.c_str());
+    hipError_t e = top->allocate();
+    uint32_t *flag = nullptr;
+    if (e == hipSuccess) e = hipMalloc(&flag, sizeof(uint32_t));
+    const tl::Thr T = table_of(s);
+    const size_t words = s->model->state_words();
+    uint64_t total = 0;
+    uint32_t R = 1, differ = 1;
+    for (; e == hipSuccess && R <= max_log2; ++R) {
+        e = s->model->init(false, s->stream);
+        if (e == hipSuccess) e = top->init(true, s->stream);
+        for (int r = (int)R; r >= 0 && e == hipSuccess; --r) {
+            const uint32_t t0 = r ? 1u << (r - 1) : 0u, count = r ? 1u << (r - 1) : 1u;
+            e = s->model->sweeps(t0, count, T, false, s->seed, s->opt, s->stream);
+            if (e == hipSuccess) e = top->sweeps(t0, count, T, false, s->seed, s->opt, s->stream);
+        }
+        total += 2ull << R;
+        if (e == hipSuccess) e = hipMemsetAsync(flag, 0, sizeof(uint32_t), s->stream);
+        if (e == hipSuccess) {
+            size_t blocks = (words + 255) / 256;
+            if (blocks > 2048) blocks = 2048;
+            hipLaunchKernelGGL(words_differ_kernel, dim3((uint32_t)blocks), dim3(256), 0, s->stream,
+                               s->model->state(), top->state(), words, flag);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipMemcpyAsync(&differ, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        if (e == hipSuccess && !differ) break;
+    }
+    top->release();
+    if (flag) (void)hipFree(flag);
+    if (e != hipSuccess)
+        return fail(e == hipErrorOutOfMemory ? TL_ENOMEM : TL_EDEVICE, "coupling from the past: %s",
+                    hipGetErrorString(e));
+    const uint32_t Rend = differ ? max_log2 : R;
+    s->t = 1ull << Rend;
+    s->samples = 0;
+    const size_t nb = (size_t)s->bins_x * s->bins_y;
+    TL_HIP(hipMemsetAsync(s->bin_sum, 0, nb * sizeof(unsigned long long), s->stream));
+    if (out) {
+        out->log2_sweeps = Rend;
+        out->sweeps = 1ull << Rend;
+        out->total_sweeps = total;
+    }
+    if (differ) return fail(TL_EBUSY, "the chains have not met within 2^%u sweeps", max_log2);
     return TL_OK;
 }
 

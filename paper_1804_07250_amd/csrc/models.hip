@@ -55,6 +55,7 @@ public:
     }
     void swap_buffers() override { std::swap(d_.planes, d_.spare); }
     bool height_family() const override { return false; }
+    const uint32_t *state() const override { return d_.planes; }
     hipError_t init(bool init_max, hipStream_t s) override { return domino_init(d_, init_max ? 1 : 0, s); }
 
     hipError_t sweeps(uint32_t t0, uint32_t n, const Thr &T, bool metro, uint64_t seed, const tl_options &opt,
@@ -209,6 +210,7 @@ public:
     }
     void swap_buffers() override { std::swap(d_.planes, d_.spare); }
     bool height_family() const override { return true; }
+    const uint32_t *state() const override { return d_.planes; }
     hipError_t init(bool init_max, hipStream_t s) override { return height_init(d_, init_max ? 1 : 0, s); }
 
     // Six-vertex kernels take one threshold per weight class (sA, sB) (and

@@ -44,6 +44,8 @@ public:
                           TilePlan *p) const = 0;
     virtual void swap_buffers() = 0;
     virtual bool height_family() const = 0;
+    // Current state buffer (state_words() words; equal buffers <=> equal states).
+    virtual const uint32_t *state() const = 0;
     Timing timing;
 };
 
