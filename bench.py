@@ -67,6 +67,10 @@ def parse():
     p.add_argument("--served-budget-mib", type=int, default=1024)
     p.add_argument("--served-slots", type=int, default=64)
     p.add_argument("--served-quantum", type=int, default=8, help="sweeps per tick of a weighted request")
+    p.add_argument("--no-cftp", action="store_true")
+    p.add_argument("--cftp-n", type=int, default=128, help="six-vertex DWBC size for coupling from the past")
+    p.add_argument("--cftp-aztec", type=int, default=64, help="Aztec order for coupling from the past")
+    p.add_argument("--cftp-samples", type=int, default=2)
     return p.parse_args()
 
 
@@ -142,6 +146,33 @@ def run_served(tl, args):
                         "%d slots, ticks of %d sweeps (x4 for one-bit jobs)"
                         % (args.served_sweeps, args.served_rate, len(res), args.served_budget_mib, args.served_slots,
                            args.served_quantum)}
+
+
+def run_cftp(tl, args):
+    """Exact samples by coupling from the past: the six-vertex DWBC square with
+    (a,b,c) = (1,1,1) and the uniform Aztec diamond, seeds 0..k-1."""
+    out = {}
+    cases = [("sixv", tl.domain(tl.TL_SIXVERTEX, n=args.cftp_n), tl.weights(tl.TL_W_UNIFORM),
+              (args.cftp_n - 1) ** 2),
+             ("aztec", tl.domain(tl.TL_DOMINO, n=args.cftp_aztec), tl.weights(tl.TL_W_UNIFORM),
+              2 * args.cftp_aztec ** 2 - 2 * args.cftp_aztec + 1)]
+    for name, dom, w, sites in cases:
+        secs, logs, total = [], [], 0
+        for seed in range(args.cftp_samples):
+            s = tl.Sampler(dom, w, seed)
+            s.sync()
+            t0 = time.perf_counter()
+            info = s.cftp(30)
+            secs.append(time.perf_counter() - t0)
+            logs.append(info["log2_sweeps"])
+            total += info["total_sweeps"]
+            s.destroy()
+        out[name] = {"seconds_per_sample": round(sum(secs) / len(secs), 4), "log2_sweeps": logs,
+                     "site_updates_per_s": sites * total / sum(secs)}
+    out["workload"] = ("coupling from the past: six-vertex DWBC %dx%d with (a,b,c) = (1,1,1) and the uniform "
+                       "Aztec diamond of order %d, seeds 0..%d, doubling from 2 sweeps"
+                       % (args.cftp_n, args.cftp_n, args.cftp_aztec, args.cftp_samples - 1))
+    return out
 
 
 def make_sampler(tl, wl, args):
@@ -306,6 +337,9 @@ def main():
     if not args.no_served:
         out["served"] = run_served(tl, args)
         print("served done", file=sys.stderr, flush=True)
+    if not args.no_cftp:
+        out["cftp"] = run_cftp(tl, args)
+        print("cftp done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(out))
