@@ -53,7 +53,13 @@ typedef enum {
     TL_W_UNIFORM = 0,       /* all weights 1 (Section 1.1.1, last sentence) */
     TL_W_TWO_PERIODIC = 1,  /* domino edge weights: w[0] = a, w[1] = b (see below) */
     TL_W_VOLUME = 2,        /* lozenge volume weight q^volume: q = w[0], or w[0]/w[1] if w[1] > 0 */
-    TL_W_SIXVERTEX = 3      /* six-vertex vertex weights, squared: w[0] = a^2, w[1] = b^2, w[2] = c^2 */
+    TL_W_SIXVERTEX = 3,     /* six-vertex vertex weights, squared: w[0] = a^2, w[1] = b^2, w[2] = c^2 */
+    TL_W_VOLUME_BW = 4,     /* domino volume weights prod_v q_v^h(v): q = w[0]/w[1] on black vertices
+                             * (x+y even), w[2]/w[3] on white ones (a zero denominator reads as 1) */
+    TL_W_SIXVERTEX6 = 5     /* six-vertex weights of the six vertex types: w = a1, a2, b1, b2, c1, c2
+                             * (a1: no path edge, a2: all four, b1: left+right, b2: bottom+top,
+                             * c1: bottom+left, c2: right+top); with the boundary fixed the chain
+                             * depends on them through a1 a2, b1 b2, c1 c2 only */
 } tl_weight_kind;
 
 /* Domain (Section 1.1 "domain"; Section 1.2):
@@ -71,7 +77,10 @@ typedef struct {
 
 /* Weights (Section 1.1.1 edge and volume weights; Section 1.2 vertex weights).
  * Two-periodic: a crossed edge weighs a when its even endpoint (x+y even in
- * centred coordinates) has x even, b otherwise.  Six-vertex: corners NE/SW of a
+ * centred coordinates) has x even, b otherwise.  Domino volume weights: a
+ * rotation changes the height at its vertex by 4, up (vertical pair) raising
+ * it at black vertices and lowering it at white ones, so P(vertical) is
+ * q^4/(1+q^4) at a black site and 1/(1+q^4) at a white one.  Six-vertex: corners NE/SW of a
  * flipped face carry a, NW/SE carry b, type-c corners carry c; a flip changes
  * four corners, a and b each at two of them, so the chain depends on a^2, b^2
  * and c^2 only, which are passed exactly (c = sqrt(2) as c^2 = 2).  Acceptance uses
@@ -181,7 +190,8 @@ tl_status tl_sampler_thresholds(const tl_sampler *s, uint32_t *out, uint32_t cap
  * round R runs the counters [2^(R-1), 2^R), [2^(R-2), 2^(R-1)), ..., [1, 2),
  * [0, 1) in that order, keyed by the sampler's seed.
  * The moves must preserve the height order: heat-bath rule only, and for the
- * six-vertex model a^2 <= c^2 and b^2 <= c^2 (Section 1.2.4); otherwise
+ * six-vertex model an up threshold that never decreases when a diagonal face
+ * is raised (a <= c and b <= c for weights a, b, c, Section 1.2.4); otherwise
  * TL_EINVAL.  On success the sampler holds the sample, its sweep counter is
  * 2^R (later sweeps use fresh draws), accumulated samples are cleared, and
  * *out (nullable) reports R, the 2^R sweeps of the final round and the sweeps

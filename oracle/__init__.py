@@ -158,6 +158,13 @@ def domino_ratios(kind="uniform", a=1, b=1):
     if kind == "uniform":
         return [Fraction(1)] * 4
     a, b = Fraction(a), Fraction(b)
+    if kind == "volume":
+        # Volume weights prod_v q_v^h(v) (Section 1.1.1), q = a at black (x+y
+        # even) vertices and b at white ones.  A rotation moves the height of
+        # its vertex by 4; the vertical pair is the higher state at black
+        # vertices and the lower one at white vertices, so R = a^4 at black
+        # sites and b^-4 at white sites.
+        return [a ** 4, a ** 4, b ** -4, b ** -4]
     return [Fraction(1), Fraction(1), (b * b) / (a * a), (a * a) / (b * b)]
 
 
@@ -187,6 +194,44 @@ def sixv_ratios(a, b, c_squared):
         e = nhigh - 2
         R *= c2 ** e
         out.append(R)
+    return out
+
+
+def sixv_vertex_type(hSW, hSE, hNW, hNE):
+    """Type of the vertex surrounded by four faces of these heights (Section
+    1.2, Figure "sixvertexh": a path crosses an edge where the height rises by
+    1 towards +x or +y).  a1: no path edge, a2: all four, b1: left and right,
+    b2: bottom and top, c1: bottom and left, c2: right and top."""
+    bottom, top = hSE - hSW == 1, hNE - hNW == 1
+    left, right = hNW - hSW == 1, hNE - hSE == 1
+    return {(False, False, False, False): "a1", (True, True, True, True): "a2",
+            (True, True, False, False): "b1", (False, False, True, True): "b2",
+            (True, False, True, False): "c1", (False, True, False, True): "c2"}[(left, right, bottom, top)]
+
+
+def sixv_ratios6(a1, a2, b1, b2, c1, c2):
+    """W_up / W_down for each mask of diagonal faces at height m+1 (NE=1, NW=2,
+    SW=4, SE=8) with the six vertex weights of Section 1.2: the flipped face at
+    m-1 or m+1, its four edge neighbours at m, the diagonal faces at m+1 or
+    m-1 by the mask; the weight of each state is the product over the four
+    corners of the flipped face of the weight of the corner's type."""
+    w = {"a1": Fraction(a1), "a2": Fraction(a2), "b1": Fraction(b1), "b2": Fraction(b2),
+         "c1": Fraction(c1), "c2": Fraction(c2)}
+    out = []
+    for mask in range(16):
+        m = 10
+
+        def weight(f):
+            diag = {(1, 1): 0, (-1, 1): 1, (-1, -1): 2, (1, -1): 3}
+            h = {(0, 0): f, (1, 0): m, (-1, 0): m, (0, 1): m, (0, -1): m}
+            for pos, bit in diag.items():
+                h[pos] = m + 1 if mask >> bit & 1 else m - 1
+            W = Fraction(1)
+            for cx, cy in ((0, 0), (-1, 0), (-1, -1), (0, -1)):   # corners NE, NW, SW, SE
+                W *= w[sixv_vertex_type(h[(cx, cy)], h[(cx + 1, cy)], h[(cx, cy + 1)], h[(cx + 1, cy + 1)])]
+            return W
+
+        out.append(weight(m + 1) / weight(m - 1))
     return out
 
 

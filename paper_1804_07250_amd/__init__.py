@@ -21,7 +21,7 @@ TL_DOMINO, TL_LOZENGE, TL_SIXVERTEX = 0, 1, 2
 TL_AZTEC, TL_HEXAGON, TL_DWBC_SQUARE = 0, 1, 2
 TL_INIT_MIN, TL_INIT_MAX = 0, 1
 TL_HEATBATH, TL_METROPOLIS = 0, 1
-TL_W_UNIFORM, TL_W_TWO_PERIODIC, TL_W_VOLUME, TL_W_SIXVERTEX = 0, 1, 2, 3
+TL_W_UNIFORM, TL_W_TWO_PERIODIC, TL_W_VOLUME, TL_W_SIXVERTEX, TL_W_VOLUME_BW, TL_W_SIXVERTEX6 = 0, 1, 2, 3, 4, 5
 
 
 class TlError(RuntimeError):

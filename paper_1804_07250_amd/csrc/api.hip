@@ -100,6 +100,17 @@ tl_status make_thresholds(const tl_domain &d, const tl_weights &w, std::vector<u
             if (!finite_pos(w.w[0]) || !finite_pos(w.w[1])) return fail(TL_EINVAL, "two-periodic weights must be > 0");
             const long double a = w.w[0], b = w.w[1];
             R = {1.0L, 1.0L, (b * b) / (a * a), (a * a) / (b * b)};
+        } else if (w.kind == TL_W_VOLUME_BW) {
+            long double q[2];
+            for (int i = 0; i < 2; ++i) {
+                const double num = w.w[2 * i], den = w.w[2 * i + 1];
+                if (!finite_pos(num) || (den != 0.0 && !finite_pos(den)))
+                    return fail(TL_EINVAL, "volume weights must be > 0");
+                q[i] = den > 0.0 ? (long double)num / (long double)den : (long double)num;
+            }
+            const long double qb4 = q[0] * q[0] * q[0] * q[0], qw4 = q[1] * q[1] * q[1] * q[1];
+            // vertical raises the height by 4 at black (x+y even) vertices, lowers it at white ones
+            R = {qb4, qb4, 1.0L / qw4, 1.0L / qw4};
         } else {
             return fail(TL_EINVAL, "weight kind %d does not apply to dominoes", w.kind);
         }
@@ -117,7 +128,17 @@ tl_status make_thresholds(const tl_domain &d, const tl_weights &w, std::vector<u
         break;
     case TL_SIXVERTEX: {
         long double a2 = 1, b2 = 1, c2 = 1;
-        if (w.kind == TL_W_SIXVERTEX) {
+        if (w.kind == TL_W_SIXVERTEX6) {
+            // With the boundary fixed, each corner of a flipped face moves
+            // between two types whose weights multiply to a1 a2, b1 b2 or
+            // c1 c2, so the chain sees the six weights only through those
+            // products: a^2 = a1 a2, b^2 = b1 b2, c^2 = c1 c2.
+            for (int i = 0; i < 6; ++i)
+                if (!finite_pos(w.w[i])) return fail(TL_EINVAL, "six-vertex weights must be > 0");
+            a2 = (long double)w.w[0] * w.w[1];
+            b2 = (long double)w.w[2] * w.w[3];
+            c2 = (long double)w.w[4] * w.w[5];
+        } else if (w.kind == TL_W_SIXVERTEX) {
             if (!finite_pos(w.w[0]) || !finite_pos(w.w[1]) || !finite_pos(w.w[2]))
                 return fail(TL_EINVAL, "six-vertex weights must be > 0");
             a2 = w.w[0];
@@ -426,9 +447,15 @@ tl_status tl_sampler_cftp(tl_sampler *s, uint32_t max_log2, tl_cftp_info *out)
     if (!s) return fail(TL_EINVAL, "null sampler");
     if (max_log2 < 1 || max_log2 > 31) return fail(TL_EINVAL, "max_log2 must be in 1..31");
     if (s->w.rule != TL_HEATBATH) return fail(TL_EINVAL, "coupling from the past needs the heat-bath rule");
-    if (s->dom.model == TL_SIXVERTEX && s->w.kind == TL_W_SIXVERTEX &&
-        (s->w.w[0] > s->w.w[2] || s->w.w[1] > s->w.w[2]))
-        return fail(TL_EINVAL, "coupling from the past needs a <= c and b <= c");
+    if (s->dom.model == TL_SIXVERTEX) {
+        // the moves keep the height order iff raising a diagonal face never
+        // lowers the up threshold (for weights a, b, c: a <= c and b <= c)
+        for (uint32_t m = 0; m < 16; ++m)
+            for (uint32_t k = 0; k < 4; ++k)
+                if (!(m >> k & 1u) && s->thr[m] > s->thr[m | (1u << k)])
+                    return fail(TL_EINVAL, "coupling from the past needs weights that keep the height order "
+                                           "(a <= c and b <= c)");
+    }
     std::string why;
     std::unique_ptr<tl::Model> top = tl::make_model(s->dom, why);
     if (!top) return fail(TL_EINVAL, "%s", why.c_str());
@@ -437,6 +464,49 @@ tl_status tl_sampler_cftp(tl_sampler *s, uint32_t max_log2, tl_cftp_info *out)
     if (e == hipSuccess) e = hipMalloc(&flag, sizeof(uint32_t));
     const tl::Thr T = table_of(s);
     const size_t words = s->model->state_words();
+    // A state that is one tile runs both chains of a segment in one two-job
+    // launch (one work-group each); descriptors are staged per segment.
+    const uint32_t kSeg = 32;
+    tl::TileJob *h_jobs = nullptr, *d_jobs = nullptr;
+    tl::TileItem *d_items = nullptr;
+    bool fused = s->opt.kernel == 0 && s->opt.tile_rows == 0 && s->opt.tile_groups == 0 &&
+                 s->opt.sweeps_per_launch == 0;
+    if (fused && e == hipSuccess) {
+        tl::TileJob j;
+        tl::TilePlan p;
+        fused = s->model->tile_job(0, 1, T, false, s->seed, &j, &p) && p.tiles() == 1;
+    }
+    if (fused && e == hipSuccess) {
+        const tl::TileItem items[2] = {{0u, 0u}, {1u, 0u}};
+        e = hipHostMalloc((void **)&h_jobs, 2 * kSeg * sizeof(tl::TileJob), hipHostMallocDefault);
+        if (e == hipSuccess) e = hipMalloc(&d_jobs, 2 * kSeg * sizeof(tl::TileJob));
+        if (e == hipSuccess) e = hipMalloc(&d_items, sizeof(items));
+        if (e == hipSuccess) e = hipMemcpy(d_items, items, sizeof(items), hipMemcpyHostToDevice);
+    }
+    auto segment = [&](uint32_t slot, uint32_t t0, uint32_t count) -> hipError_t {
+        if (!fused) {
+            hipError_t err = s->model->sweeps(t0, count, T, false, s->seed, s->opt, s->stream);
+            if (err == hipSuccess) err = top->sweeps(t0, count, T, false, s->seed, s->opt, s->stream);
+            return err;
+        }
+        tl::TilePlan pb, pt;
+        if (!s->model->tile_job(t0, count, T, false, s->seed, &h_jobs[2 * slot], &pb) ||
+            !top->tile_job(t0, count, T, false, s->seed, &h_jobs[2 * slot + 1], &pt) || pb.S != count ||
+            pb.tiles() != 1 || pt.tiles() != 1)
+            return hipErrorInvalidConfiguration;
+        hipError_t err = hipMemcpyAsync(d_jobs + 2 * slot, h_jobs + 2 * slot, 2 * sizeof(tl::TileJob),
+                                        hipMemcpyHostToDevice, s->stream);
+        if (err == hipSuccess)
+            err = s->model->height_family()
+                      ? tl::height_items(d_jobs + 2 * slot, d_items, 2, pb.threads, pb.lds, h_jobs[2 * slot].mode,
+                                         h_jobs[2 * slot].kind, s->stream)
+                      : tl::domino_items(d_jobs + 2 * slot, d_items, 2, pb.threads, pb.lds, s->stream);
+        if (err == hipSuccess) {
+            s->model->swap_buffers();
+            top->swap_buffers();
+        }
+        return err;
+    };
     uint64_t total = 0;
     uint32_t R = 1, differ = 1;
     for (; e == hipSuccess && R <= max_log2; ++R) {
@@ -444,8 +514,7 @@ tl_status tl_sampler_cftp(tl_sampler *s, uint32_t max_log2, tl_cftp_info *out)
         if (e == hipSuccess) e = top->init(true, s->stream);
         for (int r = (int)R; r >= 0 && e == hipSuccess; --r) {
             const uint32_t t0 = r ? 1u << (r - 1) : 0u, count = r ? 1u << (r - 1) : 1u;
-            e = s->model->sweeps(t0, count, T, false, s->seed, s->opt, s->stream);
-            if (e == hipSuccess) e = top->sweeps(t0, count, T, false, s->seed, s->opt, s->stream);
+            e = segment((uint32_t)r, t0, count);
         }
         total += 2ull << R;
         if (e == hipSuccess) e = hipMemsetAsync(flag, 0, sizeof(uint32_t), s->stream);
@@ -460,6 +529,9 @@ tl_status tl_sampler_cftp(tl_sampler *s, uint32_t max_log2, tl_cftp_info *out)
         if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
         if (e == hipSuccess && !differ) break;
     }
+    if (h_jobs) (void)hipHostFree(h_jobs);
+    if (d_jobs) (void)hipFree(d_jobs);
+    if (d_items) (void)hipFree(d_items);
     top->release();
     if (flag) (void)hipFree(flag);
     if (e != hipSuccess)

@@ -25,10 +25,11 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
             k1 += kPhiloxW1;
         }
         // one 32 x 32 -> 64-bit product each (a single v_mad_u64_u32, where
-        // separate high and low halves cost two multiplies)
+        // separate high and low halves cost two multiplies), and each
+        // three-way XOR as one v_bitop3_b32 (truth table 0x96 = a ^ b ^ c)
         const uint64_t p0 = (uint64_t)kPhiloxM0 * c0, p1 = (uint64_t)kPhiloxM1 * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, k0, 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, k1, 0x96);
         c0 = n0;
         c1 = (uint32_t)p1;
         c2 = n2;

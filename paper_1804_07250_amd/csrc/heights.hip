@@ -52,6 +52,21 @@ namespace {
 enum { kHeatBath = 0, kMetropolis = 1, kUniform = 2 };
 static_assert(kHeatBath == kModeHeatBath && kMetropolis == kModeMetropolis && kUniform == kModeUniform,
               "kernel modes and TileJob modes agree");
+// Threads per work-group of the tiled and item kernels: 512 leaves 256 VGPRs
+// per lane for the weighted decisions (the largest plans use ~400).
+constexpr uint32_t kHeightThreads = 512;
+// Layout of a six-vertex threshold table (each layout is its own kernel
+// instantiation, so its registers are allocated for it alone): 9 classes
+// (sA, sB) [x2 for Metropolis], or 5 classes by sA + sB (heat-bath).  Lozenge
+// tables always use kKindClass.
+enum { kKindClass = 0, kKindSum = 1 };
+static_assert(kKindClass == kTableClass && kKindSum == kTableSum, "table layouts agree");
+
+// Instantiation KERNEL<mode, layout> for a rule (mode) and table layout (kind).
+#define TL_HEIGHT_PICK(KERNEL, mode, kind)                                                      \
+    ((mode) == kUniform ? KERNEL<kUniform, kKindClass>                                          \
+     : (mode) == kMetropolis ? KERNEL<kMetropolis, kKindClass>                                  \
+     : (kind) == kKindSum ? KERNEL<kHeatBath, kKindSum> : KERNEL<kHeatBath, kKindClass>)
 
 struct Geo {
     int model, a, b, c, N;
@@ -99,7 +114,8 @@ __global__ void height_init_kernel(uint32_t *pa, uint32_t *pb, size_t PS, uint32
 }
 
 // Contexts: lozenge heat-bath 1, Metropolis 2 (current up); six-vertex
-// heat-bath 9 classes 3*sA + sB, Metropolis 18 (2*class + current up).
+// heat-bath 9 classes 3*sA + sB, Metropolis 18 (2*class + current up), or,
+// when a heat-bath table has 5 entries, classes by sA + sB alone.
 template <int MODE>
 __device__ __forceinline__ void loz_decide(uint32_t k0, uint32_t k1, uint32_t g, uint32_t r, uint32_t t, uint32_t c,
                                            const Thr &Tall, const uint32_t (&R0)[4], const uint32_t (&cur)[4],
@@ -122,40 +138,56 @@ __device__ __forceinline__ void loz_decide(uint32_t k0, uint32_t k1, uint32_t g,
     }
 }
 
-template <int MODE>
+template <int MODE, int KIND>
 __device__ __forceinline__ void sixv_decide(uint32_t k0, uint32_t k1, uint32_t g, uint32_t r, uint32_t t, uint32_t c,
                                             const Thr &Tall, const uint32_t (&R0)[4], const uint32_t (&hNE)[4],
                                             const uint32_t (&hNW)[4], const uint32_t (&hSW)[4],
                                             const uint32_t (&hSE)[4], const uint32_t (&cur)[4],
                                             const uint32_t (&live)[4], uint32_t (&D)[4])
 {
-    if (MODE == kUniform) {
+    if constexpr (MODE == kUniform) {
 #pragma unroll
         for (int w = 0; w < 4; ++w) D[w] = ~R0[w];
-        return;
-    }
-    constexpr int NC = MODE == kMetropolis ? 18 : 9;
-    uint32_t T[NC], cm[NC][4];
+    } else if constexpr (KIND == kKindSum && MODE == kHeatBath) {
+        // thresholds that depend on sA + sB only (a = b): 5 classes s = 0..4
+        uint32_t T[5], cm[5][4];
 #pragma unroll
-    for (int i = 0; i < NC; ++i) T[i] = Tall.v[i];
+        for (int i = 0; i < 5; ++i) T[i] = Tall.v[i];
 #pragma unroll
-    for (int w = 0; w < 4; ++w) {
-        const uint32_t A[3] = {~hNE[w] & ~hSW[w], hNE[w] ^ hSW[w], hNE[w] & hSW[w]};
-        const uint32_t B[3] = {~hNW[w] & ~hSE[w], hNW[w] ^ hSE[w], hNW[w] & hSE[w]};
+        for (int w = 0; w < 4; ++w) {
+            const uint32_t A0 = ~hNE[w] & ~hSW[w], A1 = hNE[w] ^ hSW[w], A2 = hNE[w] & hSW[w];
+            const uint32_t B0 = ~hNW[w] & ~hSE[w], B1 = hNW[w] ^ hSE[w], B2 = hNW[w] & hSE[w];
+            cm[0][w] = A0 & B0;
+            cm[1][w] = (A0 & B1) | (A1 & B0);
+            cm[2][w] = (A0 & B2) | (A1 & B1) | (A2 & B0);
+            cm[3][w] = (A1 & B2) | (A2 & B1);
+            cm[4][w] = A2 & B2;
+        }
+        decide128<5>(k0, k1, g, r, t, c, T, cm, live, D);
+    } else {
+        constexpr int NC = MODE == kMetropolis ? 18 : 9;
+        uint32_t T[NC], cm[NC][4];
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
+        for (int i = 0; i < NC; ++i) T[i] = Tall.v[i];
 #pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                const uint32_t m = A[i] & B[j];
-                if (MODE == kMetropolis) {
-                    cm[2 * (3 * i + j)][w] = m & ~cur[w];
-                    cm[2 * (3 * i + j) + 1][w] = m & cur[w];
-                } else {
-                    cm[3 * i + j][w] = m;
+        for (int w = 0; w < 4; ++w) {
+            const uint32_t A[3] = {~hNE[w] & ~hSW[w], hNE[w] ^ hSW[w], hNE[w] & hSW[w]};
+            const uint32_t B[3] = {~hNW[w] & ~hSE[w], hNW[w] ^ hSE[w], hNW[w] & hSE[w]};
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    const uint32_t m = A[i] & B[j];
+                    if (MODE == kMetropolis) {
+                        cm[2 * (3 * i + j)][w] = m & ~cur[w];
+                        cm[2 * (3 * i + j) + 1][w] = m & cur[w];
+                    } else {
+                        cm[3 * i + j][w] = m;
+                    }
                 }
-            }
+        }
+        decide128<NC>(k0, k1, g, r, t, c, T, cm, live, D);
     }
-    decide128<NC>(k0, k1, g, r, t, c, T, cm, live, D);
 }
 
 // One lozenge group: sites k = 128 g + (0..127) of plane s0 in row Y.
@@ -211,7 +243,7 @@ __device__ __forceinline__ void loz_group(uint32_t *base, size_t ps, uint32_t rs
 }
 
 // One six-vertex group: faces I = 2k + p, k = 128 g + (0..127), of row J.
-template <int MODE>
+template <int MODE, int KIND>
 __device__ __forceinline__ void sixv_group(uint32_t *base, size_t ps, uint32_t rs, uint32_t lrow, uint32_t lgrp,
                                            const Geo &geo, int J, uint32_t g, uint32_t p, uint32_t colour, uint32_t t,
                                            const Thr &Tall, uint32_t k0, uint32_t k1)
@@ -257,7 +289,7 @@ __device__ __forceinline__ void sixv_group(uint32_t *base, size_t ps, uint32_t r
     }
     if (!any) return;
     uint32_t D[4];
-    sixv_decide<MODE>(k0, k1, g, (uint32_t)J, t, colour, Tall, R0, hNE, hNW, hSW, hSE, cur, live, D);
+    sixv_decide<MODE, KIND>(k0, k1, g, (uint32_t)J, t, colour, Tall, R0, hNE, hNW, hSW, hSE, cur, live, D);
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
         const uint32_t nw = ~(D[w] ^ up[w]);
@@ -279,7 +311,7 @@ __device__ __forceinline__ bool site_row(const Geo &geo, int y, uint32_t rows)
     return y >= 1 && y <= (int)rows - 2;
 }
 
-template <int MODE>
+template <int MODE, int KIND>
 __device__ __forceinline__ void height_group(uint32_t *base, size_t ps, uint32_t rs, uint32_t lrow, uint32_t lgrp,
                                              const Geo &geo, int y, uint32_t g, uint32_t colour, uint32_t t,
                                              const Thr &T, uint32_t k0, uint32_t k1)
@@ -289,10 +321,10 @@ __device__ __forceinline__ void height_group(uint32_t *base, size_t ps, uint32_t
     if (geo.model == TL_LOZENGE)
         loz_group<MODE>(base, ps, rs, lrow, lgrp, geo, y, g, (uint32_t)pl, colour, t, T, k0, k1);
     else
-        sixv_group<MODE>(base, ps, rs, lrow, lgrp, geo, y, g, (uint32_t)pl, colour, t, T, k0, k1);
+        sixv_group<MODE, KIND>(base, ps, rs, lrow, lgrp, geo, y, g, (uint32_t)pl, colour, t, T, k0, k1);
 }
 
-template <int MODE>
+template <int MODE, int KIND>
 __global__ void __launch_bounds__(256) height_step_kernel(uint32_t *planes, size_t PS, uint32_t RS, uint32_t ng,
                                                           uint32_t rows, Geo geo, uint32_t colour, uint32_t t, Thr T,
                                                           uint32_t k0, uint32_t k1)
@@ -300,7 +332,7 @@ __global__ void __launch_bounds__(256) height_step_kernel(uint32_t *planes, size
     const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t g = gid % ng, y = gid / ng;
     if (!site_row(geo, (int)y, rows)) return;
-    height_group<MODE>(planes, PS, RS, y, g, geo, (int)y, g, colour, t, T, k0, k1);
+    height_group<MODE, KIND>(planes, PS, RS, y, g, geo, (int)y, g, colour, t, T, k0, k1);
 }
 
 // One tile of the multi-sweep kernel.  LDS: P planes x LR rows x LRS words,
@@ -311,7 +343,7 @@ __global__ void __launch_bounds__(256) height_step_kernel(uint32_t *planes, size
 // block has a thread per (row, group) task (blockDim >= LR * LG, as every
 // launch plan gives): thread tid handles group tid % LG of row
 // rps*s + tid / LG.
-template <int MODE>
+template <int MODE, int KIND>
 __device__ __forceinline__ void height_tile(uint32_t *lds, const uint32_t *__restrict__ in,
                                             uint32_t *__restrict__ out, size_t PS, uint32_t RS, uint32_t ng,
                                             uint32_t rows, uint32_t P, const Geo &geo, uint32_t t0,
@@ -348,7 +380,7 @@ __device__ __forceinline__ void height_tile(uint32_t *lds, const uint32_t *__res
             const uint32_t lr = base + r0;
             const int gr = R0 + (int)lr;
             if (lane && lr < end && lr >= 1 && lr + 1 < LR && site_row(geo, gr, rows))
-                height_group<MODE>(lds, LPS, LRS, lr, lg, geo, gr, (uint32_t)gg, c, t, T, k0, k1);
+                height_group<MODE, KIND>(lds, LPS, LRS, lr, lg, geo, gr, (uint32_t)gg, c, t, T, k0, k1);
             __syncthreads();
         }
     }
@@ -365,8 +397,8 @@ __device__ __forceinline__ void height_tile(uint32_t *lds, const uint32_t *__res
 }
 
 // Tiled multi-sweep kernel of one state: one work-group per tile.
-template <int MODE>
-__global__ void __launch_bounds__(1024) height_tiled_kernel(const uint32_t *__restrict__ in,
+template <int MODE, int KIND>
+__global__ void __launch_bounds__(kHeightThreads) height_tiled_kernel(const uint32_t *__restrict__ in,
                                                             uint32_t *__restrict__ out, size_t PS, uint32_t RS,
                                                             uint32_t ng, uint32_t rows, uint32_t P, Geo geo,
                                                             uint32_t t0, uint32_t nsweeps, uint32_t TR, uint32_t TG,
@@ -374,32 +406,35 @@ __global__ void __launch_bounds__(1024) height_tiled_kernel(const uint32_t *__re
                                                             uint32_t k0, uint32_t k1)
 {
     extern __shared__ uint32_t lds[];
-    height_tile<MODE>(lds, in, out, PS, RS, ng, rows, P, geo, t0, nsweeps, TR, TG, HR, HG, blockIdx.x / tiles_x,
+    height_tile<MODE, KIND>(lds, in, out, PS, RS, ng, rows, P, geo, t0, nsweeps, TR, TG, HR, HG, blockIdx.x / tiles_x,
                       blockIdx.x % tiles_x, T, k0, k1);
 }
 
 // Multi-job kernel: work-group b runs tile items[b].tile of job items[b].job,
 // with that job's geometry, plan, thresholds and key.
-template <int MODE>
+template <int MODE, int KIND>
 __device__ __forceinline__ void height_item(uint32_t *lds, const TileJob &j, uint32_t tile)
 {
     const Geo geo{j.model, j.a, j.b, j.c, j.N};
-    height_tile<MODE>(lds, j.in, j.out, j.PS, j.RS, j.ng, j.rows, j.P, geo, j.t0, j.S, j.TR, j.TG, j.HR, j.HG,
+    height_tile<MODE, KIND>(lds, j.in, j.out, j.PS, j.RS, j.ng, j.rows, j.P, geo, j.t0, j.S, j.TR, j.TG, j.HR, j.HG,
                       tile / j.tiles_x, tile % j.tiles_x, j.T, j.key0, j.key1);
 }
 
-__global__ void __launch_bounds__(1024) height_items_kernel(const TileJob *__restrict__ jobs,
-                                                            const TileItem *__restrict__ items)
+template <int MODE, int KIND>
+__global__ void __launch_bounds__(kHeightThreads) height_items_kernel(const TileJob *__restrict__ jobs,
+                                                                      const TileItem *__restrict__ items)
 {
     extern __shared__ uint32_t lds[];
     const TileItem it = items[blockIdx.x];
     const TileJob &j = jobs[it.job];
-    if (j.mode == kUniform)
-        height_item<kUniform>(lds, j, it.tile);
-    else if (j.mode == kMetropolis)
-        height_item<kMetropolis>(lds, j, it.tile);
-    else
-        height_item<kHeatBath>(lds, j, it.tile);
+    if constexpr (MODE == kHeatBath) {
+        // one-bit jobs share the heat-bath launches (the lighter kernel body)
+        if (j.mode == kUniform) {
+            height_item<kUniform, kKindClass>(lds, j, it.tile);
+            return;
+        }
+    }
+    height_item<MODE, KIND>(lds, j, it.tile);
 }
 
 __device__ __forceinline__ uint32_t hbit(const uint32_t *pl, size_t PS, uint32_t RS, uint32_t p, uint32_t y,
@@ -510,8 +545,8 @@ hipError_t height_colour_step(const HeightDev &d, int colour, uint32_t t, const 
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     const uint32_t threads = d.ng * d.rows;
     dim3 block(256), grid((threads + 255) / 256);
-    auto k = T.uniform() ? height_step_kernel<kUniform>
-                         : (metropolis ? height_step_kernel<kMetropolis> : height_step_kernel<kHeatBath>);
+    const int mode = T.uniform() ? kUniform : (metropolis ? kMetropolis : kHeatBath);
+    auto k = TL_HEIGHT_PICK(height_step_kernel, mode, (int)table_kind(T));
     return launch(tm, 1, k, grid, block, 0, s, d.planes, d.PS, d.RS, d.ng, d.rows, geo_of(d), (uint32_t)colour, t, T,
                   k0, k1);
 }
@@ -525,7 +560,7 @@ HeightTile height_auto_tile(const HeightDev &d)
         t.S = 1u << 30;
         return t;
     }
-    t.TR = 32;
+    t.TR = 8;   // measured best on MI355X for the 1024 hexagon and the N = 1024 square
     t.TG = d.ng < 4 ? d.ng : 4;
     t.S = 8;
     return t;
@@ -539,7 +574,7 @@ bool height_plan(const HeightDev &d, const HeightTile &tile, uint32_t S_max, Til
     const uint32_t TG = tile.TG == 0 ? 1u : (tile.TG < d.ng ? tile.TG : d.ng);
     const uint32_t tiles_x = (d.ng + TG - 1) / TG;
     const uint32_t LG0 = TG + (tiles_x > 1 ? 2u : 0u);
-    const uint32_t max_rows = 1024u / LG0;
+    const uint32_t max_rows = kHeightThreads / LG0;
     if (max_rows < 2u * rows_per_sweep + 3u) return false;
     uint32_t TR = tile.TR == 0 ? 1u : (tile.TR < d.rows ? tile.TR : d.rows);
     if (TR < d.rows && TR > max_rows - 2u * rows_per_sweep) TR = max_rows - 2u * rows_per_sweep;
@@ -554,7 +589,7 @@ bool height_plan(const HeightDev &d, const HeightTile &tile, uint32_t S_max, Til
     const uint32_t LR = TR + 2 * HR, LG = TG + 2 * HG;
     const uint32_t tasks = LR * LG;
     const uint32_t lds = d.P * LR * 4u * (LG + 2u) * 4u;
-    if (tasks > 1024u || lds > 160u * 1024u) return false;
+    if (tasks > kHeightThreads || lds > 160u * 1024u) return false;
     p->S = S;
     p->TR = TR;
     p->TG = TG;
@@ -576,8 +611,8 @@ hipError_t height_tiled_sweeps(HeightDev &d, const HeightTile &tile, uint32_t t0
     while (done < nsw) {
         TilePlan p;
         if (!height_plan(d, tile, nsw - done, &p)) return hipErrorInvalidConfiguration;
-        auto k = T.uniform() ? height_tiled_kernel<kUniform>
-                             : (metropolis ? height_tiled_kernel<kMetropolis> : height_tiled_kernel<kHeatBath>);
+        const int mode = T.uniform() ? kUniform : (metropolis ? kMetropolis : kHeatBath);
+        auto k = TL_HEIGHT_PICK(height_tiled_kernel, mode, (int)table_kind(T));
         hipError_t e = launch(tm, colours * p.S, k, dim3(p.tiles()), dim3(p.threads), p.lds, s,
                               (const uint32_t *)d.planes, d.spare, d.PS, d.RS, d.ng, d.rows, d.P, geo_of(d),
                               t0 + done, p.S, p.TR, p.TG, p.HR, p.HG, p.tiles_x, T, k0, k1);
@@ -615,6 +650,7 @@ TileJob height_tile_job(const HeightDev &d, const TilePlan &p, uint32_t t0, cons
     j.HG = p.HG;
     j.tiles_x = p.tiles_x;
     j.mode = T.uniform() ? kModeUniform : (metropolis ? kModeMetropolis : kModeHeatBath);
+    j.kind = T.uniform() ? (uint32_t)kTableClass : table_kind(T);
     j.key0 = (uint32_t)seed;
     j.key1 = (uint32_t)(seed >> 32);
     j.T = T;
@@ -622,11 +658,13 @@ TileJob height_tile_job(const HeightDev &d, const TilePlan &p, uint32_t t0, cons
 }
 
 hipError_t height_items(const TileJob *jobs, const TileItem *items, uint32_t n_items, uint32_t threads, uint32_t lds,
-                        hipStream_t s)
+                        uint32_t mode, uint32_t kind, hipStream_t s)
 {
     if (n_items == 0) return hipSuccess;
-    if (threads == 0 || threads > 1024u || lds > 160u * 1024u) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(height_items_kernel, dim3(n_items), dim3(threads), lds, s, jobs, items);
+    if (threads == 0 || threads > kHeightThreads || lds > 160u * 1024u || mode > 2u || kind > 1u)
+        return hipErrorInvalidConfiguration;
+    auto k = TL_HEIGHT_PICK(height_items_kernel, (int)mode, (int)kind);
+    hipLaunchKernelGGL(k, dim3(n_items), dim3(threads), lds, s, jobs, items);
     return hipGetLastError();
 }
 

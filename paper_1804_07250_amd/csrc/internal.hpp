@@ -194,6 +194,10 @@ bool height_plan(const HeightDev &d, const HeightTile &tile, uint32_t S_max, Til
 // and the buffer it writes, its geometry, launch plan, thresholds and key.
 // A work-group handles one item (job, tile).
 enum { kModeHeatBath = 0, kModeMetropolis = 1, kModeUniform = 2 };
+// Layout of a height-model kernel table: classes (lozenge; six-vertex 9 classes
+// (sA, sB) [x2 Metropolis]) or six-vertex 5 classes by sA + sB (heat-bath).
+enum { kTableClass = 0, kTableSum = 1 };
+inline uint32_t table_kind(const Thr &K) { return K.count == 5u ? (uint32_t)kTableSum : (uint32_t)kTableClass; }
 struct TileJob {
     const uint32_t *in;
     uint32_t *out;
@@ -202,6 +206,7 @@ struct TileJob {
     int32_t model, a, b, c, N, omega;   // heights: model and sides; domino: omega
     uint32_t t0, S, TR, TG, HR, HG, tiles_x;
     uint32_t mode;                      // kMode*
+    uint32_t kind;                      // kTable* (height models)
     uint32_t key0, key1;
     Thr T;                              // kernel table (heights: weight classes)
 };
@@ -216,8 +221,10 @@ TileJob height_tile_job(const HeightDev &d, const TilePlan &p, uint32_t t0, cons
 // work-group at least the largest any item's plan asks for.
 hipError_t domino_items(const TileJob *jobs, const TileItem *items, uint32_t n_items, uint32_t threads,
                         uint32_t lds, hipStream_t s);
+// Height items of one launch share one rule and one table kind (one kernel
+// instantiation each); a heat-bath launch also runs one-bit jobs.
 hipError_t height_items(const TileJob *jobs, const TileItem *items, uint32_t n_items, uint32_t threads,
-                        uint32_t lds, hipStream_t s);
+                        uint32_t lds, uint32_t mode, uint32_t kind, hipStream_t s);
 
 // ----------------------------------------------------------------- hashing
 // SHA-256 of each of `rows` rows of `row_bytes` bytes at `data` (device), into

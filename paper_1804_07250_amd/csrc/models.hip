@@ -189,14 +189,14 @@ public:
         d_.spare = spare;
         owned_ = false;
     }
-    // Served tiles: a state whose (row, group) tasks fit one work-group and
+    // Served tiles: a state whose (row, group) tasks fit one work-group (512) and
     // whose planes fit 64 KB of LDS is one tile (no halo, any sweep count);
     // larger ones are cut into 32-row tiles spanning up to 8 groups.
     bool tile_job(uint32_t t0, uint32_t S_max, const Thr &T, bool metro, uint64_t seed, TileJob *j,
                   TilePlan *p) const override
     {
         HeightTile tile;
-        if (d_.rows * d_.ng <= 1024u && (size_t)d_.P * d_.rows * 4u * (d_.ng + 2u) * 4u <= 64u * 1024u) {
+        if (d_.rows * d_.ng <= 512u && (size_t)d_.P * d_.rows * 4u * (d_.ng + 2u) * 4u <= 64u * 1024u) {
             tile.TR = d_.rows;
             tile.TG = d_.ng;
         } else {
@@ -215,12 +215,33 @@ public:
 
     // Six-vertex kernels take one threshold per weight class (sA, sB) (and
     // current state for Metropolis): class 3*sA + sB <-> mask with NE = sA>=1,
-    // SW = sA>=2, NW = sB>=1, SE = sB>=2.
+    // SW = sA>=2, NW = sB>=1, SE = sB>=2.  When the thresholds depend on
+    // sA + sB only (a = b), a heat-bath table has one entry per sum s = 0..4
+    // instead, and the kernels use those 5 classes.
     Thr kernel_table(const Thr &T, bool metro) const
     {
         if (loz()) return T;
+        auto mask_of = [](int i, int j) {
+            return (i >= 1 ? 1u : 0u) | (j >= 1 ? 2u : 0u) | (i >= 2 ? 4u : 0u) | (j >= 2 ? 8u : 0u);
+        };
+        const uint32_t per = metro ? 2u : 1u;
+        bool by_sum = !metro;
+        for (int i = 0; i < 3 && by_sum; ++i)
+            for (int j = 0; j < 3; ++j) {
+                const int s = i + j, i0 = s < 2 ? s : 2;   // reference class of the sum
+                for (uint32_t q = 0; q < per; ++q)
+                    if (T.v[per * mask_of(i, j) + q] != T.v[per * mask_of(i0, s - i0) + q]) by_sum = false;
+            }
         Thr K{};
         uint32_t n = 0;
+        if (by_sum) {
+            for (int s = 0; s <= 4; ++s) {
+                const int i0 = s < 2 ? s : 2;
+                for (uint32_t q = 0; q < per; ++q) K.v[n++] = T.v[per * mask_of(i0, s - i0) + q];
+            }
+            K.count = n;
+            return K;
+        }
         for (int i = 0; i < 3; ++i)
             for (int j = 0; j < 3; ++j) {
                 const uint32_t mask = (i >= 1 ? 1u : 0u) | (j >= 1 ? 2u : 0u) | (i >= 2 ? 4u : 0u) | (j >= 2 ? 8u : 0u);

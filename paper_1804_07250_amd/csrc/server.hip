@@ -341,11 +341,9 @@ bool tick(tl_server *sv)
         else fin.push_back(j.get());
     }
     if (run.empty() && fin.empty()) return false;
-    // weighted jobs first: their items take longest
-    std::stable_sort(run.begin(), run.end(), [](const Job *a, const Job *b) { return !a->uniform && b->uniform; });
     std::vector<tl::TileJob> jobs(run.size());
     std::vector<tl::TilePlan> plans(run.size());
-    uint32_t n_items = 0, n_height = 0;
+    uint32_t n_items = 0;
     for (size_t i = 0; i < run.size(); ++i) {
         Job &j = *run[i];
         const uint64_t left = j.sweeps - j.enq;
@@ -358,7 +356,6 @@ bool tick(tl_server *sv)
             continue;
         }
         n_items += plans[i].tiles();
-        if (j.model->height_family()) n_height += plans[i].tiles();
     }
     hipError_t e = grow(sv, (uint32_t)run.size(), n_items);
     if (e != hipSuccess) {   // finish these jobs, as failed, at the next tick
@@ -372,29 +369,47 @@ bool tick(tl_server *sv)
     sv->next_slot = (sv->next_slot + 1) % tl_server::kSlots;
     tl::TileJob *hj = sv->h_jobs[slot];
     tl::TileItem *hi = sv->h_items[slot];
-    uint32_t ih = 0, idm = n_height;
-    uint32_t th_h = 0, th_d = 0, lds_h = 0, lds_d = 0;
-    for (size_t i = 0; i < run.size(); ++i) {
-        hj[i] = jobs[i];
+    // one launch per kernel instantiation: height jobs grouped by rule and
+    // table layout (one-bit jobs ride with the heat-bath ones of the 5-class
+    // layout), then the domino jobs
+    auto key = [&](size_t i) {
+        if (!run[i]->model->height_family()) return 100u;
+        if (jobs[i].mode == tl::kModeUniform) return (uint32_t)tl::kTableSum;
+        return (jobs[i].mode == tl::kModeMetropolis ? 3u : 0u) + jobs[i].kind;
+    };
+    std::vector<size_t> order(run.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return key(a) < key(b); });
+    struct Group {
+        uint32_t first, count, threads, lds, key;
+    };
+    std::vector<Group> groups;
+    uint32_t ni = 0;
+    for (size_t pos = 0; pos < order.size(); ++pos) {
+        const size_t i = order[pos];
+        hj[pos] = jobs[i];
         const tl::TilePlan &p = plans[i];
-        const bool h = run[i]->model->height_family();
-        for (uint32_t t = 0; t < p.tiles(); ++t) hi[h ? ih++ : idm++] = tl::TileItem{(uint32_t)i, t};
         if (p.tiles() == 0) continue;
-        if (h) {
-            th_h = std::max(th_h, p.threads);
-            lds_h = std::max(lds_h, p.lds);
-        } else {
-            th_d = std::max(th_d, p.threads);
-            lds_d = std::max(lds_d, p.lds);
-        }
+        if (groups.empty() || groups.back().key != key(i)) groups.push_back(Group{ni, 0u, 0u, 0u, key(i)});
+        Group &gr = groups.back();
+        for (uint32_t t = 0; t < p.tiles(); ++t) hi[ni++] = tl::TileItem{(uint32_t)pos, t};
+        gr.count += p.tiles();
+        gr.threads = std::max(gr.threads, p.threads);
+        gr.lds = std::max(gr.lds, p.lds);
     }
-    if (n_items) {
+    if (ni) {
         e = hipMemcpyAsync(sv->d_jobs, hj, run.size() * sizeof(tl::TileJob), hipMemcpyHostToDevice, sv->stream);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(sv->d_items, hi, n_items * sizeof(tl::TileItem), hipMemcpyHostToDevice, sv->stream);
-        if (e == hipSuccess) e = tl::height_items(sv->d_jobs, sv->d_items, n_height, th_h, lds_h, sv->stream);
-        if (e == hipSuccess)
-            e = tl::domino_items(sv->d_jobs, sv->d_items + n_height, n_items - n_height, th_d, lds_d, sv->stream);
+            e = hipMemcpyAsync(sv->d_items, hi, ni * sizeof(tl::TileItem), hipMemcpyHostToDevice, sv->stream);
+        for (const Group &gr : groups) {
+            if (e != hipSuccess) break;
+            if (gr.key == 100u)
+                e = tl::domino_items(sv->d_jobs, sv->d_items + gr.first, gr.count, gr.threads, gr.lds, sv->stream);
+            else
+                e = tl::height_items(sv->d_jobs, sv->d_items + gr.first, gr.count, gr.threads, gr.lds,
+                                     gr.key >= 3u ? (uint32_t)tl::kModeMetropolis : (uint32_t)tl::kModeHeatBath,
+                                     gr.key % 3u, sv->stream);
+        }
     }
     for (size_t i = 0; i < run.size(); ++i) {
         Job &j = *run[i];

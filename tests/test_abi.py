@@ -61,6 +61,12 @@ def test_thresholds_equal_exact_tables(metro):
          oracle.sixv_ratios(1, 1, 1)),
         (tl.domain(tl.TL_SIXVERTEX, n=8), tl.weights(tl.TL_W_SIXVERTEX, 4.0, 1.0, 4.0, rule=rule),
          oracle.sixv_ratios(2, 1, 4)),
+        (tl.domain(tl.TL_SIXVERTEX, n=8), tl.weights(tl.TL_W_SIXVERTEX6, 1.0, 2.0, 1.5, 0.5, 1.0, 3.0, rule=rule),
+         oracle.sixv_ratios6(1, 2, Fraction(3, 2), Fraction(1, 2), 1, 3)),
+        (tl.domain(tl.TL_DOMINO, n=8), tl.weights(tl.TL_W_VOLUME_BW, 20.0, 1.0, 1.0, 20.0, rule=rule),
+         oracle.domino_ratios("volume", 20, Fraction(1, 20))),
+        (tl.domain(tl.TL_DOMINO, n=8), tl.weights(tl.TL_W_VOLUME_BW, 5.0, 4.0, 2.0, 3.0, rule=rule),
+         oracle.domino_ratios("volume", Fraction(5, 4), Fraction(2, 3))),
     ]
     for dom, w, ratios in cases:
         assert tl.thresholds(dom, w) == oracle.table_from_ratios(ratios, metro)

@@ -156,7 +156,9 @@ def test_server_multi_tile_jobs_equal_alone(quantum):
             (tl.domain(tl.TL_SIXVERTEX, n=48), metro, 9, 29),
             (tl.domain(tl.TL_DOMINO, n=150), two_periodic(tl), 10, 19),
             (tl.domain(tl.TL_SIXVERTEX, n=64), sixv_w(tl, (1.0, 1.0, 2.0)), 11, 0),
-            (tl.domain(tl.TL_LOZENGE, a=30, b=20, c=10), tl.weights(tl.TL_W_UNIFORM), 12, 33)]
+            (tl.domain(tl.TL_LOZENGE, a=30, b=20, c=10), tl.weights(tl.TL_W_UNIFORM), 12, 33),
+            (tl.domain(tl.TL_SIXVERTEX, n=90), tl.weights(tl.TL_W_SIXVERTEX6, 1.0, 2.0, 1.5, 0.5, 1.0, 3.0), 13, 26),
+            (tl.domain(tl.TL_DOMINO, n=64), tl.weights(tl.TL_W_VOLUME_BW, 20.0, 1.0, 1.0, 20.0), 14, 15)]
     sv = Server(256 * 1024 * 1024, max_slots=3, opt=tl.options(sweeps_per_launch=quantum))
     tickets = [sv.submit(d, w, seed, n) for d, w, seed, n in jobs]
     res = [sv.wait(t, 120.0) for t in tickets]

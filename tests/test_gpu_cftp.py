@@ -16,6 +16,9 @@ def case(tl, kind, size, weights):
         dom = tl.domain(tl.TL_DOMINO, n=size)
         if weights == "uniform":
             w, thr = tl.weights(tl.TL_W_UNIFORM), oracle.table_from_ratios(oracle.domino_ratios(), False)
+        elif weights == "volume":
+            w = tl.weights(tl.TL_W_VOLUME_BW, 5.0, 4.0, 2.0, 3.0)
+            thr = oracle.table_from_ratios(oracle.domino_ratios("volume", Fraction(5, 4), Fraction(2, 3)), False)
         else:
             w = tl.weights(tl.TL_W_TWO_PERIODIC, 1.0, 0.5)
             thr = oracle.table_from_ratios(oracle.domino_ratios("two", 1, Fraction(1, 2)), False)
@@ -26,6 +29,11 @@ def case(tl, kind, size, weights):
         w = tl.weights(tl.TL_W_VOLUME, q.numerator, q.denominator)
         thr = oracle.table_from_ratios(oracle.lozenge_ratios(q), False)
         make = lambda seed: (lambda init: oracle.LozengeOracle(*size, thr, seed=seed, init=init))
+    elif len(weights) == 6:
+        dom = tl.domain(tl.TL_SIXVERTEX, n=size)
+        w = tl.weights(tl.TL_W_SIXVERTEX6, *[float(x) for x in weights])
+        thr = oracle.table_from_ratios(oracle.sixv_ratios6(*weights), False)
+        make = lambda seed: (lambda init: oracle.SixVertexOracle(size, thr, seed=seed, init=init))
     else:
         dom = tl.domain(tl.TL_SIXVERTEX, n=size)
         a2, b2, c2 = weights
@@ -37,11 +45,13 @@ def case(tl, kind, size, weights):
 
 CASES = [("domino", 1, "uniform", {}), ("domino", 2, "uniform", {}), ("domino", 7, "uniform", {}),
          ("domino", 24, "two", {}), ("domino", 32, "uniform", {"tile_rows": 8, "sweeps_per_launch": 5}),
+         ("domino", 12, "volume", {}),
          ("lozenge", (3, 4, 5), Fraction(1, 2), {}), ("lozenge", (12, 10, 8), Fraction(1999, 2000), {}),
          ("lozenge", (30, 30, 30), Fraction(1), {"tile_rows": 16, "sweeps_per_launch": 3}),
          ("sixv", 5, (1, 1, 1), {}), ("sixv", 16, (1, 1, 2), {}),
          ("sixv", 48, (1, 1, 1), {"tile_rows": 16, "sweeps_per_launch": 4}),
-         ("sixv", 40, (1, 1, 4), {"tile_rows": 12, "sweeps_per_launch": 2})]
+         ("sixv", 40, (1, 1, 4), {"tile_rows": 12, "sweeps_per_launch": 2}),
+         ("sixv", 20, (1, 2, 1, 1, 4, 4), {})]
 
 
 @pytest.mark.parametrize("kind,size,weights,opts", CASES, ids=["%s-%s-%s" % c[:3] for c in CASES])
@@ -89,6 +99,11 @@ def test_cftp_rejects_non_monotone_settings():
         s.cftp(10)
     assert e.value.status == tl.TL_EINVAL
     s = tl.Sampler(tl.domain(tl.TL_SIXVERTEX, n=6), tl.weights(tl.TL_W_SIXVERTEX, 4.0, 1.0, 1.0), 1)
+    with pytest.raises(tl.TlError) as e:
+        s.cftp(10)
+    assert e.value.status == tl.TL_EINVAL
+    # six weights that do not keep the order (a2 > c2)
+    s = tl.Sampler(tl.domain(tl.TL_SIXVERTEX, n=6), tl.weights(tl.TL_W_SIXVERTEX6, 1.0, 5.0, 1.0, 1.0, 1.0, 1.0), 1)
     with pytest.raises(tl.TlError) as e:
         s.cftp(10)
     assert e.value.status == tl.TL_EINVAL

@@ -1,5 +1,7 @@
 """GPU parity for the domino sampler: the HIP path against the oracle, bit for
 bit on the canonical export and the integer observables (Aztec diamonds)."""
+from fractions import Fraction
+
 import numpy as np
 import pytest
 
@@ -241,3 +243,24 @@ def test_reset_and_timing():
     assert s.hash() == h1
     o2 = s.observables()
     assert (o1["bin_sum"] == o2["bin_sum"]).all() and o2["samples"] == 4
+
+
+@pytest.mark.parametrize("n,q,metro,kw", [(9, (Fraction(5, 4), Fraction(2, 3)), False, {}),
+                                          (40, (Fraction(20), Fraction(1, 20)), False, {}),
+                                          (150, (Fraction(5, 4), Fraction(2, 3)), True, {}),
+                                          (300, (Fraction(20), Fraction(1, 20)), False,
+                                           {"tile_rows": 16, "sweeps_per_launch": 7})])
+def test_volume_weights_parity(n, q, metro, kw):
+    # volume weights q on black and q' on white vertices (the paper's Aztec
+    # example uses 20 and 1/20)
+    tl = need_gpu()
+    say("domino volume weights n=%d q=%s metro=%s" % (n, q, metro))
+    w = tl.weights(tl.TL_W_VOLUME_BW, q[0].numerator, q[0].denominator, q[1].numerator, q[1].denominator)
+    w.rule = tl.TL_METROPOLIS if metro else tl.TL_HEATBATH
+    s = tl.Sampler(tl.domain(tl.TL_DOMINO, n=n), w, 31, tl.options(**kw))
+    thr = oracle.table_from_ratios(oracle.domino_ratios("volume", *q), metro)
+    o = oracle.DominoOracle(n, thr, metropolis=metro, seed=31)
+    assert s.thresholds() == list(o.thr)
+    s.sweep(17)
+    o.sweep(17)
+    assert (s.export() == o.export()).all()

@@ -181,3 +181,25 @@ def test_sixvertex_1024_one_sweep_sampled(w2, metro):
     o.sweep(1)
     assert (s.export() == o.export()).all()
     assert s.hash() == oracle.canonical_hash(o.export())
+
+
+SIX = (1, 2, Fraction(3, 2), Fraction(1, 2), 1, 3)   # a1, a2, b1, b2, c1, c2
+
+
+@pytest.mark.parametrize("N,metro,kw", [(9, False, {}), (9, True, {}), (64, False, {}), (130, True, {}),
+                                        (300, False, {"tile_rows": 12, "sweeps_per_launch": 5}),
+                                        (77, True, {"kernel": 1})])
+def test_sixvertex_six_weights_parity(N, metro, kw):
+    # six distinct vertex weights: thresholds by the whole mask of diagonals
+    tl = need_gpu()
+    say("six-vertex six weights N=%d metro=%s %s" % (N, metro, kw))
+    w = tl.weights(tl.TL_W_SIXVERTEX6, *[float(x) for x in SIX])
+    w.rule = tl.TL_METROPOLIS if metro else tl.TL_HEATBATH
+    s = tl.Sampler(tl.domain(tl.TL_SIXVERTEX, n=N), w, 19, tl.options(**kw))
+    thr = oracle.table_from_ratios(oracle.sixv_ratios6(*SIX), metro)
+    o = oracle.SixVertexOracle(N, thr, metropolis=metro, seed=19)
+    assert s.thresholds() == list(o.thr)
+    for k in (1, 6):
+        s.sweep(k)
+        o.sweep(k)
+        assert (s.export() == o.export()).all()

@@ -227,3 +227,109 @@ def test_observables_accumulate_per_sample():
     assert int(d.samples[0]) == 4
     assert int(d.scalar_sum[0]) == tot
     assert (d.bin_sum == acc).all()
+
+
+# ---------------------------------------------------------------- volume weights
+# Face (X, Y) of the box is black iff X + Y is even, i.e. iff its south-west
+# corner is a black vertex.  With this colouring Thurston's rule makes the
+# vertical pair the higher state at black vertices (the up direction of the
+# rotations, reading C4).
+BLACK_FACE_PARITY = 0
+
+
+def face_heights(f, n):
+    """Height function of a tiling (canonical export, row 0 southmost) by
+    Thurston's rule (Section 1.1, Figure "hf"): along an edge with a black face
+    on its left the height rises by 1, or falls by 3 if a domino covers the
+    edge; with a white face on the left the signs flip.  Returns {vertex: h}
+    with h = 0 at the south corner (vertex (n - 1, 0))."""
+    W = 2 * n
+    inside = lambda X, Y: 0 <= X < W and 0 <= Y < W and f[Y, X] != 255
+    black = lambda X, Y: (X + Y) % 2 == BLACK_FACE_PARITY
+
+    def step(u, v):
+        (X, Y), (X2, Y2) = u, v
+        if X2 == X + 1:        # east: left face (X, Y), right face (X, Y-1)
+            left, right = (X, Y), (X, Y - 1)
+            crossed = inside(*left) and inside(*right) and f[Y - 1, X] == 0
+        elif Y2 == Y + 1:      # north: left face (X-1, Y), right face (X, Y)
+            left, right = (X - 1, Y), (X, Y)
+            crossed = inside(*left) and inside(*right) and f[Y, X - 1] == 2
+        else:
+            back = step(v, u)
+            return None if back is None else -back
+        if not (inside(*left) or inside(*right)):
+            return None
+        d = 1 if black(*left) else -1
+        return -3 * d if crossed else d
+
+    h = {(n - 1, 0): 0}
+    todo = [(n - 1, 0)]
+    while todo:
+        u = todo.pop()
+        X, Y = u
+        for v in ((X + 1, Y), (X - 1, Y), (X, Y + 1), (X, Y - 1)):
+            dh = step(u, v)
+            if dh is None:
+                continue
+            if v in h:
+                assert h[v] == h[u] + dh, "inconsistent heights"
+            else:
+                h[v] = h[u] + dh
+                todo.append(v)
+    return h
+
+
+def volume_thr(a, b, metropolis=False):
+    return oracle.table_from_ratios(oracle.domino_ratios("volume", a, b), metropolis)
+
+
+def test_height_rule_and_rotation_sign():
+    # every rotation changes the height at its own vertex only, by 4, and the
+    # vertical pair is the higher state exactly at black (x+y even) vertices
+    n = 3
+    faces = enumerate_tilings(n)
+    d = chain(n, uniform_thr())
+    checked = 0
+    for f in faces.values():
+        h0 = face_heights(f, n)
+        for (X, Y) in d.sites():
+            d.load(f)
+            if not d.flip(X, Y, 1):
+                continue
+            h1 = face_heights(d.export(), n)
+            diff = {v: h1[v] - h0[v] for v in h0 if h1[v] != h0[v]}
+            even = (X - n + Y - n) % 2 == 0
+            assert diff == {(X, Y): 4 if even else -4}
+            checked += 1
+    assert checked > 50
+
+
+def volume_law(n, a, b):
+    faces = enumerate_tilings(n)
+    w = {}
+    for k, f in faces.items():
+        h = face_heights(f, n)
+        p = Fraction(1)
+        for (X, Y), v in h.items():
+            q = a if (X + Y - 2 * n) % 2 == 0 else b
+            p *= q ** v
+        w[k] = p
+    Z = sum(w.values())
+    return {k: float(v / Z) for k, v in w.items()}
+
+
+@pytest.mark.parametrize("metropolis", [False, True])
+@pytest.mark.parametrize("n,samples,thin", [(2, 8000, 8), (3, 16000, 12)])
+def test_volume_weights_stationary(n, samples, thin, metropolis):
+    a, b = Fraction(5, 4), Fraction(2, 3)
+    probs = volume_law(n, a, b)
+    ch = chain(n, volume_thr(a, b, metropolis), metropolis=metropolis, seed=29)
+    assert chi_square_pvalue(ch, probs, samples, thin) > 1e-3
+
+
+def test_volume_weights_colours_matter():
+    a, b = Fraction(5, 4), Fraction(2, 3)
+    probs = volume_law(3, b, a)   # black and white weights swapped
+    ch = chain(3, volume_thr(a, b), seed=29)
+    assert chi_square_pvalue(ch, probs, 16000, 12) < 1e-6

@@ -195,3 +195,70 @@ def test_order_independence_and_resume():
     finally:
         oracle.set_reverse_order(False)
     assert (a.export() == b.export()).all()
+
+
+# ------------------------------------------------------ six vertex weights
+def vertex_weight_product6(h, wts):
+    """prod over the N x N vertices of the weight of the vertex type read off
+    the edges (a1 none, a2 all four, b1 left+right, b2 bottom+top, c1
+    bottom+left, c2 right+top); wts = (a1, a2, b1, b2, c1, c2)."""
+    vert, horz = edges_from_heights(h)
+    N = h.shape[0] - 1
+    kinds = {(False, False, False, False): 0, (True, True, True, True): 1, (True, True, False, False): 2,
+             (False, False, True, True): 3, (True, False, True, False): 4, (False, True, False, True): 5}
+    w = Fraction(1)
+    for j in range(1, N + 1):
+        for i in range(1, N + 1):
+            e = (bool(horz[j - 1, i - 1]), bool(horz[j - 1, i]), bool(vert[j - 1, i - 1]), bool(vert[j, i - 1]))
+            w *= Fraction(wts[kinds[e]])
+    return w
+
+
+WTS6 = (1, 2, Fraction(3, 2), Fraction(1, 2), 1, 3)
+
+
+def test_six_weights_reduce_to_three():
+    for a, b, c in ((1, 1, 1), (2, 3, 5), (Fraction(1, 2), 3, 7)):
+        assert oracle.sixv_ratios6(a, a, b, b, c, c) == oracle.sixv_ratios(a, b, c * c)
+
+
+def test_six_weights_enter_through_products():
+    # a corner of a flipped face moves between two types whose weights
+    # multiply to a1 a2, b1 b2 or c1 c2: only those products matter
+    base = oracle.sixv_ratios6(*WTS6)
+    a1, a2, b1, b2, c1, c2 = [Fraction(x) for x in WTS6]
+    for x, y, z in ((Fraction(1, 3), 5, Fraction(7, 2)), (2, Fraction(1, 9), 1)):
+        assert oracle.sixv_ratios6(x, a1 * a2 / x, y, b1 * b2 / y, z, c1 * c2 / z) == base
+    assert oracle.sixv_ratios6(2, 1, 1, 1, 1, 1) != oracle.sixv_ratios6(1, 1, 1, 1, 1, 1)
+
+
+def test_six_weight_table_matches_whole_configurations():
+    # every flip of every DWBC N = 4 state: the ratio of the two full
+    # configuration weights equals the table entry of the flip's mask
+    R = oracle.sixv_ratios6(*WTS6)
+    states = enumerate_states(4)
+    seen = set()
+    for h in states.values():
+        for J in range(1, 4):
+            for I in range(1, 4):
+                m = h[J, I + 1]
+                if not (h[J, I - 1] == m and h[J + 1, I] == m and h[J - 1, I] == m):
+                    continue
+                mask = sum(1 << k for k, (dI, dJ) in enumerate(((1, 1), (-1, 1), (-1, -1), (1, -1)))
+                           if h[J + dJ, I + dI] == m + 1)
+                up, down = h.copy(), h.copy()
+                up[J, I], down[J, I] = m + 1, m - 1
+                assert vertex_weight_product6(up, WTS6) / vertex_weight_product6(down, WTS6) == R[mask]
+                seen.add(mask)
+    assert len(seen) >= 8
+
+
+@pytest.mark.parametrize("metropolis", [False, True])
+def test_stationary_six_weights(metropolis):
+    states = enumerate_states(4)
+    w = {k: vertex_weight_product6(h, WTS6) for k, h in states.items()}
+    Z = sum(w.values())
+    probs = {k: float(v / Z) for k, v in w.items()}
+    t6 = oracle.table_from_ratios(oracle.sixv_ratios6(*WTS6), metropolis)
+    ch = oracle.SixVertexOracle(4, t6, metropolis=metropolis, seed=43)
+    assert chi_square_pvalue(ch, probs, 12000, 8) > 1e-3
