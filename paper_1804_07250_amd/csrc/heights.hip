@@ -480,51 +480,90 @@ __global__ void height_export_kernel(const uint32_t *pl, size_t PS, uint32_t RS,
     }
 }
 
-// Per-cell observables summed into bins of B x B cells, one thread per cell
-// row; counts are flushed with one atomic per bin run.
-__global__ void height_observe_kernel(const uint32_t *pl, size_t PS, uint32_t RS, uint32_t rows, Geo geo, uint32_t B,
-                                      uint32_t bins_x, unsigned long long *bins)
+// Six-vertex observable: the type-c vertices (both diagonal pairs of faces
+// around the vertex equal) counted into bins of B x B cells (cell (i-1, j-1) =
+// vertex (i, j), 1 <= i, j <= N).  One thread per vertex row j and word w: the
+// word holds vertices i = 2k+1 (faces I = 2k, 2k+1 from planes 0 and 1) and
+// i = 2k+2 (faces 2k+1, 2k+2: plane 1 and plane 0 shifted by one site) for
+// k = 32w .. 32w+31, so the test runs on whole words; the counts go to the
+// bins by popcounts of the runs of cells that share a bin.
+__global__ void sixv_observe_kernel(const uint32_t *pl, size_t PS, uint32_t RS, int N, uint32_t nw, uint32_t B,
+                                    uint32_t bins_x, unsigned long long *bins)
 {
-    const uint32_t y = blockIdx.x * blockDim.x + threadIdx.x;
-    unsigned long long acc = 0;
-    int cur_bin = -1;
-    auto add = [&](int X, int Y, unsigned long long q) {
-        const int b = (Y / (int)B) * (int)bins_x + X / (int)B;
-        if (b != cur_bin) {
-            if (cur_bin >= 0 && acc) atomicAdd(&bins[cur_bin], acc);
-            cur_bin = b;
-            acc = 0;
-        }
-        acc += q;
-    };
-    if (geo.model == TL_LOZENGE) {
-        if (y >= rows) return;
-        const int Y = (int)y;
-        const int xs = loz_xs(geo, Y), xe = loz_xe(geo, Y);
-        int H = loz_hmin(geo, xs, Y);
-        uint32_t prev = hbit(pl, PS, RS, (uint32_t)xs % 3u, y, (uint32_t)xs / 3u);
-        for (int X = xs; X <= xe; ++X) {
-            if (X > xs) {
-                const uint32_t bx = hbit(pl, PS, RS, (uint32_t)X % 3u, y, (uint32_t)X / 3u);
-                H -= (int)(bx ^ prev);
-                prev = bx;
-            }
-            add(X, Y, (unsigned long long)(H - loz_hmin(geo, X, Y)));
-        }
-    } else {
-        // vertex row j (1..N) between face rows j-1 and j; cell (i-1, j-1)
-        const int j = (int)y + 1, N = geo.N;
-        if (j > N) return;
-        for (int i = 1; i <= N; ++i) {
-            const uint32_t a00 = hbit(pl, PS, RS, (uint32_t)(i - 1) & 1u, (uint32_t)(j - 1), (uint32_t)(i - 1) >> 1);
-            const uint32_t a11 = hbit(pl, PS, RS, (uint32_t)i & 1u, (uint32_t)j, (uint32_t)i >> 1);
-            const uint32_t a10 = hbit(pl, PS, RS, (uint32_t)i & 1u, (uint32_t)(j - 1), (uint32_t)i >> 1);
-            const uint32_t a01 = hbit(pl, PS, RS, (uint32_t)(i - 1) & 1u, (uint32_t)j, (uint32_t)(i - 1) >> 1);
-            // both diagonal pairs equal (same parity => equal residual bit <=> equal height)
-            add(i - 1, j - 1, (a00 == a11 && a10 == a01) ? 1ull : 0ull);
-        }
+    const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t w = gid % nw, j = gid / nw + 1u;
+    if (j > (uint32_t)N) return;
+    const uint32_t *r0 = pl + (size_t)(j - 1) * RS + 4, *r1 = pl + (size_t)j * RS + 4;   // plane 0 rows
+    const uint32_t *q0 = r0 + PS, *q1 = r1 + PS;                                          // plane 1 rows
+    const uint32_t p0lo = r0[w], p0hi = r1[w], p1lo = q0[w], p1hi = q1[w];
+    const uint32_t p0lo_s = (r0[w] >> 1) | (r0[w + 1] << 31), p0hi_s = (r1[w] >> 1) | (r1[w + 1] << 31);
+    // i = 2k+1: a00 = p0[j-1][k], a11 = p1[j][k], a10 = p1[j-1][k], a01 = p0[j][k]
+    uint32_t c_odd = ~(p0lo ^ p1hi) & ~(p1lo ^ p0hi);
+    // i = 2k+2: a00 = p1[j-1][k], a11 = p0[j][k+1], a10 = p0[j-1][k+1], a01 = p1[j][k]
+    uint32_t c_even = ~(p1lo ^ p0hi_s) & ~(p0lo_s ^ p1hi);
+    c_odd &= range_mask((int)w, 0, (N - 1) / 2);
+    c_even &= N >= 2 ? range_mask((int)w, 0, (N - 2) / 2) : 0u;
+    // cells x = i - 1: x = 2k (odd i), x = 2k + 1 (even i), k = 32w + b
+    const uint32_t by = (j - 1) / B, x_lo = 64u * w, x_hi = x_lo + 64u;
+    for (uint32_t x = x_lo; x < x_hi;) {
+        const uint32_t nxt = (x / B + 1u) * B < x_hi ? (x / B + 1u) * B : x_hi;
+        // bits b with 2(32w + b) in [x, nxt) and 2(32w + b) + 1 in [x, nxt)
+        const uint32_t e0 = (x - x_lo + 1u) / 2u, e1 = (nxt - x_lo + 1u) / 2u;   // even cells 2b in [x, nxt)
+        const uint32_t o0 = (x - x_lo) / 2u, o1 = (nxt - x_lo) / 2u;             // odd cells 2b+1 in [x, nxt)
+        auto bits = [](uint32_t lo, uint32_t hi) -> uint32_t {
+            if (lo >= hi) return 0u;
+            const uint32_t up = hi >= 32u ? ~0u : ((1u << hi) - 1u);
+            return up & ~((1u << lo) - 1u);
+        };
+        const uint32_t cnt = (uint32_t)__popc(c_odd & bits(e0, e1)) + (uint32_t)__popc(c_even & bits(o0, o1));
+        if (cnt) atomicAdd(&bins[(size_t)by * bins_x + x / B], (unsigned long long)cnt);
+        x = nxt;
     }
-    if (cur_bin >= 0 && acc) atomicAdd(&bins[cur_bin], acc);
+}
+
+// Lozenge observable: H - H_min per vertex, summed into bins of B x B cells.
+// One wavefront per row Y: H falls by one across every change of the residual
+// bit along the row, so each lane counts the changes in its chunk of X, a
+// wavefront prefix sum gives every chunk its starting height, and the lanes
+// accumulate their chunk into per-row bins in LDS (flushed once per bin).
+__global__ void __launch_bounds__(64) loz_observe_kernel(const uint32_t *pl, size_t PS, uint32_t RS, Geo geo,
+                                                         uint32_t B, uint32_t bins_x, unsigned long long *bins)
+{
+    extern __shared__ unsigned long long rowbin[];
+    const int Y = (int)blockIdx.x, lane = (int)threadIdx.x;
+    for (uint32_t i = (uint32_t)lane; i < bins_x; i += 64u) rowbin[i] = 0ull;
+    __syncthreads();
+    const int xs = loz_xs(geo, Y), xe = loz_xe(geo, Y);
+    const int C = (xe - xs + 1 + 63) / 64;
+    const int x0 = xs + lane * C, x1 = x0 + C - 1 < xe ? x0 + C - 1 : xe;
+    auto bit = [&](int X) { return hbit(pl, PS, RS, (uint32_t)X % 3u, (uint32_t)Y, (uint32_t)X / 3u); };
+    int drops = 0;   // changes at X in [x0, x1], X > xs
+    for (int X = x0 > xs ? x0 : xs + 1; X <= x1; ++X) drops += (int)(bit(X) ^ bit(X - 1));
+    int before = drops;   // inclusive scan over the lanes
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int v = __shfl_up(before, off, 64);
+        if (lane >= off) before += v;
+    }
+    before -= drops;
+    int H = loz_hmin(geo, xs, Y) - before;
+    unsigned long long acc = 0ull;
+    int cur = -1;
+    for (int X = x0; X <= x1; ++X) {
+        if (X > xs) H -= (int)(bit(X) ^ bit(X - 1));
+        const int b = X / (int)B;
+        if (b != cur) {
+            if (cur >= 0 && acc) atomicAdd(&rowbin[cur], acc);
+            cur = b;
+            acc = 0ull;
+        }
+        acc += (unsigned long long)(H - loz_hmin(geo, X, Y));
+    }
+    if (cur >= 0 && acc) atomicAdd(&rowbin[cur], acc);
+    __syncthreads();
+    const size_t row = (size_t)(Y / (int)B) * bins_x;
+    for (uint32_t i = (uint32_t)lane; i < bins_x; i += 64u)
+        if (rowbin[i]) atomicAdd(&bins[row + i], rowbin[i]);
 }
 
 Geo geo_of(const HeightDev &d) { return Geo{d.model, d.a, d.b, d.c, d.N}; }
@@ -677,9 +716,15 @@ hipError_t height_export(const HeightDev &d, int32_t *dev, hipStream_t s)
 
 hipError_t height_observe(const HeightDev &d, uint32_t B, uint32_t bins_x, unsigned long long *bins, hipStream_t s)
 {
-    dim3 block(64), grid((d.rows + 63) / 64);
-    hipLaunchKernelGGL(height_observe_kernel, grid, block, 0, s, d.planes, d.PS, d.RS, d.rows, geo_of(d), B, bins_x,
-                       bins);
+    if (d.model == TL_LOZENGE) {
+        if ((size_t)bins_x * 8u > 64u * 1024u) return hipErrorInvalidConfiguration;
+        hipLaunchKernelGGL(loz_observe_kernel, dim3(d.rows), dim3(64), bins_x * 8u, s, d.planes, d.PS, d.RS,
+                           geo_of(d), B, bins_x, bins);
+    } else {
+        const uint32_t nw = 4u * d.ng, threads = nw * (uint32_t)d.N;
+        hipLaunchKernelGGL(sixv_observe_kernel, dim3((threads + 255) / 256), dim3(256), 0, s, d.planes, d.PS, d.RS,
+                           d.N, nw, B, bins_x, bins);
+    }
     return hipGetLastError();
 }
 

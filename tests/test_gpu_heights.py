@@ -203,3 +203,30 @@ def test_sixvertex_six_weights_parity(N, metro, kw):
         s.sweep(k)
         o.sweep(k)
         assert (s.export() == o.export()).all()
+
+
+@pytest.mark.parametrize("B", [1, 3, 16, 64, 100])
+def test_lozenge_volume_bins(B):
+    tl = need_gpu()
+    a, b, c = 37, 20, 45
+    s = loz_sampler(tl, a, b, c, seed=23, q=Fraction(3, 2), obs_every=3, obs_bin=B)
+    o = loz_oracle(a, b, c, seed=23, q=Fraction(3, 2), obs_every=3, bin_=B)
+    s.sweep(10)
+    o.sweep(10)
+    obs = s.observables()
+    assert obs["samples"] == int(o.samples[0]) == 3
+    assert (obs["bin_sum"].reshape(-1) == o.bin_sum).all()
+    assert obs["scalar_now"] == o.observe(1)[0]
+
+
+@pytest.mark.parametrize("N,B", [(1, 1), (2, 1), (33, 5), (130, 32), (130, 64), (77, 200), (64, 3)])
+def test_sixvertex_c_vertex_bins(N, B):
+    tl = need_gpu()
+    s = sixv_sampler(tl, N, seed=29, w2=(1, 1, 2), obs_every=2, obs_bin=B)
+    o = sixv_oracle(N, seed=29, w2=(1, 1, 2), obs_every=2, bin_=B)
+    s.sweep(7)
+    o.sweep(7)
+    obs = s.observables()
+    assert obs["samples"] == int(o.samples[0]) == 3
+    assert (obs["bin_sum"].reshape(-1) == o.bin_sum).all()
+    assert obs["scalar_now"] == o.observe(1)[0]
