@@ -1,8 +1,9 @@
 // Batched form: thousands of independent domino chains (Aztec diamonds of
 // uneven orders) advanced together by one persistent launch per call, replayed
-// from a captured hipGraph.  Chains are handed to work-groups longest first
-// (LPT order) through an atomic counter; each chain lives in LDS for the whole
-// call.  Every draw is keyed by (chain seed, sweep, colour, site), so a chain
+// from a captured hipGraph.  Chains are packed into bundles (several small
+// chains per work-group, first-fit over the chains longest first) and the
+// bundles are handed to work-groups costliest first (LPT order) through an
+// atomic counter; each chain lives in LDS for the whole call.  Every draw is keyed by (chain seed, sweep, colour, site), so a chain
 // gives the same tiling in the batch as alone.
 #include <algorithm>
 #include <memory>
@@ -26,7 +27,14 @@ struct tl_batch {
     uint32_t *planes = nullptr;
     std::vector<tl::BatchChain> chains;
     tl::BatchChain *d_chains = nullptr;
-    uint32_t *d_order = nullptr;
+    std::vector<uint32_t> order;   // chains, longest first
+    // bundles for each work-group size used so far (built before any capture)
+    struct BundleSet {
+        uint32_t threads = 0, count = 0;
+        tl::BatchBundle *d_bundles = nullptr;
+        uint32_t *d_members = nullptr;
+    };
+    std::vector<BundleSet> sets;
     uint32_t *d_counter = nullptr;
     uint32_t lds_max = 0;
     uint32_t threads = 256;
@@ -68,7 +76,63 @@ tl_status drop_graph(tl_batch *b)
     return TL_OK;
 }
 
-uint32_t workgroups_for(const tl_batch *b, uint32_t threads)
+// Bundles for work-groups of `threads`: chains in LPT order go first-fit into
+// bundles of at most kBundleMax chains, `threads` (row, group) tasks and the
+// LDS of the largest chain; a chain with more tasks than threads is a bundle
+// alone.  Bundles are ordered by passes per colour step, then tasks.
+tl_status bundle_set(tl_batch *b, uint32_t threads, const tl_batch::BundleSet **out)
+{
+    for (const auto &st : b->sets)
+        if (st.threads == threads) {
+            *out = &st;
+            return TL_OK;
+        }
+    struct Open {
+        uint32_t tasks, lds;
+        std::vector<uint32_t> m;
+    };
+    std::vector<Open> open;
+    for (uint32_t ci : b->order) {
+        const tl::BatchChain &c = b->chains[ci];
+        const uint32_t tasks = c.n * c.ng, lds = c.lds_bytes;
+        bool placed = false;
+        if (tasks <= threads)
+            for (Open &o : open)
+                if (o.tasks + tasks <= threads && o.lds + lds <= b->lds_max && o.m.size() < tl::kBundleMax) {
+                    o.tasks += tasks;
+                    o.lds += lds;
+                    o.m.push_back(ci);
+                    placed = true;
+                    break;
+                }
+        if (!placed) open.push_back(Open{tasks, lds, {ci}});
+    }
+    auto passes = [&](const Open &o) { return (o.tasks + threads - 1) / threads; };
+    std::stable_sort(open.begin(), open.end(), [&](const Open &x, const Open &y) {
+        return passes(x) != passes(y) ? passes(x) > passes(y) : x.tasks > y.tasks;
+    });
+    std::vector<tl::BatchBundle> bundles;
+    std::vector<uint32_t> members;
+    for (const Open &o : open) {
+        bundles.push_back(tl::BatchBundle{(uint32_t)members.size(), (uint32_t)o.m.size(), o.tasks, 0u});
+        members.insert(members.end(), o.m.begin(), o.m.end());
+    }
+    tl_batch::BundleSet st;
+    st.threads = threads;
+    st.count = (uint32_t)bundles.size();
+    if (hipMalloc(&st.d_bundles, bundles.size() * sizeof(tl::BatchBundle)) != hipSuccess ||
+        hipMalloc(&st.d_members, members.size() * sizeof(uint32_t)) != hipSuccess) {
+        if (st.d_bundles) (void)hipFree(st.d_bundles);
+        return tl::fail(TL_ENOMEM, "batch bundle tables");
+    }
+    TL_HIP(hipMemcpy(st.d_bundles, bundles.data(), bundles.size() * sizeof(tl::BatchBundle), hipMemcpyHostToDevice));
+    TL_HIP(hipMemcpy(st.d_members, members.data(), members.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    b->sets.push_back(st);
+    *out = &b->sets.back();
+    return TL_OK;
+}
+
+uint32_t workgroups_for(const tl_batch *b, uint32_t threads, uint32_t bundles)
 {
     // as many resident work-groups per CU as LDS and threads allow
     uint32_t per_cu = (160u * 1024u) / (b->lds_max + 64u);
@@ -76,7 +140,7 @@ uint32_t workgroups_for(const tl_batch *b, uint32_t threads)
     if (per_cu > by_threads) per_cu = by_threads;
     if (per_cu < 1u) per_cu = 1u;
     uint32_t wg = b->cus * per_cu;
-    if (wg > (uint32_t)b->count) wg = (uint32_t)b->count;
+    if (wg > bundles) wg = bundles;
     return wg;
 }
 
@@ -93,11 +157,16 @@ tl_status init_all(tl_batch *b)
     return TL_OK;
 }
 
+// The bundle set for `threads` must exist (bundle_set) before a capture.
 tl_status launch_direct(tl_batch *b, uint32_t nsweeps, uint32_t threads, tl::Timing *tm)
 {
-    TL_HIP(tl::domino_batch_sweeps(b->d_chains, b->d_order, (uint32_t)b->count, b->d_counter, b->planes, nsweeps,
-                                   b->T, b->metro ? 1 : 0, threads, workgroups_for(b, threads), b->lds_max,
-                                   b->stream, tm));
+    const tl_batch::BundleSet *st = nullptr;
+    for (const auto &x : b->sets)
+        if (x.threads == threads) st = &x;
+    if (!st) return tl::fail(TL_EINVAL, "no bundles for %u threads", threads);
+    TL_HIP(tl::domino_batch_sweeps(b->d_chains, st->d_bundles, st->d_members, st->count, b->d_counter, b->planes,
+                                   nsweeps, b->T, b->metro ? 1 : 0, threads,
+                                   workgroups_for(b, threads, st->count), b->lds_max, b->stream, tm));
     return TL_OK;
 }
 
@@ -164,18 +233,22 @@ tl_status tl_batch_create(int32_t n, const tl_domain *doms, const tl_weights *w,
     b->cus = (uint32_t)cus;
     if (hipMalloc(&b->planes, words * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&b->d_chains, n * sizeof(tl::BatchChain)) != hipSuccess ||
-        hipMalloc(&b->d_order, n * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&b->d_counter, sizeof(uint32_t)) != hipSuccess) {
         tl_batch_destroy(b.release());
         return tl::fail(TL_ENOMEM, "batch state allocation (%zu MB)", (size_t)(words * 4 >> 20));
     }
     // longest chains first
-    std::vector<uint32_t> order(n);
-    std::iota(order.begin(), order.end(), 0u);
-    std::stable_sort(order.begin(), order.end(),
+    b->order.resize(n);
+    std::iota(b->order.begin(), b->order.end(), 0u);
+    std::stable_sort(b->order.begin(), b->order.end(),
                      [&](uint32_t x, uint32_t y) { return b->chains[x].n > b->chains[y].n; });
-    TL_HIP(hipMemcpyAsync(b->d_order, order.data(), n * sizeof(uint32_t), hipMemcpyHostToDevice, b->stream));
     if (opt && opt->tile_rows) b->threads = opt->tile_rows;   // work-group size override
+    const tl_batch::BundleSet *set = nullptr;
+    st = bundle_set(b.get(), b->threads, &set);
+    if (st != TL_OK) {
+        tl_batch_destroy(b.release());
+        return st;
+    }
     st = init_all(b.get());
     if (st != TL_OK) {
         tl_batch_destroy(b.release());
@@ -198,6 +271,9 @@ tl_status tl_batch_autotune(tl_batch *b, uint32_t probe_sweeps, uint32_t *thread
     TL_HIP(hipEventCreate(&e0));
     TL_HIP(hipEventCreate(&e1));
     for (uint32_t th : cand) {
+        const tl_batch::BundleSet *set = nullptr;
+        tl_status sb = bundle_set(b, th, &set);
+        if (sb != TL_OK) return sb;
         TL_HIP(hipEventRecord(e0, b->stream));
         tl_status st = launch_direct(b, probe_sweeps, th, nullptr);
         if (st != TL_OK) return st;
@@ -229,6 +305,9 @@ tl_status tl_batch_sweep(tl_batch *b, uint64_t n)
     if (b->t + n > 0xFFFFFFFFull) return tl::fail(TL_EINVAL, "sweep counter would exceed 2^32");
     if (b->graph_q != (uint32_t)n) {
         drop_graph(b);
+        const tl_batch::BundleSet *set = nullptr;
+        tl_status sb = bundle_set(b, b->threads, &set);   // no allocation inside the capture
+        if (sb != TL_OK) return sb;
         TL_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
         tl_status st = launch_direct(b, (uint32_t)n, b->threads, nullptr);
         hipGraph_t g = nullptr;
@@ -275,7 +354,12 @@ tl_status tl_batch_info(const tl_batch *b, uint64_t *sites, uint64_t *state_byte
     if (sites) *sites = b->sites;
     if (state_bytes) *state_bytes = b->owner_bits / 8;
     if (threads) *threads = b->threads;
-    if (workgroups) *workgroups = workgroups_for(b, b->threads);
+    if (workgroups) {
+        uint32_t nb = (uint32_t)b->count;
+        for (const auto &x : b->sets)
+            if (x.threads == b->threads) nb = x.count;
+        *workgroups = workgroups_for(b, b->threads, nb);
+    }
     return TL_OK;
 }
 
@@ -344,7 +428,10 @@ tl_status tl_batch_destroy(tl_batch *b)
     b->timing.release();
     if (b->planes) (void)hipFree(b->planes);
     if (b->d_chains) (void)hipFree(b->d_chains);
-    if (b->d_order) (void)hipFree(b->d_order);
+    for (auto &x : b->sets) {
+        if (x.d_bundles) (void)hipFree(x.d_bundles);
+        if (x.d_members) (void)hipFree(x.d_members);
+    }
     if (b->d_counter) (void)hipFree(b->d_counter);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
     delete b;

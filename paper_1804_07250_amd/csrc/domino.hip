@@ -392,64 +392,118 @@ __global__ void __launch_bounds__(1024) domino_items_kernel(const TileJob *__res
 }
 
 // ------------------------------------------------------------ batched chains
-// Persistent kernel over a list of independent chains (longest first).  A
-// work-group takes the next chain from an atomic counter, copies its whole
-// state into LDS (compact rows of 4*ng words, n rows, no padding), runs all
-// nsweeps sweeps there and writes it back.  Every work-group leaves the loop
-// once the counter passes the end of the list.
+// Persistent kernel over a list of bundles of independent chains (costliest
+// first).  A work-group takes the next bundle from an atomic counter, copies
+// the whole state of each member into LDS (compact rows of 4*ng words, n rows,
+// no padding, members back to back), runs all nsweeps sweeps there and writes
+// the members back.  Several small chains share a work-group, so a chain too
+// small to keep a CU busy no longer holds one alone.  Every work-group leaves
+// the loop once the counter passes the end of the list.
 __global__ void batch_reset_kernel(uint32_t *counter) { *counter = 0u; }
 
 template <int MODE>
-__global__ void __launch_bounds__(1024) domino_batch_kernel(BatchChain *chains, const uint32_t *order, uint32_t count,
+__global__ void __launch_bounds__(1024) domino_batch_kernel(BatchChain *chains, const BatchBundle *bundles,
+                                                            const uint32_t *members, uint32_t nbundles,
                                                             uint32_t *counter, uint32_t *planes, uint32_t nsweeps,
                                                             Thr Tall)
 {
     extern __shared__ uint32_t lds[];
     __shared__ uint32_t s_next;
+    __shared__ uint32_t s_first[kBundleMax + 1];   // first task of each member (prefix of n * ng)
+    __shared__ uint32_t s_off[kBundleMax];         // LDS word offset of each member
     const uint32_t tid = threadIdx.x, nt = blockDim.x;
     for (;;) {
         if (tid == 0) s_next = atomicAdd(counter, 1u);
         __syncthreads();
-        const uint32_t i = s_next;
+        const uint32_t bi = s_next;
         __syncthreads();
-        if (i >= count) return;
-        const uint32_t ci = order[i];
-        const BatchChain ch = chains[ci];
-        const uint32_t n = ch.n, ng = ch.ng, LRS = 4 * ng, LPS = n * LRS;
-        const uint32_t omega = (n + 1) & 1u;
-        uint32_t *g = planes + ch.offset;
-        const uint32_t items = 4 * n * ng;
-        for (uint32_t j = tid; j < items; j += nt) {
-            const uint32_t gg = j % ng, r = (j / ng) % n, p = j / (ng * n);
-            uint32_t v[4];
-            ld4(g + p * ch.PS + (size_t)r * ch.RS + 4 * gg, v);
-            st4(lds + p * LPS + r * LRS + 4 * gg, v);
+        if (bi >= nbundles) return;
+        const BatchBundle B = bundles[bi];
+        if (tid == 0) {
+            uint32_t task = 0, off = 0;
+            for (uint32_t k = 0; k < B.count; ++k) {
+                const BatchChain &ch = chains[members[B.first + k]];
+                s_first[k] = task;
+                s_off[k] = off;
+                task += ch.n * ch.ng;
+                off += 4u * ch.n * 4u * ch.ng;
+            }
+            s_first[B.count] = task;
         }
         __syncthreads();
-        const uint32_t tasks = n * ng;
-        for (uint32_t s = 0; s < nsweeps; ++s) {
-            const uint32_t t = ch.t + s;
-            for (uint32_t c = 0; c < 2; ++c) {
-                for (uint32_t task = tid; task < tasks; task += nt) {
-                    const uint32_t r = task / ng, gg = task % ng;
-                    uint32_t *pN = lds + r * LRS + 4 * gg;
-                    if (c == omega)
-                        owner_group<MODE>(pN, pN + LPS, pN + 2 * LPS, pN + 3 * LPS, r, gg, c, t, Tall, ch.key0,
-                                          ch.key1);
-                    else if (r + 1 < n)
-                        other_group<MODE>(pN, pN + 2 * LPS, pN + LPS + LRS, pN + 3 * LPS + LRS, r, gg, c, t, Tall,
-                                          ch.key0, ch.key1, gg + 1 < ng);
-                }
-                __syncthreads();
+        // load every member (compact rows: 4 ng words, n rows, 4 planes)
+        for (uint32_t k = 0; k < B.count; ++k) {
+            const BatchChain ch = chains[members[B.first + k]];
+            const uint32_t LRS = 4 * ch.ng, LPS = ch.n * LRS, items = 4 * ch.n * ch.ng;
+            const uint32_t *g = planes + ch.offset;
+            uint32_t *l = lds + s_off[k];
+            for (uint32_t j = tid; j < items; j += nt) {
+                const uint32_t gg = j % ch.ng, r = (j / ch.ng) % ch.n, p = j / (ch.ng * ch.n);
+                uint32_t v[4];
+                ld4(g + p * ch.PS + (size_t)r * ch.RS + 4 * gg, v);
+                st4(l + p * LPS + r * LRS + 4 * gg, v);
             }
         }
-        for (uint32_t j = tid; j < items; j += nt) {
-            const uint32_t gg = j % ng, r = (j / ng) % n, p = j / (ng * n);
-            uint32_t v[4];
-            ld4(lds + p * LPS + r * LRS + 4 * gg, v);
-            st4(g + p * ch.PS + (size_t)r * ch.RS + 4 * gg, v);
+        __syncthreads();
+        if (B.count == 1) {
+            // one chain, as many passes over its (row, group) tasks as needed
+            const BatchChain ch = chains[members[B.first]];
+            const uint32_t n = ch.n, ng = ch.ng, LRS = 4 * ng, LPS = n * LRS, omega = (n + 1) & 1u;
+            const uint32_t tasks = n * ng;
+            for (uint32_t s = 0; s < nsweeps; ++s) {
+                const uint32_t t = ch.t + s;
+                for (uint32_t c = 0; c < 2; ++c) {
+                    for (uint32_t task = tid; task < tasks; task += nt) {
+                        const uint32_t r = task / ng, gg = task % ng;
+                        uint32_t *pN = lds + r * LRS + 4 * gg;
+                        if (c == omega)
+                            owner_group<MODE>(pN, pN + LPS, pN + 2 * LPS, pN + 3 * LPS, r, gg, c, t, Tall, ch.key0,
+                                              ch.key1);
+                        else if (r + 1 < n)
+                            other_group<MODE>(pN, pN + 2 * LPS, pN + LPS + LRS, pN + 3 * LPS + LRS, r, gg, c, t, Tall,
+                                              ch.key0, ch.key1, gg + 1 < ng);
+                    }
+                    __syncthreads();
+                }
+            }
+        } else {
+            // several small chains side by side: one task per thread
+            const bool has = tid < s_first[B.count];
+            uint32_t k = 0;
+            while (has && k + 1 < B.count && tid >= s_first[k + 1]) ++k;
+            const BatchChain ch = chains[members[B.first + k]];
+            const uint32_t n = ch.n, ng = ch.ng, LRS = 4 * ng, LPS = n * LRS, omega = (n + 1) & 1u;
+            const uint32_t local = tid - s_first[k], r = local / ng, gg = local % ng;
+            uint32_t *pN = lds + s_off[k] + r * LRS + 4 * gg;
+            for (uint32_t s = 0; s < nsweeps; ++s) {
+                const uint32_t t = ch.t + s;
+                for (uint32_t c = 0; c < 2; ++c) {
+                    if (has) {
+                        if (c == omega)
+                            owner_group<MODE>(pN, pN + LPS, pN + 2 * LPS, pN + 3 * LPS, r, gg, c, t, Tall, ch.key0,
+                                              ch.key1);
+                        else if (r + 1 < n)
+                            other_group<MODE>(pN, pN + 2 * LPS, pN + LPS + LRS, pN + 3 * LPS + LRS, r, gg, c, t, Tall,
+                                              ch.key0, ch.key1, gg + 1 < ng);
+                    }
+                    __syncthreads();
+                }
+            }
         }
-        if (tid == 0) chains[ci].t = ch.t + nsweeps;
+        for (uint32_t k = 0; k < B.count; ++k) {
+            const uint32_t ci = members[B.first + k];
+            const BatchChain ch = chains[ci];
+            const uint32_t LRS = 4 * ch.ng, LPS = ch.n * LRS, items = 4 * ch.n * ch.ng;
+            uint32_t *g = planes + ch.offset;
+            const uint32_t *l = lds + s_off[k];
+            for (uint32_t j = tid; j < items; j += nt) {
+                const uint32_t gg = j % ch.ng, r = (j / ch.ng) % ch.n, p = j / (ch.ng * ch.n);
+                uint32_t v[4];
+                ld4(l + p * LPS + r * LRS + 4 * gg, v);
+                st4(g + p * ch.PS + (size_t)r * ch.RS + 4 * gg, v);
+            }
+            if (tid == 0) chains[ci].t = ch.t + nsweeps;
+        }
         __syncthreads();
     }
 }
@@ -705,9 +759,10 @@ hipError_t domino_items(const TileJob *jobs, const TileItem *items, uint32_t n_i
     return hipGetLastError();
 }
 
-hipError_t domino_batch_sweeps(BatchChain *chains, const uint32_t *order, uint32_t count, uint32_t *counter,
-                               uint32_t *planes, uint32_t nsweeps, const Thr &T, int metropolis, uint32_t threads,
-                               uint32_t workgroups, uint32_t lds_bytes, hipStream_t s, Timing *tm)
+hipError_t domino_batch_sweeps(BatchChain *chains, const BatchBundle *bundles, const uint32_t *members,
+                               uint32_t nbundles, uint32_t *counter, uint32_t *planes, uint32_t nsweeps, const Thr &T,
+                               int metropolis, uint32_t threads, uint32_t workgroups, uint32_t lds_bytes,
+                               hipStream_t s, Timing *tm)
 {
     if (threads == 0 || threads > 1024 || (threads & 63) || lds_bytes > 160u * 1024u - 64u)
         return hipErrorInvalidConfiguration;
@@ -716,8 +771,8 @@ hipError_t domino_batch_sweeps(BatchChain *chains, const uint32_t *order, uint32
     if (e != hipSuccess) return e;
     auto k = T.uniform() ? domino_batch_kernel<kUniform>
                          : (metropolis ? domino_batch_kernel<kMetropolis> : domino_batch_kernel<kHeatBath>);
-    return launch(tm, 2 * nsweeps, k, dim3(workgroups), dim3(threads), lds_bytes, s, chains, order, count, counter,
-                  planes, nsweeps, T);
+    return launch(tm, 2 * nsweeps, k, dim3(workgroups), dim3(threads), lds_bytes, s, chains, bundles, members,
+                  nbundles, counter, planes, nsweeps, T);
 }
 
 hipError_t domino_export(const DominoDev &d, uint8_t *faces, hipStream_t s)

@@ -141,12 +141,20 @@ struct BatchChain {
     uint32_t lds_bytes;
     uint32_t pad;
 };
-// Advance every chain listed in order[0..count) by nsweeps sweeps: one
-// persistent launch; work-groups take chains from an atomic counter (reset by
+// A bundle: chains members[first .. first+count) that one work-group advances
+// together.  A bundle of several chains has at most as many (row, group)
+// tasks as the work-group has threads; a single chain may have more.
+constexpr uint32_t kBundleMax = 16;
+struct BatchBundle {
+    uint32_t first, count, tasks, pad;
+};
+// Advance every chain of bundles[0..nbundles) by nsweeps sweeps: one
+// persistent launch; work-groups take bundles from an atomic counter (reset by
 // a small kernel first, so the pair can be captured in a graph).
-hipError_t domino_batch_sweeps(BatchChain *chains, const uint32_t *order, uint32_t count, uint32_t *counter,
-                               uint32_t *planes, uint32_t nsweeps, const Thr &T, int metropolis, uint32_t threads,
-                               uint32_t workgroups, uint32_t lds_bytes, hipStream_t s, Timing *tm = nullptr);
+hipError_t domino_batch_sweeps(BatchChain *chains, const BatchBundle *bundles, const uint32_t *members,
+                               uint32_t nbundles, uint32_t *counter, uint32_t *planes, uint32_t nsweeps, const Thr &T,
+                               int metropolis, uint32_t threads, uint32_t workgroups, uint32_t lds_bytes,
+                               hipStream_t s, Timing *tm = nullptr);
 
 // ------------------------------------------------------ height-function models
 // Bit-planes of a 1-bit height residual: plane p, row y, word w at
