@@ -55,7 +55,7 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
 //
 // Contexts: site (w, b) is in context i iff bit b of cm[i][w] is set; the masks
 // of one word partition (at least) the live sites.
-template <int NC>
+template <int NC, uint32_t kDecidePlanes = 1>
 __device__ __forceinline__ void decide128(uint32_t key0, uint32_t key1, uint32_t g, uint32_t r,
                                           uint32_t t, uint32_t c, const uint32_t (&T)[NC],
                                           const uint32_t (&cm)[NC][4], const uint32_t (&live)[4],
@@ -67,22 +67,31 @@ __device__ __forceinline__ void decide128(uint32_t key0, uint32_t key1, uint32_t
         eq[w] = live[w];
         lt[w] = 0u;
     }
-    for (uint32_t j = 0; j < 32u; ++j) {
+    // kDecidePlanes planes per iteration (a divisor of 32): their generator
+    // calls are independent, so they overlap; a plane past the last undecided
+    // site changes nothing.  Two pay off where the generator dominates (one
+    // context), one elsewhere.
+    static_assert(32u % kDecidePlanes == 0u, "planes per iteration divide 32");
+    for (uint32_t j0 = 0; j0 < 32u; j0 += kDecidePlanes) {
         if ((eq[0] | eq[1] | eq[2] | eq[3]) == 0u) break;
-        uint32_t R[4];
-        philox4x32_10(g, r, t, (j << 2) | c, key0, key1, R);
-        const uint32_t b = 31u - j;
-        const uint32_t below = (b == 0u) ? 0u : ((1u << b) - 1u);
+        uint32_t R[kDecidePlanes][4];
 #pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            uint32_t tb = 0u, nz = 0u;
+        for (uint32_t u = 0; u < kDecidePlanes; ++u) philox4x32_10(g, r, t, ((j0 + u) << 2) | c, key0, key1, R[u]);
 #pragma unroll
-            for (int i = 0; i < NC; ++i) {
-                if ((T[i] >> b) & 1u) tb |= cm[i][w];
-                if (T[i] & below) nz |= cm[i][w];
+        for (uint32_t u = 0; u < kDecidePlanes; ++u) {
+            const uint32_t b = 31u - (j0 + u);
+            const uint32_t below = (b == 0u) ? 0u : ((1u << b) - 1u);
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                uint32_t tb = 0u, nz = 0u;
+#pragma unroll
+                for (int i = 0; i < NC; ++i) {
+                    if ((T[i] >> b) & 1u) tb |= cm[i][w];
+                    if (T[i] & below) nz |= cm[i][w];
+                }
+                lt[w] |= eq[w] & tb & ~R[u][w];
+                eq[w] &= ~(tb ^ R[u][w]) & nz;
             }
-            lt[w] |= eq[w] & tb & ~R[w];
-            eq[w] &= ~(tb ^ R[w]) & nz;
         }
     }
 #pragma unroll

@@ -126,7 +126,7 @@ __device__ __forceinline__ void loz_decide(uint32_t k0, uint32_t k1, uint32_t g,
         for (int w = 0; w < 4; ++w) D[w] = ~R0[w];
     } else if (MODE == kHeatBath) {
         uint32_t T[1] = {Tall.v[0]}, cm[1][4] = {{~0u, ~0u, ~0u, ~0u}};
-        decide128<1>(k0, k1, g, r, t, c, T, cm, live, D);
+        decide128<1, 2>(k0, k1, g, r, t, c, T, cm, live, D);
     } else {
         uint32_t T[2] = {Tall.v[0], Tall.v[1]}, cm[2][4];
 #pragma unroll
@@ -134,7 +134,7 @@ __device__ __forceinline__ void loz_decide(uint32_t k0, uint32_t k1, uint32_t g,
             cm[0][w] = ~cur[w];
             cm[1][w] = cur[w];
         }
-        decide128<2>(k0, k1, g, r, t, c, T, cm, live, D);
+        decide128<2, 2>(k0, k1, g, r, t, c, T, cm, live, D);
     }
 }
 
