@@ -62,7 +62,7 @@ def lib():
         L.or_domino_array_len.argtypes = [ctypes.c_int]
         L.or_domino_vertex_state.argtypes = [ctypes.c_int, u8p, u8p, ctypes.c_int, ctypes.c_int]
         L.or_domino_brick.argtypes = [ctypes.c_int, u8p, u8p]
-        L.or_domino_from_faces.argtypes = [ctypes.c_int, u8p, u8p, u8p]
+        L.or_domino_from_faces.argtypes = [ctypes.c_int, u8p, u8p, u8p, ctypes.c_int]
         L.or_domino_to_faces.argtypes = [ctypes.c_int, u8p, u8p, u8p]
         L.or_domino_flip.argtypes = [ctypes.c_int, u8p, u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.or_domino_sweeps.argtypes = [ctypes.c_int, u8p, u8p, u32p, ctypes.c_int, ctypes.c_uint64,
@@ -294,10 +294,12 @@ class DominoOracle(_Chain):
                                  _p(f, ctypes.c_uint8))
         return f
 
-    def load(self, faces):
+    def load(self, faces, allow_uncovered=False):
+        """Load a canonical export; with allow_uncovered, faces of the diamond
+        marked 0xFF stay uncovered (a tiling of a region inside the diamond)."""
         f = np.ascontiguousarray(faces, dtype=np.uint8)
         rc = lib().or_domino_from_faces(self.n, _p(f, ctypes.c_uint8), _p(self.Tb, ctypes.c_uint8),
-                                        _p(self.Tw, ctypes.c_uint8))
+                                        _p(self.Tw, ctypes.c_uint8), int(allow_uncovered))
         if rc != 0:
             raise ValueError("not a domino tiling of the Aztec diamond")
 
@@ -474,3 +476,7 @@ def bin_density(bin_sum, samples, in_domain, bin_):
     m = (cnt > 0) & (samples > 0)
     out[m] = s[m] / (float(samples) * cnt[m])
     return out
+
+
+from .region import (DominoRegionOracle, Untileable, check_region, extremal_heights,  # noqa: E402
+                     extremal_tilings, region_embedding, region_heights, tiling_from_heights)

@@ -94,7 +94,7 @@ static int face_in(int n, int X, int Y)
     return abs(2 * X - 2 * n + 1) + abs(2 * Y - 2 * n + 1) <= 2 * n;
 }
 
-int or_domino_from_faces(int n, const uint8_t *faces, uint8_t *Tb, uint8_t *Tw)
+int or_domino_from_faces(int n, const uint8_t *faces, uint8_t *Tb, uint8_t *Tw, int allow_uncovered)
 {
     int W = 2 * n;
     memset(Tb, 0, (size_t)or_domino_array_len(n));
@@ -106,6 +106,8 @@ int or_domino_from_faces(int n, const uint8_t *faces, uint8_t *Tb, uint8_t *Tw)
                 if (d != 0xFF) return -1;
                 continue;
             }
+            /* a region inside the diamond: faces outside it stay uncovered */
+            if (allow_uncovered && d == 0xFF) continue;
             int PX = X + (d == 2) - (d == 3), PY = Y + (d == 0) - (d == 1);
             if (d > 3 || !face_in(n, PX, PY)) return -1;
             uint8_t back = faces[PY * W + PX];
@@ -151,7 +153,7 @@ void or_domino_brick(int n, uint8_t *Tb, uint8_t *Tw)
             faces[Y * W + X] = ((X - start) % 2 == 0) ? 2 : 3;
         }
     }
-    or_domino_from_faces(n, faces, Tb, Tw);
+    or_domino_from_faces(n, faces, Tb, Tw, 0);
     free(faces);
 }
 

@@ -57,7 +57,7 @@ extern int or_reverse_order;
 /* T_b and T_w each hold (2n+4) x (n+2) tilestates (see domino.c). */
 int  or_domino_array_len(int n);
 void or_domino_brick(int n, uint8_t *Tb, uint8_t *Tw);
-int  or_domino_from_faces(int n, const uint8_t *faces, uint8_t *Tb, uint8_t *Tw);
+int  or_domino_from_faces(int n, const uint8_t *faces, uint8_t *Tb, uint8_t *Tw, int allow_uncovered);
 void or_domino_to_faces(int n, const uint8_t *Tb, const uint8_t *Tw, uint8_t *faces);
 /* Tilestate s_v of box vertex (X, Y) (0 outside the box). */
 int  or_domino_vertex_state(int n, const uint8_t *Tb, const uint8_t *Tw, int X, int Y);
