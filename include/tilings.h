@@ -44,9 +44,11 @@ typedef enum {
 } tl_status;
 
 typedef enum { TL_DOMINO = 0, TL_LOZENGE = 1, TL_SIXVERTEX = 2 } tl_model;
-typedef enum { TL_AZTEC = 0, TL_HEXAGON = 1, TL_DWBC_SQUARE = 2 } tl_shape;
-/* Extremal start: domino MIN = all-horizontal brick tiling, MAX = all-vertical;
- * lozenge MIN = empty box, MAX = full box; six-vertex MIN = |I-J|, MAX = N-|I+J-N|. */
+typedef enum { TL_AZTEC = 0, TL_HEXAGON = 1, TL_DWBC_SQUARE = 2, TL_MASK = 3 } tl_shape;
+/* Extremal start: Aztec domino MIN = all-horizontal brick tiling, MAX = all-vertical;
+ * domino domain given by a mask: MIN = T_min, MAX = T_max of its height order (see
+ * TL_MASK below); lozenge MIN = empty box, MAX = full box; six-vertex MIN = |I-J|,
+ * MAX = N-|I+J-N|. */
 typedef enum { TL_INIT_MIN = 0, TL_INIT_MAX = 1 } tl_init;
 typedef enum { TL_HEATBATH = 0, TL_METROPOLIS = 1 } tl_rule;
 typedef enum {
@@ -65,14 +67,34 @@ typedef enum {
 /* Domain (Section 1.1 "domain"; Section 1.2):
  *   TL_DOMINO    + TL_AZTEC:       Aztec diamond of order n (faces [x,x+1]x[y,y+1]
  *                                  with |2x+1|+|2y+1| <= 2n), 1 <= n <= 16384;
+ *   TL_DOMINO    + TL_MASK:        any simply-connected domain (Section 1.1): the faces
+ *                                  (x, y) of a w x h box with mask[y*w + x] != 0, row 0
+ *                                  southmost; w, h >= 1, w + h <= 32768;
  *   TL_LOZENGE   + TL_HEXAGON:     hexagon with sides a, b, c >= 1, a+c and b+c <= 32767;
- *   TL_SIXVERTEX + TL_DWBC_SQUARE: N x N vertices, domain-wall boundary, 1 <= n <= 32767. */
+ *   TL_SIXVERTEX + TL_DWBC_SQUARE: N x N vertices, domain-wall boundary, 1 <= n <= 32767.
+ *
+ * TL_MASK.  The mask (host memory, h*w bytes) is read during tl_sampler_create
+ * only; the sampler keeps a copy.  The domain must be non-empty, connected through
+ * edges, without a vertex where exactly two diagonally opposite faces belong to it,
+ * and without holes (TL_EINVAL otherwise); a domain without tilings gives
+ * TL_EUNTILEABLE (Thurston's test, Section 1.1).  The chain runs on the Aztec
+ * diamond of order n = ceil((w+h)/2) that holds the box at face offset (ox, oy),
+ * ox + oy = n, ox - oy = D with m = floor((h-w)/2), D = m if m - n is even, else
+ * m - 1; its faces outside the domain stay uncovered, and the draws of a site are
+ * those of the same site of that diamond.  Heights: a face of the diamond's box is
+ * black when its coordinates sum to an even number; across an edge walked with a
+ * black face on its left the height rises by 1 (edge of a domino) or falls by 3
+ * (edge covered by a domino).  T_max / T_min are the tilings of largest / smallest
+ * height.  Exports and observables use the w x h box (0xFF outside the domain).
+ * Batches and servers take the fixed shapes only. */
 typedef struct {
     int32_t model;   /* tl_model */
     int32_t shape;   /* tl_shape */
     int32_t n;       /* Aztec order / six-vertex N */
     int32_t a, b, c; /* hexagon sides */
     int32_t init;    /* tl_init */
+    int32_t w, h;    /* TL_MASK: box of the mask, in faces */
+    const uint8_t *mask; /* TL_MASK: h rows of w bytes, nonzero = face in the domain */
 } tl_domain;
 
 /* Weights (Section 1.1.1 edge and volume weights; Section 1.2 vertex weights).
@@ -104,8 +126,9 @@ typedef struct {
 
 typedef struct tl_sampler tl_sampler;
 
-/* Observables (cells: domino faces of the 2n x 2n box, lozenge vertices of the
- * (a+c+1) x (b+c+1) box, six-vertex vertices of the N x N grid).  Per-cell
+/* Observables (cells: domino faces of the 2n x 2n box or of the mask's w x h
+ * box, lozenge vertices of the (a+c+1) x (b+c+1) box, six-vertex vertices of
+ * the N x N grid).  Per-cell
  * quantity: domino = face covered by a horizontal domino; lozenge = H - H_min;
  * six-vertex = vertex of type c.  Buffers are caller-owned and may be NULL. */
 typedef struct {
@@ -122,7 +145,8 @@ typedef struct {
 
 /* Create a sampler in the extremal state of dom->init, with sweep counter 0.
  * The seed keys every draw (Philox key = (seed mod 2^32, seed >> 32)).
- * opt may be NULL.  Errors: TL_EINVAL, TL_ENOMEM, TL_EDEVICE. */
+ * opt may be NULL.  Errors: TL_EINVAL, TL_EUNTILEABLE (TL_MASK), TL_ENOMEM,
+ * TL_EDEVICE. */
 tl_status tl_sampler_create(const tl_domain *dom, const tl_weights *w, uint64_t seed,
                             const tl_options *opt, tl_sampler **out);
 
@@ -137,8 +161,8 @@ tl_status tl_sampler_sync(tl_sampler *s);
 tl_status tl_sampler_observables(tl_sampler *s, tl_observables *out);
 
 /* Size in bytes of the canonical export, and its row layout (rows x row_bytes):
- * domino uint8 per face of the 2n x 2n box (partner 0:N 1:S 2:E 3:W, 0xFF
- * outside); lozenge int32 H per vertex of the sheared box (INT32_MIN outside);
+ * domino uint8 per face of the 2n x 2n box, or of the w x h box of a mask
+ * (partner 0:N 1:S 2:E 3:W, 0xFF outside the domain); lozenge int32 H per vertex of the sheared box (INT32_MIN outside);
  * six-vertex int32 h per face of the (N+1)^2 box.  Row 0 is the southmost. */
 tl_status tl_sampler_export_size(const tl_sampler *s, size_t *bytes, uint32_t *rows, uint32_t *row_bytes);
 
@@ -286,6 +310,13 @@ tl_status tl_server_destroy(tl_server *sv);
  * 2c + (x mod 2); lozenge 0; six-vertex the mask of high diagonal faces
  * NE=1, NW=2, SW=4, SE=8.  Writes up to cap entries, the count in *count. */
 tl_status tl_thresholds(const tl_domain *dom, const tl_weights *w, uint32_t *out, uint32_t cap, uint32_t *count);
+
+/* Thurston's tileability test and the extremal tilings of a TL_MASK domino
+ * domain (Section 1.1), on the host (no device work): the canonical exports of
+ * T_max and T_min (h x w bytes each, caller-owned, either may be NULL) in the
+ * height convention stated with TL_MASK.  Errors: TL_EINVAL (not a mask domain,
+ * bad mask, buffers smaller than w*h bytes), TL_EUNTILEABLE. */
+tl_status tl_domain_extremes(const tl_domain *dom, uint8_t *tmax, uint8_t *tmin, size_t bytes);
 
 const char *tl_status_str(tl_status st);
 const char *tl_last_error(void);

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libtilings.so")
 
 TL_OK, TL_EINVAL, TL_EUNTILEABLE, TL_ENOMEM, TL_EBUDGET, TL_EDEVICE, TL_EBUSY = 0, -1, -2, -3, -4, -5, -6
 TL_DOMINO, TL_LOZENGE, TL_SIXVERTEX = 0, 1, 2
-TL_AZTEC, TL_HEXAGON, TL_DWBC_SQUARE = 0, 1, 2
+TL_AZTEC, TL_HEXAGON, TL_DWBC_SQUARE, TL_MASK = 0, 1, 2, 3
 TL_INIT_MIN, TL_INIT_MAX = 0, 1
 TL_HEATBATH, TL_METROPOLIS = 0, 1
 TL_W_UNIFORM, TL_W_TWO_PERIODIC, TL_W_VOLUME, TL_W_SIXVERTEX, TL_W_VOLUME_BW, TL_W_SIXVERTEX6 = 0, 1, 2, 3, 4, 5
@@ -38,7 +38,8 @@ def _status_name(st):
 class tl_domain(ctypes.Structure):
     _fields_ = [("model", ctypes.c_int32), ("shape", ctypes.c_int32), ("n", ctypes.c_int32),
                 ("a", ctypes.c_int32), ("b", ctypes.c_int32), ("c", ctypes.c_int32),
-                ("init", ctypes.c_int32)]
+                ("init", ctypes.c_int32), ("w", ctypes.c_int32), ("h", ctypes.c_int32),
+                ("mask", ctypes.POINTER(ctypes.c_uint8))]
 
 
 class tl_weights(ctypes.Structure):
@@ -101,7 +102,8 @@ def lib():
         for name in ("tl_sampler_create", "tl_sampler_sweep", "tl_sampler_sync", "tl_sampler_observables",
                      "tl_sampler_export_size", "tl_sampler_export", "tl_sampler_hash", "tl_sampler_import",
                      "tl_sampler_destroy", "tl_sampler_info", "tl_sampler_thresholds", "tl_sampler_reset",
-                     "tl_sampler_set_timing", "tl_sampler_kernel_time", "tl_sampler_cftp"):
+                     "tl_sampler_set_timing", "tl_sampler_kernel_time", "tl_sampler_cftp",
+                     "tl_domain_extremes"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -112,9 +114,31 @@ def _check(st):
         raise TlError(st, lib().tl_last_error().decode())
 
 
-def domain(model, n=0, a=0, b=0, c=0, init=TL_INIT_MIN):
+def domain(model, n=0, a=0, b=0, c=0, init=TL_INIT_MIN, mask=None):
+    """A domain; mask (2-D array, row 0 southmost, nonzero = face inside)
+    selects the TL_MASK shape (dominoes).  The returned struct keeps the
+    mask's bytes alive; the library copies them when a sampler is created."""
+    if mask is not None:
+        m = np.ascontiguousarray(np.asarray(mask) != 0, dtype=np.uint8)
+        if m.ndim != 2:
+            raise ValueError("mask must be 2-D")
+        d = tl_domain(model, TL_MASK, 0, 0, 0, 0, init, m.shape[1], m.shape[0],
+                      m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+        d._mask = m
+        return d
     shape = {TL_DOMINO: TL_AZTEC, TL_LOZENGE: TL_HEXAGON, TL_SIXVERTEX: TL_DWBC_SQUARE}[model]
     return tl_domain(model, shape, n, a, b, c, init)
+
+
+def domain_extremes(dom):
+    """(T_max, T_min) of a mask domain as canonical exports (host only);
+    raises TlError (TL_EUNTILEABLE when the domain has no tiling)."""
+    tmax = np.empty((dom.h, dom.w), dtype=np.uint8)
+    tmin = np.empty((dom.h, dom.w), dtype=np.uint8)
+    u8 = ctypes.POINTER(ctypes.c_uint8)
+    _check(lib().tl_domain_extremes(ctypes.byref(dom), tmax.ctypes.data_as(u8), tmin.ctypes.data_as(u8),
+                                    tmax.nbytes))
+    return tmax, tmin
 
 
 def weights(kind=TL_W_UNIFORM, *w, rule=TL_HEATBATH):

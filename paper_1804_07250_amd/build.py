@@ -1,5 +1,6 @@
 """Build step of the HIP library: compiles every csrc/*.hip for gfx950 with
-hipcc and links libtilings.so next to this file.  Objects go to _build/."""
+hipcc (host-only csrc/*.cpp with the C++ compiler) and links libtilings.so
+next to this file.  Objects go to _build/."""
 import os
 import subprocess
 import sys
@@ -13,15 +14,20 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function"]
+CXX = os.environ.get("CXX", "g++")
+CXXFLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall"]
 
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    srcs = sorted(f for f in os.listdir(CSRC) if f.endswith(".hip"))
+    srcs = sorted(f for f in os.listdir(CSRC) if f.endswith(".hip") or f.endswith(".cpp"))
 
     def compile_one(f):
         obj = os.path.join(BUILD, f + ".o")
-        cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, f), "-o", obj]
+        if f.endswith(".cpp"):   # host-only C++
+            cmd = [CXX] + CXXFLAGS + ["-c", os.path.join(CSRC, f), "-o", obj]
+        else:
+            cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, f), "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError("hipcc failed for %s:\n%s" % (f, r.stderr))

@@ -13,6 +13,7 @@
 #include "errors.hpp"
 #include "internal.hpp"
 #include "models.hpp"
+#include "region.hpp"
 
 namespace {
 thread_local std::string g_last_error;
@@ -223,6 +224,22 @@ const char *tl_status_str(tl_status st)
 
 const char *tl_last_error(void) { return g_last_error.c_str(); }
 
+tl_status tl_domain_extremes(const tl_domain *dom, uint8_t *tmax, uint8_t *tmin, size_t bytes)
+{
+    if (!dom) return fail(TL_EINVAL, "null argument");
+    if (dom->model != TL_DOMINO || dom->shape != TL_MASK)
+        return fail(TL_EINVAL, "extremal tilings are computed for domino mask domains");
+    tl::Region r;
+    std::string why;
+    const tl::RegionStatus st = tl::build_region(dom->mask, dom->w, dom->h, r, why);
+    if (st != tl::kRegionOk) return fail(st == tl::kRegionUntileable ? TL_EUNTILEABLE : TL_EINVAL, "%s", why.c_str());
+    const size_t need = (size_t)r.w * r.h;
+    if ((tmax || tmin) && bytes < need) return fail(TL_EINVAL, "buffers hold %zu bytes, %zu needed", bytes, need);
+    if (tmax) memcpy(tmax, r.tmax.data(), need);
+    if (tmin) memcpy(tmin, r.tmin.data(), need);
+    return TL_OK;
+}
+
 tl_status tl_thresholds(const tl_domain *dom, const tl_weights *w, uint32_t *out, uint32_t cap, uint32_t *count)
 {
     if (!dom || !w) return fail(TL_EINVAL, "null argument");
@@ -250,8 +267,10 @@ tl_status tl_sampler_create(const tl_domain *dom, const tl_weights *w, uint64_t 
     tl_status st = make_thresholds(*dom, *w, s->thr);
     if (st != TL_OK) return st;
     std::string why;
-    s->model = tl::make_model(*dom, why);
-    if (!s->model) return fail(TL_EINVAL, "%s", why.c_str());
+    tl_status mst = TL_EINVAL;
+    s->model = tl::make_model(*dom, why, &mst);
+    if (!s->model) return fail(mst, "%s", why.c_str());
+    s->dom.mask = nullptr;   // the model keeps its own copy of a mask
     if (s->opt.stream) {
         s->stream = (hipStream_t)s->opt.stream;
     } else {
@@ -456,9 +475,7 @@ tl_status tl_sampler_cftp(tl_sampler *s, uint32_t max_log2, tl_cftp_info *out)
                     return fail(TL_EINVAL, "coupling from the past needs weights that keep the height order "
                                            "(a <= c and b <= c)");
     }
-    std::string why;
-    std::unique_ptr<tl::Model> top = tl::make_model(s->dom, why);
-    if (!top) return fail(TL_EINVAL, "%s", why.c_str());
+    std::unique_ptr<tl::Model> top = s->model->twin();
     hipError_t e = top->allocate();
     uint32_t *flag = nullptr;
     if (e == hipSuccess) e = hipMalloc(&flag, sizeof(uint32_t));

@@ -534,10 +534,15 @@ __device__ __forceinline__ bool face_in(int n, int X, int Y)
     return abs(2 * X - 2 * n + 1) + abs(2 * Y - 2 * n + 1) <= 2 * n;
 }
 
-__global__ void domino_export_kernel(const uint32_t *pl, size_t PS, uint32_t RS, int n, int om, uint8_t *faces)
+// Faces (x, y) of a w x h box at face offset (ox, oy) in the diamond's box
+// (the whole 2n x 2n box for the Aztec diamond).  Uncovered faces (outside the
+// diamond, or outside a domain inside it) have no crossed edge: 0xFF.
+__global__ void domino_export_kernel(const uint32_t *pl, size_t PS, uint32_t RS, int n, int om, int ox, int oy,
+                                     int w, int h, uint8_t *faces)
 {
-    const int X = blockIdx.x * 16 + threadIdx.x, Y = blockIdx.y * 16 + threadIdx.y;
-    if (X >= 2 * n || Y >= 2 * n) return;
+    const int x = blockIdx.x * 16 + threadIdx.x, y = blockIdx.y * 16 + threadIdx.y;
+    if (x >= w || y >= h) return;
+    const int X = x + ox, Y = y + oy;
     uint8_t d = 0xFF;
     if (face_in(n, X, Y)) {
         if (hseg(pl, PS, RS, n, om, X, Y + 1)) d = 0;
@@ -545,7 +550,7 @@ __global__ void domino_export_kernel(const uint32_t *pl, size_t PS, uint32_t RS,
         else if (vseg(pl, PS, RS, n, om, X + 1, Y)) d = 2;
         else if (vseg(pl, PS, RS, n, om, X, Y)) d = 3;
     }
-    faces[(size_t)Y * (2 * n) + X] = d;
+    faces[(size_t)y * w + x] = d;
 }
 
 // Faces covered by horizontal dominoes = the two faces beside every crossed
@@ -554,11 +559,14 @@ __global__ void domino_export_kernel(const uint32_t *pl, size_t PS, uint32_t RS,
 // a crossed N edge covers faces (X-1, Y) and (X, Y), a crossed S edge faces
 // (X-1, Y-1) and (X, Y-1).  Counts go to a block-local copy of the bins in LDS
 // (when they fit) and are flushed with one global atomic per touched bin.
+// Bins cover the box of a domain at face offset (ox, oy) (0 for the Aztec
+// diamond); the run-counting path below assumes offset 0.
 constexpr uint32_t kLdsBins = 8192;
 
 __global__ void __launch_bounds__(256) domino_observe_kernel(const uint32_t *pl, size_t PS, uint32_t RS, int n,
                                                              uint32_t nw, uint32_t B, uint32_t bins_x,
-                                                             uint32_t nbins, unsigned long long *bins)
+                                                             uint32_t nbins, int ox, int oy,
+                                                             unsigned long long *bins)
 {
     extern __shared__ uint32_t lbin[];
     const bool local = nbins <= kLdsBins;
@@ -571,7 +579,7 @@ __global__ void __launch_bounds__(256) domino_observe_kernel(const uint32_t *pl,
     if (r < (uint32_t)n) {
         for (int p = 0; p < 2; ++p) {
             uint32_t m = pl[(size_t)p * PS + (size_t)r * RS + w];
-            if (B >= 32u) {
+            if (B >= 32u && ox == 0 && oy == 0) {
                 // site k = 32w + b sits at X = X0 - b, Y = Y0 + b: with bins of
                 // at least 32 faces, the word's bits fall into at most three
                 // runs per face column (X - 1 and X), each one bin
@@ -601,7 +609,7 @@ __global__ void __launch_bounds__(256) domino_observe_kernel(const uint32_t *pl,
                 const int b = __builtin_ctz(m);
                 m &= m - 1u;
                 const int k = (int)(w * 32u) + b;
-                const int X = (int)r - k + n, Y = (int)r + k + 1 - p;   // face row of the crossed edge
+                const int X = (int)r - k + n - ox, Y = (int)r + k + 1 - p - oy;   // face row of the crossed edge
                 const uint32_t i0 = (uint32_t)(Y / (int)B) * bins_x + (uint32_t)((X - 1) / (int)B);
                 const uint32_t i1 = (uint32_t)(Y / (int)B) * bins_x + (uint32_t)(X / (int)B);
                 if (local) {
@@ -777,21 +785,33 @@ hipError_t domino_batch_sweeps(BatchChain *chains, const BatchBundle *bundles, c
 
 hipError_t domino_export(const DominoDev &d, uint8_t *faces, hipStream_t s)
 {
-    dim3 block(16, 16), grid((2 * d.n + 15) / 16, (2 * d.n + 15) / 16);
-    hipLaunchKernelGGL(domino_export_kernel, grid, block, 0, s, d.planes, d.PS, d.RS, d.n, d.omega, faces);
+    return domino_export_box(d, 0, 0, 2 * d.n, 2 * d.n, faces, s);
+}
+
+hipError_t domino_export_box(const DominoDev &d, int ox, int oy, int w, int h, uint8_t *faces, hipStream_t s)
+{
+    dim3 block(16, 16), grid((w + 15) / 16, (h + 15) / 16);
+    hipLaunchKernelGGL(domino_export_kernel, grid, block, 0, s, d.planes, d.PS, d.RS, d.n, d.omega, ox, oy, w, h,
+                       faces);
     return hipGetLastError();
 }
 
 hipError_t domino_observe(const DominoDev &d, uint32_t B, uint32_t bins_x, unsigned long long *bins, hipStream_t s)
 {
+    return domino_observe_box(d, 0, 0, 2 * d.n, B, bins_x, bins, s);
+}
+
+hipError_t domino_observe_box(const DominoDev &d, int ox, int oy, int h, uint32_t B, uint32_t bins_x,
+                              unsigned long long *bins, hipStream_t s)
+{
     const uint32_t nw = (uint32_t)((d.n + 31) / 32);
-    const uint32_t bins_y = (2u * (uint32_t)d.n + B - 1) / B;
+    const uint32_t bins_y = ((uint32_t)h + B - 1) / B;
     const uint32_t nbins = bins_x * bins_y;
     const uint32_t threads = nw * (uint32_t)d.n;
     dim3 block(256), grid((threads + 255) / 256);
     const uint32_t shmem = nbins <= kLdsBins ? nbins * 4u : 0u;
     hipLaunchKernelGGL(domino_observe_kernel, grid, block, shmem, s, d.planes, d.PS, d.RS, d.n, nw, B, bins_x, nbins,
-                       bins);
+                       ox, oy, bins);
     return hipGetLastError();
 }
 

@@ -128,6 +128,11 @@ DominoTile domino_auto_tile(int n);
 hipError_t domino_export(const DominoDev &d, uint8_t *faces, hipStream_t s);
 hipError_t domino_observe(const DominoDev &d, uint32_t B, uint32_t bins_x, unsigned long long *bins,
                           hipStream_t s);
+// The same over a w x h box of faces at face offset (ox, oy) in the diamond's
+// box (a domain embedded in the diamond); bins are counted in box coordinates.
+hipError_t domino_export_box(const DominoDev &d, int ox, int oy, int w, int h, uint8_t *faces, hipStream_t s);
+hipError_t domino_observe_box(const DominoDev &d, int ox, int oy, int h, uint32_t B, uint32_t bins_x,
+                              unsigned long long *bins, hipStream_t s);
 
 // ------------------------------------------------------------ batched chains
 // One entry per domino chain of a batch; planes of chain i start at word

@@ -8,21 +8,25 @@
 #include <string.h>
 
 #include "models.hpp"
+#include "region.hpp"
 
 namespace tl {
 
 namespace {
 
 // ------------------------------------------------------------------ domino
+// The Aztec diamond of order n, or a domain given by a mask, embedded in the
+// Aztec diamond of its region (faces outside the domain stay uncovered, so no
+// rotation reaches them and the kernels run unchanged).
 class DominoModel : public Model {
 public:
-    explicit DominoModel(int n)
-    {
-        d_.n = n;
-        d_.omega = (n + 1) & 1;
-        words_ = domino_words(n, &d_.ng, &d_.RS, &d_.PS);
-    }
+    explicit DominoModel(int n) { setup(n); }
+    explicit DominoModel(std::shared_ptr<const Region> r) : region_(std::move(r)) { setup(region_->n); }
 
+    std::unique_ptr<Model> twin() const override
+    {
+        return std::unique_ptr<Model>(region_ ? new DominoModel(region_) : new DominoModel(d_.n));
+    }
     hipError_t allocate() override
     {
         hipError_t e = hipMalloc(&d_.planes, words_ * sizeof(uint32_t));
@@ -56,7 +60,23 @@ public:
     void swap_buffers() override { std::swap(d_.planes, d_.spare); }
     bool height_family() const override { return false; }
     const uint32_t *state() const override { return d_.planes; }
-    hipError_t init(bool init_max, hipStream_t s) override { return domino_init(d_, init_max ? 1 : 0, s); }
+    hipError_t init(bool init_max, hipStream_t s) override
+    {
+        if (!region_) return domino_init(d_, init_max ? 1 : 0, s);
+        // the extremal tilings of the domain, packed once on the host, go to
+        // both buffers (the zero padding included)
+        std::vector<uint32_t> &host = init_max ? packed_max_ : packed_min_;
+        if (host.empty()) {
+            std::string why;
+            if (!pack(init_max ? region_->tmax.data() : region_->tmin.data(), host, why))
+                return hipErrorInvalidValue;
+        }
+        hipError_t e = hipMemcpyAsync(d_.planes, host.data(), host.size() * sizeof(uint32_t),
+                                      hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d_.spare, host.data(), host.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s);
+        return e;
+    }
 
     hipError_t sweeps(uint32_t t0, uint32_t n, const Thr &T, bool metro, uint64_t seed, const tl_options &opt,
                       hipStream_t s) override
@@ -77,30 +97,72 @@ public:
     }
     hipError_t observe(uint32_t B, uint32_t bins_x, unsigned long long *bins, hipStream_t s) override
     {
-        return domino_observe(d_, B, bins_x, bins, s);
+        if (!region_) return domino_observe(d_, B, bins_x, bins, s);
+        return domino_observe_box(d_, region_->ox, region_->oy, region_->h, B, bins_x, bins, s);
     }
-    void cell_box(uint32_t *w, uint32_t *h) const override { *w = *h = 2u * (uint32_t)d_.n; }
+    void cell_box(uint32_t *w, uint32_t *h) const override
+    {
+        *w = region_ ? (uint32_t)region_->w : 2u * (uint32_t)d_.n;
+        *h = region_ ? (uint32_t)region_->h : 2u * (uint32_t)d_.n;
+    }
     static bool face_in(int n, int X, int Y) { return abs(2 * X - 2 * n + 1) + abs(2 * Y - 2 * n + 1) <= 2 * n; }
+    // Is face (x, y) of the export box part of the domain?
+    bool in_domain(int x, int y) const
+    {
+        if (region_) return region_->mask[(size_t)y * region_->w + x] != 0;
+        return face_in(d_.n, x, y);
+    }
     std::vector<uint32_t> cells_per_bin(uint32_t B, uint32_t bx, uint32_t by) const override
     {
         std::vector<uint32_t> c((size_t)bx * by, 0u);
-        const int W = 2 * d_.n;
-        for (int Y = 0; Y < W; ++Y)
-            for (int X = 0; X < W; ++X)
-                if (face_in(d_.n, X, Y)) c[(size_t)(Y / B) * bx + X / B] += 1;
+        uint32_t W, H;
+        cell_box(&W, &H);
+        for (uint32_t y = 0; y < H; ++y)
+            for (uint32_t x = 0; x < W; ++x)
+                if (in_domain((int)x, (int)y)) c[(size_t)(y / B) * bx + x / B] += 1;
         return c;
     }
-    void export_layout(uint32_t *rows, uint32_t *row_bytes) const override
+    void export_layout(uint32_t *rows, uint32_t *row_bytes) const override { cell_box(row_bytes, rows); }
+    hipError_t export_canonical(uint8_t *dev, hipStream_t s) override
     {
-        *rows = 2u * (uint32_t)d_.n;
-        *row_bytes = 2u * (uint32_t)d_.n;
+        if (!region_) return domino_export(d_, dev, s);
+        return domino_export_box(d_, region_->ox, region_->oy, region_->w, region_->h, dev, s);
     }
-    hipError_t export_canonical(uint8_t *dev, hipStream_t s) override { return domino_export(d_, dev, s); }
 
     bool import_canonical(const uint8_t *f, hipStream_t s, std::string &why, hipError_t *err) override
     {
-        const int n = d_.n, W = 2 * n;
-        std::vector<uint32_t> host(4 * d_.PS, 0u);
+        std::vector<uint32_t> host;
+        if (!pack(f, host, why)) return false;
+        hipError_t e = hipMemcpyAsync(d_.planes, host.data(), host.size() * sizeof(uint32_t),
+                                      hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) { *err = e; return false; }
+        return true;
+    }
+    uint64_t sites() const override
+    {
+        return region_ ? region_->sites : 2ull * d_.n * d_.n - 2ull * d_.n + 1ull;
+    }
+    int colours() const override { return 2; }
+    // 4 bits per owner site (n^2 owners), read and written: n^2 bytes
+    double bytes_per_colour_step() const override { return 2.0 * 4.0 * (double)d_.n * d_.n / 8.0; }
+
+private:
+    void setup(int n)
+    {
+        d_.n = n;
+        d_.omega = (n + 1) & 1;
+        words_ = domino_words(n, &d_.ng, &d_.RS, &d_.PS);
+    }
+    // Validate a canonical export (the export box: the diamond's 2n x 2n box, or
+    // the domain's w x h box) and pack its crossed edges into owner planes.
+    bool pack(const uint8_t *f, std::vector<uint32_t> &host, std::string &why) const
+    {
+        const int n = d_.n;
+        uint32_t W, H;
+        cell_box(&W, &H);
+        const int ox = region_ ? region_->ox : 0, oy = region_ ? region_->oy : 0;
+        host.assign(4 * d_.PS, 0u);
         auto set_owner = [&](int p, int P, int Q) -> bool {
             const int r2 = P + Q - n - 1, k2 = Q - P + n - 1;
             if (r2 < 0 || k2 < 0 || (r2 & 1) || (k2 & 1)) return false;
@@ -109,20 +171,21 @@ public:
             host[(size_t)p * d_.PS + (size_t)r * d_.RS + (k >> 5)] |= 1u << (k & 31);
             return true;
         };
-        for (int Y = 0; Y < W; ++Y)
-            for (int X = 0; X < W; ++X) {
-                const uint8_t dir = f[(size_t)Y * W + X];
-                if (!face_in(n, X, Y)) {
-                    if (dir != 0xFF) { why = "face outside the diamond is not 0xFF"; return false; }
+        for (int y = 0; y < (int)H; ++y)
+            for (int x = 0; x < (int)W; ++x) {
+                const uint8_t dir = f[(size_t)y * W + x];
+                if (!in_domain(x, y)) {
+                    if (dir != 0xFF) { why = "face outside the domain is not 0xFF"; return false; }
                     continue;
                 }
                 if (dir > 3) { why = "invalid partner code"; return false; }
-                const int PX = X + (dir == 2) - (dir == 3), PY = Y + (dir == 0) - (dir == 1);
-                if (PX < 0 || PY < 0 || PX >= W || PY >= W || !face_in(n, PX, PY) ||
-                    f[(size_t)PY * W + PX] != (uint8_t)(dir ^ 1u)) {
+                const int px = x + (dir == 2) - (dir == 3), py = y + (dir == 0) - (dir == 1);
+                if (px < 0 || py < 0 || px >= (int)W || py >= (int)H || !in_domain(px, py) ||
+                    f[(size_t)py * W + px] != (uint8_t)(dir ^ 1u)) {
                     why = "faces do not form a domino tiling";
                     return false;
                 }
+                const int X = x + ox, Y = y + oy;   // face in the diamond's box
                 bool ok = true;
                 if (dir == 2) {   // vertical segment (X+1,Y)-(X+1,Y+1)
                     ok = (((X + 1 + Y) & 1) == d_.omega) ? set_owner(0, X + 1, Y) : set_owner(1, X + 1, Y + 1);
@@ -131,27 +194,20 @@ public:
                 }
                 if (!ok) { why = "crossed edge without an interior owner"; return false; }
             }
-        hipError_t e = hipMemcpyAsync(d_.planes, host.data(), host.size() * sizeof(uint32_t),
-                                      hipMemcpyHostToDevice, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) { *err = e; return false; }
         return true;
     }
-    uint64_t sites() const override { return 2ull * d_.n * d_.n - 2ull * d_.n + 1ull; }
-    int colours() const override { return 2; }
-    // 4 bits per owner site (n^2 owners), read and written: n^2 bytes
-    double bytes_per_colour_step() const override { return 2.0 * 4.0 * (double)d_.n * d_.n / 8.0; }
 
-private:
     DominoDev d_;
     size_t words_ = 0;
     bool owned_ = false;
+    std::shared_ptr<const Region> region_;
+    std::vector<uint32_t> packed_max_, packed_min_;
 };
 
 // ------------------------------------------------------- lozenge / six-vertex
 class HeightModel : public Model {
 public:
-    explicit HeightModel(const tl_domain &dom)
+    explicit HeightModel(const tl_domain &dom) : dom_(dom)
     {
         d_.model = dom.model;
         d_.a = dom.a;
@@ -160,6 +216,7 @@ public:
         d_.N = dom.n;
         height_words(d_);
     }
+    std::unique_ptr<Model> twin() const override { return std::unique_ptr<Model>(new HeightModel(dom_)); }
     bool loz() const { return d_.model == TL_LOZENGE; }
     int width() const { return loz() ? d_.a + d_.c + 1 : d_.N + 1; }   // export row length
 
@@ -379,16 +436,27 @@ public:
     double bytes_per_colour_step() const override { return 2.0 * d_.P * (double)d_.rows * d_.K / 8.0; }
 
 private:
+    tl_domain dom_;
     HeightDev d_;
     bool owned_ = false;
 };
 
 }  // namespace
 
-std::unique_ptr<Model> make_model(const tl_domain &d, std::string &why)
+std::unique_ptr<Model> make_model(const tl_domain &d, std::string &why, tl_status *status)
 {
+    if (status) *status = TL_EINVAL;
+    if (d.model == TL_DOMINO && d.shape == TL_MASK) {
+        auto r = std::make_shared<Region>();
+        const RegionStatus st = build_region(d.mask, d.w, d.h, *r, why);
+        if (st != kRegionOk) {
+            if (status && st == kRegionUntileable) *status = TL_EUNTILEABLE;
+            return nullptr;
+        }
+        return std::unique_ptr<Model>(new DominoModel(std::shared_ptr<const Region>(std::move(r))));
+    }
     if (d.model == TL_DOMINO) {
-        if (d.shape != TL_AZTEC) { why = "dominoes support the Aztec diamond shape"; return nullptr; }
+        if (d.shape != TL_AZTEC) { why = "dominoes support the Aztec diamond and mask shapes"; return nullptr; }
         if (d.n < 1 || d.n > 16384) { why = "Aztec order must be in [1, 16384]"; return nullptr; }
         return std::unique_ptr<Model>(new DominoModel(d.n));
     }
@@ -416,7 +484,7 @@ namespace tl {
 size_t sampler_device_bytes(const tl_domain &d, uint32_t obs_bin)
 {
     std::string why;
-    if (!make_model(d, why)) return 0;
+    if (d.shape == TL_MASK || !make_model(d, why)) return 0;
     const uint32_t B = obs_bin ? obs_bin : 1u;
     size_t words = 0, cells_w = 0, cells_h = 0;
     if (d.model == TL_DOMINO) {

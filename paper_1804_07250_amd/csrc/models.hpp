@@ -13,6 +13,8 @@ namespace tl {
 class Model {
 public:
     virtual ~Model() {}
+    // A fresh model of the same domain (nothing allocated).
+    virtual std::unique_ptr<Model> twin() const = 0;
     virtual hipError_t allocate() = 0;
     virtual void release() = 0;
     virtual hipError_t init(bool init_max, hipStream_t s) = 0;
@@ -49,7 +51,9 @@ public:
     Timing timing;
 };
 
-std::unique_ptr<Model> make_model(const tl_domain &d, std::string &why);
+// nullptr on error, with why set and *status (nullable) the error code:
+// TL_EINVAL, or TL_EUNTILEABLE for a mask domain without tilings.
+std::unique_ptr<Model> make_model(const tl_domain &d, std::string &why, tl_status *status = nullptr);
 // Device bytes a sampler of this domain allocates (state, spare buffer, bins
 // of edge obs_bin), or 0 if the domain is invalid.
 size_t sampler_device_bytes(const tl_domain &d, uint32_t obs_bin);

@@ -1,0 +1,244 @@
+// Host pre-pass for general domino domains (Section 1.1; Thurston's
+// tileability test with the extremal tilings, linear in the domain's size).
+//
+// Boundary edges always bound a domino, so walking the boundary fixes the
+// heights there.  Any height function obeys h(v) <= h(u) + 1 across an edge
+// u -> v with a black face on its left and h(v) <= h(u) + 3 with a white one,
+// so h <= U(v) = min over boundary vertices b of h(b) + dist(b, v) (edge
+// lengths 1 and 3); symmetrically h >= L(v) with lengths 3 and 1 walked
+// backwards.  The domain is tileable iff U and L equal the boundary heights
+// on the boundary; then U is the height function of T_max and L that of
+// T_min.  Distances take small integer lengths, so a bucket queue (Dial's
+// method) keeps the work linear.
+#include "region.hpp"
+
+#include <limits.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+namespace tl {
+
+namespace {
+
+constexpr int32_t kUnset = INT32_MIN;
+
+struct Grid {
+    int w, h, parity;
+    const std::vector<uint8_t> &m;
+    int vw() const { return w + 1; }
+    bool in(int x, int y) const { return x >= 0 && y >= 0 && x < w && y < h && m[(size_t)y * w + x]; }
+    bool black(int x, int y) const { return ((x + y + parity) & 1) == 0; }
+};
+
+// The four edges out of vertex (i, j): neighbour and the faces on the left
+// and the right of the walk.
+struct Step {
+    int di, dj, lx, ly, rx, ry;
+};
+constexpr Step kSteps[4] = {
+    {1, 0, 0, 0, 0, -1},     // east:  left (i, j),       right (i, j-1)
+    {-1, 0, -1, -1, -1, 0},  // west:  left (i-1, j-1),   right (i-1, j)
+    {0, 1, -1, 0, 0, 0},     // north: left (i-1, j),     right (i, j)
+    {0, -1, 0, -1, -1, -1},  // south: left (i, j-1),     right (i-1, j-1)
+};
+
+int floor_div2(int v) { return v >= 0 ? v / 2 : -((-v + 1) / 2); }
+
+bool connected(const std::vector<uint8_t> &sel, int W, int H, size_t expected)
+{
+    if (expected == 0) return true;
+    size_t start = 0;
+    while (!sel[start]) ++start;
+    std::vector<uint8_t> seen(sel.size(), 0);
+    std::vector<size_t> stack{start};
+    seen[start] = 1;
+    size_t count = 1;
+    while (!stack.empty()) {
+        const size_t c = stack.back();
+        stack.pop_back();
+        const int x = (int)(c % W), y = (int)(c / W);
+        const int nx[4] = {x + 1, x - 1, x, x}, ny[4] = {y, y, y + 1, y - 1};
+        for (int k = 0; k < 4; ++k) {
+            if (nx[k] < 0 || ny[k] < 0 || nx[k] >= W || ny[k] >= H) continue;
+            const size_t d = (size_t)ny[k] * W + nx[k];
+            if (sel[d] && !seen[d]) {
+                seen[d] = 1;
+                ++count;
+                stack.push_back(d);
+            }
+        }
+    }
+    return count == expected;
+}
+
+// Multi-source shortest paths with edge lengths len_black / len_white, the
+// sources being the boundary vertices at key sign * hb.
+std::vector<int32_t> bound(const Grid &g, const std::vector<int32_t> &hb, int sign, int len_black, int len_white)
+{
+    const int VW = g.vw();
+    const size_t V = hb.size();
+    std::vector<int32_t> dist(V, kUnset);
+    int32_t kmin = INT32_MAX;
+    for (size_t v = 0; v < V; ++v)
+        if (hb[v] != kUnset) kmin = std::min(kmin, sign * hb[v]);
+    std::vector<std::vector<uint32_t>> buckets;
+    auto push = [&](uint32_t v, int32_t key) {
+        dist[v] = key;
+        const size_t b = (size_t)(key - kmin);
+        if (b >= buckets.size()) buckets.resize(b + 1);
+        buckets[b].push_back(v);
+    };
+    for (size_t v = 0; v < V; ++v)
+        if (hb[v] != kUnset) push((uint32_t)v, sign * hb[v]);
+    for (size_t b = 0; b < buckets.size(); ++b) {
+        for (size_t q = 0; q < buckets[b].size(); ++q) {
+            const uint32_t v = buckets[b][q];
+            const int32_t d = (int32_t)b + kmin;
+            if (dist[v] != d) continue;   // a shorter path reached v first
+            const int i = (int)(v % VW), j = (int)(v / VW);
+            for (const Step &s : kSteps) {
+                const bool l = g.in(i + s.lx, j + s.ly), r = g.in(i + s.rx, j + s.ry);
+                if (!l && !r) continue;
+                const uint32_t u = (uint32_t)((j + s.dj) * VW + i + s.di);
+                const int32_t nd = d + (g.black(i + s.lx, j + s.ly) ? len_black : len_white);
+                if (dist[u] == kUnset || nd < dist[u]) push(u, nd);
+            }
+        }
+        std::vector<uint32_t>().swap(buckets[b]);
+    }
+    return dist;
+}
+
+// Canonical export of the tiling with height function hv (sign * dist).
+bool tiling_of(const Grid &g, const std::vector<int32_t> &dist, int sign, std::vector<uint8_t> &out)
+{
+    const int VW = g.vw();
+    out.assign((size_t)g.w * g.h, 0xFF);
+    auto H = [&](int i, int j) { return (int64_t)sign * dist[(size_t)j * VW + i]; };
+    for (int y = 0; y < g.h; ++y)
+        for (int x = 0; x < g.w; ++x) {
+            if (!g.in(x, y)) continue;
+            // edge (two corners), partner code, partner face
+            const int e[4][4] = {{x, y + 1, x + 1, y + 1}, {x, y, x + 1, y}, {x + 1, y, x + 1, y + 1}, {x, y, x, y + 1}};
+            const int px[4] = {x, x, x + 1, x - 1}, py[4] = {y + 1, y - 1, y, y};
+            int code = -1;
+            for (int k = 0; k < 4; ++k) {
+                const int64_t dh = H(e[k][0], e[k][1]) - H(e[k][2], e[k][3]);
+                if (dh != 3 && dh != -3) continue;
+                if (code >= 0 || !g.in(px[k], py[k])) return false;
+                code = k;
+            }
+            if (code < 0) return false;
+            out[(size_t)y * g.w + x] = (uint8_t)code;
+        }
+    return true;
+}
+
+}  // namespace
+
+void region_embedding(int w, int h, int *n, int *ox, int *oy)
+{
+    const int N = (w + h + 1) / 2;
+    const int m = floor_div2(h - w);
+    const int D = ((m - N) & 1) == 0 ? m : m - 1;
+    *n = N;
+    *ox = (N + D) / 2;
+    *oy = (N - D) / 2;
+}
+
+RegionStatus build_region(const uint8_t *mask, int w, int h, Region &r, std::string &why)
+{
+    if (!mask || w < 1 || h < 1 || (int64_t)w + h > 32768) {
+        why = "mask domain needs a mask and 1 <= w, h with w + h <= 32768";
+        return kRegionInvalid;
+    }
+    r.w = w;
+    r.h = h;
+    region_embedding(w, h, &r.n, &r.ox, &r.oy);
+    r.mask.assign((size_t)w * h, 0);
+    r.faces = 0;
+    for (size_t i = 0; i < r.mask.size(); ++i) {
+        r.mask[i] = mask[i] ? 1 : 0;
+        r.faces += r.mask[i];
+    }
+    if (r.faces == 0) {
+        why = "empty domain";
+        return kRegionInvalid;
+    }
+    const Grid g{w, h, r.n & 1, r.mask};
+    // pinch vertices: exactly two diagonally opposite faces inside
+    for (int j = 0; j <= h; ++j)
+        for (int i = 0; i <= w; ++i) {
+            const bool sw = g.in(i - 1, j - 1), se = g.in(i, j - 1), nw = g.in(i - 1, j), ne = g.in(i, j);
+            if ((sw && ne && !se && !nw) || (se && nw && !sw && !ne)) {
+                why = "domain pinched at vertex (" + std::to_string(i) + ", " + std::to_string(j) + ")";
+                return kRegionInvalid;
+            }
+        }
+    if (!connected(r.mask, w, h, r.faces)) {
+        why = "domain is not connected";
+        return kRegionInvalid;
+    }
+    {   // holes: the complement in the box grown by one face must be connected
+        const int W2 = w + 2, H2 = h + 2;
+        std::vector<uint8_t> out((size_t)W2 * H2, 1);
+        for (int y = 0; y < h; ++y)
+            for (int x = 0; x < w; ++x) out[(size_t)(y + 1) * W2 + x + 1] = r.mask[(size_t)y * w + x] ? 0 : 1;
+        if (!connected(out, W2, H2, (size_t)W2 * H2 - r.faces)) {
+            why = "domain has a hole";
+            return kRegionInvalid;
+        }
+    }
+    r.sites = 0;
+    for (int j = 1; j < h; ++j)
+        for (int i = 1; i < w; ++i)
+            r.sites += g.in(i - 1, j - 1) && g.in(i, j - 1) && g.in(i - 1, j) && g.in(i, j);
+
+    // boundary heights, walking the boundary edges from the lowest, then
+    // leftmost, vertex of the domain
+    const int VW = w + 1;
+    const size_t V = (size_t)VW * (h + 1);
+    std::vector<int32_t> hb(V, kUnset);
+    size_t start = 0;
+    for (int j = 0, found = 0; j <= h && !found; ++j)
+        for (int i = 0; i <= w && !found; ++i)
+            if (g.in(i - 1, j - 1) || g.in(i, j - 1) || g.in(i - 1, j) || g.in(i, j)) {
+                start = (size_t)j * VW + i;
+                found = 1;
+            }
+    hb[start] = 0;
+    std::vector<size_t> stack{start};
+    while (!stack.empty()) {
+        const size_t v = stack.back();
+        stack.pop_back();
+        const int i = (int)(v % VW), j = (int)(v / VW);
+        for (const Step &s : kSteps) {
+            const bool l = g.in(i + s.lx, j + s.ly), rr = g.in(i + s.rx, j + s.ry);
+            if (l == rr) continue;   // interior edge, or no edge of the domain
+            const size_t u = (size_t)(j + s.dj) * VW + i + s.di;
+            const int32_t hu = hb[v] + (g.black(i + s.lx, j + s.ly) ? 1 : -1);
+            if (hb[u] == kUnset) {
+                hb[u] = hu;
+                stack.push_back(u);
+            } else if (hb[u] != hu) {
+                why = "no tiling: the boundary heights do not close up";
+                return kRegionUntileable;
+            }
+        }
+    }
+    const std::vector<int32_t> up = bound(g, hb, 1, 1, 3);
+    const std::vector<int32_t> down = bound(g, hb, -1, 3, 1);
+    for (size_t v = 0; v < V; ++v)
+        if (hb[v] != kUnset && (up[v] != hb[v] || down[v] != -hb[v])) {
+            why = "no tiling: no height function meets the boundary heights";
+            return kRegionUntileable;
+        }
+    if (!tiling_of(g, up, 1, r.tmax) || !tiling_of(g, down, -1, r.tmin)) {
+        why = "no tiling: extremal heights do not describe a tiling";
+        return kRegionUntileable;
+    }
+    return kRegionOk;
+}
+
+}  // namespace tl

@@ -556,6 +556,7 @@ tl_status tl_server_submit(tl_server *sv, const tl_domain *dom, const tl_weights
                            uint64_t n_sweeps, uint64_t *ticket)
 {
     if (!sv || !dom || !w || !ticket) return tl::fail(TL_EINVAL, "null argument");
+    if (dom->shape == TL_MASK) return tl::fail(TL_EINVAL, "served jobs take the fixed shapes");
     std::vector<uint32_t> thr;
     tl_status st = tl::make_table(*dom, *w, thr);
     if (st != TL_OK) return st;

@@ -1,0 +1,110 @@
+"""The library's host pre-pass for mask domains (Thurston's tileability test
+and extremal tilings, Section 1.1) against the oracle's, bit for bit; no
+device work is involved."""
+import ctypes
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1804_07250_amd as tl
+from test_oracle_region import l_shape, ones, random_domain
+
+
+def extremes(mask):
+    return tl.domain_extremes(tl.domain(tl.TL_DOMINO, mask=mask))
+
+
+def oracle_extremes(mask):
+    o = oracle.DominoRegionOracle(mask, [0] * 4)
+    return o.tmax, o.tmin
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_domains_match_the_oracle(seed):
+    rng = np.random.default_rng(seed)
+    tileable = 0
+    for _ in range(60):
+        w, h = int(rng.integers(1, 14)), int(rng.integers(1, 14))
+        m = random_domain(rng, w, h, rng.uniform(0.4, 1.0))
+        try:
+            want = oracle_extremes(m)
+        except oracle.Untileable:
+            with pytest.raises(tl.TlError) as e:
+                extremes(m)
+            assert e.value.status == tl.TL_EUNTILEABLE
+            continue
+        got = extremes(m)
+        assert (got[0] == want[0]).all() and (got[1] == want[1]).all()
+        tileable += 1
+    assert tileable > 5
+
+
+@pytest.mark.parametrize("shape", ["square", "rect", "l", "aztec", "tall", "wide"])
+def test_named_domains_match_the_oracle(shape):
+    m = {"square": ones(40, 40), "rect": ones(17, 30), "l": l_shape(30, 12, 18),
+         "aztec": oracle.DominoOracle(12, [0] * 4).in_domain_cells(), "tall": ones(60, 2),
+         "wide": ones(1, 64)}[shape]
+    got, want = extremes(m), oracle_extremes(m)
+    assert (got[0] == want[0]).all() and (got[1] == want[1]).all()
+
+
+def test_aztec_mask_gives_the_bricks():
+    for n in (3, 4):
+        d = oracle.DominoOracle(n, [0] * 4)
+        horizontal = d.export()
+        vertical = oracle.domino_vertical_brick(horizontal)
+        tmax, tmin = extremes(d.in_domain_cells())
+        assert ((tmax == vertical).all() and (tmin == horizontal).all()) == (n % 2 == 1)
+        assert ((tmax == horizontal).all() and (tmin == vertical).all()) == (n % 2 == 0)
+
+
+def test_rejected_domains():
+    ring = ones(4, 4)
+    ring[1:3, 1:3] = False
+    pinch = np.array([[1, 1, 0], [1, 1, 0], [0, 0, 1]], dtype=bool)
+    split = np.array([[1, 1, 0, 1, 1]], dtype=bool)
+    for m in (ring, pinch, split, np.zeros((3, 3), dtype=bool)):
+        with pytest.raises(tl.TlError) as e:
+            extremes(m)
+        assert e.value.status == tl.TL_EINVAL
+    board = ones(8, 8)
+    board[0, 0] = board[7, 7] = False
+    for m in (board, ones(3, 5)):
+        with pytest.raises(tl.TlError) as e:
+            extremes(m)
+        assert e.value.status == tl.TL_EUNTILEABLE
+    # not a mask domain
+    with pytest.raises(tl.TlError) as e:
+        tl.domain_extremes(tl.domain(tl.TL_DOMINO, n=4))
+    assert e.value.status == tl.TL_EINVAL
+
+
+def test_box_limits():
+    # w + h above 32768 is refused before the mask is read
+    d = tl.domain(tl.TL_DOMINO, mask=ones(2, 2))
+    d.w, d.h = 20000, 12769
+    assert tl.lib().tl_domain_extremes(ctypes.byref(d), None, None, 0) == tl.TL_EINVAL
+    d.w, d.h = 0, 2
+    assert tl.lib().tl_domain_extremes(ctypes.byref(d), None, None, 0) == tl.TL_EINVAL
+    d.w, d.h = 2, 2
+    assert tl.lib().tl_domain_extremes(ctypes.byref(d), None, None, 0) == tl.TL_OK
+    small = np.zeros(3, dtype=np.uint8)
+    assert tl.lib().tl_domain_extremes(ctypes.byref(d), small.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                       None, 3) == tl.TL_EINVAL
+
+
+def test_large_square_is_linear_time():
+    m = ones(1024, 1024)
+    t = time.time()
+    tmax, tmin = extremes(m)
+    assert time.time() - t < 20
+    assert (tmax != 255).all() and (tmin != 255).all()
+    # the extremes differ, and each is a tiling (partners point back)
+    for f in (tmax, tmin):
+        ys, xs = np.nonzero(f == 2)
+        assert (f[ys, xs + 1] == 3).all()
+        ys, xs = np.nonzero(f == 0)
+        assert (f[ys + 1, xs] == 1).all()
+    assert (tmax != tmin).any()
