@@ -41,6 +41,7 @@ from __future__ import annotations
 import heapq
 
 import numpy as np
+from scipy import ndimage
 
 NORTH, SOUTH, EAST, WEST = 0, 1, 2, 3
 
@@ -67,33 +68,18 @@ def check_region(mask):
     m = np.asarray(mask, dtype=bool)
     if m.ndim != 2 or not m.any():
         raise ValueError("empty domain")
-    h, w = m.shape
-    P = np.zeros((h + 2, w + 2), dtype=bool)
+    P = np.zeros((m.shape[0] + 2, m.shape[1] + 2), dtype=bool)
     P[1:-1, 1:-1] = m
-    for j in range(h + 1):
-        for i in range(w + 1):
-            sw, se, nw, ne = P[j, i], P[j, i + 1], P[j + 1, i], P[j + 1, i + 1]
-            if (sw and ne and not se and not nw) or (se and nw and not sw and not ne):
-                raise ValueError("domain pinched at vertex (%d, %d)" % (i, j))
+    # the four faces around every vertex (i, j) of the grown box
+    sw, se, nw, ne = P[:-1, :-1], P[:-1, 1:], P[1:, :-1], P[1:, 1:]
+    pinch = (sw & ne & ~se & ~nw) | (se & nw & ~sw & ~ne)
+    if pinch.any():
+        j, i = np.argwhere(pinch)[0]
+        raise ValueError("domain pinched at vertex (%d, %d)" % (i, j))
 
     def components(sel):
-        H, W = sel.shape
-        seen = np.zeros_like(sel)
-        count = 0
-        for y0 in range(H):
-            for x0 in range(W):
-                if not sel[y0, x0] or seen[y0, x0]:
-                    continue
-                count += 1
-                seen[y0, x0] = True
-                stack = [(x0, y0)]
-                while stack:
-                    x, y = stack.pop()
-                    for x2, y2 in ((x + 1, y), (x - 1, y), (x, y + 1), (x, y - 1)):
-                        if 0 <= x2 < W and 0 <= y2 < H and sel[y2, x2] and not seen[y2, x2]:
-                            seen[y2, x2] = True
-                            stack.append((x2, y2))
-        return count
+        # connected components through shared edges
+        return ndimage.label(sel, structure=[[0, 1, 0], [1, 1, 1], [0, 1, 0]])[1]
 
     if components(P) != 1:
         raise ValueError("domain is not connected")
@@ -253,9 +239,11 @@ class DominoRegionOracle:
         self.h, self.w = m.shape
         self.n, self.ox, self.oy = region_embedding(self.w, self.h)
         self.parity = (self.ox + self.oy) % 2
-        self.tmax, self.tmin = extremal_tilings(m, self.parity)
         self.chain = DominoOracle(self.n, thr, metropolis=metropolis, seed=seed)
-        self.load(self.tmax if init == "max" else self.tmin)
+        # init None: no start state yet (load one); skips the extremal tilings
+        if init is not None:
+            self.tmax, self.tmin = extremal_tilings(m, self.parity)
+            self.load(self.tmax if init == "max" else self.tmin)
         self.metropolis = metropolis
         self.seed = seed
         self.cells = (self.h, self.w)
