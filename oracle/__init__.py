@@ -66,14 +66,14 @@ def lib():
         L.or_domino_to_faces.argtypes = [ctypes.c_int, u8p, u8p, u8p]
         L.or_domino_flip.argtypes = [ctypes.c_int, u8p, u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.or_domino_sweeps.argtypes = [ctypes.c_int, u8p, u8p, u32p, ctypes.c_int, ctypes.c_uint64,
-                                       ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p]
+                                       ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, ctypes.c_void_p]
         L.or_domino_observe.argtypes = [ctypes.c_int, u8p, u8p, ctypes.c_uint32, ctypes.c_void_p]
         L.or_domino_observe.restype = ctypes.c_int64
         L.or_lozenge_min.argtypes = [ctypes.c_int] * 3 + [i32p]
         L.or_lozenge_max.argtypes = [ctypes.c_int] * 3 + [i32p]
         L.or_lozenge_flip.argtypes = [ctypes.c_int] * 3 + [i32p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.or_lozenge_sweeps.argtypes = [ctypes.c_int] * 3 + [i32p, u32p, ctypes.c_int, ctypes.c_uint64,
-                                                             ctypes.c_uint32, ctypes.c_uint32,
+                                                             ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
                                                              ctypes.c_void_p]
         L.or_lozenge_observe.argtypes = [ctypes.c_int] * 3 + [i32p, ctypes.c_uint32, ctypes.c_void_p]
         L.or_lozenge_observe.restype = ctypes.c_int64
@@ -81,7 +81,9 @@ def lib():
         L.or_sixv_max.argtypes = [ctypes.c_int, i32p]
         L.or_sixv_flip.argtypes = [ctypes.c_int, i32p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.or_sixv_sweeps.argtypes = [ctypes.c_int, i32p, u32p, ctypes.c_int, ctypes.c_uint64,
-                                     ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p]
+                                     ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, ctypes.c_void_p]
+        L.or_step_colour.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32]
+        L.or_step_colour.restype = ctypes.c_uint32
         L.or_sixv_observe.argtypes = [ctypes.c_int, i32p, ctypes.c_uint32, ctypes.c_void_p]
         L.or_sixv_observe.restype = ctypes.c_int64
         _lib = L
@@ -116,6 +118,11 @@ def set_reverse_order(rev: bool):
 
 def site_uniform(seed, r, k, t, c):
     return int(lib().or_site_uniform(seed, r, k, t, c))
+
+
+def step_colour(seed, step, K):
+    """Colour of colour step `step` under the random colour order."""
+    return int(lib().or_step_colour(seed, step, K))
 
 
 # --------------------------------------------------------------------- thresholds
@@ -250,7 +257,10 @@ def canonical_hash(arr2d: np.ndarray) -> str:
 # ----------------------------------------------------------------------- models
 
 class _Chain:
+    """random_colours: the paper's random colour choice per step (or_step_colour)
+    instead of the fixed order 0 .. K-1 within a sweep."""
     metropolis = False
+    random_colours = False
 
     def _obs(self, obs_every, bin_, nbins):
         self.bin_sum = np.zeros(nbins, dtype=np.uint64)
@@ -265,8 +275,9 @@ class _Chain:
 class DominoOracle(_Chain):
     """Aztec diamond of order n; state = the paper's split tilestate arrays."""
 
-    def __init__(self, n, thr, metropolis=False, seed=0, obs_every=0, bin_=1, init="min"):
+    def __init__(self, n, thr, metropolis=False, seed=0, obs_every=0, bin_=1, init="min", random_colours=False):
         self.n = n
+        self.random_colours = random_colours
         L = lib()
         m = L.or_domino_array_len(n)
         self.Tb = np.zeros(m, dtype=np.uint8)
@@ -285,7 +296,7 @@ class DominoOracle(_Chain):
     def sweep(self, nsweeps):
         lib().or_domino_sweeps(self.n, _p(self.Tb, ctypes.c_uint8), _p(self.Tw, ctypes.c_uint8),
                                _p(self.thr, ctypes.c_uint32), int(self.metropolis), self.seed,
-                               self.t, nsweeps, ctypes.byref(self._o))
+                               self.t, nsweeps, int(self.random_colours), ctypes.byref(self._o))
         self.t += nsweeps
 
     def export(self):
@@ -332,8 +343,10 @@ class DominoOracle(_Chain):
 
 
 class LozengeOracle(_Chain):
-    def __init__(self, a, b, c, thr, metropolis=False, seed=0, obs_every=0, bin_=1, init="min"):
+    def __init__(self, a, b, c, thr, metropolis=False, seed=0, obs_every=0, bin_=1, init="min",
+                 random_colours=False):
         self.a, self.b, self.c = a, b, c
+        self.random_colours = random_colours
         self.W, self.H = a + c + 1, b + c + 1
         self.Hs = np.zeros(self.W * self.H, dtype=np.int32)
         f = lib().or_lozenge_min if init == "min" else lib().or_lozenge_max
@@ -348,7 +361,7 @@ class LozengeOracle(_Chain):
     def sweep(self, nsweeps):
         lib().or_lozenge_sweeps(self.a, self.b, self.c, _p(self.Hs, ctypes.c_int32),
                                 _p(self.thr, ctypes.c_uint32), int(self.metropolis), self.seed,
-                                self.t, nsweeps, ctypes.byref(self._o))
+                                self.t, nsweeps, int(self.random_colours), ctypes.byref(self._o))
         self.t += nsweeps
 
     def export(self):
@@ -382,8 +395,9 @@ class LozengeOracle(_Chain):
 
 
 class SixVertexOracle(_Chain):
-    def __init__(self, N, thr, metropolis=False, seed=0, obs_every=0, bin_=1, init="min"):
+    def __init__(self, N, thr, metropolis=False, seed=0, obs_every=0, bin_=1, init="min", random_colours=False):
         self.N = N
+        self.random_colours = random_colours
         self.h = np.zeros((N + 1) * (N + 1), dtype=np.int32)
         f = lib().or_sixv_min if init == "min" else lib().or_sixv_max
         f(N, _p(self.h, ctypes.c_int32))
@@ -396,7 +410,8 @@ class SixVertexOracle(_Chain):
 
     def sweep(self, nsweeps):
         lib().or_sixv_sweeps(self.N, _p(self.h, ctypes.c_int32), _p(self.thr, ctypes.c_uint32),
-                             int(self.metropolis), self.seed, self.t, nsweeps, ctypes.byref(self._o))
+                             int(self.metropolis), self.seed, self.t, nsweeps, int(self.random_colours),
+                             ctypes.byref(self._o))
         self.t += nsweeps
 
     def export(self):

@@ -215,14 +215,23 @@ int64_t or_domino_observe(int n, const uint8_t *Tb, const uint8_t *Tw, uint32_t 
 }
 
 int or_domino_sweeps(int n, uint8_t *Tb, uint8_t *Tw, const uint32_t *thr, int metropolis,
-                     uint64_t seed, uint32_t t0, uint32_t nsweeps, or_obs *obs)
+                     uint64_t seed, uint32_t t0, uint32_t nsweeps, int random_colours, or_obs *obs)
 {
     for (uint32_t s = 0; s < nsweeps; ++s) {
         uint32_t t = t0 + s;
-        rotate(n, Tb, 0, thr, metropolis, seed, t);
-        update_white(n, Tw, Tb);
-        rotate(n, Tw, 1, thr, metropolis, seed, t);
-        update_black(n, Tb, Tw);
+        for (uint32_t i = 0; i < 2; ++i) {
+            /* the colour of the step and the sweep counter of its draws */
+            uint32_t step = 2u * t + i;
+            uint32_t colour = random_colours ? or_step_colour(seed, step, 2u) : i;
+            uint32_t tc = random_colours ? step : t;
+            if (colour == 0) {
+                rotate(n, Tb, 0, thr, metropolis, seed, tc);
+                update_white(n, Tw, Tb);
+            } else {
+                rotate(n, Tw, 1, thr, metropolis, seed, tc);
+                update_black(n, Tb, Tw);
+            }
+        }
         if (obs && obs->obs_every && (t + 1) % obs->obs_every == 0) {
             int64_t v = or_domino_observe(n, Tb, Tw, obs->bin, obs->bin_sum);
             if (obs->scalar_sum) *obs->scalar_sum += v;

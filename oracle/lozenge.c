@@ -102,12 +102,16 @@ int64_t or_lozenge_observe(int a, int b, int c, const int32_t *Hs, uint32_t bin,
 }
 
 int or_lozenge_sweeps(int a, int b, int c, int32_t *Hs, const uint32_t *thr, int metropolis,
-                      uint64_t seed, uint32_t t0, uint32_t nsweeps, or_obs *obs)
+                      uint64_t seed, uint32_t t0, uint32_t nsweeps, int random_colours, or_obs *obs)
 {
     int W = a + c + 1, Hh = b + c + 1;
     for (uint32_t s = 0; s < nsweeps; ++s) {
         uint32_t t = t0 + s;
-        for (int colour = 0; colour < 3; ++colour)
+        for (uint32_t i = 0; i < 3; ++i) {
+            /* the colour of the step and the sweep counter of its draws */
+            uint32_t step = 3u * t + i;
+            int colour = random_colours ? (int)or_step_colour(seed, step, 3u) : (int)i;
+            uint32_t tc = random_colours ? step : t;
             for (int Yi = 0; Yi < Hh; ++Yi)
                 for (int Xi = 0; Xi < W; ++Xi) {
                     int Y = or_reverse_order ? Hh - 1 - Yi : Yi;
@@ -116,10 +120,11 @@ int or_lozenge_sweeps(int a, int b, int c, int32_t *Hs, const uint32_t *thr, int
                     int32_t f;
                     if (!hexagon_at(a, b, c, Hs, X, Y, &f)) continue;
                     int ctx = metropolis ? (Hs[Y * W + X] == f + 1) : 0;
-                    uint32_t u = or_site_uniform(seed, (uint32_t)Y, (uint32_t)(X / 3), t,
+                    uint32_t u = or_site_uniform(seed, (uint32_t)Y, (uint32_t)(X / 3), tc,
                                                  (uint32_t)colour);
                     Hs[Y * W + X] = (u < thr[ctx]) ? f + 1 : f;
                 }
+        }
         if (obs && obs->obs_every && (t + 1) % obs->obs_every == 0) {
             int64_t v = or_lozenge_observe(a, b, c, Hs, obs->bin, obs->bin_sum);
             if (obs->scalar_sum) *obs->scalar_sum += v;

@@ -37,6 +37,12 @@ void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out
  * Philox(key = seed, ctr = (k>>7, r, t, 4j + c)), j = 0..31. */
 uint32_t or_site_uniform(uint64_t seed, uint32_t r, uint32_t k, uint32_t t, uint32_t c);
 
+/* Random colour order (the paper's RandomWalk): sweep t is the K colour steps
+ * step = K t .. K t + K - 1, step `step` updating colour or_step_colour(seed,
+ * step, K) with the site draws of sweep counter `step`.  The fixed order runs
+ * colours 0 .. K-1 with sweep counter t. */
+uint32_t or_step_colour(uint64_t seed, uint32_t step, uint32_t K);
+
 /* Observable accumulator shared by the three models.  Cells are faces
  * (domino), vertices (lozenge) or vertices (six-vertex); bins are bin x bin
  * cells; bin_sum has bins_x*bins_y entries.  Any pointer may be NULL. */
@@ -67,7 +73,7 @@ int  or_domino_flip(int n, uint8_t *Tb, uint8_t *Tw, int X, int Y, int up);
 /* Run sweeps t0 .. t0+nsweeps-1.  thr has 4 entries (heat-bath, index
  * 2c + (x mod 2)) or 8 entries (lazy Metropolis, index 2*(2c + x mod 2) + cur). */
 int  or_domino_sweeps(int n, uint8_t *Tb, uint8_t *Tw, const uint32_t *thr, int metropolis,
-                      uint64_t seed, uint32_t t0, uint32_t nsweeps, or_obs *obs);
+                      uint64_t seed, uint32_t t0, uint32_t nsweeps, int random_colours, or_obs *obs);
 int64_t or_domino_observe(int n, const uint8_t *Tb, const uint8_t *Tw, uint32_t bin,
                           uint64_t *bin_sum);
 
@@ -78,7 +84,7 @@ void or_lozenge_max(int a, int b, int c, int32_t *Hs);
 int  or_lozenge_flip(int a, int b, int c, int32_t *Hs, int X, int Y, int up);
 /* thr: 1 entry (heat-bath) or 2 entries (Metropolis, index = current is up). */
 int  or_lozenge_sweeps(int a, int b, int c, int32_t *Hs, const uint32_t *thr, int metropolis,
-                       uint64_t seed, uint32_t t0, uint32_t nsweeps, or_obs *obs);
+                       uint64_t seed, uint32_t t0, uint32_t nsweeps, int random_colours, or_obs *obs);
 int64_t or_lozenge_observe(int a, int b, int c, const int32_t *Hs, uint32_t bin, uint64_t *bin_sum);
 
 /* ---------------- six-vertex model, domain-wall boundary, N x N ----------- */
@@ -88,7 +94,7 @@ int  or_sixv_flip(int N, int32_t *h, int I, int J, int up);
 /* thr: 16 entries (heat-bath, index = 4-bit mask of high diagonal faces
  * NE=1, NW=2, SW=4, SE=8) or 32 entries (Metropolis, index 2*mask + current is up). */
 int  or_sixv_sweeps(int N, int32_t *h, const uint32_t *thr, int metropolis,
-                    uint64_t seed, uint32_t t0, uint32_t nsweeps, or_obs *obs);
+                    uint64_t seed, uint32_t t0, uint32_t nsweeps, int random_colours, or_obs *obs);
 int64_t or_sixv_observe(int N, const int32_t *h, uint32_t bin, uint64_t *bin_sum);
 
 #ifdef __cplusplus

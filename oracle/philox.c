@@ -57,5 +57,18 @@ uint32_t or_site_uniform(uint64_t seed, uint32_t r, uint32_t k, uint32_t t, uint
 }
 
 /* Iteration order switch used by the order-independence tests. */
+/* Colour of colour step `step` under the random colour order: the paper's
+ * RandomWalk picks the colour of every step at random; here it is
+ * floor(K u / 2^32) with u word 0 of Philox(key = seed, ctr = (step, 0, 0, 2^31)),
+ * a counter no site draw uses (their last word is below 128). */
+uint32_t or_step_colour(uint64_t seed, uint32_t step, uint32_t K)
+{
+    const uint32_t ctr[4] = {step, 0u, 0u, 0x80000000u};
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t out[4];
+    or_philox4x32_10(ctr, key, out);
+    return (uint32_t)(((uint64_t)out[0] * K) >> 32);
+}
+
 int or_reverse_order = 0;
 void or_set_reverse_order(int reverse) { or_reverse_order = reverse ? 1 : 0; }

@@ -231,7 +231,8 @@ class DominoRegionOracle:
     Aztec diamond the domain is embedded in (module docstring).  Same
     interface as DominoOracle, in the domain's own coordinates."""
 
-    def __init__(self, mask, thr, metropolis=False, seed=0, obs_every=0, bin_=1, init="min"):
+    def __init__(self, mask, thr, metropolis=False, seed=0, obs_every=0, bin_=1, init="min",
+                 random_colours=False):
         from . import DominoOracle
         m = np.asarray(mask, dtype=bool)
         check_region(m)
@@ -239,7 +240,7 @@ class DominoRegionOracle:
         self.h, self.w = m.shape
         self.n, self.ox, self.oy = region_embedding(self.w, self.h)
         self.parity = (self.ox + self.oy) % 2
-        self.chain = DominoOracle(self.n, thr, metropolis=metropolis, seed=seed)
+        self.chain = DominoOracle(self.n, thr, metropolis=metropolis, seed=seed, random_colours=random_colours)
         # init None: no start state yet (load one); skips the extremal tilings
         if init is not None:
             self.tmax, self.tmin = extremal_tilings(m, self.parity)

@@ -82,12 +82,16 @@ int64_t or_sixv_observe(int N, const int32_t *h, uint32_t bin, uint64_t *bin_sum
 }
 
 int or_sixv_sweeps(int N, int32_t *h, const uint32_t *thr, int metropolis,
-                   uint64_t seed, uint32_t t0, uint32_t nsweeps, or_obs *obs)
+                   uint64_t seed, uint32_t t0, uint32_t nsweeps, int random_colours, or_obs *obs)
 {
     int P = N + 1;
     for (uint32_t s = 0; s < nsweeps; ++s) {
         uint32_t t = t0 + s;
-        for (int colour = 0; colour < 4; ++colour)
+        for (uint32_t i = 0; i < 4; ++i) {
+            /* the colour of the step and the sweep counter of its draws */
+            uint32_t step = 4u * t + i;
+            int colour = random_colours ? (int)or_step_colour(seed, step, 4u) : (int)i;
+            uint32_t tc = random_colours ? step : t;
             for (int Ji = 1; Ji < N; ++Ji)
                 for (int Ii = 1; Ii < N; ++Ii) {
                     int J = or_reverse_order ? N - Ji : Ji;
@@ -97,10 +101,11 @@ int or_sixv_sweeps(int N, int32_t *h, const uint32_t *thr, int metropolis,
                     unsigned mask;
                     if (!flippable(N, h, I, J, &m, &mask)) continue;
                     unsigned ctx = metropolis ? 2u * mask + (h[J * P + I] == m + 1) : mask;
-                    uint32_t u = or_site_uniform(seed, (uint32_t)J, (uint32_t)(I >> 1), t,
+                    uint32_t u = or_site_uniform(seed, (uint32_t)J, (uint32_t)(I >> 1), tc,
                                                  (uint32_t)colour);
                     h[J * P + I] = (u < thr[ctx]) ? m + 1 : m - 1;
                 }
+        }
         if (obs && obs->obs_every && (t + 1) % obs->obs_every == 0) {
             int64_t v = or_sixv_observe(N, h, obs->bin, obs->bin_sum);
             if (obs->scalar_sum) *obs->scalar_sum += v;
