@@ -122,7 +122,16 @@ typedef struct {
     uint32_t tile_rows;          /* tile height of the tiled kernel; 0 = automatic */
     uint32_t kernel;             /* 0 = automatic, 1 = one launch per colour step, 2 = tiled multi-sweep */
     uint32_t tile_groups;        /* tile width in groups of 128 sites; 0 = automatic */
+    uint32_t colour_order;       /* 0 = colours 0..K-1 in every sweep; 1 = random (see below) */
 } tl_options;
+
+/* Random colour order (Section 2.2, RandomWalk: the colour of every step is
+ * drawn at random).  Sweep t is the K colour steps s = K t .. K t + K - 1;
+ * step s updates colour floor(K u / 2^32), u = word 0 of Philox(key = seed,
+ * ctr = (s, 0, 0, 2^31)), with the site draws of sweep counter s (the per-site
+ * uniform defined above with t replaced by s).  K t must stay below 2^32.
+ * Samplers only (plain sweeps and coupling from the past); batches and servers
+ * run the fixed order. */
 
 typedef struct tl_sampler tl_sampler;
 

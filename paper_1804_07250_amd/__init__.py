@@ -49,7 +49,7 @@ class tl_weights(ctypes.Structure):
 class tl_options(ctypes.Structure):
     _fields_ = [("stream", ctypes.c_void_p), ("obs_every", ctypes.c_uint32), ("obs_bin", ctypes.c_uint32),
                 ("sweeps_per_launch", ctypes.c_uint32), ("tile_rows", ctypes.c_uint32),
-                ("kernel", ctypes.c_uint32), ("tile_groups", ctypes.c_uint32)]
+                ("kernel", ctypes.c_uint32), ("tile_groups", ctypes.c_uint32), ("colour_order", ctypes.c_uint32)]
 
 
 class tl_observables(ctypes.Structure):
@@ -146,8 +146,10 @@ def weights(kind=TL_W_UNIFORM, *w, rule=TL_HEATBATH):
     return tl_weights(kind, rule, arr)
 
 
-def options(stream=None, obs_every=0, obs_bin=1, sweeps_per_launch=0, tile_rows=0, kernel=0, tile_groups=0):
-    return tl_options(stream, obs_every, obs_bin, sweeps_per_launch, tile_rows, kernel, tile_groups)
+def options(stream=None, obs_every=0, obs_bin=1, sweeps_per_launch=0, tile_rows=0, kernel=0, tile_groups=0,
+            colour_order=0):
+    """colour_order: 0 = colours 0..K-1 in every sweep, 1 = a random colour per step."""
+    return tl_options(stream, obs_every, obs_bin, sweeps_per_launch, tile_rows, kernel, tile_groups, colour_order)
 
 
 def thresholds(dom: tl_domain, w: tl_weights):

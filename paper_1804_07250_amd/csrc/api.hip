@@ -264,6 +264,7 @@ tl_status tl_sampler_create(const tl_domain *dom, const tl_weights *w, uint64_t 
     s->seed = seed;
     if (opt) s->opt = *opt;
     if (dom->init != TL_INIT_MIN && dom->init != TL_INIT_MAX) return fail(TL_EINVAL, "unknown init %d", dom->init);
+    if (s->opt.colour_order > 1) return fail(TL_EINVAL, "unknown colour order %u", s->opt.colour_order);
     tl_status st = make_thresholds(*dom, *w, s->thr);
     if (st != TL_OK) return st;
     std::string why;
@@ -271,6 +272,7 @@ tl_status tl_sampler_create(const tl_domain *dom, const tl_weights *w, uint64_t 
     s->model = tl::make_model(*dom, why, &mst);
     if (!s->model) return fail(mst, "%s", why.c_str());
     s->dom.mask = nullptr;   // the model keeps its own copy of a mask
+    s->model->order = s->opt.colour_order;
     if (s->opt.stream) {
         s->stream = (hipStream_t)s->opt.stream;
     } else {
@@ -306,6 +308,8 @@ tl_status tl_sampler_sweep(tl_sampler *s, uint64_t n)
 {
     if (!s) return fail(TL_EINVAL, "null sampler");
     if (s->t + n > 0xFFFFFFFFull) return fail(TL_EINVAL, "sweep counter would exceed 2^32");
+    if (s->model->order && (s->t + n) * (uint64_t)s->model->colours() > 0x100000000ull)
+        return fail(TL_EINVAL, "step counter would exceed 2^32 (random colour order)");
     const tl::Thr T = table_of(s);
     const bool metro = s->w.rule == TL_METROPOLIS;
     const uint32_t every = s->opt.obs_every;
@@ -466,6 +470,8 @@ tl_status tl_sampler_cftp(tl_sampler *s, uint32_t max_log2, tl_cftp_info *out)
     if (!s) return fail(TL_EINVAL, "null sampler");
     if (max_log2 < 1 || max_log2 > 31) return fail(TL_EINVAL, "max_log2 must be in 1..31");
     if (s->w.rule != TL_HEATBATH) return fail(TL_EINVAL, "coupling from the past needs the heat-bath rule");
+    if (s->model->order && max_log2 > 30)
+        return fail(TL_EINVAL, "max_log2 must be <= 30 under the random colour order");
     if (s->dom.model == TL_SIXVERTEX) {
         // the moves keep the height order iff raising a diagonal face never
         // lowers the up threshold (for weights a, b, c: a <= c and b <= c)

@@ -41,6 +41,16 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
     out[3] = c3;
 }
 
+// Colour of colour step `step` under the random colour order: floor(K u / 2^32)
+// with u word 0 of Philox(ctr = (step, 0, 0, 2^31)); no site draw uses that
+// counter (their last word is below 128).
+__device__ __forceinline__ uint32_t step_colour(uint32_t step, uint32_t K, uint32_t k0, uint32_t k1)
+{
+    uint32_t out[4];
+    philox4x32_10(step, 0u, 0u, 0x80000000u, k0, k1, out);
+    return (uint32_t)(((uint64_t)out[0] * K) >> 32);
+}
+
 // Acceptance decisions for the 128 sites k = 128 g + 32 w + b (w = 0..3,
 // b = 0..31) of class row r in colour step (t, c): bit b of D[w] is 1 iff the
 // site's uniform u is below the threshold of its context.

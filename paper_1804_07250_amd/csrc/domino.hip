@@ -293,15 +293,17 @@ __global__ void __launch_bounds__(256) domino_other_step(uint32_t *planes, size_
 // loaded into LDS, advanced nsweeps sweeps there, and the interior written to
 // `out`.  Halo cells repeat their neighbours' keyed draws, so the interior
 // matches the sweep of the whole state; halo rows go stale one per sweep from
-// each side, so sweep s computes only rows [s, LR - s).  The block has a
-// thread per (row, group) task (blockDim >= LR * LG, as every launch plan
-// gives): thread tid handles group tid % LG of row s + tid / LG.
+// each side, so sweep s computes only rows [s, LR - s).  Under the random
+// colour order (order = 1) step q of the launch (2 per sweep) draws its colour
+// and computes rows [q, LR - q), the halo covering 2 rows per sweep.  The block
+// has a thread per (row, group) task (blockDim >= LR * LG, as every launch
+// plan gives): thread tid handles group tid % LG of row base + tid / LG.
 template <int MODE>
 __device__ __forceinline__ void domino_tile(uint32_t *lds, const uint32_t *__restrict__ in,
                                             uint32_t *__restrict__ out, size_t PS, uint32_t RS, uint32_t ng,
                                             uint32_t n, uint32_t omega, uint32_t t0, uint32_t nsweeps, uint32_t TR,
                                             uint32_t TG, uint32_t HR, uint32_t HG, uint32_t tile_r, uint32_t tile_g,
-                                            const Thr &Tall, uint32_t key0, uint32_t key1)
+                                            const Thr &Tall, uint32_t key0, uint32_t key1, uint32_t order)
 {
     const uint32_t LR = TR + 2 * HR, LG = TG + 2 * HG, LRS = 4 * LG + 4;
     const uint32_t LPS = LR * LRS;
@@ -324,9 +326,16 @@ __device__ __forceinline__ void domino_tile(uint32_t *lds, const uint32_t *__res
     const int gg = G0 + (int)lg;
     const bool lane = gg >= 0 && gg < (int)ng;
     for (uint32_t s = 0; s < nsweeps; ++s) {
-        const uint32_t t = t0 + s;
-        const uint32_t base = HR ? s : 0u, end = HR ? LR - s : LR;
-        for (uint32_t c = 0; c < 2; ++c) {
+        for (uint32_t i = 0; i < 2; ++i) {
+            // colour, sweep counter of the draws and valid rows of this step
+            uint32_t c = i, t = t0 + s, base = HR ? s : 0u, end = HR ? LR - s : LR;
+            if (order) {
+                const uint32_t step = 2u * t + i, q = 2u * s + i;
+                c = step_colour(step, 2u, key0, key1);
+                t = step;
+                base = HR ? q : 0u;
+                end = HR ? LR - q : LR;
+            }
             const uint32_t lr = base + r0;
             const int gr = R0 + (int)lr;
             if (lane && lr < end && gr >= 0 && gr < (int)n) {
@@ -361,11 +370,11 @@ __global__ void __launch_bounds__(1024) domino_tiled_kernel(const uint32_t *__re
                                                             uint32_t ng, uint32_t n, uint32_t omega, uint32_t t0,
                                                             uint32_t nsweeps, uint32_t TR, uint32_t TG,
                                                             uint32_t HR, uint32_t HG, uint32_t tiles_x,
-                                                            Thr Tall, uint32_t key0, uint32_t key1)
+                                                            Thr Tall, uint32_t key0, uint32_t key1, uint32_t order)
 {
     extern __shared__ uint32_t lds[];
     domino_tile<MODE>(lds, in, out, PS, RS, ng, n, omega, t0, nsweeps, TR, TG, HR, HG, blockIdx.x / tiles_x,
-                      blockIdx.x % tiles_x, Tall, key0, key1);
+                      blockIdx.x % tiles_x, Tall, key0, key1, order);
 }
 
 // Multi-job kernel: work-group b runs tile items[b].tile of job items[b].job,
@@ -374,7 +383,7 @@ template <int MODE>
 __device__ __forceinline__ void domino_item(uint32_t *lds, const TileJob &j, uint32_t tile)
 {
     domino_tile<MODE>(lds, j.in, j.out, j.PS, j.RS, j.ng, j.rows, (uint32_t)j.omega, j.t0, j.S, j.TR, j.TG, j.HR,
-                      j.HG, tile / j.tiles_x, tile % j.tiles_x, j.T, j.key0, j.key1);
+                      j.HG, tile / j.tiles_x, tile % j.tiles_x, j.T, j.key0, j.key1, j.order);
 }
 
 __global__ void __launch_bounds__(1024) domino_items_kernel(const TileJob *__restrict__ jobs,
@@ -688,11 +697,14 @@ bool domino_plan(const DominoDev &d, const DominoTile &tile, uint32_t S_max, Til
     if (TR < n && TR > max_rows - 2u) TR = max_rows - 2u;   // leave room for a halo
     if (TR >= n && n > max_rows) TR = max_rows - 2u;
     const uint32_t tiles_y = (n + TR - 1) / TR;
+    // halo rows per sweep: 1 (one step of the other colour), 2 under the
+    // random colour order (any step may be of the other colour)
+    const uint32_t hps = tile.order ? 2u : 1u;
     uint32_t S = S_max < tile.S ? S_max : tile.S;
-    if (tiles_x > 1 && S > 128u) S = 128u;   // the one-group column halo covers 128 sweeps
-    if (tiles_y > 1 && S > (max_rows - TR) / 2u) S = (max_rows - TR) / 2u;
+    if (tiles_x > 1 && S * hps > 128u) S = 128u / hps;   // the one-group column halo covers 128 steps
+    if (tiles_y > 1 && S * hps > (max_rows - TR) / 2u) S = (max_rows - TR) / 2u / hps;
     if (S == 0u) S = 1u;
-    const uint32_t HR = tiles_y > 1 ? S : 0u;
+    const uint32_t HR = tiles_y > 1 ? hps * S : 0u;
     const uint32_t HG = tiles_x > 1 ? 1u : 0u;
     const uint32_t LR = TR + 2 * HR, LG = TG + 2 * HG;
     const uint32_t tasks = LR * LG;
@@ -707,6 +719,7 @@ bool domino_plan(const DominoDev &d, const DominoTile &tile, uint32_t S_max, Til
     p->tiles_y = tiles_y;
     p->threads = (tasks + 63) / 64 * 64;
     p->lds = lds;
+    p->order = tile.order;
     return true;
 }
 
@@ -722,7 +735,7 @@ hipError_t domino_tiled_sweeps(DominoDev &d, const DominoTile &tile, uint32_t t0
                              : (metropolis ? domino_tiled_kernel<kMetropolis> : domino_tiled_kernel<kHeatBath>);
         hipError_t e = launch(tm, 2 * p.S, k, dim3(p.tiles()), dim3(p.threads), p.lds, s, (const uint32_t *)d.planes,
                               d.spare, d.PS, d.RS, d.ng, (uint32_t)d.n, (uint32_t)d.omega, t0 + done, p.S, p.TR,
-                              p.TG, p.HR, p.HG, p.tiles_x, T, key0, key1);
+                              p.TG, p.HR, p.HG, p.tiles_x, T, key0, key1, p.order);
         if (e != hipSuccess) return e;
         uint32_t *tmp = d.planes;
         d.planes = d.spare;
@@ -751,6 +764,7 @@ TileJob domino_tile_job(const DominoDev &d, const TilePlan &p, uint32_t t0, cons
     j.HR = p.HR;
     j.HG = p.HG;
     j.tiles_x = p.tiles_x;
+    j.order = p.order;
     j.mode = T.uniform() ? kModeUniform : (metropolis ? kModeMetropolis : kModeHeatBath);
     j.key0 = (uint32_t)seed;
     j.key1 = (uint32_t)(seed >> 32);

@@ -339,17 +339,18 @@ __global__ void __launch_bounds__(256) height_step_kernel(uint32_t *planes, size
 // LRS = 4*(LG+2) (the pad groups hold the neighbouring groups, or zero).  Local
 // row lr is global row R0 + lr, local group lg is global group G0 + lg.  With a
 // row halo, the rows still valid before sweep s are [rps*s, LR - rps*s) (rps
-// rows go stale per sweep on each side), and only those are computed.  The
-// block has a thread per (row, group) task (blockDim >= LR * LG, as every
-// launch plan gives): thread tid handles group tid % LG of row
-// rps*s + tid / LG.
+// rows go stale per sweep on each side), and only those are computed.  Under
+// the random colour order (order = 1) step q of the launch (K per sweep) draws
+// its colour and computes rows [q, LR - q).  The block has a thread per
+// (row, group) task (blockDim >= LR * LG, as every launch plan gives): thread
+// tid handles group tid % LG of row base + tid / LG.
 template <int MODE, int KIND>
 __device__ __forceinline__ void height_tile(uint32_t *lds, const uint32_t *__restrict__ in,
                                             uint32_t *__restrict__ out, size_t PS, uint32_t RS, uint32_t ng,
                                             uint32_t rows, uint32_t P, const Geo &geo, uint32_t t0,
                                             uint32_t nsweeps, uint32_t TR, uint32_t TG, uint32_t HR, uint32_t HG,
                                             uint32_t tile_r, uint32_t tile_g, const Thr &T, uint32_t k0,
-                                            uint32_t k1)
+                                            uint32_t k1, uint32_t order)
 {
     const uint32_t LR = TR + 2 * HR, LG = TG + 2 * HG, LRS = 4 * (LG + 2);
     const uint32_t LPS = LR * LRS;
@@ -374,9 +375,16 @@ __device__ __forceinline__ void height_tile(uint32_t *lds, const uint32_t *__res
     const uint32_t K_colours = geo.model == TL_LOZENGE ? 3u : 4u;
     const uint32_t rps = geo.model == TL_LOZENGE ? 3u : 2u;
     for (uint32_t s = 0; s < nsweeps; ++s) {
-        const uint32_t t = t0 + s;
-        const uint32_t base = HR ? rps * s : 0u, end = HR ? LR - rps * s : LR;
-        for (uint32_t c = 0; c < K_colours; ++c) {
+        for (uint32_t i = 0; i < K_colours; ++i) {
+            // colour, sweep counter of the draws and valid rows of this step
+            uint32_t c = i, t = t0 + s, base = HR ? rps * s : 0u, end = HR ? LR - rps * s : LR;
+            if (order) {
+                const uint32_t step = K_colours * t + i, q = K_colours * s + i;
+                c = step_colour(step, K_colours, k0, k1);
+                t = step;
+                base = HR ? q : 0u;
+                end = HR ? LR - q : LR;
+            }
             const uint32_t lr = base + r0;
             const int gr = R0 + (int)lr;
             if (lane && lr < end && lr >= 1 && lr + 1 < LR && site_row(geo, gr, rows))
@@ -403,11 +411,11 @@ __global__ void __launch_bounds__(kHeightThreads) height_tiled_kernel(const uint
                                                             uint32_t ng, uint32_t rows, uint32_t P, Geo geo,
                                                             uint32_t t0, uint32_t nsweeps, uint32_t TR, uint32_t TG,
                                                             uint32_t HR, uint32_t HG, uint32_t tiles_x, Thr T,
-                                                            uint32_t k0, uint32_t k1)
+                                                            uint32_t k0, uint32_t k1, uint32_t order)
 {
     extern __shared__ uint32_t lds[];
     height_tile<MODE, KIND>(lds, in, out, PS, RS, ng, rows, P, geo, t0, nsweeps, TR, TG, HR, HG, blockIdx.x / tiles_x,
-                      blockIdx.x % tiles_x, T, k0, k1);
+                      blockIdx.x % tiles_x, T, k0, k1, order);
 }
 
 // Multi-job kernel: work-group b runs tile items[b].tile of job items[b].job,
@@ -417,7 +425,7 @@ __device__ __forceinline__ void height_item(uint32_t *lds, const TileJob &j, uin
 {
     const Geo geo{j.model, j.a, j.b, j.c, j.N};
     height_tile<MODE, KIND>(lds, j.in, j.out, j.PS, j.RS, j.ng, j.rows, j.P, geo, j.t0, j.S, j.TR, j.TG, j.HR, j.HG,
-                      tile / j.tiles_x, tile % j.tiles_x, j.T, j.key0, j.key1);
+                      tile / j.tiles_x, tile % j.tiles_x, j.T, j.key0, j.key1, j.order);
 }
 
 template <int MODE, int KIND>
@@ -608,8 +616,11 @@ HeightTile height_auto_tile(const HeightDev &d)
 bool height_plan(const HeightDev &d, const HeightTile &tile, uint32_t S_max, TilePlan *p)
 {
     if (d.rows == 0 || S_max == 0) return false;
-    const uint32_t rows_per_sweep = d.model == TL_LOZENGE ? 3u : 2u;   // halo rows invalidated per sweep
-    const uint32_t cols_per_sweep = d.model == TL_LOZENGE ? 1u : 2u;   // halo sites (per plane) per sweep
+    // halo rows invalidated per sweep, halo sites (per plane) per sweep; under
+    // the random colour order each of the K steps may cost one of each
+    const uint32_t K = d.model == TL_LOZENGE ? 3u : 4u;
+    const uint32_t rows_per_sweep = tile.order ? K : (d.model == TL_LOZENGE ? 3u : 2u);
+    const uint32_t cols_per_sweep = tile.order ? K : (d.model == TL_LOZENGE ? 1u : 2u);
     const uint32_t TG = tile.TG == 0 ? 1u : (tile.TG < d.ng ? tile.TG : d.ng);
     const uint32_t tiles_x = (d.ng + TG - 1) / TG;
     const uint32_t LG0 = TG + (tiles_x > 1 ? 2u : 0u);
@@ -638,6 +649,7 @@ bool height_plan(const HeightDev &d, const HeightTile &tile, uint32_t S_max, Til
     p->tiles_y = tiles_y;
     p->threads = (tasks + 63) / 64 * 64;
     p->lds = lds;
+    p->order = tile.order;
     return true;
 }
 
@@ -654,7 +666,7 @@ hipError_t height_tiled_sweeps(HeightDev &d, const HeightTile &tile, uint32_t t0
         auto k = TL_HEIGHT_PICK(height_tiled_kernel, mode, (int)table_kind(T));
         hipError_t e = launch(tm, colours * p.S, k, dim3(p.tiles()), dim3(p.threads), p.lds, s,
                               (const uint32_t *)d.planes, d.spare, d.PS, d.RS, d.ng, d.rows, d.P, geo_of(d),
-                              t0 + done, p.S, p.TR, p.TG, p.HR, p.HG, p.tiles_x, T, k0, k1);
+                              t0 + done, p.S, p.TR, p.TG, p.HR, p.HG, p.tiles_x, T, k0, k1, p.order);
         if (e != hipSuccess) return e;
         uint32_t *tmp = d.planes;
         d.planes = d.spare;
@@ -688,6 +700,7 @@ TileJob height_tile_job(const HeightDev &d, const TilePlan &p, uint32_t t0, cons
     j.HR = p.HR;
     j.HG = p.HG;
     j.tiles_x = p.tiles_x;
+    j.order = p.order;
     j.mode = T.uniform() ? kModeUniform : (metropolis ? kModeMetropolis : kModeHeatBath);
     j.kind = T.uniform() ? (uint32_t)kTableClass : table_kind(T);
     j.key0 = (uint32_t)seed;

@@ -116,9 +116,12 @@ struct DominoDev {
 // halo left and right (a dimension covered by one tile needs no halo).
 struct DominoTile {
     uint32_t TR = 32, TG = 4, S = 8;
+    uint32_t order = 0;   // colour order: 0 fixed, 1 random per step
 };
 size_t domino_words(int n, uint32_t *ng, uint32_t *RS, size_t *PS);
 hipError_t domino_init(const DominoDev &d, int init_max, hipStream_t s);
+// One colour step; t is the sweep counter of the draws (the step index under
+// the random colour order).
 hipError_t domino_colour_step(const DominoDev &d, int colour, uint32_t t, const Thr &T, int metropolis,
                               uint64_t seed, hipStream_t s, Timing *tm = nullptr);
 // Sweeps t0 .. t0+n-1 with the tiled kernel; swaps d.planes / d.spare.
@@ -177,6 +180,7 @@ struct HeightDev {
 };
 struct HeightTile {
     uint32_t TR = 32, TG = 4, S = 8;
+    uint32_t order = 0;   // colour order: 0 fixed, 1 random per step
 };
 size_t height_words(HeightDev &d);
 hipError_t height_init(const HeightDev &d, int init_max, hipStream_t s);
@@ -196,6 +200,7 @@ hipError_t height_observe(const HeightDev &d, uint32_t B, uint32_t bins_x, unsig
 // thread and row pass), `lds` bytes of LDS per work-group.
 struct TilePlan {
     uint32_t S = 0, TR = 0, TG = 0, HR = 0, HG = 0, tiles_x = 0, tiles_y = 0, threads = 0, lds = 0;
+    uint32_t order = 0;   // colour order of the launch (the halo covers it)
     uint32_t tiles() const { return tiles_x * tiles_y; }
 };
 // Largest launch of at most S_max sweeps the tile shape allows (tile sizes
@@ -220,6 +225,7 @@ struct TileJob {
     uint32_t t0, S, TR, TG, HR, HG, tiles_x;
     uint32_t mode;                      // kMode*
     uint32_t kind;                      // kTable* (height models)
+    uint32_t order;                     // colour order: 0 fixed, 1 random per step
     uint32_t key0, key1;
     Thr T;                              // kernel table (heights: weight classes)
 };

@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include "models.hpp"
+#include "host_philox.hpp"
 #include "region.hpp"
 
 namespace tl {
@@ -25,7 +26,9 @@ public:
 
     std::unique_ptr<Model> twin() const override
     {
-        return std::unique_ptr<Model>(region_ ? new DominoModel(region_) : new DominoModel(d_.n));
+        std::unique_ptr<Model> m(region_ ? new DominoModel(region_) : new DominoModel(d_.n));
+        m->order = order;
+        return m;
     }
     hipError_t allocate() override
     {
@@ -53,6 +56,7 @@ public:
     {
         DominoTile tile = domino_auto_tile(d_.n);
         tile.S = S_max;
+        tile.order = order;
         if (!domino_plan(d_, tile, S_max, p)) return false;
         *j = domino_tile_job(d_, *p, t0, T, metro ? 1 : 0, seed);
         return true;
@@ -83,8 +87,11 @@ public:
     {
         if (opt.kernel == 1) {   // one launch per colour step
             for (uint32_t i = 0; i < n; ++i)
-                for (int c = 0; c < 2; ++c) {
-                    hipError_t e = domino_colour_step(d_, c, t0 + i, T, metro ? 1 : 0, seed, s, &timing);
+                for (uint32_t j = 0; j < 2; ++j) {
+                    const uint32_t step = 2u * (t0 + i) + j;
+                    const int c = order ? (int)host_step_colour(seed, step, 2u) : (int)j;
+                    hipError_t e = domino_colour_step(d_, c, order ? step : t0 + i, T, metro ? 1 : 0, seed, s,
+                                                      &timing);
                     if (e != hipSuccess) return e;
                 }
             return hipSuccess;
@@ -93,6 +100,7 @@ public:
         if (opt.tile_rows) tile.TR = opt.tile_rows;
         if (opt.tile_groups) tile.TG = opt.tile_groups;
         if (opt.sweeps_per_launch) tile.S = opt.sweeps_per_launch;
+        tile.order = order;
         return domino_tiled_sweeps(d_, tile, t0, n, T, metro ? 1 : 0, seed, s, &timing);
     }
     hipError_t observe(uint32_t B, uint32_t bins_x, unsigned long long *bins, hipStream_t s) override
@@ -216,7 +224,12 @@ public:
         d_.N = dom.n;
         height_words(d_);
     }
-    std::unique_ptr<Model> twin() const override { return std::unique_ptr<Model>(new HeightModel(dom_)); }
+    std::unique_ptr<Model> twin() const override
+    {
+        std::unique_ptr<Model> m(new HeightModel(dom_));
+        m->order = order;
+        return m;
+    }
     bool loz() const { return d_.model == TL_LOZENGE; }
     int width() const { return loz() ? d_.a + d_.c + 1 : d_.N + 1; }   // export row length
 
@@ -261,6 +274,7 @@ public:
             tile.TG = d_.ng <= 8u ? d_.ng : 4u;
         }
         tile.S = S_max;
+        tile.order = order;
         if (!height_plan(d_, tile, S_max, p)) return false;
         *j = height_tile_job(d_, *p, t0, kernel_table(T, metro), metro ? 1 : 0, seed);
         return true;
@@ -317,10 +331,13 @@ public:
     {
         const Thr K = kernel_table(T, metro);
         if (opt.kernel == 1) {
-            const int colours = loz() ? 3 : 4;
+            const uint32_t colours = loz() ? 3u : 4u;
             for (uint32_t i = 0; i < n; ++i)
-                for (int c = 0; c < colours; ++c) {
-                    hipError_t e = height_colour_step(d_, c, t0 + i, K, metro ? 1 : 0, seed, s, &timing);
+                for (uint32_t j = 0; j < colours; ++j) {
+                    const uint32_t step = colours * (t0 + i) + j;
+                    const int c = order ? (int)host_step_colour(seed, step, colours) : (int)j;
+                    hipError_t e = height_colour_step(d_, c, order ? step : t0 + i, K, metro ? 1 : 0, seed, s,
+                                                      &timing);
                     if (e != hipSuccess) return e;
                 }
             return hipSuccess;
@@ -329,6 +346,7 @@ public:
         if (opt.tile_rows) tile.TR = opt.tile_rows;
         if (opt.tile_groups) tile.TG = opt.tile_groups;
         if (opt.sweeps_per_launch) tile.S = opt.sweeps_per_launch;
+        tile.order = order;
         return height_tiled_sweeps(d_, tile, t0, n, K, metro ? 1 : 0, seed, s, &timing);
     }
     hipError_t observe(uint32_t B, uint32_t bins_x, unsigned long long *bins, hipStream_t s) override

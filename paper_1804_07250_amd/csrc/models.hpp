@@ -49,6 +49,10 @@ public:
     // Current state buffer (state_words() words; equal buffers <=> equal states).
     virtual const uint32_t *state() const = 0;
     Timing timing;
+    // Colour order of sweeps and tile jobs: 0 = colours 0..K-1 in every sweep,
+    // 1 = a random colour per step (step s = K t + i draws its colour and uses
+    // sweep counter s for its site draws).
+    uint32_t order = 0;
 };
 
 // nullptr on error, with why set and *status (nullable) the error code:
