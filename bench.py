@@ -68,6 +68,9 @@ def parse():
     p.add_argument("--served-slots", type=int, default=64)
     p.add_argument("--served-quantum", type=int, default=8, help="sweeps per tick of a weighted request")
     p.add_argument("--no-cftp", action="store_true")
+    p.add_argument("--no-variants", action="store_true",
+                   help="skip the random-colour-order and general-domain legs of the plain workload")
+    p.add_argument("--domain-side", type=int, default=2048, help="side of the square domain leg")
     p.add_argument("--cftp-n", type=int, default=128, help="six-vertex DWBC size for coupling from the past")
     p.add_argument("--cftp-aztec", type=int, default=64, help="Aztec order for coupling from the past")
     p.add_argument("--cftp-samples", type=int, default=2)
@@ -172,6 +175,46 @@ def run_cftp(tl, args):
     out["workload"] = ("coupling from the past: six-vertex DWBC %dx%d with (a,b,c) = (1,1,1) and the uniform "
                        "Aztec diamond of order %d, seeds 0..%d, doubling from 2 sweeps"
                        % (args.cftp_n, args.cftp_n, args.cftp_aztec, args.cftp_samples - 1))
+    return out
+
+
+def run_variants(tl, wl, args):
+    """The plain domino workload under the random colour order, and the same
+    sweeps on a square domain given by a mask (start T_min), each timed over
+    args.steps jobs after one warm-up job."""
+    import numpy as np
+    out = {}
+    side = args.domain_side
+    legs = [("random_order", tl.domain(tl.TL_DOMINO, n=wl["n"]), 1, 2 * wl["n"] ** 2 - 2 * wl["n"] + 1),
+            ("square_domain", tl.domain(tl.TL_DOMINO, mask=np.ones((side, side), dtype=np.uint8)), 0, None)]
+    for name, dom, order, sites in legs:
+        t_make = time.perf_counter()
+        s = tl.Sampler(dom, tl.weights(tl.TL_W_UNIFORM), wl["seed"],
+                       tl.options(obs_every=wl["obs_every"], obs_bin=wl["obs_bin"], colour_order=order))
+        t_make = time.perf_counter() - t_make
+        sites = s.info()[0]
+
+        def job():
+            s.reset(wl["seed"])
+            s.sweep(wl["sweeps"])
+            s.observables()
+            return s.hash()
+
+        job()
+        s.sync()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            digest = job()
+        s.sync()
+        el = time.perf_counter() - t0
+        s.destroy()
+        out[name] = {"value": sites * wl["sweeps"] * args.steps / el, "unit": "site-updates/s",
+                     "ms_per_step": el / args.steps * 1e3, "sites": sites, "hash": digest,
+                     "create_s": round(t_make, 3)}
+    out["workload"] = ("the plain domino job (%d sweeps, density bins, row hash) with a random colour per step on "
+                       "the order-%d Aztec diamond, and with the fixed order on the %dx%d square domain (mask, "
+                       "T_min start; create_s includes the host tileability pre-pass)"
+                       % (wl["sweeps"], wl["n"], side, side))
     return out
 
 
@@ -331,6 +374,9 @@ def main():
         print(json.dumps({"sweeps_only_s_per_step": el / args.steps, "kernel_ms": kms, "launches": launches}))
         return
     s.destroy()
+    if not args.no_variants and wl["model"] == "domino":
+        out["variants"] = run_variants(tl, wl, args)
+        print("variants done", file=sys.stderr, flush=True)
     if not args.no_batched:
         out["batched"] = run_batched(tl, args)
         print("batched done", file=sys.stderr, flush=True)
