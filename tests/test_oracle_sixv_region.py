@@ -1,0 +1,244 @@
+"""Pins for the oracle's six-vertex model on general domains (Section 1.2 with
+the domains of Section 1.1; the L-shaped example with domain-wall type
+boundary).
+
+* on the N x N square the boundary heights are the domain-wall ones, the
+  extremes are |I - J| and N - |I + J - N|, and the chain equals the
+  domain-wall oracle bit for bit (same draws, moves and contexts);
+* a brute-force enumerator of height functions (checked against the ASM
+  numbers on squares) decides which domains admit a configuration, and the
+  extremes are the pointwise max / min over everything it finds;
+* flips from either extreme reach every enumerated configuration, the
+  chain's law on an L-shape is prod w(vertex) (chi-square), and coupling
+  from the past coalesces from every state.
+"""
+import math
+from collections import Counter
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle_helpers import bfs, chi_square_pvalue
+from test_oracle_cftp import chi_square_of_samples, run_from
+from test_oracle_region import accepted, l_shape, ones, random_domain
+import test_oracle_sixvertex as tos
+
+I32MIN = np.iinfo(np.int32).min
+
+
+def enumerate_configs(mask):
+    """Every height function of the domain (brute force): sites in row-major
+    order take a value one away from their west and south neighbours (both
+    already known), the east and north neighbours that are fixed are checked,
+    and a complete assignment is kept if every cell side joins heights one
+    apart."""
+    pts, sites = oracle.sixv_points(mask)
+    hb = oracle.sixv_boundary_heights(mask)
+    H = np.full(pts.shape, I32MIN, dtype=np.int64)
+    for (I, J), v in hb.items():
+        H[J, I] = v
+    order = [(I, J) for J in range(pts.shape[0]) for I in range(pts.shape[1]) if sites[J, I]]
+    fixed = {(I, J) for (I, J) in hb}
+    out = []
+
+    m = np.asarray(mask, dtype=bool)
+
+    def valid():
+        # every side of every cell of the domain joins heights one apart
+        for y, x in zip(*np.nonzero(m)):
+            c = H[y:y + 2, x:x + 2]
+            if abs(c[0, 0] - c[0, 1]) != 1 or abs(c[1, 0] - c[1, 1]) != 1 or abs(c[0, 0] - c[1, 0]) != 1 \
+                    or abs(c[0, 1] - c[1, 1]) != 1:
+                return False
+        return True
+
+    def rec(i):
+        if i == len(order):
+            if valid():
+                out.append(H.copy())
+            return
+        I, J = order[i]
+        for v in (H[J, I - 1] - 1, H[J, I - 1] + 1):
+            if abs(v - H[J - 1, I]) != 1:
+                continue
+            if (I + 1, J) in fixed and abs(v - H[J, I + 1]) != 1:
+                continue
+            if (I, J + 1) in fixed and abs(v - H[J + 1, I]) != 1:
+                continue
+            H[J, I] = v
+            rec(i + 1)
+        H[J, I] = I32MIN
+
+    rec(0)
+    return out
+
+
+def vertex_weight(mask, H, a, b, c):
+    """prod over the domain's cells of a, b or c by the vertex type read off
+    the edge occupancy (a: none or all four, b: left+right or bottom+top,
+    c: bottom+left or right+top)."""
+    vert = (H[:, 1:] - H[:, :-1]) == 1
+    horz = (H[1:, :] - H[:-1, :]) == 1
+    w = Fraction(1)
+    for y, x in zip(*np.nonzero(mask)):
+        e = (bool(horz[y, x]), bool(horz[y, x + 1]), bool(vert[y, x]), bool(vert[y + 1, x]))
+        if e in ((False, False, False, False), (True, True, True, True)):
+            w *= a
+        elif e in ((True, True, False, False), (False, False, True, True)):
+            w *= b
+        elif e in ((True, False, True, False), (False, True, False, True)):
+            w *= c
+        else:
+            raise AssertionError("not a six-vertex configuration")
+    return w
+
+
+def chain(mask, thr=None, seed=1, init="min", **kw):
+    return oracle.SixVertexRegionOracle(mask, thr if thr is not None else tos.thr(1, 1, 1), seed=seed, init=init,
+                                        **kw)
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 9])
+def test_square_is_the_domain_wall_square(N):
+    m = ones(N, N)
+    hmax, hmin = oracle.sixv_extremal_heights(m)
+    I, J = np.meshgrid(np.arange(N + 1), np.arange(N + 1))
+    assert (hmin == np.abs(I - J)).all() and (hmax == N - np.abs(I + J - N)).all()
+    d = oracle.SixVertexOracle(N, tos.thr(1, 1, 1))
+    hb = oracle.sixv_boundary_heights(m)
+    for (i, j), v in hb.items():
+        assert d.export()[j, i] == v
+
+
+@pytest.mark.parametrize("w2,metro,random", [((1, 1, 2), False, False), ((4, 1, 4), True, False),
+                                             ((1, 1, 1), False, True)])
+def test_square_chain_equals_the_domain_wall_chain(w2, metro, random):
+    N = 12
+    thr = oracle.table_from_ratios(oracle.sixv_ratios(int(round(w2[0] ** 0.5)), int(round(w2[1] ** 0.5)), w2[2]),
+                                   metro)
+    for init in ("min", "max"):
+        a = chain(ones(N, N), thr, seed=5, init=init, metropolis=metro, random_colours=random)
+        b = oracle.SixVertexOracle(N, thr, metropolis=metro, seed=5, init=init, random_colours=random)
+        for k in (1, 3, 8):
+            a.sweep(k)
+            b.sweep(k)
+            assert (a.export() == b.export()).all()
+
+
+@pytest.mark.parametrize("N,asm", [(1, 1), (2, 2), (3, 7), (4, 42), (5, 429)])
+def test_enumerator_counts_alternating_sign_matrices(N, asm):
+    assert len(enumerate_configs(ones(N, N))) == asm
+
+
+def check_against_enumeration(m):
+    try:
+        hmax, hmin = oracle.sixv_extremal_heights(m)
+    except oracle.Untileable:
+        try:
+            configs = enumerate_configs(m)
+        except oracle.Untileable:
+            return 0
+        assert configs == []
+        return 0
+    configs = enumerate_configs(m)
+    assert configs
+    stack = np.stack(configs)
+    pts = hmax != I32MIN
+    assert (stack.max(axis=0)[pts] == hmax[pts]).all() and (stack.min(axis=0)[pts] == hmin[pts]).all()
+    keys = {c.tobytes() for c in configs}
+    assert hmax.tobytes() in keys and hmin.tobytes() in keys
+    # flips from either extreme reach every configuration
+    for init in ("min", "max"):
+        ch = chain(m, init=init)
+        get = lambda: ch.H.copy()
+
+        def put(s):
+            ch.H[:] = s
+
+        seen = bfs(ch, get, put, lambda: ch.export().astype(np.int64).tobytes())
+        assert set(seen) == keys
+    return len(configs)
+
+
+@pytest.mark.parametrize("name", ["l4", "l5", "l6b", "rect3x5", "rect4x2", "t"])
+def test_named_domains(name):
+    t = ones(4, 5)
+    t[:2, :2] = False
+    t[:2, 3:] = False
+    m = {"l4": l_shape(4, 2, 2), "l5": l_shape(5, 2, 3), "l6b": l_shape(6, 3, 3), "rect3x5": ones(3, 5),
+         "rect4x2": ones(4, 2), "t": t}[name]
+    check_against_enumeration(m)
+
+
+def test_l_shapes():
+    # square minus a corner block: thick arms admit configurations, thin ones
+    # (fewer cells to route the entering paths through) may not
+    counts = {}
+    for a in range(2, 7):
+        for b in range(1, a):
+            for c in range(1, a):
+                counts[(a, b, c)] = check_against_enumeration(l_shape(a, b, c))
+    assert counts[(4, 2, 2)] > 0 and counts[(6, 3, 3)] > 0 and counts[(3, 2, 2)] == 0
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_random_domains(seed):
+    rng = np.random.default_rng(seed)
+    m = random_domain(rng, 4 + seed % 3, 4, 0.7)
+    check_against_enumeration(m)
+
+
+def test_some_domains_have_no_configuration():
+    found = 0
+    for bits in range(1, 1 << 9):
+        m = np.array([(bits >> i) & 1 for i in range(9)], dtype=bool).reshape(3, 3)
+        if not accepted(m):
+            continue
+        try:
+            oracle.sixv_extremal_heights(m)
+        except oracle.Untileable:
+            found += 1
+            continue
+    assert found > 0
+    # a 2 x 1 domino of cells: two paths enter (south, west) but three legs leave
+    with pytest.raises(oracle.Untileable):
+        oracle.sixv_extremal_heights(ones(1, 2))
+
+
+def test_law_on_an_l_shape():
+    m = l_shape(5, 2, 3)
+    configs = enumerate_configs(m)
+    w = {c.astype(np.int64).tobytes(): math.sqrt(vertex_weight(m, c, 1, 1, 2)) for c in configs}
+    Z = sum(w.values())
+    probs = {k: v / Z for k, v in w.items()}
+    ch = chain(m, tos.thr(1, 1, 2), seed=31)
+
+    class View:
+        def sweep(self, n):
+            ch.sweep(n)
+
+        def export(self):
+            return ch.export().astype(np.int64)
+
+    assert chi_square_pvalue(View(), probs, 8000, 4) > 1e-3
+
+
+def test_cftp_on_an_l_shape():
+    m = l_shape(5, 2, 3)
+    states = enumerate_configs(m)
+    for seed in range(4):
+        make = lambda init, s=seed: chain(m, tos.thr(1, 1, 2), seed=s, init=init)
+        R, sample = oracle.cftp(make)
+        for st in states:
+            assert np.array_equal(run_from(make, st, R), sample)
+
+
+def test_observables_on_a_domain():
+    m = l_shape(8, 3, 4)
+    ch = chain(m, seed=2, obs_every=2, bin_=3)
+    ch.sweep(9)
+    v, bs = ch.observe()
+    assert v == int(oracle.sixv_c_vertices(m, ch.export()).sum()) and bs.sum() == v
+    assert int(ch.samples[0]) == 4
