@@ -522,8 +522,8 @@ tl_status tl_sampler_cftp(tl_sampler *s, uint32_t max_log2, tl_cftp_info *out)
         if (err == hipSuccess)
             err = s->model->height_family()
                       ? tl::height_items(d_jobs + 2 * slot, d_items, 2, pb.threads, pb.lds, h_jobs[2 * slot].mode,
-                                         h_jobs[2 * slot].kind, s->stream)
-                      : tl::domino_items(d_jobs + 2 * slot, d_items, 2, pb.threads, pb.lds, s->stream);
+                                         h_jobs[2 * slot].kind, pb.order, s->stream)
+                      : tl::domino_items(d_jobs + 2 * slot, d_items, 2, pb.threads, pb.lds, pb.order, s->stream);
         if (err == hipSuccess) {
             s->model->swap_buffers();
             top->swap_buffers();

@@ -294,16 +294,16 @@ __global__ void __launch_bounds__(256) domino_other_step(uint32_t *planes, size_
 // `out`.  Halo cells repeat their neighbours' keyed draws, so the interior
 // matches the sweep of the whole state; halo rows go stale one per sweep from
 // each side, so sweep s computes only rows [s, LR - s).  Under the random
-// colour order (order = 1) step q of the launch (2 per sweep) draws its colour
+// colour order (RANDOM) step q of the launch (2 per sweep) draws its colour
 // and computes rows [q, LR - q), the halo covering 2 rows per sweep.  The block
 // has a thread per (row, group) task (blockDim >= LR * LG, as every launch
 // plan gives): thread tid handles group tid % LG of row base + tid / LG.
-template <int MODE>
+template <int MODE, bool RANDOM>
 __device__ __forceinline__ void domino_tile(uint32_t *lds, const uint32_t *__restrict__ in,
                                             uint32_t *__restrict__ out, size_t PS, uint32_t RS, uint32_t ng,
                                             uint32_t n, uint32_t omega, uint32_t t0, uint32_t nsweeps, uint32_t TR,
                                             uint32_t TG, uint32_t HR, uint32_t HG, uint32_t tile_r, uint32_t tile_g,
-                                            const Thr &Tall, uint32_t key0, uint32_t key1, uint32_t order)
+                                            const Thr &Tall, uint32_t key0, uint32_t key1)
 {
     const uint32_t LR = TR + 2 * HR, LG = TG + 2 * HG, LRS = 4 * LG + 4;
     const uint32_t LPS = LR * LRS;
@@ -329,7 +329,7 @@ __device__ __forceinline__ void domino_tile(uint32_t *lds, const uint32_t *__res
         for (uint32_t i = 0; i < 2; ++i) {
             // colour, sweep counter of the draws and valid rows of this step
             uint32_t c = i, t = t0 + s, base = HR ? s : 0u, end = HR ? LR - s : LR;
-            if (order) {
+            if constexpr (RANDOM) {
                 const uint32_t step = 2u * t + i, q = 2u * s + i;
                 c = step_colour(step, 2u, key0, key1);
                 t = step;
@@ -364,28 +364,30 @@ __device__ __forceinline__ void domino_tile(uint32_t *lds, const uint32_t *__res
 }
 
 // Tiled multi-sweep kernel of one state: one work-group per tile.
-template <int MODE>
+template <int MODE, bool RANDOM>
 __global__ void __launch_bounds__(1024) domino_tiled_kernel(const uint32_t *__restrict__ in,
                                                             uint32_t *__restrict__ out, size_t PS, uint32_t RS,
                                                             uint32_t ng, uint32_t n, uint32_t omega, uint32_t t0,
                                                             uint32_t nsweeps, uint32_t TR, uint32_t TG,
                                                             uint32_t HR, uint32_t HG, uint32_t tiles_x,
-                                                            Thr Tall, uint32_t key0, uint32_t key1, uint32_t order)
+                                                            Thr Tall, uint32_t key0, uint32_t key1)
 {
     extern __shared__ uint32_t lds[];
-    domino_tile<MODE>(lds, in, out, PS, RS, ng, n, omega, t0, nsweeps, TR, TG, HR, HG, blockIdx.x / tiles_x,
-                      blockIdx.x % tiles_x, Tall, key0, key1, order);
+    domino_tile<MODE, RANDOM>(lds, in, out, PS, RS, ng, n, omega, t0, nsweeps, TR, TG, HR, HG, blockIdx.x / tiles_x,
+                              blockIdx.x % tiles_x, Tall, key0, key1);
 }
 
 // Multi-job kernel: work-group b runs tile items[b].tile of job items[b].job,
 // with that job's plan, thresholds and key.
-template <int MODE>
+template <int MODE, bool RANDOM>
 __device__ __forceinline__ void domino_item(uint32_t *lds, const TileJob &j, uint32_t tile)
 {
-    domino_tile<MODE>(lds, j.in, j.out, j.PS, j.RS, j.ng, j.rows, (uint32_t)j.omega, j.t0, j.S, j.TR, j.TG, j.HR,
-                      j.HG, tile / j.tiles_x, tile % j.tiles_x, j.T, j.key0, j.key1, j.order);
+    domino_tile<MODE, RANDOM>(lds, j.in, j.out, j.PS, j.RS, j.ng, j.rows, (uint32_t)j.omega, j.t0, j.S, j.TR, j.TG,
+                              j.HR, j.HG, tile / j.tiles_x, tile % j.tiles_x, j.T, j.key0, j.key1);
 }
 
+// Every job of a launch has the colour order RANDOM.
+template <bool RANDOM>
 __global__ void __launch_bounds__(1024) domino_items_kernel(const TileJob *__restrict__ jobs,
                                                             const TileItem *__restrict__ items)
 {
@@ -393,11 +395,11 @@ __global__ void __launch_bounds__(1024) domino_items_kernel(const TileJob *__res
     const TileItem it = items[blockIdx.x];
     const TileJob &j = jobs[it.job];
     if (j.mode == kUniform)
-        domino_item<kUniform>(lds, j, it.tile);
+        domino_item<kUniform, RANDOM>(lds, j, it.tile);
     else if (j.mode == kMetropolis)
-        domino_item<kMetropolis>(lds, j, it.tile);
+        domino_item<kMetropolis, RANDOM>(lds, j, it.tile);
     else
-        domino_item<kHeatBath>(lds, j, it.tile);
+        domino_item<kHeatBath, RANDOM>(lds, j, it.tile);
 }
 
 // ------------------------------------------------------------ batched chains
@@ -731,11 +733,15 @@ hipError_t domino_tiled_sweeps(DominoDev &d, const DominoTile &tile, uint32_t t0
     while (done < nsw) {
         TilePlan p;
         if (!domino_plan(d, tile, nsw - done, &p)) return hipErrorInvalidConfiguration;
-        auto k = T.uniform() ? domino_tiled_kernel<kUniform>
-                             : (metropolis ? domino_tiled_kernel<kMetropolis> : domino_tiled_kernel<kHeatBath>);
+        auto k = p.order ? (T.uniform() ? domino_tiled_kernel<kUniform, true>
+                                        : (metropolis ? domino_tiled_kernel<kMetropolis, true>
+                                                      : domino_tiled_kernel<kHeatBath, true>))
+                         : (T.uniform() ? domino_tiled_kernel<kUniform, false>
+                                        : (metropolis ? domino_tiled_kernel<kMetropolis, false>
+                                                      : domino_tiled_kernel<kHeatBath, false>));
         hipError_t e = launch(tm, 2 * p.S, k, dim3(p.tiles()), dim3(p.threads), p.lds, s, (const uint32_t *)d.planes,
                               d.spare, d.PS, d.RS, d.ng, (uint32_t)d.n, (uint32_t)d.omega, t0 + done, p.S, p.TR,
-                              p.TG, p.HR, p.HG, p.tiles_x, T, key0, key1, p.order);
+                              p.TG, p.HR, p.HG, p.tiles_x, T, key0, key1);
         if (e != hipSuccess) return e;
         uint32_t *tmp = d.planes;
         d.planes = d.spare;
@@ -773,11 +779,14 @@ TileJob domino_tile_job(const DominoDev &d, const TilePlan &p, uint32_t t0, cons
 }
 
 hipError_t domino_items(const TileJob *jobs, const TileItem *items, uint32_t n_items, uint32_t threads, uint32_t lds,
-                        hipStream_t s)
+                        uint32_t order, hipStream_t s)
 {
     if (n_items == 0) return hipSuccess;
     if (threads == 0 || threads > 1024u || lds > 160u * 1024u) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(domino_items_kernel, dim3(n_items), dim3(threads), lds, s, jobs, items);
+    if (order)
+        hipLaunchKernelGGL(domino_items_kernel<true>, dim3(n_items), dim3(threads), lds, s, jobs, items);
+    else
+        hipLaunchKernelGGL(domino_items_kernel<false>, dim3(n_items), dim3(threads), lds, s, jobs, items);
     return hipGetLastError();
 }
 

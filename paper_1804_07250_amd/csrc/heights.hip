@@ -67,6 +67,11 @@ static_assert(kKindClass == kTableClass && kKindSum == kTableSum, "table layouts
     ((mode) == kUniform ? KERNEL<kUniform, kKindClass>                                          \
      : (mode) == kMetropolis ? KERNEL<kMetropolis, kKindClass>                                  \
      : (kind) == kKindSum ? KERNEL<kHeatBath, kKindSum> : KERNEL<kHeatBath, kKindClass>)
+// The same with the colour order as a third parameter (random: true).
+#define TL_HEIGHT_PICK_R(KERNEL, mode, kind, R)                                                 \
+    ((mode) == kUniform ? KERNEL<kUniform, kKindClass, R>                                       \
+     : (mode) == kMetropolis ? KERNEL<kMetropolis, kKindClass, R>                               \
+     : (kind) == kKindSum ? KERNEL<kHeatBath, kKindSum, R> : KERNEL<kHeatBath, kKindClass, R>)
 
 struct Geo {
     int model, a, b, c, N;
@@ -340,17 +345,17 @@ __global__ void __launch_bounds__(256) height_step_kernel(uint32_t *planes, size
 // row lr is global row R0 + lr, local group lg is global group G0 + lg.  With a
 // row halo, the rows still valid before sweep s are [rps*s, LR - rps*s) (rps
 // rows go stale per sweep on each side), and only those are computed.  Under
-// the random colour order (order = 1) step q of the launch (K per sweep) draws
+// the random colour order (RANDOM) step q of the launch (K per sweep) draws
 // its colour and computes rows [q, LR - q).  The block has a thread per
 // (row, group) task (blockDim >= LR * LG, as every launch plan gives): thread
 // tid handles group tid % LG of row base + tid / LG.
-template <int MODE, int KIND>
+template <int MODE, int KIND, bool RANDOM>
 __device__ __forceinline__ void height_tile(uint32_t *lds, const uint32_t *__restrict__ in,
                                             uint32_t *__restrict__ out, size_t PS, uint32_t RS, uint32_t ng,
                                             uint32_t rows, uint32_t P, const Geo &geo, uint32_t t0,
                                             uint32_t nsweeps, uint32_t TR, uint32_t TG, uint32_t HR, uint32_t HG,
                                             uint32_t tile_r, uint32_t tile_g, const Thr &T, uint32_t k0,
-                                            uint32_t k1, uint32_t order)
+                                            uint32_t k1)
 {
     const uint32_t LR = TR + 2 * HR, LG = TG + 2 * HG, LRS = 4 * (LG + 2);
     const uint32_t LPS = LR * LRS;
@@ -378,7 +383,7 @@ __device__ __forceinline__ void height_tile(uint32_t *lds, const uint32_t *__res
         for (uint32_t i = 0; i < K_colours; ++i) {
             // colour, sweep counter of the draws and valid rows of this step
             uint32_t c = i, t = t0 + s, base = HR ? rps * s : 0u, end = HR ? LR - rps * s : LR;
-            if (order) {
+            if constexpr (RANDOM) {
                 const uint32_t step = K_colours * t + i, q = K_colours * s + i;
                 c = step_colour(step, K_colours, k0, k1);
                 t = step;
@@ -405,30 +410,31 @@ __device__ __forceinline__ void height_tile(uint32_t *lds, const uint32_t *__res
 }
 
 // Tiled multi-sweep kernel of one state: one work-group per tile.
-template <int MODE, int KIND>
+template <int MODE, int KIND, bool RANDOM>
 __global__ void __launch_bounds__(kHeightThreads) height_tiled_kernel(const uint32_t *__restrict__ in,
                                                             uint32_t *__restrict__ out, size_t PS, uint32_t RS,
                                                             uint32_t ng, uint32_t rows, uint32_t P, Geo geo,
                                                             uint32_t t0, uint32_t nsweeps, uint32_t TR, uint32_t TG,
                                                             uint32_t HR, uint32_t HG, uint32_t tiles_x, Thr T,
-                                                            uint32_t k0, uint32_t k1, uint32_t order)
+                                                            uint32_t k0, uint32_t k1)
 {
     extern __shared__ uint32_t lds[];
-    height_tile<MODE, KIND>(lds, in, out, PS, RS, ng, rows, P, geo, t0, nsweeps, TR, TG, HR, HG, blockIdx.x / tiles_x,
-                      blockIdx.x % tiles_x, T, k0, k1, order);
+    height_tile<MODE, KIND, RANDOM>(lds, in, out, PS, RS, ng, rows, P, geo, t0, nsweeps, TR, TG, HR, HG,
+                                    blockIdx.x / tiles_x, blockIdx.x % tiles_x, T, k0, k1);
 }
 
 // Multi-job kernel: work-group b runs tile items[b].tile of job items[b].job,
 // with that job's geometry, plan, thresholds and key.
-template <int MODE, int KIND>
+template <int MODE, int KIND, bool RANDOM>
 __device__ __forceinline__ void height_item(uint32_t *lds, const TileJob &j, uint32_t tile)
 {
     const Geo geo{j.model, j.a, j.b, j.c, j.N};
-    height_tile<MODE, KIND>(lds, j.in, j.out, j.PS, j.RS, j.ng, j.rows, j.P, geo, j.t0, j.S, j.TR, j.TG, j.HR, j.HG,
-                      tile / j.tiles_x, tile % j.tiles_x, j.T, j.key0, j.key1, j.order);
+    height_tile<MODE, KIND, RANDOM>(lds, j.in, j.out, j.PS, j.RS, j.ng, j.rows, j.P, geo, j.t0, j.S, j.TR, j.TG, j.HR,
+                                    j.HG, tile / j.tiles_x, tile % j.tiles_x, j.T, j.key0, j.key1);
 }
 
-template <int MODE, int KIND>
+// Every job of a launch has the colour order RANDOM.
+template <int MODE, int KIND, bool RANDOM>
 __global__ void __launch_bounds__(kHeightThreads) height_items_kernel(const TileJob *__restrict__ jobs,
                                                                       const TileItem *__restrict__ items)
 {
@@ -438,11 +444,11 @@ __global__ void __launch_bounds__(kHeightThreads) height_items_kernel(const Tile
     if constexpr (MODE == kHeatBath) {
         // one-bit jobs share the heat-bath launches (the lighter kernel body)
         if (j.mode == kUniform) {
-            height_item<kUniform, kKindClass>(lds, j, it.tile);
+            height_item<kUniform, kKindClass, RANDOM>(lds, j, it.tile);
             return;
         }
     }
-    height_item<MODE, KIND>(lds, j, it.tile);
+    height_item<MODE, KIND, RANDOM>(lds, j, it.tile);
 }
 
 __device__ __forceinline__ uint32_t hbit(const uint32_t *pl, size_t PS, uint32_t RS, uint32_t p, uint32_t y,
@@ -663,10 +669,11 @@ hipError_t height_tiled_sweeps(HeightDev &d, const HeightTile &tile, uint32_t t0
         TilePlan p;
         if (!height_plan(d, tile, nsw - done, &p)) return hipErrorInvalidConfiguration;
         const int mode = T.uniform() ? kUniform : (metropolis ? kMetropolis : kHeatBath);
-        auto k = TL_HEIGHT_PICK(height_tiled_kernel, mode, (int)table_kind(T));
+        auto k = p.order ? TL_HEIGHT_PICK_R(height_tiled_kernel, mode, (int)table_kind(T), true)
+                         : TL_HEIGHT_PICK_R(height_tiled_kernel, mode, (int)table_kind(T), false);
         hipError_t e = launch(tm, colours * p.S, k, dim3(p.tiles()), dim3(p.threads), p.lds, s,
                               (const uint32_t *)d.planes, d.spare, d.PS, d.RS, d.ng, d.rows, d.P, geo_of(d),
-                              t0 + done, p.S, p.TR, p.TG, p.HR, p.HG, p.tiles_x, T, k0, k1, p.order);
+                              t0 + done, p.S, p.TR, p.TG, p.HR, p.HG, p.tiles_x, T, k0, k1);
         if (e != hipSuccess) return e;
         uint32_t *tmp = d.planes;
         d.planes = d.spare;
@@ -710,12 +717,13 @@ TileJob height_tile_job(const HeightDev &d, const TilePlan &p, uint32_t t0, cons
 }
 
 hipError_t height_items(const TileJob *jobs, const TileItem *items, uint32_t n_items, uint32_t threads, uint32_t lds,
-                        uint32_t mode, uint32_t kind, hipStream_t s)
+                        uint32_t mode, uint32_t kind, uint32_t order, hipStream_t s)
 {
     if (n_items == 0) return hipSuccess;
     if (threads == 0 || threads > kHeightThreads || lds > 160u * 1024u || mode > 2u || kind > 1u)
         return hipErrorInvalidConfiguration;
-    auto k = TL_HEIGHT_PICK(height_items_kernel, (int)mode, (int)kind);
+    auto k = order ? TL_HEIGHT_PICK_R(height_items_kernel, (int)mode, (int)kind, true)
+                   : TL_HEIGHT_PICK_R(height_items_kernel, (int)mode, (int)kind, false);
     hipLaunchKernelGGL(k, dim3(n_items), dim3(threads), lds, s, jobs, items);
     return hipGetLastError();
 }

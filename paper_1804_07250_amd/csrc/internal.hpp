@@ -238,12 +238,13 @@ TileJob height_tile_job(const HeightDev &d, const TilePlan &p, uint32_t t0, cons
                         uint64_t seed);
 // One launch over items[0..n_items) (device arrays): threads and LDS bytes per
 // work-group at least the largest any item's plan asks for.
+// Every job of a launch has colour order `order`.
 hipError_t domino_items(const TileJob *jobs, const TileItem *items, uint32_t n_items, uint32_t threads,
-                        uint32_t lds, hipStream_t s);
+                        uint32_t lds, uint32_t order, hipStream_t s);
 // Height items of one launch share one rule and one table kind (one kernel
 // instantiation each); a heat-bath launch also runs one-bit jobs.
 hipError_t height_items(const TileJob *jobs, const TileItem *items, uint32_t n_items, uint32_t threads,
-                        uint32_t lds, uint32_t mode, uint32_t kind, hipStream_t s);
+                        uint32_t lds, uint32_t mode, uint32_t kind, uint32_t order, hipStream_t s);
 
 // ----------------------------------------------------------------- hashing
 // SHA-256 of each of `rows` rows of `row_bytes` bytes at `data` (device), into

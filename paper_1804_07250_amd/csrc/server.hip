@@ -404,11 +404,12 @@ bool tick(tl_server *sv)
         for (const Group &gr : groups) {
             if (e != hipSuccess) break;
             if (gr.key == 100u)
-                e = tl::domino_items(sv->d_jobs, sv->d_items + gr.first, gr.count, gr.threads, gr.lds, sv->stream);
+                e = tl::domino_items(sv->d_jobs, sv->d_items + gr.first, gr.count, gr.threads, gr.lds, 0u,
+                                     sv->stream);
             else
                 e = tl::height_items(sv->d_jobs, sv->d_items + gr.first, gr.count, gr.threads, gr.lds,
                                      gr.key >= 3u ? (uint32_t)tl::kModeMetropolis : (uint32_t)tl::kModeHeatBath,
-                                     gr.key % 3u, sv->stream);
+                                     gr.key % 3u, 0u, sv->stream);
         }
     }
     for (size_t i = 0; i < run.size(); ++i) {
