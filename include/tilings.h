@@ -320,12 +320,13 @@ tl_status tl_server_destroy(tl_server *sv);
  * NE=1, NW=2, SW=4, SE=8.  Writes up to cap entries, the count in *count. */
 tl_status tl_thresholds(const tl_domain *dom, const tl_weights *w, uint32_t *out, uint32_t cap, uint32_t *count);
 
-/* Thurston's tileability test and the extremal tilings of a TL_MASK domino
- * domain (Section 1.1), on the host (no device work): the canonical exports of
- * T_max and T_min (h x w bytes each, caller-owned, either may be NULL) in the
- * height convention stated with TL_MASK.  Errors: TL_EINVAL (not a mask domain,
- * bad mask, buffers smaller than w*h bytes), TL_EUNTILEABLE. */
-tl_status tl_domain_extremes(const tl_domain *dom, uint8_t *tmax, uint8_t *tmin, size_t bytes);
+/* Extremal states of a TL_MASK domain on the host (no device work), as
+ * canonical exports (caller-owned buffers of `bytes` bytes each, either may be
+ * NULL): dominoes, Thurston's tileability test and T_max / T_min (Section 1.1;
+ * h x w bytes, height convention stated with TL_MASK); six-vertex, h_max and
+ * h_min of the domain-wall type boundary ((h+1) x (w+1) int32).  Errors:
+ * TL_EINVAL (not a mask domain, bad mask, buffers too small), TL_EUNTILEABLE. */
+tl_status tl_domain_extremes(const tl_domain *dom, void *max_out, void *min_out, size_t bytes);
 
 const char *tl_status_str(tl_status st);
 const char *tl_last_error(void);

@@ -131,13 +131,16 @@ def domain(model, n=0, a=0, b=0, c=0, init=TL_INIT_MIN, mask=None):
 
 
 def domain_extremes(dom):
-    """(T_max, T_min) of a mask domain as canonical exports (host only);
-    raises TlError (TL_EUNTILEABLE when the domain has no tiling)."""
-    tmax = np.empty((dom.h, dom.w), dtype=np.uint8)
-    tmin = np.empty((dom.h, dom.w), dtype=np.uint8)
-    u8 = ctypes.POINTER(ctypes.c_uint8)
-    _check(lib().tl_domain_extremes(ctypes.byref(dom), tmax.ctypes.data_as(u8), tmin.ctypes.data_as(u8),
-                                    tmax.nbytes))
+    """Extremal states of a mask domain as canonical exports (host only):
+    dominoes (T_max, T_min), six-vertex (h_max, h_min); raises TlError
+    (TL_EUNTILEABLE when the domain has no tiling / configuration)."""
+    if dom.model == TL_SIXVERTEX:
+        tmax = np.empty((dom.h + 1, dom.w + 1), dtype=np.int32)
+    else:
+        tmax = np.empty((dom.h, dom.w), dtype=np.uint8)
+    tmin = np.empty_like(tmax)
+    _check(lib().tl_domain_extremes(ctypes.byref(dom), tmax.ctypes.data_as(ctypes.c_void_p),
+                                    tmin.ctypes.data_as(ctypes.c_void_p), tmax.nbytes))
     return tmax, tmin
 
 

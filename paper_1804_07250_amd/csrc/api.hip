@@ -224,11 +224,23 @@ const char *tl_status_str(tl_status st)
 
 const char *tl_last_error(void) { return g_last_error.c_str(); }
 
-tl_status tl_domain_extremes(const tl_domain *dom, uint8_t *tmax, uint8_t *tmin, size_t bytes)
+tl_status tl_domain_extremes(const tl_domain *dom, void *tmax, void *tmin, size_t bytes)
 {
     if (!dom) return fail(TL_EINVAL, "null argument");
-    if (dom->model != TL_DOMINO || dom->shape != TL_MASK)
-        return fail(TL_EINVAL, "extremal tilings are computed for domino mask domains");
+    if (dom->shape != TL_MASK || (dom->model != TL_DOMINO && dom->model != TL_SIXVERTEX))
+        return fail(TL_EINVAL, "extremal states are computed for domino and six-vertex mask domains");
+    if (dom->model == TL_SIXVERTEX) {
+        tl::SixvRegion r;
+        std::string why;
+        const tl::RegionStatus st = tl::build_sixv_region(dom->mask, dom->w, dom->h, r, why);
+        if (st != tl::kRegionOk)
+            return fail(st == tl::kRegionUntileable ? TL_EUNTILEABLE : TL_EINVAL, "%s", why.c_str());
+        const size_t need = r.hmax.size() * sizeof(int32_t);
+        if ((tmax || tmin) && bytes < need) return fail(TL_EINVAL, "buffers hold %zu bytes, %zu needed", bytes, need);
+        if (tmax) memcpy(tmax, r.hmax.data(), need);
+        if (tmin) memcpy(tmin, r.hmin.data(), need);
+        return TL_OK;
+    }
     tl::Region r;
     std::string why;
     const tl::RegionStatus st = tl::build_region(dom->mask, dom->w, dom->h, r, why);
@@ -522,7 +534,8 @@ tl_status tl_sampler_cftp(tl_sampler *s, uint32_t max_log2, tl_cftp_info *out)
         if (err == hipSuccess)
             err = s->model->height_family()
                       ? tl::height_items(d_jobs + 2 * slot, d_items, 2, pb.threads, pb.lds, h_jobs[2 * slot].mode,
-                                         h_jobs[2 * slot].kind, pb.order, s->stream)
+                                         h_jobs[2 * slot].kind, pb.order, h_jobs[2 * slot].site != nullptr,
+                                         s->stream)
                       : tl::domino_items(d_jobs + 2 * slot, d_items, 2, pb.threads, pb.lds, pb.order, s->stream);
         if (err == hipSuccess) {
             s->model->swap_buffers();

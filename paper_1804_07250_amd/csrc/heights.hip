@@ -62,19 +62,28 @@ constexpr uint32_t kHeightThreads = 512;
 enum { kKindClass = 0, kKindSum = 1 };
 static_assert(kKindClass == kTableClass && kKindSum == kTableSum, "table layouts agree");
 
-// Instantiation KERNEL<mode, layout> for a rule (mode) and table layout (kind).
-#define TL_HEIGHT_PICK(KERNEL, mode, kind)                                                      \
-    ((mode) == kUniform ? KERNEL<kUniform, kKindClass>                                          \
-     : (mode) == kMetropolis ? KERNEL<kMetropolis, kKindClass>                                  \
-     : (kind) == kKindSum ? KERNEL<kHeatBath, kKindSum> : KERNEL<kHeatBath, kKindClass>)
-// The same with the colour order as a third parameter (random: true).
+// Instantiation KERNEL<mode, layout, flag> for a rule (mode), a table layout
+// (kind) and a compile-time flag.
 #define TL_HEIGHT_PICK_R(KERNEL, mode, kind, R)                                                 \
     ((mode) == kUniform ? KERNEL<kUniform, kKindClass, R>                                       \
      : (mode) == kMetropolis ? KERNEL<kMetropolis, kKindClass, R>                               \
      : (kind) == kKindSum ? KERNEL<kHeatBath, kKindSum, R> : KERNEL<kHeatBath, kKindClass, R>)
+// And with two: the colour order (random) and site planes (masked domain).
+#define TL_HEIGHT_PICK_RM(KERNEL, mode, kind, R, M)                                             \
+    ((mode) == kUniform ? KERNEL<kUniform, kKindClass, R, M>                                    \
+     : (mode) == kMetropolis ? KERNEL<kMetropolis, kKindClass, R, M>                            \
+     : (kind) == kKindSum ? KERNEL<kHeatBath, kKindSum, R, M> : KERNEL<kHeatBath, kKindClass, R, M>)
+#define TL_HEIGHT_PICK_ORDER_MASK(KERNEL, mode, kind, order, masked)                            \
+    ((order) ? ((masked) ? TL_HEIGHT_PICK_RM(KERNEL, mode, kind, true, true)                    \
+                         : TL_HEIGHT_PICK_RM(KERNEL, mode, kind, true, false))                  \
+             : ((masked) ? TL_HEIGHT_PICK_RM(KERNEL, mode, kind, false, true)                   \
+                         : TL_HEIGHT_PICK_RM(KERNEL, mode, kind, false, false)))
 
 struct Geo {
     int model, a, b, c, N;
+    const uint32_t *site;   // six-vertex site planes of a masked domain (layout sPS, sRS), or nullptr
+    size_t sPS;
+    uint32_t sRS;
 };
 
 __device__ __forceinline__ int imax(int p, int q) { return p > q ? p : q; }
@@ -248,7 +257,7 @@ __device__ __forceinline__ void loz_group(uint32_t *base, size_t ps, uint32_t rs
 }
 
 // One six-vertex group: faces I = 2k + p, k = 128 g + (0..127), of row J.
-template <int MODE, int KIND>
+template <int MODE, int KIND, bool MASKED>
 __device__ __forceinline__ void sixv_group(uint32_t *base, size_t ps, uint32_t rs, uint32_t lrow, uint32_t lgrp,
                                            const Geo &geo, int J, uint32_t g, uint32_t p, uint32_t colour, uint32_t t,
                                            const Thr &Tall, uint32_t k0, uint32_t k1)
@@ -275,14 +284,16 @@ __device__ __forceinline__ void sixv_group(uint32_t *base, size_t ps, uint32_t r
         hld4_plus1(P(0, lrow - 1), SE);
         hld4(P(0, lrow - 1), SW);
     }
-    // interior faces 1 <= I <= N-1
+    // interior faces 1 <= I <= N-1 (and, in a masked domain, its sites)
     const int klo = p == 0 ? 1 : 0, khi = (geo.N - 1 - (int)p) >> 1;
+    uint32_t sm[4] = {~0u, ~0u, ~0u, ~0u};
+    if constexpr (MASKED) hld4(geo.site + p * geo.sPS + (size_t)J * geo.sRS + 4u + 4u * g, sm);
     const bool podd = ((p + (uint32_t)J) & 1u) != 0u;   // parity of I + J
     uint32_t live[4], up[4], hNE[4], hNW[4], hSW[4], hSE[4], cur[4];
     uint32_t any = 0u;
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
-        const uint32_t m = range_mask((int)(4 * g) + w, klo, khi);
+        const uint32_t m = range_mask((int)(4 * g) + w, klo, khi) & sm[w];
         live[w] = ~(E[w] ^ W[w]) & ~(E[w] ^ Nn[w]) & ~(E[w] ^ Sn[w]) & m;
         up[w] = podd ? E[w] : ~E[w];      // residual bit of m+1
         hNE[w] = ~(NE[w] ^ up[w]);
@@ -316,7 +327,7 @@ __device__ __forceinline__ bool site_row(const Geo &geo, int y, uint32_t rows)
     return y >= 1 && y <= (int)rows - 2;
 }
 
-template <int MODE, int KIND>
+template <int MODE, int KIND, bool MASKED>
 __device__ __forceinline__ void height_group(uint32_t *base, size_t ps, uint32_t rs, uint32_t lrow, uint32_t lgrp,
                                              const Geo &geo, int y, uint32_t g, uint32_t colour, uint32_t t,
                                              const Thr &T, uint32_t k0, uint32_t k1)
@@ -326,10 +337,10 @@ __device__ __forceinline__ void height_group(uint32_t *base, size_t ps, uint32_t
     if (geo.model == TL_LOZENGE)
         loz_group<MODE>(base, ps, rs, lrow, lgrp, geo, y, g, (uint32_t)pl, colour, t, T, k0, k1);
     else
-        sixv_group<MODE, KIND>(base, ps, rs, lrow, lgrp, geo, y, g, (uint32_t)pl, colour, t, T, k0, k1);
+        sixv_group<MODE, KIND, MASKED>(base, ps, rs, lrow, lgrp, geo, y, g, (uint32_t)pl, colour, t, T, k0, k1);
 }
 
-template <int MODE, int KIND>
+template <int MODE, int KIND, bool MASKED>
 __global__ void __launch_bounds__(256) height_step_kernel(uint32_t *planes, size_t PS, uint32_t RS, uint32_t ng,
                                                           uint32_t rows, Geo geo, uint32_t colour, uint32_t t, Thr T,
                                                           uint32_t k0, uint32_t k1)
@@ -337,7 +348,7 @@ __global__ void __launch_bounds__(256) height_step_kernel(uint32_t *planes, size
     const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t g = gid % ng, y = gid / ng;
     if (!site_row(geo, (int)y, rows)) return;
-    height_group<MODE, KIND>(planes, PS, RS, y, g, geo, (int)y, g, colour, t, T, k0, k1);
+    height_group<MODE, KIND, MASKED>(planes, PS, RS, y, g, geo, (int)y, g, colour, t, T, k0, k1);
 }
 
 // One tile of the multi-sweep kernel.  LDS: P planes x LR rows x LRS words,
@@ -349,7 +360,7 @@ __global__ void __launch_bounds__(256) height_step_kernel(uint32_t *planes, size
 // its colour and computes rows [q, LR - q).  The block has a thread per
 // (row, group) task (blockDim >= LR * LG, as every launch plan gives): thread
 // tid handles group tid % LG of row base + tid / LG.
-template <int MODE, int KIND, bool RANDOM>
+template <int MODE, int KIND, bool RANDOM, bool MASKED>
 __device__ __forceinline__ void height_tile(uint32_t *lds, const uint32_t *__restrict__ in,
                                             uint32_t *__restrict__ out, size_t PS, uint32_t RS, uint32_t ng,
                                             uint32_t rows, uint32_t P, const Geo &geo, uint32_t t0,
@@ -393,7 +404,7 @@ __device__ __forceinline__ void height_tile(uint32_t *lds, const uint32_t *__res
             const uint32_t lr = base + r0;
             const int gr = R0 + (int)lr;
             if (lane && lr < end && lr >= 1 && lr + 1 < LR && site_row(geo, gr, rows))
-                height_group<MODE, KIND>(lds, LPS, LRS, lr, lg, geo, gr, (uint32_t)gg, c, t, T, k0, k1);
+                height_group<MODE, KIND, MASKED>(lds, LPS, LRS, lr, lg, geo, gr, (uint32_t)gg, c, t, T, k0, k1);
             __syncthreads();
         }
     }
@@ -410,7 +421,7 @@ __device__ __forceinline__ void height_tile(uint32_t *lds, const uint32_t *__res
 }
 
 // Tiled multi-sweep kernel of one state: one work-group per tile.
-template <int MODE, int KIND, bool RANDOM>
+template <int MODE, int KIND, bool RANDOM, bool MASKED>
 __global__ void __launch_bounds__(kHeightThreads) height_tiled_kernel(const uint32_t *__restrict__ in,
                                                             uint32_t *__restrict__ out, size_t PS, uint32_t RS,
                                                             uint32_t ng, uint32_t rows, uint32_t P, Geo geo,
@@ -419,22 +430,23 @@ __global__ void __launch_bounds__(kHeightThreads) height_tiled_kernel(const uint
                                                             uint32_t k0, uint32_t k1)
 {
     extern __shared__ uint32_t lds[];
-    height_tile<MODE, KIND, RANDOM>(lds, in, out, PS, RS, ng, rows, P, geo, t0, nsweeps, TR, TG, HR, HG,
+    height_tile<MODE, KIND, RANDOM, MASKED>(lds, in, out, PS, RS, ng, rows, P, geo, t0, nsweeps, TR, TG, HR, HG,
                                     blockIdx.x / tiles_x, blockIdx.x % tiles_x, T, k0, k1);
 }
 
 // Multi-job kernel: work-group b runs tile items[b].tile of job items[b].job,
 // with that job's geometry, plan, thresholds and key.
-template <int MODE, int KIND, bool RANDOM>
+template <int MODE, int KIND, bool RANDOM, bool MASKED>
 __device__ __forceinline__ void height_item(uint32_t *lds, const TileJob &j, uint32_t tile)
 {
-    const Geo geo{j.model, j.a, j.b, j.c, j.N};
-    height_tile<MODE, KIND, RANDOM>(lds, j.in, j.out, j.PS, j.RS, j.ng, j.rows, j.P, geo, j.t0, j.S, j.TR, j.TG, j.HR,
+    const Geo geo{j.model, j.a, j.b, j.c, j.N, j.site, j.PS, j.RS};
+    height_tile<MODE, KIND, RANDOM, MASKED>(lds, j.in, j.out, j.PS, j.RS, j.ng, j.rows, j.P, geo, j.t0, j.S, j.TR,
+                                            j.TG, j.HR,
                                     j.HG, tile / j.tiles_x, tile % j.tiles_x, j.T, j.key0, j.key1);
 }
 
-// Every job of a launch has the colour order RANDOM.
-template <int MODE, int KIND, bool RANDOM>
+// Every job of a launch has the colour order RANDOM, and site planes iff MASKED.
+template <int MODE, int KIND, bool RANDOM, bool MASKED>
 __global__ void __launch_bounds__(kHeightThreads) height_items_kernel(const TileJob *__restrict__ jobs,
                                                                       const TileItem *__restrict__ items)
 {
@@ -444,11 +456,11 @@ __global__ void __launch_bounds__(kHeightThreads) height_items_kernel(const Tile
     if constexpr (MODE == kHeatBath) {
         // one-bit jobs share the heat-bath launches (the lighter kernel body)
         if (j.mode == kUniform) {
-            height_item<kUniform, kKindClass, RANDOM>(lds, j, it.tile);
+            height_item<kUniform, kKindClass, RANDOM, MASKED>(lds, j, it.tile);
             return;
         }
     }
-    height_item<MODE, KIND, RANDOM>(lds, j, it.tile);
+    height_item<MODE, KIND, RANDOM, MASKED>(lds, j, it.tile);
 }
 
 __device__ __forceinline__ uint32_t hbit(const uint32_t *pl, size_t PS, uint32_t RS, uint32_t p, uint32_t y,
@@ -535,6 +547,43 @@ __global__ void sixv_observe_kernel(const uint32_t *pl, size_t PS, uint32_t RS, 
     }
 }
 
+// Six-vertex domain given by a mask: heights of the (h+1) x (w+1) points, one
+// thread per row J.  Off the domain INT32_MIN; boundary points take their fixed
+// height; a site takes the value one away from its west neighbour (a point of
+// the domain) whose residual bit floor(h/2) mod 2 matches its own.
+__global__ void sixv_region_export_kernel(const uint32_t *pl, size_t PS, uint32_t RS, const int32_t *anchor, int w,
+                                          int h, int32_t *out)
+{
+    const int J = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (J > h) return;
+    int32_t prev = 0;
+    for (int I = 0; I <= w; ++I) {
+        const size_t v = (size_t)J * (w + 1) + I;
+        const int32_t a = anchor[v];
+        int32_t x = a;
+        if (a == INT32_MAX) {
+            const uint32_t bx = hbit(pl, PS, RS, (uint32_t)I & 1u, (uint32_t)J, (uint32_t)I >> 1);
+            x = ((uint32_t)(((prev + 1) >> 1) & 1) == bx) ? prev + 1 : prev - 1;
+        }
+        out[v] = x;
+        prev = x;
+    }
+}
+
+// Type-c cells of a masked six-vertex domain (both diagonal pairs of corner
+// heights equal) into bins of B x B cells, one thread per cell.
+__global__ void sixv_region_count_kernel(const int32_t *H, const uint8_t *cells, int w, int h, uint32_t B,
+                                         uint32_t bins_x, unsigned long long *bins)
+{
+    const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (uint32_t)w * (uint32_t)h) return;
+    const int x = (int)(gid % (uint32_t)w), y = (int)(gid / (uint32_t)w);
+    if (!cells[gid]) return;
+    const size_t sw = (size_t)y * (w + 1) + x, nw = sw + (size_t)(w + 1);
+    if (H[sw] == H[nw + 1] && H[sw + 1] == H[nw])
+        atomicAdd(&bins[(size_t)((uint32_t)y / B) * bins_x + (uint32_t)x / B], 1ull);
+}
+
 // Lozenge observable: H - H_min per vertex, summed into bins of B x B cells.
 // One wavefront per row Y: H falls by one across every change of the residual
 // bit along the row, so each lane counts the changes in its chunk of X, a
@@ -580,7 +629,7 @@ __global__ void __launch_bounds__(64) loz_observe_kernel(const uint32_t *pl, siz
         if (rowbin[i]) atomicAdd(&bins[row + i], rowbin[i]);
 }
 
-Geo geo_of(const HeightDev &d) { return Geo{d.model, d.a, d.b, d.c, d.N}; }
+Geo geo_of(const HeightDev &d) { return Geo{d.model, d.a, d.b, d.c, d.N, d.site, d.PS, d.RS}; }
 
 }  // namespace
 
@@ -599,7 +648,8 @@ hipError_t height_colour_step(const HeightDev &d, int colour, uint32_t t, const 
     const uint32_t threads = d.ng * d.rows;
     dim3 block(256), grid((threads + 255) / 256);
     const int mode = T.uniform() ? kUniform : (metropolis ? kMetropolis : kHeatBath);
-    auto k = TL_HEIGHT_PICK(height_step_kernel, mode, (int)table_kind(T));
+    auto k = d.site ? TL_HEIGHT_PICK_R(height_step_kernel, mode, (int)table_kind(T), true)
+                    : TL_HEIGHT_PICK_R(height_step_kernel, mode, (int)table_kind(T), false);
     return launch(tm, 1, k, grid, block, 0, s, d.planes, d.PS, d.RS, d.ng, d.rows, geo_of(d), (uint32_t)colour, t, T,
                   k0, k1);
 }
@@ -669,8 +719,8 @@ hipError_t height_tiled_sweeps(HeightDev &d, const HeightTile &tile, uint32_t t0
         TilePlan p;
         if (!height_plan(d, tile, nsw - done, &p)) return hipErrorInvalidConfiguration;
         const int mode = T.uniform() ? kUniform : (metropolis ? kMetropolis : kHeatBath);
-        auto k = p.order ? TL_HEIGHT_PICK_R(height_tiled_kernel, mode, (int)table_kind(T), true)
-                         : TL_HEIGHT_PICK_R(height_tiled_kernel, mode, (int)table_kind(T), false);
+        auto k = TL_HEIGHT_PICK_ORDER_MASK(height_tiled_kernel, mode, (int)table_kind(T), p.order,
+                                           d.site != nullptr);
         hipError_t e = launch(tm, colours * p.S, k, dim3(p.tiles()), dim3(p.threads), p.lds, s,
                               (const uint32_t *)d.planes, d.spare, d.PS, d.RS, d.ng, d.rows, d.P, geo_of(d),
                               t0 + done, p.S, p.TR, p.TG, p.HR, p.HG, p.tiles_x, T, k0, k1);
@@ -710,6 +760,7 @@ TileJob height_tile_job(const HeightDev &d, const TilePlan &p, uint32_t t0, cons
     j.order = p.order;
     j.mode = T.uniform() ? kModeUniform : (metropolis ? kModeMetropolis : kModeHeatBath);
     j.kind = T.uniform() ? (uint32_t)kTableClass : table_kind(T);
+    j.site = d.site;
     j.key0 = (uint32_t)seed;
     j.key1 = (uint32_t)(seed >> 32);
     j.T = T;
@@ -717,13 +768,12 @@ TileJob height_tile_job(const HeightDev &d, const TilePlan &p, uint32_t t0, cons
 }
 
 hipError_t height_items(const TileJob *jobs, const TileItem *items, uint32_t n_items, uint32_t threads, uint32_t lds,
-                        uint32_t mode, uint32_t kind, uint32_t order, hipStream_t s)
+                        uint32_t mode, uint32_t kind, uint32_t order, uint32_t masked, hipStream_t s)
 {
     if (n_items == 0) return hipSuccess;
     if (threads == 0 || threads > kHeightThreads || lds > 160u * 1024u || mode > 2u || kind > 1u)
         return hipErrorInvalidConfiguration;
-    auto k = order ? TL_HEIGHT_PICK_R(height_items_kernel, (int)mode, (int)kind, true)
-                   : TL_HEIGHT_PICK_R(height_items_kernel, (int)mode, (int)kind, false);
+    auto k = TL_HEIGHT_PICK_ORDER_MASK(height_items_kernel, (int)mode, (int)kind, order, masked);
     hipLaunchKernelGGL(k, dim3(n_items), dim3(threads), lds, s, jobs, items);
     return hipGetLastError();
 }
@@ -732,6 +782,25 @@ hipError_t height_export(const HeightDev &d, int32_t *dev, hipStream_t s)
 {
     dim3 block(64), grid((d.rows + 63) / 64);
     hipLaunchKernelGGL(height_export_kernel, grid, block, 0, s, d.planes, d.PS, d.RS, d.rows, geo_of(d), dev);
+    return hipGetLastError();
+}
+
+hipError_t sixv_region_export(const HeightDev &d, const int32_t *anchor, int w, int h, int32_t *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(sixv_region_export_kernel, dim3((h + 64) / 64), dim3(64), 0, s, d.planes, d.PS, d.RS, anchor,
+                       w, h, out);
+    return hipGetLastError();
+}
+
+hipError_t sixv_region_observe(const HeightDev &d, const int32_t *anchor, const uint8_t *cells, int w, int h,
+                               int32_t *heights, uint32_t B, uint32_t bins_x, unsigned long long *bins,
+                               hipStream_t s)
+{
+    hipError_t e = sixv_region_export(d, anchor, w, h, heights, s);
+    if (e != hipSuccess) return e;
+    const uint32_t n = (uint32_t)w * (uint32_t)h;
+    hipLaunchKernelGGL(sixv_region_count_kernel, dim3((n + 255) / 256), dim3(256), 0, s, heights, cells, w, h, B,
+                       bins_x, bins);
     return hipGetLastError();
 }
 

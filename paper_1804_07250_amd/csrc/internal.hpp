@@ -177,6 +177,9 @@ struct HeightDev {
     uint32_t ng = 0, RS = 0;
     size_t PS = 0;
     uint32_t *planes = nullptr, *spare = nullptr;
+    // six-vertex domain given by a mask: bit planes (same layout as the state)
+    // of the points that may flip; nullptr for the domain-wall square
+    const uint32_t *site = nullptr;
 };
 struct HeightTile {
     uint32_t TR = 32, TG = 4, S = 8;
@@ -192,6 +195,15 @@ HeightTile height_auto_tile(const HeightDev &d);
 // int32 canonical export into dev (rows x (row length) values)
 hipError_t height_export(const HeightDev &d, int32_t *dev, hipStream_t s);
 hipError_t height_observe(const HeightDev &d, uint32_t B, uint32_t bins_x, unsigned long long *bins, hipStream_t s);
+// Six-vertex domain given by a mask (w x h cells in the state's box): the
+// (h+1) x (w+1) heights, anchored at the boundary points (anchor: boundary
+// height, INT32_MIN off the domain, INT32_MAX at sites); type-c cells of the
+// domain (cells: w*h bytes, 1 = in the domain) into bins, through `heights`,
+// a (w+1)*(h+1) int32 scratch buffer.
+hipError_t sixv_region_export(const HeightDev &d, const int32_t *anchor, int w, int h, int32_t *out, hipStream_t s);
+hipError_t sixv_region_observe(const HeightDev &d, const int32_t *anchor, const uint8_t *cells, int w, int h,
+                               int32_t *heights, uint32_t B, uint32_t bins_x, unsigned long long *bins,
+                               hipStream_t s);
 
 // ------------------------------------------------------ planned tile launches
 // One launch of a tiled multi-sweep kernel, planned on the host: S sweeps,
@@ -227,6 +239,7 @@ struct TileJob {
     uint32_t kind;                      // kTable* (height models)
     uint32_t order;                     // colour order: 0 fixed, 1 random per step
     uint32_t key0, key1;
+    const uint32_t *site;               // six-vertex site planes of a masked domain, or nullptr
     Thr T;                              // kernel table (heights: weight classes)
 };
 struct TileItem {
@@ -243,8 +256,9 @@ hipError_t domino_items(const TileJob *jobs, const TileItem *items, uint32_t n_i
                         uint32_t lds, uint32_t order, hipStream_t s);
 // Height items of one launch share one rule and one table kind (one kernel
 // instantiation each); a heat-bath launch also runs one-bit jobs.
+// Every job has colour order `order`, and site planes iff `masked`.
 hipError_t height_items(const TileJob *jobs, const TileItem *items, uint32_t n_items, uint32_t threads,
-                        uint32_t lds, uint32_t mode, uint32_t kind, uint32_t order, hipStream_t s);
+                        uint32_t lds, uint32_t mode, uint32_t kind, uint32_t order, uint32_t masked, hipStream_t s);
 
 // ----------------------------------------------------------------- hashing
 // SHA-256 of each of `rows` rows of `row_bytes` bytes at `data` (device), into

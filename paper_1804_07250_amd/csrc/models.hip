@@ -224,9 +224,21 @@ public:
         d_.N = dom.n;
         height_words(d_);
     }
+    // Six-vertex domain given by a mask: the state is the square box of
+    // N = max(w, h) cells (the domain's box at its south-west corner); sites
+    // outside the domain never flip (site planes), exports and observables use
+    // the domain's own box.
+    explicit HeightModel(std::shared_ptr<const SixvRegion> r) : region_(std::move(r))
+    {
+        dom_ = tl_domain{};
+        dom_.model = TL_SIXVERTEX;
+        d_.model = TL_SIXVERTEX;
+        d_.N = std::max(region_->w, region_->h);
+        height_words(d_);
+    }
     std::unique_ptr<Model> twin() const override
     {
-        std::unique_ptr<Model> m(new HeightModel(dom_));
+        std::unique_ptr<Model> m(region_ ? new HeightModel(region_) : new HeightModel(dom_));
         m->order = order;
         return m;
     }
@@ -239,6 +251,19 @@ public:
         hipError_t e = hipMalloc(&d_.planes, words * sizeof(uint32_t));
         if (e == hipSuccess) e = hipMalloc(&d_.spare, words * sizeof(uint32_t));
         owned_ = true;
+        if (e != hipSuccess || !region_) return e;
+        const size_t V = region_->anchor.size(), C = region_->mask.size();
+        e = hipMalloc(&site_, words * sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMalloc(&anchor_, V * sizeof(int32_t));
+        if (e == hipSuccess) e = hipMalloc(&heights_, V * sizeof(int32_t));
+        if (e == hipSuccess) e = hipMalloc(&cells_, C);
+        if (e != hipSuccess) return e;
+        std::vector<uint32_t> planes;
+        pack_points(region_->site, planes, [](int32_t v) { return v != 0; });
+        e = hipMemcpy(site_, planes.data(), planes.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(anchor_, region_->anchor.data(), V * sizeof(int32_t), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(cells_, region_->mask.data(), C, hipMemcpyHostToDevice);
+        d_.site = site_;
         return e;
     }
     void release() override
@@ -246,7 +271,25 @@ public:
         if (owned_ && d_.planes) (void)hipFree(d_.planes);
         if (owned_ && d_.spare) (void)hipFree(d_.spare);
         d_.planes = d_.spare = nullptr;
+        for (void *p : {(void *)site_, (void *)anchor_, (void *)heights_, (void *)cells_})
+            if (p) (void)hipFree(p);
+        site_ = nullptr;
+        anchor_ = heights_ = nullptr;
+        cells_ = nullptr;
+        d_.site = nullptr;
         timing.release();
+    }
+    // Bit planes (state layout) of a per-point property of a masked domain:
+    // bit of point (I, J) set iff pred(value at J*(w+1) + I).
+    template <typename V, typename F>
+    void pack_points(const std::vector<V> &vals, std::vector<uint32_t> &host, F pred) const
+    {
+        host.assign(d_.P * d_.PS, 0u);
+        const int w = region_->w, h = region_->h;
+        for (int J = 0; J <= h; ++J)
+            for (int I = 0; I <= w; ++I)
+                if (pred((int32_t)vals[(size_t)J * (w + 1) + I]))
+                    host[(size_t)(I & 1) * d_.PS + (size_t)J * d_.RS + 4 + ((I >> 1) >> 5)] |= 1u << ((I >> 1) & 31);
     }
     size_t state_words() const override
     {
@@ -282,7 +325,21 @@ public:
     void swap_buffers() override { std::swap(d_.planes, d_.spare); }
     bool height_family() const override { return true; }
     const uint32_t *state() const override { return d_.planes; }
-    hipError_t init(bool init_max, hipStream_t s) override { return height_init(d_, init_max ? 1 : 0, s); }
+    hipError_t init(bool init_max, hipStream_t s) override
+    {
+        if (!region_) return height_init(d_, init_max ? 1 : 0, s);
+        // residual bits floor(h/2) mod 2 of the extremal configuration, packed
+        // once, into both buffers
+        std::vector<uint32_t> &host = init_max ? packed_max_ : packed_min_;
+        if (host.empty())
+            pack_points(init_max ? region_->hmax : region_->hmin, host,
+                        [](int32_t v) { return v != INT32_MIN && ((v >> 1) & 1); });
+        hipError_t e = hipMemcpyAsync(d_.planes, host.data(), host.size() * sizeof(uint32_t),
+                                      hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d_.spare, host.data(), host.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s);
+        return e;
+    }
 
     // Six-vertex kernels take one threshold per weight class (sA, sB) (and
     // current state for Metropolis): class 3*sA + sB <-> mask with NE = sA>=1,
@@ -351,11 +408,16 @@ public:
     }
     hipError_t observe(uint32_t B, uint32_t bins_x, unsigned long long *bins, hipStream_t s) override
     {
+        if (region_)
+            return sixv_region_observe(d_, anchor_, cells_, region_->w, region_->h, heights_, B, bins_x, bins, s);
         return height_observe(d_, B, bins_x, bins, s);
     }
     void cell_box(uint32_t *w, uint32_t *h) const override
     {
-        if (loz()) {
+        if (region_) {
+            *w = (uint32_t)region_->w;
+            *h = (uint32_t)region_->h;
+        } else if (loz()) {
             *w = (uint32_t)(d_.a + d_.c + 1);
             *h = (uint32_t)(d_.b + d_.c + 1);
         } else {
@@ -375,21 +437,70 @@ public:
         uint32_t w, h;
         cell_box(&w, &h);
         for (uint32_t Y = 0; Y < h; ++Y)
-            for (uint32_t X = 0; X < w; ++X)
-                if (!loz() || in_hex((int)X, (int)Y)) cnt[(size_t)(Y / B) * bx + X / B] += 1;
+            for (uint32_t X = 0; X < w; ++X) {
+                const bool in = region_ ? region_->mask[(size_t)Y * w + X] != 0 : (!loz() || in_hex((int)X, (int)Y));
+                if (in) cnt[(size_t)(Y / B) * bx + X / B] += 1;
+            }
         return cnt;
     }
     void export_layout(uint32_t *rows, uint32_t *row_bytes) const override
     {
-        *rows = d_.rows;
-        *row_bytes = 4u * (uint32_t)width();
+        *rows = region_ ? (uint32_t)region_->h + 1u : d_.rows;
+        *row_bytes = 4u * (uint32_t)(region_ ? region_->w + 1 : width());
     }
     hipError_t export_canonical(uint8_t *dev, hipStream_t s) override
     {
+        if (region_)
+            return sixv_region_export(d_, anchor_, region_->w, region_->h, reinterpret_cast<int32_t *>(dev), s);
         return height_export(d_, reinterpret_cast<int32_t *>(dev), s);
+    }
+    // Masked six-vertex domain: off the domain INT32_MIN, boundary points their
+    // fixed heights, sites one away from their four neighbours with the parity
+    // of I + J.
+    bool import_region(const int32_t *H, std::vector<uint32_t> &host, std::string &why) const
+    {
+        const int w = region_->w, h = region_->h, PW = w + 1;
+        std::vector<int32_t> vals((size_t)PW * (h + 1), INT32_MIN);
+        for (int J = 0; J <= h; ++J)
+            for (int I = 0; I <= w; ++I) {
+                const size_t v = (size_t)J * PW + I;
+                const int32_t a = region_->anchor[v], x = H[v];
+                if (a != INT32_MAX) {
+                    if (x != a) {
+                        why = a == INT32_MIN ? "point off the domain is not INT32_MIN" : "boundary height violated";
+                        return false;
+                    }
+                    if (a != INT32_MIN) vals[v] = x;
+                    continue;
+                }
+                const int32_t nb[4] = {H[v - 1], H[v + 1], H[v - PW], H[v + PW]};
+                for (int32_t y : nb)
+                    if (y == INT32_MIN || (x > y ? x - y : y - x) != 1) {
+                        why = "ice rule violated";
+                        return false;
+                    }
+                if (((int64_t)x - I - J) & 1) {
+                    why = "height parity differs from I + J";
+                    return false;
+                }
+                vals[v] = x;
+            }
+        pack_points(vals, host, [](int32_t x) { return x != INT32_MIN && ((x >> 1) & 1); });
+        return true;
     }
     bool import_canonical(const uint8_t *raw, hipStream_t s, std::string &why, hipError_t *err) override
     {
+        if (region_) {
+            std::vector<int32_t> H((size_t)(region_->w + 1) * (region_->h + 1));
+            memcpy(H.data(), raw, H.size() * sizeof(int32_t));
+            std::vector<uint32_t> host;
+            if (!import_region(H.data(), host, why)) return false;
+            hipError_t e = hipMemcpyAsync(d_.planes, host.data(), host.size() * sizeof(uint32_t),
+                                          hipMemcpyHostToDevice, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) { *err = e; return false; }
+            return true;
+        }
         const int W = width(), R = (int)d_.rows;
         std::vector<int32_t> h((size_t)W * R);
         memcpy(h.data(), raw, h.size() * sizeof(int32_t));
@@ -440,6 +551,7 @@ public:
     }
     uint64_t sites() const override
     {
+        if (region_) return region_->sites;
         if (loz()) {
             uint64_t n = 0;
             for (int Y = 1; Y < (int)d_.rows - 1; ++Y) {
@@ -457,6 +569,11 @@ private:
     tl_domain dom_;
     HeightDev d_;
     bool owned_ = false;
+    std::shared_ptr<const SixvRegion> region_;
+    uint32_t *site_ = nullptr;
+    int32_t *anchor_ = nullptr, *heights_ = nullptr;
+    uint8_t *cells_ = nullptr;
+    std::vector<uint32_t> packed_max_, packed_min_;
 };
 
 }  // namespace
@@ -464,6 +581,15 @@ private:
 std::unique_ptr<Model> make_model(const tl_domain &d, std::string &why, tl_status *status)
 {
     if (status) *status = TL_EINVAL;
+    if (d.model == TL_SIXVERTEX && d.shape == TL_MASK) {
+        auto r = std::make_shared<SixvRegion>();
+        const RegionStatus st = build_sixv_region(d.mask, d.w, d.h, *r, why);
+        if (st != kRegionOk) {
+            if (status && st == kRegionUntileable) *status = TL_EUNTILEABLE;
+            return nullptr;
+        }
+        return std::unique_ptr<Model>(new HeightModel(std::shared_ptr<const SixvRegion>(std::move(r))));
+    }
     if (d.model == TL_DOMINO && d.shape == TL_MASK) {
         auto r = std::make_shared<Region>();
         const RegionStatus st = build_region(d.mask, d.w, d.h, *r, why);

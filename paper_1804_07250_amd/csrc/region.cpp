@@ -147,49 +147,63 @@ void region_embedding(int w, int h, int *n, int *ox, int *oy)
     *oy = (N - D) / 2;
 }
 
-RegionStatus build_region(const uint8_t *mask, int w, int h, Region &r, std::string &why)
+namespace {
+
+// Copy the mask (0/1) and check it describes an accepted domain: non-empty,
+// edge-connected, no pinch vertex, no hole.
+RegionStatus validate_mask(const uint8_t *mask, int w, int h, std::vector<uint8_t> &m, uint64_t &count,
+                           std::string &why)
 {
     if (!mask || w < 1 || h < 1 || (int64_t)w + h > 32768) {
         why = "mask domain needs a mask and 1 <= w, h with w + h <= 32768";
         return kRegionInvalid;
     }
-    r.w = w;
-    r.h = h;
-    region_embedding(w, h, &r.n, &r.ox, &r.oy);
-    r.mask.assign((size_t)w * h, 0);
-    r.faces = 0;
-    for (size_t i = 0; i < r.mask.size(); ++i) {
-        r.mask[i] = mask[i] ? 1 : 0;
-        r.faces += r.mask[i];
+    m.assign((size_t)w * h, 0);
+    count = 0;
+    for (size_t i = 0; i < m.size(); ++i) {
+        m[i] = mask[i] ? 1 : 0;
+        count += m[i];
     }
-    if (r.faces == 0) {
+    if (count == 0) {
         why = "empty domain";
         return kRegionInvalid;
     }
-    const Grid g{w, h, r.n & 1, r.mask};
-    // pinch vertices: exactly two diagonally opposite faces inside
+    auto in = [&](int x, int y) { return x >= 0 && y >= 0 && x < w && y < h && m[(size_t)y * w + x]; };
+    // pinch vertices: exactly two diagonally opposite cells inside
     for (int j = 0; j <= h; ++j)
         for (int i = 0; i <= w; ++i) {
-            const bool sw = g.in(i - 1, j - 1), se = g.in(i, j - 1), nw = g.in(i - 1, j), ne = g.in(i, j);
+            const bool sw = in(i - 1, j - 1), se = in(i, j - 1), nw = in(i - 1, j), ne = in(i, j);
             if ((sw && ne && !se && !nw) || (se && nw && !sw && !ne)) {
                 why = "domain pinched at vertex (" + std::to_string(i) + ", " + std::to_string(j) + ")";
                 return kRegionInvalid;
             }
         }
-    if (!connected(r.mask, w, h, r.faces)) {
+    if (!connected(m, w, h, count)) {
         why = "domain is not connected";
         return kRegionInvalid;
     }
-    {   // holes: the complement in the box grown by one face must be connected
-        const int W2 = w + 2, H2 = h + 2;
-        std::vector<uint8_t> out((size_t)W2 * H2, 1);
-        for (int y = 0; y < h; ++y)
-            for (int x = 0; x < w; ++x) out[(size_t)(y + 1) * W2 + x + 1] = r.mask[(size_t)y * w + x] ? 0 : 1;
-        if (!connected(out, W2, H2, (size_t)W2 * H2 - r.faces)) {
-            why = "domain has a hole";
-            return kRegionInvalid;
-        }
+    // holes: the complement in the box grown by one cell must be connected
+    const int W2 = w + 2, H2 = h + 2;
+    std::vector<uint8_t> out((size_t)W2 * H2, 1);
+    for (int y = 0; y < h; ++y)
+        for (int x = 0; x < w; ++x) out[(size_t)(y + 1) * W2 + x + 1] = m[(size_t)y * w + x] ? 0 : 1;
+    if (!connected(out, W2, H2, (size_t)W2 * H2 - count)) {
+        why = "domain has a hole";
+        return kRegionInvalid;
     }
+    return kRegionOk;
+}
+
+}  // namespace
+
+RegionStatus build_region(const uint8_t *mask, int w, int h, Region &r, std::string &why)
+{
+    const RegionStatus vs = validate_mask(mask, w, h, r.mask, r.faces, why);
+    if (vs != kRegionOk) return vs;
+    r.w = w;
+    r.h = h;
+    region_embedding(w, h, &r.n, &r.ox, &r.oy);
+    const Grid g{w, h, r.n & 1, r.mask};
     r.sites = 0;
     for (int j = 1; j < h; ++j)
         for (int i = 1; i < w; ++i)
@@ -237,6 +251,120 @@ RegionStatus build_region(const uint8_t *mask, int w, int h, Region &r, std::str
     if (!tiling_of(g, up, 1, r.tmax) || !tiling_of(g, down, -1, r.tmin)) {
         why = "no tiling: extremal heights do not describe a tiling";
         return kRegionUntileable;
+    }
+    return kRegionOk;
+}
+
+// Six-vertex domains.  Neighbouring heights differ by exactly 1, so the
+// configurations are the functions that are 1-Lipschitz along the cell sides
+// of the domain, agree with the boundary and have the parity of I + J: the
+// largest is min_b h(b) + dist(b, v), the smallest max_b h(b) - dist(b, v)
+// (unit lengths, a bucket queue from all boundary points at once), and one
+// exists iff both meet the boundary heights.
+RegionStatus build_sixv_region(const uint8_t *mask, int w, int h, SixvRegion &r, std::string &why)
+{
+    const RegionStatus vs = validate_mask(mask, w, h, r.mask, r.cells, why);
+    if (vs != kRegionOk) return vs;
+    r.w = w;
+    r.h = h;
+    const int PW = w + 1;
+    const size_t V = (size_t)PW * (h + 1);
+    auto in = [&](int x, int y) { return x >= 0 && y >= 0 && x < w && y < h && r.mask[(size_t)y * w + x] != 0; };
+    std::vector<uint8_t> pt(V, 0);
+    r.site.assign(V, 0);
+    r.sites = 0;
+    size_t start = V;
+    for (int J = 0; J <= h; ++J)
+        for (int I = 0; I <= w; ++I) {
+            const bool a = in(I - 1, J - 1), b = in(I, J - 1), c = in(I - 1, J), d = in(I, J);
+            const size_t v = (size_t)J * PW + I;
+            pt[v] = a || b || c || d;
+            r.site[v] = a && b && c && d;
+            r.sites += r.site[v];
+            if (pt[v] && start == V) start = v;
+        }
+    // Steps out of point (I, J): neighbour offset, the two cells beside the
+    // edge (above / below for horizontal steps, right / left for vertical
+    // ones) and the direction sign of the boundary increment.
+    struct Edge {
+        int dI, dJ, ax, ay, bx, by, sign;
+    };
+    static constexpr Edge kE[4] = {{1, 0, 0, 0, 0, -1, 1},
+                                   {-1, 0, -1, 0, -1, -1, -1},
+                                   {0, 1, 0, 0, -1, 0, 1},
+                                   {0, -1, 0, -1, -1, -1, -1}};
+    std::vector<int32_t> hb(V, kUnset);
+    {
+        const int I0 = (int)(start % PW), J0 = (int)(start / PW);
+        hb[start] = (I0 + J0) & 1;
+        std::vector<size_t> stack{start};
+        while (!stack.empty()) {
+            const size_t v = stack.back();
+            stack.pop_back();
+            const int I = (int)(v % PW), J = (int)(v / PW);
+            for (const Edge &e : kE) {
+                const bool a = in(I + e.ax, J + e.ay), b = in(I + e.bx, J + e.by);
+                if (a == b) continue;   // interior side, or no side of the domain
+                const size_t u = (size_t)(J + e.dJ) * PW + I + e.dI;
+                const int32_t hu = hb[v] + e.sign * (a ? 1 : -1);
+                if (hb[u] == kUnset) {
+                    hb[u] = hu;
+                    stack.push_back(u);
+                } else if (hb[u] != hu) {
+                    why = "no configuration: the boundary heights do not close up";
+                    return kRegionUntileable;
+                }
+            }
+        }
+    }
+    for (size_t v = 0; v < V; ++v)
+        if (pt[v] && !r.site[v] && hb[v] == kUnset) {
+            why = "boundary not connected";
+            return kRegionInvalid;
+        }
+    auto bound = [&](int sign) {
+        std::vector<int32_t> dist(V, kUnset);
+        int32_t kmin = INT32_MAX;
+        for (size_t v = 0; v < V; ++v)
+            if (hb[v] != kUnset) kmin = std::min(kmin, sign * hb[v]);
+        std::vector<std::vector<uint32_t>> buckets;
+        auto push = [&](size_t v, int32_t key) {
+            dist[v] = key;
+            const size_t b = (size_t)(key - kmin);
+            if (b >= buckets.size()) buckets.resize(b + 1);
+            buckets[b].push_back((uint32_t)v);
+        };
+        for (size_t v = 0; v < V; ++v)
+            if (hb[v] != kUnset) push(v, sign * hb[v]);
+        for (size_t b = 0; b < buckets.size(); ++b) {
+            for (size_t q = 0; q < buckets[b].size(); ++q) {
+                const uint32_t v = buckets[b][q];
+                const int32_t d = (int32_t)b + kmin;
+                if (dist[v] != d) continue;
+                const int I = (int)(v % PW), J = (int)(v / PW);
+                for (const Edge &e : kE) {
+                    if (!in(I + e.ax, J + e.ay) && !in(I + e.bx, J + e.by)) continue;
+                    const size_t u = (size_t)(J + e.dJ) * PW + I + e.dI;
+                    if (dist[u] == kUnset || d + 1 < dist[u]) push(u, d + 1);
+                }
+            }
+            std::vector<uint32_t>().swap(buckets[b]);
+        }
+        return dist;
+    };
+    const std::vector<int32_t> up = bound(1), down = bound(-1);
+    r.hmax.assign(V, INT32_MIN);
+    r.hmin.assign(V, INT32_MIN);
+    r.anchor.assign(V, INT32_MIN);
+    for (size_t v = 0; v < V; ++v) {
+        if (!pt[v]) continue;
+        if (hb[v] != kUnset && (up[v] != hb[v] || down[v] != -hb[v])) {
+            why = "no configuration meets the boundary heights";
+            return kRegionUntileable;
+        }
+        r.hmax[v] = up[v];
+        r.hmin[v] = -down[v];
+        r.anchor[v] = r.site[v] ? INT32_MAX : hb[v];
     }
     return kRegionOk;
 }

@@ -409,7 +409,7 @@ bool tick(tl_server *sv)
             else
                 e = tl::height_items(sv->d_jobs, sv->d_items + gr.first, gr.count, gr.threads, gr.lds,
                                      gr.key >= 3u ? (uint32_t)tl::kModeMetropolis : (uint32_t)tl::kModeHeatBath,
-                                     gr.key % 3u, 0u, sv->stream);
+                                     gr.key % 3u, 0u, 0u, sv->stream);
         }
     }
     for (size_t i = 0; i < run.size(); ++i) {

@@ -1,0 +1,186 @@
+"""GPU parity for the six-vertex model on domains given by masks (Section 1.2
+with the domains of Section 1.1; the L-shaped example with domain-wall type
+boundary): the HIP path against the oracle's chain, bit for bit, and the masked
+square against the domain-wall sampler itself."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import need_gpu, say
+from test_oracle_region import l_shape, ones, random_domain
+
+pytestmark = pytest.mark.gpu
+
+KERNELS = {"auto": {}, "step": {"kernel": 1}, "tiled": {"kernel": 2, "tile_rows": 8, "sweeps_per_launch": 3}}
+
+
+def weights(tl, w2, metro):
+    w = tl.weights(tl.TL_W_SIXVERTEX, *[float(x) for x in w2])
+    w.rule = tl.TL_METROPOLIS if metro else tl.TL_HEATBATH
+    a, b = int(round(w2[0] ** 0.5)), int(round(w2[1] ** 0.5))
+    return w, oracle.table_from_ratios(oracle.sixv_ratios(a, b, w2[2]), metro)
+
+
+def random30(seed=66):
+    return random_domain(np.random.default_rng(seed), 30, 30, 0.9)
+
+
+@pytest.mark.parametrize("N,w2,kernel,order", [(16, (1, 1, 2), "auto", 0), (130, (1, 1, 2), "auto", 0),
+                                               (130, (1, 1, 1), "tiled", 0), (64, (4, 1, 4), "step", 1)])
+def test_masked_square_equals_domain_wall_square(N, w2, kernel, order):
+    tl = need_gpu()
+    say("six-vertex masked square N=%d %s %s order=%d" % (N, w2, kernel, order))
+    w, _ = weights(tl, w2, False)
+    for init in (tl.TL_INIT_MIN, tl.TL_INIT_MAX):
+        opt = tl.options(colour_order=order, **KERNELS[kernel])
+        a = tl.Sampler(tl.domain(tl.TL_SIXVERTEX, mask=ones(N, N), init=init), w, 9, opt)
+        b = tl.Sampler(tl.domain(tl.TL_SIXVERTEX, n=N, init=init), w, 9, opt)
+        for k in (0, 3, 11):
+            a.sweep(k)
+            b.sweep(k)
+            assert (a.export() == b.export()).all()
+            assert a.hash() == b.hash()
+
+
+CASES = [("l40", (1, 1, 2), False, "min", "auto"), ("l40", (1, 1, 1), False, "max", "step"),
+         ("l64", (4, 1, 4), True, "min", "tiled"), ("l130", (1, 1, 2), False, "max", "auto"),
+         ("random30", (1, 1, 2), False, "min", "auto"), ("l33", (1, 1, 1), False, "min", "tiled")]
+
+
+def mask_of(name):
+    return {"l40": l_shape(40, 16, 20), "l64": l_shape(64, 24, 30), "l130": l_shape(130, 60, 50),
+            "random30": random30(), "l33": l_shape(33, 10, 12)}[name]
+
+
+@pytest.mark.parametrize("name,w2,metro,init,kernel", CASES, ids=["-".join(map(str, c)) for c in CASES])
+def test_domain_parity(name, w2, metro, init, kernel):
+    tl = need_gpu()
+    say("six-vertex domain parity %s %s metro=%s init=%s %s" % (name, w2, metro, init, kernel))
+    m = mask_of(name)
+    w, thr = weights(tl, w2, metro)
+    dom = tl.domain(tl.TL_SIXVERTEX, mask=m, init=tl.TL_INIT_MAX if init == "max" else tl.TL_INIT_MIN)
+    s = tl.Sampler(dom, w, 21, tl.options(**KERNELS[kernel]))
+    o = oracle.SixVertexRegionOracle(m, thr, metropolis=metro, seed=21, init=init)
+    assert (s.rows, s.row_bytes // 4) == (m.shape[0] + 1, m.shape[1] + 1)
+    assert (s.export() == o.export()).all()
+    for k in (1, 4, 12):
+        s.sweep(k)
+        o.sweep(k)
+        assert (s.export() == o.export()).all(), "after %d sweeps" % o.t
+    assert s.hash() == oracle.canonical_hash(o.export())
+    assert s.info() == (len(o.sites()), 4)
+
+
+def test_domain_random_order():
+    tl = need_gpu()
+    m = l_shape(40, 16, 20)
+    w, thr = weights(tl, (1, 1, 2), False)
+    s = tl.Sampler(tl.domain(tl.TL_SIXVERTEX, mask=m), w, 4, tl.options(colour_order=1))
+    o = oracle.SixVertexRegionOracle(m, thr, seed=4, random_colours=True)
+    for k in (2, 9):
+        s.sweep(k)
+        o.sweep(k)
+        assert (s.export() == o.export()).all()
+
+
+@pytest.mark.parametrize("name,B", [("l40", 1), ("l40", 7), ("l130", 40), ("random30", 4)])
+def test_domain_observables(name, B):
+    tl = need_gpu()
+    m = mask_of(name)
+    w, thr = weights(tl, (1, 1, 2), False)
+    s = tl.Sampler(tl.domain(tl.TL_SIXVERTEX, mask=m), w, 6, tl.options(obs_every=3, obs_bin=B))
+    o = oracle.SixVertexRegionOracle(m, thr, seed=6, obs_every=3, bin_=B)
+    s.sweep(20)
+    o.sweep(20)
+    obs = s.observables()
+    assert obs["samples"] == int(o.samples[0]) == 6
+    assert (obs["bin_sum"].reshape(-1) == o.bin_sum).all()
+    v, now = o.observe(B)
+    assert obs["scalar_now"] == v and (obs["bin_now"].reshape(-1) == now).all()
+    dens = oracle.bin_density(o.bin_sum, int(o.samples[0]), m, B)
+    assert np.allclose(obs["bin_density"], dens, rtol=1e-12, atol=0)
+
+
+def test_domain_import_export_and_rejects():
+    tl = need_gpu()
+    m = l_shape(24, 10, 8)
+    w, thr = weights(tl, (1, 1, 2), False)
+    s = tl.Sampler(tl.domain(tl.TL_SIXVERTEX, mask=m), w, 8)
+    o = oracle.SixVertexRegionOracle(m, thr, seed=8)
+    o.sweep(25)
+    mid = o.export()
+    s.import_(mid, 25)
+    s.sweep(6)
+    o.sweep(6)
+    assert (s.export() == o.export()).all()
+    pts, sites = oracle.sixv_points(m)
+    J, I = np.argwhere(sites)[0]
+    bad = mid.copy()
+    bad[J, I] += 2                                   # breaks the ice rule
+    with pytest.raises(tl.TlError) as e:
+        s.import_(bad, 0)
+    assert e.value.status == tl.TL_EINVAL
+    bad = mid.copy()
+    Jb, Ib = np.argwhere(pts & ~sites)[0]
+    bad[Jb, Ib] += 2                                 # a boundary height
+    with pytest.raises(tl.TlError) as e:
+        s.import_(bad, 0)
+    assert e.value.status == tl.TL_EINVAL
+    bad = mid.copy()
+    Jo, Io = np.argwhere(~pts)[0]
+    bad[Jo, Io] = 0                                  # a point off the domain
+    with pytest.raises(tl.TlError) as e:
+        s.import_(bad, 0)
+    assert e.value.status == tl.TL_EINVAL
+
+
+def test_domain_create_errors():
+    tl = need_gpu()
+    w = tl.weights(tl.TL_W_SIXVERTEX, 1.0, 1.0, 2.0)
+    with pytest.raises(tl.TlError) as e:
+        tl.Sampler(tl.domain(tl.TL_SIXVERTEX, mask=ones(9, 14)), w, 1)   # the boundary does not close up
+    assert e.value.status == tl.TL_EUNTILEABLE
+    ring = ones(6, 6)
+    ring[2:4, 2:4] = False
+    with pytest.raises(tl.TlError) as e:
+        tl.Sampler(tl.domain(tl.TL_SIXVERTEX, mask=ring), w, 1)
+    assert e.value.status == tl.TL_EINVAL
+
+
+@pytest.mark.parametrize("name,w2", [("l12", (1, 1, 2)), ("l16", (1, 1, 1)), ("random30", (1, 1, 2))])
+def test_domain_cftp_equals_oracle(name, w2):
+    tl = need_gpu()
+    say("six-vertex domain cftp %s %s" % (name, w2))
+    m = {"l12": l_shape(12, 6, 4), "l16": l_shape(16, 8, 8), "random30": random30()}[name]
+    w, thr = weights(tl, w2, False)
+    for seed in (3, 4):
+        s = tl.Sampler(tl.domain(tl.TL_SIXVERTEX, mask=m), w, seed)
+        info = s.cftp(24)
+        make = lambda init, sd=seed: oracle.SixVertexRegionOracle(m, thr, seed=sd, init=init)
+        R, sample = oracle.cftp(make, max_log2=24)
+        assert info["log2_sweeps"] == R
+        assert (s.export() == sample).all()
+
+
+def test_large_l_shape_one_sweep_sampled():
+    # the L-shape 512 minus its 256 x 256 north-east quarter: 400 sweeps on the
+    # GPU, then the oracle, loaded with that state (validated), takes the next
+    # sweep as the GPU does
+    tl = need_gpu()
+    say("six-vertex L-shape 512, 400 sweeps + one-sweep parity")
+    m = l_shape(512, 256, 256)
+    w, thr = weights(tl, (1, 1, 2), False)
+    s = tl.Sampler(tl.domain(tl.TL_SIXVERTEX, mask=m), w, 12)
+    start = s.export()
+    s.sweep(400)
+    mid = s.export()
+    o = oracle.SixVertexRegionOracle(m, thr, seed=12)
+    assert (start == o.export()).all()
+    o.load(mid)
+    o.t = 400
+    s.sweep(1)
+    o.sweep(1)
+    assert (s.export() == o.export()).all()
+    assert (mid != start).any()

@@ -108,3 +108,37 @@ def test_large_square_is_linear_time():
         ys, xs = np.nonzero(f == 0)
         assert (f[ys + 1, xs] == 1).all()
     assert (tmax != tmin).any()
+
+
+def sixv_extremes(mask):
+    return tl.domain_extremes(tl.domain(tl.TL_SIXVERTEX, mask=mask))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_sixvertex_domains_match_the_oracle(seed):
+    rng = np.random.default_rng(100 + seed)
+    ok = 0
+    for _ in range(60):
+        w, h = int(rng.integers(1, 12)), int(rng.integers(1, 12))
+        m = random_domain(rng, w, h, rng.uniform(0.6, 1.0))
+        try:
+            want = oracle.sixv_extremal_heights(m)
+        except oracle.Untileable:
+            with pytest.raises(tl.TlError) as e:
+                sixv_extremes(m)
+            assert e.value.status == tl.TL_EUNTILEABLE
+            continue
+        got = sixv_extremes(m)
+        assert (got[0] == want[0]).all() and (got[1] == want[1]).all()
+        ok += 1
+    assert ok > 2   # most random domains admit no domain-wall type configuration
+
+
+@pytest.mark.parametrize("shape", ["square", "l", "l2", "big_l"])
+def test_sixvertex_named_domains_match_the_oracle(shape):
+    m = {"square": ones(20, 20), "l": l_shape(12, 5, 6), "l2": l_shape(16, 8, 8), "big_l": l_shape(200, 80, 90)}[shape]
+    got, want = sixv_extremes(m), oracle.sixv_extremal_heights(m)
+    assert (got[0] == want[0]).all() and (got[1] == want[1]).all()
+    if shape == "square":
+        I, J = np.meshgrid(np.arange(21), np.arange(21))
+        assert (got[1] == np.abs(I - J)).all() and (got[0] == 20 - np.abs(I + J - 20)).all()
