@@ -27,7 +27,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
-SOURCES = ["philox.c", "domino.c", "lozenge.c", "sixvertex.c", "sixvertex_region.c"]
+SOURCES = ["philox.c", "domino.c", "lozenge.c", "sixvertex.c", "sixvertex_region.c", "lozenge_region.c"]
 TWO32 = 1 << 32
 
 
@@ -85,6 +85,9 @@ def lib():
         L.or_sixvr_flip.argtypes = [ctypes.c_int, ctypes.c_int, i32p, u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.or_sixvr_sweeps.argtypes = [ctypes.c_int, ctypes.c_int, i32p, u8p, u32p, ctypes.c_int, ctypes.c_uint64,
                                       ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int]
+        L.or_lozr_flip.argtypes = [ctypes.c_int, ctypes.c_int, i32p, u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.or_lozr_sweeps.argtypes = [ctypes.c_int, ctypes.c_int, i32p, u8p, u32p, ctypes.c_int, ctypes.c_uint64,
+                                     ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int]
         L.or_step_colour.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32]
         L.or_step_colour.restype = ctypes.c_uint32
         L.or_sixv_observe.argtypes = [ctypes.c_int, i32p, ctypes.c_uint32, ctypes.c_void_p]
@@ -500,3 +503,5 @@ from .region import (DominoRegionOracle, Untileable, check_region, extremal_heig
                      extremal_tilings, region_embedding, region_heights, tiling_from_heights)
 from .sixv_region import (SixVertexRegionOracle, sixv_boundary_heights, sixv_c_vertices,  # noqa: E402
                           sixv_extremal_heights, sixv_points)
+from .loz_region import (LozengeRegionOracle, check_loz_region, hexagon_mask, loz_extremal_heights,  # noqa: E402
+                         loz_points)

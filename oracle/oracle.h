@@ -97,6 +97,13 @@ int  or_sixv_sweeps(int N, int32_t *h, const uint32_t *thr, int metropolis,
                     uint64_t seed, uint32_t t0, uint32_t nsweeps, int random_colours, or_obs *obs);
 int64_t or_sixv_observe(int N, const int32_t *h, uint32_t bin, uint64_t *bin_sum);
 
+/* ---------------- lozenge tilings of a general domain -------------------- */
+/* w x h unit squares, heights on the (w+1) x (h+1) vertices (index Y*(w+1) + X),
+ * site[Y*(w+1) + X] = 1 for vertices whose six triangles lie in the domain. */
+int  or_lozr_flip(int W, int H, int32_t *Hs, const uint8_t *site, int X, int Y, int up);
+int  or_lozr_sweeps(int W, int H, int32_t *Hs, const uint8_t *site, const uint32_t *thr, int metropolis,
+                    uint64_t seed, uint32_t t0, uint32_t nsweeps, int random_colours);
+
 /* ---------------- six-vertex model on a general domain ------------------- */
 /* W x H cell box, heights on its (W+1) x (H+1) points (index J*(W+1) + I),
  * site[J*(W+1) + I] = 1 for points whose four cells lie in the domain. */
