@@ -70,6 +70,14 @@ typedef enum {
  *   TL_DOMINO    + TL_MASK:        any simply-connected domain (Section 1.1): the faces
  *                                  (x, y) of a w x h box with mask[y*w + x] != 0, row 0
  *                                  southmost; w, h >= 1, w + h <= 32768;
+ *   TL_SIXVERTEX + TL_MASK:        the six-vertex model on a simply-connected domain whose
+ *                                  vertices are the cells (x, y) with mask[y*w + x] != 0,
+ *                                  domain-wall type boundary (below); w, h <= 32767;
+ *   TL_LOZENGE   + TL_MASK:        lozenge tilings of a simply-connected union of unit
+ *                                  triangles: mask[(y*w + x)*2 + t] != 0 selects triangle t
+ *                                  of square (x, y) of the sheared box, t = 0 the lower-right
+ *                                  {(x,y),(x+1,y),(x+1,y+1)}, t = 1 the upper-left
+ *                                  {(x,y),(x,y+1),(x+1,y+1)}; w + h <= 32766;
  *   TL_LOZENGE   + TL_HEXAGON:     hexagon with sides a, b, c >= 1, a+c and b+c <= 32767;
  *   TL_SIXVERTEX + TL_DWBC_SQUARE: N x N vertices, domain-wall boundary, 1 <= n <= 32767.
  *
@@ -86,6 +94,19 @@ typedef enum {
  * black face on its left the height rises by 1 (edge of a domino) or falls by 3
  * (edge covered by a domino).  T_max / T_min are the tilings of largest / smallest
  * height.  Exports and observables use the w x h box (0xFF outside the domain).
+ *
+ * Height-model masks keep the draws, colours and moves of their fixed shapes,
+ * with heights on the (w+1) x (h+1) corner points (export: int32, INT32_MIN off
+ * the domain); the sites are the points whose cells (six-vertex: four;
+ * lozenge: six triangles) all lie in the domain, the other points of the
+ * domain are fixed.  Six-vertex: legs through the south and west sides of cells
+ * carry paths, legs through the north and east sides are empty (the N x N mask
+ * is the domain-wall square); the lowest, then leftmost, point has height
+ * (I + J) mod 2; extremes h_max / h_min; observables: type-c cells of the w x h
+ * box.  Lozenge: Thurston's heights 3H + X + Y fix the boundary; T_max / T_min
+ * are normalised so that the smallest H of T_min is 0 (the hexagon's triangles
+ * give the hexagon exactly); observables: H - H_min at the (w+1) x (h+1)
+ * points.  Either: TL_EUNTILEABLE when no state meets the boundary.
  * Batches and servers take the fixed shapes only. */
 typedef struct {
     int32_t model;   /* tl_model */

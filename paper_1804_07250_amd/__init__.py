@@ -120,8 +120,8 @@ def domain(model, n=0, a=0, b=0, c=0, init=TL_INIT_MIN, mask=None):
     mask's bytes alive; the library copies them when a sampler is created."""
     if mask is not None:
         m = np.ascontiguousarray(np.asarray(mask) != 0, dtype=np.uint8)
-        if m.ndim != 2:
-            raise ValueError("mask must be 2-D")
+        if m.ndim != (3 if model == TL_LOZENGE else 2) or (model == TL_LOZENGE and m.shape[2] != 2):
+            raise ValueError("mask must be (h, w) cells, or (h, w, 2) triangles for lozenges")
         d = tl_domain(model, TL_MASK, 0, 0, 0, 0, init, m.shape[1], m.shape[0],
                       m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
         d._mask = m
@@ -134,7 +134,7 @@ def domain_extremes(dom):
     """Extremal states of a mask domain as canonical exports (host only):
     dominoes (T_max, T_min), six-vertex (h_max, h_min); raises TlError
     (TL_EUNTILEABLE when the domain has no tiling / configuration)."""
-    if dom.model == TL_SIXVERTEX:
+    if dom.model in (TL_SIXVERTEX, TL_LOZENGE):
         tmax = np.empty((dom.h + 1, dom.w + 1), dtype=np.int32)
     else:
         tmax = np.empty((dom.h, dom.w), dtype=np.uint8)

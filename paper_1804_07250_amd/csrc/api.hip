@@ -227,12 +227,14 @@ const char *tl_last_error(void) { return g_last_error.c_str(); }
 tl_status tl_domain_extremes(const tl_domain *dom, void *tmax, void *tmin, size_t bytes)
 {
     if (!dom) return fail(TL_EINVAL, "null argument");
-    if (dom->shape != TL_MASK || (dom->model != TL_DOMINO && dom->model != TL_SIXVERTEX))
-        return fail(TL_EINVAL, "extremal states are computed for domino and six-vertex mask domains");
-    if (dom->model == TL_SIXVERTEX) {
-        tl::SixvRegion r;
+    if (dom->shape != TL_MASK)
+        return fail(TL_EINVAL, "extremal states are computed for mask domains");
+    if (dom->model == TL_SIXVERTEX || dom->model == TL_LOZENGE) {
+        tl::HeightRegion r;
         std::string why;
-        const tl::RegionStatus st = tl::build_sixv_region(dom->mask, dom->w, dom->h, r, why);
+        const tl::RegionStatus st = dom->model == TL_SIXVERTEX
+                                        ? tl::build_sixv_region(dom->mask, dom->w, dom->h, r, why)
+                                        : tl::build_loz_region(dom->mask, dom->w, dom->h, r, why);
         if (st != tl::kRegionOk)
             return fail(st == tl::kRegionUntileable ? TL_EUNTILEABLE : TL_EINVAL, "%s", why.c_str());
         const size_t need = r.hmax.size() * sizeof(int32_t);
@@ -241,6 +243,7 @@ tl_status tl_domain_extremes(const tl_domain *dom, void *tmax, void *tmin, size_
         if (tmin) memcpy(tmin, r.hmin.data(), need);
         return TL_OK;
     }
+    if (dom->model != TL_DOMINO) return fail(TL_EINVAL, "unknown model %d", dom->model);
     tl::Region r;
     std::string why;
     const tl::RegionStatus st = tl::build_region(dom->mask, dom->w, dom->h, r, why);

@@ -207,7 +207,7 @@ __device__ __forceinline__ void sixv_decide(uint32_t k0, uint32_t k1, uint32_t g
 // One lozenge group: sites k = 128 g + (0..127) of plane s0 in row Y.
 // base(p, row) -> pointer to word 4 lg of that plane row (data words, pads
 // around it).  lrow is the row index in the addressed array.
-template <int MODE>
+template <int MODE, bool MASKED>
 __device__ __forceinline__ void loz_group(uint32_t *base, size_t ps, uint32_t rs, uint32_t lrow, uint32_t lgrp,
                                           const Geo &geo, int Y, uint32_t g, uint32_t s0, uint32_t colour, uint32_t t,
                                           const Thr &Tall, uint32_t k0, uint32_t k1)
@@ -236,11 +236,14 @@ __device__ __forceinline__ void loz_group(uint32_t *base, size_t ps, uint32_t rs
     // interior of row Y: X in (max(0, Y-b), min(a+c, Y+a)), X = 3k + s0
     const int xlo = imax(0, Y - geo.b), xhi = imin(geo.a + geo.c, Y + geo.a);
     const int klo = floordiv(xlo - (int)s0, 3) + 1, khi = floordiv(xhi - (int)s0 - 1, 3);
+    // a masked domain: only its sites
+    uint32_t sm[4] = {~0u, ~0u, ~0u, ~0u};
+    if constexpr (MASKED) hld4(geo.site + s0 * geo.sPS + (size_t)Y * geo.sRS + 4u + 4u * g, sm);
     uint32_t live[4], cur[4];
     uint32_t any = 0u;
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
-        const uint32_t m = range_mask((int)(4 * g) + w, klo, khi);
+        const uint32_t m = range_mask((int)(4 * g) + w, klo, khi) & sm[w];
         live[w] = ~(f1[w] ^ f2[w]) & ~(f1[w] ^ f3[w]) & ~(b1[w] ^ b2[w]) & ~(b1[w] ^ b3[w]) & (f1[w] ^ b1[w]) & m;
         cur[w] = ~(O[w] ^ b1[w]);
         any |= live[w];
@@ -335,7 +338,7 @@ __device__ __forceinline__ void height_group(uint32_t *base, size_t ps, uint32_t
     const int pl = colour_plane(geo, y, colour);
     if (pl < 0) return;
     if (geo.model == TL_LOZENGE)
-        loz_group<MODE>(base, ps, rs, lrow, lgrp, geo, y, g, (uint32_t)pl, colour, t, T, k0, k1);
+        loz_group<MODE, MASKED>(base, ps, rs, lrow, lgrp, geo, y, g, (uint32_t)pl, colour, t, T, k0, k1);
     else
         sixv_group<MODE, KIND, MASKED>(base, ps, rs, lrow, lgrp, geo, y, g, (uint32_t)pl, colour, t, T, k0, k1);
 }
@@ -570,6 +573,42 @@ __global__ void sixv_region_export_kernel(const uint32_t *pl, size_t PS, uint32_
     }
 }
 
+// Lozenge domain given by a mask: heights of the (h+1) x (w+1) vertices, one
+// thread per row Y.  Off the domain INT32_MIN; boundary vertices take their
+// fixed height; a site is its west neighbour's height minus one where the
+// parity bits differ (steps along (1,0) are 0 or -1).
+__global__ void loz_region_export_kernel(const uint32_t *pl, size_t PS, uint32_t RS, const int32_t *anchor, int w,
+                                         int h, int32_t *out)
+{
+    const int Y = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (Y > h) return;
+    int32_t prev = 0;
+    uint32_t pbit = 0u;
+    for (int X = 0; X <= w; ++X) {
+        const size_t v = (size_t)Y * (w + 1) + X;
+        const int32_t a = anchor[v];
+        const uint32_t bx = hbit(pl, PS, RS, (uint32_t)X % 3u, (uint32_t)Y, (uint32_t)X / 3u);
+        const int32_t x = a == INT32_MAX ? prev - (int32_t)(bx ^ pbit) : a;
+        out[v] = x;
+        prev = x;
+        pbit = bx;
+    }
+}
+
+// Lozenge domain: H - H_min of every vertex of the domain into bins of B x B
+// vertices, one thread per vertex.
+__global__ void loz_region_volume_kernel(const int32_t *H, const int32_t *hmin, int w, int h, uint32_t B,
+                                         uint32_t bins_x, unsigned long long *bins)
+{
+    const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t n = (uint32_t)(w + 1) * (uint32_t)(h + 1);
+    if (gid >= n) return;
+    if (hmin[gid] == INT32_MIN) return;
+    const int32_t q = H[gid] - hmin[gid];
+    const uint32_t X = gid % (uint32_t)(w + 1), Y = gid / (uint32_t)(w + 1);
+    if (q) atomicAdd(&bins[(size_t)(Y / B) * bins_x + X / B], (unsigned long long)q);
+}
+
 // Type-c cells of a masked six-vertex domain (both diagonal pairs of corner
 // heights equal) into bins of B x B cells, one thread per cell.
 __global__ void sixv_region_count_kernel(const int32_t *H, const uint8_t *cells, int w, int h, uint32_t B,
@@ -789,6 +828,24 @@ hipError_t sixv_region_export(const HeightDev &d, const int32_t *anchor, int w, 
 {
     hipLaunchKernelGGL(sixv_region_export_kernel, dim3((h + 64) / 64), dim3(64), 0, s, d.planes, d.PS, d.RS, anchor,
                        w, h, out);
+    return hipGetLastError();
+}
+
+hipError_t loz_region_export(const HeightDev &d, const int32_t *anchor, int w, int h, int32_t *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(loz_region_export_kernel, dim3((h + 64) / 64), dim3(64), 0, s, d.planes, d.PS, d.RS, anchor, w,
+                       h, out);
+    return hipGetLastError();
+}
+
+hipError_t loz_region_observe(const HeightDev &d, const int32_t *anchor, const int32_t *hmin, int w, int h,
+                              int32_t *heights, uint32_t B, uint32_t bins_x, unsigned long long *bins, hipStream_t s)
+{
+    hipError_t e = loz_region_export(d, anchor, w, h, heights, s);
+    if (e != hipSuccess) return e;
+    const uint32_t n = (uint32_t)(w + 1) * (uint32_t)(h + 1);
+    hipLaunchKernelGGL(loz_region_volume_kernel, dim3((n + 255) / 256), dim3(256), 0, s, heights, hmin, w, h, B,
+                       bins_x, bins);
     return hipGetLastError();
 }
 

@@ -204,6 +204,13 @@ hipError_t sixv_region_export(const HeightDev &d, const int32_t *anchor, int w, 
 hipError_t sixv_region_observe(const HeightDev &d, const int32_t *anchor, const uint8_t *cells, int w, int h,
                                int32_t *heights, uint32_t B, uint32_t bins_x, unsigned long long *bins,
                                hipStream_t s);
+// Lozenge domain given by a mask (w x h squares, c = 0 box): the (h+1) x (w+1)
+// heights anchored as above; the volume H - H_min of its vertices into bins
+// of B x B vertices (hmin: INT32_MIN off the domain).
+hipError_t loz_region_export(const HeightDev &d, const int32_t *anchor, int w, int h, int32_t *out, hipStream_t s);
+hipError_t loz_region_observe(const HeightDev &d, const int32_t *anchor, const int32_t *hmin, int w, int h,
+                              int32_t *heights, uint32_t B, uint32_t bins_x, unsigned long long *bins,
+                              hipStream_t s);
 
 // ------------------------------------------------------ planned tile launches
 // One launch of a tiled multi-sweep kernel, planned on the host: S sweeps,

@@ -224,16 +224,23 @@ public:
         d_.N = dom.n;
         height_words(d_);
     }
-    // Six-vertex domain given by a mask: the state is the square box of
-    // N = max(w, h) cells (the domain's box at its south-west corner); sites
-    // outside the domain never flip (site planes), exports and observables use
-    // the domain's own box.
-    explicit HeightModel(std::shared_ptr<const SixvRegion> r) : region_(std::move(r))
+    // Domain given by a mask: the state box holds the domain's box at its
+    // south-west corner (six-vertex: the square of N = max(w, h) cells;
+    // lozenge: the w x h x 0 box, i.e. the (w+1) x (h+1) vertices); points that
+    // are not sites never flip (site planes); exports and observables use the
+    // domain's own box.
+    explicit HeightModel(std::shared_ptr<const HeightRegion> r) : region_(std::move(r))
     {
         dom_ = tl_domain{};
-        dom_.model = TL_SIXVERTEX;
-        d_.model = TL_SIXVERTEX;
-        d_.N = std::max(region_->w, region_->h);
+        dom_.model = region_->model;
+        d_.model = region_->model;
+        if (region_->model == TL_LOZENGE) {
+            d_.a = region_->w;
+            d_.b = region_->h;
+            d_.c = 0;
+        } else {
+            d_.N = std::max(region_->w, region_->h);
+        }
         height_words(d_);
     }
     std::unique_ptr<Model> twin() const override
@@ -252,17 +259,19 @@ public:
         if (e == hipSuccess) e = hipMalloc(&d_.spare, words * sizeof(uint32_t));
         owned_ = true;
         if (e != hipSuccess || !region_) return e;
-        const size_t V = region_->anchor.size(), C = region_->mask.size();
+        const size_t V = region_->anchor.size(), C = region_->cells.size();
         e = hipMalloc(&site_, words * sizeof(uint32_t));
         if (e == hipSuccess) e = hipMalloc(&anchor_, V * sizeof(int32_t));
         if (e == hipSuccess) e = hipMalloc(&heights_, V * sizeof(int32_t));
+        if (e == hipSuccess) e = hipMalloc(&hmin_, V * sizeof(int32_t));
         if (e == hipSuccess) e = hipMalloc(&cells_, C);
         if (e != hipSuccess) return e;
         std::vector<uint32_t> planes;
         pack_points(region_->site, planes, [](int32_t v) { return v != 0; });
         e = hipMemcpy(site_, planes.data(), planes.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(anchor_, region_->anchor.data(), V * sizeof(int32_t), hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipMemcpy(cells_, region_->mask.data(), C, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(hmin_, region_->hmin.data(), V * sizeof(int32_t), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(cells_, region_->cells.data(), C, hipMemcpyHostToDevice);
         d_.site = site_;
         return e;
     }
@@ -271,26 +280,31 @@ public:
         if (owned_ && d_.planes) (void)hipFree(d_.planes);
         if (owned_ && d_.spare) (void)hipFree(d_.spare);
         d_.planes = d_.spare = nullptr;
-        for (void *p : {(void *)site_, (void *)anchor_, (void *)heights_, (void *)cells_})
+        for (void *p : {(void *)site_, (void *)anchor_, (void *)heights_, (void *)hmin_, (void *)cells_})
             if (p) (void)hipFree(p);
         site_ = nullptr;
-        anchor_ = heights_ = nullptr;
+        anchor_ = heights_ = hmin_ = nullptr;
         cells_ = nullptr;
         d_.site = nullptr;
         timing.release();
     }
     // Bit planes (state layout) of a per-point property of a masked domain:
-    // bit of point (I, J) set iff pred(value at J*(w+1) + I).
+    // bit of point (I, J) set iff pred(value at J*(w+1) + I).  Six-vertex
+    // plane I mod 2, site I / 2; lozenge plane I mod 3, site I / 3.
     template <typename V, typename F>
     void pack_points(const std::vector<V> &vals, std::vector<uint32_t> &host, F pred) const
     {
         host.assign(d_.P * d_.PS, 0u);
-        const int w = region_->w, h = region_->h;
+        const int w = region_->w, h = region_->h, P = loz() ? 3 : 2;
         for (int J = 0; J <= h; ++J)
             for (int I = 0; I <= w; ++I)
-                if (pred((int32_t)vals[(size_t)J * (w + 1) + I]))
-                    host[(size_t)(I & 1) * d_.PS + (size_t)J * d_.RS + 4 + ((I >> 1) >> 5)] |= 1u << ((I >> 1) & 31);
+                if (pred((int32_t)vals[(size_t)J * (w + 1) + I])) {
+                    const int p = I % P, k = I / P;
+                    host[(size_t)p * d_.PS + (size_t)J * d_.RS + 4 + (k >> 5)] |= 1u << (k & 31);
+                }
     }
+    // The residual bit of a height: six-vertex floor(h/2) mod 2, lozenge H mod 2.
+    bool residual(int32_t v) const { return loz() ? (v & 1) != 0 : ((v >> 1) & 1) != 0; }
     size_t state_words() const override
     {
         HeightDev d = d_;
@@ -333,7 +347,7 @@ public:
         std::vector<uint32_t> &host = init_max ? packed_max_ : packed_min_;
         if (host.empty())
             pack_points(init_max ? region_->hmax : region_->hmin, host,
-                        [](int32_t v) { return v != INT32_MIN && ((v >> 1) & 1); });
+                        [this](int32_t v) { return v != INT32_MIN && residual(v); });
         hipError_t e = hipMemcpyAsync(d_.planes, host.data(), host.size() * sizeof(uint32_t),
                                       hipMemcpyHostToDevice, s);
         if (e == hipSuccess)
@@ -408,6 +422,8 @@ public:
     }
     hipError_t observe(uint32_t B, uint32_t bins_x, unsigned long long *bins, hipStream_t s) override
     {
+        if (region_ && loz())
+            return loz_region_observe(d_, anchor_, hmin_, region_->w, region_->h, heights_, B, bins_x, bins, s);
         if (region_)
             return sixv_region_observe(d_, anchor_, cells_, region_->w, region_->h, heights_, B, bins_x, bins, s);
         return height_observe(d_, B, bins_x, bins, s);
@@ -415,8 +431,8 @@ public:
     void cell_box(uint32_t *w, uint32_t *h) const override
     {
         if (region_) {
-            *w = (uint32_t)region_->w;
-            *h = (uint32_t)region_->h;
+            *w = (uint32_t)region_->cw;
+            *h = (uint32_t)region_->ch;
         } else if (loz()) {
             *w = (uint32_t)(d_.a + d_.c + 1);
             *h = (uint32_t)(d_.b + d_.c + 1);
@@ -438,7 +454,7 @@ public:
         cell_box(&w, &h);
         for (uint32_t Y = 0; Y < h; ++Y)
             for (uint32_t X = 0; X < w; ++X) {
-                const bool in = region_ ? region_->mask[(size_t)Y * w + X] != 0 : (!loz() || in_hex((int)X, (int)Y));
+                const bool in = region_ ? region_->cells[(size_t)Y * w + X] != 0 : (!loz() || in_hex((int)X, (int)Y));
                 if (in) cnt[(size_t)(Y / B) * bx + X / B] += 1;
             }
         return cnt;
@@ -450,13 +466,16 @@ public:
     }
     hipError_t export_canonical(uint8_t *dev, hipStream_t s) override
     {
+        if (region_ && loz())
+            return loz_region_export(d_, anchor_, region_->w, region_->h, reinterpret_cast<int32_t *>(dev), s);
         if (region_)
             return sixv_region_export(d_, anchor_, region_->w, region_->h, reinterpret_cast<int32_t *>(dev), s);
         return height_export(d_, reinterpret_cast<int32_t *>(dev), s);
     }
-    // Masked six-vertex domain: off the domain INT32_MIN, boundary points their
-    // fixed heights, sites one away from their four neighbours with the parity
-    // of I + J.
+    // Masked domain: off the domain INT32_MIN, boundary points their fixed
+    // heights; six-vertex sites one away from their four neighbours with the
+    // parity of I + J; lozenge sites with steps 0 or -1 to their six
+    // neighbours along (1,0), (0,1), (1,1).
     bool import_region(const int32_t *H, std::vector<uint32_t> &host, std::string &why) const
     {
         const int w = region_->w, h = region_->h, PW = w + 1;
@@ -473,6 +492,19 @@ public:
                     if (a != INT32_MIN) vals[v] = x;
                     continue;
                 }
+                if (loz()) {
+                    // forward neighbours: x minus 0 or 1; backward ones: x plus 0 or 1
+                    const int32_t fw[3] = {H[v + 1], H[v + PW], H[v + PW + 1]};
+                    const int32_t bw[3] = {H[v - 1], H[v - PW], H[v - PW - 1]};
+                    for (int q = 0; q < 3; ++q)
+                        if (fw[q] == INT32_MIN || bw[q] == INT32_MIN || (x - fw[q] != 0 && x - fw[q] != 1) ||
+                            (bw[q] - x != 0 && bw[q] - x != 1)) {
+                            why = "height step not in {0, -1}";
+                            return false;
+                        }
+                    vals[v] = x;
+                    continue;
+                }
                 const int32_t nb[4] = {H[v - 1], H[v + 1], H[v - PW], H[v + PW]};
                 for (int32_t y : nb)
                     if (y == INT32_MIN || (x > y ? x - y : y - x) != 1) {
@@ -485,7 +517,7 @@ public:
                 }
                 vals[v] = x;
             }
-        pack_points(vals, host, [](int32_t x) { return x != INT32_MIN && ((x >> 1) & 1); });
+        pack_points(vals, host, [this](int32_t x) { return x != INT32_MIN && residual(x); });
         return true;
     }
     bool import_canonical(const uint8_t *raw, hipStream_t s, std::string &why, hipError_t *err) override
@@ -569,9 +601,9 @@ private:
     tl_domain dom_;
     HeightDev d_;
     bool owned_ = false;
-    std::shared_ptr<const SixvRegion> region_;
+    std::shared_ptr<const HeightRegion> region_;
     uint32_t *site_ = nullptr;
-    int32_t *anchor_ = nullptr, *heights_ = nullptr;
+    int32_t *anchor_ = nullptr, *heights_ = nullptr, *hmin_ = nullptr;
     uint8_t *cells_ = nullptr;
     std::vector<uint32_t> packed_max_, packed_min_;
 };
@@ -582,13 +614,22 @@ std::unique_ptr<Model> make_model(const tl_domain &d, std::string &why, tl_statu
 {
     if (status) *status = TL_EINVAL;
     if (d.model == TL_SIXVERTEX && d.shape == TL_MASK) {
-        auto r = std::make_shared<SixvRegion>();
+        auto r = std::make_shared<HeightRegion>();
         const RegionStatus st = build_sixv_region(d.mask, d.w, d.h, *r, why);
         if (st != kRegionOk) {
             if (status && st == kRegionUntileable) *status = TL_EUNTILEABLE;
             return nullptr;
         }
-        return std::unique_ptr<Model>(new HeightModel(std::shared_ptr<const SixvRegion>(std::move(r))));
+        return std::unique_ptr<Model>(new HeightModel(std::shared_ptr<const HeightRegion>(std::move(r))));
+    }
+    if (d.model == TL_LOZENGE && d.shape == TL_MASK) {
+        auto r = std::make_shared<HeightRegion>();
+        const RegionStatus st = build_loz_region(d.mask, d.w, d.h, *r, why);
+        if (st != kRegionOk) {
+            if (status && st == kRegionUntileable) *status = TL_EUNTILEABLE;
+            return nullptr;
+        }
+        return std::unique_ptr<Model>(new HeightModel(std::shared_ptr<const HeightRegion>(std::move(r))));
     }
     if (d.model == TL_DOMINO && d.shape == TL_MASK) {
         auto r = std::make_shared<Region>();

@@ -261,15 +261,19 @@ RegionStatus build_region(const uint8_t *mask, int w, int h, Region &r, std::str
 // largest is min_b h(b) + dist(b, v), the smallest max_b h(b) - dist(b, v)
 // (unit lengths, a bucket queue from all boundary points at once), and one
 // exists iff both meet the boundary heights.
-RegionStatus build_sixv_region(const uint8_t *mask, int w, int h, SixvRegion &r, std::string &why)
+RegionStatus build_sixv_region(const uint8_t *mask, int w, int h, HeightRegion &r, std::string &why)
 {
-    const RegionStatus vs = validate_mask(mask, w, h, r.mask, r.cells, why);
+    uint64_t ncells = 0;
+    const RegionStatus vs = validate_mask(mask, w, h, r.cells, ncells, why);
     if (vs != kRegionOk) return vs;
+    r.model = 2;   // TL_SIXVERTEX
     r.w = w;
     r.h = h;
+    r.cw = w;
+    r.ch = h;
     const int PW = w + 1;
     const size_t V = (size_t)PW * (h + 1);
-    auto in = [&](int x, int y) { return x >= 0 && y >= 0 && x < w && y < h && r.mask[(size_t)y * w + x] != 0; };
+    auto in = [&](int x, int y) { return x >= 0 && y >= 0 && x < w && y < h && r.cells[(size_t)y * w + x] != 0; };
     std::vector<uint8_t> pt(V, 0);
     r.site.assign(V, 0);
     r.sites = 0;
@@ -365,6 +369,196 @@ RegionStatus build_sixv_region(const uint8_t *mask, int w, int h, SixvRegion &r,
         r.hmax[v] = up[v];
         r.hmin[v] = -down[v];
         r.anchor[v] = r.site[v] ? INT32_MAX : hb[v];
+    }
+    return kRegionOk;
+}
+
+// Lozenge domains.  Triangle (x, y, t) has edge-neighbours: t = 0 -> (x, y, 1),
+// (x, y-1, 1), (x+1, y, 1); t = 1 -> (x, y, 0), (x, y+1, 0), (x-1, y, 0).
+RegionStatus build_loz_region(const uint8_t *mask, int w, int h, HeightRegion &r, std::string &why)
+{
+    if (!mask || w < 1 || h < 1 || (int64_t)w + h > 32766) {
+        why = "lozenge mask domain needs a mask and 1 <= w, h with w + h <= 32766";
+        return kRegionInvalid;
+    }
+    const size_t T = (size_t)w * h * 2;
+    std::vector<uint8_t> m(T);
+    uint64_t count = 0;
+    for (size_t i = 0; i < T; ++i) {
+        m[i] = mask[i] ? 1 : 0;
+        count += m[i];
+    }
+    if (!count) {
+        why = "empty domain";
+        return kRegionInvalid;
+    }
+    auto in = [&](int x, int y, int t) {
+        return x >= 0 && y >= 0 && x < w && y < h && m[((size_t)y * w + x) * 2 + t] != 0;
+    };
+    // the six triangles at point (X, Y), counter-clockwise from the edge (1,0)
+    auto ring = [&](int X, int Y, bool out[6]) {
+        out[0] = in(X, Y, 0);
+        out[1] = in(X, Y, 1);
+        out[2] = in(X - 1, Y, 0);
+        out[3] = in(X - 1, Y - 1, 1);
+        out[4] = in(X - 1, Y - 1, 0);
+        out[5] = in(X, Y - 1, 1);
+    };
+    const int PW = w + 1;
+    const size_t V = (size_t)PW * (h + 1);
+    std::vector<uint8_t> pt(V, 0);
+    r.site.assign(V, 0);
+    r.sites = 0;
+    size_t start = V;
+    for (int Y = 0; Y <= h; ++Y)
+        for (int X = 0; X <= w; ++X) {
+            bool rg[6];
+            ring(X, Y, rg);
+            int n = 0, runs = 0;
+            for (int i = 0; i < 6; ++i) {
+                n += rg[i];
+                runs += rg[i] && !rg[(i + 5) % 6];
+            }
+            if (n > 0 && n < 6 && runs > 1) {
+                why = "domain pinched at vertex (" + std::to_string(X) + ", " + std::to_string(Y) + ")";
+                return kRegionInvalid;
+            }
+            const size_t v = (size_t)Y * PW + X;
+            pt[v] = n > 0;
+            r.site[v] = n == 6;
+            r.sites += r.site[v];
+            if (pt[v] && start == V) start = v;
+        }
+    // connectivity of the triangles, and of the complement in the box grown by
+    // one square (no holes)
+    auto components_ok = [&](int W, int H, auto sel, uint64_t expected) {
+        std::vector<uint8_t> seen((size_t)W * H * 2, 0);
+        size_t first = seen.size();
+        for (size_t i = 0; i < seen.size() && first == seen.size(); ++i)
+            if (sel((int)((i / 2) % W), (int)((i / 2) / W), (int)(i & 1))) first = i;
+        if (first == seen.size()) return expected == 0;
+        std::vector<size_t> stack{first};
+        seen[first] = 1;
+        uint64_t got = 1;
+        while (!stack.empty()) {
+            const size_t c = stack.back();
+            stack.pop_back();
+            const int x = (int)((c / 2) % W), y = (int)((c / 2) / W), t = (int)(c & 1);
+            const int nb[3][3] = {{x, y, 1 - t}, {x, t ? y + 1 : y - 1, 1 - t}, {t ? x - 1 : x + 1, y, 1 - t}};
+            for (const auto &q : nb) {
+                if (q[0] < 0 || q[1] < 0 || q[0] >= W || q[1] >= H || !sel(q[0], q[1], q[2])) continue;
+                const size_t d = ((size_t)q[1] * W + q[0]) * 2 + q[2];
+                if (!seen[d]) {
+                    seen[d] = 1;
+                    ++got;
+                    stack.push_back(d);
+                }
+            }
+        }
+        return got == expected;
+    };
+    if (!components_ok(w, h, in, count)) {
+        why = "domain is not connected";
+        return kRegionInvalid;
+    }
+    if (!components_ok(w + 2, h + 2, [&](int x, int y, int t) { return !in(x - 1, y - 1, t); },
+                       (uint64_t)(w + 2) * (h + 2) * 2 - count)) {
+        why = "domain has a hole";
+        return kRegionInvalid;
+    }
+    // Steps out of a point: offset, the triangle on the left and on the right.
+    struct Step {
+        int dX, dY, lx, ly, lt, rx, ry, rt;
+    };
+    static constexpr Step kS[6] = {{1, 0, 0, 0, 0, 0, -1, 1},     {0, 1, -1, 0, 0, 0, 0, 1},
+                                   {1, 1, 0, 0, 1, 0, 0, 0},      {-1, 0, -1, -1, 1, -1, 0, 0},
+                                   {0, -1, 0, -1, 1, -1, -1, 0},  {-1, -1, -1, -1, 0, -1, -1, 1}};
+    std::vector<int32_t> hb(V, kUnset);
+    {
+        const int X0 = (int)(start % PW), Y0 = (int)(start / PW);
+        hb[start] = X0 + Y0;
+        std::vector<size_t> stack{start};
+        while (!stack.empty()) {
+            const size_t v = stack.back();
+            stack.pop_back();
+            const int X = (int)(v % PW), Y = (int)(v / PW);
+            for (const Step &s : kS) {
+                const bool li = in(X + s.lx, Y + s.ly, s.lt), ri = in(X + s.rx, Y + s.ry, s.rt);
+                if (li == ri) continue;
+                // bounding edge: +1 along a lower-right triangle's counter-clockwise
+                // walk, -1 along an upper-left one's
+                const int inc = li ? (s.lt == 0 ? 1 : -1) : (s.rt == 0 ? -1 : 1);
+                const size_t u = (size_t)(Y + s.dY) * PW + X + s.dX;
+                const int32_t hu = hb[v] + inc;
+                if (hb[u] == kUnset) {
+                    hb[u] = hu;
+                    stack.push_back(u);
+                } else if (hb[u] != hu) {
+                    why = "no tiling: the boundary heights do not close up";
+                    return kRegionUntileable;
+                }
+            }
+        }
+    }
+    auto bound = [&](int sign, int len_lr, int len_ul) {
+        std::vector<int32_t> dist(V, kUnset);
+        int32_t kmin = INT32_MAX;
+        for (size_t v = 0; v < V; ++v)
+            if (hb[v] != kUnset) kmin = std::min(kmin, sign * hb[v]);
+        std::vector<std::vector<uint32_t>> buckets;
+        auto push = [&](size_t v, int32_t key) {
+            dist[v] = key;
+            const size_t b = (size_t)(key - kmin);
+            if (b >= buckets.size()) buckets.resize(b + 1);
+            buckets[b].push_back((uint32_t)v);
+        };
+        for (size_t v = 0; v < V; ++v)
+            if (hb[v] != kUnset) push(v, sign * hb[v]);
+        for (size_t b = 0; b < buckets.size(); ++b) {
+            for (size_t q = 0; q < buckets[b].size(); ++q) {
+                const uint32_t v = buckets[b][q];
+                const int32_t d = (int32_t)b + kmin;
+                if (dist[v] != d) continue;
+                const int X = (int)(v % PW), Y = (int)(v / PW);
+                for (const Step &s : kS) {
+                    if (!in(X + s.lx, Y + s.ly, s.lt) && !in(X + s.rx, Y + s.ry, s.rt)) continue;
+                    const size_t u = (size_t)(Y + s.dY) * PW + X + s.dX;
+                    const int32_t nd = d + (s.lt == 0 ? len_lr : len_ul);
+                    if (dist[u] == kUnset || nd < dist[u]) push(u, nd);
+                }
+            }
+            std::vector<uint32_t>().swap(buckets[b]);
+        }
+        return dist;
+    };
+    const std::vector<int32_t> up = bound(1, 1, 2), down = bound(-1, 2, 1);
+    r.model = 1;   // TL_LOZENGE
+    r.w = w;
+    r.h = h;
+    r.cw = w + 1;
+    r.ch = h + 1;
+    r.cells.assign(V, 0);
+    r.hmax.assign(V, INT32_MIN);
+    r.hmin.assign(V, INT32_MIN);
+    r.anchor.assign(V, INT32_MIN);
+    int32_t lowest = INT32_MAX;
+    for (size_t v = 0; v < V; ++v) {
+        if (!pt[v]) continue;
+        if (hb[v] != kUnset && (up[v] != hb[v] || down[v] != -hb[v])) {
+            why = "no tiling: no height function meets the boundary heights";
+            return kRegionUntileable;
+        }
+        const int XY = (int)(v % PW) + (int)(v / PW);
+        r.hmax[v] = (up[v] - XY) / 3;    // exact: h' - X - Y is a multiple of 3
+        r.hmin[v] = (-down[v] - XY) / 3;
+        lowest = std::min(lowest, r.hmin[v]);
+    }
+    for (size_t v = 0; v < V; ++v) {
+        if (!pt[v]) continue;
+        r.cells[v] = 1;
+        r.hmax[v] -= lowest;
+        r.hmin[v] -= lowest;
+        r.anchor[v] = r.site[v] ? INT32_MAX : r.hmin[v];
     }
     return kRegionOk;
 }

@@ -35,23 +35,42 @@ void region_embedding(int w, int h, int *n, int *ox, int *oy);
 // or -3 (a domino covers it), with a white face on its left by -1 or +3.
 RegionStatus build_region(const uint8_t *mask, int w, int h, Region &r, std::string &why);
 
-// The six-vertex model on a domain (Section 1.2 with the domains of Section
-// 1.1): the model's vertices are the cells of a w x h mask, heights live on the
-// (w+1) x (h+1) cell corners (point (I, J) at index J*(w+1) + I), sites are the
-// corners whose four cells all lie in the domain.  Domain-wall type boundary:
-// legs through the south and west sides of cells carry paths, legs through the
-// north and east sides are empty; walking a boundary edge in +x the height
-// rises by 1 if the domain is above it and falls by 1 if below, in +y it rises
-// if the domain is to its right and falls if to its left; the lowest, then
-// leftmost, point gets height (I + J) mod 2.
-struct SixvRegion {
+// A height-function model on a domain given by a mask over a box of w x h
+// unit squares: heights on the (w+1) x (h+1) points (point (I, J) at index
+// J*(w+1) + I), the sites those whose surrounding cells all lie in the domain,
+// the other points of the domain fixed by its boundary.  Observable cells:
+// six-vertex, the cw x ch = w x h cells (the model's vertices); lozenge, the
+// (w+1) x (h+1) points of the domain.
+struct HeightRegion {
+    int model = 0;                       // TL_SIXVERTEX or TL_LOZENGE
     int w = 0, h = 0;
-    std::vector<uint8_t> mask;           // w*h cells, 1 = in the domain
+    int cw = 0, ch = 0;                  // box of the observable cells
+    std::vector<uint8_t> cells;          // cw*ch, 1 = cell of the domain
     std::vector<uint8_t> site;           // (w+1)*(h+1) points, 1 = site
     std::vector<int32_t> anchor;         // boundary height; INT32_MIN off the domain; INT32_MAX at sites
-    std::vector<int32_t> hmax, hmin;     // extremal configurations (INT32_MIN off the domain)
-    uint64_t sites = 0, cells = 0;
+    std::vector<int32_t> hmax, hmin;     // extremal states (INT32_MIN off the domain)
+    uint64_t sites = 0;
 };
-RegionStatus build_sixv_region(const uint8_t *mask, int w, int h, SixvRegion &r, std::string &why);
+
+// Six-vertex (Section 1.2 with the domains of Section 1.1): the model's
+// vertices are the cells of a w x h mask, sites are the corners whose four
+// cells lie in the domain.  Domain-wall type boundary: legs through the south
+// and west sides of cells carry paths, legs through the north and east sides
+// are empty; walking a boundary edge in +x the height rises by 1 if the domain
+// is above it and falls by 1 if below, in +y it rises if the domain is to its
+// right and falls if to its left; the lowest, then leftmost, point gets height
+// (I + J) mod 2.
+RegionStatus build_sixv_region(const uint8_t *mask, int w, int h, HeightRegion &r, std::string &why);
+
+// Lozenges (Section 1.2's triangular lattice: Z^2 with the diagonals (1,1);
+// the domains of Section 1.1): mask[(y*w + x)*2 + t] selects triangle t of unit
+// square (x, y), t = 0 the lower-right {(x,y), (x+1,y), (x+1,y+1)}, t = 1 the
+// upper-left {(x,y), (x,y+1), (x+1,y+1)}.  Sites are the points whose six
+// triangles lie in the domain.  Thurston's heights h' = 3H + X + Y rise by 1
+// along the bounding edges of a lower-right triangle walked counter-clockwise
+// and fall by 2 across the edge its lozenge covers (signs flipped for
+// upper-left triangles); H_max / H_min are the shortest-path bounds from the
+// boundary (lengths 1 and 2), normalised so that the smallest H_min is 0.
+RegionStatus build_loz_region(const uint8_t *mask, int w, int h, HeightRegion &r, std::string &why);
 
 }  // namespace tl

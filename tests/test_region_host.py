@@ -142,3 +142,45 @@ def test_sixvertex_named_domains_match_the_oracle(shape):
     if shape == "square":
         I, J = np.meshgrid(np.arange(21), np.arange(21))
         assert (got[1] == np.abs(I - J)).all() and (got[0] == 20 - np.abs(I + J - 20)).all()
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_lozenge_domains_match_the_oracle(seed):
+    from test_oracle_loz_region import random_tri_domain
+    rng = np.random.default_rng(200 + seed)
+    ok = 0
+    for _ in range(40):
+        m = random_tri_domain(rng, int(rng.integers(2, 8)), int(rng.integers(2, 7)), rng.uniform(0.6, 1.0))
+        try:
+            want = oracle.loz_extremal_heights(m)
+        except oracle.Untileable:
+            with pytest.raises(tl.TlError) as e:
+                tl.domain_extremes(tl.domain(tl.TL_LOZENGE, mask=m))
+            assert e.value.status == tl.TL_EUNTILEABLE
+            continue
+        got = tl.domain_extremes(tl.domain(tl.TL_LOZENGE, mask=m))
+        assert (got[0] == want[0]).all() and (got[1] == want[1]).all()
+        ok += 1
+    assert ok > 2
+
+
+@pytest.mark.parametrize("abc", [(1, 1, 1), (7, 5, 6), (40, 31, 25)])
+def test_lozenge_hexagon_masks_give_the_boxes(abc):
+    got = tl.domain_extremes(tl.domain(tl.TL_LOZENGE, mask=oracle.hexagon_mask(*abc)))
+    assert (got[1] == oracle.LozengeOracle(*abc, [0, 0]).export()).all()
+    assert (got[0] == oracle.LozengeOracle(*abc, [0, 0], init="max").export()).all()
+
+
+def test_lozenge_mask_errors():
+    ring = np.ones((4, 4, 2), dtype=bool)
+    ring[1:3, 1:3, :] = False
+    with pytest.raises(tl.TlError) as e:
+        tl.domain_extremes(tl.domain(tl.TL_LOZENGE, mask=ring))
+    assert e.value.status == tl.TL_EINVAL
+    one = np.zeros((1, 1, 2), dtype=bool)
+    one[0, 0, 0] = True
+    with pytest.raises(tl.TlError) as e:
+        tl.domain_extremes(tl.domain(tl.TL_LOZENGE, mask=one))
+    assert e.value.status == tl.TL_EUNTILEABLE
+    with pytest.raises(ValueError):
+        tl.domain(tl.TL_LOZENGE, mask=np.ones((3, 3), dtype=bool))
