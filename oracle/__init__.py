@@ -83,8 +83,8 @@ def lib():
         L.or_sixv_sweeps.argtypes = [ctypes.c_int, i32p, u32p, ctypes.c_int, ctypes.c_uint64,
                                      ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, ctypes.c_void_p]
         L.or_sixvr_flip.argtypes = [ctypes.c_int, ctypes.c_int, i32p, u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
-        L.or_sixvr_sweeps.argtypes = [ctypes.c_int, ctypes.c_int, i32p, u8p, u32p, ctypes.c_int, ctypes.c_uint64,
-                                      ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int]
+        L.or_sixvr_sweeps.argtypes = [ctypes.c_int, ctypes.c_int, i32p, u8p, u32p, u32p, ctypes.c_int,
+                                      ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int]
         L.or_lozr_flip.argtypes = [ctypes.c_int, ctypes.c_int, i32p, u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.or_lozr_sweeps.argtypes = [ctypes.c_int, ctypes.c_int, i32p, u8p, u32p, ctypes.c_int, ctypes.c_uint64,
                                      ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int]
@@ -243,6 +243,29 @@ def sixv_ratios6(a1, a2, b1, b2, c1, c2):
             for cx, cy in ((0, 0), (-1, 0), (-1, -1), (0, -1)):   # corners NE, NW, SW, SE
                 W *= w[sixv_vertex_type(h[(cx, cy)], h[(cx + 1, cy)], h[(cx, cy + 1)], h[(cx + 1, cy + 1)])]
             return W
+
+        out.append(weight(m + 1) / weight(m - 1))
+    return out
+
+
+def sixv_free_ratios6(a1, a2, b1, b2, c1, c2):
+    """W_up / W_down of a flip at a point of a free north edge (the boundary
+    variation of the c-flip, Section 1.2), for each context
+    (SW at m+1) + 2 (SE at m+1): the point at m-1 or m+1, its west, east and
+    south neighbours at m, the two diagonal points below it at m+1 or m-1;
+    the weight of a state is the product over the two cells below the point
+    (the only vertices it touches) of the weight of the cell's type."""
+    w = {"a1": Fraction(a1), "a2": Fraction(a2), "b1": Fraction(b1), "b2": Fraction(b2),
+         "c1": Fraction(c1), "c2": Fraction(c2)}
+    out = []
+    for ctx in range(4):
+        m = 10
+        hSW = m + 1 if ctx & 1 else m - 1
+        hSE = m + 1 if ctx & 2 else m - 1
+
+        def weight(f):
+            # cell left of the point: corners SW, S, W, point; right: S, SE, point, E
+            return w[sixv_vertex_type(hSW, m, m, f)] * w[sixv_vertex_type(m, hSE, f, m)]
 
         out.append(weight(m + 1) / weight(m - 1))
     return out
@@ -502,6 +525,6 @@ def bin_density(bin_sum, samples, in_domain, bin_):
 from .region import (DominoRegionOracle, Untileable, check_region, extremal_heights,  # noqa: E402
                      extremal_tilings, region_embedding, region_heights, tiling_from_heights)
 from .sixv_region import (SixVertexRegionOracle, sixv_boundary_heights, sixv_c_vertices,  # noqa: E402
-                          sixv_extremal_heights, sixv_points)
+                          sixv_extremal_heights, sixv_free_points, sixv_points)
 from .loz_region import (LozengeRegionOracle, check_loz_region, hexagon_mask, loz_extremal_heights,  # noqa: E402
                          loz_points)

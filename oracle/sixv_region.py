@@ -73,10 +73,18 @@ def _edges(inside, I, J):
             yield (I2, J2), ir + il, sign * (1 if ir else -1)
 
 
-def sixv_boundary_heights(mask):
-    """Heights of the boundary points (points of the domain that are not
-    sites) under the domain-wall type boundary; raises Untileable if the walk
-    around the boundary does not close up."""
+def _free_edge(inside, u, v):
+    """Is the boundary edge u-v the north side of a domain cell?"""
+    (I, J), (I2, J2) = u, v
+    return J == J2 and inside(min(I, I2), J - 1) and not inside(min(I, I2), J)
+
+
+def sixv_boundary_heights(mask, free_north=False):
+    """Heights of the fixed boundary points under the domain-wall type
+    boundary; raises Untileable if the walk around the boundary does not close
+    up.  With free_north the legs through the north sides of cells are free:
+    those boundary edges are not walked, and the points whose boundary edges
+    are all such edges are free (absent from the result)."""
     m, w, h, inside = _cells(mask)
     pts, sites = sixv_points(m)
     order = [(I, J) for J in range(h + 1) for I in range(w + 1) if pts[J, I]]
@@ -86,7 +94,7 @@ def sixv_boundary_heights(mask):
     while stack:
         u = stack.pop()
         for v, ncells, dh in _edges(inside, *u):
-            if ncells != 1:
+            if ncells != 1 or (free_north and _free_edge(inside, u, v)):
                 continue
             hv = hb[u] + dh
             if v in hb:
@@ -98,15 +106,32 @@ def sixv_boundary_heights(mask):
     return hb
 
 
-def sixv_extremal_heights(mask):
+def sixv_free_points(mask):
+    """Points whose boundary edges are all north sides of domain cells."""
+    m, w, h, inside = _cells(mask)
+    pts, sites = sixv_points(m)
+    free = np.zeros_like(pts)
+    for J in range(h + 1):
+        for I in range(w + 1):
+            if not pts[J, I] or sites[J, I]:
+                continue
+            bnd = [(v, ncells) for v, ncells, _ in _edges(inside, I, J) if ncells == 1]
+            free[J, I] = all(_free_edge(inside, (I, J), v) for v, _ in bnd)
+    return free
+
+
+def sixv_extremal_heights(mask, free_north=False):
     """(h_max, h_min) as (h+1) x (w+1) int64 arrays (I32MIN off the domain);
-    raises Untileable when no configuration meets the boundary."""
+    raises Untileable when no configuration meets the boundary, ValueError
+    when free edges split the fixed boundary into several pieces."""
     m, w, h, inside = _cells(mask)
     check_region(m)
     pts, sites = sixv_points(m)
-    hb = sixv_boundary_heights(m)
-    if any(not sites[J, I] for J in range(h + 1) for I in range(w + 1) if pts[J, I] and (I, J) not in hb):
-        raise Untileable("boundary not connected")
+    hb = sixv_boundary_heights(m, free_north)
+    free = sixv_free_points(m) if free_north else np.zeros_like(pts)
+    if any(not sites[J, I] and not free[J, I] for J in range(h + 1) for I in range(w + 1)
+           if pts[J, I] and (I, J) not in hb):
+        raise ValueError("the fixed boundary is not one piece")
 
     def bound(sign):
         dist = {v: sign * x for v, x in hb.items()}
@@ -148,7 +173,7 @@ class SixVertexRegionOracle:
     domain-wall square) on a general domain with domain-wall type boundary."""
 
     def __init__(self, mask, thr, metropolis=False, seed=0, obs_every=0, bin_=1, init="min",
-                 random_colours=False):
+                 random_colours=False, free_north=False, thr_free=None):
         from . import _p, lib
         self._lib, self._pp = lib, _p
         m = np.asarray(mask, dtype=bool)
@@ -156,8 +181,11 @@ class SixVertexRegionOracle:
         self.h_, self.w = m.shape
         pts, sites = sixv_points(m)
         self.points = pts
-        self.site = np.ascontiguousarray(sites, dtype=np.uint8)
-        self.hmax, self.hmin = sixv_extremal_heights(m)
+        self.free = sixv_free_points(m) if free_north else np.zeros_like(pts)
+        # site codes: 1 interior, 2 on a free north edge
+        self.site = np.ascontiguousarray(sites.astype(np.uint8) + 2 * self.free.astype(np.uint8))
+        self.thr_free = np.asarray(thr_free if thr_free is not None else [0] * 8, dtype=np.uint32)
+        self.hmax, self.hmin = sixv_extremal_heights(m, free_north)
         self.H = np.ascontiguousarray((self.hmax if init == "max" else self.hmin).astype(np.int32))
         self.thr = np.asarray(thr, dtype=np.uint32)
         self.metropolis = metropolis
@@ -175,8 +203,8 @@ class SixVertexRegionOracle:
     def _sweep(self, n):
         p = self._pp
         self._lib().or_sixvr_sweeps(self.w, self.h_, p(self.H, ctypes.c_int32), p(self.site, ctypes.c_uint8),
-                                    p(self.thr, ctypes.c_uint32), int(self.metropolis), self.seed, self.t, n,
-                                    int(self.random_colours))
+                                    p(self.thr, ctypes.c_uint32), p(self.thr_free, ctypes.c_uint32),
+                                    int(self.metropolis), self.seed, self.t, n, int(self.random_colours))
         self.t += n
 
     def sweep(self, nsweeps):
@@ -201,7 +229,7 @@ class SixVertexRegionOracle:
         H = np.asarray(H, dtype=np.int64)
         if H.shape != self.H.shape:
             raise ValueError("wrong shape")
-        fixed = self.points & ~self.site.astype(bool)
+        fixed = self.points & (self.site == 0)
         if not (H[fixed] == self.hmin[fixed]).all() or not (H[~self.points] == I32MIN).all():
             raise ValueError("boundary heights differ")
         self.H[:] = np.where(self.points, H, 0).astype(np.int32)
@@ -225,4 +253,5 @@ class SixVertexRegionOracle:
         return self.mask.copy()
 
     def sites(self):
+        """Points that may flip (interior sites and free-edge points)."""
         return [(I, J) for J in range(self.h_ + 1) for I in range(self.w + 1) if self.site[J, I]]

@@ -28,18 +28,19 @@ import test_oracle_sixvertex as tos
 I32MIN = np.iinfo(np.int32).min
 
 
-def enumerate_configs(mask):
-    """Every height function of the domain (brute force): sites in row-major
-    order take a value one away from their west and south neighbours (both
-    already known), the east and north neighbours that are fixed are checked,
-    and a complete assignment is kept if every cell side joins heights one
-    apart."""
+def enumerate_configs(mask, free_north=False):
+    """Every height function of the domain (brute force): sites (and free
+    points) in row-major order take a value one away from their west and
+    south neighbours (both already known), the east and north neighbours that
+    are fixed are checked, and a complete assignment is kept if every cell side
+    joins heights one apart."""
     pts, sites = oracle.sixv_points(mask)
-    hb = oracle.sixv_boundary_heights(mask)
+    hb = oracle.sixv_boundary_heights(mask, free_north)
     H = np.full(pts.shape, I32MIN, dtype=np.int64)
     for (I, J), v in hb.items():
         H[J, I] = v
-    order = [(I, J) for J in range(pts.shape[0]) for I in range(pts.shape[1]) if sites[J, I]]
+    free = oracle.sixv_free_points(mask) if free_north else np.zeros_like(pts)
+    order = [(I, J) for J in range(pts.shape[0]) for I in range(pts.shape[1]) if sites[J, I] or free[J, I]]
     fixed = {(I, J) for (I, J) in hb}
     out = []
 
@@ -242,3 +243,121 @@ def test_observables_on_a_domain():
     v, bs = ch.observe()
     assert v == int(oracle.sixv_c_vertices(m, ch.export()).sum()) and bs.sum() == v
     assert int(ch.samples[0]) == 4
+
+
+# ------------------------------------------------------------ free north edge
+
+STOCH = (1, 1, Fraction(3, 10), Fraction(7, 10), Fraction(3, 10), Fraction(7, 10))
+
+
+def weight6(mask, H, wts):
+    """prod over the domain's cells of the weight of the vertex type read off
+    the corner heights (a1 none, a2 all four, b1 left+right, b2 bottom+top,
+    c1 bottom+left, c2 right+top)."""
+    names = ("a1", "a2", "b1", "b2", "c1", "c2")
+    w = dict(zip(names, [Fraction(x) for x in wts]))
+    p = Fraction(1)
+    for y, x in zip(*np.nonzero(mask)):
+        p *= w[oracle.sixv_vertex_type(H[y, x], H[y, x + 1], H[y + 1, x], H[y + 1, x + 1])]
+    return p
+
+
+def free_chain(mask, wts, seed=1, init="min", **kw):
+    thr = oracle.table_from_ratios(oracle.sixv_ratios6(*wts), False)
+    thr_free = oracle.table_from_ratios(oracle.sixv_free_ratios6(*wts), False)
+    return oracle.SixVertexRegionOracle(mask, thr, seed=seed, init=init, free_north=True, thr_free=thr_free, **kw)
+
+
+@pytest.mark.parametrize("hw", [(3, 4), (2, 5), (4, 4), (3, 6)])
+def test_free_north_extremes_and_connectivity(hw):
+    m = ones(*hw)
+    configs = enumerate_configs(m, free_north=True)
+    assert configs
+    hmax, hmin = oracle.sixv_extremal_heights(m, free_north=True)
+    stack = np.stack(configs)
+    pts = hmax != I32MIN
+    assert (stack.max(axis=0)[pts] == hmax[pts]).all() and (stack.min(axis=0)[pts] == hmin[pts]).all()
+    keys = {c.tobytes() for c in configs}
+    for init in ("min", "max"):
+        ch = free_chain(m, STOCH, init=init)
+        get = lambda: ch.H.copy()
+
+        def put(s):
+            ch.H[:] = s
+
+        seen = bfs(ch, get, put, lambda: ch.export().astype(np.int64).tobytes())
+        assert set(seen) == keys
+    # on the square the fixed west and east sides force the free top edge
+    # (N steps from N down to 0): the configurations are the domain-wall ones
+    if hw[0] == hw[1]:
+        assert {c.tobytes() for c in enumerate_configs(m)} == keys
+
+
+def test_free_table_is_the_configuration_weight_ratio():
+    # every flip at a free point of every configuration changes the weight by
+    # the table entry of its context
+    m = ones(3, 5)
+    wts = (2, 1, Fraction(3, 10), Fraction(7, 10), Fraction(1, 2), 3)
+    R = oracle.sixv_free_ratios6(*wts)
+    free = oracle.sixv_free_points(m)
+    checked = 0
+    for H in enumerate_configs(m, free_north=True):
+        for J, I in np.argwhere(free):
+            e, w_, s = H[J, I + 1], H[J, I - 1], H[J - 1, I]
+            if not (e == w_ == s) or H[J, I] != e - 1:
+                continue
+            ctx = (1 if H[J - 1, I - 1] == e + 1 else 0) | (2 if H[J - 1, I + 1] == e + 1 else 0)
+            up = H.copy()
+            up[J, I] = e + 1
+            assert weight6(m, up, wts) / weight6(m, H, wts) == R[ctx]
+            checked += 1
+    assert checked > 20
+
+
+@pytest.mark.parametrize("wts", [STOCH, (1, 2, 1, Fraction(1, 2), 3, 1)])
+def test_free_north_law(wts):
+    m = ones(3, 4)
+    configs = enumerate_configs(m, free_north=True)
+    w = {c.astype(np.int64).tobytes(): float(weight6(m, c, wts)) for c in configs}
+    Z = sum(w.values())
+    probs = {k: v / Z for k, v in w.items()}
+    ch = free_chain(m, wts, seed=41)
+
+    class View:
+        def sweep(self, n):
+            ch.sweep(n)
+
+        def export(self):
+            return ch.export().astype(np.int64)
+
+    assert chi_square_pvalue(View(), probs, 12000, 3) > 1e-3
+
+
+def test_free_north_law_needs_the_free_table():
+    # negative control: flipping free points with the interior table's
+    # product form (a2 = a1 a2, ...) gives another law
+    m = ones(3, 4)
+    wts = STOCH
+    configs = enumerate_configs(m, free_north=True)
+    w = {c.astype(np.int64).tobytes(): float(weight6(m, c, wts)) for c in configs}
+    Z = sum(w.values())
+    probs = {k: v / Z for k, v in w.items()}
+    thr = oracle.table_from_ratios(oracle.sixv_ratios6(*wts), False)
+    wrong = oracle.table_from_ratios(oracle.sixv_free_ratios6(1, 1, Fraction(21, 100), 1, Fraction(21, 100), 1),
+                                     False)
+    ch = oracle.SixVertexRegionOracle(m, thr, seed=41, free_north=True, thr_free=wrong)
+
+    class View:
+        def sweep(self, n):
+            ch.sweep(n)
+
+        def export(self):
+            return ch.export().astype(np.int64)
+
+    assert chi_square_pvalue(View(), probs, 12000, 3) < 1e-6
+
+
+def test_free_north_refuses_split_boundaries():
+    # an L-shape's free north edges cut its fixed boundary in two
+    with pytest.raises(ValueError):
+        oracle.sixv_extremal_heights(l_shape(6, 3, 3), free_north=True)
