@@ -116,7 +116,19 @@ typedef struct {
     int32_t init;    /* tl_init */
     int32_t w, h;    /* TL_MASK: box of the mask, in faces */
     const uint8_t *mask; /* TL_MASK: h rows of w bytes, nonzero = face in the domain */
+    uint32_t flags;  /* TL_FREE_NORTH (six-vertex masks only), else 0 */
 } tl_domain;
+
+/* Free boundary (Section 1.2: boundary faces need variations of the c-flip).
+ * TL_FREE_NORTH leaves the legs through the north sides of the cells of a
+ * six-vertex mask free instead of empty: the boundary points all of whose
+ * boundary edges are such sides move too, flipping when their west, east and
+ * south neighbours share a height m (no north neighbour).  Such a flip changes
+ * only the two cells below the point, so it has its own table over the
+ * context (SW at m+1) + 2 (SE at m+1), built from all six weights (weight kinds
+ * TL_W_UNIFORM and TL_W_SIXVERTEX6 only); the rest of the boundary keeps the
+ * domain-wall type legs and must be one piece (TL_EINVAL otherwise). */
+#define TL_FREE_NORTH 1u
 
 /* Weights (Section 1.1.1 edge and volume weights; Section 1.2 vertex weights).
  * Two-periodic: a crossed edge weighs a when its even endpoint (x+y even in
@@ -338,7 +350,9 @@ tl_status tl_server_destroy(tl_server *sv);
  * only, no device work): heat-bath tables have one entry per context, lazy
  * Metropolis tables two ([ctx*2 + current state is up]).  Contexts: domino
  * 2c + (x mod 2); lozenge 0; six-vertex the mask of high diagonal faces
- * NE=1, NW=2, SW=4, SE=8.  Writes up to cap entries, the count in *count. */
+ * NE=1, NW=2, SW=4, SE=8, followed, for a TL_FREE_NORTH domain, by the table of
+ * its free points (context (SW high) + 2 (SE high)).  Writes up to cap
+ * entries, the count in *count. */
 tl_status tl_thresholds(const tl_domain *dom, const tl_weights *w, uint32_t *out, uint32_t cap, uint32_t *count);
 
 /* Extremal states of a TL_MASK domain on the host (no device work), as

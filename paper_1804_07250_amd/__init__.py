@@ -39,7 +39,7 @@ class tl_domain(ctypes.Structure):
     _fields_ = [("model", ctypes.c_int32), ("shape", ctypes.c_int32), ("n", ctypes.c_int32),
                 ("a", ctypes.c_int32), ("b", ctypes.c_int32), ("c", ctypes.c_int32),
                 ("init", ctypes.c_int32), ("w", ctypes.c_int32), ("h", ctypes.c_int32),
-                ("mask", ctypes.POINTER(ctypes.c_uint8))]
+                ("mask", ctypes.POINTER(ctypes.c_uint8)), ("flags", ctypes.c_uint32)]
 
 
 class tl_weights(ctypes.Structure):
@@ -114,7 +114,10 @@ def _check(st):
         raise TlError(st, lib().tl_last_error().decode())
 
 
-def domain(model, n=0, a=0, b=0, c=0, init=TL_INIT_MIN, mask=None):
+TL_FREE_NORTH = 1
+
+
+def domain(model, n=0, a=0, b=0, c=0, init=TL_INIT_MIN, mask=None, free_north=False):
     """A domain; mask (2-D array, row 0 southmost, nonzero = face inside)
     selects the TL_MASK shape (dominoes).  The returned struct keeps the
     mask's bytes alive; the library copies them when a sampler is created."""
@@ -123,7 +126,7 @@ def domain(model, n=0, a=0, b=0, c=0, init=TL_INIT_MIN, mask=None):
         if m.ndim != (3 if model == TL_LOZENGE else 2) or (model == TL_LOZENGE and m.shape[2] != 2):
             raise ValueError("mask must be (h, w) cells, or (h, w, 2) triangles for lozenges")
         d = tl_domain(model, TL_MASK, 0, 0, 0, 0, init, m.shape[1], m.shape[0],
-                      m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+                      m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), TL_FREE_NORTH if free_north else 0)
         d._mask = m
         return d
     shape = {TL_DOMINO: TL_AZTEC, TL_LOZENGE: TL_HEXAGON, TL_SIXVERTEX: TL_DWBC_SQUARE}[model]

@@ -79,6 +79,7 @@ struct tl_sampler {
     uint64_t t = 0;
     uint64_t samples = 0;
     std::vector<uint32_t> thr;
+    std::vector<uint32_t> thr_free;    // six-vertex free north edges
     std::unique_ptr<tl::Model> model;
     unsigned long long *bin_sum = nullptr;  // device accumulators
     unsigned long long *bin_tmp = nullptr;
@@ -171,6 +172,39 @@ tl_status make_thresholds(const tl_domain &d, const tl_weights &w, std::vector<u
     return TL_OK;
 }
 
+// Table of the free north-edge points of a six-vertex domain (empty for any
+// other domain).  Such a flip changes only the two cells below the point: with
+// its west, east and south neighbours at m, the left cell (corners SW, S, W and
+// the point) goes from type c1 (SW at m-1) or a1 (SW at m+1) to a2 or c2, the
+// right one (S, SE, the point, E) from c2 (SE at m-1) or b2 (SE at m+1) to b1
+// or c1, so W_up / W_down = (SW high ? c2/a1 : a2/c1) (SE high ? c1/b2 : b1/c2)
+// over the context (SW high) + 2 (SE high).
+tl_status make_free_thresholds(const tl_domain &d, const tl_weights &w, std::vector<uint32_t> &out)
+{
+    out.clear();
+    if (d.model != TL_SIXVERTEX || d.shape != TL_MASK || !(d.flags & TL_FREE_NORTH)) return TL_OK;
+    long double a1 = 1, a2 = 1, b1 = 1, b2 = 1, c1 = 1, c2 = 1;
+    if (w.kind == TL_W_SIXVERTEX6) {
+        for (int i = 0; i < 6; ++i)
+            if (!finite_pos(w.w[i])) return fail(TL_EINVAL, "six-vertex weights must be > 0");
+        a1 = w.w[0];
+        a2 = w.w[1];
+        b1 = w.w[2];
+        b2 = w.w[3];
+        c1 = w.w[4];
+        c2 = w.w[5];
+    } else if (w.kind != TL_W_UNIFORM) {
+        return fail(TL_EINVAL, "free north edges need uniform weights or the six vertex weights");
+    }
+    std::vector<long double> R;
+    for (int ctx = 0; ctx < 4; ++ctx) {
+        const bool sw = ctx & 1, se = ctx & 2;
+        R.push_back((sw ? c2 / a1 : a2 / c1) * (se ? c1 / b2 : b1 / c2));
+    }
+    out = tl::thresholds_from_ratios(R, w.rule == TL_METROPOLIS);
+    return TL_OK;
+}
+
 tl::Thr table_of(const tl_sampler *s)
 {
     tl::Thr T{};
@@ -233,7 +267,8 @@ tl_status tl_domain_extremes(const tl_domain *dom, void *tmax, void *tmin, size_
         tl::HeightRegion r;
         std::string why;
         const tl::RegionStatus st = dom->model == TL_SIXVERTEX
-                                        ? tl::build_sixv_region(dom->mask, dom->w, dom->h, r, why)
+                                        ? tl::build_sixv_region(dom->mask, dom->w, dom->h,
+                                                                (dom->flags & TL_FREE_NORTH) != 0, r, why)
                                         : tl::build_loz_region(dom->mask, dom->w, dom->h, r, why);
         if (st != tl::kRegionOk)
             return fail(st == tl::kRegionUntileable ? TL_EUNTILEABLE : TL_EINVAL, "%s", why.c_str());
@@ -258,9 +293,11 @@ tl_status tl_domain_extremes(const tl_domain *dom, void *tmax, void *tmin, size_
 tl_status tl_thresholds(const tl_domain *dom, const tl_weights *w, uint32_t *out, uint32_t cap, uint32_t *count)
 {
     if (!dom || !w) return fail(TL_EINVAL, "null argument");
-    std::vector<uint32_t> thr;
+    std::vector<uint32_t> thr, thr_free;
     tl_status st = make_thresholds(*dom, *w, thr);
+    if (st == TL_OK) st = make_free_thresholds(*dom, *w, thr_free);
     if (st != TL_OK) return st;
+    thr.insert(thr.end(), thr_free.begin(), thr_free.end());
     if (count) *count = (uint32_t)thr.size();
     if (out)
         for (uint32_t i = 0; i < cap && i < thr.size(); ++i) out[i] = thr[i];
@@ -281,6 +318,7 @@ tl_status tl_sampler_create(const tl_domain *dom, const tl_weights *w, uint64_t 
     if (dom->init != TL_INIT_MIN && dom->init != TL_INIT_MAX) return fail(TL_EINVAL, "unknown init %d", dom->init);
     if (s->opt.colour_order > 1) return fail(TL_EINVAL, "unknown colour order %u", s->opt.colour_order);
     tl_status st = make_thresholds(*dom, *w, s->thr);
+    if (st == TL_OK) st = make_free_thresholds(*dom, *w, s->thr_free);
     if (st != TL_OK) return st;
     std::string why;
     tl_status mst = TL_EINVAL;
@@ -288,6 +326,7 @@ tl_status tl_sampler_create(const tl_domain *dom, const tl_weights *w, uint64_t 
     if (!s->model) return fail(mst, "%s", why.c_str());
     s->dom.mask = nullptr;   // the model keeps its own copy of a mask
     s->model->order = s->opt.colour_order;
+    s->model->set_boundary_table(s->thr_free);
     if (s->opt.stream) {
         s->stream = (hipStream_t)s->opt.stream;
     } else {
@@ -495,6 +534,12 @@ tl_status tl_sampler_cftp(tl_sampler *s, uint32_t max_log2, tl_cftp_info *out)
                 if (!(m >> k & 1u) && s->thr[m] > s->thr[m | (1u << k)])
                     return fail(TL_EINVAL, "coupling from the past needs weights that keep the height order "
                                            "(a <= c and b <= c)");
+        // free north-edge points: raising SW or SE must not lower the up threshold
+        for (uint32_t m = 0; m < 4 && !s->thr_free.empty(); ++m)
+            for (uint32_t k = 0; k < 2; ++k)
+                if (!(m >> k & 1u) && s->thr_free[m] > s->thr_free[m | (1u << k)])
+                    return fail(TL_EINVAL, "coupling from the past needs free-edge weights that keep the "
+                                           "height order");
     }
     std::unique_ptr<tl::Model> top = s->model->twin();
     hipError_t e = top->allocate();
@@ -627,9 +672,11 @@ tl_status tl_sampler_info(const tl_sampler *s, uint64_t *sites, uint32_t *colour
 tl_status tl_sampler_thresholds(const tl_sampler *s, uint32_t *out, uint32_t cap, uint32_t *count)
 {
     if (!s) return fail(TL_EINVAL, "null sampler");
-    if (count) *count = (uint32_t)s->thr.size();
+    std::vector<uint32_t> all = s->thr;
+    all.insert(all.end(), s->thr_free.begin(), s->thr_free.end());
+    if (count) *count = (uint32_t)all.size();
     if (out)
-        for (uint32_t i = 0; i < cap && i < s->thr.size(); ++i) out[i] = s->thr[i];
+        for (uint32_t i = 0; i < cap && i < all.size(); ++i) out[i] = all[i];
     return TL_OK;
 }
 

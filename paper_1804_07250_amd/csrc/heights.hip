@@ -81,9 +81,10 @@ static_assert(kKindClass == kTableClass && kKindSum == kTableSum, "table layouts
 
 struct Geo {
     int model, a, b, c, N;
-    const uint32_t *site;   // six-vertex site planes of a masked domain (layout sPS, sRS), or nullptr
+    const uint32_t *site;   // site planes of a masked domain (layout sPS, sRS), or nullptr
     size_t sPS;
     uint32_t sRS;
+    const uint32_t *freep;  // six-vertex: planes of the free north-edge points (same layout), or nullptr
 };
 
 __device__ __forceinline__ int imax(int p, int q) { return p > q ? p : q; }
@@ -149,6 +150,39 @@ __device__ __forceinline__ void loz_decide(uint32_t k0, uint32_t k1, uint32_t g,
             cm[1][w] = cur[w];
         }
         decide128<2, 2>(k0, k1, g, r, t, c, T, cm, live, D);
+    }
+}
+
+// Points of a free north edge (no north neighbour): table Tall.v[kFreeBase ..]
+// over the context (SW at m+1) + 2 (SE at m+1) [x2: current state up].
+template <int MODE>
+__device__ __forceinline__ void sixv_free_decide(uint32_t k0, uint32_t k1, uint32_t g, uint32_t r, uint32_t t,
+                                                 uint32_t c, const Thr &Tall, const uint32_t (&R0)[4],
+                                                 const uint32_t (&hSW)[4], const uint32_t (&hSE)[4],
+                                                 const uint32_t (&cur)[4], const uint32_t (&live)[4],
+                                                 uint32_t (&D)[4])
+{
+    if constexpr (MODE == kUniform) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w) D[w] = ~R0[w];
+    } else {
+        constexpr int NC = MODE == kMetropolis ? 8 : 4;
+        uint32_t T[NC], cm[NC][4];
+#pragma unroll
+        for (int i = 0; i < NC; ++i) T[i] = Tall.v[Thr::kFreeBase + i];
+#pragma unroll
+        for (int w = 0; w < 4; ++w)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t m = ((q & 1) ? hSW[w] : ~hSW[w]) & ((q & 2) ? hSE[w] : ~hSE[w]);
+                if (MODE == kMetropolis) {
+                    cm[2 * q][w] = m & ~cur[w];
+                    cm[2 * q + 1][w] = m & cur[w];
+                } else {
+                    cm[q][w] = m;
+                }
+            }
+        decide128<NC>(k0, k1, g, r, t, c, T, cm, live, D);
     }
 }
 
@@ -289,15 +323,19 @@ __device__ __forceinline__ void sixv_group(uint32_t *base, size_t ps, uint32_t r
     }
     // interior faces 1 <= I <= N-1 (and, in a masked domain, its sites)
     const int klo = p == 0 ? 1 : 0, khi = (geo.N - 1 - (int)p) >> 1;
-    uint32_t sm[4] = {~0u, ~0u, ~0u, ~0u};
-    if constexpr (MASKED) hld4(geo.site + p * geo.sPS + (size_t)J * geo.sRS + 4u + 4u * g, sm);
+    uint32_t sm[4] = {~0u, ~0u, ~0u, ~0u}, fm[4] = {0u, 0u, 0u, 0u};
+    if constexpr (MASKED) {
+        hld4(geo.site + p * geo.sPS + (size_t)J * geo.sRS + 4u + 4u * g, sm);
+        // points of a free north edge ignore their (absent) north neighbour
+        if (geo.freep) hld4(geo.freep + p * geo.sPS + (size_t)J * geo.sRS + 4u + 4u * g, fm);
+    }
     const bool podd = ((p + (uint32_t)J) & 1u) != 0u;   // parity of I + J
     uint32_t live[4], up[4], hNE[4], hNW[4], hSW[4], hSE[4], cur[4];
     uint32_t any = 0u;
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
         const uint32_t m = range_mask((int)(4 * g) + w, klo, khi) & sm[w];
-        live[w] = ~(E[w] ^ W[w]) & ~(E[w] ^ Nn[w]) & ~(E[w] ^ Sn[w]) & m;
+        live[w] = ~(E[w] ^ W[w]) & (~(E[w] ^ Nn[w]) | fm[w]) & ~(E[w] ^ Sn[w]) & m;
         up[w] = podd ? E[w] : ~E[w];      // residual bit of m+1
         hNE[w] = ~(NE[w] ^ up[w]);
         hNW[w] = ~(NW[w] ^ up[w]);
@@ -308,7 +346,24 @@ __device__ __forceinline__ void sixv_group(uint32_t *base, size_t ps, uint32_t r
     }
     if (!any) return;
     uint32_t D[4];
-    sixv_decide<MODE, KIND>(k0, k1, g, (uint32_t)J, t, colour, Tall, R0, hNE, hNW, hSW, hSE, cur, live, D);
+    if constexpr (MASKED) {
+        uint32_t li[4], lf[4], anyf = 0u;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            li[w] = live[w] & ~fm[w];
+            lf[w] = live[w] & fm[w];
+            anyf |= lf[w];
+        }
+        sixv_decide<MODE, KIND>(k0, k1, g, (uint32_t)J, t, colour, Tall, R0, hNE, hNW, hSW, hSE, cur, li, D);
+        if (anyf) {
+            uint32_t Df[4];
+            sixv_free_decide<MODE>(k0, k1, g, (uint32_t)J, t, colour, Tall, R0, hSW, hSE, cur, lf, Df);
+#pragma unroll
+            for (int w = 0; w < 4; ++w) D[w] = (D[w] & ~fm[w]) | (Df[w] & fm[w]);
+        }
+    } else {
+        sixv_decide<MODE, KIND>(k0, k1, g, (uint32_t)J, t, colour, Tall, R0, hNE, hNW, hSW, hSE, cur, live, D);
+    }
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
         const uint32_t nw = ~(D[w] ^ up[w]);
@@ -442,7 +497,7 @@ __global__ void __launch_bounds__(kHeightThreads) height_tiled_kernel(const uint
 template <int MODE, int KIND, bool RANDOM, bool MASKED>
 __device__ __forceinline__ void height_item(uint32_t *lds, const TileJob &j, uint32_t tile)
 {
-    const Geo geo{j.model, j.a, j.b, j.c, j.N, j.site, j.PS, j.RS};
+    const Geo geo{j.model, j.a, j.b, j.c, j.N, j.site, j.PS, j.RS, j.freep};
     height_tile<MODE, KIND, RANDOM, MASKED>(lds, j.in, j.out, j.PS, j.RS, j.ng, j.rows, j.P, geo, j.t0, j.S, j.TR,
                                             j.TG, j.HR,
                                     j.HG, tile / j.tiles_x, tile % j.tiles_x, j.T, j.key0, j.key1);
@@ -668,7 +723,7 @@ __global__ void __launch_bounds__(64) loz_observe_kernel(const uint32_t *pl, siz
         if (rowbin[i]) atomicAdd(&bins[row + i], rowbin[i]);
 }
 
-Geo geo_of(const HeightDev &d) { return Geo{d.model, d.a, d.b, d.c, d.N, d.site, d.PS, d.RS}; }
+Geo geo_of(const HeightDev &d) { return Geo{d.model, d.a, d.b, d.c, d.N, d.site, d.PS, d.RS, d.freep}; }
 
 }  // namespace
 
@@ -800,6 +855,7 @@ TileJob height_tile_job(const HeightDev &d, const TilePlan &p, uint32_t t0, cons
     j.mode = T.uniform() ? kModeUniform : (metropolis ? kModeMetropolis : kModeHeatBath);
     j.kind = T.uniform() ? (uint32_t)kTableClass : table_kind(T);
     j.site = d.site;
+    j.freep = d.freep;
     j.key0 = (uint32_t)seed;
     j.key1 = (uint32_t)(seed >> 32);
     j.T = T;

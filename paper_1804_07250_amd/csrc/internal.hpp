@@ -15,11 +15,16 @@ namespace tl {
 struct Thr {
     uint32_t v[32];
     uint32_t count;
+    // six-vertex free north edges: nfree entries at v[kFreeBase ..]
+    uint32_t nfree;
+    static constexpr uint32_t kFreeBase = 24;
     // every threshold is 2^31: one random bit per site decides
     bool uniform() const
     {
         for (uint32_t i = 0; i < count; ++i)
             if (v[i] != 0x80000000u) return false;
+        for (uint32_t i = 0; i < nfree; ++i)
+            if (v[kFreeBase + i] != 0x80000000u) return false;
         return count > 0;
     }
 };
@@ -178,8 +183,10 @@ struct HeightDev {
     size_t PS = 0;
     uint32_t *planes = nullptr, *spare = nullptr;
     // six-vertex domain given by a mask: bit planes (same layout as the state)
-    // of the points that may flip; nullptr for the domain-wall square
+    // of the points that may flip, and of those on free north edges (or
+    // nullptr); nullptr for the domain-wall square
     const uint32_t *site = nullptr;
+    const uint32_t *freep = nullptr;
 };
 struct HeightTile {
     uint32_t TR = 32, TG = 4, S = 8;
@@ -247,6 +254,7 @@ struct TileJob {
     uint32_t order;                     // colour order: 0 fixed, 1 random per step
     uint32_t key0, key1;
     const uint32_t *site;               // six-vertex site planes of a masked domain, or nullptr
+    const uint32_t *freep;              // planes of its free north-edge points, or nullptr
     Thr T;                              // kernel table (heights: weight classes)
 };
 struct TileItem {

@@ -239,7 +239,9 @@ public:
             d_.b = region_->h;
             d_.c = 0;
         } else {
-            d_.N = std::max(region_->w, region_->h);
+            // free north-edge points may sit on the domain's top row: keep a row
+            // above it in the box so that they are inner rows of the state
+            d_.N = std::max(region_->w, region_->h + (region_->free_sites ? 1 : 0));
         }
         height_words(d_);
     }
@@ -247,6 +249,7 @@ public:
     {
         std::unique_ptr<Model> m(region_ ? new HeightModel(region_) : new HeightModel(dom_));
         m->order = order;
+        m->set_boundary_table(free_thr_);
         return m;
     }
     bool loz() const { return d_.model == TL_LOZENGE; }
@@ -265,10 +268,16 @@ public:
         if (e == hipSuccess) e = hipMalloc(&heights_, V * sizeof(int32_t));
         if (e == hipSuccess) e = hipMalloc(&hmin_, V * sizeof(int32_t));
         if (e == hipSuccess) e = hipMalloc(&cells_, C);
+        if (e == hipSuccess && region_->free_sites) e = hipMalloc(&freep_, words * sizeof(uint32_t));
         if (e != hipSuccess) return e;
         std::vector<uint32_t> planes;
         pack_points(region_->site, planes, [](int32_t v) { return v != 0; });
         e = hipMemcpy(site_, planes.data(), planes.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+        if (e == hipSuccess && freep_) {
+            pack_points(region_->site, planes, [](int32_t v) { return v == 2; });
+            e = hipMemcpy(freep_, planes.data(), planes.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+            d_.freep = freep_;
+        }
         if (e == hipSuccess) e = hipMemcpy(anchor_, region_->anchor.data(), V * sizeof(int32_t), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(hmin_, region_->hmin.data(), V * sizeof(int32_t), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(cells_, region_->cells.data(), C, hipMemcpyHostToDevice);
@@ -280,9 +289,11 @@ public:
         if (owned_ && d_.planes) (void)hipFree(d_.planes);
         if (owned_ && d_.spare) (void)hipFree(d_.spare);
         d_.planes = d_.spare = nullptr;
-        for (void *p : {(void *)site_, (void *)anchor_, (void *)heights_, (void *)hmin_, (void *)cells_})
+        for (void *p : {(void *)site_, (void *)anchor_, (void *)heights_, (void *)hmin_, (void *)cells_,
+                        (void *)freep_})
             if (p) (void)hipFree(p);
-        site_ = nullptr;
+        site_ = freep_ = nullptr;
+        d_.freep = nullptr;
         anchor_ = heights_ = hmin_ = nullptr;
         cells_ = nullptr;
         d_.site = nullptr;
@@ -360,7 +371,17 @@ public:
     // SW = sA>=2, NW = sB>=1, SE = sB>=2.  When the thresholds depend on
     // sA + sB only (a = b), a heat-bath table has one entry per sum s = 0..4
     // instead, and the kernels use those 5 classes.
+    // Kernel table: the interior classes (below), and for a domain with free
+    // north edges their table at v[kFreeBase ..].
     Thr kernel_table(const Thr &T, bool metro) const
+    {
+        Thr K = interior_table(T, metro);
+        K.nfree = (uint32_t)free_thr_.size();
+        for (uint32_t i = 0; i < K.nfree; ++i) K.v[Thr::kFreeBase + i] = free_thr_[i];
+        return K;
+    }
+    void set_boundary_table(const std::vector<uint32_t> &t) override { free_thr_ = t; }
+    Thr interior_table(const Thr &T, bool metro) const
     {
         if (loz()) return T;
         auto mask_of = [](int i, int j) {
@@ -505,7 +526,9 @@ public:
                     vals[v] = x;
                     continue;
                 }
-                const int32_t nb[4] = {H[v - 1], H[v + 1], H[v - PW], H[v + PW]};
+                // a point of a free north edge has no north neighbour
+                const bool fr = region_->site[v] == 2;
+                const int32_t nb[4] = {H[v - 1], H[v + 1], H[v - PW], fr ? H[v - 1] : H[v + PW]};
                 for (int32_t y : nb)
                     if (y == INT32_MIN || (x > y ? x - y : y - x) != 1) {
                         why = "ice rule violated";
@@ -602,8 +625,9 @@ private:
     HeightDev d_;
     bool owned_ = false;
     std::shared_ptr<const HeightRegion> region_;
-    uint32_t *site_ = nullptr;
+    uint32_t *site_ = nullptr, *freep_ = nullptr;
     int32_t *anchor_ = nullptr, *heights_ = nullptr, *hmin_ = nullptr;
+    std::vector<uint32_t> free_thr_;
     uint8_t *cells_ = nullptr;
     std::vector<uint32_t> packed_max_, packed_min_;
 };
@@ -613,9 +637,13 @@ private:
 std::unique_ptr<Model> make_model(const tl_domain &d, std::string &why, tl_status *status)
 {
     if (status) *status = TL_EINVAL;
+    if (d.shape == TL_MASK && d.flags && (d.model != TL_SIXVERTEX || d.flags != TL_FREE_NORTH)) {
+        why = "free north edges are a six-vertex option";
+        return nullptr;
+    }
     if (d.model == TL_SIXVERTEX && d.shape == TL_MASK) {
         auto r = std::make_shared<HeightRegion>();
-        const RegionStatus st = build_sixv_region(d.mask, d.w, d.h, *r, why);
+        const RegionStatus st = build_sixv_region(d.mask, d.w, d.h, (d.flags & TL_FREE_NORTH) != 0, *r, why);
         if (st != kRegionOk) {
             if (status && st == kRegionUntileable) *status = TL_EUNTILEABLE;
             return nullptr;

@@ -15,6 +15,8 @@ public:
     virtual ~Model() {}
     // A fresh model of the same domain (nothing allocated).
     virtual std::unique_ptr<Model> twin() const = 0;
+    // Threshold table of the free north-edge points of a six-vertex domain.
+    virtual void set_boundary_table(const std::vector<uint32_t> &) {}
     virtual hipError_t allocate() = 0;
     virtual void release() = 0;
     virtual hipError_t init(bool init_max, hipStream_t s) = 0;

@@ -261,7 +261,8 @@ RegionStatus build_region(const uint8_t *mask, int w, int h, Region &r, std::str
 // largest is min_b h(b) + dist(b, v), the smallest max_b h(b) - dist(b, v)
 // (unit lengths, a bucket queue from all boundary points at once), and one
 // exists iff both meet the boundary heights.
-RegionStatus build_sixv_region(const uint8_t *mask, int w, int h, HeightRegion &r, std::string &why)
+RegionStatus build_sixv_region(const uint8_t *mask, int w, int h, bool free_north, HeightRegion &r,
+                               std::string &why)
 {
     uint64_t ncells = 0;
     const RegionStatus vs = validate_mask(mask, w, h, r.cells, ncells, why);
@@ -271,6 +272,7 @@ RegionStatus build_sixv_region(const uint8_t *mask, int w, int h, HeightRegion &
     r.h = h;
     r.cw = w;
     r.ch = h;
+    r.free_sites = 0;
     const int PW = w + 1;
     const size_t V = (size_t)PW * (h + 1);
     auto in = [&](int x, int y) { return x >= 0 && y >= 0 && x < w && y < h && r.cells[(size_t)y * w + x] != 0; };
@@ -309,6 +311,7 @@ RegionStatus build_sixv_region(const uint8_t *mask, int w, int h, HeightRegion &
             for (const Edge &e : kE) {
                 const bool a = in(I + e.ax, J + e.ay), b = in(I + e.bx, J + e.by);
                 if (a == b) continue;   // interior side, or no side of the domain
+                if (free_north && e.dJ == 0 && b) continue;   // the north side of a cell: a free leg
                 const size_t u = (size_t)(J + e.dJ) * PW + I + e.dI;
                 const int32_t hu = hb[v] + e.sign * (a ? 1 : -1);
                 if (hb[u] == kUnset) {
@@ -321,11 +324,25 @@ RegionStatus build_sixv_region(const uint8_t *mask, int w, int h, HeightRegion &
             }
         }
     }
-    for (size_t v = 0; v < V; ++v)
-        if (pt[v] && !r.site[v] && hb[v] == kUnset) {
-            why = "boundary not connected";
+    // boundary points the walk did not reach: free (code 2) when every boundary
+    // edge at them is the north side of a cell, otherwise the fixed boundary is
+    // in pieces
+    for (size_t v = 0; v < V; ++v) {
+        if (!pt[v] || r.site[v] || hb[v] != kUnset) continue;
+        const int I = (int)(v % PW), J = (int)(v / PW);
+        bool all_free = free_north;
+        for (const Edge &e : kE) {
+            const bool a = in(I + e.ax, J + e.ay), b = in(I + e.bx, J + e.by);
+            if (a != b && !(e.dJ == 0 && b)) all_free = false;
+        }
+        if (!all_free) {
+            why = free_north ? "free edges split the fixed boundary" : "boundary not connected";
             return kRegionInvalid;
         }
+        r.site[v] = 2;
+        r.sites += 1;
+        r.free_sites += 1;
+    }
     auto bound = [&](int sign) {
         std::vector<int32_t> dist(V, kUnset);
         int32_t kmin = INT32_MAX;

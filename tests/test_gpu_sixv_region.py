@@ -184,3 +184,103 @@ def test_large_l_shape_one_sweep_sampled():
     o.sweep(1)
     assert (s.export() == o.export()).all()
     assert (mid != start).any()
+
+
+# ------------------------------------------------------------ free north edge
+
+STOCH = (1.0, 1.0, 0.25, 0.75, 0.25, 0.75)
+
+
+def free_pair(tl, m, wts, seed, metro=False, init="min", **kw):
+    w = tl.weights(tl.TL_W_SIXVERTEX6, *wts)
+    w.rule = tl.TL_METROPOLIS if metro else tl.TL_HEATBATH
+    dom = tl.domain(tl.TL_SIXVERTEX, mask=m, free_north=True,
+                    init=tl.TL_INIT_MAX if init == "max" else tl.TL_INIT_MIN)
+    s = tl.Sampler(dom, w, seed, tl.options(**kw))
+    fr = [Fraction(x) for x in wts]
+    thr = oracle.table_from_ratios(oracle.sixv_ratios6(*fr), metro)
+    thr_free = oracle.table_from_ratios(oracle.sixv_free_ratios6(*fr), metro)
+    o = oracle.SixVertexRegionOracle(m, thr, metropolis=metro, seed=seed, init=init, free_north=True,
+                                     thr_free=thr_free, random_colours=kw.get("colour_order", 0) == 1)
+    assert s.thresholds() == list(thr) + list(thr_free)
+    return s, o
+
+
+FREE = [((30, 50), STOCH, False, "min", {}), ((30, 50), STOCH, False, "max", {"kernel": 1}),
+        ((40, 64), (2.0, 1.0, 0.5, 1.5, 0.5, 3.0), True, "min", {"kernel": 2, "tile_rows": 8, "sweeps_per_launch": 3}),
+        ((130, 200), STOCH, False, "min", {}), ((20, 33), STOCH, False, "max", {"colour_order": 1})]
+
+
+@pytest.mark.parametrize("hw,wts,metro,init,opts", FREE, ids=["%s-%s-%s-%s-%s" % (c[0], c[1][2], c[2], c[3], c[4])
+                                                            for c in FREE])
+def test_free_north_parity(hw, wts, metro, init, opts):
+    tl = need_gpu()
+    say("six-vertex free north %s %s metro=%s init=%s %s" % (hw, wts, metro, init, opts))
+    m = ones(*hw)
+    s, o = free_pair(tl, m, wts, 29, metro, init, **opts)
+    assert (s.export() == o.export()).all()
+    for k in (1, 4, 12):
+        s.sweep(k)
+        o.sweep(k)
+        assert (s.export() == o.export()).all(), "after %d sweeps" % o.t
+    assert s.info() == (len(o.sites()), 4)
+
+
+def test_free_north_observables_and_import():
+    tl = need_gpu()
+    m = ones(24, 40)
+    s, o = free_pair(tl, m, STOCH, 3, obs_every=2, obs_bin=5)
+    fr = [Fraction(x) for x in STOCH]
+    o = oracle.SixVertexRegionOracle(m, oracle.table_from_ratios(oracle.sixv_ratios6(*fr), False), seed=3,
+                                     free_north=True, obs_every=2, bin_=5,
+                                     thr_free=oracle.table_from_ratios(oracle.sixv_free_ratios6(*fr), False))
+    s.sweep(10)
+    o.sweep(10)
+    obs = s.observables()
+    assert (obs["bin_sum"].reshape(-1) == o.bin_sum).all() and obs["samples"] == int(o.samples[0]) == 5
+    mid = o.export()
+    s.import_(mid, 10)
+    s.sweep(5)
+    o.sweep(5)
+    assert (s.export() == o.export()).all()
+    free = oracle.sixv_free_points(m)
+    J, I = np.argwhere(free)[3]
+    bad = mid.copy()
+    bad[J, I] += 2
+    with pytest.raises(tl.TlError):
+        s.import_(bad, 0)
+
+
+def test_free_north_cftp():
+    tl = need_gpu()
+    m = ones(10, 16)
+    uni = (1.0,) * 6
+    for seed in (1, 2):
+        s, _ = free_pair(tl, m, uni, seed)
+        info = s.cftp(24)
+        fr = [Fraction(1)] * 6
+        thr = oracle.table_from_ratios(oracle.sixv_ratios6(*fr), False)
+        thr_free = oracle.table_from_ratios(oracle.sixv_free_ratios6(*fr), False)
+        make = lambda init, sd=seed: oracle.SixVertexRegionOracle(m, thr, seed=sd, init=init, free_north=True,
+                                                                  thr_free=thr_free)
+        R, sample = oracle.cftp(make, max_log2=24)
+        assert info["log2_sweeps"] == R and (s.export() == sample).all()
+    # the stochastic weights do not keep the height order
+    s, _ = free_pair(tl, m, STOCH, 1)
+    with pytest.raises(tl.TlError) as e:
+        s.cftp(10)
+    assert e.value.status == tl.TL_EINVAL
+
+
+def test_free_north_large_one_sweep_sampled():
+    tl = need_gpu()
+    say("six-vertex free north 256 x 512, 300 sweeps + one-sweep parity")
+    m = ones(256, 512)
+    s, o = free_pair(tl, m, STOCH, 12)
+    s.sweep(300)
+    mid = s.export()
+    o.load(mid)
+    o.t = 300
+    s.sweep(1)
+    o.sweep(1)
+    assert (s.export() == o.export()).all()

@@ -184,3 +184,33 @@ def test_lozenge_mask_errors():
     assert e.value.status == tl.TL_EUNTILEABLE
     with pytest.raises(ValueError):
         tl.domain(tl.TL_LOZENGE, mask=np.ones((3, 3), dtype=bool))
+
+
+@pytest.mark.parametrize("hw", [(4, 6), (10, 17), (3, 3), (40, 90)])
+def test_sixvertex_free_north_matches_the_oracle(hw):
+    m = ones(*hw)
+    want = oracle.sixv_extremal_heights(m, free_north=True)
+    got = tl.domain_extremes(tl.domain(tl.TL_SIXVERTEX, mask=m, free_north=True))
+    assert (got[0] == want[0]).all() and (got[1] == want[1]).all()
+
+
+def test_free_north_thresholds_match_the_oracle():
+    from fractions import Fraction
+    m = ones(5, 7)
+    for wts in ((1, 1, 0.25, 0.75, 0.25, 0.75), (2, 1, 0.5, 1.5, 0.5, 3)):
+        for rule in (tl.TL_HEATBATH, tl.TL_METROPOLIS):
+            w = tl.weights(tl.TL_W_SIXVERTEX6, *wts, rule=rule)
+            metro = rule == tl.TL_METROPOLIS
+            want = list(oracle.table_from_ratios(oracle.sixv_ratios6(*map(Fraction, wts)), metro)) + \
+                list(oracle.table_from_ratios(oracle.sixv_free_ratios6(*map(Fraction, wts)), metro))
+            assert tl.thresholds(tl.domain(tl.TL_SIXVERTEX, mask=m, free_north=True), w) == want
+    # three-weight kinds carry only squares: refused with free edges
+    with pytest.raises(tl.TlError) as e:
+        tl.thresholds(tl.domain(tl.TL_SIXVERTEX, mask=m, free_north=True), tl.weights(tl.TL_W_SIXVERTEX, 1.0, 1.0, 2.0))
+    assert e.value.status == tl.TL_EINVAL
+
+
+def test_free_north_refusals():
+    with pytest.raises(tl.TlError) as e:      # free edges split the fixed boundary of an L-shape
+        tl.domain_extremes(tl.domain(tl.TL_SIXVERTEX, mask=l_shape(6, 3, 3), free_north=True))
+    assert e.value.status == tl.TL_EINVAL
