@@ -156,6 +156,10 @@ typedef struct {
     uint32_t kernel;             /* 0 = automatic, 1 = one launch per colour step, 2 = tiled multi-sweep */
     uint32_t tile_groups;        /* tile width in groups of 128 sites; 0 = automatic */
     uint32_t colour_order;       /* 0 = colours 0..K-1 in every sweep; 1 = random (see below) */
+    void *device_buf;            /* samplers: caller-owned device memory for the state (NULL = the
+                                  * library allocates it); at least tl_sampler_state_bytes bytes,
+                                  * 256-byte aligned, kept alive until tl_sampler_destroy */
+    size_t device_buf_bytes;
 } tl_options;
 
 /* Random colour order (Section 2.2, RandomWalk: the colour of every step is
@@ -165,6 +169,19 @@ typedef struct {
  * uniform defined above with t replaced by s).  K t must stay below 2^32.
  * Samplers only (plain sweeps and coupling from the past); batches and servers
  * run the fixed order. */
+
+/* Caller-owned state (device_buf).  A sampler created with device_buf set
+ * keeps its two bit-plane buffers (the state and the spare it is swapped with
+ * by the tiled kernel) in that memory instead of allocating them: buffer 0 at
+ * device_buf, buffer 1 tl_sampler_state_bytes / 2 bytes further (each
+ * buffer's size rounded up to a multiple of 256 bytes).  Which of the
+ * two holds the current state is internal; read it with tl_sampler_export.
+ * The library never frees device_buf; the caller keeps it alive, and touches
+ * it on no other stream, until tl_sampler_destroy returns.  Observable bins,
+ * masked-domain tables and the upper chain of coupling from the past are still
+ * allocated by the library.  Errors: TL_EINVAL if device_buf_bytes is below
+ * tl_sampler_state_bytes or device_buf is not 256-byte aligned; batches and
+ * servers refuse device_buf (they manage their own pools). */
 
 typedef struct tl_sampler tl_sampler;
 
@@ -191,6 +208,12 @@ typedef struct {
  * TL_EDEVICE. */
 tl_status tl_sampler_create(const tl_domain *dom, const tl_weights *w, uint64_t seed,
                             const tl_options *opt, tl_sampler **out);
+
+/* Device bytes of a sampler's state (its two bit-plane buffers, each rounded
+ * up to a multiple of 256 bytes) for this domain: the size opt->device_buf
+ * must have (host only, no device work; see "Caller-owned state" above).
+ * Errors: TL_EINVAL, TL_EUNTILEABLE. */
+tl_status tl_sampler_state_bytes(const tl_domain *dom, size_t *bytes);
 
 /* Enqueue n sweeps (sweeps t .. t+n-1) on the sampler's stream; returns without
  * waiting.  sweep(a); sweep(b) gives the same state as sweep(a+b). */

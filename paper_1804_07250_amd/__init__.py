@@ -49,7 +49,8 @@ class tl_weights(ctypes.Structure):
 class tl_options(ctypes.Structure):
     _fields_ = [("stream", ctypes.c_void_p), ("obs_every", ctypes.c_uint32), ("obs_bin", ctypes.c_uint32),
                 ("sweeps_per_launch", ctypes.c_uint32), ("tile_rows", ctypes.c_uint32),
-                ("kernel", ctypes.c_uint32), ("tile_groups", ctypes.c_uint32), ("colour_order", ctypes.c_uint32)]
+                ("kernel", ctypes.c_uint32), ("tile_groups", ctypes.c_uint32), ("colour_order", ctypes.c_uint32),
+                ("device_buf", ctypes.c_void_p), ("device_buf_bytes", ctypes.c_size_t)]
 
 
 class tl_observables(ctypes.Structure):
@@ -103,7 +104,7 @@ def lib():
                      "tl_sampler_export_size", "tl_sampler_export", "tl_sampler_hash", "tl_sampler_import",
                      "tl_sampler_destroy", "tl_sampler_info", "tl_sampler_thresholds", "tl_sampler_reset",
                      "tl_sampler_set_timing", "tl_sampler_kernel_time", "tl_sampler_cftp",
-                     "tl_domain_extremes"):
+                     "tl_domain_extremes", "tl_sampler_state_bytes"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -153,9 +154,19 @@ def weights(kind=TL_W_UNIFORM, *w, rule=TL_HEATBATH):
 
 
 def options(stream=None, obs_every=0, obs_bin=1, sweeps_per_launch=0, tile_rows=0, kernel=0, tile_groups=0,
-            colour_order=0):
-    """colour_order: 0 = colours 0..K-1 in every sweep, 1 = a random colour per step."""
-    return tl_options(stream, obs_every, obs_bin, sweeps_per_launch, tile_rows, kernel, tile_groups, colour_order)
+            colour_order=0, device_buf=None, device_buf_bytes=0):
+    """colour_order: 0 = colours 0..K-1 in every sweep, 1 = a random colour per step.
+    device_buf: caller-owned device memory (an address, e.g. a tensor's data_ptr())
+    holding the sampler's state, at least state_bytes(domain) bytes."""
+    return tl_options(stream, obs_every, obs_bin, sweeps_per_launch, tile_rows, kernel, tile_groups, colour_order,
+                      device_buf, device_buf_bytes)
+
+
+def state_bytes(dom):
+    """Device bytes of a sampler's state for this domain (host only)."""
+    n = ctypes.c_size_t()
+    _check(lib().tl_sampler_state_bytes(ctypes.byref(dom), ctypes.byref(n)))
+    return n.value
 
 
 def thresholds(dom: tl_domain, w: tl_weights):

@@ -304,6 +304,13 @@ tl_status tl_thresholds(const tl_domain *dom, const tl_weights *w, uint32_t *out
     return TL_OK;
 }
 
+// Bytes of one state buffer inside caller-owned memory, rounded up so that the
+// second buffer starts 256-byte aligned like a hipMalloc allocation.
+static size_t state_half_bytes(const tl::Model &m)
+{
+    return (m.state_words() * sizeof(uint32_t) + 255u) & ~(size_t)255u;
+}
+
 tl_status tl_sampler_create(const tl_domain *dom, const tl_weights *w, uint64_t seed, const tl_options *opt,
                             tl_sampler **out)
 {
@@ -333,8 +340,21 @@ tl_status tl_sampler_create(const tl_domain *dom, const tl_weights *w, uint64_t 
         TL_HIP(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
         s->own_stream = true;
     }
-    hipError_t e = s->model->allocate();
+    hipError_t e;
+    if (s->opt.device_buf) {
+        // the state in caller-owned memory: two buffers, each 256-byte aligned
+        const size_t half = state_half_bytes(*s->model), need = 2 * half;
+        if (s->opt.device_buf_bytes < need || ((uintptr_t)s->opt.device_buf & 255u)) {
+            if (s->own_stream) (void)hipStreamDestroy(s->stream);
+            return fail(TL_EINVAL, "device_buf must hold %zu bytes, 256-byte aligned", need);
+        }
+        char *buf = (char *)s->opt.device_buf;
+        e = s->model->allocate_into((uint32_t *)buf, (uint32_t *)(buf + half));
+    } else {
+        e = s->model->allocate();
+    }
     if (e != hipSuccess) {
+        s->model->release();
         if (s->own_stream) (void)hipStreamDestroy(s->stream);
         return fail(e == hipErrorOutOfMemory ? TL_ENOMEM : TL_EDEVICE, "state allocation: %s", hipGetErrorString(e));
     }
@@ -355,6 +375,17 @@ tl_status tl_sampler_create(const tl_domain *dom, const tl_weights *w, uint64_t 
     TL_HIP(hipMemsetAsync(s->bin_sum, 0, nb * sizeof(unsigned long long), s->stream));
     TL_HIP(s->model->init(dom->init == TL_INIT_MAX, s->stream));
     *out = s.release();
+    return TL_OK;
+}
+
+tl_status tl_sampler_state_bytes(const tl_domain *dom, size_t *bytes)
+{
+    if (!dom || !bytes) return fail(TL_EINVAL, "null argument");
+    std::string why;
+    tl_status mst = TL_EINVAL;
+    std::unique_ptr<tl::Model> m = tl::make_model(*dom, why, &mst);
+    if (!m) return fail(mst, "%s", why.c_str());
+    *bytes = 2 * state_half_bytes(*m);
     return TL_OK;
 }
 

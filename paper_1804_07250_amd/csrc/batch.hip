@@ -179,6 +179,7 @@ tl_status tl_batch_create(int32_t n, const tl_domain *doms, const tl_weights *w,
 {
     if (!doms || !w || !seeds || !out || n <= 0) return tl::fail(TL_EINVAL, "invalid batch arguments");
     if (opt && opt->colour_order) return tl::fail(TL_EINVAL, "batches run the fixed colour order");
+    if (opt && opt->device_buf) return tl::fail(TL_EINVAL, "batches allocate their own chain pool");
     *out = nullptr;
     std::unique_ptr<tl_batch> b(new (std::nothrow) tl_batch());
     if (!b) return tl::fail(TL_ENOMEM, "host allocation failed");

@@ -37,6 +37,11 @@ public:
         owned_ = true;
         return e;
     }
+    hipError_t allocate_into(uint32_t *state, uint32_t *spare) override
+    {
+        attach(state, spare);
+        return hipSuccess;
+    }
     void release() override
     {
         if (owned_ && d_.planes) (void)hipFree(d_.planes);
@@ -261,7 +266,20 @@ public:
         hipError_t e = hipMalloc(&d_.planes, words * sizeof(uint32_t));
         if (e == hipSuccess) e = hipMalloc(&d_.spare, words * sizeof(uint32_t));
         owned_ = true;
-        if (e != hipSuccess || !region_) return e;
+        if (e != hipSuccess) return e;
+        return allocate_region();
+    }
+    hipError_t allocate_into(uint32_t *state, uint32_t *spare) override
+    {
+        attach(state, spare);
+        return allocate_region();
+    }
+    // Device copies of a masked domain's site planes, anchors and cells.
+    hipError_t allocate_region()
+    {
+        if (!region_) return hipSuccess;
+        const size_t words = height_words(d_);
+        hipError_t e = hipSuccess;
         const size_t V = region_->anchor.size(), C = region_->cells.size();
         e = hipMalloc(&site_, words * sizeof(uint32_t));
         if (e == hipSuccess) e = hipMalloc(&anchor_, V * sizeof(int32_t));

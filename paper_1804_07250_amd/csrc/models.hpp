@@ -18,6 +18,9 @@ public:
     // Threshold table of the free north-edge points of a six-vertex domain.
     virtual void set_boundary_table(const std::vector<uint32_t> &) {}
     virtual hipError_t allocate() = 0;
+    // The same with the state in caller-owned buffers of state_words() words
+    // each (freed by the caller); other buffers are allocated as usual.
+    virtual hipError_t allocate_into(uint32_t *state, uint32_t *spare) = 0;
     virtual void release() = 0;
     virtual hipError_t init(bool init_max, hipStream_t s) = 0;
     // Sweeps t0 .. t0+n-1, every colour in order 0..K-1 within a sweep.

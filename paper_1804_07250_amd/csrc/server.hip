@@ -533,6 +533,7 @@ tl_status tl_server_create(size_t hbm_budget_bytes, int32_t max_slots, const tl_
 {
     if (!out || hbm_budget_bytes == 0 || max_slots <= 0) return tl::fail(TL_EINVAL, "invalid server arguments");
     if (opt && opt->colour_order) return tl::fail(TL_EINVAL, "servers run the fixed colour order");
+    if (opt && opt->device_buf) return tl::fail(TL_EINVAL, "servers allocate their own state pool");
     *out = nullptr;
     std::unique_ptr<tl_server> sv(new (std::nothrow) tl_server());
     if (!sv) return tl::fail(TL_ENOMEM, "host allocation failed");

@@ -70,3 +70,44 @@ def test_thresholds_equal_exact_tables(metro):
     ]
     for dom, w, ratios in cases:
         assert tl.thresholds(dom, w) == oracle.table_from_ratios(ratios, metro)
+
+
+def test_state_bytes_on_the_host():
+    """tl_sampler_state_bytes needs no device: two bit-plane buffers, each a
+    multiple of 256 bytes and at least one bit per site of the domain."""
+    import numpy as np
+    import paper_1804_07250_amd as tl
+    cases = [(tl.domain(tl.TL_DOMINO, n=64), 2 * 64 * 64 * 2 * 2),
+             (tl.domain(tl.TL_LOZENGE, a=50, b=40, c=30), 51 * 41),
+             (tl.domain(tl.TL_SIXVERTEX, n=128), 127 * 127),
+             (tl.domain(tl.TL_DOMINO, mask=np.ones((30, 50), dtype=bool)), 30 * 50 * 2),
+             (tl.domain(tl.TL_SIXVERTEX, mask=np.ones((20, 32), dtype=bool), free_north=True), 20 * 31)]
+    sizes = []
+    for dom, bits in cases:
+        n = tl.state_bytes(dom)
+        assert n % 512 == 0 and n // 2 >= bits // 8
+        sizes.append(n)
+    assert tl.state_bytes(tl.domain(tl.TL_DOMINO, n=128)) > sizes[0]
+    one = np.zeros((3, 3), dtype=bool)
+    one[1, 1] = True
+    with pytest.raises(tl.TlError) as e:
+        tl.state_bytes(tl.domain(tl.TL_DOMINO, mask=one))
+    assert e.value.status == tl.TL_EUNTILEABLE
+    with pytest.raises(tl.TlError) as e:
+        tl.state_bytes(tl.domain(tl.TL_DOMINO, n=0))
+    assert e.value.status == tl.TL_EINVAL
+    assert tl.lib().tl_sampler_state_bytes(None, None) == tl.TL_EINVAL
+
+
+def test_batches_and_servers_refuse_caller_state():
+    import ctypes
+    import paper_1804_07250_amd as tl
+    L = tl.lib()
+    dom = tl.domain(tl.TL_DOMINO, n=8)
+    w = tl.weights(tl.TL_W_UNIFORM)
+    seeds = (ctypes.c_uint64 * 1)(1)
+    opt = tl.options(device_buf=256, device_buf_bytes=1 << 20)
+    h = ctypes.c_void_p()
+    assert L.tl_batch_create(1, ctypes.byref(dom), ctypes.byref(w), seeds, ctypes.byref(opt),
+                             ctypes.byref(h)) == tl.TL_EINVAL
+    assert L.tl_server_create(1 << 20, 4, ctypes.byref(opt), ctypes.byref(h)) == tl.TL_EINVAL
