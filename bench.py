@@ -61,7 +61,7 @@ def parse():
     p.add_argument("--no-served", action="store_true")
     p.add_argument("--batched-chains", type=int, default=4096)
     p.add_argument("--batched-sweeps", type=int, default=5000)
-    p.add_argument("--served-requests", type=int, default=400)
+    p.add_argument("--served-requests", type=int, default=2000)
     p.add_argument("--served-rate", type=float, default=200.0)
     p.add_argument("--served-sweeps", type=int, default=2000)
     p.add_argument("--served-budget-mib", type=int, default=1024)
@@ -118,8 +118,8 @@ def run_batched(tl, args):
 
 def run_served(tl, args):
     """Served form: six-vertex domain-wall requests, N uniform over
-    {64,...,1024}, weights (1,1,sqrt 2) heat-bath / (1,1,1) alternating, 2000
-    sweeps, Poisson arrivals; admitted by a device-memory budget."""
+    {64,...,1024}, weights (1,1,sqrt 2) / (1,1,1) alternating as lazy Metropolis
+    thresholds, 2000 sweeps, Poisson arrivals; admitted by a device-memory budget."""
     from paper_1804_07250_amd import workloads
     from paper_1804_07250_amd.serving import Server
     reqs = workloads.serve_requests(args.served_requests, args.served_rate)
@@ -132,6 +132,7 @@ def run_served(tl, args):
             time.sleep(delay)
         dom = tl.domain(tl.TL_SIXVERTEX, n=r["N"])
         w = tl.weights(tl.TL_W_SIXVERTEX, *r["w2"])
+        w.rule = tl.TL_METROPOLIS if r["metropolis"] else tl.TL_HEATBATH
         tickets.append((sv.submit(dom, w, r["seed"], args.served_sweeps), r))
     res = [(sv.wait(t, 600.0), r) for t, r in tickets]
     end = time.perf_counter()
@@ -145,7 +146,7 @@ def run_served(tl, args):
             "max_ms": round(float(lat.max()), 3), "span_s": round(end - start, 3),
             "peak_active": st["peak_active"], "peak_bytes": st["peak_bytes"],
             "workload": "served: six-vertex DWBC, N uniform over {64,128,256,512,1024}, weights (1,1,sqrt2) and "
-                        "(1,1,1) alternating, %d sweeps per request, Poisson %.0f/s, %d requests, budget %d MiB, "
+                        "(1,1,1) alternating (lazy Metropolis), %d sweeps per request, Poisson %.0f/s, %d requests, budget %d MiB, "
                         "%d slots, ticks of %d sweeps (x4 for one-bit jobs)"
                         % (args.served_sweeps, args.served_rate, len(res), args.served_budget_mib, args.served_slots,
                            args.served_quantum)}

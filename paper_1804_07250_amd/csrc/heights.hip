@@ -415,9 +415,12 @@ __global__ void __launch_bounds__(256) height_step_kernel(uint32_t *planes, size
 // row halo, the rows still valid before sweep s are [rps*s, LR - rps*s) (rps
 // rows go stale per sweep on each side), and only those are computed.  Under
 // the random colour order (RANDOM) step q of the launch (K per sweep) draws
-// its colour and computes rows [q, LR - q).  The block has a thread per
-// (row, group) task (blockDim >= LR * LG, as every launch plan gives): thread
-// tid handles group tid % LG of row base + tid / LG.
+// its colour and computes rows [q, LR - q).  Lozenge: every row holds sites
+// of every colour; the block has a thread per (row, group) task (blockDim >=
+// LR * LG) and thread tid handles group tid % LG of row base + tid / LG.
+// Six-vertex: only rows of parity c >> 1 hold sites of colour c, so the
+// threads cover those rows alone (blockDim >= ceil(LR / 2) * LG): thread tid
+// handles group tid % LG of the (tid / LG)-th such row from base.
 template <int MODE, int KIND, bool RANDOM, bool MASKED>
 __device__ __forceinline__ void height_tile(uint32_t *lds, const uint32_t *__restrict__ in,
                                             uint32_t *__restrict__ out, size_t PS, uint32_t RS, uint32_t ng,
@@ -448,6 +451,7 @@ __device__ __forceinline__ void height_tile(uint32_t *lds, const uint32_t *__res
     const bool lane = gg >= 0 && gg < (int)ng;
     const uint32_t K_colours = geo.model == TL_LOZENGE ? 3u : 4u;
     const uint32_t rps = geo.model == TL_LOZENGE ? 3u : 2u;
+    const bool sixv = geo.model != TL_LOZENGE;
     for (uint32_t s = 0; s < nsweeps; ++s) {
         for (uint32_t i = 0; i < K_colours; ++i) {
             // colour, sweep counter of the draws and valid rows of this step
@@ -459,7 +463,8 @@ __device__ __forceinline__ void height_tile(uint32_t *lds, const uint32_t *__res
                 base = HR ? q : 0u;
                 end = HR ? LR - q : LR;
             }
-            const uint32_t lr = base + r0;
+            // six-vertex: the first row >= base of parity c >> 1, then every other row
+            const uint32_t lr = sixv ? base + (((uint32_t)(R0 + (int)base) & 1u) ^ (c >> 1)) + 2u * r0 : base + r0;
             const int gr = R0 + (int)lr;
             if (lane && lr < end && lr >= 1 && lr + 1 < LR && site_row(geo, gr, rows))
                 height_group<MODE, KIND, MASKED>(lds, LPS, LRS, lr, lg, geo, gr, (uint32_t)gg, c, t, T, k0, k1);
@@ -748,7 +753,7 @@ hipError_t height_colour_step(const HeightDev &d, int colour, uint32_t t, const 
                   k0, k1);
 }
 
-HeightTile height_auto_tile(const HeightDev &d)
+HeightTile height_auto_tile(const HeightDev &d, bool uniform)
 {
     HeightTile t;
     if (d.rows <= 96 && d.ng <= 4) {   // whole domain in one tile, no halo
@@ -757,9 +762,13 @@ HeightTile height_auto_tile(const HeightDev &d)
         t.S = 1u << 30;
         return t;
     }
-    t.TR = 8;   // measured best on MI355X for the 1024 hexagon and the N = 1024 square
-    t.TG = d.ng < 4 ? d.ng : 4;
-    t.S = 8;
+    // Rows up to 8 groups wide are one tile wide (no column halo).  Weighted
+    // decisions (a chain of Philox planes per step) favour short tiles and few
+    // sweeps per launch, one-bit decisions longer launches; measured on MI355X
+    // for the 1024 hexagon (q = 1999/2000) and the N = 1024 squares.
+    t.TG = d.ng <= 8 ? d.ng : 4;
+    t.TR = uniform ? 8 : 4;
+    t.S = uniform ? 16 : 6;
     return t;
 }
 
@@ -774,7 +783,9 @@ bool height_plan(const HeightDev &d, const HeightTile &tile, uint32_t S_max, Til
     const uint32_t TG = tile.TG == 0 ? 1u : (tile.TG < d.ng ? tile.TG : d.ng);
     const uint32_t tiles_x = (d.ng + TG - 1) / TG;
     const uint32_t LG0 = TG + (tiles_x > 1 ? 2u : 0u);
-    const uint32_t max_rows = kHeightThreads / LG0;
+    // six-vertex tiles run a thread per row pair (one row of each pair is idle
+    // in every colour step), lozenge tiles a thread per row
+    const uint32_t max_rows = (d.model == TL_LOZENGE ? 1u : 2u) * (kHeightThreads / LG0);
     if (max_rows < 2u * rows_per_sweep + 3u) return false;
     uint32_t TR = tile.TR == 0 ? 1u : (tile.TR < d.rows ? tile.TR : d.rows);
     if (TR < d.rows && TR > max_rows - 2u * rows_per_sweep) TR = max_rows - 2u * rows_per_sweep;
@@ -787,7 +798,7 @@ bool height_plan(const HeightDev &d, const HeightTile &tile, uint32_t S_max, Til
     const uint32_t HR = tiles_y > 1 ? rows_per_sweep * S : 0u;
     const uint32_t HG = tiles_x > 1 ? 1u : 0u;
     const uint32_t LR = TR + 2 * HR, LG = TG + 2 * HG;
-    const uint32_t tasks = LR * LG;
+    const uint32_t tasks = height_task_rows(d.model, LR) * LG;
     const uint32_t lds = d.P * LR * 4u * (LG + 2u) * 4u;
     if (tasks > kHeightThreads || lds > 160u * 1024u) return false;
     p->S = S;

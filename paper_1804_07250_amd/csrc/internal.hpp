@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
+#include "../../include/tilings.h"
 
 #include <vector>
 
@@ -198,7 +199,7 @@ hipError_t height_colour_step(const HeightDev &d, int colour, uint32_t t, const 
                               uint64_t seed, hipStream_t s, Timing *tm = nullptr);
 hipError_t height_tiled_sweeps(HeightDev &d, const HeightTile &tile, uint32_t t0, uint32_t n, const Thr &T,
                                int metropolis, uint64_t seed, hipStream_t s, Timing *tm = nullptr);
-HeightTile height_auto_tile(const HeightDev &d);
+HeightTile height_auto_tile(const HeightDev &d, bool uniform);
 // int32 canonical export into dev (rows x (row length) values)
 hipError_t height_export(const HeightDev &d, int32_t *dev, hipStream_t s);
 hipError_t height_observe(const HeightDev &d, uint32_t B, uint32_t bins_x, unsigned long long *bins, hipStream_t s);
@@ -232,6 +233,9 @@ struct TilePlan {
 // Largest launch of at most S_max sweeps the tile shape allows (tile sizes
 // clamped as the single-state launches clamp them); false if none fits.
 bool domino_plan(const DominoDev &d, const DominoTile &tile, uint32_t S_max, TilePlan *p);
+// Thread rows of a height tile of LR rows: lozenge one per row, six-vertex
+// one per row pair (each colour step updates rows of one parity only).
+inline uint32_t height_task_rows(int model, uint32_t LR) { return model == TL_LOZENGE ? LR : (LR + 1u) / 2u; }
 bool height_plan(const HeightDev &d, const HeightTile &tile, uint32_t S_max, TilePlan *p);
 
 // One state's share of a multi-job launch (served form): the state it reads

@@ -352,7 +352,8 @@ public:
                   TilePlan *p) const override
     {
         HeightTile tile;
-        if (d_.rows * d_.ng <= 512u && (size_t)d_.P * d_.rows * 4u * (d_.ng + 2u) * 4u <= 64u * 1024u) {
+        if (height_task_rows(d_.model, d_.rows) * d_.ng <= 512u &&
+            (size_t)d_.P * d_.rows * 4u * (d_.ng + 2u) * 4u <= 64u * 1024u) {
             tile.TR = d_.rows;
             tile.TG = d_.ng;
         } else {
@@ -452,7 +453,7 @@ public:
                 }
             return hipSuccess;
         }
-        HeightTile tile = height_auto_tile(d_);
+        HeightTile tile = height_auto_tile(d_, K.uniform());
         if (opt.tile_rows) tile.TR = opt.tile_rows;
         if (opt.tile_groups) tile.TG = opt.tile_groups;
         if (opt.sweeps_per_launch) tile.S = opt.sweeps_per_launch;

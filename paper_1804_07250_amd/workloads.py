@@ -21,7 +21,8 @@ def batch_orders(count=4096, lo=16, hi=512, seed=BATCH_SEED):
 
 
 def serve_requests(count, rate_per_s=200.0, seed=0x5E4E, sizes=SERVE_SIZES):
-    """List of dicts: arrival time (s), N, weights (a^2, b^2, c^2), seed."""
+    """List of dicts: arrival time (s), N, weights (a^2, b^2, c^2), rule
+    (lazy Metropolis thresholds), seed."""
     rng = np.random.Generator(np.random.PCG64(seed))
     gaps = rng.exponential(1.0 / rate_per_s, size=count)
     ns = rng.integers(0, len(sizes), size=count)
@@ -29,5 +30,5 @@ def serve_requests(count, rate_per_s=200.0, seed=0x5E4E, sizes=SERVE_SIZES):
     out = []
     for i in range(count):
         w2 = (1.0, 1.0, 2.0) if i % 2 == 0 else (1.0, 1.0, 1.0)
-        out.append({"arrival": float(t[i]), "N": int(sizes[ns[i]]), "w2": w2, "seed": i})
+        out.append({"arrival": float(t[i]), "N": int(sizes[ns[i]]), "w2": w2, "metropolis": True, "seed": i})
     return out
