@@ -27,6 +27,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# LDS: 256 bytes per clock per CU for conflict-free 128-bit reads (gfx950),
+# 256 CUs, 2.4 GHz
+LDS_PEAK_GBS = 256 * 256 * 2.4
 
 WORKLOADS = {
     "aztec2048": dict(model="domino", n=2048, sweeps=10000, seed=7, obs_every=100, obs_bin=64),
@@ -268,6 +271,22 @@ def traffic_record(name):
     return rec
 
 
+def lds_roofline(rec, avg_launch_s):
+    """LDS bytes per launch (rocprofv3 SQ_INSTS_LDS_{LOAD,STORE,ATOMIC}_BANDWIDTH,
+    64-byte units) over the live average launch time, against the LDS peak;
+    the fraction of CU-cycles the LDS was busy, and of those the share stalled
+    by bank conflicts (SQ_LDS_IDX_ACTIVE, SQ_LDS_BANK_CONFLICT)."""
+    if not rec or "lds_bytes_per_launch" not in rec or avg_launch_s <= 0:
+        return None
+    achieved = rec["lds_bytes_per_launch"] / avg_launch_s / 1e9
+    busy = rec["lds_active_cycles_per_launch"] / (256 * 2.4e9 * avg_launch_s)
+    return {"achieved": round(achieved, 1), "peak": round(LDS_PEAK_GBS, 1), "unit": "GB/s",
+            "frac": round(achieved / LDS_PEAK_GBS, 4), "bytes_per_launch": rec["lds_bytes_per_launch"],
+            "busy_frac": round(busy, 4),
+            "bank_conflict_frac": round(rec["lds_bank_conflict_cycles_per_launch"] /
+                                        max(1.0, rec["lds_active_cycles_per_launch"]), 4)}
+
+
 def cpu_baseline(wl, budget_s):
     """The serial oracle on the same workload from its start, for a bounded
     number of sweeps (about budget_s seconds)."""
@@ -361,7 +380,8 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": rec["bytes_per_launch"] if rec else None,
             "kernel": kname, "avg_launch_us": round(avg_ms * 1e3, 3), "launches": launches,
-            "algorithmic_bytes_per_launch": bytes_per_launch}
+            "algorithmic_bytes_per_launch": bytes_per_launch,
+            "lds": lds_roofline(rec, avg_ms * 1e-3)}
     out = {"metric": "site-updates/sec on 1 MI355X (plain vs batched vs served p50/p99), bit-exact",
            "value": value, "unit": "site-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": el / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
