@@ -91,13 +91,20 @@ __device__ __forceinline__ void decide128(uint32_t key0, uint32_t key1, uint32_t
         for (uint32_t u = 0; u < kDecidePlanes; ++u) {
             const uint32_t b = 31u - (j0 + u);
             const uint32_t below = (b == 0u) ? 0u : ((1u << b) - 1u);
+            // per-context all-ones / all-zero masks (uniform across the wave)
+            uint32_t tsel[NC], nsel[NC];
+#pragma unroll
+            for (int i = 0; i < NC; ++i) {
+                tsel[i] = 0u - ((T[i] >> b) & 1u);
+                nsel[i] = (T[i] & below) ? ~0u : 0u;
+            }
 #pragma unroll
             for (int w = 0; w < 4; ++w) {
                 uint32_t tb = 0u, nz = 0u;
 #pragma unroll
                 for (int i = 0; i < NC; ++i) {
-                    if ((T[i] >> b) & 1u) tb |= cm[i][w];
-                    if (T[i] & below) nz |= cm[i][w];
+                    tb |= cm[i][w] & tsel[i];
+                    nz |= cm[i][w] & nsel[i];
                 }
                 lt[w] |= eq[w] & tb & ~R[u][w];
                 eq[w] &= ~(tb ^ R[u][w]) & nz;
