@@ -53,11 +53,13 @@ def test_lozenge_parity(abc, kind):
         assert (s.export() == o.export()).all(), "%s %s after %d sweeps" % (abc, kind, o.t)
 
 
-@pytest.mark.parametrize("abc,tile_rows,spl,kernel", [((60, 70, 80), 16, 3, 2), ((130, 120, 140), 24, 5, 2),
-                                                       ((200, 90, 300), 32, 40, 2), ((33, 44, 55), 0, 0, 1)])
-def test_lozenge_tiles_and_streaming(abc, tile_rows, spl, kernel):
+@pytest.mark.parametrize("abc,tile_rows,spl,kernel,groups", [((60, 70, 80), 16, 3, 2, 0), ((130, 120, 140), 24, 5, 2, 0),
+                                                              ((200, 90, 300), 32, 40, 2, 0), ((33, 44, 55), 0, 0, 1, 0),
+                                                              ((150, 140, 160), 5, 3, 2, 1), ((90, 100, 80), 7, 4, 2, 2)])
+def test_lozenge_tiles_and_streaming(abc, tile_rows, spl, kernel, groups):
     tl = need_gpu()
-    s = loz_sampler(tl, *abc, seed=5, q=Fraction(3, 4), kernel=kernel, tile_rows=tile_rows, sweeps_per_launch=spl)
+    s = loz_sampler(tl, *abc, seed=5, q=Fraction(3, 4), kernel=kernel, tile_rows=tile_rows, sweeps_per_launch=spl,
+                    tile_groups=groups)
     o = loz_oracle(*abc, seed=5, q=Fraction(3, 4))
     s.sweep(11)
     o.sweep(11)
@@ -127,12 +129,19 @@ def test_sixvertex_parity(N, kind):
         assert (s.export() == o.export()).all(), "N=%d %s after %d sweeps" % (N, kind, o.t)
 
 
-@pytest.mark.parametrize("N,tile_rows,spl,kernel", [(100, 16, 3, 2), (300, 20, 6, 2), (513, 32, 30, 2),
-                                                     (77, 0, 0, 1)])
-def test_sixvertex_tiles_and_streaming(N, tile_rows, spl, kernel):
+# Odd tile heights put tiles at odd first rows, where a six-vertex tile's
+# threads start on the other row parity; tile_groups splits rows into columns.
+@pytest.mark.parametrize("N,tile_rows,spl,kernel,groups,order",
+                         [(100, 16, 3, 2, 0, 0), (300, 20, 6, 2, 0, 0), (513, 32, 30, 2, 0, 0), (77, 0, 0, 1, 0, 0),
+                          (211, 5, 3, 2, 0, 0), (150, 7, 4, 2, 1, 0), (64, 3, 2, 2, 0, 0), (301, 9, 5, 2, 2, 0),
+                          (211, 5, 3, 2, 0, 1), (150, 7, 2, 2, 1, 1)])
+def test_sixvertex_tiles_and_streaming(N, tile_rows, spl, kernel, groups, order):
     tl = need_gpu()
-    s = sixv_sampler(tl, N, seed=8, w2=(1, 1, 2), kernel=kernel, tile_rows=tile_rows, sweeps_per_launch=spl)
-    o = sixv_oracle(N, seed=8, w2=(1, 1, 2))
+    say("six-vertex tiles N=%d rows=%d spl=%d kernel=%d groups=%d order=%d" % (N, tile_rows, spl, kernel, groups,
+                                                                             order))
+    s = sixv_sampler(tl, N, seed=8, w2=(1, 1, 2), kernel=kernel, tile_rows=tile_rows, sweeps_per_launch=spl,
+                     tile_groups=groups, colour_order=order)
+    o = sixv_oracle(N, seed=8, w2=(1, 1, 2), random_colours=order == 1)
     s.sweep(13)
     o.sweep(13)
     assert (s.export() == o.export()).all()
