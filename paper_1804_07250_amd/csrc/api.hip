@@ -85,6 +85,16 @@ struct tl_sampler {
     unsigned long long *bin_tmp = nullptr;
     uint32_t bins_x = 0, bins_y = 0, B = 1;
     std::vector<uint32_t> cells_per_bin;    // lazily computed on the host
+
+    // Releases whatever was set up (also after a failed create).
+    ~tl_sampler()
+    {
+        if (stream) (void)hipStreamSynchronize(stream);
+        if (model) model->release();
+        if (bin_sum) (void)hipFree(bin_sum);
+        if (bin_tmp) (void)hipFree(bin_tmp);
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
 };
 
 namespace {
@@ -344,20 +354,15 @@ tl_status tl_sampler_create(const tl_domain *dom, const tl_weights *w, uint64_t 
     if (s->opt.device_buf) {
         // the state in caller-owned memory: two buffers, each 256-byte aligned
         const size_t half = state_half_bytes(*s->model), need = 2 * half;
-        if (s->opt.device_buf_bytes < need || ((uintptr_t)s->opt.device_buf & 255u)) {
-            if (s->own_stream) (void)hipStreamDestroy(s->stream);
+        if (s->opt.device_buf_bytes < need || ((uintptr_t)s->opt.device_buf & 255u))
             return fail(TL_EINVAL, "device_buf must hold %zu bytes, 256-byte aligned", need);
-        }
         char *buf = (char *)s->opt.device_buf;
         e = s->model->allocate_into((uint32_t *)buf, (uint32_t *)(buf + half));
     } else {
         e = s->model->allocate();
     }
-    if (e != hipSuccess) {
-        s->model->release();
-        if (s->own_stream) (void)hipStreamDestroy(s->stream);
+    if (e != hipSuccess)
         return fail(e == hipErrorOutOfMemory ? TL_ENOMEM : TL_EDEVICE, "state allocation: %s", hipGetErrorString(e));
-    }
     s->B = s->opt.obs_bin ? s->opt.obs_bin : 1u;
     uint32_t cw, ch;
     s->model->cell_box(&cw, &ch);
@@ -365,13 +370,8 @@ tl_status tl_sampler_create(const tl_domain *dom, const tl_weights *w, uint64_t 
     s->bins_y = (ch + s->B - 1) / s->B;
     const size_t nb = (size_t)s->bins_x * s->bins_y;
     if (hipMalloc(&s->bin_sum, nb * sizeof(unsigned long long)) != hipSuccess ||
-        hipMalloc(&s->bin_tmp, nb * sizeof(unsigned long long)) != hipSuccess) {
-        if (s->bin_sum) (void)hipFree(s->bin_sum);
-        s->bin_sum = nullptr;
-        s->model->release();
-        if (s->own_stream) (void)hipStreamDestroy(s->stream);
+        hipMalloc(&s->bin_tmp, nb * sizeof(unsigned long long)) != hipSuccess)
         return fail(TL_ENOMEM, "observable buffers");
-    }
     TL_HIP(hipMemsetAsync(s->bin_sum, 0, nb * sizeof(unsigned long long), s->stream));
     TL_HIP(s->model->init(dom->init == TL_INIT_MAX, s->stream));
     *out = s.release();
@@ -528,13 +528,7 @@ tl_status tl_sampler_import(tl_sampler *s, const void *host, size_t bytes, uint6
 
 tl_status tl_sampler_destroy(tl_sampler *s)
 {
-    if (!s) return TL_OK;
-    if (s->stream) (void)hipStreamSynchronize(s->stream);
-    if (s->model) s->model->release();
-    if (s->bin_sum) (void)hipFree(s->bin_sum);
-    if (s->bin_tmp) (void)hipFree(s->bin_tmp);
-    if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
-    delete s;
+    delete s;   // the destructor synchronises and releases
     return TL_OK;
 }
 

@@ -181,7 +181,11 @@ tl_status tl_batch_create(int32_t n, const tl_domain *doms, const tl_weights *w,
     if (opt && opt->colour_order) return tl::fail(TL_EINVAL, "batches run the fixed colour order");
     if (opt && opt->device_buf) return tl::fail(TL_EINVAL, "batches allocate their own chain pool");
     *out = nullptr;
-    std::unique_ptr<tl_batch> b(new (std::nothrow) tl_batch());
+    // every early return below releases what was set up so far
+    struct Destroy {
+        void operator()(tl_batch *p) const { (void)tl_batch_destroy(p); }
+    };
+    std::unique_ptr<tl_batch, Destroy> b(new (std::nothrow) tl_batch());
     if (!b) return tl::fail(TL_ENOMEM, "host allocation failed");
     b->count = n;
     b->doms.assign(doms, doms + n);
@@ -235,10 +239,8 @@ tl_status tl_batch_create(int32_t n, const tl_domain *doms, const tl_weights *w,
     b->cus = (uint32_t)cus;
     if (hipMalloc(&b->planes, words * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&b->d_chains, n * sizeof(tl::BatchChain)) != hipSuccess ||
-        hipMalloc(&b->d_counter, sizeof(uint32_t)) != hipSuccess) {
-        tl_batch_destroy(b.release());
+        hipMalloc(&b->d_counter, sizeof(uint32_t)) != hipSuccess)
         return tl::fail(TL_ENOMEM, "batch state allocation (%zu MB)", (size_t)(words * 4 >> 20));
-    }
     // longest chains first
     b->order.resize(n);
     std::iota(b->order.begin(), b->order.end(), 0u);
@@ -247,15 +249,9 @@ tl_status tl_batch_create(int32_t n, const tl_domain *doms, const tl_weights *w,
     if (opt && opt->tile_rows) b->threads = opt->tile_rows;   // work-group size override
     const tl_batch::BundleSet *set = nullptr;
     st = bundle_set(b.get(), b->threads, &set);
-    if (st != TL_OK) {
-        tl_batch_destroy(b.release());
-        return st;
-    }
+    if (st != TL_OK) return st;
     st = init_all(b.get());
-    if (st != TL_OK) {
-        tl_batch_destroy(b.release());
-        return st;
-    }
+    if (st != TL_OK) return st;
     TL_HIP(hipStreamSynchronize(b->stream));
     *out = b.release();
     return TL_OK;
