@@ -185,6 +185,10 @@ struct tl_server {
 
     // scheduler-thread state
     hipStream_t stream = nullptr;
+    // a tick's launches of different kernel instantiations run side by side:
+    // the first on `stream`, the others on `side`, joined through events
+    hipStream_t side = nullptr;
+    hipEvent_t ev_upload = nullptr, ev_side = nullptr;
     Arena arena;
     PinnedPool pinned;
     std::vector<std::unique_ptr<Job>> active;
@@ -401,16 +405,24 @@ bool tick(tl_server *sv)
         e = hipMemcpyAsync(sv->d_jobs, hj, run.size() * sizeof(tl::TileJob), hipMemcpyHostToDevice, sv->stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(sv->d_items, hi, ni * sizeof(tl::TileItem), hipMemcpyHostToDevice, sv->stream);
-        for (const Group &gr : groups) {
+        // launches after the first wait for the uploads on the side stream, and
+        // the main stream waits for them before anything else of this tick
+        const bool split = groups.size() > 1;
+        if (split && e == hipSuccess) e = hipEventRecord(sv->ev_upload, sv->stream);
+        if (split && e == hipSuccess) e = hipStreamWaitEvent(sv->side, sv->ev_upload, 0);
+        for (size_t k = 0; k < groups.size(); ++k) {
+            const Group &gr = groups[k];
+            hipStream_t st = k == 0 ? sv->stream : sv->side;
             if (e != hipSuccess) break;
             if (gr.key == 100u)
-                e = tl::domino_items(sv->d_jobs, sv->d_items + gr.first, gr.count, gr.threads, gr.lds, 0u,
-                                     sv->stream);
+                e = tl::domino_items(sv->d_jobs, sv->d_items + gr.first, gr.count, gr.threads, gr.lds, 0u, st);
             else
                 e = tl::height_items(sv->d_jobs, sv->d_items + gr.first, gr.count, gr.threads, gr.lds,
                                      gr.key >= 3u ? (uint32_t)tl::kModeMetropolis : (uint32_t)tl::kModeHeatBath,
-                                     gr.key % 3u, 0u, 0u, sv->stream);
+                                     gr.key % 3u, 0u, 0u, st);
         }
+        if (split && e == hipSuccess) e = hipEventRecord(sv->ev_side, sv->side);
+        if (split && e == hipSuccess) e = hipStreamWaitEvent(sv->stream, sv->ev_side, 0);
     }
     for (size_t i = 0; i < run.size(); ++i) {
         Job &j = *run[i];
@@ -510,6 +522,7 @@ void scheduler(tl_server *sv)
 void destroy_resources(tl_server *sv)
 {
     if (sv->stream) (void)hipStreamSynchronize(sv->stream);
+    if (sv->side) (void)hipStreamSynchronize(sv->side);
     for (hipEvent_t e : sv->events)
         if (e) (void)hipEventDestroy(e);
     sv->events.clear();
@@ -521,6 +534,11 @@ void destroy_resources(tl_server *sv)
     }
     sv->pinned.release();
     sv->arena.release();
+    if (sv->ev_upload) (void)hipEventDestroy(sv->ev_upload);
+    if (sv->ev_side) (void)hipEventDestroy(sv->ev_side);
+    sv->ev_upload = sv->ev_side = nullptr;
+    if (sv->side) (void)hipStreamDestroy(sv->side);
+    sv->side = nullptr;
     if (sv->stream) (void)hipStreamDestroy(sv->stream);
     sv->stream = nullptr;
 }
@@ -543,6 +561,9 @@ tl_status tl_server_create(size_t hbm_budget_bytes, int32_t max_slots, const tl_
     sv->t0 = std::chrono::steady_clock::now();
     if (hipGetDevice(&sv->device) != hipSuccess) return tl::fail(TL_EDEVICE, "no current device");
     hipError_t e = hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&sv->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&sv->ev_upload, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&sv->ev_side, hipEventDisableTiming);
     if (e == hipSuccess) e = sv->arena.init(hbm_budget_bytes);
     if (e == hipSuccess) e = grow(sv.get(), 64, 4096);
     if (e != hipSuccess) {
