@@ -66,12 +66,14 @@ static_assert(kKindClass == kTableClass && kKindSum == kTableSum, "table layouts
 // (kind) and a compile-time flag.
 #define TL_HEIGHT_PICK_R(KERNEL, mode, kind, R)                                                 \
     ((mode) == kUniform ? KERNEL<kUniform, kKindClass, R>                                       \
-     : (mode) == kMetropolis ? KERNEL<kMetropolis, kKindClass, R>                               \
+     : (mode) == kMetropolis                                                                    \
+         ? ((kind) == kKindSum ? KERNEL<kMetropolis, kKindSum, R> : KERNEL<kMetropolis, kKindClass, R>) \
      : (kind) == kKindSum ? KERNEL<kHeatBath, kKindSum, R> : KERNEL<kHeatBath, kKindClass, R>)
 // And with two: the colour order (random) and site planes (masked domain).
 #define TL_HEIGHT_PICK_RM(KERNEL, mode, kind, R, M)                                             \
     ((mode) == kUniform ? KERNEL<kUniform, kKindClass, R, M>                                    \
-     : (mode) == kMetropolis ? KERNEL<kMetropolis, kKindClass, R, M>                            \
+     : (mode) == kMetropolis                                                                    \
+         ? ((kind) == kKindSum ? KERNEL<kMetropolis, kKindSum, R, M> : KERNEL<kMetropolis, kKindClass, R, M>) \
      : (kind) == kKindSum ? KERNEL<kHeatBath, kKindSum, R, M> : KERNEL<kHeatBath, kKindClass, R, M>)
 #define TL_HEIGHT_PICK_ORDER_MASK(KERNEL, mode, kind, order, masked)                            \
     ((order) ? ((masked) ? TL_HEIGHT_PICK_RM(KERNEL, mode, kind, true, true)                    \
@@ -196,22 +198,30 @@ __device__ __forceinline__ void sixv_decide(uint32_t k0, uint32_t k1, uint32_t g
     if constexpr (MODE == kUniform) {
 #pragma unroll
         for (int w = 0; w < 4; ++w) D[w] = ~R0[w];
-    } else if constexpr (KIND == kKindSum && MODE == kHeatBath) {
+    } else if constexpr (KIND == kKindSum) {
         // thresholds that depend on sA + sB only (a = b): 5 classes s = 0..4
-        uint32_t T[5], cm[5][4];
+        // (Metropolis: x current state, down then up)
+        constexpr int NC = MODE == kMetropolis ? 10 : 5;
+        uint32_t T[NC], cm[NC][4];
 #pragma unroll
-        for (int i = 0; i < 5; ++i) T[i] = Tall.v[i];
+        for (int i = 0; i < NC; ++i) T[i] = Tall.v[i];
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
             const uint32_t A0 = ~hNE[w] & ~hSW[w], A1 = hNE[w] ^ hSW[w], A2 = hNE[w] & hSW[w];
             const uint32_t B0 = ~hNW[w] & ~hSE[w], B1 = hNW[w] ^ hSE[w], B2 = hNW[w] & hSE[w];
-            cm[0][w] = A0 & B0;
-            cm[1][w] = (A0 & B1) | (A1 & B0);
-            cm[2][w] = (A0 & B2) | (A1 & B1) | (A2 & B0);
-            cm[3][w] = (A1 & B2) | (A2 & B1);
-            cm[4][w] = A2 & B2;
+            const uint32_t s[5] = {A0 & B0, (A0 & B1) | (A1 & B0), (A0 & B2) | (A1 & B1) | (A2 & B0),
+                                   (A1 & B2) | (A2 & B1), A2 & B2};
+#pragma unroll
+            for (int q = 0; q < 5; ++q) {
+                if constexpr (MODE == kMetropolis) {
+                    cm[2 * q][w] = s[q] & ~cur[w];
+                    cm[2 * q + 1][w] = s[q] & cur[w];
+                } else {
+                    cm[q][w] = s[q];
+                }
+            }
         }
-        decide128<5>(k0, k1, g, r, t, c, T, cm, live, D);
+        decide128<NC>(k0, k1, g, r, t, c, T, cm, live, D);
     } else {
         constexpr int NC = MODE == kMetropolis ? 18 : 9;
         uint32_t T[NC], cm[NC][4];

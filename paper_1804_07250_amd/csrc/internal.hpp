@@ -245,7 +245,11 @@ enum { kModeHeatBath = 0, kModeMetropolis = 1, kModeUniform = 2 };
 // Layout of a height-model kernel table: classes (lozenge; six-vertex 9 classes
 // (sA, sB) [x2 Metropolis]) or six-vertex 5 classes by sA + sB (heat-bath).
 enum { kTableClass = 0, kTableSum = 1 };
-inline uint32_t table_kind(const Thr &K) { return K.count == 5u ? (uint32_t)kTableSum : (uint32_t)kTableClass; }
+// Six-vertex tables by sA + sB: 5 entries (heat-bath) or 5 x 2 (Metropolis).
+inline uint32_t table_kind(const Thr &K)
+{
+    return K.count == 5u || K.count == 10u ? (uint32_t)kTableSum : (uint32_t)kTableClass;
+}
 struct TileJob {
     const uint32_t *in;
     uint32_t *out;

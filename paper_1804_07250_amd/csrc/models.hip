@@ -388,8 +388,9 @@ public:
     // Six-vertex kernels take one threshold per weight class (sA, sB) (and
     // current state for Metropolis): class 3*sA + sB <-> mask with NE = sA>=1,
     // SW = sA>=2, NW = sB>=1, SE = sB>=2.  When the thresholds depend on
-    // sA + sB only (a = b), a heat-bath table has one entry per sum s = 0..4
-    // instead, and the kernels use those 5 classes.
+    // sA + sB only (a = b), the table has one entry per sum s = 0..4 (two for
+    // Metropolis: current state down, up) instead, and the kernels use those
+    // 5 classes.
     // Kernel table: the interior classes (below), and for a domain with free
     // north edges their table at v[kFreeBase ..].
     Thr kernel_table(const Thr &T, bool metro) const
@@ -407,7 +408,7 @@ public:
             return (i >= 1 ? 1u : 0u) | (j >= 1 ? 2u : 0u) | (i >= 2 ? 4u : 0u) | (j >= 2 ? 8u : 0u);
         };
         const uint32_t per = metro ? 2u : 1u;
-        bool by_sum = !metro;
+        bool by_sum = true;
         for (int i = 0; i < 3 && by_sum; ++i)
             for (int j = 0; j < 3; ++j) {
                 const int s = i + j, i0 = s < 2 ? s : 2;   // reference class of the sum

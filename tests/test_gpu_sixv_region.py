@@ -46,7 +46,9 @@ def test_masked_square_equals_domain_wall_square(N, w2, kernel, order):
 
 CASES = [("l40", (1, 1, 2), False, "min", "auto"), ("l40", (1, 1, 1), False, "max", "step"),
          ("l64", (4, 1, 4), True, "min", "tiled"), ("l130", (1, 1, 2), False, "max", "auto"),
-         ("random30", (1, 1, 2), False, "min", "auto"), ("l33", (1, 1, 1), False, "min", "tiled")]
+         ("random30", (1, 1, 2), False, "min", "auto"), ("l33", (1, 1, 1), False, "min", "tiled"),
+         ("l33", (1, 1, 2), True, "max", "tiled"), ("random30", (1, 1, 2), True, "min", "step"),
+         ("l130", (1, 1, 2), True, "min", "auto")]
 
 
 def mask_of(name):
