@@ -119,9 +119,12 @@ TL_FREE_NORTH = 1
 
 
 def domain(model, n=0, a=0, b=0, c=0, init=TL_INIT_MIN, mask=None, free_north=False):
-    """A domain; mask (2-D array, row 0 southmost, nonzero = face inside)
-    selects the TL_MASK shape (dominoes).  The returned struct keeps the
-    mask's bytes alive; the library copies them when a sampler is created."""
+    """A domain: the model's fixed shape (Aztec diamond of order n, a x b x c
+    hexagon, N x N domain-wall square), or with `mask` the TL_MASK shape:
+    (h, w) cells for dominoes and six-vertex domains, (h, w, 2) unit
+    triangles for lozenges, row 0 southmost, nonzero = inside.  free_north:
+    six-vertex domains whose north edges are free.  The returned struct keeps
+    the mask's bytes alive; the library copies them when a sampler is created."""
     if mask is not None:
         m = np.ascontiguousarray(np.asarray(mask) != 0, dtype=np.uint8)
         if m.ndim != (3 if model == TL_LOZENGE else 2) or (model == TL_LOZENGE and m.shape[2] != 2):
