@@ -159,7 +159,13 @@ size_t job_bytes(const tl::Model &m, uint32_t *rows, uint32_t *row_bytes)
 struct Tick {
     hipEvent_t ev = nullptr;
     uint32_t slot = 0;
-    std::vector<Job *> finishing;
+};
+
+// Jobs whose last tick has been enqueued: their export, digests and
+// observable run on the finishing stream; ev marks the end of that work.
+struct Finish {
+    hipEvent_t ev = nullptr;
+    std::vector<Job *> jobs;
 };
 
 }  // namespace
@@ -189,6 +195,10 @@ struct tl_server {
     // the first on `stream`, the others on `side`, joined through events
     hipStream_t side = nullptr;
     hipEvent_t ev_upload = nullptr, ev_side = nullptr;
+    // the results of finished jobs are produced on `fin`, after their last
+    // tick, so that they never hold up the ticks of the other jobs
+    hipStream_t fin = nullptr;
+    std::deque<Finish> finishing;
     Arena arena;
     PinnedPool pinned;
     std::vector<std::unique_ptr<Job>> active;
@@ -257,18 +267,38 @@ int32_t start_job(tl_server *sv, Job &j)
 
 // Result of a finished job: canonical export -> row digests -> host, and the
 // whole-state observable -> host, after its last tick.
-hipError_t enqueue_finish(tl_server *sv, Job &j)
+hipError_t enqueue_finish(Job &j, hipStream_t st)
 {
-    hipError_t e = j.model->export_canonical(j.d_export, sv->stream);
-    if (e == hipSuccess) e = tl::hash_rows(j.d_export, j.rows, j.row_bytes, j.d_digest, sv->stream);
+    hipError_t e = j.model->export_canonical(j.d_export, st);
+    if (e == hipSuccess) e = tl::hash_rows(j.d_export, j.rows, j.row_bytes, j.d_digest, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(j.h_res, j.d_digest, 32 * (size_t)j.rows, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemsetAsync(j.d_bin, 0, sizeof(unsigned long long), st);
+    if (e == hipSuccess) e = j.model->observe(j.obs_B, 1, j.d_bin, st);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(j.h_res, j.d_digest, 32 * (size_t)j.rows, hipMemcpyDeviceToHost, sv->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(j.d_bin, 0, sizeof(unsigned long long), sv->stream);
-    if (e == hipSuccess) e = j.model->observe(j.obs_B, 1, j.d_bin, sv->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(j.h_res + 32 * (size_t)j.rows, j.d_bin, sizeof(unsigned long long),
-                           hipMemcpyDeviceToHost, sv->stream);
+        e = hipMemcpyAsync(j.h_res + 32 * (size_t)j.rows, j.d_bin, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                           st);
     return e;
+}
+
+hipEvent_t take_event(tl_server *sv)
+{
+    if (sv->events.empty()) {
+        hipEvent_t ev;
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return nullptr;
+        return ev;
+    }
+    hipEvent_t ev = sv->events.back();
+    sv->events.pop_back();
+    return ev;
+}
+
+void post_and_drop(tl_server *sv, Job *jp, int32_t st)
+{
+    auto it = std::find_if(sv->active.begin(), sv->active.end(),
+                           [&](const std::unique_ptr<Job> &p) { return p.get() == jp; });
+    if (it == sv->active.end()) return;
+    post(sv, *jp, jp->status != TL_OK ? jp->status : st);
+    sv->active.erase(it);
 }
 
 hipError_t grow(tl_server *sv, uint32_t jobs, uint32_t items)
@@ -311,17 +341,13 @@ bool retire(tl_server *sv)
     const hipError_t q = hipEventQuery(tk.ev);
     if (q == hipErrorNotReady) return false;
     const int32_t st = q == hipSuccess ? TL_OK : TL_EDEVICE;
-    for (Job *jp : tk.finishing) {
-        auto it = std::find_if(sv->active.begin(), sv->active.end(),
-                               [&](const std::unique_ptr<Job> &p) { return p.get() == jp; });
-        if (it == sv->active.end()) continue;
-        post(sv, *jp, jp->status != TL_OK ? jp->status : st);
-        sv->active.erase(it);
-    }
     sv->events.push_back(tk.ev);
     sv->inflight.pop_front();
     if (st != TL_OK) {   // the stream is unusable: fail every admitted job
         (void)hipStreamSynchronize(sv->stream);
+        (void)hipStreamSynchronize(sv->fin);
+        for (Finish &f : sv->finishing) sv->events.push_back(f.ev);
+        sv->finishing.clear();
         while (!sv->inflight.empty()) {
             sv->events.push_back(sv->inflight.front().ev);
             sv->inflight.pop_front();
@@ -433,33 +459,55 @@ bool tick(tl_server *sv)
     }
     Tick tk;
     tk.slot = slot;
+    Finish f;
     for (auto &jp : sv->active) {
         Job &j = *jp;
         if (j.finishing || j.enq < j.sweeps) continue;
-        if (j.status == TL_OK && enqueue_finish(sv, j) != hipSuccess) j.status = TL_EDEVICE;
         j.finishing = true;
-        tk.finishing.push_back(&j);
+        f.jobs.push_back(&j);
     }
-    if (sv->events.empty()) {
-        hipEvent_t ev;
-        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) ev = nullptr;
-        sv->events.push_back(ev);
-    }
-    tk.ev = sv->events.back();
-    sv->events.pop_back();
+    tk.ev = take_event(sv);
     if (!tk.ev || hipEventRecord(tk.ev, sv->stream) != hipSuccess) {
-        // no event: wait for the stream instead
+        // no event: wait for the stream instead, and fail the jobs it ends
         (void)hipStreamSynchronize(sv->stream);
-        for (Job *jp : tk.finishing) {
-            auto it = std::find_if(sv->active.begin(), sv->active.end(),
-                                   [&](const std::unique_ptr<Job> &p) { return p.get() == jp; });
-            post(sv, *jp, TL_EDEVICE);
-            sv->active.erase(it);
+        for (Job *jp : f.jobs) {
+            jp->status = TL_EDEVICE;
+            post_and_drop(sv, jp, TL_EDEVICE);
         }
         if (tk.ev) sv->events.push_back(tk.ev);
         return true;
     }
+    if (!f.jobs.empty()) {
+        // results of the jobs this tick ends, on the finishing stream after it
+        hipError_t fe = hipStreamWaitEvent(sv->fin, tk.ev, 0);
+        for (Job *jp : f.jobs)
+            if (jp->status == TL_OK && (fe != hipSuccess || enqueue_finish(*jp, sv->fin) != hipSuccess))
+                jp->status = TL_EDEVICE;
+        f.ev = take_event(sv);
+        if (!f.ev || hipEventRecord(f.ev, sv->fin) != hipSuccess) {
+            (void)hipStreamSynchronize(sv->fin);
+            for (Job *jp : f.jobs) post_and_drop(sv, jp, TL_EDEVICE);
+            if (f.ev) sv->events.push_back(f.ev);
+        } else {
+            sv->finishing.push_back(std::move(f));
+        }
+    }
     sv->inflight.push_back(std::move(tk));
+    return true;
+}
+
+// Post the jobs of the oldest finishing record if its work has completed;
+// false if it has not (or there is none).
+bool retire_finished(tl_server *sv)
+{
+    if (sv->finishing.empty()) return false;
+    Finish &f = sv->finishing.front();
+    const hipError_t q = hipEventQuery(f.ev);
+    if (q == hipErrorNotReady) return false;
+    const int32_t st = q == hipSuccess ? TL_OK : TL_EDEVICE;
+    for (Job *jp : f.jobs) post_and_drop(sv, jp, st);
+    sv->events.push_back(f.ev);
+    sv->finishing.pop_front();
     return true;
 }
 
@@ -497,12 +545,17 @@ void scheduler(tl_server *sv)
         if (sv->n_active > sv->peak_active) sv->peak_active = sv->n_active.load();
         bool busy = false;
         while (retire(sv)) busy = true;
+        while (retire_finished(sv)) busy = true;
         if (sv->inflight.size() < tl_server::kInflight && tick(sv)) busy = true;
-        if (!busy && !sv->inflight.empty()) std::this_thread::sleep_for(std::chrono::microseconds(20));
+        if (!busy && !(sv->inflight.empty() && sv->finishing.empty()))
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
     }
-    // shutdown: drain the stream, fail what has not finished
+    // shutdown: drain the streams, fail what has not finished
     (void)hipStreamSynchronize(sv->stream);
+    (void)hipStreamSynchronize(sv->fin);
     while (retire(sv)) {
+    }
+    while (retire_finished(sv)) {
     }
     for (auto &j : sv->active) post(sv, *j, TL_EBUSY);
     sv->active.clear();
@@ -523,6 +576,7 @@ void destroy_resources(tl_server *sv)
 {
     if (sv->stream) (void)hipStreamSynchronize(sv->stream);
     if (sv->side) (void)hipStreamSynchronize(sv->side);
+    if (sv->fin) (void)hipStreamSynchronize(sv->fin);
     for (hipEvent_t e : sv->events)
         if (e) (void)hipEventDestroy(e);
     sv->events.clear();
@@ -539,6 +593,8 @@ void destroy_resources(tl_server *sv)
     sv->ev_upload = sv->ev_side = nullptr;
     if (sv->side) (void)hipStreamDestroy(sv->side);
     sv->side = nullptr;
+    if (sv->fin) (void)hipStreamDestroy(sv->fin);
+    sv->fin = nullptr;
     if (sv->stream) (void)hipStreamDestroy(sv->stream);
     sv->stream = nullptr;
 }
@@ -562,6 +618,7 @@ tl_status tl_server_create(size_t hbm_budget_bytes, int32_t max_slots, const tl_
     if (hipGetDevice(&sv->device) != hipSuccess) return tl::fail(TL_EDEVICE, "no current device");
     hipError_t e = hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&sv->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&sv->fin, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&sv->ev_upload, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&sv->ev_side, hipEventDisableTiming);
     if (e == hipSuccess) e = sv->arena.init(hbm_budget_bytes);
