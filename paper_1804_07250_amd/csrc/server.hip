@@ -206,11 +206,11 @@ struct tl_server {
     std::vector<hipEvent_t> events;
     static constexpr uint32_t kInflight = 2, kSlots = kInflight + 1;
     uint32_t next_slot = 0;
+    // a tick's job descriptors and then its items, staged in one pinned
+    // buffer per slot and uploaded with one copy into d_buf
     uint32_t cap_jobs = 0, cap_items = 0;
-    tl::TileJob *d_jobs = nullptr;
-    tl::TileItem *d_items = nullptr;
-    tl::TileJob *h_jobs[kSlots] = {};
-    tl::TileItem *h_items[kSlots] = {};
+    uint8_t *d_buf = nullptr;
+    uint8_t *h_buf[kSlots] = {};
 
     double now() const
     {
@@ -301,6 +301,10 @@ void post_and_drop(tl_server *sv, Job *jp, int32_t st)
     sv->active.erase(it);
 }
 
+// Bytes of n job descriptors at the start of a staging buffer (the items
+// follow, 16-byte aligned).
+size_t staged_jobs_bytes(size_t n) { return (n * sizeof(tl::TileJob) + 15) & ~(size_t)15; }
+
 hipError_t grow(tl_server *sv, uint32_t jobs, uint32_t items)
 {
     if (jobs <= sv->cap_jobs && items <= sv->cap_items) return hipSuccess;
@@ -309,23 +313,17 @@ hipError_t grow(tl_server *sv, uint32_t jobs, uint32_t items)
     if (e != hipSuccess) return e;
     const uint32_t cj = std::max(jobs, std::max(2 * sv->cap_jobs, 64u));
     const uint32_t ci = std::max(items, std::max(2 * sv->cap_items, 4096u));
-    if (sv->d_jobs) (void)hipFree(sv->d_jobs);
-    if (sv->d_items) (void)hipFree(sv->d_items);
+    if (sv->d_buf) (void)hipFree(sv->d_buf);
     for (uint32_t s = 0; s < tl_server::kSlots; ++s) {
-        if (sv->h_jobs[s]) (void)hipHostFree(sv->h_jobs[s]);
-        if (sv->h_items[s]) (void)hipHostFree(sv->h_items[s]);
-        sv->h_jobs[s] = nullptr;
-        sv->h_items[s] = nullptr;
+        if (sv->h_buf[s]) (void)hipHostFree(sv->h_buf[s]);
+        sv->h_buf[s] = nullptr;
     }
-    sv->d_jobs = nullptr;
-    sv->d_items = nullptr;
+    sv->d_buf = nullptr;
     sv->cap_jobs = sv->cap_items = 0;
-    e = hipMalloc(&sv->d_jobs, cj * sizeof(tl::TileJob));
-    if (e == hipSuccess) e = hipMalloc(&sv->d_items, ci * sizeof(tl::TileItem));
-    for (uint32_t s = 0; s < tl_server::kSlots && e == hipSuccess; ++s) {
-        e = hipHostMalloc((void **)&sv->h_jobs[s], cj * sizeof(tl::TileJob), hipHostMallocDefault);
-        if (e == hipSuccess) e = hipHostMalloc((void **)&sv->h_items[s], ci * sizeof(tl::TileItem), hipHostMallocDefault);
-    }
+    const size_t bytes = staged_jobs_bytes(cj) + ci * sizeof(tl::TileItem);
+    e = hipMalloc(&sv->d_buf, bytes);
+    for (uint32_t s = 0; s < tl_server::kSlots && e == hipSuccess; ++s)
+        e = hipHostMalloc((void **)&sv->h_buf[s], bytes, hipHostMallocDefault);
     if (e == hipSuccess) {
         sv->cap_jobs = cj;
         sv->cap_items = ci;
@@ -397,8 +395,11 @@ bool tick(tl_server *sv)
     }
     const uint32_t slot = sv->next_slot;
     sv->next_slot = (sv->next_slot + 1) % tl_server::kSlots;
-    tl::TileJob *hj = sv->h_jobs[slot];
-    tl::TileItem *hi = sv->h_items[slot];
+    const size_t joff = staged_jobs_bytes(run.size());
+    tl::TileJob *hj = reinterpret_cast<tl::TileJob *>(sv->h_buf[slot]);
+    tl::TileItem *hi = reinterpret_cast<tl::TileItem *>(sv->h_buf[slot] + joff);
+    tl::TileJob *dj = reinterpret_cast<tl::TileJob *>(sv->d_buf);
+    tl::TileItem *di = reinterpret_cast<tl::TileItem *>(sv->d_buf + joff);
     // one launch per kernel instantiation: height jobs grouped by rule and
     // table layout (one-bit jobs ride with the heat-bath ones of the 5-class
     // layout), then the domino jobs
@@ -428,9 +429,8 @@ bool tick(tl_server *sv)
         gr.lds = std::max(gr.lds, p.lds);
     }
     if (ni) {
-        e = hipMemcpyAsync(sv->d_jobs, hj, run.size() * sizeof(tl::TileJob), hipMemcpyHostToDevice, sv->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(sv->d_items, hi, ni * sizeof(tl::TileItem), hipMemcpyHostToDevice, sv->stream);
+        e = hipMemcpyAsync(sv->d_buf, sv->h_buf[slot], joff + ni * sizeof(tl::TileItem), hipMemcpyHostToDevice,
+                           sv->stream);
         // launches after the first wait for the uploads on the side stream, and
         // the main stream waits for them before anything else of this tick
         const bool split = groups.size() > 1;
@@ -441,9 +441,9 @@ bool tick(tl_server *sv)
             hipStream_t st = k == 0 ? sv->stream : sv->side;
             if (e != hipSuccess) break;
             if (gr.key == 100u)
-                e = tl::domino_items(sv->d_jobs, sv->d_items + gr.first, gr.count, gr.threads, gr.lds, 0u, st);
+                e = tl::domino_items(dj, di + gr.first, gr.count, gr.threads, gr.lds, 0u, st);
             else
-                e = tl::height_items(sv->d_jobs, sv->d_items + gr.first, gr.count, gr.threads, gr.lds,
+                e = tl::height_items(dj, di + gr.first, gr.count, gr.threads, gr.lds,
                                      gr.key >= 3u ? (uint32_t)tl::kModeMetropolis : (uint32_t)tl::kModeHeatBath,
                                      gr.key % 3u, 0u, 0u, st);
         }
@@ -580,12 +580,9 @@ void destroy_resources(tl_server *sv)
     for (hipEvent_t e : sv->events)
         if (e) (void)hipEventDestroy(e);
     sv->events.clear();
-    if (sv->d_jobs) (void)hipFree(sv->d_jobs);
-    if (sv->d_items) (void)hipFree(sv->d_items);
-    for (uint32_t s = 0; s < tl_server::kSlots; ++s) {
-        if (sv->h_jobs[s]) (void)hipHostFree(sv->h_jobs[s]);
-        if (sv->h_items[s]) (void)hipHostFree(sv->h_items[s]);
-    }
+    if (sv->d_buf) (void)hipFree(sv->d_buf);
+    for (uint32_t s = 0; s < tl_server::kSlots; ++s)
+        if (sv->h_buf[s]) (void)hipHostFree(sv->h_buf[s]);
     sv->pinned.release();
     sv->arena.release();
     if (sv->ev_upload) (void)hipEventDestroy(sv->ev_upload);
