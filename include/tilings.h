@@ -160,6 +160,8 @@ typedef struct {
                                   * library allocates it); at least tl_sampler_state_bytes bytes,
                                   * 256-byte aligned, kept alive until tl_sampler_destroy */
     size_t device_buf_bytes;
+    const char *tune_cache;      /* samplers: path of the tile-shape cache tl_sampler_autotune
+                                  * reads and appends to (NULL = none) */
 } tl_options;
 
 /* Random colour order (Section 2.2, RandomWalk: the colour of every step is
@@ -208,6 +210,24 @@ typedef struct {
  * TL_EDEVICE. */
 tl_status tl_sampler_create(const tl_domain *dom, const tl_weights *w, uint64_t seed,
                             const tl_options *opt, tl_sampler **out);
+
+/* Tile shape of the tiled kernel picked by measurement (a performance choice
+ * only: every shape gives the same chain).  Candidates of tile height, width
+ * in groups and sweeps per launch are timed over probe_sweeps sweeps (0 = 50)
+ * on a copy of the state, which the sampler's state and sweep counter never
+ * see; the fastest is kept for the sampler's later sweeps (tile fields of its
+ * options still take precedence).  With opt->tune_cache set, a shape
+ * recorded there for the same model, shape, sizes, table kind, colour order
+ * and device is used without probing, and a newly measured one is appended
+ * (one text line per entry).  Synchronous.  Errors: TL_EINVAL, TL_ENOMEM,
+ * TL_EDEVICE. */
+typedef struct {
+    uint32_t tile_rows, tile_groups, sweeps_per_launch;   /* 0, 0, 0: the automatic shape won */
+    uint32_t candidates;     /* shapes timed (0 when taken from the cache) */
+    uint32_t from_cache;     /* 1 if the shape came from the cache */
+    float ms_per_sweep;      /* of the chosen shape, as measured (0 from the cache) */
+} tl_tune_info;
+tl_status tl_sampler_autotune(tl_sampler *s, uint32_t probe_sweeps, tl_tune_info *out);
 
 /* Device bytes of a sampler's state (its two bit-plane buffers, each rounded
  * up to a multiple of 256 bytes) for this domain: the size opt->device_buf

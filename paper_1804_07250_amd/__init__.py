@@ -50,7 +50,8 @@ class tl_options(ctypes.Structure):
     _fields_ = [("stream", ctypes.c_void_p), ("obs_every", ctypes.c_uint32), ("obs_bin", ctypes.c_uint32),
                 ("sweeps_per_launch", ctypes.c_uint32), ("tile_rows", ctypes.c_uint32),
                 ("kernel", ctypes.c_uint32), ("tile_groups", ctypes.c_uint32), ("colour_order", ctypes.c_uint32),
-                ("device_buf", ctypes.c_void_p), ("device_buf_bytes", ctypes.c_size_t)]
+                ("device_buf", ctypes.c_void_p), ("device_buf_bytes", ctypes.c_size_t),
+                ("tune_cache", ctypes.c_char_p)]
 
 
 class tl_observables(ctypes.Structure):
@@ -58,6 +59,12 @@ class tl_observables(ctypes.Structure):
                 ("scalar_sum", ctypes.c_int64), ("bins_x", ctypes.c_uint32), ("bins_y", ctypes.c_uint32),
                 ("bin_sum", ctypes.POINTER(ctypes.c_uint64)), ("bin_now", ctypes.POINTER(ctypes.c_uint64)),
                 ("bin_density", ctypes.POINTER(ctypes.c_double)), ("bin_capacity", ctypes.c_size_t)]
+
+
+class tl_tune_info(ctypes.Structure):
+    _fields_ = [("tile_rows", ctypes.c_uint32), ("tile_groups", ctypes.c_uint32),
+                ("sweeps_per_launch", ctypes.c_uint32), ("candidates", ctypes.c_uint32),
+                ("from_cache", ctypes.c_uint32), ("ms_per_sweep", ctypes.c_float)]
 
 
 class tl_cftp_info(ctypes.Structure):
@@ -94,6 +101,7 @@ def lib():
         L.tl_sampler_kernel_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(u64),
                                              ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_double)]
         L.tl_sampler_thresholds.argtypes = [vp, ctypes.POINTER(u32), u32, ctypes.POINTER(u32)]
+        L.tl_sampler_autotune.argtypes = [vp, u32, ctypes.POINTER(tl_tune_info)]
         L.tl_thresholds.argtypes = [ctypes.POINTER(tl_domain), ctypes.POINTER(tl_weights),
                                     ctypes.POINTER(u32), u32, ctypes.POINTER(u32)]
         L.tl_thresholds.restype = i32
@@ -104,7 +112,7 @@ def lib():
                      "tl_sampler_export_size", "tl_sampler_export", "tl_sampler_hash", "tl_sampler_import",
                      "tl_sampler_destroy", "tl_sampler_info", "tl_sampler_thresholds", "tl_sampler_reset",
                      "tl_sampler_set_timing", "tl_sampler_kernel_time", "tl_sampler_cftp",
-                     "tl_domain_extremes", "tl_sampler_state_bytes"):
+                     "tl_domain_extremes", "tl_sampler_state_bytes", "tl_sampler_autotune"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -157,12 +165,14 @@ def weights(kind=TL_W_UNIFORM, *w, rule=TL_HEATBATH):
 
 
 def options(stream=None, obs_every=0, obs_bin=1, sweeps_per_launch=0, tile_rows=0, kernel=0, tile_groups=0,
-            colour_order=0, device_buf=None, device_buf_bytes=0):
+            colour_order=0, device_buf=None, device_buf_bytes=0, tune_cache=None):
     """colour_order: 0 = colours 0..K-1 in every sweep, 1 = a random colour per step.
     device_buf: caller-owned device memory (an address, e.g. a tensor's data_ptr())
-    holding the sampler's state, at least state_bytes(domain) bytes."""
+    holding the sampler's state, at least state_bytes(domain) bytes.
+    tune_cache: path of the tile-shape cache of Sampler.autotune."""
     return tl_options(stream, obs_every, obs_bin, sweeps_per_launch, tile_rows, kernel, tile_groups, colour_order,
-                      device_buf, device_buf_bytes)
+                      device_buf, device_buf_bytes,
+                      None if tune_cache is None else os.fsencode(tune_cache))
 
 
 def state_bytes(dom):
@@ -208,6 +218,14 @@ class Sampler:
 
     def reset(self, seed: int):
         _check(lib().tl_sampler_reset(self._h, seed))
+
+    def autotune(self, probe_sweeps: int = 0):
+        """Pick the tiled kernel's tile shape by measurement (the chain does not
+        change).  Returns {"tile_rows", "tile_groups", "sweeps_per_launch",
+        "candidates", "from_cache", "ms_per_sweep"}."""
+        info = tl_tune_info()
+        _check(lib().tl_sampler_autotune(self._h, int(probe_sweeps), ctypes.byref(info)))
+        return {k: getattr(info, k) for k, _ in tl_tune_info._fields_}
 
     def cftp(self, max_log2: int = 24):
         """Exact sample by coupling from the past (raises TlError TL_EBUSY if the

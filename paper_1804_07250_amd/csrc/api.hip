@@ -5,6 +5,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <cstdio>
+
 #include <memory>
 #include <string>
 #include <vector>
@@ -250,6 +252,51 @@ tl_status make_table(const tl_domain &d, const tl_weights &w, std::vector<uint32
 }
 }  // namespace tl
 
+namespace {
+
+// Cache key of a tile shape: model, shape and sizes, table kind, colour
+// order and device (architecture and CU count).
+std::string tune_key(const tl_sampler *s, bool uniform)
+{
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    std::string arch = "?";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        arch = std::string(prop.gcnArchName) + "/" + std::to_string(prop.multiProcessorCount);
+    for (char &ch : arch)
+        if (ch == ' ') ch = '_';
+    const tl_domain &d = s->dom;
+    std::string k = "m" + std::to_string(d.model) + ":s" + std::to_string(d.shape) + ":" + std::to_string(d.n) + "," +
+                    std::to_string(d.a) + "," + std::to_string(d.b) + "," + std::to_string(d.c) + "," +
+                    std::to_string(d.w) + "x" + std::to_string(d.h) + "," + std::to_string(s->model->sites()) +
+                    ":f" + std::to_string(d.flags) + ":" + (uniform ? "one-bit" : "weighted") + ":o" +
+                    std::to_string(s->opt.colour_order) + ":" + arch;
+    return k;
+}
+
+// Last entry of `key` in the cache file: rows, groups, sweeps; false if none.
+bool tune_lookup(const char *path, const std::string &key, uint32_t v[3])
+{
+    FILE *f = path ? std::fopen(path, "r") : nullptr;
+    if (!f) return false;
+    char line[1024];
+    bool found = false;
+    while (std::fgets(line, sizeof line, f)) {
+        char k[768];
+        unsigned a, b, c;
+        if (std::sscanf(line, "%767s %u %u %u", k, &a, &b, &c) == 4 && key == k) {
+            v[0] = a;
+            v[1] = b;
+            v[2] = c;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *tl_status_str(tl_status st)
@@ -375,6 +422,109 @@ tl_status tl_sampler_create(const tl_domain *dom, const tl_weights *w, uint64_t 
     TL_HIP(hipMemsetAsync(s->bin_sum, 0, nb * sizeof(unsigned long long), s->stream));
     TL_HIP(s->model->init(dom->init == TL_INIT_MAX, s->stream));
     *out = s.release();
+    return TL_OK;
+}
+
+
+tl_status tl_sampler_autotune(tl_sampler *s, uint32_t probe_sweeps, tl_tune_info *out)
+{
+    if (!s) return fail(TL_EINVAL, "null sampler");
+    if (s->opt.kernel == 1) return fail(TL_EINVAL, "the streaming kernel has no tile shape");
+    if (probe_sweeps == 0) probe_sweeps = 50;
+    const tl::Thr T = table_of(s);
+    const bool metro = s->w.rule == TL_METROPOLIS;
+    const std::string key = tune_key(s, T.uniform());
+    tl_tune_info info{};
+    uint32_t cached[3];
+    if (tune_lookup(s->opt.tune_cache, key, cached)) {
+        s->model->tuned_rows = cached[0];
+        s->model->tuned_groups = cached[1];
+        s->model->tuned_sweeps = cached[2];
+        info.tile_rows = cached[0];
+        info.tile_groups = cached[1];
+        info.sweeps_per_launch = cached[2];
+        info.from_cache = 1;
+        if (out) *out = info;
+        return TL_OK;
+    }
+    // candidates: the automatic shape first, then heights x widths x sweeps
+    struct Cand {
+        uint32_t rows, groups, sweeps;
+    };
+    std::vector<Cand> cands{{0u, 0u, 0u}};
+    const uint32_t ng = s->model->row_groups();
+    std::vector<uint32_t> widths{ng <= 8u ? ng : 8u};
+    if (ng > 4u) widths.push_back(4u);
+    if (ng > 2u) widths.push_back(2u);
+    const bool domino = !s->model->height_family();
+    const std::vector<uint32_t> rows = domino ? std::vector<uint32_t>{16u, 24u, 32u, 48u}
+                                              : std::vector<uint32_t>{4u, 8u, 16u, 32u};
+    const std::vector<uint32_t> sweeps = domino ? std::vector<uint32_t>{12u, 25u} : std::vector<uint32_t>{4u, 6u, 8u, 16u};
+    for (uint32_t r : rows)
+        for (uint32_t g : widths)
+            for (uint32_t sw : sweeps) cands.push_back(Cand{r, g, sw});
+    // probe on a copy of the state, from the sampler's sweep counter
+    std::unique_ptr<tl::Model> probe = s->model->twin();
+    hipError_t e = probe->allocate();
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(const_cast<uint32_t *>(probe->state()), s->model->state(),
+                           s->model->state_words() * sizeof(uint32_t), hipMemcpyDeviceToDevice, s->stream);
+    tl_options popt = s->opt;
+    popt.tile_rows = popt.tile_groups = popt.sweeps_per_launch = 0;
+    popt.kernel = 2;
+    const uint32_t t0 = (uint32_t)s->t;
+    float best = -1.0f;
+    Cand pick{0u, 0u, 0u};
+    for (const Cand &c : cands) {
+        if (e != hipSuccess) break;
+        probe->tuned_rows = c.rows;
+        probe->tuned_groups = c.groups;
+        probe->tuned_sweeps = c.sweeps;
+        hipError_t pe = probe->sweeps(t0, probe_sweeps, T, metro, s->seed, popt, s->stream);   // warm-up
+        if (pe == hipErrorInvalidConfiguration) {   // no launch plan for this shape
+            (void)hipGetLastError();
+            continue;
+        }
+        if (pe == hipSuccess) pe = hipEventRecord(e0, s->stream);
+        if (pe == hipSuccess) pe = probe->sweeps(t0, probe_sweeps, T, metro, s->seed, popt, s->stream);
+        if (pe == hipSuccess) pe = hipEventRecord(e1, s->stream);
+        if (pe == hipSuccess) pe = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (pe == hipSuccess) pe = hipEventElapsedTime(&ms, e0, e1);
+        if (pe != hipSuccess) {
+            e = pe;
+            break;
+        }
+        ++info.candidates;
+        if (best < 0.0f || ms < best) {
+            best = ms;
+            pick = c;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    probe->release();
+    if (e != hipSuccess)
+        return fail(e == hipErrorOutOfMemory ? TL_ENOMEM : TL_EDEVICE, "autotune: %s", hipGetErrorString(e));
+    if (info.candidates == 0) return fail(TL_EINVAL, "no tile shape has a launch plan for this domain");
+    s->model->tuned_rows = pick.rows;
+    s->model->tuned_groups = pick.groups;
+    s->model->tuned_sweeps = pick.sweeps;
+    info.tile_rows = pick.rows;
+    info.tile_groups = pick.groups;
+    info.sweeps_per_launch = pick.sweeps;
+    info.ms_per_sweep = best / (float)probe_sweeps;
+    if (s->opt.tune_cache) {
+        FILE *f = std::fopen(s->opt.tune_cache, "a");
+        if (!f) return fail(TL_EINVAL, "cannot append to the tune cache %s", s->opt.tune_cache);
+        std::fprintf(f, "%s %u %u %u\n", key.c_str(), pick.rows, pick.groups, pick.sweeps);
+        std::fclose(f);
+    }
+    if (out) *out = info;
     return TL_OK;
 }
 

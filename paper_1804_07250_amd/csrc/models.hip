@@ -28,6 +28,9 @@ public:
     {
         std::unique_ptr<Model> m(region_ ? new DominoModel(region_) : new DominoModel(d_.n));
         m->order = order;
+        m->tuned_rows = tuned_rows;
+        m->tuned_groups = tuned_groups;
+        m->tuned_sweeps = tuned_sweeps;
         return m;
     }
     hipError_t allocate() override
@@ -50,6 +53,7 @@ public:
         timing.release();
     }
     size_t state_words() const override { return words_; }
+    uint32_t row_groups() const override { return d_.ng; }
     void attach(uint32_t *state, uint32_t *spare) override
     {
         d_.planes = state;
@@ -102,6 +106,11 @@ public:
             return hipSuccess;
         }
         DominoTile tile = domino_auto_tile(d_.n);
+        if (tuned_rows) {
+            tile.TR = tuned_rows;
+            tile.TG = tuned_groups;
+            tile.S = tuned_sweeps;
+        }
         if (opt.tile_rows) tile.TR = opt.tile_rows;
         if (opt.tile_groups) tile.TG = opt.tile_groups;
         if (opt.sweeps_per_launch) tile.S = opt.sweeps_per_launch;
@@ -254,6 +263,9 @@ public:
     {
         std::unique_ptr<Model> m(region_ ? new HeightModel(region_) : new HeightModel(dom_));
         m->order = order;
+        m->tuned_rows = tuned_rows;
+        m->tuned_groups = tuned_groups;
+        m->tuned_sweeps = tuned_sweeps;
         m->set_boundary_table(free_thr_);
         return m;
     }
@@ -339,6 +351,7 @@ public:
         HeightDev d = d_;
         return height_words(d);
     }
+    uint32_t row_groups() const override { return d_.ng; }
     void attach(uint32_t *state, uint32_t *spare) override
     {
         d_.planes = state;
@@ -455,6 +468,11 @@ public:
             return hipSuccess;
         }
         HeightTile tile = height_auto_tile(d_, K.uniform());
+        if (tuned_rows) {
+            tile.TR = tuned_rows;
+            tile.TG = tuned_groups;
+            tile.S = tuned_sweeps;
+        }
         if (opt.tile_rows) tile.TR = opt.tile_rows;
         if (opt.tile_groups) tile.TG = opt.tile_groups;
         if (opt.sweeps_per_launch) tile.S = opt.sweeps_per_launch;

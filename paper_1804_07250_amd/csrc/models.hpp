@@ -58,6 +58,11 @@ public:
     // 1 = a random colour per step (step s = K t + i draws its colour and uses
     // sweep counter s for its site draws).
     uint32_t order = 0;
+    // Tile shape for sweeps whose options leave it automatic (0 = the
+    // automatic shape), as picked by the autotuner.
+    uint32_t tuned_rows = 0, tuned_groups = 0, tuned_sweeps = 0;
+    // Groups of 128 sites per state row (the tile-width unit).
+    virtual uint32_t row_groups() const = 0;
 };
 
 // nullptr on error, with why set and *status (nullable) the error code:
