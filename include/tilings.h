@@ -306,8 +306,12 @@ tl_status tl_sampler_thresholds(const tl_sampler *s, uint32_t *out, uint32_t cap
  * *out (nullable) reports R, the 2^R sweeps of the final round and the sweeps
  * run over all rounds and both chains.  If the chains have not met at
  * max_log2 (1..31), TL_EBUSY; the sampler then holds the minimal chain at time
- * 0 of the last round.  Allocates a second state for the maximal chain while
- * it runs; synchronous. */
+ * 0 of the last round.  A state that fits one work-group runs up to three
+ * consecutive rounds side by side (each with its own two chains, on the
+ * sampler's stream and two more), judged in order of R, so the answer is the
+ * same as with one round after the other; total_sweeps counts the rounds up
+ * to R only.  Larger states run the rounds one after the other with a second
+ * state for the maximal chain.  Synchronous. */
 typedef struct {
     uint32_t log2_sweeps;   /* R of the round whose chains met */
     uint64_t sweeps;        /* 2^R */

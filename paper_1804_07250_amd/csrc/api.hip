@@ -5,7 +5,10 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <chrono>
 #include <cstdio>
+#include <deque>
+#include <thread>
 
 #include <memory>
 #include <string>
@@ -233,6 +236,211 @@ __global__ void __launch_bounds__(256) words_differ_kernel(const uint32_t *a, co
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) acc |= a[i] ^ b[i];
     if (acc) atomicOr(flag, 1u);
+}
+
+// Coupling from the past with rounds side by side (one-tile states).  Round R
+// is the same computation as in the sequential doubling (both chains over the
+// counters [2^(R-1), 2^R), ..., [1, 2), [0, 1)); up to kRounds rounds run at
+// once, each on its own stream (the sampler's and two more, so that every
+// round has a hardware queue of its own under the default four) with its own
+// two chains, issued in pieces of at most kPiece sweeps with at most kRing
+// pieces in flight, so that a round made unnecessary by a smaller round that
+// met stops after its current pieces.  Rounds are judged in order of R: the
+// answer is the smallest R whose chains meet, exactly as when the rounds run
+// one after the other.
+struct CftpRound {
+    static constexpr uint32_t kRing = 2;
+    uint32_t R = 0;
+    std::unique_ptr<tl::Model> bot, top;
+    hipStream_t st = nullptr;
+    bool own_stream = false;
+    uint32_t *d_flag = nullptr, *h_flag = nullptr;
+    tl::TileJob *h_jobs = nullptr, *d_jobs = nullptr;   // kRing x 2 descriptors
+    hipEvent_t ring[kRing] = {};
+    bool ring_used[kRing] = {};   // a piece has been recorded on ring[i]
+    hipEvent_t done = nullptr;
+    uint32_t slot = 0;
+    std::vector<std::pair<uint32_t, uint32_t>> pieces;   // (first sweep counter, sweeps)
+    size_t next = 0;
+    bool checked = false;
+
+    hipError_t setup(const tl::Model &m, hipStream_t shared)
+    {
+        bot = m.twin();
+        top = m.twin();
+        hipError_t e = bot->allocate();
+        if (e == hipSuccess) e = top->allocate();
+        if (shared) {
+            st = shared;
+        } else if (e == hipSuccess) {
+            e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+            own_stream = e == hipSuccess;
+        }
+        if (e == hipSuccess) e = hipMalloc(&d_flag, sizeof(uint32_t));
+        if (e == hipSuccess) e = hipHostMalloc((void **)&h_flag, sizeof(uint32_t), hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&h_jobs, 2 * kRing * sizeof(tl::TileJob), hipHostMallocDefault);
+        if (e == hipSuccess) e = hipMalloc(&d_jobs, 2 * kRing * sizeof(tl::TileJob));
+        for (uint32_t i = 0; i < kRing && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&ring[i], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+        return e;
+    }
+    void teardown()
+    {
+        if (st) (void)hipStreamSynchronize(st);
+        if (bot) bot->release();
+        if (top) top->release();
+        for (hipEvent_t &ev : ring)
+            if (ev) (void)hipEventDestroy(ev);
+        if (done) (void)hipEventDestroy(done);
+        if (d_jobs) (void)hipFree(d_jobs);
+        if (h_jobs) (void)hipHostFree(h_jobs);
+        if (h_flag) (void)hipHostFree(h_flag);
+        if (d_flag) (void)hipFree(d_flag);
+        if (own_stream) (void)hipStreamDestroy(st);
+    }
+    hipError_t start(uint32_t r_log2, uint32_t piece)
+    {
+        R = r_log2;
+        next = 0;
+        checked = false;
+        pieces.clear();
+        for (int r = (int)R; r >= 0; --r) {
+            const uint32_t t0 = r ? 1u << (r - 1) : 0u, count = r ? 1u << (r - 1) : 1u;
+            for (uint32_t k = 0; k < count; k += piece) pieces.emplace_back(t0 + k, std::min(piece, count - k));
+        }
+        hipError_t e = bot->init(false, st);
+        if (e == hipSuccess) e = top->init(true, st);
+        return e;
+    }
+};
+
+hipError_t cftp_issue_piece(CftpRound &rd, const tl::Thr &T, uint64_t seed, const tl::TileItem *d_items)
+{
+    const uint32_t sl = rd.slot % CftpRound::kRing;
+    const auto pc = rd.pieces[rd.next];
+    tl::TilePlan pb, pt;
+    tl::TileJob *hj = rd.h_jobs + 2 * sl;
+    if (!rd.bot->tile_job(pc.first, pc.second, T, false, seed, &hj[0], &pb) ||
+        !rd.top->tile_job(pc.first, pc.second, T, false, seed, &hj[1], &pt) || pb.S != pc.second ||
+        pb.tiles() != 1 || pt.tiles() != 1)
+        return hipErrorInvalidConfiguration;
+    hipError_t e = hipMemcpyAsync(rd.d_jobs + 2 * sl, hj, 2 * sizeof(tl::TileJob), hipMemcpyHostToDevice, rd.st);
+    if (e == hipSuccess)
+        e = rd.bot->height_family()
+                ? tl::height_items(rd.d_jobs + 2 * sl, d_items, 2, std::max(pb.threads, pt.threads),
+                                   std::max(pb.lds, pt.lds), hj[0].mode, hj[0].kind, pb.order, hj[0].site != nullptr,
+                                   rd.st)
+                : tl::domino_items(rd.d_jobs + 2 * sl, d_items, 2, std::max(pb.threads, pt.threads),
+                                   std::max(pb.lds, pt.lds), pb.order, rd.st);
+    if (e == hipSuccess) e = hipEventRecord(rd.ring[sl], rd.st);
+    if (e == hipSuccess) {
+        rd.ring_used[sl] = true;
+        rd.bot->swap_buffers();
+        rd.top->swap_buffers();
+        ++rd.slot;
+        ++rd.next;
+    }
+    return e;
+}
+
+hipError_t cftp_queue_check(CftpRound &rd)
+{
+    const size_t words = rd.bot->state_words();
+    hipError_t e = hipMemsetAsync(rd.d_flag, 0, sizeof(uint32_t), rd.st);
+    if (e == hipSuccess) {
+        size_t blocks = (words + 255) / 256;
+        if (blocks > 2048) blocks = 2048;
+        hipLaunchKernelGGL(words_differ_kernel, dim3((uint32_t)blocks), dim3(256), 0, rd.st, rd.bot->state(),
+                           rd.top->state(), words, rd.d_flag);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(rd.h_flag, rd.d_flag, sizeof(uint32_t), hipMemcpyDeviceToHost, rd.st);
+    if (e == hipSuccess) e = hipEventRecord(rd.done, rd.st);
+    if (e == hipSuccess) rd.checked = true;
+    return e;
+}
+
+// Runs the rounds; on return *R_out is the round whose chains met (*met) or
+// the last round, and the sampler's state holds that round's minimal chain.
+hipError_t cftp_side_by_side(tl_sampler *s, uint32_t max_log2, const tl::Thr &T, uint32_t *R_out, bool *met)
+{
+    constexpr uint32_t kRounds = 3, kPiece = 512;
+    std::vector<std::unique_ptr<CftpRound>> all;
+    std::deque<CftpRound *> active, idle;
+    tl::TileItem *d_items = nullptr;
+    const tl::TileItem items[2] = {{0u, 0u}, {1u, 0u}};
+    hipError_t e = hipMalloc(&d_items, sizeof(items));
+    if (e == hipSuccess) e = hipMemcpy(d_items, items, sizeof(items), hipMemcpyHostToDevice);
+    for (uint32_t i = 0; i < std::min(kRounds, max_log2) && e == hipSuccess; ++i) {
+        all.emplace_back(new CftpRound());
+        e = all.back()->setup(*s->model, i == 0 ? s->stream : nullptr);
+        idle.push_back(all.back().get());
+    }
+    uint32_t next_R = 1;
+    CftpRound *answer = nullptr;
+    *met = false;
+    while (e == hipSuccess && !answer) {
+        while (!idle.empty() && next_R <= max_log2 && e == hipSuccess) {
+            CftpRound *rd = idle.front();
+            idle.pop_front();
+            e = rd->start(next_R++, kPiece);
+            active.push_back(rd);
+        }
+        bool progress = false;
+        for (CftpRound *rd : active) {
+            while (e == hipSuccess && rd->next < rd->pieces.size()) {
+                // the ring slot is free once the piece that last used it has run
+                const uint32_t sl = rd->slot % CftpRound::kRing;
+                if (rd->ring_used[sl]) {
+                    const hipError_t q = hipEventQuery(rd->ring[sl]);
+                    if (q == hipErrorNotReady) break;
+                    if (q != hipSuccess) {
+                        e = q;
+                        break;
+                    }
+                }
+                e = cftp_issue_piece(*rd, T, s->seed, d_items);
+                progress = true;
+            }
+            if (e == hipSuccess && rd->next == rd->pieces.size() && !rd->checked) {
+                e = cftp_queue_check(*rd);
+                progress = true;
+            }
+        }
+        if (e != hipSuccess) break;
+        if (active.empty()) {
+            e = hipErrorUnknown;
+            break;
+        }
+        CftpRound *front = active.front();
+        if (front->checked) {
+            const hipError_t q = hipEventQuery(front->done);
+            if (q == hipSuccess) {
+                if (*front->h_flag == 0u || front->R == max_log2) {
+                    *met = *front->h_flag == 0u;
+                    answer = front;
+                } else {
+                    active.pop_front();
+                    idle.push_back(front);
+                }
+                progress = true;
+            } else if (q != hipErrorNotReady) {
+                e = q;
+            }
+        }
+        if (!progress) std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+    if (e == hipSuccess && answer) {
+        *R_out = answer->R;
+        e = hipStreamSynchronize(answer->st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(const_cast<uint32_t *>(s->model->state()), answer->bot->state(),
+                               s->model->state_words() * sizeof(uint32_t), hipMemcpyDeviceToDevice, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    }
+    for (auto &rd : all) rd->teardown();   // waits for the rounds still running
+    if (d_items) (void)hipFree(d_items);
+    return e;
 }
 
 tl_status enqueue_sample(tl_sampler *s)
@@ -715,6 +923,36 @@ tl_status tl_sampler_cftp(tl_sampler *s, uint32_t max_log2, tl_cftp_info *out)
                 if (!(m >> k & 1u) && s->thr_free[m] > s->thr_free[m | (1u << k)])
                     return fail(TL_EINVAL, "coupling from the past needs free-edge weights that keep the "
                                            "height order");
+    }
+    {
+        // a state that is one tile: the rounds run side by side
+        const tl::Thr T1 = table_of(s);
+        tl::TileJob j1;
+        tl::TilePlan p1;
+        if (s->opt.kernel == 0 && s->opt.tile_rows == 0 && s->opt.tile_groups == 0 &&
+            s->opt.sweeps_per_launch == 0 && s->model->tile_job(0, 1, T1, false, s->seed, &j1, &p1) &&
+            p1.tiles() == 1) {
+            uint32_t Rm = 0;
+            bool met = false;
+            TL_HIP(hipStreamSynchronize(s->stream));
+            const hipError_t ce = cftp_side_by_side(s, max_log2, T1, &Rm, &met);
+            if (ce != hipSuccess)
+                return fail(ce == hipErrorOutOfMemory ? TL_ENOMEM : TL_EDEVICE, "coupling from the past: %s",
+                            hipGetErrorString(ce));
+            uint64_t total = 0;
+            for (uint32_t r = 1; r <= Rm; ++r) total += 2ull << r;
+            s->t = 1ull << Rm;
+            s->samples = 0;
+            const size_t nb = (size_t)s->bins_x * s->bins_y;
+            TL_HIP(hipMemsetAsync(s->bin_sum, 0, nb * sizeof(unsigned long long), s->stream));
+            if (out) {
+                out->log2_sweeps = Rm;
+                out->sweeps = 1ull << Rm;
+                out->total_sweeps = total;
+            }
+            if (!met) return fail(TL_EBUSY, "the chains have not met within 2^%u sweeps", max_log2);
+            return TL_OK;
+        }
     }
     std::unique_ptr<tl::Model> top = s->model->twin();
     hipError_t e = top->allocate();
