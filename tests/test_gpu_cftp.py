@@ -112,3 +112,27 @@ def test_cftp_rejects_non_monotone_settings():
         with pytest.raises(tl.TlError) as e:
             s.cftp(bad)
         assert e.value.status == tl.TL_EINVAL
+
+
+@pytest.mark.parametrize("model", ["domino", "sixv", "lozenge"])
+def test_rounds_side_by_side_equal_rounds_in_turn(model):
+    # One-tile states run consecutive rounds side by side; a tile option
+    # forces the rounds one after the other: R, the sample and the reported
+    # sweeps must agree.
+    tl = need_gpu()
+    say("cftp side by side vs in turn: %s" % model)
+    if model == "domino":
+        dom, w = tl.domain(tl.TL_DOMINO, n=20), tl.weights(tl.TL_W_TWO_PERIODIC, 1.0, 0.5)
+    elif model == "sixv":
+        dom, w = tl.domain(tl.TL_SIXVERTEX, n=24), tl.weights(tl.TL_W_SIXVERTEX, 1.0, 1.0, 2.0)
+    else:
+        dom, w = tl.domain(tl.TL_LOZENGE, a=8, b=9, c=7), tl.weights(tl.TL_W_VOLUME, 2.0, 3.0)
+    for seed in (11, 12, 13):
+        a = tl.Sampler(dom, w, seed)
+        b = tl.Sampler(dom, w, seed, tl.options(kernel=2, sweeps_per_launch=64))
+        ia, ib = a.cftp(24), b.cftp(24)
+        assert ia == ib
+        assert (a.export() == b.export()).all()
+        a.sweep(3)
+        b.sweep(3)
+        assert (a.export() == b.export()).all()       # both continue from counter 2^R
