@@ -115,6 +115,15 @@ __device__ __forceinline__ void decide128(uint32_t key0, uint32_t key1, uint32_t
     for (int w = 0; w < 4; ++w) D[w] = lt[w];
 }
 
+// Tile of work-group b of n in an XCD-aware order: work-groups are dispatched
+// to the 8 XCDs in turn (b mod 8), so when n is a multiple of 8, XCD x takes
+// the contiguous tile range [x n / 8, (x + 1) n / 8) and neighbouring tiles,
+// whose halos overlap, share that XCD's L2.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t n)
+{
+    return (n & 7u) ? b : (b & 7u) * (n >> 3) + (b >> 3);
+}
+
 // Adds the per-cell quantity q of the calling thread to bin (X / B, Y / B).
 // Launch shape: 16 x 16 threads per block over a 16 x 16 tile of cells.  When
 // B is a multiple of 16 the whole tile falls in one bin and is reduced in the

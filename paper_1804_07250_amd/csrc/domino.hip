@@ -373,8 +373,9 @@ __global__ void __launch_bounds__(1024) domino_tiled_kernel(const uint32_t *__re
                                                             Thr Tall, uint32_t key0, uint32_t key1)
 {
     extern __shared__ uint32_t lds[];
-    domino_tile<MODE, RANDOM>(lds, in, out, PS, RS, ng, n, omega, t0, nsweeps, TR, TG, HR, HG, blockIdx.x / tiles_x,
-                              blockIdx.x % tiles_x, Tall, key0, key1);
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    domino_tile<MODE, RANDOM>(lds, in, out, PS, RS, ng, n, omega, t0, nsweeps, TR, TG, HR, HG, tile / tiles_x,
+                              tile % tiles_x, Tall, key0, key1);
 }
 
 // Multi-job kernel: work-group b runs tile items[b].tile of job items[b].job,
