@@ -116,12 +116,16 @@ __device__ __forceinline__ void decide128(uint32_t key0, uint32_t key1, uint32_t
 }
 
 // Tile of work-group b of n in an XCD-aware order: work-groups are dispatched
-// to the 8 XCDs in turn (b mod 8), so when n is a multiple of 8, XCD x takes
-// the contiguous tile range [x n / 8, (x + 1) n / 8) and neighbouring tiles,
-// whose halos overlap, share that XCD's L2.
+// to the 8 XCDs in turn (b mod 8), and XCD x, which receives ceil((n - x) / 8)
+// of them, takes the next contiguous range of tiles, so that neighbouring
+// tiles, whose halos overlap, share that XCD's L2.  A permutation of 0..n-1.
+// It suits tiles of equal work (each XCD gets a contiguous band of them).
 __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t n)
 {
-    return (n & 7u) ? b : (b & 7u) * (n >> 3) + (b >> 3);
+    const uint32_t x = b & 7u;
+    uint32_t first = 0;
+    for (uint32_t y = 0; y < x; ++y) first += (n + 7u - y) >> 3;
+    return first + (b >> 3);
 }
 
 // Adds the per-cell quantity q of the calling thread to bin (X / B, Y / B).

@@ -503,9 +503,10 @@ __global__ void __launch_bounds__(kHeightThreads) height_tiled_kernel(const uint
                                                             uint32_t k0, uint32_t k1)
 {
     extern __shared__ uint32_t lds[];
-    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    // plain work-group order: tiles of a hexagon differ in work, and the
+    // round-robin dispatch over the XCDs balances them
     height_tile<MODE, KIND, RANDOM, MASKED>(lds, in, out, PS, RS, ng, rows, P, geo, t0, nsweeps, TR, TG, HR, HG,
-                                            tile / tiles_x, tile % tiles_x, T, k0, k1);
+                                            blockIdx.x / tiles_x, blockIdx.x % tiles_x, T, k0, k1);
 }
 
 // Multi-job kernel: work-group b runs tile items[b].tile of job items[b].job,
