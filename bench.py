@@ -287,6 +287,17 @@ def lds_roofline(rec, avg_launch_s):
                                         max(1.0, rec["lds_active_cycles_per_launch"]), 4)}
 
 
+def valu_summary(rec, avg_launch_s):
+    """VALU use of a launch from rocprofv3 SQ counters: the share of SIMD cycles
+    issuing VALU work (SQ_ACTIVE_INST_VALU over 256 CUs x 2.4 GHz x the live
+    launch time) and the share of lanes active in it (SQ_THREAD_CYCLES_VALU /
+    (SQ_ACTIVE_INST_VALU x 64))."""
+    if not rec or "valu_active_per_launch" not in rec or avg_launch_s <= 0:
+        return None
+    return {"busy_frac": round(rec["valu_active_per_launch"] / (256 * 2.4e9 * avg_launch_s), 4),
+            "lane_util": rec["valu_lane_util"]}
+
+
 def cpu_baseline(wl, budget_s):
     """The serial oracle on the same workload from its start, for a bounded
     number of sweeps (about budget_s seconds)."""
@@ -381,7 +392,7 @@ def main():
             "traffic": rec["bytes_per_launch"] if rec else None,
             "kernel": kname, "avg_launch_us": round(avg_ms * 1e3, 3), "launches": launches,
             "algorithmic_bytes_per_launch": bytes_per_launch,
-            "lds": lds_roofline(rec, avg_ms * 1e-3)}
+            "lds": lds_roofline(rec, avg_ms * 1e-3), "valu": valu_summary(rec, avg_ms * 1e-3)}
     out = {"metric": "site-updates/sec on 1 MI355X (plain vs batched vs served p50/p99), bit-exact",
            "value": value, "unit": "site-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": el / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
