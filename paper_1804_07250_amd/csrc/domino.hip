@@ -286,7 +286,8 @@ __global__ void __launch_bounds__(256) domino_other_step(uint32_t *planes, size_
 
 // -------------------------------------------------------------- tiled kernel
 // Block = one tile.  Local (lr, lg) is global row R0 + lr, group G0 + lg.  LDS:
-// 4 planes x LR rows x LRS words (LRS = 4*LG + 4: one zero pad group per row).
+// 4 planes x LR rows x LRS words (LRS = domino_lds_row_words(LG): the LG groups, the neighbouring group
+// the shifted planes read, and an odd slot count).
 // One thread per (row, group) task; blockDim >= LR * LG.
 // One tile of the multi-sweep kernel: TR owner rows x TG groups (tile index
 // (tile_r, tile_g)) plus HR halo rows and HG halo groups on each side are
@@ -297,7 +298,9 @@ __global__ void __launch_bounds__(256) domino_other_step(uint32_t *planes, size_
 // colour order (RANDOM) step q of the launch (2 per sweep) draws its colour
 // and computes rows [q, LR - q), the halo covering 2 rows per sweep.  The block
 // has a thread per (row, group) task (blockDim >= LR * LG, as every launch
-// plan gives): thread tid handles group tid % LG of row base + tid / LG.
+// plan gives): thread tid handles group tid / LR of row base + tid % LR, so
+// the 16 lanes an LDS access serves at once are 16 rows of one group, which
+// the odd row stride spreads over distinct banks.
 template <int MODE, bool RANDOM>
 __device__ __forceinline__ void domino_tile(uint32_t *lds, const uint32_t *__restrict__ in,
                                             uint32_t *__restrict__ out, size_t PS, uint32_t RS, uint32_t ng,
@@ -305,7 +308,7 @@ __device__ __forceinline__ void domino_tile(uint32_t *lds, const uint32_t *__res
                                             uint32_t TG, uint32_t HR, uint32_t HG, uint32_t tile_r, uint32_t tile_g,
                                             const Thr &Tall, uint32_t key0, uint32_t key1)
 {
-    const uint32_t LR = TR + 2 * HR, LG = TG + 2 * HG, LRS = 4 * LG + 4;
+    const uint32_t LR = TR + 2 * HR, LG = TG + 2 * HG, LRS = domino_lds_row_words(LG);
     const uint32_t LPS = LR * LRS;
     const int R0 = (int)(tile_r * TR) - (int)HR, G0 = (int)(tile_g * TG) - (int)HG;
     const uint32_t tid = threadIdx.x, nt = blockDim.x;
@@ -322,9 +325,9 @@ __device__ __forceinline__ void domino_tile(uint32_t *lds, const uint32_t *__res
     }
     __syncthreads();
 
-    const uint32_t r0 = tid / LG, lg = tid % LG;
+    const uint32_t r0 = tid % LR, lg = tid / LR;
     const int gg = G0 + (int)lg;
-    const bool lane = gg >= 0 && gg < (int)ng;
+    const bool lane = lg < LG && gg >= 0 && gg < (int)ng;
     for (uint32_t s = 0; s < nsweeps; ++s) {
         for (uint32_t i = 0; i < 2; ++i) {
             // colour, sweep counter of the draws and valid rows of this step
@@ -711,7 +714,7 @@ bool domino_plan(const DominoDev &d, const DominoTile &tile, uint32_t S_max, Til
     const uint32_t HG = tiles_x > 1 ? 1u : 0u;
     const uint32_t LR = TR + 2 * HR, LG = TG + 2 * HG;
     const uint32_t tasks = LR * LG;
-    const uint32_t lds = 4u * LR * (4u * LG + 4u) * 4u;
+    const uint32_t lds = 4u * LR * domino_lds_row_words(LG) * 4u;
     if (tasks > 1024u || lds > 160u * 1024u) return false;
     p->S = S;
     p->TR = TR;

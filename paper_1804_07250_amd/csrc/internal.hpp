@@ -120,6 +120,14 @@ struct DominoDev {
 // Tile of the multi-sweep kernel: TR owner rows x TG groups of 4 words, run for
 // up to S sweeps per launch with an S-row halo above and below and a one-group
 // halo left and right (a dimension covered by one tile needs no halo).
+// Words per LDS row of a domino tile of LG groups: the groups, one more group
+// (the neighbour the shifted planes read), rounded to an odd number of 4-word
+// slots so that 16 consecutive rows of one group fall in distinct banks.
+inline __host__ __device__ uint32_t domino_lds_row_words(uint32_t LG)
+{
+    const uint32_t slots = LG + 1u;
+    return 4u * (slots | 1u);
+}
 struct DominoTile {
     uint32_t TR = 32, TG = 4, S = 8;
     uint32_t order = 0;   // colour order: 0 fixed, 1 random per step
