@@ -337,7 +337,7 @@ def cpu_baseline(wl, budget_s):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding)",
+        print("bench.py runs on one GPU only: the library has no multi-GPU path; --gpus must be 1",
               file=sys.stderr)
         sys.exit(2)
     import torch

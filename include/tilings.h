@@ -308,7 +308,7 @@ tl_status tl_sampler_thresholds(const tl_sampler *s, uint32_t *out, uint32_t cap
  * max_log2 (1..31), TL_EBUSY; the sampler then holds the minimal chain at time
  * 0 of the last round.  A state that fits one work-group runs up to three
  * consecutive rounds side by side (each with its own two chains, on the
- * sampler's stream and two more), judged in order of R, so the answer is the
+ * sampler's stream and two more), checked in order of R, so the answer is the
  * same as with one round after the other; total_sweeps counts the rounds up
  * to R only.  Larger states run the rounds one after the other with a second
  * state for the maximal chain.  Synchronous. */

@@ -245,7 +245,7 @@ __global__ void __launch_bounds__(256) words_differ_kernel(const uint32_t *a, co
 // round has a hardware queue of its own under the default four) with its own
 // two chains, issued in pieces of at most kPiece sweeps with at most kRing
 // pieces in flight, so that a round made unnecessary by a smaller round that
-// met stops after its current pieces.  Rounds are judged in order of R: the
+// met stops after its current pieces.  Rounds are checked in order of R: the
 // answer is the smallest R whose chains meet, exactly as when the rounds run
 // one after the other.
 struct CftpRound {
