@@ -1,0 +1,171 @@
+"""Counter records for the roofline figures of bench.py.
+
+Reads the CSV output of rocprofv3 ``--pmc`` runs (``counter_collection.csv``
+under each run's ``-d`` folder) and writes ``profiles/<name>_traffic.json``:
+HBM bytes per launch of one kernel from FETCH_SIZE and WRITE_SIZE, each scaled
+by what the same counter reads for a device copy of known size, LDS bytes and
+busy / bank-conflict cycles from the SQ LDS counters, and VALU use from the SQ
+VALU counters.  The record carries a SHA-256 of the kernel sources it was
+measured on; bench.py ignores it once they change.
+
+    python -m paper_1804_07250_amd.counters summary DIR
+    python -m paper_1804_07250_amd.counters record NAME --kernel 'domino_tiled_kernel<2, false>' \\
+        --fetch DIR --write DIR --copy-fetch DIR --copy-write DIR --copy-mib 256 \\
+        [--lds DIR] [--valu DIR] [--sources domino.hip device_common.hpp]
+
+Each DIR is the output folder of one rocprofv3 run (one counter block per run:
+FETCH_SIZE and WRITE_SIZE cannot share a pass).  The copy runs profile
+``bench.py --copy-calibration MIB``, whose copies the runtime issues as
+``__amd_rocclr_copyBuffer``.
+"""
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import statistics
+import sys
+from collections import defaultdict
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+LDS_COUNTERS = ("SQ_INSTS_LDS_LOAD_BANDWIDTH", "SQ_INSTS_LDS_STORE_BANDWIDTH", "SQ_INSTS_LDS_ATOMIC_BANDWIDTH",
+                "SQ_LDS_BANK_CONFLICT", "SQ_LDS_IDX_ACTIVE")
+VALU_COUNTERS = ("SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_THREAD_CYCLES_VALU")
+
+
+def kernel_label(name):
+    """A kernel's name without its return type, namespaces and parameter list
+    (template arguments kept): 'domino_tiled_kernel<2, false>'."""
+    name = name.replace("(anonymous namespace)::", "").replace("void ", "").replace("tl::", "").strip()
+    depth = 0
+    for i, ch in enumerate(name):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            return name[:i].strip()
+    return name
+
+
+def _col(row, *names):
+    for n in names:
+        if n in row:
+            return row[n]
+    raise KeyError("none of the columns %s in the counter CSV" % (names,))
+
+
+def counter_values(folder):
+    """{(kernel label, counter): [value per dispatch]} over every
+    counter_collection.csv under folder."""
+    files = sorted(glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True))
+    if not files:
+        raise FileNotFoundError("no counter_collection.csv under %s" % folder)
+    out = defaultdict(list)
+    for f in files:
+        with open(f, newline="") as fh:
+            for r in csv.DictReader(fh):
+                out[(kernel_label(_col(r, "Kernel_Name", "KERNEL_NAME")), _col(r, "Counter_Name", "COUNTER_NAME"))] \
+                    .append(float(_col(r, "Counter_Value", "COUNTER_VALUE")))
+    return out
+
+
+def mean_of(values, kernel, counter):
+    v = values.get((kernel, counter))
+    if not v:
+        raise KeyError("no %s for kernel %s" % (counter, kernel))
+    return statistics.fmean(v), len(v)
+
+
+def sources_sha256(sources):
+    h = hashlib.sha256()
+    for s in sources:
+        with open(os.path.join(PKG, "csrc", s), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def make_record(kernel, fetch, write, copy_fetch, copy_write, copy_mib, sources, lds=None, valu=None, base=None):
+    """The record as a dict.  fetch / write / copy_* / lds / valu are the
+    counter_values() of the corresponding runs; base supplies the fields kept
+    from an existing record (workload, commands)."""
+    rec = dict(base or {})
+    rec["kernel"] = kernel
+    rec["sources"] = list(sources)
+    rec["sources_sha256"] = sources_sha256(sources)
+    f, launches = mean_of(fetch, kernel, "FETCH_SIZE")
+    w, _ = mean_of(write, kernel, "WRITE_SIZE")
+    copy_kib = copy_mib * 1024.0
+    fs = copy_kib / mean_of(copy_fetch, COPY_KERNEL, "FETCH_SIZE")[0]
+    ws = copy_kib / mean_of(copy_write, COPY_KERNEL, "WRITE_SIZE")[0]
+    rec["bytes_per_launch"] = int(round(f * 1024 * fs + w * 1024 * ws))
+    rec["fetch_kib_per_launch_raw"] = round(f, 1)
+    rec["write_kib_per_launch_raw"] = round(w, 1)
+    rec["fetch_scale"] = round(fs, 5)
+    rec["write_scale"] = round(ws, 5)
+    rec["launches_profiled"] = launches
+    if lds is not None:
+        raw = {c: round(mean_of(lds, kernel, c)[0], 1) for c in LDS_COUNTERS}
+        rec["lds_counters_raw"] = raw
+        rec["lds_bytes_per_launch"] = int(round(64 * (raw["SQ_INSTS_LDS_LOAD_BANDWIDTH"] +
+                                                      raw["SQ_INSTS_LDS_STORE_BANDWIDTH"] +
+                                                      raw["SQ_INSTS_LDS_ATOMIC_BANDWIDTH"])))
+        rec["lds_active_cycles_per_launch"] = raw["SQ_LDS_IDX_ACTIVE"]
+        rec["lds_bank_conflict_cycles_per_launch"] = raw["SQ_LDS_BANK_CONFLICT"]
+    if valu is not None:
+        raw = {c: round(mean_of(valu, kernel, c)[0], 1) for c in VALU_COUNTERS}
+        rec["valu_counters_raw"] = raw
+        rec["valu_active_per_launch"] = raw["SQ_ACTIVE_INST_VALU"]
+        rec["valu_lane_util"] = round(raw["SQ_THREAD_CYCLES_VALU"] / (64.0 * raw["SQ_ACTIVE_INST_VALU"]), 4)
+    return rec
+
+
+def main(argv=None):
+    p = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    sub = p.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("summary", help="mean of every counter per kernel")
+    s.add_argument("folder")
+    r = sub.add_parser("record", help="write profiles/<name>_traffic.json")
+    r.add_argument("name")
+    r.add_argument("--kernel", required=True)
+    for k in ("fetch", "write", "copy-fetch", "copy-write"):
+        r.add_argument("--" + k, required=True)
+    r.add_argument("--copy-mib", type=float, required=True)
+    r.add_argument("--lds")
+    r.add_argument("--valu")
+    r.add_argument("--sources", nargs="+")
+    r.add_argument("--out", help="record path (default profiles/<name>_traffic.json, whose workload, commands\n"
+                                  "and sources a new record keeps)")
+    a = p.parse_args(argv)
+    if a.cmd == "summary":
+        for (k, c), v in sorted(counter_values(a.folder).items()):
+            print("%-60s %-30s n=%6d mean=%14.1f" % (k[:60], c, len(v), statistics.fmean(v)))
+        return 0
+    committed = os.path.join(ROOT, "profiles", a.name + "_traffic.json")
+    out = a.out or committed
+    base = {}
+    for path in (out, committed):   # fields kept from an existing record
+        if os.path.exists(path):
+            with open(path) as fh:
+                base = json.load(fh)
+            break
+    base.setdefault("workload", a.name.split("_")[-1])
+    sources = a.sources or base.get("sources")
+    if not sources:
+        p.error("--sources is needed for a new record")
+    rec = make_record(a.kernel, counter_values(a.fetch), counter_values(a.write), counter_values(a.copy_fetch),
+                      counter_values(a.copy_write), a.copy_mib, sources,
+                      counter_values(a.lds) if a.lds else None, counter_values(a.valu) if a.valu else None, base)
+    with open(out, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print("%s: %d bytes per launch%s" % (out, rec["bytes_per_launch"],
+                                         ", %d LDS bytes" % rec["lds_bytes_per_launch"] if "lds_bytes_per_launch"
+                                         in rec else ""))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,7 +1,8 @@
 """Host logic of bench.py, no GPU: the one-GPU refusal, the counter records in
 profiles/ (their derived figures follow from the raw counters they store, and
-a record stops counting once a kernel source it names changes), and the LDS and
-VALU summaries built from them."""
+a record stops counting once a kernel source it names changes), the LDS and
+VALU summaries built from them, and the tool that writes the records from
+rocprofv3 counter CSV output."""
 import hashlib
 import json
 import os
@@ -94,3 +95,52 @@ def test_lds_and_valu_summaries():
     for bad in ({}, None):
         assert bench.lds_roofline(bad, t) is None and bench.valu_summary(bad, t) is None
     assert bench.lds_roofline(rec, 0.0) is None and bench.valu_summary(rec, -1.0) is None
+
+
+def write_counters(folder, rows):
+    """A rocprofv3-style counter_collection.csv: rows of (kernel, counter, value)."""
+    d = folder / "host" / "123"
+    d.mkdir(parents=True)
+    with open(d / "123_counter_collection.csv", "w") as fh:
+        fh.write("Correlation_Id,Dispatch_Id,Agent_Id,Kernel_Name,Counter_Name,Counter_Value\n")
+        for i, (k, c, v) in enumerate(rows):
+            fh.write('%d,%d,1,"%s",%s,%r\n' % (i, i, k, c, v))
+    return str(folder)
+
+
+def test_counter_tool_builds_the_record(tmp_path):
+    from paper_1804_07250_amd import counters
+    k = "void tl::domino_tiled_kernel<2, false>(unsigned int const*, unsigned int*, unsigned long, int)"
+    assert counters.kernel_label(k) == "domino_tiled_kernel<2, false>"
+    assert counters.kernel_label("(anonymous namespace)::f<(x)>(int)") == "f<(x)>"
+    copy = "__amd_rocclr_copyBuffer"
+    fetch = write_counters(tmp_path / "f", [(k, "FETCH_SIZE", 1000.0), (k, "FETCH_SIZE", 1002.0),
+                                            ("other_kernel", "FETCH_SIZE", 5.0)])
+    write = write_counters(tmp_path / "w", [(k, "WRITE_SIZE", 500.0), (k, "WRITE_SIZE", 500.0)])
+    cf = write_counters(tmp_path / "cf", [(copy, "FETCH_SIZE", 131072.0)] * 5)
+    cw = write_counters(tmp_path / "cw", [(copy, "WRITE_SIZE", 262144.0)] * 5)
+    lds = write_counters(tmp_path / "l", [(k, c, v) for c, v in (
+        ("SQ_INSTS_LDS_LOAD_BANDWIDTH", 100.0), ("SQ_INSTS_LDS_STORE_BANDWIDTH", 20.0),
+        ("SQ_INSTS_LDS_ATOMIC_BANDWIDTH", 4.0), ("SQ_LDS_BANK_CONFLICT", 30.0), ("SQ_LDS_IDX_ACTIVE", 120.0),
+        ("SQ_INSTS_LDS", 9.0))])
+    valu = write_counters(tmp_path / "v", [(k, "SQ_INSTS_VALU", 10.0), (k, "SQ_ACTIVE_INST_VALU", 10.0),
+                                           (k, "SQ_THREAD_CYCLES_VALU", 480.0)])
+    out = tmp_path / "rec.json"
+    rc = counters.main(["record", "x_aztec9", "--kernel", "domino_tiled_kernel<2, false>", "--fetch", fetch,
+                        "--write", write, "--copy-fetch", cf, "--copy-write", cw, "--copy-mib", "256",
+                        "--lds", lds, "--valu", valu, "--sources", "domino.hip", "device_common.hpp",
+                        "--out", str(out)])
+    assert rc == 0
+    rec = json.load(open(out))
+    assert rec["launches_profiled"] == 2 and rec["fetch_scale"] == 2.0 and rec["write_scale"] == 1.0
+    assert rec["bytes_per_launch"] == (1001 * 2 + 500) * 1024
+    assert rec["lds_bytes_per_launch"] == 124 * 64
+    assert rec["lds_bank_conflict_cycles_per_launch"] == 30.0 and rec["lds_active_cycles_per_launch"] == 120.0
+    assert rec["valu_lane_util"] == 0.75 and rec["workload"] == "aztec9"
+    h = hashlib.sha256()
+    for s in ("domino.hip", "device_common.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_1804_07250_amd", "csrc", s), "rb").read())
+    assert rec["sources_sha256"] == h.hexdigest()
+    with pytest.raises(KeyError):
+        counters.make_record("missing_kernel", counters.counter_values(fetch), counters.counter_values(write),
+                             counters.counter_values(cf), counters.counter_values(cw), 256, ["domino.hip"])
