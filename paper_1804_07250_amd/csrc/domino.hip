@@ -672,7 +672,7 @@ hipError_t domino_colour_step(const DominoDev &d, int colour, uint32_t t, const 
     return launch(tm, 1, k, grid, block, 0, s, d.planes, d.PS, d.RS, d.ng, n, c, t, T, key0, key1);
 }
 
-DominoTile domino_auto_tile(int n)
+DominoTile domino_auto_tile(int n, bool random_order)
 {
     DominoTile t;
     uint32_t ng, RS;
@@ -682,6 +682,14 @@ DominoTile domino_auto_tile(int n)
         t.TR = (uint32_t)n;
         t.TG = ng;
         t.S = 1u << 30;
+        return t;
+    }
+    if (random_order) {
+        // two halo rows per sweep: taller, narrower tiles carry less halo per
+        // owned row (measured best on MI355X for order 2048: 64 rows x 2 groups)
+        t.TR = 64;
+        t.TG = ng < 2 ? ng : 2;
+        t.S = 16;
         return t;
     }
     t.TR = 32;

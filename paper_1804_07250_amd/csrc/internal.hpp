@@ -141,7 +141,7 @@ hipError_t domino_colour_step(const DominoDev &d, int colour, uint32_t t, const 
 // Sweeps t0 .. t0+n-1 with the tiled kernel; swaps d.planes / d.spare.
 hipError_t domino_tiled_sweeps(DominoDev &d, const DominoTile &tile, uint32_t t0, uint32_t n, const Thr &T,
                                int metropolis, uint64_t seed, hipStream_t s, Timing *tm = nullptr);
-DominoTile domino_auto_tile(int n);
+DominoTile domino_auto_tile(int n, bool random_order);
 hipError_t domino_export(const DominoDev &d, uint8_t *faces, hipStream_t s);
 hipError_t domino_observe(const DominoDev &d, uint32_t B, uint32_t bins_x, unsigned long long *bins,
                           hipStream_t s);

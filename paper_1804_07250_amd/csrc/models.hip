@@ -63,7 +63,7 @@ public:
     bool tile_job(uint32_t t0, uint32_t S_max, const Thr &T, bool metro, uint64_t seed, TileJob *j,
                   TilePlan *p) const override
     {
-        DominoTile tile = domino_auto_tile(d_.n);
+        DominoTile tile = domino_auto_tile(d_.n, order != 0);
         tile.S = S_max;
         tile.order = order;
         if (!domino_plan(d_, tile, S_max, p)) return false;
@@ -105,7 +105,7 @@ public:
                 }
             return hipSuccess;
         }
-        DominoTile tile = domino_auto_tile(d_.n);
+        DominoTile tile = domino_auto_tile(d_.n, order != 0);
         if (tuned_rows) {
             tile.TR = tuned_rows;
             tile.TG = tuned_groups;
