@@ -102,6 +102,9 @@ def run_batched(tl, args):
     b.sync()
     el = time.perf_counter() - t0
     kms, launches, steps = b.kernel_time()
+    # rocprofv3 counters of the same workload's full launches, if recorded for the current sources
+    rec = traffic_record("domino_batch_batched4096") if (len(orders), args.batched_sweeps) == (4096, 5000) else None
+    avg_s = kms * 1e-3 / max(1, launches)
     updates = info["sites"] * args.batched_sweeps
     h0 = b.hash(0)
     b.destroy()
@@ -112,7 +115,9 @@ def run_batched(tl, args):
             "state_bytes": info["state_bytes"], "threads": threads, "workgroups": info["workgroups"],
             "autotune_probe_ms": round(probe_ms, 3), "launch_ms": round(kms, 3),
             "roofline": {"bound": "hbm", "achieved": round(alg / (kms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": round(alg / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+                         "unit": "GB/s", "frac": round(alg / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                         "traffic": rec["bytes_per_launch"] if rec else None, "launches": launches,
+                         "lds": lds_roofline(rec, avg_s), "valu": valu_summary(rec, avg_s)},
             "chain0_hash": h0,
             "workload": "batched: %d domino chains, Aztec orders uniform in [16,512] (PCG64 seed 0x5EED), "
                         "two-periodic a=1 b=1/2, %d sweeps, seeds 0..%d, one graph-replayed persistent launch"

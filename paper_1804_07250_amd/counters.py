@@ -11,7 +11,7 @@ measured on; bench.py ignores it once they change.
     python -m paper_1804_07250_amd.counters summary DIR
     python -m paper_1804_07250_amd.counters record NAME --kernel 'domino_tiled_kernel<2, false>' \\
         --fetch DIR --write DIR --copy-fetch DIR --copy-write DIR --copy-mib 256 \\
-        [--lds DIR] [--valu DIR] [--sources domino.hip device_common.hpp]
+        [--lds DIR] [--valu DIR] [--sources domino.hip device_common.hpp] [--largest N]
 
 Each DIR is the output folder of one rocprofv3 run (one counter block per run:
 FETCH_SIZE and WRITE_SIZE cannot share a pass).  The copy runs profile
@@ -73,10 +73,17 @@ def counter_values(folder):
     return out
 
 
-def mean_of(values, kernel, counter):
+def mean_of(values, kernel, counter, largest=None):
+    """Mean of a counter over a kernel's dispatches, or over its `largest`
+    largest values (a run that also launches the kernel on small probe inputs
+    keeps only the full launches that way)."""
     v = values.get((kernel, counter))
     if not v:
         raise KeyError("no %s for kernel %s" % (counter, kernel))
+    if largest:
+        if len(v) < largest:
+            raise KeyError("%d dispatches of %s for %s, %d asked for" % (len(v), kernel, counter, largest))
+        v = sorted(v, reverse=True)[:largest]
     return statistics.fmean(v), len(v)
 
 
@@ -88,7 +95,8 @@ def sources_sha256(sources):
     return h.hexdigest()
 
 
-def make_record(kernel, fetch, write, copy_fetch, copy_write, copy_mib, sources, lds=None, valu=None, base=None):
+def make_record(kernel, fetch, write, copy_fetch, copy_write, copy_mib, sources, lds=None, valu=None, base=None,
+                largest=None):
     """The record as a dict.  fetch / write / copy_* / lds / valu are the
     counter_values() of the corresponding runs; base supplies the fields kept
     from an existing record (workload, commands)."""
@@ -96,8 +104,8 @@ def make_record(kernel, fetch, write, copy_fetch, copy_write, copy_mib, sources,
     rec["kernel"] = kernel
     rec["sources"] = list(sources)
     rec["sources_sha256"] = sources_sha256(sources)
-    f, launches = mean_of(fetch, kernel, "FETCH_SIZE")
-    w, _ = mean_of(write, kernel, "WRITE_SIZE")
+    f, launches = mean_of(fetch, kernel, "FETCH_SIZE", largest)
+    w, _ = mean_of(write, kernel, "WRITE_SIZE", largest)
     copy_kib = copy_mib * 1024.0
     fs = copy_kib / mean_of(copy_fetch, COPY_KERNEL, "FETCH_SIZE")[0]
     ws = copy_kib / mean_of(copy_write, COPY_KERNEL, "WRITE_SIZE")[0]
@@ -108,7 +116,7 @@ def make_record(kernel, fetch, write, copy_fetch, copy_write, copy_mib, sources,
     rec["write_scale"] = round(ws, 5)
     rec["launches_profiled"] = launches
     if lds is not None:
-        raw = {c: round(mean_of(lds, kernel, c)[0], 1) for c in LDS_COUNTERS}
+        raw = {c: round(mean_of(lds, kernel, c, largest)[0], 1) for c in LDS_COUNTERS}
         rec["lds_counters_raw"] = raw
         rec["lds_bytes_per_launch"] = int(round(64 * (raw["SQ_INSTS_LDS_LOAD_BANDWIDTH"] +
                                                       raw["SQ_INSTS_LDS_STORE_BANDWIDTH"] +
@@ -116,7 +124,7 @@ def make_record(kernel, fetch, write, copy_fetch, copy_write, copy_mib, sources,
         rec["lds_active_cycles_per_launch"] = raw["SQ_LDS_IDX_ACTIVE"]
         rec["lds_bank_conflict_cycles_per_launch"] = raw["SQ_LDS_BANK_CONFLICT"]
     if valu is not None:
-        raw = {c: round(mean_of(valu, kernel, c)[0], 1) for c in VALU_COUNTERS}
+        raw = {c: round(mean_of(valu, kernel, c, largest)[0], 1) for c in VALU_COUNTERS}
         rec["valu_counters_raw"] = raw
         rec["valu_active_per_launch"] = raw["SQ_ACTIVE_INST_VALU"]
         rec["valu_lane_util"] = round(raw["SQ_THREAD_CYCLES_VALU"] / (64.0 * raw["SQ_ACTIVE_INST_VALU"]), 4)
@@ -137,6 +145,7 @@ def main(argv=None):
     r.add_argument("--lds")
     r.add_argument("--valu")
     r.add_argument("--sources", nargs="+")
+    r.add_argument("--largest", type=int, help="use only the N dispatches with the largest value of each counter")
     r.add_argument("--out", help="record path (default profiles/<name>_traffic.json, whose workload, commands\n"
                                   "and sources a new record keeps)")
     a = p.parse_args(argv)
@@ -158,7 +167,8 @@ def main(argv=None):
         p.error("--sources is needed for a new record")
     rec = make_record(a.kernel, counter_values(a.fetch), counter_values(a.write), counter_values(a.copy_fetch),
                       counter_values(a.copy_write), a.copy_mib, sources,
-                      counter_values(a.lds) if a.lds else None, counter_values(a.valu) if a.valu else None, base)
+                      counter_values(a.lds) if a.lds else None, counter_values(a.valu) if a.valu else None, base,
+                      a.largest)
     with open(out, "w") as fh:
         json.dump(rec, fh, indent=1)
     print("%s: %d bytes per launch%s" % (out, rec["bytes_per_launch"],

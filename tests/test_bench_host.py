@@ -141,6 +141,12 @@ def test_counter_tool_builds_the_record(tmp_path):
     for s in ("domino.hip", "device_common.hpp"):
         h.update(open(os.path.join(ROOT, "paper_1804_07250_amd", "csrc", s), "rb").read())
     assert rec["sources_sha256"] == h.hexdigest()
+    # probe launches of the same kernel are left out with largest=N
+    probe = write_counters(tmp_path / "p", [(k, "FETCH_SIZE", 7.0), (k, "FETCH_SIZE", 1000.0), (k, "FETCH_SIZE", 3.0),
+                                            (k, "FETCH_SIZE", 1002.0)])
+    assert counters.mean_of(counters.counter_values(probe), "domino_tiled_kernel<2, false>", "FETCH_SIZE", 2) == (1001.0, 2)
+    with pytest.raises(KeyError):
+        counters.mean_of(counters.counter_values(probe), "domino_tiled_kernel<2, false>", "FETCH_SIZE", 5)
     with pytest.raises(KeyError):
         counters.make_record("missing_kernel", counters.counter_values(fetch), counters.counter_values(write),
                              counters.counter_values(cf), counters.counter_values(cw), 256, ["domino.hip"])
