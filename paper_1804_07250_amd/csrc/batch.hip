@@ -78,8 +78,9 @@ tl_status drop_graph(tl_batch *b)
 
 // Bundles for work-groups of `threads`: chains in LPT order go first-fit into
 // bundles of at most kBundleMax chains, `threads` (row, group) tasks and the
-// LDS of the largest chain; a chain with more tasks than threads is a bundle
-// alone.  Bundles are ordered by passes per colour step, then tasks.
+// LDS of the largest chain, all of one diamond parity (n + 1) & 1, so that a
+// colour step is the owner step for every chain of a bundle or for none; a
+// chain with more tasks than threads is a bundle alone.  Bundles are ordered by passes per colour step, then tasks.
 tl_status bundle_set(tl_batch *b, uint32_t threads, const tl_batch::BundleSet **out)
 {
     for (const auto &st : b->sets)
@@ -88,24 +89,25 @@ tl_status bundle_set(tl_batch *b, uint32_t threads, const tl_batch::BundleSet **
             return TL_OK;
         }
     struct Open {
-        uint32_t tasks, lds;
+        uint32_t tasks, lds, parity;
         std::vector<uint32_t> m;
     };
     std::vector<Open> open;
     for (uint32_t ci : b->order) {
         const tl::BatchChain &c = b->chains[ci];
-        const uint32_t tasks = c.n * c.ng, lds = c.lds_bytes;
+        const uint32_t tasks = c.n * c.ng, lds = c.lds_bytes, parity = (c.n + 1) & 1u;
         bool placed = false;
         if (tasks <= threads)
             for (Open &o : open)
-                if (o.tasks + tasks <= threads && o.lds + lds <= b->lds_max && o.m.size() < tl::kBundleMax) {
+                if (o.parity == parity && o.tasks + tasks <= threads && o.lds + lds <= b->lds_max &&
+                    o.m.size() < tl::kBundleMax) {
                     o.tasks += tasks;
                     o.lds += lds;
                     o.m.push_back(ci);
                     placed = true;
                     break;
                 }
-        if (!placed) open.push_back(Open{tasks, lds, {ci}});
+        if (!placed) open.push_back(Open{tasks, lds, parity, {ci}});
     }
     auto passes = [&](const Open &o) { return (o.tasks + threads - 1) / threads; };
     std::stable_sort(open.begin(), open.end(), [&](const Open &x, const Open &y) {
