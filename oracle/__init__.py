@@ -157,7 +157,10 @@ def table_from_ratios(ratios, metropolis: bool):
             out.append(_floor32(R / (1 + R)))
         else:
             out.append(_floor32(min(Fraction(1), R) / 2))
-            out.append(TWO32 - _floor32(min(Fraction(1), 1 / R) / 2))
+            f = _floor32(min(Fraction(1), 1 / R) / 2)
+            if f == 0:   # 2^32 does not fit a 32-bit table
+                raise ValueError("threshold out of range")
+            out.append(TWO32 - f)
     return out
 
 

@@ -16,6 +16,7 @@
 
 #include "../../include/tilings.h"
 #include "errors.hpp"
+#include "exact_ratio.hpp"
 #include "internal.hpp"
 #include "models.hpp"
 #include "region.hpp"
@@ -44,35 +45,6 @@ namespace {
 bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
 
 }  // namespace
-
-namespace tl {
-
-// Thresholds T = floor(2^32 p) in 80-bit extended precision from up/down weight
-// ratios R (heat-bath p = R/(1+R); lazy Metropolis pairs [down, up]).
-std::vector<uint32_t> thresholds_from_ratios(const std::vector<long double> &R, bool metropolis)
-{
-    auto fl = [](long double p) -> uint32_t {
-        long double v = floorl(ldexpl(p, 32));
-        if (v < 0) v = 0;
-        if (v > 4294967295.0L) v = 4294967295.0L;
-        return (uint32_t)v;
-    };
-    std::vector<uint32_t> out;
-    for (long double r : R) {
-        if (!metropolis) {
-            out.push_back(fl(r / (1.0L + r)));
-        } else {
-            const long double up = r < 1.0L ? r : 1.0L;
-            const long double dn = r > 1.0L ? 1.0L / r : 1.0L;
-            out.push_back(fl(up / 2.0L));
-            const uint64_t f = fl(dn / 2.0L);
-            out.push_back((uint32_t)((1ull << 32) - f));
-        }
-    }
-    return out;
-}
-
-}  // namespace tl
 
 struct tl_sampler {
     tl_domain dom{};
@@ -106,45 +78,46 @@ namespace {
 
 tl_status make_thresholds(const tl_domain &d, const tl_weights &w, std::vector<uint32_t> &thr)
 {
+    using tl::Ratio;
     const bool metro = w.rule == TL_METROPOLIS;
     if (w.rule != TL_HEATBATH && w.rule != TL_METROPOLIS) return fail(TL_EINVAL, "unknown rule %d", w.rule);
-    std::vector<long double> R;
+    std::vector<Ratio> R;
+    const Ratio one;
     switch (d.model) {
     case TL_DOMINO:
         if (w.kind == TL_W_UNIFORM) {
-            R.assign(4, 1.0L);
+            R.assign(4, one);
         } else if (w.kind == TL_W_TWO_PERIODIC) {
             if (!finite_pos(w.w[0]) || !finite_pos(w.w[1])) return fail(TL_EINVAL, "two-periodic weights must be > 0");
-            const long double a = w.w[0], b = w.w[1];
-            R = {1.0L, 1.0L, (b * b) / (a * a), (a * a) / (b * b)};
+            const Ratio b2a2 = (Ratio::of(w.w[1]) / Ratio::of(w.w[0])).pow(2);
+            R = {one, one, b2a2, b2a2.inv()};
         } else if (w.kind == TL_W_VOLUME_BW) {
-            long double q[2];
+            Ratio q[2];
             for (int i = 0; i < 2; ++i) {
                 const double num = w.w[2 * i], den = w.w[2 * i + 1];
                 if (!finite_pos(num) || (den != 0.0 && !finite_pos(den)))
                     return fail(TL_EINVAL, "volume weights must be > 0");
-                q[i] = den > 0.0 ? (long double)num / (long double)den : (long double)num;
+                q[i] = den > 0.0 ? Ratio::of(num) / Ratio::of(den) : Ratio::of(num);
             }
-            const long double qb4 = q[0] * q[0] * q[0] * q[0], qw4 = q[1] * q[1] * q[1] * q[1];
             // vertical raises the height by 4 at black (x+y even) vertices, lowers it at white ones
-            R = {qb4, qb4, 1.0L / qw4, 1.0L / qw4};
+            R = {q[0].pow(4), q[0].pow(4), q[1].pow(-4), q[1].pow(-4)};
         } else {
             return fail(TL_EINVAL, "weight kind %d does not apply to dominoes", w.kind);
         }
         break;
     case TL_LOZENGE:
         if (w.kind == TL_W_UNIFORM) {
-            R = {1.0L};
+            R = {one};
         } else if (w.kind == TL_W_VOLUME) {
             if (!finite_pos(w.w[0])) return fail(TL_EINVAL, "volume weight q must be > 0");
             if (w.w[1] != 0.0 && !finite_pos(w.w[1])) return fail(TL_EINVAL, "volume weight denominator must be > 0");
-            R = {w.w[1] > 0.0 ? (long double)w.w[0] / (long double)w.w[1] : (long double)w.w[0]};
+            R = {w.w[1] > 0.0 ? Ratio::of(w.w[0]) / Ratio::of(w.w[1]) : Ratio::of(w.w[0])};
         } else {
             return fail(TL_EINVAL, "weight kind %d does not apply to lozenges", w.kind);
         }
         break;
     case TL_SIXVERTEX: {
-        long double a2 = 1, b2 = 1, c2 = 1;
+        Ratio a2, b2, c2;
         if (w.kind == TL_W_SIXVERTEX6) {
             // With the boundary fixed, each corner of a flipped face moves
             // between two types whose weights multiply to a1 a2, b1 b2 or
@@ -152,15 +125,15 @@ tl_status make_thresholds(const tl_domain &d, const tl_weights &w, std::vector<u
             // products: a^2 = a1 a2, b^2 = b1 b2, c^2 = c1 c2.
             for (int i = 0; i < 6; ++i)
                 if (!finite_pos(w.w[i])) return fail(TL_EINVAL, "six-vertex weights must be > 0");
-            a2 = (long double)w.w[0] * w.w[1];
-            b2 = (long double)w.w[2] * w.w[3];
-            c2 = (long double)w.w[4] * w.w[5];
+            a2 = Ratio::of(w.w[0]) * Ratio::of(w.w[1]);
+            b2 = Ratio::of(w.w[2]) * Ratio::of(w.w[3]);
+            c2 = Ratio::of(w.w[4]) * Ratio::of(w.w[5]);
         } else if (w.kind == TL_W_SIXVERTEX) {
             if (!finite_pos(w.w[0]) || !finite_pos(w.w[1]) || !finite_pos(w.w[2]))
                 return fail(TL_EINVAL, "six-vertex weights must be > 0");
-            a2 = w.w[0];
-            b2 = w.w[1];
-            c2 = w.w[2];
+            a2 = Ratio::of(w.w[0]);
+            b2 = Ratio::of(w.w[1]);
+            c2 = Ratio::of(w.w[2]);
         } else if (w.kind != TL_W_UNIFORM) {
             return fail(TL_EINVAL, "weight kind %d does not apply to the six-vertex model", w.kind);
         }
@@ -172,18 +145,15 @@ tl_status make_thresholds(const tl_domain &d, const tl_weights &w, std::vector<u
             const int ea = 1 - hNE - hSW;   // exponent of a^2
             const int eb = 1 - hNW - hSE;   // exponent of b^2
             const int ec = hNE + hNW + hSW + hSE - 2;   // exponent of c^2
-            long double r = 1.0L;
-            for (int i = 0; i < (ea > 0 ? ea : -ea); ++i) r = ea > 0 ? r * a2 : r / a2;
-            for (int i = 0; i < (eb > 0 ? eb : -eb); ++i) r = eb > 0 ? r * b2 : r / b2;
-            for (int i = 0; i < (ec > 0 ? ec : -ec); ++i) r = ec > 0 ? r * c2 : r / c2;
-            R.push_back(r);
+            R.push_back(a2.pow(ea) * b2.pow(eb) * c2.pow(ec));
         }
         break;
     }
     default:
         return fail(TL_EINVAL, "unknown model %d", d.model);
     }
-    thr = tl::thresholds_from_ratios(R, metro);
+    if (!tl::exact_thresholds(R, metro, thr))
+        return fail(TL_EINVAL, "weights too uneven for 32-bit Metropolis thresholds (a ratio above 2^31)");
     return TL_OK;
 }
 
@@ -196,27 +166,29 @@ tl_status make_thresholds(const tl_domain &d, const tl_weights &w, std::vector<u
 // over the context (SW high) + 2 (SE high).
 tl_status make_free_thresholds(const tl_domain &d, const tl_weights &w, std::vector<uint32_t> &out)
 {
+    using tl::Ratio;
     out.clear();
     if (d.model != TL_SIXVERTEX || d.shape != TL_MASK || !(d.flags & TL_FREE_NORTH)) return TL_OK;
-    long double a1 = 1, a2 = 1, b1 = 1, b2 = 1, c1 = 1, c2 = 1;
+    Ratio a1, a2, b1, b2, c1, c2;
     if (w.kind == TL_W_SIXVERTEX6) {
         for (int i = 0; i < 6; ++i)
             if (!finite_pos(w.w[i])) return fail(TL_EINVAL, "six-vertex weights must be > 0");
-        a1 = w.w[0];
-        a2 = w.w[1];
-        b1 = w.w[2];
-        b2 = w.w[3];
-        c1 = w.w[4];
-        c2 = w.w[5];
+        a1 = Ratio::of(w.w[0]);
+        a2 = Ratio::of(w.w[1]);
+        b1 = Ratio::of(w.w[2]);
+        b2 = Ratio::of(w.w[3]);
+        c1 = Ratio::of(w.w[4]);
+        c2 = Ratio::of(w.w[5]);
     } else if (w.kind != TL_W_UNIFORM) {
         return fail(TL_EINVAL, "free north edges need uniform weights or the six vertex weights");
     }
-    std::vector<long double> R;
+    std::vector<Ratio> R;
     for (int ctx = 0; ctx < 4; ++ctx) {
         const bool sw = ctx & 1, se = ctx & 2;
         R.push_back((sw ? c2 / a1 : a2 / c1) * (se ? c1 / b2 : b1 / c2));
     }
-    out = tl::thresholds_from_ratios(R, w.rule == TL_METROPOLIS);
+    if (!tl::exact_thresholds(R, w.rule == TL_METROPOLIS, out))
+        return fail(TL_EINVAL, "weights too uneven for 32-bit Metropolis thresholds (a ratio above 2^31)");
     return TL_OK;
 }
 

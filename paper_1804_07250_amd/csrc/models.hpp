@@ -71,6 +71,6 @@ std::unique_ptr<Model> make_model(const tl_domain &d, std::string &why, tl_statu
 // Device bytes a sampler of this domain allocates (state, spare buffer, bins
 // of edge obs_bin), or 0 if the domain is invalid.
 size_t sampler_device_bytes(const tl_domain &d, uint32_t obs_bin);
-std::vector<uint32_t> thresholds_from_ratios(const std::vector<long double> &R, bool metropolis);
+
 
 }  // namespace tl
