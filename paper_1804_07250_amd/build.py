@@ -1,7 +1,6 @@
 """Build step of the HIP library: compiles every csrc/*.hip for gfx950 with
 hipcc (host-only csrc/*.cpp with the C++ compiler) and links libtilings.so
-next to this file.  Objects go to _build/.  The measurement helpers in
-probes/ are built as stand-alone executables beside their sources."""
+next to this file.  Objects go to _build/."""
 import os
 import subprocess
 import sys
@@ -44,24 +43,7 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s" % r.stderr)
     os.replace(tmp, OUT)
-    build_probes()
     return OUT
-
-
-PROBES = os.path.join(HERE, "probes")
-
-
-def build_probes():
-    """Measurement helpers (probes/*.hip), each a stand-alone executable."""
-    for f in sorted(os.listdir(PROBES)):
-        if not f.endswith(".hip"):
-            continue
-        exe = os.path.join(PROBES, f[:-4])
-        cmd = [HIPCC] + [x for x in FLAGS if x != "-fPIC"] + [os.path.join(PROBES, f), "-o", exe + ".tmp"]
-        r = subprocess.run(cmd, capture_output=True, text=True)
-        if r.returncode != 0:
-            raise RuntimeError("hipcc failed for probes/%s:\n%s" % (f, r.stderr))
-        os.replace(exe + ".tmp", exe)
 
 
 if __name__ == "__main__":
