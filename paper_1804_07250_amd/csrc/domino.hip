@@ -706,14 +706,15 @@ bool domino_plan(const DominoDev &d, const DominoTile &tile, uint32_t S_max, Til
     const uint32_t tiles_x = (d.ng + TG - 1) / TG;
     const uint32_t LG0 = TG + (tiles_x > 1 ? 2u : 0u);
     const uint32_t max_rows = 1024u / LG0;   // one thread per (row, group) task
-    if (max_rows < 3u) return false;
-    uint32_t TR = tile.TR == 0 ? 1u : (tile.TR < n ? tile.TR : n);
-    if (TR < n && TR > max_rows - 2u) TR = max_rows - 2u;   // leave room for a halo
-    if (TR >= n && n > max_rows) TR = max_rows - 2u;
-    const uint32_t tiles_y = (n + TR - 1) / TR;
     // halo rows per sweep: 1 (one step of the other colour), 2 under the
     // random colour order (any step may be of the other colour)
     const uint32_t hps = tile.order ? 2u : 1u;
+    if (max_rows < 2u * hps + 1u) return false;
+    uint32_t TR = tile.TR == 0 ? 1u : (tile.TR < n ? tile.TR : n);
+    // leave room for a halo of one sweep on each side
+    if (TR < n && TR > max_rows - 2u * hps) TR = max_rows - 2u * hps;
+    if (TR >= n && n > max_rows) TR = max_rows - 2u * hps;
+    const uint32_t tiles_y = (n + TR - 1) / TR;
     uint32_t S = S_max < tile.S ? S_max : tile.S;
     if (tiles_x > 1 && S * hps > 128u) S = 128u / hps;   // the one-group column halo covers 128 steps
     if (tiles_y > 1 && S * hps > (max_rows - TR) / 2u) S = (max_rows - TR) / 2u / hps;

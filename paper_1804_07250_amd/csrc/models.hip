@@ -656,7 +656,9 @@ public:
         return (uint64_t)(d_.N - 1) * (uint64_t)(d_.N - 1);
     }
     int colours() const override { return loz() ? 3 : 4; }
-    double bytes_per_colour_step() const override { return 2.0 * d_.P * (double)d_.rows * d_.K / 8.0; }
+    // one bit per site read and written once per colour step (the streaming
+    // formulation), counted over the sites, not the padded box of the planes
+    double bytes_per_colour_step() const override { return 2.0 * (double)sites() / 8.0; }
 
 private:
     tl_domain dom_;
