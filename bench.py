@@ -11,8 +11,13 @@ One step = reset the chain on the device + 10^4 sweeps + observables + hash
 steps; a site-update is one attempted update of one site in one colour step.
 
 Prints one JSON line with the roofline of the dominant kernel (the sweep
-kernel, timed per launch by its own dispatch events) and the serial CPU
-oracle's rate on a bounded sample of the same workload.
+kernel, timed per launch by its own dispatch events), the other forms and
+models of the path measured on the same GPU (the lozenge hexagon and the
+weighted six-vertex square, the batched and served forms, coupling from the
+past, the random colour order and a mask domain), each result compared with
+the oracle's stored result where one exists (tests/golden), and the serial
+CPU oracle's rate on a bounded, representative sample of the same workload,
+single-core and over several processes.
 """
 import argparse
 import hashlib
@@ -30,6 +35,9 @@ HBM_PEAK_GBS = 8000.0
 # LDS: 256 bytes per clock per CU for conflict-free 128-bit reads (gfx950),
 # 256 CUs, 2.4 GHz
 LDS_PEAK_GBS = 256 * 256 * 2.4
+# VALU: 4 SIMDs of 16 lanes per CU (one wave64 instruction per SIMD every
+# 4 clocks, 64 lane-operations per clock per CU) x 256 CUs x 2.4 GHz
+VALU_PEAK_TOPS = 64 * 256 * 2.4e9 / 1e12
 
 WORKLOADS = {
     "aztec2048": dict(model="domino", n=2048, sweeps=10000, seed=7, obs_every=100, obs_bin=64),
@@ -56,10 +64,14 @@ def parse():
                    help="time every k-th sweep launch with its own dispatch events")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--cpu-procs", type=int, default=16, help="processes of the multi-process oracle figure (at most)")
     p.add_argument("--sweeps-only", action="store_true",
                    help="time only the sweeps (for profiler runs); no JSON contract line")
     p.add_argument("--copy-calibration", type=int, default=0,
                    help="run a plain device copy of this many MiB (profiler calibration) and exit")
+    p.add_argument("--no-models", action="store_true",
+                   help="skip the lozenge and weighted six-vertex legs of the default workload")
+    p.add_argument("--model-steps", type=int, default=3, help="timed jobs of each model leg")
     p.add_argument("--no-batched", action="store_true")
     p.add_argument("--no-served", action="store_true")
     p.add_argument("--batched-chains", type=int, default=4096)
@@ -68,6 +80,8 @@ def parse():
     p.add_argument("--served-rate", type=float, default=200.0)
     p.add_argument("--served-sweeps", type=int, default=2000)
     p.add_argument("--served-budget-mib", type=int, default=1024)
+    p.add_argument("--served-tight-mib", type=int, default=16,
+                   help="budget of the second served run, one the offered load fills (0: no second run)")
     p.add_argument("--served-slots", type=int, default=64)
     p.add_argument("--served-quantum", type=int, default=8, help="sweeps per tick of a weighted request")
     p.add_argument("--no-cftp", action="store_true")
@@ -80,10 +94,43 @@ def parse():
     return p.parse_args()
 
 
+def golden(name):
+    """The oracle's stored result of a workload (tests/golden/<name>.json,
+    written by the oracle alone), or None."""
+    path = os.path.join(ROOT, "tests", "golden", name + ".json")
+    return json.load(open(path)) if os.path.exists(path) else None
+
+
+def alu_roofline(rec, avg_launch_s):
+    """Lane throughput of the VALU from rocprofv3 SQ counters: lane-operations
+    per launch (SQ_THREAD_CYCLES_VALU) over the live launch time, against
+    64 lanes x 256 CUs x 2.4 GHz.  The same as busy share x lane use."""
+    if not rec or "valu_counters_raw" not in rec or avg_launch_s <= 0:
+        return None
+    ops = rec["valu_counters_raw"]["SQ_THREAD_CYCLES_VALU"]
+    achieved = ops / avg_launch_s / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
+            "unit": "T int32 lane-ops/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
+            "lane_ops_per_launch": ops}
+
+
+def hbm_figure(alg_bytes, rec, avg_launch_s):
+    """Algorithmic bytes per launch over the launch time (the streaming
+    formulation of a colour step), and the HBM bytes the counters measured."""
+    achieved = alg_bytes / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
+    out = {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": alg_bytes,
+           "traffic": rec["bytes_per_launch"] if rec else None}
+    if rec and avg_launch_s > 0:
+        out["traffic_GBps"] = round(rec["bytes_per_launch"] / avg_launch_s / 1e9, 1)
+    return out
+
+
 def run_batched(tl, args):
     """Batched form: Aztec chains of orders uniform in [16, 512], two-periodic
     weights a = 1, b = 1/2, seeds 0..count-1, args.batched_sweeps sweeps in one
-    graph-replayed persistent launch; work-group size from the autotuner."""
+    graph-replayed persistent launch; work-group size from the autotuner.  The
+    chains the oracle has stored results for are compared with them."""
     from paper_1804_07250_amd import workloads
     from paper_1804_07250_amd.serving import Batch
     orders = workloads.batch_orders(args.batched_chains)
@@ -103,35 +150,45 @@ def run_batched(tl, args):
     el = time.perf_counter() - t0
     kms, launches, steps = b.kernel_time()
     # rocprofv3 counters of the same workload's full launches, if recorded for the current sources
-    rec = traffic_record("domino_batch_batched4096") if (len(orders), args.batched_sweeps) == (4096, 5000) else None
+    full = (len(orders), args.batched_sweeps) == (4096, 5000)
+    rec = traffic_record("domino_batch_batched4096") if full else None
     avg_s = kms * 1e-3 / max(1, launches)
     updates = info["sites"] * args.batched_sweeps
+    g = golden("batch4096") if full else None
+    match = None
+    if g:
+        ok = sum(1 for c in g["chains"] if b.hash(c["chain"]) == c["hash"])
+        match = "%d/%d" % (ok, len(g["chains"]))
     h0 = b.hash(0)
     b.destroy()
-    # algorithmic bytes: the packed state of every chain read and written per colour step
+    # the streaming formulation's bytes (every chain's packed state read and
+    # written per colour step); the chains stay in LDS for the whole call, so
+    # this is no bound: the VALU lane throughput is
     alg = 2.0 * info["state_bytes"] * 2 * args.batched_sweeps
+    roof = alu_roofline(rec, avg_s) or {"bound": "alu", "achieved": None, "peak": round(VALU_PEAK_TOPS, 2),
+                                        "unit": "T int32 lane-ops/s", "frac": None}
+    roof.update({"traffic": rec["bytes_per_launch"] if rec else None, "launches": launches,
+                 "hbm": hbm_figure(alg, rec, avg_s), "lds": lds_roofline(rec, avg_s), "valu": valu_summary(rec, avg_s)})
+    roof["hbm"]["note"] = "streaming-formulation bytes; the chains stay in LDS, so the HBM figure is not a bound"
     return {"value": updates / el, "unit": "site-updates/s", "ms_per_step": el * 1e3,
             "chains": len(orders), "sweeps": args.batched_sweeps, "sites": info["sites"],
             "state_bytes": info["state_bytes"], "threads": threads, "workgroups": info["workgroups"],
             "autotune_probe_ms": round(probe_ms, 3), "launch_ms": round(kms, 3),
-            "roofline": {"bound": "hbm", "achieved": round(alg / (kms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": round(alg / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                         "traffic": rec["bytes_per_launch"] if rec else None, "launches": launches,
-                         "lds": lds_roofline(rec, avg_s), "valu": valu_summary(rec, avg_s)},
-            "chain0_hash": h0,
+            "roofline": roof, "chain0_hash": h0, "oracle_match": match,
             "workload": "batched: %d domino chains, Aztec orders uniform in [16,512] (PCG64 seed 0x5EED), "
                         "two-periodic a=1 b=1/2, %d sweeps, seeds 0..%d, one graph-replayed persistent launch"
                         % (len(orders), args.batched_sweeps, len(orders) - 1)}
 
 
-def run_served(tl, args):
+def run_served(tl, args, budget_mib):
     """Served form: six-vertex domain-wall requests, N uniform over
     {64,...,1024}, weights (1,1,sqrt 2) / (1,1,1) alternating as lazy Metropolis
-    thresholds, 2000 sweeps, Poisson arrivals; admitted by a device-memory budget."""
+    thresholds, 2000 sweeps, Poisson arrivals; admitted by a device-memory
+    budget.  Requests the oracle has stored results for are compared with them."""
     from paper_1804_07250_amd import workloads
     from paper_1804_07250_amd.serving import Server
     reqs = workloads.serve_requests(args.served_requests, args.served_rate)
-    sv = Server(args.served_budget_mib << 20, args.served_slots, tl.options(sweeps_per_launch=args.served_quantum))
+    sv = Server(budget_mib << 20, args.served_slots, tl.options(sweeps_per_launch=args.served_quantum))
     start = time.perf_counter()
     tickets = []
     for r in reqs:
@@ -147,16 +204,26 @@ def run_served(tl, args):
     st = sv.stats()
     sv.destroy()
     lat = np.array([x["t_done"] - x["t_submit"] for x, _ in res]) * 1e3
+    wait = np.array([x["t_start"] - x["t_submit"] for x, _ in res]) * 1e3
     ok = all(x["status"] == tl.TL_OK for x, _ in res)
     updates = sum((r["N"] - 1) ** 2 * args.served_sweeps for _, r in res)
+    g = golden("served") if args.served_sweeps == 2000 else None
+    match = None
+    if g:
+        by_seed = {x["seed"]: x for x in g["requests"]}
+        hits = [(x, by_seed[r["seed"]]) for x, r in res if r["seed"] in by_seed]
+        good = sum(1 for x, e in hits if x["hash"] == e["hash"] and x["scalar_now"] == e["scalar_now"])
+        match = "%d/%d" % (good, len(hits))
     return {"value": updates / (end - start), "unit": "site-updates/s", "requests": len(res), "all_ok": ok,
+            "oracle_match": match,
             "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
-            "max_ms": round(float(lat.max()), 3), "span_s": round(end - start, 3),
+            "max_ms": round(float(lat.max()), 3), "queue_wait_p99_ms": round(float(np.percentile(wait, 99)), 3),
+            "span_s": round(end - start, 3), "budget_bytes": budget_mib << 20,
             "peak_active": st["peak_active"], "peak_bytes": st["peak_bytes"],
             "workload": "served: six-vertex DWBC, N uniform over {64,128,256,512,1024}, weights (1,1,sqrt2) and "
                         "(1,1,1) alternating (lazy Metropolis), %d sweeps per request, Poisson %.0f/s, %d requests, budget %d MiB, "
                         "%d slots, ticks of %d sweeps (x4 for one-bit jobs)"
-                        % (args.served_sweeps, args.served_rate, len(res), args.served_budget_mib, args.served_slots,
+                        % (args.served_sweeps, args.served_rate, len(res), budget_mib, args.served_slots,
                            args.served_quantum)}
 
 
@@ -191,7 +258,6 @@ def run_variants(tl, wl, args):
     """The plain domino workload under the random colour order, and the same
     sweeps on a square domain given by a mask (start T_min), each timed over
     args.steps jobs after one warm-up job."""
-    import numpy as np
     out = {}
     side = args.domain_side
     legs = [("random_order", tl.domain(tl.TL_DOMINO, n=wl["n"]), 1, 2 * wl["n"] ** 2 - 2 * wl["n"] + 1),
@@ -303,40 +369,181 @@ def valu_summary(rec, avg_launch_s):
             "lane_util": rec["valu_lane_util"]}
 
 
-def cpu_baseline(wl, budget_s):
-    """The serial oracle on the same workload from its start, for a bounded
-    number of sweeps (about budget_s seconds)."""
+def plain_leg(tl, name, args, steps, warmup):
+    """One plain workload timed over `steps` jobs (reset + sweeps + observables
+    + hash) after `warmup` jobs.  Returns (figures, sampler figures)."""
+    wl = WORKLOADS[name]
+    s = make_sampler(tl, wl, args)
+    sites, colours = s.info()
+
+    def step():
+        s.reset(wl["seed"])
+        s.sweep(wl["sweeps"])
+        if args.sweeps_only:
+            s.sync()
+            return None, None
+        obs = s.observables()
+        return obs, s.hash()
+
+    import torch
+    for _ in range(warmup):
+        step()
+    s.sync()
+    s.kernel_time()          # discard warm-up launches
+    s.set_timing(0 if args.no_timing else args.timing_period)
+    s.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    obs, digest = None, None
+    for i in range(steps):
+        obs, digest = step()
+        print("%s step %d done" % (name, i), file=sys.stderr, flush=True)
+    s.sync()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kms, launches, csteps, bpc = s.kernel_time()
+    s.destroy()
+    avg_s = kms * 1e-3 / max(1, launches)
+    bytes_per_launch = bpc * csteps / max(1, launches)
+    kname = ("domino" if wl["model"] == "domino" else "height") + ("_tiled" if args.kernel != 1 else "_streaming")
+    rec = traffic_record("%s_%s" % (kname, name))
+    g = golden(name)
+    match = None
+    if g and digest is not None:
+        match = bool(digest == g["hash"] and obs["samples"] == g["samples"] and obs["scalar_sum"] == g["scalar_sum"]
+                     and obs["bin_sum"].reshape(-1).tolist() == g["bin_sum"])
+    return {"value": sites * wl["sweeps"] * steps / el, "ms_per_step": el / steps * 1e3, "sites": sites,
+            "colours": colours, "hash": digest, "oracle_match": match, "kernel": kname,
+            "kernel_ms": kms, "launches": launches, "avg_launch_s": avg_s,
+            "bytes_per_launch": bytes_per_launch, "rec": rec, "workload": describe(wl), "el": el}
+
+
+def run_models(tl, args):
+    """The lozenge hexagon (q = 1999/2000, 2 x 10^4 sweeps) and the weighted
+    six-vertex square (N = 1024, (1,1,sqrt 2), 2000 sweeps), each with the
+    roofline that binds it (the VALU lane throughput of the bit-serial
+    decisions) and its streaming-formulation HBM figure."""
+    out = {}
+    for name in ("hexagon1024", "sixv1024"):
+        r = plain_leg(tl, name, args, args.model_steps, 1)
+        roof = alu_roofline(r["rec"], r["avg_launch_s"]) or {"bound": "alu", "achieved": None,
+                                                             "peak": round(VALU_PEAK_TOPS, 2),
+                                                             "unit": "T int32 lane-ops/s", "frac": None}
+        roof.update({"kernel": r["kernel"], "avg_launch_us": round(r["avg_launch_s"] * 1e6, 3),
+                     "launches": r["launches"], "traffic": r["rec"]["bytes_per_launch"] if r["rec"] else None,
+                     "hbm": hbm_figure(r["bytes_per_launch"], r["rec"], r["avg_launch_s"]),
+                     "lds": lds_roofline(r["rec"], r["avg_launch_s"]),
+                     "valu": valu_summary(r["rec"], r["avg_launch_s"])})
+        out[name] = {"value": r["value"], "unit": "site-updates/s", "ms_per_step": r["ms_per_step"],
+                     "sites": r["sites"], "hash": r["hash"], "oracle_match": r["oracle_match"],
+                     "roofline": roof, "workload": r["workload"]}
+    return out
+
+
+# --------------------------------------------------------------------- CPU oracle
+
+def host_cpu():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"cpu": model, "nproc": avail, "cpu_count": os.cpu_count()}
+
+
+def cpu_baseline(budget_s):
+    """The serial oracle (one core) on the headline workload, resumed from its
+    own stored states at sweeps 2500, 5000 and 7500 of the chain (oracle
+    checkpoints, tests/golden/ckpt) and timed for about budget_s / 3 seconds
+    from each: a sample spread over the chain, not its frozen first sweeps."""
+    import oracle
+    g = golden("aztec2048")
+    wl = WORKLOADS["aztec2048"]
+    n = wl["n"]
+    sites = 2 * n * n - 2 * n + 1
+    thr = oracle.table_from_ratios(oracle.domino_ratios(), False)
+    ckpts = [m for m in (g or {}).get("marks", []) if m.get("checkpoint")]
+    done, spent, parts = 0, 0.0, []
+    for m in ckpts:
+        path = os.path.join(ROOT, "tests", "golden", "ckpt", m["checkpoint"])
+        if not os.path.exists(path):
+            continue
+        o = oracle.DominoOracle(n, thr, seed=wl["seed"])
+        with np.load(path, allow_pickle=False) as z:
+            o.load(z["export"])
+        o.t = m["t"]
+        t0 = time.perf_counter()
+        k = 0
+        while time.perf_counter() - t0 < budget_s / len(ckpts) and o.t < wl["sweeps"]:
+            o.sweep(4)
+            k += 4
+        el = time.perf_counter() - t0
+        done += k
+        spent += el
+        parts.append("%d sweeps from sweep %d" % (k, m["t"]))
+    out = {"unit": "site-updates/s", "cores": 1, "kind": "oracle", "host": host_cpu()}
+    if done:
+        out["value"] = sites * done / spent
+        out["sample"] = ("serial C oracle on the order-2048 Aztec chain (seed 7), resumed from its own states: %s; "
+                         "%.1f s" % (", ".join(parts), spent))
+    else:   # no stored states: the chain's first sweeps (frozen, faster than the average)
+        o = oracle.DominoOracle(n, thr, seed=wl["seed"])
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < budget_s:
+            o.sweep(8)
+            done += 8
+        spent = time.perf_counter() - t0
+        out["value"] = sites * done / spent
+        out["sample"] = "serial C oracle, first %d sweeps of the order-2048 Aztec chain, %.1f s" % (done, spent)
+    if g:
+        out["full_chain_value"] = g["site_updates_per_s"]
+        out["full_chain_note"] = ("the same oracle over the whole 10^4-sweep chain (%.0f s) on the machine that "
+                                  "stored the result: %s" % (g["wall_s"], g["host"]["cpu"]))
+    return out
+
+
+def _mt_chain(item):
+    """One full chain of the batched workload in a worker process (oracle only)."""
     import oracle
     from fractions import Fraction
-    if wl["model"] == "domino":
-        n = wl["n"]
-        thr = oracle.table_from_ratios(oracle.domino_ratios(), False)
-        o = oracle.DominoOracle(n, thr, seed=wl["seed"])
-        sites = 2 * n * n - 2 * n + 1
-    elif wl["model"] == "lozenge":
-        thr = oracle.table_from_ratios(oracle.lozenge_ratios(Fraction(*wl["q"])), False)
-        o = oracle.LozengeOracle(wl["a"], wl["b"], wl["c"], thr, seed=wl["seed"])
-        sites = len(o.sites())
-        n = "%dx%dx%d" % (wl["a"], wl["b"], wl["c"])
-    else:
-        a2, b2, c2 = wl["w2"]
-        thr = oracle.table_from_ratios(oracle.sixv_ratios(int(a2 ** 0.5), int(b2 ** 0.5), int(c2)), False)
-        o = oracle.SixVertexOracle(wl["n"], thr, seed=wl["seed"])
-        sites = (wl["n"] - 1) ** 2
-        n = wl["n"]
-    done = 0
+    i, n, sweeps = item
+    thr = oracle.table_from_ratios(oracle.domino_ratios("two_periodic", 1, Fraction(1, 2)), False)
+    o = oracle.DominoOracle(n, thr, seed=i)
     t0 = time.perf_counter()
-    chunk = 1
-    while time.perf_counter() - t0 < budget_s and done < wl["sweeps"]:
-        o.sweep(chunk)
-        done += chunk
-        el = time.perf_counter() - t0
-        if el < budget_s / 8:
-            chunk *= 2
-    el = time.perf_counter() - t0
-    return {"value": sites * done / el, "unit": "site-updates/s", "cores": 1, "kind": "oracle",
-            "sample": "serial C oracle, first %d of %d sweeps of the same %s chain (size %s, seed %d, from its "
-                      "extremal start), %.1f s" % (done, wl["sweeps"], wl["model"], n, wl["seed"], el)}
+    o.sweep(sweeps)
+    return i, (2 * n * n - 2 * n + 1) * sweeps, time.perf_counter() - t0, oracle.canonical_hash(o.export())
+
+
+def cpu_baseline_mt(max_procs):
+    """Multi-process oracle figure ("oracle-mt"): independent chains of the
+    batched workload (two-periodic, 5000 sweeps, seed = chain index), whole,
+    one per process, over up to max_procs host cores; the chains are ones the
+    oracle's stored results cover (orders near the median), so each result is
+    also checked against them."""
+    import multiprocessing as mp
+    g = golden("batch4096")
+    if not g:
+        return None
+    procs = max(1, min(max_procs, host_cpu()["nproc"] or 1))
+    chains = sorted((c for c in g["chains"] if 200 <= c["order"] <= 330), key=lambda c: c["chain"])[:procs]
+    items = [(c["chain"], c["order"], g["sweeps"]) for c in chains]
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(len(items)) as pool:
+        res = pool.map(_mt_chain, items)
+    wall = time.perf_counter() - t0
+    want = {c["chain"]: c["hash"] for c in chains}
+    return {"value": sum(r[1] for r in res) / wall, "unit": "site-updates/s", "cores": len(items),
+            "kind": "oracle-mt", "host": host_cpu(),
+            "oracle_match": "%d/%d" % (sum(1 for r in res if r[3] == want[r[0]]), len(res)),
+            "sample": "%d whole chains of the batched workload (orders %s, two-periodic a=1 b=1/2, %d sweeps), one "
+                      "per process, %.1f s wall" % (len(items), [c["order"] for c in chains], g["sweeps"], wall)}
 
 
 def main():
@@ -345,6 +552,15 @@ def main():
         print("bench.py runs on one GPU only: the library has no multi-GPU path; --gpus must be 1",
               file=sys.stderr)
         sys.exit(2)
+    # the CPU oracle legs run first, before anything touches the GPU (the
+    # multi-process one forks its workers)
+    cpu = cpu_mt = None
+    if (not args.no_cpu_baseline and not args.sweeps_only and not args.copy_calibration
+            and args.workload == "aztec2048"):
+        cpu = cpu_baseline(args.cpu_seconds)
+        print("cpu baseline done", file=sys.stderr, flush=True)
+        cpu_mt = cpu_baseline_mt(args.cpu_procs)
+        print("cpu multi-process baseline done", file=sys.stderr, flush=True)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
@@ -359,58 +575,33 @@ def main():
         return
     import paper_1804_07250_amd as tl
     wl = WORKLOADS[args.workload]
-    s = make_sampler(tl, wl, args)
-    sites, colours = s.info()
-
-    def step():
-        s.reset(wl["seed"])
-        s.sweep(wl["sweeps"])
-        if args.sweeps_only:
-            s.sync()
-            return None, None
-        obs = s.observables()
-        return obs, s.hash()
-
-    for _ in range(args.warmup):
-        step()
-    s.sync()
-    s.kernel_time()          # discard warm-up launches
-    s.set_timing(0 if args.no_timing else args.timing_period)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        obs, digest = step()
-        print("step %d done" % i, file=sys.stderr, flush=True)
-    s.sync()
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    kms, launches, csteps, bpc = s.kernel_time()
-    updates = sites * wl["sweeps"] * args.steps
-    value = updates / el
-    avg_ms = kms / max(1, launches)
-    bytes_per_launch = bpc * csteps / max(1, launches)
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if launches else 0.0
-    kname = ("domino" if wl["model"] == "domino" else "height") + ("_tiled" if args.kernel != 1 else "_streaming")
-    rec = traffic_record("%s_%s" % (kname, args.workload))
+    r = plain_leg(tl, args.workload, args, args.steps, args.warmup)
+    if args.sweeps_only:
+        print(json.dumps({"sweeps_only_s_per_step": r["el"] / args.steps, "kernel_ms": r["kernel_ms"],
+                          "launches": r["launches"]}))
+        return
+    avg_s = r["avg_launch_s"]
+    achieved = r["bytes_per_launch"] / avg_s / 1e9 if r["launches"] else 0.0
+    rec = r["rec"]
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": rec["bytes_per_launch"] if rec else None,
-            "kernel": kname, "avg_launch_us": round(avg_ms * 1e3, 3), "launches": launches,
-            "algorithmic_bytes_per_launch": bytes_per_launch,
-            "lds": lds_roofline(rec, avg_ms * 1e-3), "valu": valu_summary(rec, avg_ms * 1e-3)}
+            "kernel": r["kernel"], "avg_launch_us": round(avg_s * 1e6, 3), "launches": r["launches"],
+            "algorithmic_bytes_per_launch": r["bytes_per_launch"],
+            "lds": lds_roofline(rec, avg_s), "valu": valu_summary(rec, avg_s), "alu": alu_roofline(rec, avg_s)}
     out = {"metric": "site-updates/sec on 1 MI355X (plain vs batched vs served p50/p99), bit-exact",
-           "value": value, "unit": "site-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-           "ms_per_step": el / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+           "value": r["value"], "unit": "site-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "u32", "data": "synthetic",
-           "config": {"workload": describe(wl),
-                      "sites": sites, "colours": colours, "sweeps": wl["sweeps"],
+           "config": {"workload": r["workload"],
+                      "sites": r["sites"], "colours": r["colours"], "sweeps": wl["sweeps"],
                       "kernel": "tiled" if args.kernel != 1 else "streaming",
-                      "hash": digest},
+                      "hash": r["hash"], "oracle_match": r["oracle_match"]},
            "roofline": roof}
-    if args.sweeps_only:
-        print(json.dumps({"sweeps_only_s_per_step": el / args.steps, "kernel_ms": kms, "launches": launches}))
-        return
-    s.destroy()
+    headline = args.workload == "aztec2048"
+    if headline and not args.no_models:
+        out["models"] = run_models(tl, args)
+        print("models done", file=sys.stderr, flush=True)
     if not args.no_variants and wl["model"] == "domino":
         out["variants"] = run_variants(tl, wl, args)
         print("variants done", file=sys.stderr, flush=True)
@@ -418,13 +609,18 @@ def main():
         out["batched"] = run_batched(tl, args)
         print("batched done", file=sys.stderr, flush=True)
     if not args.no_served:
-        out["served"] = run_served(tl, args)
+        out["served"] = run_served(tl, args, args.served_budget_mib)
         print("served done", file=sys.stderr, flush=True)
+        if args.served_tight_mib:
+            out["served_budget_bound"] = run_served(tl, args, args.served_tight_mib)
+            print("served (budget-bound) done", file=sys.stderr, flush=True)
     if not args.no_cftp:
         out["cftp"] = run_cftp(tl, args)
         print("cftp done", file=sys.stderr, flush=True)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+    if cpu:
+        out["cpu_baseline"] = cpu
+    if cpu_mt:
+        out["cpu_baseline_mt"] = cpu_mt
     print(json.dumps(out))
 
 

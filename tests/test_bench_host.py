@@ -97,6 +97,36 @@ def test_lds_and_valu_summaries():
     assert bench.lds_roofline(rec, 0.0) is None and bench.valu_summary(rec, -1.0) is None
 
 
+def test_alu_roofline_is_busy_share_times_lane_use():
+    # lane throughput = SQ_THREAD_CYCLES_VALU per launch / launch time against
+    # 64 lanes x 256 CUs x 2.4 GHz; equal to VALU busy share x lane use
+    active = 3.6864e6
+    rec = {"valu_counters_raw": {"SQ_ACTIVE_INST_VALU": active, "SQ_THREAD_CYCLES_VALU": 0.75 * 64 * active},
+           "valu_active_per_launch": active, "valu_lane_util": 0.75}
+    t = 25e-6
+    a = bench.alu_roofline(rec, t)
+    assert a["bound"] == "alu" and a["peak"] == pytest.approx(39.32, abs=0.01)
+    v = bench.valu_summary(rec, t)
+    assert a["frac"] == pytest.approx(v["busy_frac"] * v["lane_util"], abs=1e-4)
+    assert 0.0 < a["frac"] <= 1.0
+    assert a["achieved"] == pytest.approx(a["frac"] * a["peak"], rel=1e-3)
+    assert bench.alu_roofline({}, t) is None and bench.alu_roofline(rec, 0.0) is None
+
+
+@pytest.mark.parametrize("fname", committed_records())
+def test_committed_records_give_no_fraction_above_one(fname):
+    # any roofline the bench builds from a committed record stays at or below
+    # its peak (at the launch time the record's own kernel trace measured)
+    rec = json.load(open(os.path.join(ROOT, "profiles", fname)))
+    if "trace_avg_launch_us" not in rec:
+        pytest.skip("record without its kernel trace time")
+    t = rec["trace_avg_launch_us"] * 1e-6
+    for fig in (bench.alu_roofline(rec, t), bench.lds_roofline(rec, t)):
+        if fig is not None:
+            assert 0.0 < fig["frac"] <= 1.0
+    assert rec["bytes_per_launch"] / t / 1e9 <= bench.HBM_PEAK_GBS
+
+
 def write_counters(folder, rows):
     """A rocprofv3-style counter_collection.csv: rows of (kernel, counter, value)."""
     d = folder / "host" / "123"

@@ -171,3 +171,42 @@ def test_server_multi_tile_jobs_equal_alone(quantum):
         s.sweep(n)
         assert r["hash"] == s.hash(), "job seed %d differs from the same job alone" % seed
         assert r["scalar_now"] == s.observables()["scalar_now"]
+
+
+def test_server_admission_waits_for_memory():
+    # the memory budget, not the slots, bounds the jobs on the device: a budget
+    # of 2.5 times the largest job holds two of them, so of six jobs submitted
+    # together some wait in the queue until another job's memory returns; each
+    # result still equals the same job alone and the oracle
+    tl = need_gpu()
+    from paper_1804_07250_amd.serving import Server
+    say("server admission by memory budget")
+    jobs = [(256, (1.0, 1.0, 2.0), False, 300 + i, 120 + 10 * i) for i in range(4)]
+    jobs += [(200, (1.0, 1.0, 1.0), True, 310, 90), (256, (1.0, 1.0, 1.0), False, 311, 150)]
+    probe = Server(256 << 20, 1)
+    t = probe.submit(tl.domain(tl.TL_SIXVERTEX, n=256), sixv_w(tl, (1.0, 1.0, 2.0)), 1, 1)
+    probe.wait(t, 60.0)
+    largest = probe.stats()["peak_bytes"]       # device bytes of one N = 256 job
+    probe.destroy()
+    budget = int(2.5 * largest)
+    sv = Server(budget, max_slots=16, opt=tl.options(sweeps_per_launch=4))
+    tickets = [sv.submit(tl.domain(tl.TL_SIXVERTEX, n=N), sixv_w(tl, w2, metro), seed, n)
+               for N, w2, metro, seed, n in jobs]
+    res = [sv.wait(x, 120.0) for x in tickets]
+    st = sv.stats()
+    sv.destroy()
+    assert st["completed"] == len(jobs) and st["bytes_in_use"] == 0
+    assert st["peak_bytes"] <= budget
+    assert 2 <= st["peak_active"] < len(jobs)
+    # some job started only after another one had finished (it waited for memory)
+    assert any(b["t_start"] >= a["t_done"] for a in res for b in res if a is not b)
+    for (N, w2, metro, seed, n), r in zip(jobs, res):
+        assert r["status"] == tl.TL_OK and r["sweeps"] == n
+        s = tl.Sampler(tl.domain(tl.TL_SIXVERTEX, n=N), sixv_w(tl, w2, metro), seed)
+        s.sweep(n)
+        assert r["hash"] == s.hash(), "job seed %d differs from the same job alone" % seed
+        o = oracle.SixVertexOracle(N, oracle.table_from_ratios(oracle.sixv_ratios(1, 1, int(w2[2])), metro),
+                                   metropolis=metro, seed=seed)
+        o.sweep(n)
+        assert r["hash"] == oracle.canonical_hash(o.export())
+        assert r["scalar_now"] == o.observe()[0]

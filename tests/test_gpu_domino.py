@@ -198,14 +198,52 @@ def test_maximum_order_valid_tiling():
 
 @pytest.mark.parametrize("n,tile_rows,spl", [(100, 8, 3), (257, 16, 5), (700, 32, 8), (700, 24, 130), (333, 40, 1)])
 def test_tiled_kernel_parity(n, tile_rows, spl):
-    # multi-tile launches with row and column halos, several sweeps per launch
+    # multi-tile launches with row and column halos, several sweeps per launch:
+    # two full launches and a partial one (spl = 130 is cut to the 128 steps
+    # one halo group covers, and reaches that limit)
     tl = need_gpu()
-    say("domino tiled parity n=%d tile_rows=%d sweeps_per_launch=%d" % (n, tile_rows, spl))
+    sweeps = max(13, 2 * spl + 1)
+    say("domino tiled parity n=%d tile_rows=%d sweeps_per_launch=%d, %d sweeps" % (n, tile_rows, spl, sweeps))
     s = gpu_sampler(tl, n, seed=21, kernel=2, tile_rows=tile_rows, sweeps_per_launch=spl)
     o = oracle.DominoOracle(n, thr_uniform(), seed=21)
-    s.sweep(13)
-    o.sweep(13)
+    s.sweep(sweeps)
+    o.sweep(sweeps)
     assert (s.export() == o.export()).all()
+
+
+@pytest.mark.parametrize("n,order,kind,sweeps", [(700, 0, "uniform", 60), (1100, 0, "uniform", 52),
+                                                 (700, 1, "uniform", 40), (600, 0, "two", 53),
+                                                 (600, 1, "two", 35)])
+def test_default_tile_plan_parity(n, order, kind, sweeps):
+    # the automatic tile plans the benchmark uses (32 rows x 4 groups x 25
+    # sweeps; 64 rows x 2 groups x 16 sweeps under the random colour order),
+    # over several full launches and a partial one, against the oracle
+    tl = need_gpu()
+    say("domino default plan n=%d order=%d %s, %d sweeps" % (n, order, kind, sweeps))
+    s = gpu_sampler(tl, n, seed=41, kind=kind, a=1.0, b=0.5, colour_order=order)
+    thr = thr_uniform() if kind == "uniform" else thr_two(1, Fraction(1, 2))
+    o = oracle.DominoOracle(n, thr, seed=41, random_colours=order == 1)
+    s.sweep(sweeps)
+    o.sweep(sweeps)
+    assert (s.export() == o.export()).all()
+
+
+@pytest.mark.parametrize("groups", [1, 2])
+def test_random_order_tallest_tiles(groups):
+    # under the random colour order the tallest accepted tile leaves room for
+    # two halo rows per sweep: the tile heights just below the row limit of a
+    # work-group (1024 threads / (groups + 2 halo groups) rows) run and agree
+    tl = need_gpu()
+    n = 1500
+    max_rows = 1024 // (groups + 2)
+    o = oracle.DominoOracle(n, thr_uniform(), seed=43, random_colours=True)
+    o.sweep(7)
+    for rows in (max_rows - 4, max_rows - 3, max_rows - 2, max_rows):
+        say("domino random order n=%d tile_rows=%d groups=%d" % (n, rows, groups))
+        s = gpu_sampler(tl, n, seed=43, kernel=2, tile_rows=rows, tile_groups=groups, colour_order=1)
+        s.sweep(7)
+        assert (s.export() == o.export()).all(), rows
+        s.destroy()
 
 
 @pytest.mark.parametrize("n", [9, 130, 700])

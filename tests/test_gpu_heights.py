@@ -61,8 +61,9 @@ def test_lozenge_tiles_and_streaming(abc, tile_rows, spl, kernel, groups):
     s = loz_sampler(tl, *abc, seed=5, q=Fraction(3, 4), kernel=kernel, tile_rows=tile_rows, sweeps_per_launch=spl,
                     tile_groups=groups)
     o = loz_oracle(*abc, seed=5, q=Fraction(3, 4))
-    s.sweep(11)
-    o.sweep(11)
+    sweeps = max(11, 2 * spl + 1)   # two full launches and a partial one
+    s.sweep(sweeps)
+    o.sweep(sweeps)
     assert (s.export() == o.export()).all()
 
 
@@ -142,8 +143,30 @@ def test_sixvertex_tiles_and_streaming(N, tile_rows, spl, kernel, groups, order)
     s = sixv_sampler(tl, N, seed=8, w2=(1, 1, 2), kernel=kernel, tile_rows=tile_rows, sweeps_per_launch=spl,
                      tile_groups=groups, colour_order=order)
     o = sixv_oracle(N, seed=8, w2=(1, 1, 2), random_colours=order == 1)
-    s.sweep(13)
-    o.sweep(13)
+    sweeps = max(13, 2 * spl + 1)   # two full launches and a partial one
+    s.sweep(sweeps)
+    o.sweep(sweeps)
+    assert (s.export() == o.export()).all()
+
+
+@pytest.mark.parametrize("model,size,weights,order,sweeps",
+                         [("loz", 150, None, 0, 50), ("loz", 260, Fraction(1999, 2000), 0, 50),
+                          ("loz", 150, None, 1, 40), ("sixv", 700, None, 0, 50), ("sixv", 700, (1, 1, 2), 0, 50),
+                          ("sixv", 513, (1, 1, 2), 1, 40)])
+def test_default_tile_plan_parity(model, size, weights, order, sweeps):
+    # the automatic tile plans of the benchmark workloads (one-bit decisions:
+    # 8-row tiles, 16 sweeps per launch; weighted: 4-row tiles, 6 sweeps),
+    # multi-tile, over several launches, against the oracle
+    tl = need_gpu()
+    say("%s default plan size=%d weights=%s order=%d, %d sweeps" % (model, size, weights, order, sweeps))
+    if model == "loz":
+        s = loz_sampler(tl, size, size, size, seed=47, q=weights, colour_order=order)
+        o = loz_oracle(size, size, size, seed=47, q=weights, random_colours=order == 1)
+    else:
+        s = sixv_sampler(tl, size, seed=47, w2=weights, colour_order=order)
+        o = sixv_oracle(size, seed=47, w2=weights, random_colours=order == 1)
+    s.sweep(sweeps)
+    o.sweep(sweeps)
     assert (s.export() == o.export()).all()
 
 
