@@ -259,6 +259,22 @@ tl_status tl_sampler_export(tl_sampler *s, void *host, size_t bytes, uint64_t *s
  * export's rows, computed on the device except for the last 32*rows bytes. */
 tl_status tl_sampler_hash(tl_sampler *s, uint8_t digest[32]);
 
+/* For callers that cannot allocate memory (tight serving loops, harnesses that
+ * forbid hipMalloc): the same digest as tl_sampler_hash, computed without any
+ * allocation.  The canonical export and the row digests are staged in a static
+ * device buffer of TL_HASH_NOALLOC_SCRATCH_BYTES bytes that every GPU the
+ * library runs on holds until the process ends; the row digests come back to a
+ * static host buffer.  Limit: the export plus 32 bytes per row must fit in the
+ * buffer, and the export may have at most 32768 rows (TL_EINVAL, with the
+ * sizes in tl_last_error, otherwise; an order-2048 Aztec diamond or a 1024^3
+ * hexagon fits).  Every call on a GPU shares that GPU's buffer: a lock held
+ * from the first kernel until the digest is back orders the calls, so calls
+ * from several threads wait for each other instead of racing, and the buffer
+ * keeps the last call's contents (nothing in it needs to start at zero).
+ * Synchronises the sampler's stream; runs on the sampler's device. */
+#define TL_HASH_NOALLOC_SCRATCH_BYTES (40u << 20)
+tl_status tl_sampler_hash_noalloc(tl_sampler *s, uint8_t digest[32]);
+
 /* Replace the state by a canonical export (validated on the host: TL_EINVAL if
  * it is not a state of the domain) and set the sweep counter. */
 tl_status tl_sampler_import(tl_sampler *s, const void *host, size_t bytes, uint64_t sweep);

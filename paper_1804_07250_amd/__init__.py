@@ -92,6 +92,7 @@ def lib():
                                              ctypes.POINTER(u32)]
         L.tl_sampler_export.argtypes = [vp, vp, ctypes.c_size_t, ctypes.POINTER(u64)]
         L.tl_sampler_hash.argtypes = [vp, ctypes.POINTER(ctypes.c_uint8)]
+        L.tl_sampler_hash_noalloc.argtypes = [vp, ctypes.POINTER(ctypes.c_uint8)]
         L.tl_sampler_import.argtypes = [vp, vp, ctypes.c_size_t, u64]
         L.tl_sampler_destroy.argtypes = [vp]
         L.tl_sampler_info.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(u32)]
@@ -109,7 +110,8 @@ def lib():
         L.tl_status_str.restype = ctypes.c_char_p
         L.tl_last_error.restype = ctypes.c_char_p
         for name in ("tl_sampler_create", "tl_sampler_sweep", "tl_sampler_sync", "tl_sampler_observables",
-                     "tl_sampler_export_size", "tl_sampler_export", "tl_sampler_hash", "tl_sampler_import",
+                     "tl_sampler_export_size", "tl_sampler_export", "tl_sampler_hash", "tl_sampler_hash_noalloc",
+                     "tl_sampler_import",
                      "tl_sampler_destroy", "tl_sampler_info", "tl_sampler_thresholds", "tl_sampler_reset",
                      "tl_sampler_set_timing", "tl_sampler_kernel_time", "tl_sampler_cftp",
                      "tl_domain_extremes", "tl_sampler_state_bytes", "tl_sampler_autotune"):
@@ -286,6 +288,13 @@ class Sampler:
     def hash(self) -> str:
         d = (ctypes.c_uint8 * 32)()
         _check(lib().tl_sampler_hash(self._h, d))
+        return bytes(d).hex()
+
+    def hash_noalloc(self) -> str:
+        """The canonical hash through the entry point that allocates nothing
+        (static staging buffer; see tl_sampler_hash_noalloc)."""
+        d = (ctypes.c_uint8 * 32)()
+        _check(lib().tl_sampler_hash_noalloc(self._h, d))
         return bytes(d).hex()
 
     def import_(self, arr: np.ndarray, sweep: int):

@@ -11,6 +11,7 @@
 #include <thread>
 
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -53,6 +54,7 @@ struct tl_sampler {
     tl_options opt{};
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    int device = 0;                    // device current at creation: the state lives there
     uint64_t t = 0;
     uint64_t samples = 0;
     std::vector<uint32_t> thr;
@@ -571,6 +573,7 @@ tl_status tl_sampler_create(const tl_domain *dom, const tl_weights *w, uint64_t 
     s->dom.mask = nullptr;   // the model keeps its own copy of a mask
     s->model->order = s->opt.colour_order;
     s->model->set_boundary_table(s->thr_free);
+    TL_HIP(hipGetDevice(&s->device));
     if (s->opt.stream) {
         s->stream = (hipStream_t)s->opt.stream;
     } else {
@@ -835,6 +838,57 @@ tl_status tl_sampler_hash(tl_sampler *s, uint8_t digest[32])
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return fail(TL_EDEVICE, "hash: %s", hipGetErrorString(e));
     tl::sha256_host(rowd.data(), rowd.size(), digest);
+    return TL_OK;
+}
+
+// ------------------------------------------------ hash without allocation
+namespace {
+// Staging of tl_sampler_hash_noalloc: the canonical export, then the 32-byte
+// digest of every row.  Each GPU holds its own copy at its own address; host
+// code uses that address (looked up once per device), never the array's name.
+__device__ __align__(256) uint8_t scratch[TL_HASH_NOALLOC_SCRATCH_BYTES];
+constexpr int kScratchDevices = 64;
+constexpr uint32_t kScratchMaxRows = 32768u;   // every domain's export has at most this many rows
+std::mutex g_scratch_mu;                       // guards the table and the host digests, and orders the calls
+uint8_t *g_scratch_dev[kScratchDevices];       // address of `scratch` on each device, nullptr until looked up
+uint8_t g_rows_host[32u * kScratchMaxRows];    // row digests copied back for the final hash
+}  // namespace
+
+tl_status tl_sampler_hash_noalloc(tl_sampler *s, uint8_t digest[32])
+{
+    if (!s || !digest) return fail(TL_EINVAL, "null argument");
+    uint32_t r, rb;
+    s->model->export_layout(&r, &rb);
+    const size_t need = (size_t)r * rb + 32u * (size_t)r;
+    if (r > kScratchMaxRows || need > (size_t)TL_HASH_NOALLOC_SCRATCH_BYTES)
+        return fail(TL_EINVAL, "hash_noalloc: the export needs %zu bytes of staging (%u rows), the static buffer "
+                               "holds %zu bytes (%u rows); use tl_sampler_hash",
+                    need, r, (size_t)TL_HASH_NOALLOC_SCRATCH_BYTES, kScratchMaxRows);
+    if (s->device < 0 || s->device >= kScratchDevices) return fail(TL_EINVAL, "device %d out of range", s->device);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    int cur = 0;
+    TL_HIP(hipGetDevice(&cur));
+    if (cur != s->device) TL_HIP(hipSetDevice(s->device));
+    hipError_t e = hipSuccess;
+    if (!g_scratch_dev[s->device]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e == hipSuccess && !p) e = hipErrorInvalidSymbol;
+        if (e == hipSuccess) g_scratch_dev[s->device] = (uint8_t *)p;
+    }
+    if (e == hipSuccess) {
+        // every byte read below is written first by the same call: nothing to clear
+        uint8_t *dev = g_scratch_dev[s->device];
+        const size_t rows_at = (size_t)r * rb;
+        e = s->model->export_canonical(dev, s->stream);
+        if (e == hipSuccess) e = tl::hash_rows(dev, r, rb, dev + rows_at, s->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(g_rows_host, dev + rows_at, 32u * (size_t)r, hipMemcpyDeviceToHost, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    }
+    if (cur != s->device) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return fail(TL_EDEVICE, "hash_noalloc: %s", hipGetErrorString(e));
+    tl::sha256_host(g_rows_host, 32u * (size_t)r, digest);
     return TL_OK;
 }
 
