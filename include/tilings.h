@@ -153,7 +153,11 @@ typedef struct {
     uint32_t obs_bin;            /* observable bin edge in cells (0 or 1 = per cell) */
     uint32_t sweeps_per_launch;  /* sweeps fused in one launch of the tiled kernel; 0 = automatic */
     uint32_t tile_rows;          /* tile height of the tiled kernel; 0 = automatic */
-    uint32_t kernel;             /* 0 = automatic, 1 = one launch per colour step, 2 = tiled multi-sweep */
+    uint32_t kernel;             /* 0 = automatic, 1 = one launch per colour step, 2 = tiled multi-sweep
+                                  * with the tile in LDS, 3 = tiled with the tile in registers (dominoes:
+                                  * a lane per row, a wavefront per group column, at most 64 rows with
+                                  * the halo; other models run kernel 2).  Automatic: kernel 3 for
+                                  * dominoes above order 128 unless tile fields are set, else kernel 2 */
     uint32_t tile_groups;        /* tile width in groups of 128 sites; 0 = automatic */
     uint32_t colour_order;       /* 0 = colours 0..K-1 in every sweep; 1 = random (see below) */
     void *device_buf;            /* samplers: caller-owned device memory for the state (NULL = the
@@ -213,7 +217,8 @@ tl_status tl_sampler_create(const tl_domain *dom, const tl_weights *w, uint64_t 
 
 /* Tile shape of the tiled kernel picked by measurement (a performance choice
  * only: every shape gives the same chain).  Candidates of tile height, width
- * in groups and sweeps per launch are timed over probe_sweeps sweeps (0 = 50)
+ * in groups and sweeps per launch (for dominoes, in LDS and in registers) are
+ * timed over probe_sweeps sweeps (0 = 50)
  * on a copy of the state, which the sampler's state and sweep counter never
  * see; the fastest is kept for the sampler's later sweeps (tile fields of its
  * options still take precedence).  With opt->tune_cache set, a shape
@@ -226,6 +231,7 @@ typedef struct {
     uint32_t candidates;     /* shapes timed (0 when taken from the cache) */
     uint32_t from_cache;     /* 1 if the shape came from the cache */
     float ms_per_sweep;      /* of the chosen shape, as measured (0 from the cache) */
+    uint32_t kernel;         /* tiled kernel of the chosen shape: 2 LDS tiles, 3 register tiles */
 } tl_tune_info;
 tl_status tl_sampler_autotune(tl_sampler *s, uint32_t probe_sweeps, tl_tune_info *out);
 

@@ -64,7 +64,7 @@ class tl_observables(ctypes.Structure):
 class tl_tune_info(ctypes.Structure):
     _fields_ = [("tile_rows", ctypes.c_uint32), ("tile_groups", ctypes.c_uint32),
                 ("sweeps_per_launch", ctypes.c_uint32), ("candidates", ctypes.c_uint32),
-                ("from_cache", ctypes.c_uint32), ("ms_per_sweep", ctypes.c_float)]
+                ("from_cache", ctypes.c_uint32), ("ms_per_sweep", ctypes.c_float), ("kernel", ctypes.c_uint32)]
 
 
 class tl_cftp_info(ctypes.Structure):
@@ -224,7 +224,7 @@ class Sampler:
     def autotune(self, probe_sweeps: int = 0):
         """Pick the tiled kernel's tile shape by measurement (the chain does not
         change).  Returns {"tile_rows", "tile_groups", "sweeps_per_launch",
-        "candidates", "from_cache", "ms_per_sweep"}."""
+        "candidates", "from_cache", "ms_per_sweep", "kernel"}."""
         info = tl_tune_info()
         _check(lib().tl_sampler_autotune(self._h, int(probe_sweeps), ctypes.byref(info)))
         return {k: getattr(info, k) for k, _ in tl_tune_info._fields_}

@@ -456,8 +456,9 @@ std::string tune_key(const tl_sampler *s, bool uniform)
     return k;
 }
 
-// Last entry of `key` in the cache file: rows, groups, sweeps; false if none.
-bool tune_lookup(const char *path, const std::string &key, uint32_t v[3])
+// Last entry of `key` in the cache file: rows, groups, sweeps and the tiled
+// kernel (2 when the line has no fourth number); false if none.
+bool tune_lookup(const char *path, const std::string &key, uint32_t v[4])
 {
     FILE *f = path ? std::fopen(path, "r") : nullptr;
     if (!f) return false;
@@ -465,11 +466,13 @@ bool tune_lookup(const char *path, const std::string &key, uint32_t v[3])
     bool found = false;
     while (std::fgets(line, sizeof line, f)) {
         char k[768];
-        unsigned a, b, c;
-        if (std::sscanf(line, "%767s %u %u %u", k, &a, &b, &c) == 4 && key == k) {
+        unsigned a, b, c, kk = 2;
+        const int got = std::sscanf(line, "%767s %u %u %u %u", k, &a, &b, &c, &kk);
+        if (got >= 4 && key == k) {
             v[0] = a;
             v[1] = b;
             v[2] = c;
+            v[3] = got == 5 ? kk : 2u;
             found = true;
         }
     }
@@ -618,23 +621,25 @@ tl_status tl_sampler_autotune(tl_sampler *s, uint32_t probe_sweeps, tl_tune_info
     const bool metro = s->w.rule == TL_METROPOLIS;
     const std::string key = tune_key(s, T.uniform());
     tl_tune_info info{};
-    uint32_t cached[3];
+    uint32_t cached[4];
     if (tune_lookup(s->opt.tune_cache, key, cached)) {
         s->model->tuned_rows = cached[0];
         s->model->tuned_groups = cached[1];
         s->model->tuned_sweeps = cached[2];
+        s->model->tuned_kernel = cached[3];
         info.tile_rows = cached[0];
         info.tile_groups = cached[1];
         info.sweeps_per_launch = cached[2];
+        info.kernel = cached[3];
         info.from_cache = 1;
         if (out) *out = info;
         return TL_OK;
     }
     // candidates: the automatic shape first, then heights x widths x sweeps
     struct Cand {
-        uint32_t rows, groups, sweeps;
+        uint32_t rows, groups, sweeps, kernel;
     };
-    std::vector<Cand> cands{{0u, 0u, 0u}};
+    std::vector<Cand> cands{{0u, 0u, 0u, 2u}};
     const uint32_t ng = s->model->row_groups();
     std::vector<uint32_t> widths{ng <= 8u ? ng : 8u};
     if (ng > 4u) widths.push_back(4u);
@@ -645,7 +650,14 @@ tl_status tl_sampler_autotune(tl_sampler *s, uint32_t probe_sweeps, tl_tune_info
     const std::vector<uint32_t> sweeps = domino ? std::vector<uint32_t>{12u, 25u} : std::vector<uint32_t>{4u, 6u, 8u, 16u};
     for (uint32_t r : rows)
         for (uint32_t g : widths)
-            for (uint32_t sw : sweeps) cands.push_back(Cand{r, g, sw});
+            for (uint32_t sw : sweeps) cands.push_back(Cand{r, g, sw, 2u});
+    if (domino) {
+        // register tiles: 64 lanes of rows, halo included (the plan trims the
+        // sweeps per launch to what the halo covers)
+        for (uint32_t r : {24u, 32u, 40u, 48u})
+            for (uint32_t g : {2u, 4u})
+                if (g <= ng) cands.push_back(Cand{r, g, (64u - r) / 2u, 3u});
+    }
     // probe on a copy of the state, from the sampler's sweep counter
     std::unique_ptr<tl::Model> probe = s->model->twin();
     hipError_t e = probe->allocate();
@@ -657,15 +669,16 @@ tl_status tl_sampler_autotune(tl_sampler *s, uint32_t probe_sweeps, tl_tune_info
                            s->model->state_words() * sizeof(uint32_t), hipMemcpyDeviceToDevice, s->stream);
     tl_options popt = s->opt;
     popt.tile_rows = popt.tile_groups = popt.sweeps_per_launch = 0;
-    popt.kernel = 2;
+    popt.kernel = 0;
     const uint32_t t0 = (uint32_t)s->t;
     float best = -1.0f;
-    Cand pick{0u, 0u, 0u};
+    Cand pick{0u, 0u, 0u, 2u};
     for (const Cand &c : cands) {
         if (e != hipSuccess) break;
         probe->tuned_rows = c.rows;
         probe->tuned_groups = c.groups;
         probe->tuned_sweeps = c.sweeps;
+        probe->tuned_kernel = c.kernel;
         hipError_t pe = probe->sweeps(t0, probe_sweeps, T, metro, s->seed, popt, s->stream);   // warm-up
         if (pe == hipErrorInvalidConfiguration) {   // no launch plan for this shape
             (void)hipGetLastError();
@@ -697,14 +710,16 @@ tl_status tl_sampler_autotune(tl_sampler *s, uint32_t probe_sweeps, tl_tune_info
     s->model->tuned_rows = pick.rows;
     s->model->tuned_groups = pick.groups;
     s->model->tuned_sweeps = pick.sweeps;
+    s->model->tuned_kernel = pick.kernel;
     info.tile_rows = pick.rows;
     info.tile_groups = pick.groups;
     info.sweeps_per_launch = pick.sweeps;
+    info.kernel = pick.kernel;
     info.ms_per_sweep = best / (float)probe_sweeps;
     if (s->opt.tune_cache) {
         FILE *f = std::fopen(s->opt.tune_cache, "a");
         if (!f) return fail(TL_EINVAL, "cannot append to the tune cache %s", s->opt.tune_cache);
-        std::fprintf(f, "%s %u %u %u\n", key.c_str(), pick.rows, pick.groups, pick.sweeps);
+        std::fprintf(f, "%s %u %u %u %u\n", key.c_str(), pick.rows, pick.groups, pick.sweeps, pick.kernel);
         std::fclose(f);
     }
     if (out) *out = info;

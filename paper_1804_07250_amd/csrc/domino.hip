@@ -381,6 +381,154 @@ __global__ void __launch_bounds__(1024) domino_tiled_kernel(const uint32_t *__re
                               tile % tiles_x, Tall, key0, key1);
 }
 
+// ------------------------------------------------ register-resident tiles
+// The tiles, halo and draws of domino_tile with the state held in registers:
+// wavefront w of the block holds local group w (LG wavefronts), lane l local
+// row l (LR <= 64), sixteen words per lane (the group's four words in each of
+// the four planes).  An owner step touches only a lane's own words.  The other
+// colour's site (r, k) reads owner row r + 1, which is the next lane (a DPP
+// wavefront shift), and bit 0 of the next group's first E word (row r) and S
+// word (row r + 1), which live in the next wavefront and are exchanged through
+// LDS; its flips change row r + 1's S and W planes (shifted back to the next
+// lane) and, through the carry of the group's last site, bit 0 of those two
+// words of the next group (LDS again).  The rows computed in each step, and
+// every value written, are those of domino_tile.
+constexpr uint32_t kRegRows = 64, kRegGroups = 16;
+
+// Lane l receives lane l+1's value (lane_next) or lane l-1's (lane_prev);
+// the lane past either end of the wavefront receives 0.
+__device__ __forceinline__ uint32_t lane_next(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xF, 0xF, true);   // wave_shl:1
+}
+__device__ __forceinline__ uint32_t lane_prev(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138, 0xF, 0xF, true);   // wave_shr:1
+}
+
+template <int MODE, bool RANDOM>
+__global__ void __launch_bounds__(1024) domino_reg_kernel(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
+                                                          size_t PS, uint32_t RS, uint32_t ng, uint32_t n,
+                                                          uint32_t omega, uint32_t t0, uint32_t nsweeps, uint32_t TR,
+                                                          uint32_t TG, uint32_t HR, uint32_t HG, uint32_t tiles_x,
+                                                          Thr Tall, uint32_t key0, uint32_t key1)
+{
+    // first words of E and S published for the previous group, and carries
+    __shared__ uint32_t xE[kRegGroups][kRegRows], xS[kRegGroups][kRegRows], xC[kRegGroups][kRegRows];
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t tile_r = tile / tiles_x, tile_g = tile % tiles_x;
+    const uint32_t LR = TR + 2 * HR, LG = TG + 2 * HG;
+    const int R0 = (int)(tile_r * TR) - (int)HR, G0 = (int)(tile_g * TG) - (int)HG;
+    const uint32_t lr = threadIdx.x & (kRegRows - 1u), lg = threadIdx.x / kRegRows;
+    const int gr = R0 + (int)lr, gg = G0 + (int)lg;
+    const bool mine = lr < LR && gr >= 0 && gr < (int)n && gg >= 0 && gg < (int)ng;
+    uint32_t N[4] = {0u, 0u, 0u, 0u}, S[4] = {0u, 0u, 0u, 0u}, E[4] = {0u, 0u, 0u, 0u}, W[4] = {0u, 0u, 0u, 0u};
+    if (mine) {
+        const uint32_t *p = in + (size_t)gr * RS + 4 * gg;
+        ld4(p, N);
+        ld4(p + PS, S);
+        ld4(p + 2 * PS, E);
+        ld4(p + 3 * PS, W);
+    }
+    const bool has_next = lg + 1u < LG;
+    for (uint32_t s = 0; s < nsweeps; ++s) {
+        for (uint32_t i = 0; i < 2; ++i) {
+            uint32_t c = i, t = t0 + s, base = HR ? s : 0u, end = HR ? LR - s : LR;
+            if constexpr (RANDOM) {
+                const uint32_t step = 2u * t + i, q = 2u * s + i;
+                c = step_colour(step, 2u, key0, key1);
+                t = step;
+                base = HR ? q : 0u;
+                end = HR ? LR - q : LR;
+            }
+            const bool act = mine && lr >= base && lr < end;
+            uint32_t R0v[4] = {0u, 0u, 0u, 0u};
+            if (MODE == kUniform) philox4x32_10((uint32_t)gg, (uint32_t)gr, t, c, key0, key1, R0v);
+            if (c == omega) {
+                uint32_t horiz[4], vert[4], live[4], any = 0u;
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    horiz[w] = N[w] & S[w];
+                    vert[w] = E[w] & W[w];
+                    live[w] = horiz[w] | vert[w];
+                    any |= live[w];
+                }
+                if (act && any) {
+                    uint32_t D[4];
+                    decide_group<MODE>(key0, key1, (uint32_t)gg, (uint32_t)gr, t, c, Tall, R0v, vert, live, D);
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) {
+                        const uint32_t F = (horiz[w] & D[w]) | (vert[w] & ~D[w]);
+                        N[w] ^= F;
+                        S[w] ^= F;
+                        E[w] ^= F;
+                        W[w] ^= F;
+                    }
+                }
+            } else {
+                xE[lg][lr] = E[0];
+                xS[lg][lr] = S[0];
+                uint32_t S1[4], W1[4];
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    S1[w] = lane_next(S[w]);
+                    W1[w] = lane_next(W[w]);
+                }
+                __syncthreads();
+                const uint32_t eNext = has_next ? xE[lg + 1][lr] : 0u;
+                const uint32_t sNext = has_next && lr + 1u < kRegRows ? xS[lg + 1][lr + 1] : 0u;
+                uint32_t horiz[4], vert[4], live[4], any = 0u;
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    const uint32_t eHi = (w < 3) ? E[w + 1] : eNext;
+                    const uint32_t sHi = (w < 3) ? S1[w + 1] : sNext;
+                    const uint32_t sN = (S1[w] >> 1) | (sHi << 31);
+                    const uint32_t sW = (E[w] >> 1) | (eHi << 31);
+                    horiz[w] = sN & N[w];
+                    vert[w] = W1[w] & sW;
+                    live[w] = horiz[w] | vert[w];
+                    any |= live[w];
+                }
+                uint32_t F[4] = {0u, 0u, 0u, 0u};
+                if (act && lr + 1u < LR && any) {
+                    uint32_t D[4];
+                    decide_group<MODE>(key0, key1, (uint32_t)gg, (uint32_t)gr, t, c, Tall, R0v, vert, live, D);
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) F[w] = (horiz[w] & D[w]) | (vert[w] & ~D[w]);
+                }
+                // own N and E planes (E shifted by one site)
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    N[w] ^= F[w];
+                    E[w] ^= (F[w] << 1) | (w > 0 ? F[w - 1] >> 31 : 0u);
+                }
+                // the flips of the row above: this row's W and S planes (S shifted)
+                uint32_t Fd[4];
+#pragma unroll
+                for (int w = 0; w < 4; ++w) Fd[w] = lane_prev(F[w]);
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    W[w] ^= Fd[w];
+                    S[w] ^= (Fd[w] << 1) | (w > 0 ? Fd[w - 1] >> 31 : 0u);
+                }
+                xC[lg][lr] = F[3] >> 31;
+                __syncthreads();
+                if (lg > 0u) {
+                    E[0] ^= xC[lg - 1][lr];
+                    if (lr > 0u) S[0] ^= xC[lg - 1][lr - 1];
+                }
+            }
+        }
+    }
+    if (mine && lr >= HR && lr < HR + TR && lg >= HG && lg < HG + TG) {
+        uint32_t *p = out + (size_t)gr * RS + 4 * gg;
+        st4(p, N);
+        st4(p + PS, S);
+        st4(p + 2 * PS, E);
+        st4(p + 3 * PS, W);
+    }
+}
+
 // Multi-job kernel: work-group b runs tile items[b].tile of job items[b].job,
 // with that job's plan, thresholds and key.
 template <int MODE, bool RANDOM>
@@ -672,7 +820,7 @@ hipError_t domino_colour_step(const DominoDev &d, int colour, uint32_t t, const 
     return launch(tm, 1, k, grid, block, 0, s, d.planes, d.PS, d.RS, d.ng, n, c, t, T, key0, key1);
 }
 
-DominoTile domino_auto_tile(int n, bool random_order)
+DominoTile domino_auto_tile(int n, bool random_order, bool weighted)
 {
     DominoTile t;
     uint32_t ng, RS;
@@ -684,17 +832,14 @@ DominoTile domino_auto_tile(int n, bool random_order)
         t.S = 1u << 30;
         return t;
     }
-    if (random_order) {
-        // two halo rows per sweep: taller, narrower tiles carry less halo per
-        // owned row (measured best on MI355X for order 2048: 64 rows x 2 groups)
-        t.TR = 64;
-        t.TG = ng < 2 ? ng : 2;
-        t.S = 16;
-        return t;
-    }
+    // register tiles of 64 lanes: 32 owned rows and a halo of 16 sweeps (8
+    // under the random colour order, two halo rows per sweep); measured on
+    // MI355X for order 2048: 2 groups wide for one-bit decisions, 4 for
+    // bit-serial ones
+    t.reg = 1;
     t.TR = 32;
-    t.TG = ng < 4 ? ng : 4;
-    t.S = 25;   // measured best on MI355X for order 2048 (tile 32 rows x 4 groups)
+    t.TG = weighted && !random_order ? (ng < 4 ? ng : 4) : (ng < 2 ? ng : 2);
+    t.S = random_order ? 8 : 16;
     return t;
 }
 
@@ -705,7 +850,10 @@ bool domino_plan(const DominoDev &d, const DominoTile &tile, uint32_t S_max, Til
     const uint32_t TG = tile.TG == 0 ? 1u : (tile.TG < d.ng ? tile.TG : d.ng);
     const uint32_t tiles_x = (d.ng + TG - 1) / TG;
     const uint32_t LG0 = TG + (tiles_x > 1 ? 2u : 0u);
-    const uint32_t max_rows = 1024u / LG0;   // one thread per (row, group) task
+    // one thread per (row, group) task; register tiles: a wavefront of 64
+    // rows per group
+    const uint32_t max_rows = tile.reg ? kRegRows : 1024u / LG0;
+    if (tile.reg && LG0 > kRegGroups) return false;
     // halo rows per sweep: 1 (one step of the other colour), 2 under the
     // random colour order (any step may be of the other colour)
     const uint32_t hps = tile.order ? 2u : 1u;
@@ -732,9 +880,10 @@ bool domino_plan(const DominoDev &d, const DominoTile &tile, uint32_t S_max, Til
     p->HG = HG;
     p->tiles_x = tiles_x;
     p->tiles_y = tiles_y;
-    p->threads = (tasks + 63) / 64 * 64;
-    p->lds = lds;
+    p->threads = tile.reg ? LG * kRegRows : (tasks + 63) / 64 * 64;
+    p->lds = tile.reg ? 0u : lds;
     p->order = tile.order;
+    p->reg = tile.reg;
     return true;
 }
 
@@ -746,12 +895,13 @@ hipError_t domino_tiled_sweeps(DominoDev &d, const DominoTile &tile, uint32_t t0
     while (done < nsw) {
         TilePlan p;
         if (!domino_plan(d, tile, nsw - done, &p)) return hipErrorInvalidConfiguration;
-        auto k = p.order ? (T.uniform() ? domino_tiled_kernel<kUniform, true>
-                                        : (metropolis ? domino_tiled_kernel<kMetropolis, true>
-                                                      : domino_tiled_kernel<kHeatBath, true>))
-                         : (T.uniform() ? domino_tiled_kernel<kUniform, false>
-                                        : (metropolis ? domino_tiled_kernel<kMetropolis, false>
-                                                      : domino_tiled_kernel<kHeatBath, false>));
+#define TL_DOMINO_PICK(KERNEL)                                                                        \
+    (p.order ? (T.uniform() ? KERNEL<kUniform, true>                                                  \
+                            : (metropolis ? KERNEL<kMetropolis, true> : KERNEL<kHeatBath, true>))    \
+             : (T.uniform() ? KERNEL<kUniform, false>                                                 \
+                            : (metropolis ? KERNEL<kMetropolis, false> : KERNEL<kHeatBath, false>)))
+        auto k = p.reg ? TL_DOMINO_PICK(domino_reg_kernel) : TL_DOMINO_PICK(domino_tiled_kernel);
+#undef TL_DOMINO_PICK
         hipError_t e = launch(tm, 2 * p.S, k, dim3(p.tiles()), dim3(p.threads), p.lds, s, (const uint32_t *)d.planes,
                               d.spare, d.PS, d.RS, d.ng, (uint32_t)d.n, (uint32_t)d.omega, t0 + done, p.S, p.TR,
                               p.TG, p.HR, p.HG, p.tiles_x, T, key0, key1);

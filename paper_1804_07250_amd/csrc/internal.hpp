@@ -131,6 +131,7 @@ inline __host__ __device__ uint32_t domino_lds_row_words(uint32_t LG)
 struct DominoTile {
     uint32_t TR = 32, TG = 4, S = 8;
     uint32_t order = 0;   // colour order: 0 fixed, 1 random per step
+    uint32_t reg = 0;     // 1: register-resident tiles (a lane per row, a wavefront per group column)
 };
 size_t domino_words(int n, uint32_t *ng, uint32_t *RS, size_t *PS);
 hipError_t domino_init(const DominoDev &d, int init_max, hipStream_t s);
@@ -141,7 +142,7 @@ hipError_t domino_colour_step(const DominoDev &d, int colour, uint32_t t, const 
 // Sweeps t0 .. t0+n-1 with the tiled kernel; swaps d.planes / d.spare.
 hipError_t domino_tiled_sweeps(DominoDev &d, const DominoTile &tile, uint32_t t0, uint32_t n, const Thr &T,
                                int metropolis, uint64_t seed, hipStream_t s, Timing *tm = nullptr);
-DominoTile domino_auto_tile(int n, bool random_order);
+DominoTile domino_auto_tile(int n, bool random_order, bool weighted = false);
 hipError_t domino_export(const DominoDev &d, uint8_t *faces, hipStream_t s);
 hipError_t domino_observe(const DominoDev &d, uint32_t B, uint32_t bins_x, unsigned long long *bins,
                           hipStream_t s);
@@ -236,6 +237,7 @@ hipError_t loz_region_observe(const HeightDev &d, const int32_t *anchor, const i
 struct TilePlan {
     uint32_t S = 0, TR = 0, TG = 0, HR = 0, HG = 0, tiles_x = 0, tiles_y = 0, threads = 0, lds = 0;
     uint32_t order = 0;   // colour order of the launch (the halo covers it)
+    uint32_t reg = 0;     // domino: register-resident tiles
     uint32_t tiles() const { return tiles_x * tiles_y; }
 };
 // Largest launch of at most S_max sweeps the tile shape allows (tile sizes

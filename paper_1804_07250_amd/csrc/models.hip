@@ -31,6 +31,7 @@ public:
         m->tuned_rows = tuned_rows;
         m->tuned_groups = tuned_groups;
         m->tuned_sweeps = tuned_sweeps;
+        m->tuned_kernel = tuned_kernel;
         return m;
     }
     hipError_t allocate() override
@@ -63,7 +64,8 @@ public:
     bool tile_job(uint32_t t0, uint32_t S_max, const Thr &T, bool metro, uint64_t seed, TileJob *j,
                   TilePlan *p) const override
     {
-        DominoTile tile = domino_auto_tile(d_.n, order != 0);
+        DominoTile tile = domino_auto_tile(d_.n, order != 0, !T.uniform());
+        tile.reg = 0;   // multi-job launches run LDS tiles
         tile.S = S_max;
         tile.order = order;
         if (!domino_plan(d_, tile, S_max, p)) return false;
@@ -105,16 +107,22 @@ public:
                 }
             return hipSuccess;
         }
-        DominoTile tile = domino_auto_tile(d_.n, order != 0);
+        DominoTile tile = domino_auto_tile(d_.n, order != 0, !T.uniform());
         if (tuned_rows) {
             tile.TR = tuned_rows;
             tile.TG = tuned_groups;
             tile.S = tuned_sweeps;
+            tile.reg = tuned_kernel == 3 ? 1u : 0u;
         }
+        // tile fields given with the automatic kernel keep their meaning for
+        // the LDS tiles
+        if (opt.kernel == 0 && (opt.tile_rows || opt.tile_groups || opt.sweeps_per_launch)) tile.reg = 0;
         if (opt.tile_rows) tile.TR = opt.tile_rows;
         if (opt.tile_groups) tile.TG = opt.tile_groups;
         if (opt.sweeps_per_launch) tile.S = opt.sweeps_per_launch;
         tile.order = order;
+        if (opt.kernel == 2) tile.reg = 0;
+        if (opt.kernel == 3) tile.reg = 1;
         return domino_tiled_sweeps(d_, tile, t0, n, T, metro ? 1 : 0, seed, s, &timing);
     }
     hipError_t observe(uint32_t B, uint32_t bins_x, unsigned long long *bins, hipStream_t s) override
@@ -266,6 +274,7 @@ public:
         m->tuned_rows = tuned_rows;
         m->tuned_groups = tuned_groups;
         m->tuned_sweeps = tuned_sweeps;
+        m->tuned_kernel = tuned_kernel;
         m->set_boundary_table(free_thr_);
         return m;
     }

@@ -61,6 +61,7 @@ public:
     // Tile shape for sweeps whose options leave it automatic (0 = the
     // automatic shape), as picked by the autotuner.
     uint32_t tuned_rows = 0, tuned_groups = 0, tuned_sweeps = 0;
+    uint32_t tuned_kernel = 2;   // dominoes: 2 LDS tiles, 3 register tiles
     // Groups of 128 sites per state row (the tile-width unit).
     virtual uint32_t row_groups() const = 0;
 };

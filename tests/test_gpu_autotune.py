@@ -64,12 +64,12 @@ def test_cache_is_written_and_reused(tmp_path):
     assert first["from_cache"] == 0
     lines = open(path).read().splitlines()
     assert len(lines) == 1 and lines[0].split()[1:] == [str(first["tile_rows"]), str(first["tile_groups"]),
-                                                          str(first["sweeps_per_launch"])]
+                                                          str(first["sweeps_per_launch"]), str(first["kernel"])]
     s = tl.Sampler(dom, w, 2, tl.options(tune_cache=path))
     again = s.autotune(8)
     assert again["from_cache"] == 1 and again["candidates"] == 0
-    assert [again[k] for k in ("tile_rows", "tile_groups", "sweeps_per_launch")] == \
-        [first[k] for k in ("tile_rows", "tile_groups", "sweeps_per_launch")]
+    assert [again[k] for k in ("tile_rows", "tile_groups", "sweeps_per_launch", "kernel")] == \
+        [first[k] for k in ("tile_rows", "tile_groups", "sweeps_per_launch", "kernel")]
     assert len(open(path).read().splitlines()) == 1
     # another table kind is another entry
     u = tl.Sampler(dom, tl.weights(tl.TL_W_UNIFORM), 3, tl.options(tune_cache=path)).autotune(8)
@@ -86,3 +86,20 @@ def test_autotune_refuses_the_streaming_kernel():
     with pytest.raises(tl.TlError) as e:
         s.autotune()
     assert e.value.status == tl.TL_EINVAL
+
+
+def test_domino_autotune_register_tiles_cache(tmp_path):
+    # a domino large enough for register tiles: the chosen kernel goes to the
+    # cache with the shape, comes back from it, and the chain is unchanged
+    tl = need_gpu()
+    path = str(tmp_path / "tiles.txt")
+    dom = tl.domain(tl.TL_DOMINO, n=700)
+    first = tl.Sampler(dom, tl.weights(tl.TL_W_UNIFORM), 1, tl.options(tune_cache=path)).autotune(20)
+    assert first["from_cache"] == 0 and first["kernel"] in (2, 3) and first["candidates"] > 1
+    s = tl.Sampler(dom, tl.weights(tl.TL_W_UNIFORM), 5, tl.options(tune_cache=path))
+    again = s.autotune(20)
+    assert again["from_cache"] == 1 and again["kernel"] == first["kernel"]
+    ref = tl.Sampler(dom, tl.weights(tl.TL_W_UNIFORM), 5, tl.options(kernel=1))
+    s.sweep(37)
+    ref.sweep(37)
+    assert s.hash() == ref.hash()

@@ -246,6 +246,48 @@ def test_random_order_tallest_tiles(groups):
         s.destroy()
 
 
+@pytest.mark.parametrize("n,rows,groups,spl,order,kind,metro,sweeps", [
+    (1, 0, 0, 0, 0, "uniform", False, 5),          # a single row
+    (2, 0, 0, 0, 0, "uniform", False, 9),
+    (60, 0, 0, 0, 0, "uniform", False, 21),        # one tile, no halo
+    (64, 0, 0, 0, 0, "two", False, 21),            # one tile of exactly 64 rows
+    (100, 16, 0, 5, 0, "uniform", False, 13),      # one group per row, row halo only
+    (257, 20, 1, 7, 0, "uniform", False, 22),      # three groups, one per tile: column halos
+    (700, 32, 4, 16, 0, "uniform", False, 40),     # the default shape
+    (700, 48, 4, 8, 0, "uniform", False, 19),
+    (700, 24, 2, 8, 1, "uniform", False, 30),      # random colour order: two halo rows per sweep
+    (600, 0, 0, 0, 0, "two", False, 40),           # bit-serial decisions
+    (600, 0, 0, 0, 1, "two", False, 25),
+    (333, 30, 3, 9, 0, "two", True, 31),           # lazy Metropolis
+    (2048, 32, 14, 16, 0, "uniform", False, 17),   # 16 wavefronts per tile
+])
+def test_register_tile_parity(n, rows, groups, spl, order, kind, metro, sweeps):
+    # register-resident tiles (kernel 3) against the oracle: several full
+    # launches and a partial one, row and column halos, both colour orders,
+    # one-bit and bit-serial decisions
+    tl = need_gpu()
+    say("domino register tiles n=%d rows=%d groups=%d spl=%d order=%d %s metro=%d, %d sweeps"
+        % (n, rows, groups, spl, order, kind, metro, sweeps))
+    s = gpu_sampler(tl, n, seed=51, kind=kind, a=1.0, b=0.5, metro=metro, kernel=3, tile_rows=rows,
+                    tile_groups=groups, sweeps_per_launch=spl, colour_order=order)
+    thr = thr_uniform(metro) if kind == "uniform" else thr_two(1, Fraction(1, 2), metro)
+    o = oracle.DominoOracle(n, thr, metropolis=metro, seed=51, random_colours=order == 1)
+    s.sweep(sweeps)
+    o.sweep(sweeps)
+    assert (s.export() == o.export()).all()
+    s.destroy()
+
+
+def test_register_tiles_equal_lds_tiles_order_2048():
+    tl = need_gpu()
+    say("domino order 2048 register tiles vs LDS tiles, 300 sweeps")
+    a = gpu_sampler(tl, 2048, seed=7, kernel=2)
+    b = gpu_sampler(tl, 2048, seed=7, kernel=3)
+    a.sweep(300)
+    b.sweep(300)
+    assert a.hash() == b.hash()
+
+
 @pytest.mark.parametrize("n", [9, 130, 700])
 def test_streaming_kernel_parity(n):
     tl = need_gpu()
