@@ -118,8 +118,11 @@ def hbm_figure(alg_bytes, rec, avg_launch_s):
     """Algorithmic bytes per launch over the launch time (the streaming
     formulation of a colour step), and the HBM bytes the counters measured."""
     achieved = alg_bytes / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
+    # a rate above the peak means the state did not stream through HBM: the
+    # figure is then no roofline, and no fraction of it is given
+    frac = achieved / HBM_PEAK_GBS
     out = {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": round(achieved / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": alg_bytes,
+           "frac": round(frac, 4) if frac <= 1.0 else None, "algorithmic_bytes_per_launch": alg_bytes,
            "traffic": rec["bytes_per_launch"] if rec else None}
     if rec and avg_launch_s > 0:
         out["traffic_GBps"] = round(rec["bytes_per_launch"] / avg_launch_s / 1e9, 1)
