@@ -115,6 +115,80 @@ __device__ __forceinline__ void decide128(uint32_t key0, uint32_t key1, uint32_t
     for (int w = 0; w < 4; ++w) D[w] = lt[w];
 }
 
+// One step of decide128_quad's ordered combine: the partner lane given by
+// the quad permutation PERM holds the results of the planes just before
+// (first = false) or just after (first = true) this lane's.
+template <int PERM>
+__device__ __forceinline__ void quad_combine(bool first, uint32_t (&d)[4], uint32_t (&l)[4])
+{
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const uint32_t dp = (uint32_t)__builtin_amdgcn_mov_dpp((int)d[w], PERM, 0xF, 0xF, false);
+        const uint32_t lp = (uint32_t)__builtin_amdgcn_mov_dpp((int)l[w], PERM, 0xF, 0xF, false);
+        l[w] = first ? (l[w] | (lp & ~d[w])) : (lp | (l[w] & ~dp));
+        d[w] |= dp;
+    }
+}
+
+// The same decisions with the planes spread over the four lanes of a quad
+// (lanes 4i .. 4i+3 hold the same 128 sites and call this together): in round
+// m lane q draws plane 4m + q, and the quad combines its four per-plane
+// results in plane order (DPP quad permutations), so one generator call per
+// lane settles four planes.  A site's decision is taken at its first plane
+// whose bit differs from its threshold's or after which the threshold has no
+// 1 bit left; that plane's verdict (threshold bit 1, uniform bit 0: below) is
+// the same one the plane-by-plane loop reaches.  All four lanes return D.
+template <int NC>
+__device__ __forceinline__ void decide128_quad(uint32_t key0, uint32_t key1, uint32_t g, uint32_t r, uint32_t t,
+                                               uint32_t c, const uint32_t (&T)[NC], const uint32_t (&cm)[NC][4],
+                                               const uint32_t (&live)[4], uint32_t q, uint32_t (&D)[4])
+{
+    uint32_t eq[4], lt[4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        eq[w] = live[w];
+        lt[w] = 0u;
+    }
+    for (uint32_t j0 = 0; j0 < 32u; j0 += 4u) {
+        // the quad's lanes share eq, so they leave together
+        if ((eq[0] | eq[1] | eq[2] | eq[3]) == 0u) break;
+        const uint32_t j = j0 + q, b = 31u - j;
+        uint32_t R[4];
+        philox4x32_10(g, r, t, (j << 2) | c, key0, key1, R);
+        const uint32_t below = (b == 0u) ? 0u : ((1u << b) - 1u);
+        uint32_t tsel[NC], nsel[NC];
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            tsel[i] = 0u - ((T[i] >> b) & 1u);
+            nsel[i] = (T[i] & below) ? ~0u : 0u;
+        }
+        // this plane: decided (bits differ, or no threshold bit left) and below
+        uint32_t d[4], l[4];
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            uint32_t tb = 0u, nz = 0u;
+#pragma unroll
+            for (int i = 0; i < NC; ++i) {
+                tb |= cm[i][w] & tsel[i];
+                nz |= cm[i][w] & nsel[i];
+            }
+            d[w] = (tb ^ R[w]) | ~nz;
+            l[w] = tb & ~R[w];
+        }
+        // ordered combine, first plane first: (d, l) then (d', l') gives
+        // (d | d', l | (l' & ~d)); pairs by lane bit 0, then by bit 1
+        quad_combine<0xB1>((q & 1u) == 0u, d, l);   // quad_perm [1, 0, 3, 2]
+        quad_combine<0x4E>((q & 2u) == 0u, d, l);   // quad_perm [2, 3, 0, 1]
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            lt[w] |= eq[w] & l[w];
+            eq[w] &= ~d[w];
+        }
+    }
+#pragma unroll
+    for (int w = 0; w < 4; ++w) D[w] = lt[w];
+}
+
 // Tile of work-group b of n in an XCD-aware order: work-groups are dispatched
 // to the 8 XCDs in turn (b mod 8), and XCD x, which receives ceil((n - x) / 8)
 // of them, takes the next contiguous range of tiles, so that neighbouring

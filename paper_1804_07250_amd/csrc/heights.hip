@@ -55,6 +55,7 @@ static_assert(kHeatBath == kModeHeatBath && kMetropolis == kModeMetropolis && kU
 // Threads per work-group of the tiled and item kernels: 512 leaves 256 VGPRs
 // per lane for the weighted decisions (the largest plans use ~400).
 constexpr uint32_t kHeightThreads = 512;
+constexpr uint32_t kLozThreads = 1024;
 // Layout of a six-vertex threshold table (each layout is its own kernel
 // instantiation, so its registers are allocated for it alone): 9 classes
 // (sA, sB) [x2 for Metropolis], or 5 classes by sA + sB (heat-bath).  Lozenge
@@ -130,20 +131,34 @@ __global__ void height_init_kernel(uint32_t *pa, uint32_t *pb, size_t PS, uint32
     if (pb) pb[p * PS + (size_t)y * RS + w] = bits;
 }
 
+// Bit-serial decisions of one group: plane by plane in one lane (L = 1,
+// kPlanes generator calls per iteration), or with the planes spread over the
+// quad of lanes that holds the group (L = 4, this lane is q of the quad).
+template <int NC, uint32_t L, uint32_t kPlanes = 1>
+__device__ __forceinline__ void decide_sites(uint32_t k0, uint32_t k1, uint32_t g, uint32_t r, uint32_t t, uint32_t c,
+                                             const uint32_t (&T)[NC], const uint32_t (&cm)[NC][4],
+                                             const uint32_t (&live)[4], uint32_t q, uint32_t (&D)[4])
+{
+    if constexpr (L == 4)
+        decide128_quad<NC>(k0, k1, g, r, t, c, T, cm, live, q, D);
+    else
+        decide128<NC, kPlanes>(k0, k1, g, r, t, c, T, cm, live, D);
+}
+
 // Contexts: lozenge heat-bath 1, Metropolis 2 (current up); six-vertex
 // heat-bath 9 classes 3*sA + sB, Metropolis 18 (2*class + current up), or,
 // when a heat-bath table has 5 entries, classes by sA + sB alone.
-template <int MODE>
+template <int MODE, uint32_t L>
 __device__ __forceinline__ void loz_decide(uint32_t k0, uint32_t k1, uint32_t g, uint32_t r, uint32_t t, uint32_t c,
                                            const Thr &Tall, const uint32_t (&R0)[4], const uint32_t (&cur)[4],
-                                           const uint32_t (&live)[4], uint32_t (&D)[4])
+                                           const uint32_t (&live)[4], uint32_t q, uint32_t (&D)[4])
 {
     if (MODE == kUniform) {
 #pragma unroll
         for (int w = 0; w < 4; ++w) D[w] = ~R0[w];
     } else if (MODE == kHeatBath) {
         uint32_t T[1] = {Tall.v[0]}, cm[1][4] = {{~0u, ~0u, ~0u, ~0u}};
-        decide128<1, 2>(k0, k1, g, r, t, c, T, cm, live, D);
+        decide_sites<1, L, 2>(k0, k1, g, r, t, c, T, cm, live, q, D);
     } else {
         uint32_t T[2] = {Tall.v[0], Tall.v[1]}, cm[2][4];
 #pragma unroll
@@ -151,17 +166,17 @@ __device__ __forceinline__ void loz_decide(uint32_t k0, uint32_t k1, uint32_t g,
             cm[0][w] = ~cur[w];
             cm[1][w] = cur[w];
         }
-        decide128<2, 2>(k0, k1, g, r, t, c, T, cm, live, D);
+        decide_sites<2, L, 2>(k0, k1, g, r, t, c, T, cm, live, q, D);
     }
 }
 
 // Points of a free north edge (no north neighbour): table Tall.v[kFreeBase ..]
 // over the context (SW at m+1) + 2 (SE at m+1) [x2: current state up].
-template <int MODE>
+template <int MODE, uint32_t L>
 __device__ __forceinline__ void sixv_free_decide(uint32_t k0, uint32_t k1, uint32_t g, uint32_t r, uint32_t t,
                                                  uint32_t c, const Thr &Tall, const uint32_t (&R0)[4],
                                                  const uint32_t (&hSW)[4], const uint32_t (&hSE)[4],
-                                                 const uint32_t (&cur)[4], const uint32_t (&live)[4],
+                                                 const uint32_t (&cur)[4], const uint32_t (&live)[4], uint32_t q,
                                                  uint32_t (&D)[4])
 {
     if constexpr (MODE == kUniform) {
@@ -184,16 +199,16 @@ __device__ __forceinline__ void sixv_free_decide(uint32_t k0, uint32_t k1, uint3
                     cm[q][w] = m;
                 }
             }
-        decide128<NC>(k0, k1, g, r, t, c, T, cm, live, D);
+        decide_sites<NC, L>(k0, k1, g, r, t, c, T, cm, live, q, D);
     }
 }
 
-template <int MODE, int KIND>
+template <int MODE, int KIND, uint32_t L>
 __device__ __forceinline__ void sixv_decide(uint32_t k0, uint32_t k1, uint32_t g, uint32_t r, uint32_t t, uint32_t c,
                                             const Thr &Tall, const uint32_t (&R0)[4], const uint32_t (&hNE)[4],
                                             const uint32_t (&hNW)[4], const uint32_t (&hSW)[4],
                                             const uint32_t (&hSE)[4], const uint32_t (&cur)[4],
-                                            const uint32_t (&live)[4], uint32_t (&D)[4])
+                                            const uint32_t (&live)[4], uint32_t q, uint32_t (&D)[4])
 {
     if constexpr (MODE == kUniform) {
 #pragma unroll
@@ -221,7 +236,7 @@ __device__ __forceinline__ void sixv_decide(uint32_t k0, uint32_t k1, uint32_t g
                 }
             }
         }
-        decide128<NC>(k0, k1, g, r, t, c, T, cm, live, D);
+        decide_sites<NC, L>(k0, k1, g, r, t, c, T, cm, live, q, D);
     } else {
         constexpr int NC = MODE == kMetropolis ? 18 : 9;
         uint32_t T[NC], cm[NC][4];
@@ -244,17 +259,17 @@ __device__ __forceinline__ void sixv_decide(uint32_t k0, uint32_t k1, uint32_t g
                     }
                 }
         }
-        decide128<NC>(k0, k1, g, r, t, c, T, cm, live, D);
+        decide_sites<NC, L>(k0, k1, g, r, t, c, T, cm, live, q, D);
     }
 }
 
 // One lozenge group: sites k = 128 g + (0..127) of plane s0 in row Y.
 // base(p, row) -> pointer to word 4 lg of that plane row (data words, pads
 // around it).  lrow is the row index in the addressed array.
-template <int MODE, bool MASKED>
+template <int MODE, bool MASKED, uint32_t L>
 __device__ __forceinline__ void loz_group(uint32_t *base, size_t ps, uint32_t rs, uint32_t lrow, uint32_t lgrp,
                                           const Geo &geo, int Y, uint32_t g, uint32_t s0, uint32_t colour, uint32_t t,
-                                          const Thr &Tall, uint32_t k0, uint32_t k1)
+                                          const Thr &Tall, uint32_t k0, uint32_t k1, uint32_t q)
 {
     uint32_t R0[4] = {0u, 0u, 0u, 0u};
     if (MODE == kUniform) philox4x32_10(g, (uint32_t)Y, t, colour, k0, k1, R0);
@@ -294,20 +309,20 @@ __device__ __forceinline__ void loz_group(uint32_t *base, size_t ps, uint32_t rs
     }
     if (!any) return;
     uint32_t D[4];
-    loz_decide<MODE>(k0, k1, g, (uint32_t)Y, t, colour, Tall, R0, cur, live, D);
+    loz_decide<MODE, L>(k0, k1, g, (uint32_t)Y, t, colour, Tall, R0, cur, live, q, D);
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
         const uint32_t nw = (D[w] & b1[w]) | (~D[w] & f1[w]);
         O[w] = (O[w] & ~live[w]) | (nw & live[w]);
     }
-    hst4(P(s0, lrow), O);
+    if (q == 0u) hst4(P(s0, lrow), O);
 }
 
 // One six-vertex group: faces I = 2k + p, k = 128 g + (0..127), of row J.
-template <int MODE, int KIND, bool MASKED>
+template <int MODE, int KIND, bool MASKED, uint32_t L>
 __device__ __forceinline__ void sixv_group(uint32_t *base, size_t ps, uint32_t rs, uint32_t lrow, uint32_t lgrp,
                                            const Geo &geo, int J, uint32_t g, uint32_t p, uint32_t colour, uint32_t t,
-                                           const Thr &Tall, uint32_t k0, uint32_t k1)
+                                           const Thr &Tall, uint32_t k0, uint32_t k1, uint32_t q)
 {
     uint32_t R0[4] = {0u, 0u, 0u, 0u};
     if (MODE == kUniform) philox4x32_10(g, (uint32_t)J, t, colour, k0, k1, R0);
@@ -364,22 +379,22 @@ __device__ __forceinline__ void sixv_group(uint32_t *base, size_t ps, uint32_t r
             lf[w] = live[w] & fm[w];
             anyf |= lf[w];
         }
-        sixv_decide<MODE, KIND>(k0, k1, g, (uint32_t)J, t, colour, Tall, R0, hNE, hNW, hSW, hSE, cur, li, D);
+        sixv_decide<MODE, KIND, L>(k0, k1, g, (uint32_t)J, t, colour, Tall, R0, hNE, hNW, hSW, hSE, cur, li, q, D);
         if (anyf) {
             uint32_t Df[4];
-            sixv_free_decide<MODE>(k0, k1, g, (uint32_t)J, t, colour, Tall, R0, hSW, hSE, cur, lf, Df);
+            sixv_free_decide<MODE, L>(k0, k1, g, (uint32_t)J, t, colour, Tall, R0, hSW, hSE, cur, lf, q, Df);
 #pragma unroll
             for (int w = 0; w < 4; ++w) D[w] = (D[w] & ~fm[w]) | (Df[w] & fm[w]);
         }
     } else {
-        sixv_decide<MODE, KIND>(k0, k1, g, (uint32_t)J, t, colour, Tall, R0, hNE, hNW, hSW, hSE, cur, live, D);
+        sixv_decide<MODE, KIND, L>(k0, k1, g, (uint32_t)J, t, colour, Tall, R0, hNE, hNW, hSW, hSE, cur, live, q, D);
     }
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
         const uint32_t nw = ~(D[w] ^ up[w]);
         O[w] = (O[w] & ~live[w]) | (nw & live[w]);
     }
-    hst4(P(p, lrow), O);
+    if (q == 0u) hst4(P(p, lrow), O);
 }
 
 // Which plane of row y holds the sites of colour c (-1: none in this row).
@@ -395,17 +410,20 @@ __device__ __forceinline__ bool site_row(const Geo &geo, int y, uint32_t rows)
     return y >= 1 && y <= (int)rows - 2;
 }
 
-template <int MODE, int KIND, bool MASKED>
+// GEOM: the model when known at compile time (kGeomLozenge, kGeomSixv), or
+// kGeomAny to read it from geo.
+enum { kGeomAny = 0, kGeomLozenge = 1, kGeomSixv = 2 };
+template <int MODE, int KIND, bool MASKED, uint32_t L = 1, int GEOM = kGeomAny>
 __device__ __forceinline__ void height_group(uint32_t *base, size_t ps, uint32_t rs, uint32_t lrow, uint32_t lgrp,
                                              const Geo &geo, int y, uint32_t g, uint32_t colour, uint32_t t,
-                                             const Thr &T, uint32_t k0, uint32_t k1)
+                                             const Thr &T, uint32_t k0, uint32_t k1, uint32_t q = 0)
 {
     const int pl = colour_plane(geo, y, colour);
     if (pl < 0) return;
-    if (geo.model == TL_LOZENGE)
-        loz_group<MODE, MASKED>(base, ps, rs, lrow, lgrp, geo, y, g, (uint32_t)pl, colour, t, T, k0, k1);
+    if (GEOM == kGeomLozenge || (GEOM == kGeomAny && geo.model == TL_LOZENGE))
+        loz_group<MODE, MASKED, L>(base, ps, rs, lrow, lgrp, geo, y, g, (uint32_t)pl, colour, t, T, k0, k1, q);
     else
-        sixv_group<MODE, KIND, MASKED>(base, ps, rs, lrow, lgrp, geo, y, g, (uint32_t)pl, colour, t, T, k0, k1);
+        sixv_group<MODE, KIND, MASKED, L>(base, ps, rs, lrow, lgrp, geo, y, g, (uint32_t)pl, colour, t, T, k0, k1, q);
 }
 
 template <int MODE, int KIND, bool MASKED>
@@ -431,7 +449,7 @@ __global__ void __launch_bounds__(256) height_step_kernel(uint32_t *planes, size
 // Six-vertex: only rows of parity c >> 1 hold sites of colour c, so the
 // threads cover those rows alone (blockDim >= ceil(LR / 2) * LG): thread tid
 // handles group tid % LG of the (tid / LG)-th such row from base.
-template <int MODE, int KIND, bool RANDOM, bool MASKED>
+template <int MODE, int KIND, bool RANDOM, bool MASKED, int GEOM = kGeomAny>
 __device__ __forceinline__ void height_tile(uint32_t *lds, const uint32_t *__restrict__ in,
                                             uint32_t *__restrict__ out, size_t PS, uint32_t RS, uint32_t ng,
                                             uint32_t rows, uint32_t P, const Geo &geo, uint32_t t0,
@@ -456,12 +474,16 @@ __device__ __forceinline__ void height_tile(uint32_t *lds, const uint32_t *__res
     }
     __syncthreads();
 
-    const uint32_t r0 = tid / LG, lg = tid % LG;
-    const int gg = G0 + (int)lg;
-    const bool lane = gg >= 0 && gg < (int)ng;
-    const uint32_t K_colours = geo.model == TL_LOZENGE ? 3u : 4u;
-    const uint32_t rps = geo.model == TL_LOZENGE ? 3u : 2u;
+    // Tasks: (row, group), six-vertex (row pair, group).  Bit-serial
+    // decisions give each task a quad of lanes that spreads the planes over
+    // its four lanes (L = 4), one-bit decisions one lane; a work-group with
+    // fewer lanes than the tasks need takes them in turns.
+    constexpr uint32_t L = MODE == kUniform ? 1u : 4u;
+    const uint32_t ql = tid % L, slots = nt / L;
     const bool sixv = geo.model != TL_LOZENGE;
+    const uint32_t ntasks = (sixv ? (LR + 1u) / 2u : LR) * LG;
+    const uint32_t K_colours = sixv ? 4u : 3u;
+    const uint32_t rps = sixv ? 2u : 3u;
     for (uint32_t s = 0; s < nsweeps; ++s) {
         for (uint32_t i = 0; i < K_colours; ++i) {
             // colour, sweep counter of the draws and valid rows of this step
@@ -473,11 +495,16 @@ __device__ __forceinline__ void height_tile(uint32_t *lds, const uint32_t *__res
                 base = HR ? q : 0u;
                 end = HR ? LR - q : LR;
             }
-            // six-vertex: the first row >= base of parity c >> 1, then every other row
-            const uint32_t lr = sixv ? base + (((uint32_t)(R0 + (int)base) & 1u) ^ (c >> 1)) + 2u * r0 : base + r0;
-            const int gr = R0 + (int)lr;
-            if (lane && lr < end && lr >= 1 && lr + 1 < LR && site_row(geo, gr, rows))
-                height_group<MODE, KIND, MASKED>(lds, LPS, LRS, lr, lg, geo, gr, (uint32_t)gg, c, t, T, k0, k1);
+            for (uint32_t task = tid / L; task < ntasks; task += slots) {
+                const uint32_t r0 = task / LG, lg = task % LG;
+                const int gg = G0 + (int)lg;
+                // six-vertex: the first row >= base of parity c >> 1, then every other row
+                const uint32_t lr = sixv ? base + (((uint32_t)(R0 + (int)base) & 1u) ^ (c >> 1)) + 2u * r0 : base + r0;
+                const int gr = R0 + (int)lr;
+                if (gg >= 0 && gg < (int)ng && lr < end && lr >= 1 && lr + 1 < LR && site_row(geo, gr, rows))
+                    height_group<MODE, KIND, MASKED, L, GEOM>(lds, LPS, LRS, lr, lg, geo, gr, (uint32_t)gg, c, t,
+                                                              T, k0, k1, ql);
+            }
             __syncthreads();
         }
     }
@@ -493,9 +520,17 @@ __device__ __forceinline__ void height_tile(uint32_t *lds, const uint32_t *__res
     }
 }
 
-// Tiled multi-sweep kernel of one state: one work-group per tile.
+// Tiled multi-sweep kernels of one state: one work-group per tile.  Six-
+// vertex tiles with the nine-class tables, or Metropolis tables by sA + sB on
+// masked domains, run up to 512 lanes (their bit-serial context masks need up
+// to ~190 registers per lane), the others and lozenge tiles up to 1024.
+template <int MODE, int KIND, bool MASKED>
+constexpr uint32_t sixv_threads()
+{
+    return MODE == kUniform || (KIND == kKindSum && !(MASKED && MODE == kMetropolis)) ? kLozThreads : kHeightThreads;
+}
 template <int MODE, int KIND, bool RANDOM, bool MASKED>
-__global__ void __launch_bounds__(kHeightThreads) height_tiled_kernel(const uint32_t *__restrict__ in,
+__global__ void __launch_bounds__((sixv_threads<MODE, KIND, MASKED>())) height_tiled_kernel(const uint32_t *__restrict__ in,
                                                             uint32_t *__restrict__ out, size_t PS, uint32_t RS,
                                                             uint32_t ng, uint32_t rows, uint32_t P, Geo geo,
                                                             uint32_t t0, uint32_t nsweeps, uint32_t TR, uint32_t TG,
@@ -505,8 +540,20 @@ __global__ void __launch_bounds__(kHeightThreads) height_tiled_kernel(const uint
     extern __shared__ uint32_t lds[];
     // plain work-group order: tiles of a hexagon differ in work, and the
     // round-robin dispatch over the XCDs balances them
-    height_tile<MODE, KIND, RANDOM, MASKED>(lds, in, out, PS, RS, ng, rows, P, geo, t0, nsweeps, TR, TG, HR, HG,
-                                            blockIdx.x / tiles_x, blockIdx.x % tiles_x, T, k0, k1);
+    height_tile<MODE, KIND, RANDOM, MASKED, kGeomSixv>(lds, in, out, PS, RS, ng, rows, P, geo, t0, nsweeps, TR, TG,
+                                                       HR, HG, blockIdx.x / tiles_x, blockIdx.x % tiles_x, T, k0, k1);
+}
+template <int MODE, int KIND, bool RANDOM, bool MASKED>
+__global__ void __launch_bounds__(kLozThreads) loz_tiled_kernel(const uint32_t *__restrict__ in,
+                                                        uint32_t *__restrict__ out, size_t PS, uint32_t RS,
+                                                        uint32_t ng, uint32_t rows, uint32_t P, Geo geo, uint32_t t0,
+                                                        uint32_t nsweeps, uint32_t TR, uint32_t TG, uint32_t HR,
+                                                        uint32_t HG, uint32_t tiles_x, Thr T, uint32_t k0, uint32_t k1)
+{
+    extern __shared__ uint32_t lds[];
+    height_tile<MODE, kKindClass, RANDOM, MASKED, kGeomLozenge>(lds, in, out, PS, RS, ng, rows, P, geo, t0, nsweeps,
+                                                                TR, TG, HR, HG, blockIdx.x / tiles_x,
+                                                                blockIdx.x % tiles_x, T, k0, k1);
 }
 
 // Multi-job kernel: work-group b runs tile items[b].tile of job items[b].job,
@@ -765,7 +812,7 @@ hipError_t height_colour_step(const HeightDev &d, int colour, uint32_t t, const 
                   k0, k1);
 }
 
-HeightTile height_auto_tile(const HeightDev &d, bool uniform)
+HeightTile height_auto_tile(const HeightDev &d, bool uniform, bool metropolis)
 {
     HeightTile t;
     if (d.rows <= 96 && d.ng <= 4) {   // whole domain in one tile, no halo
@@ -774,13 +821,22 @@ HeightTile height_auto_tile(const HeightDev &d, bool uniform)
         t.S = 1u << 30;
         return t;
     }
-    // Rows up to 8 groups wide are one tile wide (no column halo).  Weighted
-    // decisions (a chain of Philox planes per step) favour short tiles and few
-    // sweeps per launch, one-bit decisions longer launches; measured on MI355X
-    // for the 1024 hexagon (q = 1999/2000) and the N = 1024 squares.
+    // Rows up to 8 groups wide are one tile wide (no column halo).  Bit-serial
+    // decisions favour short tiles and few sweeps per launch, one-bit
+    // decisions longer launches; measured on MI355X for the 1024 hexagon
+    // (q = 1999/2000: 6 rows, 3 sweeps) and the N = 1024 squares (heat-bath
+    // 4 rows and 6 sweeps, lazy Metropolis 8 and 8).
     t.TG = d.ng <= 8 ? d.ng : 4;
-    t.TR = uniform ? 8 : 4;
-    t.S = uniform ? 16 : 6;
+    if (uniform) {
+        t.TR = 8;
+        t.S = 16;
+    } else if (d.model == TL_LOZENGE) {
+        t.TR = 6;
+        t.S = 3;
+    } else {
+        t.TR = metropolis ? 8 : 4;
+        t.S = metropolis ? 8 : 6;
+    }
     return t;
 }
 
@@ -820,7 +876,11 @@ bool height_plan(const HeightDev &d, const HeightTile &tile, uint32_t S_max, Til
     p->HG = HG;
     p->tiles_x = tiles_x;
     p->tiles_y = tiles_y;
-    p->threads = (tasks + 63) / 64 * 64;
+    // a thread per task, a quad per task for bit-serial decisions (the
+    // kernel loops over the tasks when the work-group has fewer lanes)
+    const uint32_t lanes = (tasks * (tile.lanes ? tile.lanes : 1u) + 63) / 64 * 64;
+    const uint32_t cap = tile.items ? kHeightThreads : (tile.wide || d.model == TL_LOZENGE ? kLozThreads : kHeightThreads);
+    p->threads = lanes < cap ? lanes : cap;
     p->lds = lds;
     p->order = tile.order;
     return true;
@@ -836,8 +896,16 @@ hipError_t height_tiled_sweeps(HeightDev &d, const HeightTile &tile, uint32_t t0
         TilePlan p;
         if (!height_plan(d, tile, nsw - done, &p)) return hipErrorInvalidConfiguration;
         const int mode = T.uniform() ? kUniform : (metropolis ? kMetropolis : kHeatBath);
-        auto k = TL_HEIGHT_PICK_ORDER_MASK(height_tiled_kernel, mode, (int)table_kind(T), p.order,
-                                           d.site != nullptr);
+#define TL_LOZ_PICK(R, M)                                                                              \
+    (mode == kUniform ? loz_tiled_kernel<kUniform, kKindClass, R, M>                                   \
+     : mode == kMetropolis ? loz_tiled_kernel<kMetropolis, kKindClass, R, M>                           \
+                           : loz_tiled_kernel<kHeatBath, kKindClass, R, M>)
+        const bool masked = d.site != nullptr;
+        auto k = d.model == TL_LOZENGE
+                     ? (p.order ? (masked ? TL_LOZ_PICK(true, true) : TL_LOZ_PICK(true, false))
+                                : (masked ? TL_LOZ_PICK(false, true) : TL_LOZ_PICK(false, false)))
+                     : TL_HEIGHT_PICK_ORDER_MASK(height_tiled_kernel, mode, (int)table_kind(T), p.order, masked);
+#undef TL_LOZ_PICK
         hipError_t e = launch(tm, colours * p.S, k, dim3(p.tiles()), dim3(p.threads), p.lds, s,
                               (const uint32_t *)d.planes, d.spare, d.PS, d.RS, d.ng, d.rows, d.P, geo_of(d),
                               t0 + done, p.S, p.TR, p.TG, p.HR, p.HG, p.tiles_x, T, k0, k1);

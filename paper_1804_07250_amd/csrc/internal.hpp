@@ -201,6 +201,9 @@ struct HeightDev {
 struct HeightTile {
     uint32_t TR = 32, TG = 4, S = 8;
     uint32_t order = 0;   // colour order: 0 fixed, 1 random per step
+    uint32_t lanes = 1;   // lanes per task: 1 (one-bit decisions) or 4 (bit-serial, a quad per task)
+    uint32_t items = 0;   // 1: a share of a multi-job launch (work-groups of at most 512 lanes)
+    uint32_t wide = 0;    // 1: six-vertex tables the 1024-lane kernels take (one-bit, or by sA + sB)
 };
 size_t height_words(HeightDev &d);
 hipError_t height_init(const HeightDev &d, int init_max, hipStream_t s);
@@ -208,7 +211,7 @@ hipError_t height_colour_step(const HeightDev &d, int colour, uint32_t t, const 
                               uint64_t seed, hipStream_t s, Timing *tm = nullptr);
 hipError_t height_tiled_sweeps(HeightDev &d, const HeightTile &tile, uint32_t t0, uint32_t n, const Thr &T,
                                int metropolis, uint64_t seed, hipStream_t s, Timing *tm = nullptr);
-HeightTile height_auto_tile(const HeightDev &d, bool uniform);
+HeightTile height_auto_tile(const HeightDev &d, bool uniform, bool metropolis = false);
 // int32 canonical export into dev (rows x (row length) values)
 hipError_t height_export(const HeightDev &d, int32_t *dev, hipStream_t s);
 hipError_t height_observe(const HeightDev &d, uint32_t B, uint32_t bins_x, unsigned long long *bins, hipStream_t s);

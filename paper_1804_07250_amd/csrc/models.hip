@@ -384,8 +384,11 @@ public:
         }
         tile.S = S_max;
         tile.order = order;
+        const Thr K = kernel_table(T, metro);
+        tile.lanes = K.uniform() ? 1u : 4u;
+        tile.items = 1;
         if (!height_plan(d_, tile, S_max, p)) return false;
-        *j = height_tile_job(d_, *p, t0, kernel_table(T, metro), metro ? 1 : 0, seed);
+        *j = height_tile_job(d_, *p, t0, K, metro ? 1 : 0, seed);
         return true;
     }
     void swap_buffers() override { std::swap(d_.planes, d_.spare); }
@@ -476,7 +479,7 @@ public:
                 }
             return hipSuccess;
         }
-        HeightTile tile = height_auto_tile(d_, K.uniform());
+        HeightTile tile = height_auto_tile(d_, K.uniform(), metro);
         if (tuned_rows) {
             tile.TR = tuned_rows;
             tile.TG = tuned_groups;
@@ -486,6 +489,8 @@ public:
         if (opt.tile_groups) tile.TG = opt.tile_groups;
         if (opt.sweeps_per_launch) tile.S = opt.sweeps_per_launch;
         tile.order = order;
+        tile.lanes = K.uniform() ? 1u : 4u;
+        tile.wide = K.uniform() || (table_kind(K) == kTableSum && !(metro && region_)) ? 1u : 0u;
         return height_tiled_sweeps(d_, tile, t0, n, K, metro ? 1 : 0, seed, s, &timing);
     }
     hipError_t observe(uint32_t B, uint32_t bins_x, unsigned long long *bins, hipStream_t s) override
