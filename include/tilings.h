@@ -107,7 +107,7 @@ typedef enum {
  * are normalised so that the smallest H of T_min is 0 (the hexagon's triangles
  * give the hexagon exactly); observables: H - H_min at the (w+1) x (h+1)
  * points.  Either: TL_EUNTILEABLE when no state meets the boundary.
- * Batches and servers take the fixed shapes only. */
+ * Batches take domino masks, servers masks of every model. */
 typedef struct {
     int32_t model;   /* tl_model */
     int32_t shape;   /* tl_shape */
@@ -173,8 +173,7 @@ typedef struct {
  * step s updates colour floor(K u / 2^32), u = word 0 of Philox(key = seed,
  * ctr = (s, 0, 0, 2^31)), with the site draws of sweep counter s (the per-site
  * uniform defined above with t replaced by s).  K t must stay below 2^32.
- * Samplers only (plain sweeps and coupling from the past); batches and servers
- * run the fixed order. */
+ * Samplers (plain sweeps and coupling from the past) and batches. */
 
 /* Caller-owned state (device_buf).  A sampler created with device_buf set
  * keeps its two bit-plane buffers (the state and the spare it is swapped with
@@ -342,16 +341,20 @@ typedef struct {
 tl_status tl_sampler_cftp(tl_sampler *s, uint32_t max_log2, tl_cftp_info *out);
 
 /* ------------------------------------------------------------------ batched
- * Many independent domino chains on Aztec diamonds of uneven orders (1..512),
- * advanced together: each tl_batch_sweep call is one persistent kernel launch
- * (replayed from a captured hipGraph) in which work-groups take whole chains,
- * longest first, and keep them in LDS for all the call's sweeps.  Chain i is
- * keyed by seeds[i], so its tiling equals the tiling of a tl_sampler with the
- * same domain, weights and seed.  One weight set for all chains. */
+ * Many independent domino chains on Aztec diamonds of uneven orders (1..512)
+ * or on domains given by masks (TL_MASK, w + h <= 1024; each runs on the Aztec
+ * diamond it is embedded in, as a sampler does), advanced together: each
+ * tl_batch_sweep call is one persistent kernel launch (replayed from a
+ * captured hipGraph) in which work-groups take whole chains, longest first,
+ * and keep them in LDS for all the call's sweeps.  Chain i is keyed by
+ * seeds[i], so its tiling equals the tiling of a tl_sampler with the same
+ * domain, weights, seed and colour order.  One weight set and one colour
+ * order (opt->colour_order, fixed or random per step) for all chains. */
 typedef struct tl_batch tl_batch;
 
-/* doms[0..n) (domino, Aztec, order <= 512), seeds[0..n).  Errors: TL_EINVAL,
- * TL_ENOMEM, TL_EDEVICE. */
+/* doms[0..n) (domino: Aztec of order <= 512, or a mask), seeds[0..n).
+ * Errors: TL_EINVAL, TL_EUNTILEABLE (a mask without tilings), TL_ENOMEM,
+ * TL_EDEVICE. */
 tl_status tl_batch_create(int32_t n, const tl_domain *doms, const tl_weights *w, const uint64_t *seeds,
                           const tl_options *opt, tl_batch **out);
 /* Pick the work-group size (256, 512 or 1024 threads) with the shortest probe
@@ -369,7 +372,9 @@ tl_status tl_batch_info(const tl_batch *b, uint64_t *sites, uint64_t *state_byte
 /* Time each batch launch with events (enable != 0); report and clear. */
 tl_status tl_batch_set_timing(tl_batch *b, int enable);
 tl_status tl_batch_kernel_time(tl_batch *b, double *ms, uint64_t *launches, uint64_t *colour_steps);
-/* Canonical export / hash of one chain (same formats as the sampler's). */
+/* Canonical export / hash of one chain (same formats as the sampler's: the
+ * diamond's 2n x 2n box, or the mask's w x h box), and the export's size. */
+tl_status tl_batch_export_size(tl_batch *b, int32_t chain, size_t *bytes, uint32_t *rows, uint32_t *row_bytes);
 tl_status tl_batch_export(tl_batch *b, int32_t chain, void *host, size_t bytes);
 tl_status tl_batch_hash(tl_batch *b, int32_t chain, uint8_t digest[32]);
 tl_status tl_batch_destroy(tl_batch *b);
@@ -382,7 +387,11 @@ tl_status tl_batch_destroy(tl_batch *b);
  * tl_options.sweeps_per_launch sweeps (default 250) on their own streams, so
  * jobs that arrive while others run overlap with them on the GPU.  A finished
  * job's result is its canonical hash and whole-domain observable; its memory
- * is released at once.  A job gives the same result alone and in a mix. */
+ * is released at once.  A job gives the same result alone and in a mix.
+ * Domains given by masks are served too (their host pre-pass runs in
+ * tl_server_submit; a masked height-model domain's device tables count
+ * against the budget), and opt->colour_order sets the colour order of every
+ * job (fixed, or random per step as for a sampler). */
 typedef struct tl_server tl_server;
 typedef struct {
     uint64_t ticket;
@@ -401,7 +410,7 @@ typedef struct {
 } tl_server_counters;
 
 /* Budget in bytes of device state (sum over resident jobs), at most max_slots
- * resident jobs; opt (nullable): sweeps_per_launch = quantum, obs_bin. */
+ * resident jobs; opt (nullable): sweeps_per_launch = quantum, colour_order. */
 tl_status tl_server_create(size_t hbm_budget_bytes, int32_t max_slots, const tl_options *opt, tl_server **out);
 /* Queue a job; TL_EBUDGET if it can never fit the budget, TL_EINVAL for an
  * invalid domain or weights.  *ticket identifies it. */

@@ -432,6 +432,10 @@ tl_status make_table(const tl_domain &d, const tl_weights &w, std::vector<uint32
 {
     return make_thresholds(d, w, thr);
 }
+tl_status make_free_table(const tl_domain &d, const tl_weights &w, std::vector<uint32_t> &thr)
+{
+    return make_free_thresholds(d, w, thr);
+}
 }  // namespace tl
 
 namespace {

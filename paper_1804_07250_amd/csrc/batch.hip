@@ -1,5 +1,6 @@
 // Batched form: thousands of independent domino chains (Aztec diamonds of
-// uneven orders) advanced together by one persistent launch per call, replayed
+// uneven orders, or domains given by masks, each run on the Aztec diamond it
+// is embedded in) advanced together by one persistent launch per call, replayed
 // from a captured hipGraph.  Chains are packed into bundles (several small
 // chains per work-group, first-fit over the chains longest first) and the
 // bundles are handed to work-groups costliest first (LPT order) through an
@@ -14,6 +15,7 @@
 
 #include "errors.hpp"
 #include "internal.hpp"
+#include "models.hpp"
 
 struct tl_batch {
     int32_t count = 0;
@@ -22,6 +24,11 @@ struct tl_batch {
     tl_weights w{};
     tl::Thr T{};
     bool metro = false;
+    uint32_t colour_order = 0;   // 0 fixed, 1 random per step (Section 2.2)
+    // mask-domain chains: the model that knows the domain's extremal tilings
+    // and export box (nullptr for Aztec chains); attached to the chain's
+    // stretch of the pool when used
+    std::vector<std::unique_ptr<tl::Model>> masks;
     hipStream_t stream = nullptr;
     bool own_stream = false;
     uint32_t *planes = nullptr;
@@ -146,11 +153,27 @@ uint32_t workgroups_for(const tl_batch *b, uint32_t threads, uint32_t bundles)
     return wg;
 }
 
+// The mask model of chain i, attached to the chain's state in the pool.
+tl::Model *mask_model(tl_batch *b, int32_t i)
+{
+    tl::Model *m = b->masks[i].get();
+    if (m) {
+        uint32_t *st = b->planes + b->chains[i].offset;
+        m->attach(st, st);
+    }
+    return m;
+}
+
 tl_status init_all(tl_batch *b)
 {
     for (int32_t i = 0; i < b->count; ++i) {
+        const bool init_max = b->doms[i].init == TL_INIT_MAX;
+        if (tl::Model *m = mask_model(b, i)) {
+            TL_HIP(m->init(init_max, b->stream));
+            continue;
+        }
         const tl::DominoDev d = chain_dev(b, i);
-        TL_HIP(tl::domino_init(d, b->doms[i].init == TL_INIT_MAX ? 1 : 0, b->stream));
+        TL_HIP(tl::domino_init(d, init_max ? 1 : 0, b->stream));
     }
     for (auto &c : b->chains) c.t = 0;
     TL_HIP(hipMemcpyAsync(b->d_chains, b->chains.data(), b->chains.size() * sizeof(tl::BatchChain),
@@ -167,7 +190,7 @@ tl_status launch_direct(tl_batch *b, uint32_t nsweeps, uint32_t threads, tl::Tim
         if (x.threads == threads) st = &x;
     if (!st) return tl::fail(TL_EINVAL, "no bundles for %u threads", threads);
     TL_HIP(tl::domino_batch_sweeps(b->d_chains, st->d_bundles, st->d_members, st->count, b->d_counter, b->planes,
-                                   nsweeps, b->T, b->metro ? 1 : 0, threads,
+                                   nsweeps, b->T, b->metro ? 1 : 0, b->colour_order, threads,
                                    workgroups_for(b, threads, st->count), b->lds_max, b->stream, tm));
     return TL_OK;
 }
@@ -180,7 +203,7 @@ tl_status tl_batch_create(int32_t n, const tl_domain *doms, const tl_weights *w,
                           const tl_options *opt, tl_batch **out)
 {
     if (!doms || !w || !seeds || !out || n <= 0) return tl::fail(TL_EINVAL, "invalid batch arguments");
-    if (opt && opt->colour_order) return tl::fail(TL_EINVAL, "batches run the fixed colour order");
+    if (opt && opt->colour_order > 1) return tl::fail(TL_EINVAL, "unknown colour order %u", opt->colour_order);
     if (opt && opt->device_buf) return tl::fail(TL_EINVAL, "batches allocate their own chain pool");
     *out = nullptr;
     // every early return below releases what was set up so far
@@ -194,13 +217,28 @@ tl_status tl_batch_create(int32_t n, const tl_domain *doms, const tl_weights *w,
     b->seeds.assign(seeds, seeds + n);
     b->w = *w;
     b->metro = w->rule == TL_METROPOLIS;
+    b->colour_order = opt ? opt->colour_order : 0u;
+    b->masks.resize(n);
     std::vector<uint32_t> thr;
     for (int32_t i = 0; i < n; ++i) {
-        const tl_domain &d = doms[i];
-        if (d.model != TL_DOMINO || d.shape != TL_AZTEC)
-            return tl::fail(TL_EINVAL, "batches hold domino chains on Aztec diamonds (chain %d)", i);
-        if (d.n < 1 || d.n > 512) return tl::fail(TL_EINVAL, "batched Aztec orders must be in [1, 512] (chain %d)", i);
+        tl_domain &d = b->doms[i];
+        if (d.model != TL_DOMINO || (d.shape != TL_AZTEC && d.shape != TL_MASK))
+            return tl::fail(TL_EINVAL, "batches hold domino chains on Aztec diamonds or masks (chain %d)", i);
         if (d.init != TL_INIT_MIN && d.init != TL_INIT_MAX) return tl::fail(TL_EINVAL, "unknown init (chain %d)", i);
+        if (d.shape == TL_MASK) {
+            // the host pre-pass (domain checks, Thurston's test, extremal
+            // tilings); the chain runs on the Aztec diamond of order
+            // ceil((w + h) / 2) that holds the box
+            if (d.w < 1 || d.h < 1 || d.w + d.h > 1024)
+                return tl::fail(TL_EINVAL, "batched mask boxes need w + h <= 1024 (chain %d)", i);
+            std::string why;
+            tl_status mst = TL_EINVAL;
+            b->masks[i] = tl::make_model(d, why, &mst);
+            if (!b->masks[i]) return tl::fail(mst, "chain %d: %s", i, why.c_str());
+            d.n = (d.w + d.h + 1) / 2;
+            d.mask = nullptr;   // the model keeps its own copy
+        }
+        if (d.n < 1 || d.n > 512) return tl::fail(TL_EINVAL, "batched Aztec orders must be in [1, 512] (chain %d)", i);
     }
     tl_status st = tl::make_table(doms[0], *w, thr);
     if (st != TL_OK) return st;
@@ -213,10 +251,12 @@ tl_status tl_batch_create(int32_t n, const tl_domain *doms, const tl_weights *w,
         tl::BatchChain &c = b->chains[i];
         uint32_t ng, RS;
         size_t PS;
-        const size_t wds = tl::domino_words(doms[i].n, &ng, &RS, &PS);
+        const size_t wds = tl::domino_words(b->doms[i].n, &ng, &RS, &PS);
+        if (b->masks[i] && b->masks[i]->state_words() != wds)
+            return tl::fail(TL_EINVAL, "chain %d: mask layout does not match its diamond", i);
         c.offset = words;
         c.PS = PS;
-        c.n = (uint32_t)doms[i].n;
+        c.n = (uint32_t)b->doms[i].n;
         c.ng = ng;
         c.RS = RS;
         c.key0 = (uint32_t)seeds[i];
@@ -226,7 +266,7 @@ tl_status tl_batch_create(int32_t n, const tl_domain *doms, const tl_weights *w,
         c.pad = 0;
         words += (wds + 63) / 64 * 64;   // 256-byte aligned chains
         b->lds_max = std::max(b->lds_max, c.lds_bytes);
-        b->sites += 2ull * c.n * c.n - 2ull * c.n + 1ull;
+        b->sites += b->masks[i] ? b->masks[i]->sites() : 2ull * c.n * c.n - 2ull * c.n + 1ull;
         b->owner_bits += 4ull * c.n * c.n;
     }
     if (opt && opt->stream) {
@@ -303,6 +343,8 @@ tl_status tl_batch_sweep(tl_batch *b, uint64_t n)
     if (!b) return tl::fail(TL_EINVAL, "null batch");
     if (n == 0) return TL_OK;
     if (b->t + n > 0xFFFFFFFFull) return tl::fail(TL_EINVAL, "sweep counter would exceed 2^32");
+    if (b->colour_order && 2 * (b->t + n) > 0x100000000ull)
+        return tl::fail(TL_EINVAL, "step counter would exceed 2^32 (random colour order)");
     if (b->graph_q != (uint32_t)n) {
         drop_graph(b);
         const tl_batch::BundleSet *set = nullptr;
@@ -383,16 +425,44 @@ tl_status tl_batch_kernel_time(tl_batch *b, double *ms, uint64_t *launches, uint
     return TL_OK;
 }
 
+tl_status tl_batch_export_size(tl_batch *b, int32_t chain, size_t *bytes, uint32_t *rows, uint32_t *row_bytes)
+{
+    if (!b) return tl::fail(TL_EINVAL, "null batch");
+    if (chain < 0 || chain >= b->count) return tl::fail(TL_EINVAL, "chain %d out of range", chain);
+    uint32_t r = 2u * b->chains[chain].n, rb = r;
+    if (const tl::Model *m = b->masks[chain].get()) m->export_layout(&r, &rb);
+    if (bytes) *bytes = (size_t)r * rb;
+    if (rows) *rows = r;
+    if (row_bytes) *row_bytes = rb;
+    return TL_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Canonical export of one chain into device memory (the diamond's box, or the
+// mask's box).
+hipError_t export_chain(tl_batch *b, int32_t chain, uint8_t *dev)
+{
+    if (tl::Model *m = mask_model(b, chain)) return m->export_canonical(dev, b->stream);
+    return tl::domino_export(chain_dev(b, chain), dev, b->stream);
+}
+
+}  // namespace
+
+extern "C" {
+
 tl_status tl_batch_export(tl_batch *b, int32_t chain, void *host, size_t bytes)
 {
     if (!b || !host) return tl::fail(TL_EINVAL, "null argument");
-    if (chain < 0 || chain >= b->count) return tl::fail(TL_EINVAL, "chain %d out of range", chain);
-    const tl::DominoDev d = chain_dev(b, chain);
-    const size_t need = (size_t)(2 * d.n) * (2 * d.n);
+    size_t need = 0;
+    tl_status st = tl_batch_export_size(b, chain, &need, nullptr, nullptr);
+    if (st != TL_OK) return st;
     if (bytes < need) return tl::fail(TL_EINVAL, "export buffer has %zu bytes, %zu needed", bytes, need);
     uint8_t *dev = nullptr;
     TL_HIP(hipMalloc(&dev, need));
-    hipError_t e = tl::domino_export(d, dev, b->stream);
+    hipError_t e = export_chain(b, chain, dev);
     if (e == hipSuccess) e = hipMemcpyAsync(host, dev, need, hipMemcpyDeviceToHost, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     (void)hipFree(dev);
@@ -403,14 +473,14 @@ tl_status tl_batch_export(tl_batch *b, int32_t chain, void *host, size_t bytes)
 tl_status tl_batch_hash(tl_batch *b, int32_t chain, uint8_t digest[32])
 {
     if (!b || !digest) return tl::fail(TL_EINVAL, "null argument");
-    if (chain < 0 || chain >= b->count) return tl::fail(TL_EINVAL, "chain %d out of range", chain);
-    const tl::DominoDev d = chain_dev(b, chain);
-    const uint32_t rows = 2u * (uint32_t)d.n, rb = 2u * (uint32_t)d.n;
-    const size_t need = (size_t)rows * rb;
+    size_t need = 0;
+    uint32_t rows = 0, rb = 0;
+    tl_status st = tl_batch_export_size(b, chain, &need, &rows, &rb);
+    if (st != TL_OK) return st;
     uint8_t *dev = nullptr;
     TL_HIP(hipMalloc(&dev, need + 32 * (size_t)rows));
     std::vector<uint8_t> rowd(32 * (size_t)rows);
-    hipError_t e = tl::domino_export(d, dev, b->stream);
+    hipError_t e = export_chain(b, chain, dev);
     if (e == hipSuccess) e = tl::hash_rows(dev, rows, rb, dev + need, b->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(rowd.data(), dev + need, rowd.size(), hipMemcpyDeviceToHost, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);

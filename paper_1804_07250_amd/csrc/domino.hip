@@ -564,7 +564,7 @@ __global__ void __launch_bounds__(1024) domino_items_kernel(const TileJob *__res
 // the loop once the counter passes the end of the list.
 __global__ void batch_reset_kernel(uint32_t *counter) { *counter = 0u; }
 
-template <int MODE>
+template <int MODE, bool RANDOM>
 __global__ void __launch_bounds__(1024) domino_batch_kernel(BatchChain *chains, const BatchBundle *bundles,
                                                             const uint32_t *members, uint32_t nbundles,
                                                             uint32_t *counter, uint32_t *planes, uint32_t nsweeps,
@@ -614,8 +614,12 @@ __global__ void __launch_bounds__(1024) domino_batch_kernel(BatchChain *chains, 
             const uint32_t n = ch.n, ng = ch.ng, LRS = 4 * ng, LPS = n * LRS, omega = (n + 1) & 1u;
             const uint32_t tasks = n * ng;
             for (uint32_t s = 0; s < nsweeps; ++s) {
-                const uint32_t t = ch.t + s;
-                for (uint32_t c = 0; c < 2; ++c) {
+                for (uint32_t i = 0; i < 2; ++i) {
+                    uint32_t c = i, t = ch.t + s;
+                    if constexpr (RANDOM) {
+                        t = 2u * t + i;
+                        c = step_colour(t, 2u, ch.key0, ch.key1);
+                    }
                     for (uint32_t task = tid; task < tasks; task += nt) {
                         const uint32_t r = task / ng, gg = task % ng;
                         uint32_t *pN = lds + r * LRS + 4 * gg;
@@ -639,8 +643,12 @@ __global__ void __launch_bounds__(1024) domino_batch_kernel(BatchChain *chains, 
             const uint32_t local = tid - s_first[k], r = local / ng, gg = local % ng;
             uint32_t *pN = lds + s_off[k] + r * LRS + 4 * gg;
             for (uint32_t s = 0; s < nsweeps; ++s) {
-                const uint32_t t = ch.t + s;
-                for (uint32_t c = 0; c < 2; ++c) {
+                for (uint32_t i = 0; i < 2; ++i) {
+                    uint32_t c = i, t = ch.t + s;
+                    if constexpr (RANDOM) {
+                        t = 2u * t + i;
+                        c = step_colour(t, 2u, ch.key0, ch.key1);
+                    }
                     if (has) {
                         if (c == omega)
                             owner_group<MODE>(pN, pN + LPS, pN + 2 * LPS, pN + 3 * LPS, r, gg, c, t, Tall, ch.key0,
@@ -955,16 +963,21 @@ hipError_t domino_items(const TileJob *jobs, const TileItem *items, uint32_t n_i
 
 hipError_t domino_batch_sweeps(BatchChain *chains, const BatchBundle *bundles, const uint32_t *members,
                                uint32_t nbundles, uint32_t *counter, uint32_t *planes, uint32_t nsweeps, const Thr &T,
-                               int metropolis, uint32_t threads, uint32_t workgroups, uint32_t lds_bytes,
-                               hipStream_t s, Timing *tm)
+                               int metropolis, uint32_t colour_order, uint32_t threads, uint32_t workgroups,
+                               uint32_t lds_bytes, hipStream_t s, Timing *tm)
 {
     if (threads == 0 || threads > 1024 || (threads & 63) || lds_bytes > 160u * 1024u - 64u)
         return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(1), 0, s, counter);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    auto k = T.uniform() ? domino_batch_kernel<kUniform>
-                         : (metropolis ? domino_batch_kernel<kMetropolis> : domino_batch_kernel<kHeatBath>);
+    auto k = colour_order
+                 ? (T.uniform() ? domino_batch_kernel<kUniform, true>
+                                : (metropolis ? domino_batch_kernel<kMetropolis, true>
+                                              : domino_batch_kernel<kHeatBath, true>))
+                 : (T.uniform() ? domino_batch_kernel<kUniform, false>
+                                : (metropolis ? domino_batch_kernel<kMetropolis, false>
+                                              : domino_batch_kernel<kHeatBath, false>));
     return launch(tm, 2 * nsweeps, k, dim3(workgroups), dim3(threads), lds_bytes, s, chains, bundles, members,
                   nbundles, counter, planes, nsweeps, T);
 }

@@ -13,6 +13,8 @@ tl_status fail(tl_status st, const char *fmt, ...);
 hipStream_t sampler_stream(const tl_sampler *s);
 // Threshold table of (domain, weights) as returned by tl_thresholds.
 tl_status make_table(const tl_domain &d, const tl_weights &w, std::vector<uint32_t> &thr);
+// Table of the free boundary points of a six-vertex mask (empty otherwise).
+tl_status make_free_table(const tl_domain &d, const tl_weights &w, std::vector<uint32_t> &thr);
 }
 
 #define TL_HIP(call)                                                                          \

@@ -174,10 +174,11 @@ struct BatchBundle {
 // Advance every chain of bundles[0..nbundles) by nsweeps sweeps: one
 // persistent launch; work-groups take bundles from an atomic counter (reset by
 // a small kernel first, so the pair can be captured in a graph).
+// colour_order: 0 fixed, 1 random per step (chain by chain, from its key).
 hipError_t domino_batch_sweeps(BatchChain *chains, const BatchBundle *bundles, const uint32_t *members,
                                uint32_t nbundles, uint32_t *counter, uint32_t *planes, uint32_t nsweeps, const Thr &T,
-                               int metropolis, uint32_t threads, uint32_t workgroups, uint32_t lds_bytes,
-                               hipStream_t s, Timing *tm = nullptr);
+                               int metropolis, uint32_t colour_order, uint32_t threads, uint32_t workgroups,
+                               uint32_t lds_bytes, hipStream_t s, Timing *tm = nullptr);
 
 // ------------------------------------------------------ height-function models
 // Bit-planes of a 1-bit height residual: plane p, row y, word w at

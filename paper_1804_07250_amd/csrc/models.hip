@@ -295,6 +295,49 @@ public:
         attach(state, spare);
         return allocate_region();
     }
+    // Bytes of a masked domain's device tables, each 256-byte aligned: site
+    // planes, anchors, heights, minimal heights, cells, free-edge planes.
+    static size_t al(size_t v) { return (v + 255) / 256 * 256; }
+    size_t region_bytes() const override
+    {
+        if (!region_) return 0;
+        HeightDev d = d_;
+        const size_t words = height_words(d), V = region_->anchor.size(), C = region_->cells.size();
+        return al(words * 4) + 3 * al(V * 4) + al(C) + (region_->free_sites ? al(words * 4) : 0);
+    }
+    bool masked() const override { return region_ != nullptr; }
+    hipError_t attach_region(uint8_t *dev, hipStream_t s) override
+    {
+        if (!region_) return hipSuccess;
+        HeightDev d = d_;
+        const size_t words = height_words(d), V = region_->anchor.size(), C = region_->cells.size();
+        uint8_t *p = dev;
+        site_ = (uint32_t *)p;
+        p += al(words * 4);
+        anchor_ = (int32_t *)p;
+        p += al(V * 4);
+        heights_ = (int32_t *)p;
+        p += al(V * 4);
+        hmin_ = (int32_t *)p;
+        p += al(V * 4);
+        cells_ = p;
+        p += al(C);
+        freep_ = region_->free_sites ? (uint32_t *)p : nullptr;
+        region_owned_ = false;
+        if (site_host_.empty()) pack_points(region_->site, site_host_, [](int32_t v) { return v != 0; });
+        if (freep_ && freep_host_.empty()) pack_points(region_->site, freep_host_, [](int32_t v) { return v == 2; });
+        hipError_t e = hipMemcpyAsync(site_, site_host_.data(), words * 4, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess && freep_)
+            e = hipMemcpyAsync(freep_, freep_host_.data(), words * 4, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(anchor_, region_->anchor.data(), V * sizeof(int32_t), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(hmin_, region_->hmin.data(), V * sizeof(int32_t), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(cells_, region_->cells.data(), C, hipMemcpyHostToDevice, s);
+        d_.site = site_;
+        d_.freep = freep_;
+        return e;
+    }
     // Device copies of a masked domain's site planes, anchors and cells.
     hipError_t allocate_region()
     {
@@ -328,9 +371,11 @@ public:
         if (owned_ && d_.planes) (void)hipFree(d_.planes);
         if (owned_ && d_.spare) (void)hipFree(d_.spare);
         d_.planes = d_.spare = nullptr;
-        for (void *p : {(void *)site_, (void *)anchor_, (void *)heights_, (void *)hmin_, (void *)cells_,
-                        (void *)freep_})
-            if (p) (void)hipFree(p);
+        if (region_owned_)
+            for (void *p : {(void *)site_, (void *)anchor_, (void *)heights_, (void *)hmin_, (void *)cells_,
+                            (void *)freep_})
+                if (p) (void)hipFree(p);
+        region_owned_ = true;
         site_ = freep_ = nullptr;
         d_.freep = nullptr;
         anchor_ = heights_ = hmin_ = nullptr;
@@ -680,6 +725,8 @@ private:
     bool owned_ = false;
     std::shared_ptr<const HeightRegion> region_;
     uint32_t *site_ = nullptr, *freep_ = nullptr;
+    bool region_owned_ = true;   // false: the tables live in caller-owned memory (attach_region)
+    std::vector<uint32_t> site_host_, freep_host_;   // packed planes the asynchronous uploads read
     int32_t *anchor_ = nullptr, *heights_ = nullptr, *hmin_ = nullptr;
     std::vector<uint32_t> free_thr_;
     uint8_t *cells_ = nullptr;

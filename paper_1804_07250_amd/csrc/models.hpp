@@ -51,6 +51,14 @@ public:
                           TilePlan *p) const = 0;
     virtual void swap_buffers() = 0;
     virtual bool height_family() const = 0;
+    // Device tables of a masked height-model domain placed in caller-owned
+    // memory (served jobs): region_bytes() bytes at dev, filled with
+    // asynchronous copies on stream s from host copies the model keeps; the
+    // caller keeps the memory until the model is released.
+    virtual size_t region_bytes() const { return 0; }
+    virtual hipError_t attach_region(uint8_t *, hipStream_t) { return hipSuccess; }
+    // Masked domain (the kernels read site planes).
+    virtual bool masked() const { return false; }
     // Current state buffer (state_words() words; equal buffers <=> equal states).
     virtual const uint32_t *state() const = 0;
     Timing timing;

@@ -148,12 +148,13 @@ struct Job {
 };
 
 // Device bytes of a job: two state buffers, the canonical export, one digest
-// per export row and the observable's counter.
+// per export row, the observable's counter and, for a masked height-model
+// domain, its tables.
 size_t job_bytes(const tl::Model &m, uint32_t *rows, uint32_t *row_bytes)
 {
     m.export_layout(rows, row_bytes);
     return 2 * align_up(m.state_words() * sizeof(uint32_t)) + align_up((size_t)*rows * *row_bytes) +
-           align_up(32 * (size_t)*rows) + kAlign;
+           align_up(32 * (size_t)*rows) + kAlign + align_up(m.region_bytes());
 }
 
 struct Tick {
@@ -174,6 +175,7 @@ struct tl_server {
     size_t budget = 0;
     int32_t max_slots = 0;
     uint32_t quantum = 8;   // sweeps per tick of a weighted job (4x for one-bit jobs)
+    uint32_t order = 0;     // colour order of every job: 0 fixed, 1 random per step
     int device = 0;
     std::chrono::steady_clock::time_point t0;
     std::mutex mu;
@@ -258,6 +260,7 @@ int32_t start_job(tl_server *sv, Job &j)
     j.h_res = (uint8_t *)sv->pinned.get(32 * (size_t)j.rows + 8, &j.h_cls);
     if (!j.h_res) return TL_ENOMEM;
     j.model->attach(a, b);
+    if (j.model->attach_region((uint8_t *)j.d_bin + kAlign, sv->stream) != hipSuccess) return TL_EDEVICE;
     uint32_t w = 0, h = 0;
     j.model->cell_box(&w, &h);
     j.obs_B = std::max(w, h);
@@ -400,13 +403,14 @@ bool tick(tl_server *sv)
     tl::TileItem *hi = reinterpret_cast<tl::TileItem *>(sv->h_buf[slot] + joff);
     tl::TileJob *dj = reinterpret_cast<tl::TileJob *>(sv->d_buf);
     tl::TileItem *di = reinterpret_cast<tl::TileItem *>(sv->d_buf + joff);
-    // one launch per kernel instantiation: height jobs grouped by rule and
-    // table layout (one-bit jobs ride with the heat-bath ones of the 5-class
-    // layout), then the domino jobs
+    // one launch per kernel instantiation: height jobs grouped by masked
+    // domain, rule and table layout (one-bit jobs ride with the heat-bath ones
+    // of the 5-class layout), then the domino jobs
     auto key = [&](size_t i) {
         if (!run[i]->model->height_family()) return 100u;
-        if (jobs[i].mode == tl::kModeUniform) return (uint32_t)tl::kTableSum;
-        return (jobs[i].mode == tl::kModeMetropolis ? 3u : 0u) + jobs[i].kind;
+        const uint32_t m = run[i]->model->masked() ? 10u : 0u;
+        if (jobs[i].mode == tl::kModeUniform) return m + (uint32_t)tl::kTableSum;
+        return m + (jobs[i].mode == tl::kModeMetropolis ? 3u : 0u) + jobs[i].kind;
     };
     std::vector<size_t> order(run.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = i;
@@ -441,11 +445,11 @@ bool tick(tl_server *sv)
             hipStream_t st = k == 0 ? sv->stream : sv->side;
             if (e != hipSuccess) break;
             if (gr.key == 100u)
-                e = tl::domino_items(dj, di + gr.first, gr.count, gr.threads, gr.lds, 0u, st);
+                e = tl::domino_items(dj, di + gr.first, gr.count, gr.threads, gr.lds, sv->order, st);
             else
                 e = tl::height_items(dj, di + gr.first, gr.count, gr.threads, gr.lds,
-                                     gr.key >= 3u ? (uint32_t)tl::kModeMetropolis : (uint32_t)tl::kModeHeatBath,
-                                     gr.key % 3u, 0u, 0u, st);
+                                     gr.key % 10u >= 3u ? (uint32_t)tl::kModeMetropolis : (uint32_t)tl::kModeHeatBath,
+                                     gr.key % 10u % 3u, sv->order, gr.key >= 10u ? 1u : 0u, st);
         }
         if (split && e == hipSuccess) e = hipEventRecord(sv->ev_side, sv->side);
         if (split && e == hipSuccess) e = hipStreamWaitEvent(sv->stream, sv->ev_side, 0);
@@ -603,7 +607,7 @@ extern "C" {
 tl_status tl_server_create(size_t hbm_budget_bytes, int32_t max_slots, const tl_options *opt, tl_server **out)
 {
     if (!out || hbm_budget_bytes == 0 || max_slots <= 0) return tl::fail(TL_EINVAL, "invalid server arguments");
-    if (opt && opt->colour_order) return tl::fail(TL_EINVAL, "servers run the fixed colour order");
+    if (opt && opt->colour_order > 1) return tl::fail(TL_EINVAL, "unknown colour order %u", opt->colour_order);
     if (opt && opt->device_buf) return tl::fail(TL_EINVAL, "servers allocate their own state pool");
     *out = nullptr;
     std::unique_ptr<tl_server> sv(new (std::nothrow) tl_server());
@@ -611,6 +615,7 @@ tl_status tl_server_create(size_t hbm_budget_bytes, int32_t max_slots, const tl_
     sv->budget = hbm_budget_bytes;
     sv->max_slots = max_slots;
     if (opt && opt->sweeps_per_launch) sv->quantum = opt->sweeps_per_launch;
+    if (opt) sv->order = opt->colour_order;
     sv->t0 = std::chrono::steady_clock::now();
     if (hipGetDevice(&sv->device) != hipSuccess) return tl::fail(TL_EDEVICE, "no current device");
     hipError_t e = hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking);
@@ -634,20 +639,28 @@ tl_status tl_server_submit(tl_server *sv, const tl_domain *dom, const tl_weights
                            uint64_t n_sweeps, uint64_t *ticket)
 {
     if (!sv || !dom || !w || !ticket) return tl::fail(TL_EINVAL, "null argument");
-    if (dom->shape == TL_MASK) return tl::fail(TL_EINVAL, "served jobs take the fixed shapes");
     std::vector<uint32_t> thr;
     tl_status st = tl::make_table(*dom, *w, thr);
     if (st != TL_OK) return st;
+    std::vector<uint32_t> thr_free;
+    st = tl::make_free_table(*dom, *w, thr_free);
+    if (st != TL_OK) return st;
     std::string why;
-    std::unique_ptr<tl::Model> m = tl::make_model(*dom, why);
-    if (!m) return tl::fail(TL_EINVAL, "%s", why.c_str());
+    tl_status mst = TL_EINVAL;
+    std::unique_ptr<tl::Model> m = tl::make_model(*dom, why, &mst);
+    if (!m) return tl::fail(mst, "%s", why.c_str());
+    m->order = sv->order;
+    m->set_boundary_table(thr_free);
     if (n_sweeps > 0xFFFFFFFFull) return tl::fail(TL_EINVAL, "sweep count exceeds 2^32");
+    if (sv->order && n_sweeps * (uint64_t)m->colours() > 0x100000000ull)
+        return tl::fail(TL_EINVAL, "step counter would exceed 2^32 (random colour order)");
     std::unique_ptr<Job> j(new (std::nothrow) Job());
     if (!j) return tl::fail(TL_ENOMEM, "host allocation failed");
     j->bytes = job_bytes(*m, &j->rows, &j->row_bytes);
     if (align_up(j->bytes) > sv->budget / kAlign * kAlign)
         return tl::fail(TL_EBUDGET, "job needs %zu bytes, budget is %zu", j->bytes, sv->budget);
     j->dom = *dom;
+    j->dom.mask = nullptr;   // the model keeps its own copy of a mask
     j->seed = seed;
     j->sweeps = n_sweeps;
     j->metro = w->rule == TL_METROPOLIS;

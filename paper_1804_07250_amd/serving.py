@@ -43,6 +43,7 @@ def _bind():
         "tl_batch_info": [vp, ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u32), ctypes.POINTER(u32)],
         "tl_batch_set_timing": [vp, i32],
         "tl_batch_kernel_time": [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(u64), ctypes.POINTER(u64)],
+        "tl_batch_export_size": [vp, i32, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(u32), ctypes.POINTER(u32)],
         "tl_batch_export": [vp, i32, vp, ctypes.c_size_t],
         "tl_batch_hash": [vp, i32, ctypes.POINTER(ctypes.c_uint8)],
         "tl_batch_destroy": [vp],
@@ -69,7 +70,7 @@ class Batch:
         L = _bind()
         n = len(doms)
         self.n = n
-        self.orders = [d.n for d in doms]
+        self._doms = list(doms)   # keeps mask bytes alive until the library has copied them
         arr = (tl_domain * n)(*doms)
         sd = (ctypes.c_uint64 * n)(*[int(s) for s in seeds])
         self._h = ctypes.c_void_p()
@@ -104,8 +105,11 @@ class Batch:
         return ms.value, la.value, st.value
 
     def export(self, chain):
-        n = self.orders[chain]
-        buf = np.empty((2 * n, 2 * n), dtype=np.uint8)
+        """Canonical export of one chain: the diamond's 2n x 2n box, or the
+        mask's h x w box."""
+        size, rows, rb = ctypes.c_size_t(), ctypes.c_uint32(), ctypes.c_uint32()
+        _check(_bind().tl_batch_export_size(self._h, chain, ctypes.byref(size), ctypes.byref(rows), ctypes.byref(rb)))
+        buf = np.empty((rows.value, rb.value), dtype=np.uint8)
         _check(_bind().tl_batch_export(self._h, chain, buf.ctypes.data, buf.nbytes))
         return buf
 
