@@ -82,9 +82,11 @@ def lib():
         L.or_sixv_flip.argtypes = [ctypes.c_int, i32p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.or_sixv_sweeps.argtypes = [ctypes.c_int, i32p, u32p, ctypes.c_int, ctypes.c_uint64,
                                      ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, ctypes.c_void_p]
-        L.or_sixvr_flip.argtypes = [ctypes.c_int, ctypes.c_int, i32p, u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.or_sixvr_flip.argtypes = [ctypes.c_int, ctypes.c_int, i32p, u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_int]
         L.or_sixvr_sweeps.argtypes = [ctypes.c_int, ctypes.c_int, i32p, u8p, u32p, u32p, ctypes.c_int,
-                                      ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int]
+                                      ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_int, ctypes.c_int]
         L.or_lozr_flip.argtypes = [ctypes.c_int, ctypes.c_int, i32p, u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.or_lozr_sweeps.argtypes = [ctypes.c_int, ctypes.c_int, i32p, u8p, u32p, ctypes.c_int, ctypes.c_uint64,
                                      ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int]
@@ -251,24 +253,47 @@ def sixv_ratios6(a1, a2, b1, b2, c1, c2):
     return out
 
 
-def sixv_free_ratios6(a1, a2, b1, b2, c1, c2):
-    """W_up / W_down of a flip at a point of a free north edge (the boundary
-    variation of the c-flip, Section 1.2), for each context
-    (SW at m+1) + 2 (SE at m+1): the point at m-1 or m+1, its west, east and
-    south neighbours at m, the two diagonal points below it at m+1 or m-1;
-    the weight of a state is the product over the two cells below the point
-    (the only vertices it touches) of the weight of the cell's type."""
+# Free sides of a six-vertex domain: the point's missing neighbour, its three
+# neighbours and the two diagonal points of its context (first, second), as
+# offsets (dI, dJ) from the point.
+FREE_SIDES = {
+    "north": {"missing": (0, 1), "diag": ((-1, -1), (1, -1))},
+    "south": {"missing": (0, -1), "diag": ((-1, 1), (1, 1))},
+    "east": {"missing": (1, 0), "diag": ((-1, -1), (-1, 1))},
+    "west": {"missing": (-1, 0), "diag": ((1, -1), (1, 1))},
+}
+
+
+def sixv_free_ratios6(a1, a2, b1, b2, c1, c2, side="north"):
+    """W_up / W_down of a flip at a point of a free side (the boundary
+    variation of the c-flip, Section 1.2), for each context (first diagonal
+    at m+1) + 2 (second diagonal at m+1): the point at m-1 or m+1, its three
+    neighbours at m, its two diagonal points on the domain's side at m+1 or
+    m-1; the weight of a state is the product over the two cells the point
+    touches (the cells beside its three neighbours' edges) of the weight of
+    the cell's type."""
     w = {"a1": Fraction(a1), "a2": Fraction(a2), "b1": Fraction(b1), "b2": Fraction(b2),
          "c1": Fraction(c1), "c2": Fraction(c2)}
+    miss = FREE_SIDES[side]["missing"]
+    d0, d1 = FREE_SIDES[side]["diag"]
     out = []
     for ctx in range(4):
         m = 10
-        hSW = m + 1 if ctx & 1 else m - 1
-        hSE = m + 1 if ctx & 2 else m - 1
+        h = {(1, 0): m, (-1, 0): m, (0, 1): m, (0, -1): m}
+        del h[miss]
+        h[d0] = m + 1 if ctx & 1 else m - 1
+        h[d1] = m + 1 if ctx & 2 else m - 1
 
         def weight(f):
-            # cell left of the point: corners SW, S, W, point; right: S, SE, point, E
-            return w[sixv_vertex_type(hSW, m, m, f)] * w[sixv_vertex_type(m, hSE, f, m)]
+            hh = dict(h)
+            hh[(0, 0)] = f
+            W = Fraction(1)
+            # the cells with the point as a corner whose four corners are all known
+            for cx, cy in ((0, 0), (-1, 0), (-1, -1), (0, -1)):
+                corners = [(cx, cy), (cx + 1, cy), (cx, cy + 1), (cx + 1, cy + 1)]
+                if all(c in hh for c in corners):
+                    W *= w[sixv_vertex_type(*[hh[c] for c in corners])]
+            return W
 
         out.append(weight(m + 1) / weight(m - 1))
     return out

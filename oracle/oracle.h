@@ -109,9 +109,10 @@ int  or_lozr_sweeps(int W, int H, int32_t *Hs, const uint8_t *site, const uint32
  * site[J*(W+1) + I] = 1 for points whose four cells lie in the domain, 2 for
  * points on a free north edge (flips by thr_free, which may be NULL if there
  * are none). */
-int  or_sixvr_flip(int W, int H, int32_t *h, const uint8_t *site, int I, int J, int up);
+int  or_sixvr_flip(int W, int H, int32_t *h, const uint8_t *site, int side, int I, int J, int up);
 int  or_sixvr_sweeps(int W, int H, int32_t *h, const uint8_t *site, const uint32_t *thr, const uint32_t *thr_free,
-                     int metropolis, uint64_t seed, uint32_t t0, uint32_t nsweeps, int random_colours);
+                     int metropolis, uint64_t seed, uint32_t t0, uint32_t nsweeps, int random_colours, int side,
+                     int ox, int oy);
 
 #ifdef __cplusplus
 }

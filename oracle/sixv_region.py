@@ -73,18 +73,35 @@ def _edges(inside, I, J):
             yield (I2, J2), ir + il, sign * (1 if ir else -1)
 
 
-def _free_edge(inside, u, v):
-    """Is the boundary edge u-v the north side of a domain cell?"""
+def _free_edge(inside, u, v, side="north"):
+    """Is the boundary edge u-v the `side` side (north, south, east or west)
+    of a domain cell?"""
     (I, J), (I2, J2) = u, v
-    return J == J2 and inside(min(I, I2), J - 1) and not inside(min(I, I2), J)
+    if side in ("north", "south"):
+        if J != J2:
+            return False
+        below, above = inside(min(I, I2), J - 1), inside(min(I, I2), J)
+        return (below and not above) if side == "north" else (above and not below)
+    if I != I2:
+        return False
+    left, right = inside(I - 1, min(J, J2)), inside(I, min(J, J2))
+    return (left and not right) if side == "east" else (right and not left)
 
 
-def sixv_boundary_heights(mask, free_north=False):
+def _side(free_north, free_side):
+    if free_side is not None and free_side not in ("north", "south", "east", "west"):
+        raise ValueError("unknown free side %r" % (free_side,))
+    return free_side or ("north" if free_north else None)
+
+
+def sixv_boundary_heights(mask, free_north=False, free_side=None):
     """Heights of the fixed boundary points under the domain-wall type
     boundary; raises Untileable if the walk around the boundary does not close
-    up.  With free_north the legs through the north sides of cells are free:
+    up.  With a free side (free_side one of north, south, east, west;
+    free_north for north) the legs through those sides of cells are free:
     those boundary edges are not walked, and the points whose boundary edges
     are all such edges are free (absent from the result)."""
+    side = _side(free_north, free_side)
     m, w, h, inside = _cells(mask)
     pts, sites = sixv_points(m)
     order = [(I, J) for J in range(h + 1) for I in range(w + 1) if pts[J, I]]
@@ -94,7 +111,7 @@ def sixv_boundary_heights(mask, free_north=False):
     while stack:
         u = stack.pop()
         for v, ncells, dh in _edges(inside, *u):
-            if ncells != 1 or (free_north and _free_edge(inside, u, v)):
+            if ncells != 1 or (side and _free_edge(inside, u, v, side)):
                 continue
             hv = hb[u] + dh
             if v in hb:
@@ -106,8 +123,8 @@ def sixv_boundary_heights(mask, free_north=False):
     return hb
 
 
-def sixv_free_points(mask):
-    """Points whose boundary edges are all north sides of domain cells."""
+def sixv_free_points(mask, side="north"):
+    """Points whose boundary edges are all `side` sides of domain cells."""
     m, w, h, inside = _cells(mask)
     pts, sites = sixv_points(m)
     free = np.zeros_like(pts)
@@ -116,19 +133,20 @@ def sixv_free_points(mask):
             if not pts[J, I] or sites[J, I]:
                 continue
             bnd = [(v, ncells) for v, ncells, _ in _edges(inside, I, J) if ncells == 1]
-            free[J, I] = all(_free_edge(inside, (I, J), v) for v, _ in bnd)
+            free[J, I] = all(_free_edge(inside, (I, J), v, side) for v, _ in bnd)
     return free
 
 
-def sixv_extremal_heights(mask, free_north=False):
+def sixv_extremal_heights(mask, free_north=False, free_side=None):
     """(h_max, h_min) as (h+1) x (w+1) int64 arrays (I32MIN off the domain);
     raises Untileable when no configuration meets the boundary, ValueError
     when free edges split the fixed boundary into several pieces."""
+    side = _side(free_north, free_side)
     m, w, h, inside = _cells(mask)
     check_region(m)
     pts, sites = sixv_points(m)
-    hb = sixv_boundary_heights(m, free_north)
-    free = sixv_free_points(m) if free_north else np.zeros_like(pts)
+    hb = sixv_boundary_heights(m, free_side=side)
+    free = sixv_free_points(m, side) if side else np.zeros_like(pts)
     if any(not sites[J, I] and not free[J, I] for J in range(h + 1) for I in range(w + 1)
            if pts[J, I] and (I, J) not in hb):
         raise ValueError("the fixed boundary is not one piece")
@@ -173,7 +191,7 @@ class SixVertexRegionOracle:
     domain-wall square) on a general domain with domain-wall type boundary."""
 
     def __init__(self, mask, thr, metropolis=False, seed=0, obs_every=0, bin_=1, init="min",
-                 random_colours=False, free_north=False, thr_free=None):
+                 random_colours=False, free_north=False, thr_free=None, free_side=None):
         from . import _p, lib
         self._lib, self._pp = lib, _p
         m = np.asarray(mask, dtype=bool)
@@ -181,11 +199,17 @@ class SixVertexRegionOracle:
         self.h_, self.w = m.shape
         pts, sites = sixv_points(m)
         self.points = pts
-        self.free = sixv_free_points(m) if free_north else np.zeros_like(pts)
-        # site codes: 1 interior, 2 on a free north edge
+        side = _side(free_north, free_side)
+        self.free = sixv_free_points(m, side) if side else np.zeros_like(pts)
+        # site codes: 1 interior, 2 on the free side; the side's code for the
+        # C step, and the offsets of the draws (two rows / columns for a free
+        # south / west side, whose points then sit inside the model's box)
         self.site = np.ascontiguousarray(sites.astype(np.uint8) + 2 * self.free.astype(np.uint8))
+        self.side_code = {None: 0, "north": 1, "south": 2, "east": 3, "west": 4}[side]
+        self.ox = 2 if side == "west" else 0
+        self.oy = 2 if side == "south" else 0
         self.thr_free = np.asarray(thr_free if thr_free is not None else [0] * 8, dtype=np.uint32)
-        self.hmax, self.hmin = sixv_extremal_heights(m, free_north)
+        self.hmax, self.hmin = sixv_extremal_heights(m, free_side=side)
         self.H = np.ascontiguousarray((self.hmax if init == "max" else self.hmin).astype(np.int32))
         self.thr = np.asarray(thr, dtype=np.uint32)
         self.metropolis = metropolis
@@ -204,7 +228,8 @@ class SixVertexRegionOracle:
         p = self._pp
         self._lib().or_sixvr_sweeps(self.w, self.h_, p(self.H, ctypes.c_int32), p(self.site, ctypes.c_uint8),
                                     p(self.thr, ctypes.c_uint32), p(self.thr_free, ctypes.c_uint32),
-                                    int(self.metropolis), self.seed, self.t, n, int(self.random_colours))
+                                    int(self.metropolis), self.seed, self.t, n, int(self.random_colours),
+                                    self.side_code, self.ox, self.oy)
         self.t += n
 
     def sweep(self, nsweeps):
@@ -237,7 +262,7 @@ class SixVertexRegionOracle:
     def flip(self, I, J, up):
         p = self._pp
         return self._lib().or_sixvr_flip(self.w, self.h_, p(self.H, ctypes.c_int32), p(self.site, ctypes.c_uint8),
-                                         I, J, int(up))
+                                         self.side_code, I, J, int(up))
 
     def observe(self, bin_=None):
         """Type-c cells, in total and per bin of bin_ x bin_ cells."""

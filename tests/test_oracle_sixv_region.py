@@ -28,18 +28,20 @@ import test_oracle_sixvertex as tos
 I32MIN = np.iinfo(np.int32).min
 
 
-def enumerate_configs(mask, free_north=False):
+def enumerate_configs(mask, free_north=False, free_side=None):
     """Every height function of the domain (brute force): sites (and free
-    points) in row-major order take a value one away from their west and
-    south neighbours (both already known), the east and north neighbours that
-    are fixed are checked, and a complete assignment is kept if every cell side
-    joins heights one apart."""
+    points) in row-major order take a value one away from their west or
+    south neighbour (one of them is known: a free point of a south or west
+    side may lack it, then both values one away from its known neighbour are
+    tried), and a complete assignment is kept if every cell side joins
+    heights one apart."""
+    side = free_side or ("north" if free_north else None)
     pts, sites = oracle.sixv_points(mask)
-    hb = oracle.sixv_boundary_heights(mask, free_north)
+    hb = oracle.sixv_boundary_heights(mask, free_side=side)
     H = np.full(pts.shape, I32MIN, dtype=np.int64)
     for (I, J), v in hb.items():
         H[J, I] = v
-    free = oracle.sixv_free_points(mask) if free_north else np.zeros_like(pts)
+    free = oracle.sixv_free_points(mask, side) if side else np.zeros_like(pts)
     order = [(I, J) for J in range(pts.shape[0]) for I in range(pts.shape[1]) if sites[J, I] or free[J, I]]
     fixed = {(I, J) for (I, J) in hb}
     out = []
@@ -61,8 +63,15 @@ def enumerate_configs(mask, free_north=False):
                 out.append(H.copy())
             return
         I, J = order[i]
-        for v in (H[J, I - 1] - 1, H[J, I - 1] + 1):
-            if abs(v - H[J - 1, I]) != 1:
+
+        def known(a, b):
+            return 0 <= b < H.shape[0] and 0 <= a < H.shape[1] and H[b, a] != I32MIN
+
+        base = H[J, I - 1] if known(I - 1, J) else H[J - 1, I]
+        for v in (base - 1, base + 1):
+            if known(I - 1, J) and abs(v - H[J, I - 1]) != 1:
+                continue
+            if known(I, J - 1) and abs(v - H[J - 1, I]) != 1:
                 continue
             if (I + 1, J) in fixed and abs(v - H[J, I + 1]) != 1:
                 continue
@@ -361,3 +370,147 @@ def test_free_north_refuses_split_boundaries():
     # an L-shape's free north edges cut its fixed boundary in two
     with pytest.raises(ValueError):
         oracle.sixv_extremal_heights(l_shape(6, 3, 3), free_north=True)
+
+
+# ------------------------------------------------- free south, east, west sides
+# The same pins for a free side anywhere: the enumerated configurations are
+# what the chain's flips reach from either extreme, every flip at a free point
+# changes the configuration weight by the free table's entry, and the chain's
+# law is the weight product (chi-square, with the interior table's product
+# form as a negative control).  Wide boxes for north / south, tall for east /
+# west (the others have no configuration).
+
+SIDE_BOXES = {"north": (3, 4), "south": (3, 4), "east": (4, 3), "west": (4, 3)}
+
+
+def side_chain(mask, wts, side, seed=1, init="min", thr_free=None, **kw):
+    thr = oracle.table_from_ratios(oracle.sixv_ratios6(*wts), False)
+    if thr_free is None:
+        thr_free = oracle.table_from_ratios(oracle.sixv_free_ratios6(*wts, side=side), False)
+    return oracle.SixVertexRegionOracle(mask, thr, seed=seed, init=init, free_side=side, thr_free=thr_free, **kw)
+
+
+class _View:
+    def __init__(self, ch):
+        self.ch = ch
+
+    def sweep(self, n):
+        self.ch.sweep(n)
+
+    def export(self):
+        return self.ch.export().astype(np.int64)
+
+
+@pytest.mark.parametrize("side", ["north", "south", "east", "west"])
+def test_free_side_extremes_and_connectivity(side):
+    m = ones(*SIDE_BOXES[side])
+    configs = enumerate_configs(m, free_side=side)
+    assert len(configs) > 3
+    hmax, hmin = oracle.sixv_extremal_heights(m, free_side=side)
+    stack = np.stack(configs)
+    pts = hmax != I32MIN
+    assert (stack.max(axis=0)[pts] == hmax[pts]).all() and (stack.min(axis=0)[pts] == hmin[pts]).all()
+    free = oracle.sixv_free_points(m, side)
+    assert free.sum() == (SIDE_BOXES[side][1] - 1 if side in ("north", "south") else SIDE_BOXES[side][0] - 1)
+    keys = {c.tobytes() for c in configs}
+    for init in ("min", "max"):
+        ch = side_chain(m, STOCH, side, init=init)
+        get = lambda: ch.H.copy()
+
+        def put(s_):
+            ch.H[:] = s_
+
+        seen = bfs(ch, get, put, lambda: ch.export().astype(np.int64).tobytes())
+        assert set(seen) == keys
+
+
+@pytest.mark.parametrize("side", ["north", "south", "east", "west"])
+def test_free_side_table_is_the_configuration_weight_ratio(side):
+    m = ones(*SIDE_BOXES[side])
+    wts = (2, 1, Fraction(3, 10), Fraction(7, 10), Fraction(1, 2), 3)
+    R = oracle.sixv_free_ratios6(*wts, side=side)
+    free = oracle.sixv_free_points(m, side)
+    miss = oracle.FREE_SIDES[side]["missing"]
+    d0, d1 = oracle.FREE_SIDES[side]["diag"]
+    nbrs = [d for d in ((1, 0), (-1, 0), (0, 1), (0, -1)) if d != miss]
+    checked = 0
+    for H in enumerate_configs(m, free_side=side):
+        for J, I in np.argwhere(free):
+            vals = [H[J + dj, I + di] for di, dj in nbrs]
+            if len(set(vals)) != 1 or H[J, I] != vals[0] - 1:
+                continue
+            e = vals[0]
+            ctx = (1 if H[J + d0[1], I + d0[0]] == e + 1 else 0) | (2 if H[J + d1[1], I + d1[0]] == e + 1 else 0)
+            up = H.copy()
+            up[J, I] = e + 1
+            assert weight6(m, up, wts) / weight6(m, H, wts) == R[ctx]
+            checked += 1
+    assert checked > 5
+
+
+@pytest.mark.parametrize("side", ["south", "east", "west"])
+def test_free_side_law(side):
+    m = ones(*SIDE_BOXES[side])
+    wts = STOCH
+    configs = enumerate_configs(m, free_side=side)
+    w = {c.astype(np.int64).tobytes(): float(weight6(m, c, wts)) for c in configs}
+    Z = sum(w.values())
+    probs = {k: v / Z for k, v in w.items()}
+    assert chi_square_pvalue(_View(side_chain(m, wts, side, seed=41)), probs, 12000, 3) > 1e-3
+    # negative control: the north table on this side gives another law
+    wrong = oracle.table_from_ratios(oracle.sixv_free_ratios6(*wts, side="north"), False)
+    if list(wrong) != list(oracle.table_from_ratios(oracle.sixv_free_ratios6(*wts, side=side), False)):
+        assert chi_square_pvalue(_View(side_chain(m, wts, side, seed=41, thr_free=wrong)), probs, 12000, 3) < 1e-6
+
+
+def test_free_side_tables_differ_by_side():
+    # the four sides change different cells, so their tables differ for
+    # generic weights; the north one has the closed form of its two cells
+    wts = (2, 1, Fraction(3, 10), Fraction(7, 10), Fraction(1, 2), 3)
+    tabs = {s_: oracle.sixv_free_ratios6(*wts, side=s_) for s_ in ("north", "south", "east", "west")}
+    assert len({tuple(v) for v in tabs.values()}) == 4
+    # a closed form for the north table (two cells below the point)
+    a1, a2, b1, b2, c1, c2 = [Fraction(x) for x in wts]
+    north = [(c2 / a1 if ctx & 1 else a2 / c1) * (c1 / b2 if ctx & 2 else b1 / c2) for ctx in range(4)]
+    assert tabs["north"] == north
+
+
+@pytest.mark.parametrize("side", ["north", "south", "east", "west"])
+def test_free_side_draws_use_offsets(side):
+    # a free south (west) side keys the draws two rows (columns) up (right):
+    # the chain equals a step-by-step replay of two sweeps, in plain Python,
+    # with those keys, the side's neighbours and contexts, and the tables
+    m = ones(*SIDE_BOXES[side])
+    wts = STOCH
+    ch = side_chain(m, wts, side, seed=9, init="max")
+    ox, oy = (2, 0) if side == "west" else (0, 2) if side == "south" else (0, 0)
+    assert (ch.ox, ch.oy) == (ox, oy)
+    thr = oracle.table_from_ratios(oracle.sixv_ratios6(*wts), False)
+    thr_free = oracle.table_from_ratios(oracle.sixv_free_ratios6(*wts, side=side), False)
+    miss = oracle.FREE_SIDES[side]["missing"]
+    d0, d1 = oracle.FREE_SIDES[side]["diag"]
+    H = ch.H.astype(np.int64).copy()
+    site = ch.site
+    for t in range(2):
+        for c in range(4):
+            for J in range(H.shape[0]):
+                for I in range(H.shape[1]):
+                    if not site[J, I] or (I & 1) + 2 * (J & 1) != c:
+                        continue
+                    nb = [d for d in ((1, 0), (-1, 0), (0, 1), (0, -1)) if site[J, I] == 1 or d != miss]
+                    vals = {H[J + dj, I + di] for di, dj in nb}
+                    if len(vals) != 1:
+                        continue
+                    e = vals.pop()
+                    if site[J, I] == 1:
+                        k = sum(bit for (di, dj), bit in (((1, 1), 1), ((-1, 1), 2), ((-1, -1), 4), ((1, -1), 8))
+                                if H[J + dj, I + di] == e + 1)
+                        T = thr[k]
+                    else:
+                        k = (1 if H[J + d0[1], I + d0[0]] == e + 1 else 0) | (2 if H[J + d1[1], I + d1[0]] == e + 1
+                                                                              else 0)
+                        T = thr_free[k]
+                    u = oracle.site_uniform(9, J + oy, (I + ox) >> 1, t, c)
+                    H[J, I] = e + 1 if u < T else e - 1
+    ch.sweep(2)
+    assert (ch.H.astype(np.int64) == H).all()
