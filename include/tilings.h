@@ -116,19 +116,28 @@ typedef struct {
     int32_t init;    /* tl_init */
     int32_t w, h;    /* TL_MASK: box of the mask, in faces */
     const uint8_t *mask; /* TL_MASK: h rows of w bytes, nonzero = face in the domain */
-    uint32_t flags;  /* TL_FREE_NORTH (six-vertex masks only), else 0 */
+    uint32_t flags;  /* one TL_FREE_* side (six-vertex masks only), else 0 */
 } tl_domain;
 
 /* Free boundary (Section 1.2: boundary faces need variations of the c-flip).
- * TL_FREE_NORTH leaves the legs through the north sides of the cells of a
- * six-vertex mask free instead of empty: the boundary points all of whose
- * boundary edges are such sides move too, flipping when their west, east and
- * south neighbours share a height m (no north neighbour).  Such a flip changes
- * only the two cells below the point, so it has its own table over the
- * context (SW at m+1) + 2 (SE at m+1), built from all six weights (weight kinds
- * TL_W_UNIFORM and TL_W_SIXVERTEX6 only); the rest of the boundary keeps the
- * domain-wall type legs and must be one piece (TL_EINVAL otherwise). */
+ * One of TL_FREE_NORTH, TL_FREE_SOUTH, TL_FREE_EAST, TL_FREE_WEST leaves the
+ * legs through that side of the cells of a six-vertex mask free instead of
+ * fixed: the boundary points all of whose boundary edges are such sides move
+ * too, flipping when their three other neighbours share a height m.  Such a
+ * flip changes only the two cells beside those neighbours' edges, so it has
+ * its own table over the context (first diagonal at m+1) + 2 (second diagonal
+ * at m+1), the diagonals being the two points beside those cells: north SW,
+ * SE; south NW, NE; east SW, NW; west SE, NE; built from all six weights
+ * (weight kinds TL_W_UNIFORM and TL_W_SIXVERTEX6 only).  The rest of the
+ * boundary keeps the domain-wall type legs and must be one piece (TL_EINVAL
+ * otherwise); one free side per domain.  A free south (west) side keys the
+ * draws of point (I, J) as those of point (I, J + 2) ((I + 2, J)) of the
+ * model's box, so that its points are inner points there (colours are those
+ * of (I, J)). */
 #define TL_FREE_NORTH 1u
+#define TL_FREE_SOUTH 2u
+#define TL_FREE_EAST 4u
+#define TL_FREE_WEST 8u
 
 /* Weights (Section 1.1.1 edge and volume weights; Section 1.2 vertex weights).
  * Two-periodic: a crossed edge weighs a when its even endpoint (x+y even in

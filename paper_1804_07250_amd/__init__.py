@@ -125,22 +125,25 @@ def _check(st):
         raise TlError(st, lib().tl_last_error().decode())
 
 
-TL_FREE_NORTH = 1
+TL_FREE_NORTH, TL_FREE_SOUTH, TL_FREE_EAST, TL_FREE_WEST = 1, 2, 4, 8
+FREE_SIDE_FLAGS = {"north": TL_FREE_NORTH, "south": TL_FREE_SOUTH, "east": TL_FREE_EAST, "west": TL_FREE_WEST}
 
 
-def domain(model, n=0, a=0, b=0, c=0, init=TL_INIT_MIN, mask=None, free_north=False):
+def domain(model, n=0, a=0, b=0, c=0, init=TL_INIT_MIN, mask=None, free_north=False, free_side=None):
     """A domain: the model's fixed shape (Aztec diamond of order n, a x b x c
     hexagon, N x N domain-wall square), or with `mask` the TL_MASK shape:
     (h, w) cells for dominoes and six-vertex domains, (h, w, 2) unit
-    triangles for lozenges, row 0 southmost, nonzero = inside.  free_north:
-    six-vertex domains whose north edges are free.  The returned struct keeps
-    the mask's bytes alive; the library copies them when a sampler is created."""
+    triangles for lozenges, row 0 southmost, nonzero = inside.  free_side
+    ("north", "south", "east" or "west"; free_north for "north"): six-vertex
+    domains with that side free.  The returned struct keeps the mask's bytes
+    alive; the library copies them when a sampler is created."""
     if mask is not None:
         m = np.ascontiguousarray(np.asarray(mask) != 0, dtype=np.uint8)
         if m.ndim != (3 if model == TL_LOZENGE else 2) or (model == TL_LOZENGE and m.shape[2] != 2):
             raise ValueError("mask must be (h, w) cells, or (h, w, 2) triangles for lozenges")
         d = tl_domain(model, TL_MASK, 0, 0, 0, 0, init, m.shape[1], m.shape[0],
-                      m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), TL_FREE_NORTH if free_north else 0)
+                      m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                      FREE_SIDE_FLAGS[free_side] if free_side else (TL_FREE_NORTH if free_north else 0))
         d._mask = m
         return d
     shape = {TL_DOMINO: TL_AZTEC, TL_LOZENGE: TL_HEXAGON, TL_SIXVERTEX: TL_DWBC_SQUARE}[model]

@@ -80,6 +80,8 @@ namespace {
 
 tl_status make_thresholds(const tl_domain &d, const tl_weights &w, std::vector<uint32_t> &thr)
 {
+    if (d.flags && (d.model != TL_SIXVERTEX || d.shape != TL_MASK || tl::free_side_of(d.flags) < 0))
+        return fail(TL_EINVAL, "free sides are a six-vertex mask option, one side per domain");
     using tl::Ratio;
     const bool metro = w.rule == TL_METROPOLIS;
     if (w.rule != TL_HEATBATH && w.rule != TL_METROPOLIS) return fail(TL_EINVAL, "unknown rule %d", w.rule);
@@ -159,18 +161,22 @@ tl_status make_thresholds(const tl_domain &d, const tl_weights &w, std::vector<u
     return TL_OK;
 }
 
-// Table of the free north-edge points of a six-vertex domain (empty for any
-// other domain).  Such a flip changes only the two cells below the point: with
-// its west, east and south neighbours at m, the left cell (corners SW, S, W and
-// the point) goes from type c1 (SW at m-1) or a1 (SW at m+1) to a2 or c2, the
-// right one (S, SE, the point, E) from c2 (SE at m-1) or b2 (SE at m+1) to b1
-// or c1, so W_up / W_down = (SW high ? c2/a1 : a2/c1) (SE high ? c1/b2 : b1/c2)
-// over the context (SW high) + 2 (SE high).
+// Table of the free points of a six-vertex domain (empty for any other
+// domain).  Such a flip changes only the two cells beside the point's three
+// neighbours; reading each cell's type off its corners (a1 none of its four
+// edges carries a path, a2 all four, b1 left and right, b2 bottom and top, c1
+// bottom and left, c2 right and top) with the neighbours at m, W_up / W_down
+// over the context (first diagonal high) + 2 (second diagonal high) is
+//   north (cells SW, SE of the point):  (SW ? c2/a1 : a2/c1) (SE ? c1/b2 : b1/c2)
+//   south (cells NW, NE):               (NW ? c1/b1 : b2/c2) (NE ? c2/a2 : a1/c1)
+//   east  (cells SW, NW; diagonals SW, NW): (SW ? c2/a1 : a2/c1) (NW ? c1/b1 : b2/c2)
+//   west  (cells SE, NE; diagonals SE, NE): (SE ? c1/b2 : b1/c2) (NE ? c2/a2 : a1/c1)
 tl_status make_free_thresholds(const tl_domain &d, const tl_weights &w, std::vector<uint32_t> &out)
 {
     using tl::Ratio;
     out.clear();
-    if (d.model != TL_SIXVERTEX || d.shape != TL_MASK || !(d.flags & TL_FREE_NORTH)) return TL_OK;
+    const int side = tl::free_side_of(d.flags);
+    if (d.model != TL_SIXVERTEX || d.shape != TL_MASK || side <= 0) return TL_OK;
     Ratio a1, a2, b1, b2, c1, c2;
     if (w.kind == TL_W_SIXVERTEX6) {
         for (int i = 0; i < 6; ++i)
@@ -182,12 +188,17 @@ tl_status make_free_thresholds(const tl_domain &d, const tl_weights &w, std::vec
         c1 = Ratio::of(w.w[4]);
         c2 = Ratio::of(w.w[5]);
     } else if (w.kind != TL_W_UNIFORM) {
-        return fail(TL_EINVAL, "free north edges need uniform weights or the six vertex weights");
+        return fail(TL_EINVAL, "free sides need uniform weights or the six vertex weights");
     }
     std::vector<Ratio> R;
     for (int ctx = 0; ctx < 4; ++ctx) {
-        const bool sw = ctx & 1, se = ctx & 2;
-        R.push_back((sw ? c2 / a1 : a2 / c1) * (se ? c1 / b2 : b1 / c2));
+        const bool d0 = ctx & 1, d1 = ctx & 2;
+        switch (side) {
+        case 1: R.push_back((d0 ? c2 / a1 : a2 / c1) * (d1 ? c1 / b2 : b1 / c2)); break;
+        case 2: R.push_back((d0 ? c1 / b1 : b2 / c2) * (d1 ? c2 / a2 : a1 / c1)); break;
+        case 3: R.push_back((d0 ? c2 / a1 : a2 / c1) * (d1 ? c1 / b1 : b2 / c2)); break;
+        default: R.push_back((d0 ? c1 / b2 : b1 / c2) * (d1 ? c2 / a2 : a1 / c1)); break;
+        }
     }
     if (!tl::exact_thresholds(R, w.rule == TL_METROPOLIS, out))
         return fail(TL_EINVAL, "weights too uneven for 32-bit Metropolis thresholds (a ratio above 2^31)");
@@ -509,12 +520,14 @@ tl_status tl_domain_extremes(const tl_domain *dom, void *tmax, void *tmin, size_
     if (!dom) return fail(TL_EINVAL, "null argument");
     if (dom->shape != TL_MASK)
         return fail(TL_EINVAL, "extremal states are computed for mask domains");
+    if (dom->flags && (dom->model != TL_SIXVERTEX || tl::free_side_of(dom->flags) < 0))
+        return fail(TL_EINVAL, "free sides are a six-vertex option, one side per domain");
     if (dom->model == TL_SIXVERTEX || dom->model == TL_LOZENGE) {
         tl::HeightRegion r;
         std::string why;
         const tl::RegionStatus st = dom->model == TL_SIXVERTEX
                                         ? tl::build_sixv_region(dom->mask, dom->w, dom->h,
-                                                                (dom->flags & TL_FREE_NORTH) != 0, r, why)
+                                                                tl::free_side_of(dom->flags), r, why)
                                         : tl::build_loz_region(dom->mask, dom->w, dom->h, r, why);
         if (st != tl::kRegionOk)
             return fail(st == tl::kRegionUntileable ? TL_EUNTILEABLE : TL_EINVAL, "%s", why.c_str());
@@ -962,7 +975,7 @@ tl_status tl_sampler_cftp(tl_sampler *s, uint32_t max_log2, tl_cftp_info *out)
                 if (!(m >> k & 1u) && s->thr[m] > s->thr[m | (1u << k)])
                     return fail(TL_EINVAL, "coupling from the past needs weights that keep the height order "
                                            "(a <= c and b <= c)");
-        // free north-edge points: raising SW or SE must not lower the up threshold
+        // free points: raising a context diagonal must not lower the up threshold
         for (uint32_t m = 0; m < 4 && !s->thr_free.empty(); ++m)
             for (uint32_t k = 0; k < 2; ++k)
                 if (!(m >> k & 1u) && s->thr_free[m] > s->thr_free[m | (1u << k)])

@@ -87,7 +87,8 @@ struct Geo {
     const uint32_t *site;   // site planes of a masked domain (layout sPS, sRS), or nullptr
     size_t sPS;
     uint32_t sRS;
-    const uint32_t *freep;  // six-vertex: planes of the free north-edge points (same layout), or nullptr
+    const uint32_t *freep;  // six-vertex: planes of the free points (same layout), or nullptr
+    int free_side;          // their side: 1 north, 2 south, 3 east, 4 west
 };
 
 __device__ __forceinline__ int imax(int p, int q) { return p > q ? p : q; }
@@ -170,8 +171,10 @@ __device__ __forceinline__ void loz_decide(uint32_t k0, uint32_t k1, uint32_t g,
     }
 }
 
-// Points of a free north edge (no north neighbour): table Tall.v[kFreeBase ..]
-// over the context (SW at m+1) + 2 (SE at m+1) [x2: current state up].
+// Points of the free side (no neighbour across it): table Tall.v[kFreeBase ..]
+// over the context (first diagonal at m+1) + 2 (second diagonal at m+1)
+// [x2: current state up]; the diagonals (hSW, hSE here) are north SW, SE;
+// south NW, NE; east SW, NW; west SE, NE.
 template <int MODE, uint32_t L>
 __device__ __forceinline__ void sixv_free_decide(uint32_t k0, uint32_t k1, uint32_t g, uint32_t r, uint32_t t,
                                                  uint32_t c, const Thr &Tall, const uint32_t (&R0)[4],
@@ -349,10 +352,14 @@ __device__ __forceinline__ void sixv_group(uint32_t *base, size_t ps, uint32_t r
     // interior faces 1 <= I <= N-1 (and, in a masked domain, its sites)
     const int klo = p == 0 ? 1 : 0, khi = (geo.N - 1 - (int)p) >> 1;
     uint32_t sm[4] = {~0u, ~0u, ~0u, ~0u}, fm[4] = {0u, 0u, 0u, 0u};
+    int side = 0;
     if constexpr (MASKED) {
         hld4(geo.site + p * geo.sPS + (size_t)J * geo.sRS + 4u + 4u * g, sm);
-        // points of a free north edge ignore their (absent) north neighbour
-        if (geo.freep) hld4(geo.freep + p * geo.sPS + (size_t)J * geo.sRS + 4u + 4u * g, fm);
+        // points of the free side ignore their (absent) neighbour across it
+        if (geo.freep) {
+            hld4(geo.freep + p * geo.sPS + (size_t)J * geo.sRS + 4u + 4u * g, fm);
+            side = geo.free_side;
+        }
     }
     const bool podd = ((p + (uint32_t)J) & 1u) != 0u;   // parity of I + J
     uint32_t live[4], up[4], hNE[4], hNW[4], hSW[4], hSE[4], cur[4];
@@ -360,8 +367,17 @@ __device__ __forceinline__ void sixv_group(uint32_t *base, size_t ps, uint32_t r
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
         const uint32_t m = range_mask((int)(4 * g) + w, klo, khi) & sm[w];
-        live[w] = ~(E[w] ^ W[w]) & (~(E[w] ^ Nn[w]) | fm[w]) & ~(E[w] ^ Sn[w]) & m;
-        up[w] = podd ? E[w] : ~E[w];      // residual bit of m+1
+        const uint32_t eEW = ~(E[w] ^ W[w]), eEN = ~(E[w] ^ Nn[w]), eES = ~(E[w] ^ Sn[w]);
+        // free points: the three neighbours off the free side share m
+        const uint32_t lf = side == 1   ? eEW & eES
+                            : side == 2 ? eEW & eEN
+                            : side == 3 ? ~(W[w] ^ Nn[w]) & ~(W[w] ^ Sn[w])
+                            : side == 4 ? eEN & eES
+                                        : 0u;
+        live[w] = ((eEW & eEN & eES & ~fm[w]) | (lf & fm[w])) & m;
+        // residual bit of m + 1 (m read off E, or W across a free east side)
+        const uint32_t ref = side == 3 ? (E[w] & ~fm[w]) | (W[w] & fm[w]) : E[w];
+        up[w] = podd ? ref : ~ref;
         hNE[w] = ~(NE[w] ^ up[w]);
         hNW[w] = ~(NW[w] ^ up[w]);
         hSW[w] = ~(SW[w] ^ up[w]);
@@ -382,7 +398,10 @@ __device__ __forceinline__ void sixv_group(uint32_t *base, size_t ps, uint32_t r
         sixv_decide<MODE, KIND, L>(k0, k1, g, (uint32_t)J, t, colour, Tall, R0, hNE, hNW, hSW, hSE, cur, li, q, D);
         if (anyf) {
             uint32_t Df[4];
-            sixv_free_decide<MODE, L>(k0, k1, g, (uint32_t)J, t, colour, Tall, R0, hSW, hSE, cur, lf, q, Df);
+            // context diagonals beside the two cells the flip changes
+            const uint32_t (&c0)[4] = side == 2 ? hNW : side == 4 ? hSE : hSW;
+            const uint32_t (&c1)[4] = side == 1 ? hSE : side == 3 ? hNW : hNE;
+            sixv_free_decide<MODE, L>(k0, k1, g, (uint32_t)J, t, colour, Tall, R0, c0, c1, cur, lf, q, Df);
 #pragma unroll
             for (int w = 0; w < 4; ++w) D[w] = (D[w] & ~fm[w]) | (Df[w] & fm[w]);
         }
@@ -561,7 +580,7 @@ __global__ void __launch_bounds__(kLozThreads) loz_tiled_kernel(const uint32_t *
 template <int MODE, int KIND, bool RANDOM, bool MASKED>
 __device__ __forceinline__ void height_item(uint32_t *lds, const TileJob &j, uint32_t tile)
 {
-    const Geo geo{j.model, j.a, j.b, j.c, j.N, j.site, j.PS, j.RS, j.freep};
+    const Geo geo{j.model, j.a, j.b, j.c, j.N, j.site, j.PS, j.RS, j.freep, j.free_side};
     height_tile<MODE, KIND, RANDOM, MASKED>(lds, j.in, j.out, j.PS, j.RS, j.ng, j.rows, j.P, geo, j.t0, j.S, j.TR,
                                             j.TG, j.HR,
                                     j.HG, tile / j.tiles_x, tile % j.tiles_x, j.T, j.key0, j.key1);
@@ -669,22 +688,28 @@ __global__ void sixv_observe_kernel(const uint32_t *pl, size_t PS, uint32_t RS, 
     }
 }
 
-// Six-vertex domain given by a mask: heights of the (h+1) x (w+1) points, one
-// thread per row J.  Off the domain INT32_MIN; boundary points take their fixed
-// height; a site takes the value one away from its west neighbour (a point of
-// the domain) whose residual bit floor(h/2) mod 2 matches its own.
+// Six-vertex domain given by a mask: heights of the (h+1) x (w+1) points.  Off
+// the domain INT32_MIN; boundary points take their fixed height; a site takes
+// the value one away from a neighbour already known whose residual bit
+// floor(h/2) mod 2 matches its own.  One thread per row J, walking east from
+// each row segment's first point (fixed: it has a west side of a cell on the
+// boundary), or, when the west side is free, one thread per column I walking
+// north from each column segment's lowest point (fixed by its south side).
 __global__ void sixv_region_export_kernel(const uint32_t *pl, size_t PS, uint32_t RS, const int32_t *anchor, int w,
-                                          int h, int32_t *out)
+                                          int h, int ox, int oy, int by_columns, int32_t *out)
 {
-    const int J = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (J > h) return;
+    const int line = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (line > (by_columns ? w : h)) return;
     int32_t prev = 0;
-    for (int I = 0; I <= w; ++I) {
+    for (int step = 0; step <= (by_columns ? h : w); ++step) {
+        const int I = by_columns ? line : step, J = by_columns ? step : line;
         const size_t v = (size_t)J * (w + 1) + I;
         const int32_t a = anchor[v];
         int32_t x = a;
         if (a == INT32_MAX) {
-            const uint32_t bx = hbit(pl, PS, RS, (uint32_t)I & 1u, (uint32_t)J, (uint32_t)I >> 1);
+            // the state holds point (I, J) at (I + ox, J + oy) (even offsets)
+            const uint32_t X = (uint32_t)(I + ox), Y = (uint32_t)(J + oy);
+            const uint32_t bx = hbit(pl, PS, RS, X & 1u, Y, X >> 1);
             x = ((uint32_t)(((prev + 1) >> 1) & 1) == bx) ? prev + 1 : prev - 1;
         }
         out[v] = x;
@@ -787,7 +812,10 @@ __global__ void __launch_bounds__(64) loz_observe_kernel(const uint32_t *pl, siz
         if (rowbin[i]) atomicAdd(&bins[row + i], rowbin[i]);
 }
 
-Geo geo_of(const HeightDev &d) { return Geo{d.model, d.a, d.b, d.c, d.N, d.site, d.PS, d.RS, d.freep}; }
+Geo geo_of(const HeightDev &d)
+{
+    return Geo{d.model, d.a, d.b, d.c, d.N, d.site, d.PS, d.RS, d.freep, d.free_side};
+}
 
 }  // namespace
 
@@ -947,6 +975,7 @@ TileJob height_tile_job(const HeightDev &d, const TilePlan &p, uint32_t t0, cons
     j.kind = T.uniform() ? (uint32_t)kTableClass : table_kind(T);
     j.site = d.site;
     j.freep = d.freep;
+    j.free_side = d.free_side;
     j.key0 = (uint32_t)seed;
     j.key1 = (uint32_t)(seed >> 32);
     j.T = T;
@@ -973,8 +1002,10 @@ hipError_t height_export(const HeightDev &d, int32_t *dev, hipStream_t s)
 
 hipError_t sixv_region_export(const HeightDev &d, const int32_t *anchor, int w, int h, int32_t *out, hipStream_t s)
 {
-    hipLaunchKernelGGL(sixv_region_export_kernel, dim3((h + 64) / 64), dim3(64), 0, s, d.planes, d.PS, d.RS, anchor,
-                       w, h, out);
+    const int by_columns = d.free_side == 4 ? 1 : 0;
+    const int lines = (by_columns ? w : h) + 1;
+    hipLaunchKernelGGL(sixv_region_export_kernel, dim3((lines + 63) / 64), dim3(64), 0, s, d.planes, d.PS, d.RS,
+                       anchor, w, h, d.ox, d.oy, by_columns, out);
     return hipGetLastError();
 }
 

@@ -194,10 +194,12 @@ struct HeightDev {
     size_t PS = 0;
     uint32_t *planes = nullptr, *spare = nullptr;
     // six-vertex domain given by a mask: bit planes (same layout as the state)
-    // of the points that may flip, and of those on free north edges (or
+    // of the points that may flip, and of those on its free side (or
     // nullptr); nullptr for the domain-wall square
     const uint32_t *site = nullptr;
     const uint32_t *freep = nullptr;
+    int free_side = 0;      // side of the free points: 1 north, 2 south, 3 east, 4 west
+    int ox = 0, oy = 0;     // six-vertex mask: state point of the mask box's point (0, 0)
 };
 struct HeightTile {
     uint32_t TR = 32, TG = 4, S = 8;
@@ -276,7 +278,8 @@ struct TileJob {
     uint32_t order;                     // colour order: 0 fixed, 1 random per step
     uint32_t key0, key1;
     const uint32_t *site;               // six-vertex site planes of a masked domain, or nullptr
-    const uint32_t *freep;              // planes of its free north-edge points, or nullptr
+    const uint32_t *freep;              // planes of its free points, or nullptr
+    int32_t free_side;                  // their side: 1 north, 2 south, 3 east, 4 west
     Thr T;                              // kernel table (heights: weight classes)
 };
 struct TileItem {

@@ -261,9 +261,15 @@ public:
             d_.b = region_->h;
             d_.c = 0;
         } else {
-            // free north-edge points may sit on the domain's top row: keep a row
-            // above it in the box so that they are inner rows of the state
-            d_.N = std::max(region_->w, region_->h + (region_->free_sites ? 1 : 0));
+            // free points sit on a side of the domain's box: keep them inner
+            // points of the state, with a row (column) beyond a free north
+            // (east) side and the box two rows (columns) up (right) for a free
+            // south (west) one
+            const int side = region_->free_sites ? region_->free_side : 0;
+            d_.free_side = side;
+            d_.ox = side == 4 ? 2 : 0;
+            d_.oy = side == 2 ? 2 : 0;
+            d_.N = std::max(region_->w + d_.ox + (side == 3 ? 1 : 0), region_->h + d_.oy + (side == 1 ? 1 : 0));
         }
         height_words(d_);
     }
@@ -394,8 +400,8 @@ public:
         for (int J = 0; J <= h; ++J)
             for (int I = 0; I <= w; ++I)
                 if (pred((int32_t)vals[(size_t)J * (w + 1) + I])) {
-                    const int p = I % P, k = I / P;
-                    host[(size_t)p * d_.PS + (size_t)J * d_.RS + 4 + (k >> 5)] |= 1u << (k & 31);
+                    const int X = I + d_.ox, Y = J + d_.oy, p = X % P, k = X / P;
+                    host[(size_t)p * d_.PS + (size_t)Y * d_.RS + 4 + (k >> 5)] |= 1u << (k & 31);
                 }
     }
     // The residual bit of a height: six-vertex floor(h/2) mod 2, lozenge H mod 2.
@@ -623,11 +629,16 @@ public:
                     vals[v] = x;
                     continue;
                 }
-                // a point of a free north edge has no north neighbour
-                const bool fr = region_->site[v] == 2;
-                const int32_t nb[4] = {H[v - 1], H[v + 1], H[v - PW], fr ? H[v - 1] : H[v + PW]};
-                for (int32_t y : nb)
-                    if (y == INT32_MIN || (x > y ? x - y : y - x) != 1) {
+                // a point of the free side has no neighbour across it
+                const int fs = region_->site[v] == 2 ? region_->free_side : 0;
+                int32_t nb[4];
+                int cnt = 0;
+                if (fs != 4) nb[cnt++] = H[v - 1];    // west
+                if (fs != 3) nb[cnt++] = H[v + 1];    // east
+                if (fs != 2) nb[cnt++] = H[v - PW];   // south
+                if (fs != 1) nb[cnt++] = H[v + PW];   // north
+                for (int q = 0; q < cnt; ++q)
+                    if (const int32_t y = nb[q]; y == INT32_MIN || (x > y ? x - y : y - x) != 1) {
                         why = "ice rule violated";
                         return false;
                     }
@@ -738,13 +749,13 @@ private:
 std::unique_ptr<Model> make_model(const tl_domain &d, std::string &why, tl_status *status)
 {
     if (status) *status = TL_EINVAL;
-    if (d.shape == TL_MASK && d.flags && (d.model != TL_SIXVERTEX || d.flags != TL_FREE_NORTH)) {
-        why = "free north edges are a six-vertex option";
+    if (d.shape == TL_MASK && d.flags && (d.model != TL_SIXVERTEX || free_side_of(d.flags) < 0)) {
+        why = "free sides are a six-vertex option, one side per domain";
         return nullptr;
     }
     if (d.model == TL_SIXVERTEX && d.shape == TL_MASK) {
         auto r = std::make_shared<HeightRegion>();
-        const RegionStatus st = build_sixv_region(d.mask, d.w, d.h, (d.flags & TL_FREE_NORTH) != 0, *r, why);
+        const RegionStatus st = build_sixv_region(d.mask, d.w, d.h, free_side_of(d.flags), *r, why);
         if (st != kRegionOk) {
             if (status && st == kRegionUntileable) *status = TL_EUNTILEABLE;
             return nullptr;

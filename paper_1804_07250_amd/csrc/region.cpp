@@ -11,6 +11,7 @@
 // T_min.  Distances take small integer lengths, so a bucket queue (Dial's
 // method) keeps the work linear.
 #include "region.hpp"
+#include "../../include/tilings.h"
 
 #include <limits.h>
 #include <stdint.h>
@@ -261,7 +262,19 @@ RegionStatus build_region(const uint8_t *mask, int w, int h, Region &r, std::str
 // largest is min_b h(b) + dist(b, v), the smallest max_b h(b) - dist(b, v)
 // (unit lengths, a bucket queue from all boundary points at once), and one
 // exists iff both meet the boundary heights.
-RegionStatus build_sixv_region(const uint8_t *mask, int w, int h, bool free_north, HeightRegion &r,
+int free_side_of(uint32_t flags)
+{
+    switch (flags) {
+    case 0: return 0;
+    case TL_FREE_NORTH: return 1;
+    case TL_FREE_SOUTH: return 2;
+    case TL_FREE_EAST: return 3;
+    case TL_FREE_WEST: return 4;
+    default: return -1;
+    }
+}
+
+RegionStatus build_sixv_region(const uint8_t *mask, int w, int h, int free_side, HeightRegion &r,
                                std::string &why)
 {
     uint64_t ncells = 0;
@@ -273,6 +286,7 @@ RegionStatus build_sixv_region(const uint8_t *mask, int w, int h, bool free_nort
     r.cw = w;
     r.ch = h;
     r.free_sites = 0;
+    r.free_side = free_side;
     const int PW = w + 1;
     const size_t V = (size_t)PW * (h + 1);
     auto in = [&](int x, int y) { return x >= 0 && y >= 0 && x < w && y < h && r.cells[(size_t)y * w + x] != 0; };
@@ -299,6 +313,18 @@ RegionStatus build_sixv_region(const uint8_t *mask, int w, int h, bool free_nort
                                    {-1, 0, -1, 0, -1, -1, -1},
                                    {0, 1, 0, 0, -1, 0, 1},
                                    {0, -1, 0, -1, -1, -1, -1}};
+    // Is a boundary edge (cells a, b beside it, a != b) a side of the free
+    // kind: horizontal steps have a above and b below, vertical ones a to the
+    // right and b to the left; the domain's cell is the one inside.
+    auto free_edge = [&](const Edge &e, bool a, bool b) {
+        switch (free_side) {
+        case 1: return e.dJ == 0 && b;   // north side of the cell below
+        case 2: return e.dJ == 0 && a;   // south side of the cell above
+        case 3: return e.dI == 0 && b;   // east side of the cell to the left
+        case 4: return e.dI == 0 && a;   // west side of the cell to the right
+        default: return false;
+        }
+    };
     std::vector<int32_t> hb(V, kUnset);
     {
         const int I0 = (int)(start % PW), J0 = (int)(start / PW);
@@ -311,7 +337,7 @@ RegionStatus build_sixv_region(const uint8_t *mask, int w, int h, bool free_nort
             for (const Edge &e : kE) {
                 const bool a = in(I + e.ax, J + e.ay), b = in(I + e.bx, J + e.by);
                 if (a == b) continue;   // interior side, or no side of the domain
-                if (free_north && e.dJ == 0 && b) continue;   // the north side of a cell: a free leg
+                if (free_edge(e, a, b)) continue;   // a free leg
                 const size_t u = (size_t)(J + e.dJ) * PW + I + e.dI;
                 const int32_t hu = hb[v] + e.sign * (a ? 1 : -1);
                 if (hb[u] == kUnset) {
@@ -325,18 +351,17 @@ RegionStatus build_sixv_region(const uint8_t *mask, int w, int h, bool free_nort
         }
     }
     // boundary points the walk did not reach: free (code 2) when every boundary
-    // edge at them is the north side of a cell, otherwise the fixed boundary is
-    // in pieces
+    // edge at them is a free side, otherwise the fixed boundary is in pieces
     for (size_t v = 0; v < V; ++v) {
         if (!pt[v] || r.site[v] || hb[v] != kUnset) continue;
         const int I = (int)(v % PW), J = (int)(v / PW);
-        bool all_free = free_north;
+        bool all_free = free_side != 0;
         for (const Edge &e : kE) {
             const bool a = in(I + e.ax, J + e.ay), b = in(I + e.bx, J + e.by);
-            if (a != b && !(e.dJ == 0 && b)) all_free = false;
+            if (a != b && !free_edge(e, a, b)) all_free = false;
         }
         if (!all_free) {
-            why = free_north ? "free edges split the fixed boundary" : "boundary not connected";
+            why = free_side ? "free edges split the fixed boundary" : "boundary not connected";
             return kRegionInvalid;
         }
         r.site[v] = 2;

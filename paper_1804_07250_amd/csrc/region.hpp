@@ -46,11 +46,12 @@ struct HeightRegion {
     int w = 0, h = 0;
     int cw = 0, ch = 0;                  // box of the observable cells
     std::vector<uint8_t> cells;          // cw*ch, 1 = cell of the domain
-    std::vector<uint8_t> site;           // (w+1)*(h+1) points, 1 = site, 2 = point of a free north edge
+    std::vector<uint8_t> site;           // (w+1)*(h+1) points, 1 = site, 2 = point of the free side
     std::vector<int32_t> anchor;         // boundary height; INT32_MIN off the domain; INT32_MAX at sites
     std::vector<int32_t> hmax, hmin;     // extremal states (INT32_MIN off the domain)
     uint64_t sites = 0;                  // points that may move (free ones included)
     uint64_t free_sites = 0;
+    int free_side = 0;                   // six-vertex: 0 none, 1 north, 2 south, 3 east, 4 west
 };
 
 // Six-vertex (Section 1.2 with the domains of Section 1.1): the model's
@@ -60,12 +61,14 @@ struct HeightRegion {
 // are empty; walking a boundary edge in +x the height rises by 1 if the domain
 // is above it and falls by 1 if below, in +y it rises if the domain is to its
 // right and falls if to its left; the lowest, then leftmost, point gets height
-// (I + J) mod 2.  With free_north the legs through the north sides of cells
-// are free: boundary points all of whose boundary edges are such sides move
-// (code 2: west, east and south neighbours only); the remaining fixed boundary
-// must be one piece.
-RegionStatus build_sixv_region(const uint8_t *mask, int w, int h, bool free_north, HeightRegion &r,
+// (I + J) mod 2.  With a free side (free_side 1 north, 2 south, 3 east,
+// 4 west) the legs through that side of cells are free: boundary points all
+// of whose boundary edges are such sides move (code 2: the three neighbours
+// off that side only); the remaining fixed boundary must be one piece.
+RegionStatus build_sixv_region(const uint8_t *mask, int w, int h, int free_side, HeightRegion &r,
                                std::string &why);
+// Free side of a domain's flags (0 none, 1..4), or -1 for an invalid set.
+int free_side_of(uint32_t flags);
 
 // Lozenges (Section 1.2's triangular lattice: Z^2 with the diagonals (1,1);
 // the domains of Section 1.1): mask[(y*w + x)*2 + t] selects triangle t of unit

@@ -286,3 +286,77 @@ def test_free_north_large_one_sweep_sampled():
     s.sweep(1)
     o.sweep(1)
     assert (s.export() == o.export()).all()
+
+
+def side_pair(tl, m, wts, seed, side, metro=False, init="min", **kw):
+    w = tl.weights(tl.TL_W_SIXVERTEX6, *wts)
+    w.rule = tl.TL_METROPOLIS if metro else tl.TL_HEATBATH
+    dom = tl.domain(tl.TL_SIXVERTEX, mask=m, free_side=side,
+                    init=tl.TL_INIT_MAX if init == "max" else tl.TL_INIT_MIN)
+    s = tl.Sampler(dom, w, seed, tl.options(**kw))
+    fr = [Fraction(x) for x in wts]
+    thr = oracle.table_from_ratios(oracle.sixv_ratios6(*fr), metro)
+    thr_free = oracle.table_from_ratios(oracle.sixv_free_ratios6(*fr, side=side), metro)
+    o = oracle.SixVertexRegionOracle(m, thr, metropolis=metro, seed=seed, init=init, free_side=side,
+                                     thr_free=thr_free, random_colours=kw.get("colour_order", 0) == 1)
+    assert s.thresholds() == list(thr) + list(thr_free)
+    return s, o
+
+
+SIDES = [("south", (30, 50), STOCH, False, "min", {}), ("south", (30, 50), STOCH, False, "max", {"kernel": 1}),
+         ("south", (40, 64), (2.0, 1.0, 0.5, 1.5, 0.5, 3.0), True, "min",
+          {"kernel": 2, "tile_rows": 8, "sweeps_per_launch": 3}),
+         ("south", (20, 33), STOCH, False, "max", {"colour_order": 1}),
+         ("east", (50, 30), STOCH, False, "min", {}), ("east", (50, 30), STOCH, False, "max", {"kernel": 1}),
+         ("east", (64, 40), (2.0, 1.0, 0.5, 1.5, 0.5, 3.0), True, "min",
+          {"kernel": 2, "tile_rows": 8, "sweeps_per_launch": 3}),
+         ("west", (50, 30), STOCH, False, "min", {}), ("west", (200, 130), STOCH, False, "min", {}),
+         ("west", (33, 20), STOCH, False, "max", {"colour_order": 1}), ("west", (40, 40), STOCH, True, "max",
+                                                                          {"kernel": 1}),
+         ("north", (40, 64), STOCH, False, "min", {"kernel": 2, "tile_rows": 8, "sweeps_per_launch": 3})]
+
+
+@pytest.mark.parametrize("side,hw,wts,metro,init,opts", SIDES,
+                         ids=["%s-%s-%s-%s-%s-%s" % (c[0], c[1], c[2][2], c[3], c[4], c[5]) for c in SIDES])
+def test_free_side_parity(side, hw, wts, metro, init, opts):
+    # free points on the south, east or west side (and north on a tiled plan):
+    # the HIP path against the oracle's chain, bit for bit, over several calls
+    tl = need_gpu()
+    say("six-vertex free %s %s %s metro=%s init=%s %s" % (side, hw, wts, metro, init, opts))
+    m = ones(*hw)
+    s, o = side_pair(tl, m, wts, 31, side, metro, init, **opts)
+    assert (s.export() == o.export()).all()
+    for k in (1, 4, 12):
+        s.sweep(k)
+        o.sweep(k)
+        assert (s.export() == o.export()).all(), k
+    assert s.hash() == oracle.canonical_hash(o.export())
+    s.destroy()
+
+
+@pytest.mark.parametrize("side", ["south", "east", "west"])
+def test_free_side_observables_import_and_served(side):
+    # observables and import on a free side, and the same job through a server
+    tl = need_gpu()
+    from paper_1804_07250_amd.serving import Server
+    m = ones(30, 50) if side == "south" else ones(50, 30)
+    s, o = side_pair(tl, m, STOCH, 3, side, obs_every=2, obs_bin=5)
+    o2 = oracle.SixVertexRegionOracle(m, oracle.table_from_ratios(oracle.sixv_ratios6(*map(Fraction, STOCH)), False),
+                                      seed=3, free_side=side, obs_every=2, bin_=5,
+                                      thr_free=oracle.table_from_ratios(
+                                          oracle.sixv_free_ratios6(*map(Fraction, STOCH), side=side), False))
+    s.sweep(10)
+    o2.sweep(10)
+    obs = s.observables()
+    assert (obs["bin_sum"].reshape(-1) == o2.bin_sum).all() and obs["samples"] == int(o2.samples[0]) == 5
+    mid = o2.export()
+    r = tl.Sampler(tl.domain(tl.TL_SIXVERTEX, mask=m, free_side=side), tl.weights(tl.TL_W_SIXVERTEX6, *STOCH), 3)
+    r.import_(mid, 10)
+    r.sweep(7)
+    o2.sweep(7)
+    assert (r.export() == o2.export()).all()
+    sv = Server(16 << 20, 4, tl.options(sweeps_per_launch=3))
+    tk = sv.submit(tl.domain(tl.TL_SIXVERTEX, mask=m, free_side=side), tl.weights(tl.TL_W_SIXVERTEX6, *STOCH), 3, 17)
+    res = sv.wait(tk, 60.0)
+    sv.destroy()
+    assert res["hash"] == oracle.canonical_hash(o2.export())

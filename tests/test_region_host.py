@@ -214,3 +214,48 @@ def test_free_north_refusals():
     with pytest.raises(tl.TlError) as e:      # free edges split the fixed boundary of an L-shape
         tl.domain_extremes(tl.domain(tl.TL_SIXVERTEX, mask=l_shape(6, 3, 3), free_north=True))
     assert e.value.status == tl.TL_EINVAL
+
+
+# every free side: extremes and tables equal the oracle's (wide boxes for a
+# free north or south side, tall ones for east or west; a box of the other
+# kind has no configuration), and invalid flag sets are refused
+SIDE_HW = {"north": [(4, 6), (10, 17)], "south": [(4, 6), (10, 17), (3, 3)], "east": [(6, 4), (17, 10), (3, 3)],
+           "west": [(6, 4), (17, 10), (40, 25)]}
+
+
+@pytest.mark.parametrize("side,hw", [(s_, hw) for s_, l in SIDE_HW.items() for hw in l])
+def test_sixvertex_free_side_matches_the_oracle(side, hw):
+    m = ones(*hw)
+    want = oracle.sixv_extremal_heights(m, free_side=side)
+    got = tl.domain_extremes(tl.domain(tl.TL_SIXVERTEX, mask=m, free_side=side))
+    assert (got[0] == want[0]).all() and (got[1] == want[1]).all()
+
+
+@pytest.mark.parametrize("side", ["north", "south", "east", "west"])
+def test_free_side_thresholds_match_the_oracle(side):
+    from fractions import Fraction
+    m = ones(*SIDE_HW[side][0])
+    for wts in ((1, 1, 0.25, 0.75, 0.25, 0.75), (2, 1, 0.5, 1.5, 0.5, 3)):
+        for rule in (tl.TL_HEATBATH, tl.TL_METROPOLIS):
+            w = tl.weights(tl.TL_W_SIXVERTEX6, *wts, rule=rule)
+            metro = rule == tl.TL_METROPOLIS
+            want = list(oracle.table_from_ratios(oracle.sixv_ratios6(*map(Fraction, wts)), metro)) + \
+                list(oracle.table_from_ratios(oracle.sixv_free_ratios6(*map(Fraction, wts), side=side), metro))
+            assert tl.thresholds(tl.domain(tl.TL_SIXVERTEX, mask=m, free_side=side), w) == want
+
+
+def test_free_side_refusals():
+    m = ones(6, 4)
+    bad = tl.domain(tl.TL_SIXVERTEX, mask=m)
+    bad.flags = tl.TL_FREE_EAST | tl.TL_FREE_WEST   # one side per domain
+    with pytest.raises(tl.TlError) as e:
+        tl.domain_extremes(bad)
+    assert e.value.status == tl.TL_EINVAL
+    with pytest.raises(tl.TlError) as e:      # a wide box has no configuration with a free east side
+        tl.domain_extremes(tl.domain(tl.TL_SIXVERTEX, mask=ones(4, 6), free_side="east"))
+    assert e.value.status == tl.TL_EUNTILEABLE
+    dom = tl.domain(tl.TL_DOMINO, mask=ones(4, 4))
+    dom.flags = tl.TL_FREE_SOUTH                # dominoes have no free sides
+    with pytest.raises(tl.TlError) as e:
+        tl.thresholds(dom, tl.weights(tl.TL_W_UNIFORM))
+    assert e.value.status == tl.TL_EINVAL
