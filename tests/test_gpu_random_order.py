@@ -156,9 +156,20 @@ def test_random_order_limits():
     with pytest.raises(tl.TlError) as e:
         s.cftp(31)
     assert e.value.status == tl.TL_EINVAL
+    # batches and servers take the random order, with the same step limit
     with pytest.raises(tl.TlError) as e:
-        Batch([tl.domain(tl.TL_DOMINO, n=8)], w, [1], tl.options(colour_order=1))
+        Batch([tl.domain(tl.TL_DOMINO, n=8)], w, [1], tl.options(colour_order=2))
     assert e.value.status == tl.TL_EINVAL
+    b = Batch([tl.domain(tl.TL_DOMINO, n=8)], w, [1], tl.options(colour_order=1))
     with pytest.raises(tl.TlError) as e:
-        Server(1 << 26, 4, tl.options(colour_order=1))
+        b.sweep((1 << 31) + 1)          # checked before any launch
     assert e.value.status == tl.TL_EINVAL
+    b.destroy()
+    with pytest.raises(tl.TlError) as e:
+        Server(1 << 26, 4, tl.options(colour_order=2))
+    assert e.value.status == tl.TL_EINVAL
+    sv = Server(1 << 26, 4, tl.options(colour_order=1))
+    with pytest.raises(tl.TlError) as e:
+        sv.submit(tl.domain(tl.TL_DOMINO, n=8), w, 1, (1 << 31) + 1)
+    assert e.value.status == tl.TL_EINVAL
+    sv.destroy()

@@ -154,18 +154,21 @@ def test_domain_create_errors():
         tl.domain(tl.TL_LOZENGE, mask=ones(4, 4))
 
 
-def test_batch_and_server_take_fixed_shapes():
+def test_batch_and_server_mask_refusals():
+    """Batches hold domino chains only; a server refuses what a sampler refuses."""
     tl = need_gpu()
     from paper_1804_07250_amd.serving import Batch, Server
     w = tl.weights(tl.TL_W_UNIFORM)
     with pytest.raises(tl.TlError) as e:
-        Batch([tl.domain(tl.TL_DOMINO, mask=ones(4, 4))], w, [1])
+        Batch([tl.domain(tl.TL_SIXVERTEX, mask=ones(4, 4))], tl.weights(tl.TL_W_SIXVERTEX, 1.0, 1.0, 1.0), [1])
     assert e.value.status == tl.TL_EINVAL
+    board = ones(8, 8)
+    board[0, 0] = board[7, 7] = False
     sv = Server(1 << 26, 4)
     try:
         with pytest.raises(tl.TlError) as e:
-            sv.submit(tl.domain(tl.TL_DOMINO, mask=ones(4, 4)), w, 1, 10)
-        assert e.value.status == tl.TL_EINVAL
+            sv.submit(tl.domain(tl.TL_DOMINO, mask=board), w, 1, 10)
+        assert e.value.status == tl.TL_EUNTILEABLE
     finally:
         sv.destroy()
 
