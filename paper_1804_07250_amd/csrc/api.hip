@@ -305,8 +305,8 @@ hipError_t cftp_issue_piece(CftpRound &rd, const tl::Thr &T, uint64_t seed, cons
     const auto pc = rd.pieces[rd.next];
     tl::TilePlan pb, pt;
     tl::TileJob *hj = rd.h_jobs + 2 * sl;
-    if (!rd.bot->tile_job(pc.first, pc.second, T, false, seed, &hj[0], &pb) ||
-        !rd.top->tile_job(pc.first, pc.second, T, false, seed, &hj[1], &pt) || pb.S != pc.second ||
+    if (!rd.bot->tile_job(pc.first, pc.second, T, false, seed, false, &hj[0], &pb) ||
+        !rd.top->tile_job(pc.first, pc.second, T, false, seed, false, &hj[1], &pt) || pb.S != pc.second ||
         pb.tiles() != 1 || pt.tiles() != 1)
         return hipErrorInvalidConfiguration;
     hipError_t e = hipMemcpyAsync(rd.d_jobs + 2 * sl, hj, 2 * sizeof(tl::TileJob), hipMemcpyHostToDevice, rd.st);
@@ -988,7 +988,7 @@ tl_status tl_sampler_cftp(tl_sampler *s, uint32_t max_log2, tl_cftp_info *out)
         tl::TileJob j1;
         tl::TilePlan p1;
         if (s->opt.kernel == 0 && s->opt.tile_rows == 0 && s->opt.tile_groups == 0 &&
-            s->opt.sweeps_per_launch == 0 && s->model->tile_job(0, 1, T1, false, s->seed, &j1, &p1) &&
+            s->opt.sweeps_per_launch == 0 && s->model->tile_job(0, 1, T1, false, s->seed, false, &j1, &p1) &&
             p1.tiles() == 1) {
             uint32_t Rm = 0;
             bool met = false;
@@ -1028,7 +1028,7 @@ tl_status tl_sampler_cftp(tl_sampler *s, uint32_t max_log2, tl_cftp_info *out)
     if (fused && e == hipSuccess) {
         tl::TileJob j;
         tl::TilePlan p;
-        fused = s->model->tile_job(0, 1, T, false, s->seed, &j, &p) && p.tiles() == 1;
+        fused = s->model->tile_job(0, 1, T, false, s->seed, false, &j, &p) && p.tiles() == 1;
     }
     if (fused && e == hipSuccess) {
         const tl::TileItem items[2] = {{0u, 0u}, {1u, 0u}};
@@ -1044,8 +1044,8 @@ tl_status tl_sampler_cftp(tl_sampler *s, uint32_t max_log2, tl_cftp_info *out)
             return err;
         }
         tl::TilePlan pb, pt;
-        if (!s->model->tile_job(t0, count, T, false, s->seed, &h_jobs[2 * slot], &pb) ||
-            !top->tile_job(t0, count, T, false, s->seed, &h_jobs[2 * slot + 1], &pt) || pb.S != count ||
+        if (!s->model->tile_job(t0, count, T, false, s->seed, false, &h_jobs[2 * slot], &pb) ||
+            !top->tile_job(t0, count, T, false, s->seed, false, &h_jobs[2 * slot + 1], &pt) || pb.S != count ||
             pb.tiles() != 1 || pt.tiles() != 1)
             return hipErrorInvalidConfiguration;
         hipError_t err = hipMemcpyAsync(d_jobs + 2 * slot, h_jobs + 2 * slot, 2 * sizeof(tl::TileJob),

@@ -501,6 +501,10 @@ __device__ __forceinline__ void height_tile(uint32_t *lds, const uint32_t *__res
     const uint32_t ql = tid % L, slots = nt / L;
     const bool sixv = geo.model != TL_LOZENGE;
     const uint32_t ntasks = (sixv ? (LR + 1u) / 2u : LR) * LG;
+    // (row, group) of this lane's first task, and the step to its next one,
+    // divided once here rather than in every colour step
+    const uint32_t task0 = tid / L, r00 = task0 / LG, lg00 = task0 % LG;
+    const uint32_t step_r = slots / LG, step_g = slots % LG;
     const uint32_t K_colours = sixv ? 4u : 3u;
     const uint32_t rps = sixv ? 2u : 3u;
     for (uint32_t s = 0; s < nsweeps; ++s) {
@@ -514,8 +518,8 @@ __device__ __forceinline__ void height_tile(uint32_t *lds, const uint32_t *__res
                 base = HR ? q : 0u;
                 end = HR ? LR - q : LR;
             }
-            for (uint32_t task = tid / L; task < ntasks; task += slots) {
-                const uint32_t r0 = task / LG, lg = task % LG;
+            uint32_t r0 = r00, lg = lg00;
+            for (uint32_t task = task0; task < ntasks; task += slots) {
                 const int gg = G0 + (int)lg;
                 // six-vertex: the first row >= base of parity c >> 1, then every other row
                 const uint32_t lr = sixv ? base + (((uint32_t)(R0 + (int)base) & 1u) ^ (c >> 1)) + 2u * r0 : base + r0;
@@ -523,6 +527,15 @@ __device__ __forceinline__ void height_tile(uint32_t *lds, const uint32_t *__res
                 if (gg >= 0 && gg < (int)ng && lr < end && lr >= 1 && lr + 1 < LR && site_row(geo, gr, rows))
                     height_group<MODE, KIND, MASKED, L, GEOM>(lds, LPS, LRS, lr, lg, geo, gr, (uint32_t)gg, c, t,
                                                               T, k0, k1, ql);
+                // one-bit decisions: a lane per task, and every plan gives
+                // the work-group at least as many lanes as tasks
+                if constexpr (L == 1) break;
+                r0 += step_r;
+                lg += step_g;
+                if (lg >= LG) {
+                    lg -= LG;
+                    ++r0;
+                }
             }
             __syncthreads();
         }

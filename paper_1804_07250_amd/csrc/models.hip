@@ -61,7 +61,7 @@ public:
         d_.spare = spare;
         owned_ = false;
     }
-    bool tile_job(uint32_t t0, uint32_t S_max, const Thr &T, bool metro, uint64_t seed, TileJob *j,
+    bool tile_job(uint32_t t0, uint32_t S_max, const Thr &T, bool metro, uint64_t seed, bool, TileJob *j,
                   TilePlan *p) const override
     {
         DominoTile tile = domino_auto_tile(d_.n, order != 0, !T.uniform());
@@ -418,27 +418,45 @@ public:
         d_.spare = spare;
         owned_ = false;
     }
-    // Served tiles: a state whose (row, group) tasks fit one work-group (512) and
-    // whose planes fit 64 KB of LDS is one tile (no halo, any sweep count);
-    // larger ones are cut into 32-row tiles spanning up to 8 groups.
-    bool tile_job(uint32_t t0, uint32_t S_max, const Thr &T, bool metro, uint64_t seed, TileJob *j,
+    // Multi-job tiles: a state whose (row, group) tasks fit one work-group (512)
+    // and whose planes fit 64 KB of LDS is one tile (no halo, any sweep
+    // count), unless spread asks for tiles whose tasks, a quad of lanes each
+    // for bit-serial decisions, all run at once (a work-group with fewer lanes
+    // than that takes its tasks in turns).  Larger states are cut into tiles
+    // spanning up to 8 groups, 32, 16 or 8 rows high: the tallest whose tasks
+    // fit 512 lanes, else the one that needs the fewest turns.
+    bool tile_job(uint32_t t0, uint32_t S_max, const Thr &T, bool metro, uint64_t seed, bool spread, TileJob *j,
                   TilePlan *p) const override
     {
+        const Thr K = kernel_table(T, metro);
         HeightTile tile;
-        if (height_task_rows(d_.model, d_.rows) * d_.ng <= 512u &&
+        tile.S = S_max;
+        tile.order = order;
+        tile.lanes = K.uniform() ? 1u : 4u;
+        tile.items = 1;
+        const uint32_t whole = height_task_rows(d_.model, d_.rows) * d_.ng;
+        if (whole <= 512u && (!spread || whole * tile.lanes <= 512u) &&
             (size_t)d_.P * d_.rows * 4u * (d_.ng + 2u) * 4u <= 64u * 1024u) {
             tile.TR = d_.rows;
             tile.TG = d_.ng;
+            if (!height_plan(d_, tile, S_max, p)) return false;
         } else {
-            tile.TR = 32;
             tile.TG = d_.ng <= 8u ? d_.ng : 4u;
+            uint32_t best_turns = 0;
+            for (uint32_t TR : {32u, 16u, 8u}) {
+                tile.TR = TR;
+                TilePlan q;
+                if (!height_plan(d_, tile, S_max, &q)) continue;
+                const uint32_t lanes = height_task_rows(d_.model, q.TR + 2u * q.HR) * (q.TG + 2u * q.HG) * tile.lanes;
+                const uint32_t turns = (lanes + 511u) / 512u;
+                if (best_turns == 0 || turns < best_turns) {
+                    *p = q;
+                    best_turns = turns;
+                }
+                if (turns == 1u) break;
+            }
+            if (best_turns == 0) return false;
         }
-        tile.S = S_max;
-        tile.order = order;
-        const Thr K = kernel_table(T, metro);
-        tile.lanes = K.uniform() ? 1u : 4u;
-        tile.items = 1;
-        if (!height_plan(d_, tile, S_max, p)) return false;
         *j = height_tile_job(d_, *p, t0, K, metro ? 1 : 0, seed);
         return true;
     }

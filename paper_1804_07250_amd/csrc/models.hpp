@@ -44,11 +44,13 @@ public:
     // buffers of state_words() words each (attach; release() leaves them);
     // tile_job plans the next launch of at most S_max sweeps from sweep t0 and
     // describes it (tile shape: small states in one tile, larger ones in row
-    // tiles), and swap_buffers() follows that launch.
+    // tiles; with spread, a height-model state whose tasks would take turns in
+    // one work-group goes to row tiles too, for launches that last as long as
+    // their slowest work-group), and swap_buffers() follows that launch.
     virtual size_t state_words() const = 0;
     virtual void attach(uint32_t *state, uint32_t *spare) = 0;
-    virtual bool tile_job(uint32_t t0, uint32_t S_max, const Thr &T, bool metro, uint64_t seed, TileJob *j,
-                          TilePlan *p) const = 0;
+    virtual bool tile_job(uint32_t t0, uint32_t S_max, const Thr &T, bool metro, uint64_t seed, bool spread,
+                          TileJob *j, TilePlan *p) const = 0;
     virtual void swap_buffers() = 0;
     virtual bool height_family() const = 0;
     // Device tables of a masked height-model domain placed in caller-owned

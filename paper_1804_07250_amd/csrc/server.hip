@@ -380,7 +380,7 @@ bool tick(tl_server *sv)
         const uint64_t left = j.sweeps - j.enq;
         const uint64_t want = (uint64_t)sv->quantum * (j.uniform ? 4u : 1u);
         const uint32_t smax = (uint32_t)std::min<uint64_t>(left, want);
-        if (!j.model->tile_job((uint32_t)j.enq, smax, j.T, j.metro, j.seed, &jobs[i], &plans[i])) {
+        if (!j.model->tile_job((uint32_t)j.enq, smax, j.T, j.metro, j.seed, true, &jobs[i], &plans[i])) {
             j.status = TL_EINVAL;
             j.enq = j.sweeps;   // finish (as failed) without running
             plans[i] = tl::TilePlan{};
