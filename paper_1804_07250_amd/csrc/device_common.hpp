@@ -117,15 +117,17 @@ __device__ __forceinline__ void decide128(uint32_t key0, uint32_t key1, uint32_t
 
 // One step of decide128_quad's ordered combine: the partner lane given by
 // the quad permutation PERM holds the results of the planes just before
-// (first = false) or just after (first = true) this lane's.
+// (first = 0) or just after (first = all ones) this lane's.  The choice is a
+// bit select, not a branch: the two halves of the quad take different sides.
 template <int PERM>
-__device__ __forceinline__ void quad_combine(bool first, uint32_t (&d)[4], uint32_t (&l)[4])
+__device__ __forceinline__ void quad_combine(uint32_t first, uint32_t (&d)[4], uint32_t (&l)[4])
 {
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
         const uint32_t dp = (uint32_t)__builtin_amdgcn_mov_dpp((int)d[w], PERM, 0xF, 0xF, false);
         const uint32_t lp = (uint32_t)__builtin_amdgcn_mov_dpp((int)l[w], PERM, 0xF, 0xF, false);
-        l[w] = first ? (l[w] | (lp & ~d[w])) : (lp | (l[w] & ~dp));
+        const uint32_t early = l[w] | (lp & ~d[w]), late = lp | (l[w] & ~dp);
+        l[w] = (first & early) | (~first & late);
         d[w] |= dp;
     }
 }
@@ -149,6 +151,9 @@ __device__ __forceinline__ void decide128_quad(uint32_t key0, uint32_t key1, uin
         eq[w] = live[w];
         lt[w] = 0u;
     }
+    // lanes 0, 2 of the quad precede their partner in the first combine step,
+    // lanes 0, 1 in the second
+    const uint32_t first1 = (q & 1u) ? 0u : ~0u, first2 = (q & 2u) ? 0u : ~0u;
     for (uint32_t j0 = 0; j0 < 32u; j0 += 4u) {
         // the quad's lanes share eq, so they leave together
         if ((eq[0] | eq[1] | eq[2] | eq[3]) == 0u) break;
@@ -177,8 +182,8 @@ __device__ __forceinline__ void decide128_quad(uint32_t key0, uint32_t key1, uin
         }
         // ordered combine, first plane first: (d, l) then (d', l') gives
         // (d | d', l | (l' & ~d)); pairs by lane bit 0, then by bit 1
-        quad_combine<0xB1>((q & 1u) == 0u, d, l);   // quad_perm [1, 0, 3, 2]
-        quad_combine<0x4E>((q & 2u) == 0u, d, l);   // quad_perm [2, 3, 0, 1]
+        quad_combine<0xB1>(first1, d, l);   // quad_perm [1, 0, 3, 2]
+        quad_combine<0x4E>(first2, d, l);   // quad_perm [2, 3, 0, 1]
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
             lt[w] |= eq[w] & l[w];
