@@ -115,83 +115,82 @@ __device__ __forceinline__ void decide128(uint32_t key0, uint32_t key1, uint32_t
     for (int w = 0; w < 4; ++w) D[w] = lt[w];
 }
 
-// One step of decide128_quad's ordered combine: the partner lane given by
-// the quad permutation PERM holds the results of the planes just before
-// (first = 0) or just after (first = all ones) this lane's.  The choice is a
-// bit select, not a branch: the two halves of the quad take different sides.
-template <int PERM>
-__device__ __forceinline__ void quad_combine(uint32_t first, uint32_t (&d)[4], uint32_t (&l)[4])
+// OR of v over the four lanes of a quad (DPP quad permutations).
+__device__ __forceinline__ uint32_t quad_or(uint32_t v)
 {
+    v |= (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);   // quad_perm [1, 0, 3, 2]
+    return v | (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);   // quad_perm [2, 3, 0, 1]
+}
+
+// Transpose of a 4 x 4 word matrix held by a quad, row q in lane q: after
+// it, R[x] of lane q is the old R[q] of lane x.  Two exchange steps: with
+// lane q ^ 1 the words whose index differs from q in bit 0, then with lane
+// q ^ 2 those that differ in bit 1.
+__device__ __forceinline__ void quad_transpose(uint32_t (&R)[4], uint32_t q)
+{
+    const uint32_t odd1 = (q & 1u) ? ~0u : 0u, odd2 = (q & 2u) ? ~0u : 0u;
+    uint32_t A[4];
 #pragma unroll
-    for (int w = 0; w < 4; ++w) {
-        const uint32_t dp = (uint32_t)__builtin_amdgcn_mov_dpp((int)d[w], PERM, 0xF, 0xF, false);
-        const uint32_t lp = (uint32_t)__builtin_amdgcn_mov_dpp((int)l[w], PERM, 0xF, 0xF, false);
-        const uint32_t early = l[w] | (lp & ~d[w]), late = lp | (l[w] & ~dp);
-        l[w] = (first & early) | (~first & late);
-        d[w] |= dp;
+    for (int x = 0; x < 4; ++x) {
+        const uint32_t other = (uint32_t)__builtin_amdgcn_mov_dpp((int)R[x ^ 1], 0xB1, 0xF, 0xF, false);
+        const uint32_t keep = (x & 1) ? odd1 : ~odd1;   // index and lane agree in bit 0
+        A[x] = (keep & R[x]) | (~keep & other);
+    }
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+        const uint32_t other = (uint32_t)__builtin_amdgcn_mov_dpp((int)A[x ^ 2], 0x4E, 0xF, 0xF, false);
+        const uint32_t keep = (x & 2) ? odd2 : ~odd2;   // ... in bit 1
+        R[x] = (keep & A[x]) | (~keep & other);
     }
 }
 
-// The same decisions with the planes spread over the four lanes of a quad
-// (lanes 4i .. 4i+3 hold the same 128 sites and call this together): in round
-// m lane q draws plane 4m + q, and the quad combines its four per-plane
-// results in plane order (DPP quad permutations), so one generator call per
-// lane settles four planes.  A site's decision is taken at its first plane
-// whose bit differs from its threshold's or after which the threshold has no
-// 1 bit left; that plane's verdict (threshold bit 1, uniform bit 0: below) is
-// the same one the plane-by-plane loop reaches.  All four lanes return D.
+// The same decisions for a group held by the quad of lanes 4i .. 4i+3, lane
+// q holding word q (sites 32q .. 32q+31) and calling this with the other
+// three: in round m lane q draws plane 4m + q, the quad transposes the four
+// draws so that each lane has its own word of the four planes, and each lane
+// runs those planes in order over its 32 sites.  A site's decision is taken at
+// its first plane whose bit differs from its threshold's or after which the
+// threshold has no 1 bit left, as in the plane-by-plane loop; the quad stops
+// when none of its sites is undecided.  D is this lane's word.
 template <int NC>
-__device__ __forceinline__ void decide128_quad(uint32_t key0, uint32_t key1, uint32_t g, uint32_t r, uint32_t t,
-                                               uint32_t c, const uint32_t (&T)[NC], const uint32_t (&cm)[NC][4],
-                                               const uint32_t (&live)[4], uint32_t q, uint32_t (&D)[4])
+__device__ __forceinline__ void decide32_quad(uint32_t key0, uint32_t key1, uint32_t g, uint32_t r, uint32_t t,
+                                              uint32_t c, const uint32_t (&T)[NC], const uint32_t (&cm)[NC][1],
+                                              const uint32_t (&live)[1], uint32_t q, uint32_t (&D)[1])
 {
-    uint32_t eq[4], lt[4];
+    // bit b of NZ[i]: T[i] has a 1 bit below bit b (bits above its lowest 1)
+    uint32_t NZ[NC];
 #pragma unroll
-    for (int w = 0; w < 4; ++w) {
-        eq[w] = live[w];
-        lt[w] = 0u;
+    for (int i = 0; i < NC; ++i) {
+        const uint32_t low = T[i] & (0u - T[i]);
+        NZ[i] = ~(low | (low - 1u));
     }
-    // lanes 0, 2 of the quad precede their partner in the first combine step,
-    // lanes 0, 1 in the second
-    const uint32_t first1 = (q & 1u) ? 0u : ~0u, first2 = (q & 2u) ? 0u : ~0u;
+    uint32_t eq = live[0], lt = 0u;
     for (uint32_t j0 = 0; j0 < 32u; j0 += 4u) {
-        // the quad's lanes share eq, so they leave together
-        if ((eq[0] | eq[1] | eq[2] | eq[3]) == 0u) break;
-        const uint32_t j = j0 + q, b = 31u - j;
+        if (quad_or(eq) == 0u) break;   // the same in the quad's four lanes
         uint32_t R[4];
-        philox4x32_10(g, r, t, (j << 2) | c, key0, key1, R);
-        const uint32_t below = (b == 0u) ? 0u : ((1u << b) - 1u);
-        uint32_t tsel[NC], nsel[NC];
+        philox4x32_10(g, r, t, ((j0 + q) << 2) | c, key0, key1, R);
+        quad_transpose(R, q);   // R[x]: this lane's word of plane j0 + x
+        // the round's bits of each class: plane j0 + x compares bit 31 - x
+        uint32_t Tr[NC], Nr[NC];
 #pragma unroll
         for (int i = 0; i < NC; ++i) {
-            tsel[i] = 0u - ((T[i] >> b) & 1u);
-            nsel[i] = (T[i] & below) ? ~0u : 0u;
+            Tr[i] = T[i] << j0;
+            Nr[i] = NZ[i] << j0;
         }
-        // this plane: decided (bits differ, or no threshold bit left) and below
-        uint32_t d[4], l[4];
 #pragma unroll
-        for (int w = 0; w < 4; ++w) {
+        for (int x = 0; x < 4; ++x) {
             uint32_t tb = 0u, nz = 0u;
 #pragma unroll
             for (int i = 0; i < NC; ++i) {
-                tb |= cm[i][w] & tsel[i];
-                nz |= cm[i][w] & nsel[i];
+                tb |= cm[i][0] & (uint32_t)((int32_t)(Tr[i] << x) >> 31);
+                nz |= cm[i][0] & (uint32_t)((int32_t)(Nr[i] << x) >> 31);
             }
-            d[w] = (tb ^ R[w]) | ~nz;
-            l[w] = tb & ~R[w];
-        }
-        // ordered combine, first plane first: (d, l) then (d', l') gives
-        // (d | d', l | (l' & ~d)); pairs by lane bit 0, then by bit 1
-        quad_combine<0xB1>(first1, d, l);   // quad_perm [1, 0, 3, 2]
-        quad_combine<0x4E>(first2, d, l);   // quad_perm [2, 3, 0, 1]
-#pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            lt[w] |= eq[w] & l[w];
-            eq[w] &= ~d[w];
+            const uint32_t d = (tb ^ R[x]) | ~nz, l = tb & ~R[x];
+            lt |= eq & l;
+            eq &= ~d;
         }
     }
-#pragma unroll
-    for (int w = 0; w < 4; ++w) D[w] = lt[w];
+    D[0] = lt;
 }
 
 // Tile of work-group b of n in an XCD-aware order: work-groups are dispatched

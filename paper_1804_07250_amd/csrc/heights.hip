@@ -132,16 +132,56 @@ __global__ void height_init_kernel(uint32_t *pa, uint32_t *pb, size_t PS, uint32
     if (pb) pb[p * PS + (size_t)y * RS + w] = bits;
 }
 
+// Words of a group that one lane holds: all four when a lane has the task to
+// itself (one-bit decisions), or word q alone when a quad of lanes shares it
+// (lane q of the quad, bit-serial decisions).
+template <uint32_t L>
+constexpr int kWords = L == 4 ? 1 : 4;
+
+template <int W>
+__device__ __forceinline__ void hldw(const uint32_t *p, uint32_t q, uint32_t (&v)[W])
+{
+    if constexpr (W == 4)
+        hld4(p, v);
+    else
+        v[0] = p[q];
+}
+template <int W>
+__device__ __forceinline__ void hldw_plus1(const uint32_t *p, uint32_t q, uint32_t (&v)[W])
+{
+    if constexpr (W == 4)
+        hld4_plus1(p, v);
+    else
+        v[0] = (p[q] >> 1) | (p[q + 1u] << 31);
+}
+template <int W>
+__device__ __forceinline__ void hldw_minus1(const uint32_t *p, uint32_t q, uint32_t (&v)[W])
+{
+    if constexpr (W == 4)
+        hld4_minus1(p, v);
+    else
+        v[0] = (p[q] << 1) | (p[(int)q - 1] >> 31);
+}
+template <int W>
+__device__ __forceinline__ void hstw(uint32_t *p, uint32_t q, const uint32_t (&v)[W])
+{
+    if constexpr (W == 4)
+        hst4(p, v);
+    else
+        p[q] = v[0];
+}
+
 // Bit-serial decisions of one group: plane by plane in one lane (L = 1,
-// kPlanes generator calls per iteration), or with the planes spread over the
-// quad of lanes that holds the group (L = 4, this lane is q of the quad).
+// kPlanes generator calls per iteration), or by the quad of lanes that holds
+// the group a word per lane (L = 4, this lane is q of the quad).
 template <int NC, uint32_t L, uint32_t kPlanes = 1>
 __device__ __forceinline__ void decide_sites(uint32_t k0, uint32_t k1, uint32_t g, uint32_t r, uint32_t t, uint32_t c,
-                                             const uint32_t (&T)[NC], const uint32_t (&cm)[NC][4],
-                                             const uint32_t (&live)[4], uint32_t q, uint32_t (&D)[4])
+                                             const uint32_t (&T)[NC], const uint32_t (&cm)[NC][kWords<L>],
+                                             const uint32_t (&live)[kWords<L>], uint32_t q,
+                                             uint32_t (&D)[kWords<L>])
 {
     if constexpr (L == 4)
-        decide128_quad<NC>(k0, k1, g, r, t, c, T, cm, live, q, D);
+        decide32_quad<NC>(k0, k1, g, r, t, c, T, cm, live, q, D);
     else
         decide128<NC, kPlanes>(k0, k1, g, r, t, c, T, cm, live, D);
 }
@@ -151,19 +191,23 @@ __device__ __forceinline__ void decide_sites(uint32_t k0, uint32_t k1, uint32_t 
 // when a heat-bath table has 5 entries, classes by sA + sB alone.
 template <int MODE, uint32_t L>
 __device__ __forceinline__ void loz_decide(uint32_t k0, uint32_t k1, uint32_t g, uint32_t r, uint32_t t, uint32_t c,
-                                           const Thr &Tall, const uint32_t (&R0)[4], const uint32_t (&cur)[4],
-                                           const uint32_t (&live)[4], uint32_t q, uint32_t (&D)[4])
+                                           const Thr &Tall, const uint32_t (&R0)[4],
+                                           const uint32_t (&cur)[kWords<L>], const uint32_t (&live)[kWords<L>],
+                                           uint32_t q, uint32_t (&D)[kWords<L>])
 {
-    if (MODE == kUniform) {
+    constexpr int W = kWords<L>;
+    if constexpr (MODE == kUniform) {
 #pragma unroll
-        for (int w = 0; w < 4; ++w) D[w] = ~R0[w];
-    } else if (MODE == kHeatBath) {
-        uint32_t T[1] = {Tall.v[0]}, cm[1][4] = {{~0u, ~0u, ~0u, ~0u}};
+        for (int w = 0; w < W; ++w) D[w] = ~R0[w];
+    } else if constexpr (MODE == kHeatBath) {
+        uint32_t T[1] = {Tall.v[0]}, cm[1][W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) cm[0][w] = ~0u;
         decide_sites<1, L, 2>(k0, k1, g, r, t, c, T, cm, live, q, D);
     } else {
-        uint32_t T[2] = {Tall.v[0], Tall.v[1]}, cm[2][4];
+        uint32_t T[2] = {Tall.v[0], Tall.v[1]}, cm[2][W];
 #pragma unroll
-        for (int w = 0; w < 4; ++w) {
+        for (int w = 0; w < W; ++w) {
             cm[0][w] = ~cur[w];
             cm[1][w] = cur[w];
         }
@@ -178,28 +222,29 @@ __device__ __forceinline__ void loz_decide(uint32_t k0, uint32_t k1, uint32_t g,
 template <int MODE, uint32_t L>
 __device__ __forceinline__ void sixv_free_decide(uint32_t k0, uint32_t k1, uint32_t g, uint32_t r, uint32_t t,
                                                  uint32_t c, const Thr &Tall, const uint32_t (&R0)[4],
-                                                 const uint32_t (&hSW)[4], const uint32_t (&hSE)[4],
-                                                 const uint32_t (&cur)[4], const uint32_t (&live)[4], uint32_t q,
-                                                 uint32_t (&D)[4])
+                                                 const uint32_t (&hSW)[kWords<L>], const uint32_t (&hSE)[kWords<L>],
+                                                 const uint32_t (&cur)[kWords<L>], const uint32_t (&live)[kWords<L>],
+                                                 uint32_t q, uint32_t (&D)[kWords<L>])
 {
+    constexpr int W = kWords<L>;
     if constexpr (MODE == kUniform) {
 #pragma unroll
-        for (int w = 0; w < 4; ++w) D[w] = ~R0[w];
+        for (int w = 0; w < W; ++w) D[w] = ~R0[w];
     } else {
         constexpr int NC = MODE == kMetropolis ? 8 : 4;
-        uint32_t T[NC], cm[NC][4];
+        uint32_t T[NC], cm[NC][W];
 #pragma unroll
         for (int i = 0; i < NC; ++i) T[i] = Tall.v[Thr::kFreeBase + i];
 #pragma unroll
-        for (int w = 0; w < 4; ++w)
+        for (int w = 0; w < W; ++w)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint32_t m = ((q & 1) ? hSW[w] : ~hSW[w]) & ((q & 2) ? hSE[w] : ~hSE[w]);
+            for (int x = 0; x < 4; ++x) {
+                const uint32_t m = ((x & 1) ? hSW[w] : ~hSW[w]) & ((x & 2) ? hSE[w] : ~hSE[w]);
                 if (MODE == kMetropolis) {
-                    cm[2 * q][w] = m & ~cur[w];
-                    cm[2 * q + 1][w] = m & cur[w];
+                    cm[2 * x][w] = m & ~cur[w];
+                    cm[2 * x + 1][w] = m & cur[w];
                 } else {
-                    cm[q][w] = m;
+                    cm[x][w] = m;
                 }
             }
         decide_sites<NC, L>(k0, k1, g, r, t, c, T, cm, live, q, D);
@@ -208,45 +253,46 @@ __device__ __forceinline__ void sixv_free_decide(uint32_t k0, uint32_t k1, uint3
 
 template <int MODE, int KIND, uint32_t L>
 __device__ __forceinline__ void sixv_decide(uint32_t k0, uint32_t k1, uint32_t g, uint32_t r, uint32_t t, uint32_t c,
-                                            const Thr &Tall, const uint32_t (&R0)[4], const uint32_t (&hNE)[4],
-                                            const uint32_t (&hNW)[4], const uint32_t (&hSW)[4],
-                                            const uint32_t (&hSE)[4], const uint32_t (&cur)[4],
-                                            const uint32_t (&live)[4], uint32_t q, uint32_t (&D)[4])
+                                            const Thr &Tall, const uint32_t (&R0)[4], const uint32_t (&hNE)[kWords<L>],
+                                            const uint32_t (&hNW)[kWords<L>], const uint32_t (&hSW)[kWords<L>],
+                                            const uint32_t (&hSE)[kWords<L>], const uint32_t (&cur)[kWords<L>],
+                                            const uint32_t (&live)[kWords<L>], uint32_t q, uint32_t (&D)[kWords<L>])
 {
+    constexpr int W = kWords<L>;
     if constexpr (MODE == kUniform) {
 #pragma unroll
-        for (int w = 0; w < 4; ++w) D[w] = ~R0[w];
+        for (int w = 0; w < W; ++w) D[w] = ~R0[w];
     } else if constexpr (KIND == kKindSum) {
         // thresholds that depend on sA + sB only (a = b): 5 classes s = 0..4
         // (Metropolis: x current state, down then up)
         constexpr int NC = MODE == kMetropolis ? 10 : 5;
-        uint32_t T[NC], cm[NC][4];
+        uint32_t T[NC], cm[NC][W];
 #pragma unroll
         for (int i = 0; i < NC; ++i) T[i] = Tall.v[i];
 #pragma unroll
-        for (int w = 0; w < 4; ++w) {
+        for (int w = 0; w < W; ++w) {
             const uint32_t A0 = ~hNE[w] & ~hSW[w], A1 = hNE[w] ^ hSW[w], A2 = hNE[w] & hSW[w];
             const uint32_t B0 = ~hNW[w] & ~hSE[w], B1 = hNW[w] ^ hSE[w], B2 = hNW[w] & hSE[w];
             const uint32_t s[5] = {A0 & B0, (A0 & B1) | (A1 & B0), (A0 & B2) | (A1 & B1) | (A2 & B0),
                                    (A1 & B2) | (A2 & B1), A2 & B2};
 #pragma unroll
-            for (int q = 0; q < 5; ++q) {
+            for (int x = 0; x < 5; ++x) {
                 if constexpr (MODE == kMetropolis) {
-                    cm[2 * q][w] = s[q] & ~cur[w];
-                    cm[2 * q + 1][w] = s[q] & cur[w];
+                    cm[2 * x][w] = s[x] & ~cur[w];
+                    cm[2 * x + 1][w] = s[x] & cur[w];
                 } else {
-                    cm[q][w] = s[q];
+                    cm[x][w] = s[x];
                 }
             }
         }
         decide_sites<NC, L>(k0, k1, g, r, t, c, T, cm, live, q, D);
     } else {
         constexpr int NC = MODE == kMetropolis ? 18 : 9;
-        uint32_t T[NC], cm[NC][4];
+        uint32_t T[NC], cm[NC][W];
 #pragma unroll
         for (int i = 0; i < NC; ++i) T[i] = Tall.v[i];
 #pragma unroll
-        for (int w = 0; w < 4; ++w) {
+        for (int w = 0; w < W; ++w) {
             const uint32_t A[3] = {~hNE[w] & ~hSW[w], hNE[w] ^ hSW[w], hNE[w] & hSW[w]};
             const uint32_t B[3] = {~hNW[w] & ~hSE[w], hNW[w] ^ hSE[w], hNW[w] & hSE[w]};
 #pragma unroll
@@ -266,6 +312,15 @@ __device__ __forceinline__ void sixv_decide(uint32_t k0, uint32_t k1, uint32_t g
     }
 }
 
+// Whether any lane of the quad has a nonzero value (the same answer in the
+// four lanes, so that they call the shared decisions together).
+template <uint32_t L>
+__device__ __forceinline__ uint32_t group_any(uint32_t v)
+{
+    if constexpr (L == 4) return quad_or(v);
+    return v;
+}
+
 // One lozenge group: sites k = 128 g + (0..127) of plane s0 in row Y.
 // base(p, row) -> pointer to word 4 lg of that plane row (data words, pads
 // around it).  lrow is the row index in the addressed array.
@@ -274,51 +329,55 @@ __device__ __forceinline__ void loz_group(uint32_t *base, size_t ps, uint32_t rs
                                           const Geo &geo, int Y, uint32_t g, uint32_t s0, uint32_t colour, uint32_t t,
                                           const Thr &Tall, uint32_t k0, uint32_t k1, uint32_t q)
 {
+    constexpr int W = kWords<L>;
     uint32_t R0[4] = {0u, 0u, 0u, 0u};
     if (MODE == kUniform) philox4x32_10(g, (uint32_t)Y, t, colour, k0, k1, R0);
     auto P = [&](uint32_t p, uint32_t r) { return base + p * ps + (size_t)r * rs + 4u + 4u * lgrp; };
-    uint32_t O[4], f1[4], f2[4], f3[4], b1[4], b2[4], b3[4];
-    hld4(P(s0, lrow), O);
-    hld4(P(s0, lrow + 1), f2);
-    hld4(P(s0, lrow - 1), b2);
+    uint32_t O[W], f1[W], f2[W], f3[W], b1[W], b2[W], b3[W];
+    hldw<W>(P(s0, lrow), q, O);
+    hldw<W>(P(s0, lrow + 1), q, f2);
+    hldw<W>(P(s0, lrow - 1), q, b2);
     if (s0 < 2) {
-        hld4(P(s0 + 1, lrow), f1);
-        hld4(P(s0 + 1, lrow + 1), f3);
+        hldw<W>(P(s0 + 1, lrow), q, f1);
+        hldw<W>(P(s0 + 1, lrow + 1), q, f3);
     } else {
-        hld4_plus1(P(0, lrow), f1);
-        hld4_plus1(P(0, lrow + 1), f3);
+        hldw_plus1<W>(P(0, lrow), q, f1);
+        hldw_plus1<W>(P(0, lrow + 1), q, f3);
     }
     if (s0 > 0) {
-        hld4(P(s0 - 1, lrow), b1);
-        hld4(P(s0 - 1, lrow - 1), b3);
+        hldw<W>(P(s0 - 1, lrow), q, b1);
+        hldw<W>(P(s0 - 1, lrow - 1), q, b3);
     } else {
-        hld4_minus1(P(2, lrow), b1);
-        hld4_minus1(P(2, lrow - 1), b3);
+        hldw_minus1<W>(P(2, lrow), q, b1);
+        hldw_minus1<W>(P(2, lrow - 1), q, b3);
     }
     // interior of row Y: X in (max(0, Y-b), min(a+c, Y+a)), X = 3k + s0
     const int xlo = imax(0, Y - geo.b), xhi = imin(geo.a + geo.c, Y + geo.a);
     const int klo = floordiv(xlo - (int)s0, 3) + 1, khi = floordiv(xhi - (int)s0 - 1, 3);
     // a masked domain: only its sites
-    uint32_t sm[4] = {~0u, ~0u, ~0u, ~0u};
-    if constexpr (MASKED) hld4(geo.site + s0 * geo.sPS + (size_t)Y * geo.sRS + 4u + 4u * g, sm);
-    uint32_t live[4], cur[4];
+    uint32_t sm[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) sm[w] = ~0u;
+    if constexpr (MASKED) hldw<W>(geo.site + s0 * geo.sPS + (size_t)Y * geo.sRS + 4u + 4u * g, q, sm);
+    uint32_t live[W], cur[W];
     uint32_t any = 0u;
 #pragma unroll
-    for (int w = 0; w < 4; ++w) {
-        const uint32_t m = range_mask((int)(4 * g) + w, klo, khi) & sm[w];
+    for (int w = 0; w < W; ++w) {
+        const int wi = W == 4 ? w : (int)q;   // the word's index in the group
+        const uint32_t m = range_mask((int)(4 * g) + wi, klo, khi) & sm[w];
         live[w] = ~(f1[w] ^ f2[w]) & ~(f1[w] ^ f3[w]) & ~(b1[w] ^ b2[w]) & ~(b1[w] ^ b3[w]) & (f1[w] ^ b1[w]) & m;
         cur[w] = ~(O[w] ^ b1[w]);
         any |= live[w];
     }
-    if (!any) return;
-    uint32_t D[4];
+    if (!group_any<L>(any)) return;
+    uint32_t D[W];
     loz_decide<MODE, L>(k0, k1, g, (uint32_t)Y, t, colour, Tall, R0, cur, live, q, D);
 #pragma unroll
-    for (int w = 0; w < 4; ++w) {
+    for (int w = 0; w < W; ++w) {
         const uint32_t nw = (D[w] & b1[w]) | (~D[w] & f1[w]);
         O[w] = (O[w] & ~live[w]) | (nw & live[w]);
     }
-    if (q == 0u) hst4(P(s0, lrow), O);
+    hstw<W>(P(s0, lrow), q, O);
 }
 
 // One six-vertex group: faces I = 2k + p, k = 128 g + (0..127), of row J.
@@ -327,56 +386,63 @@ __device__ __forceinline__ void sixv_group(uint32_t *base, size_t ps, uint32_t r
                                            const Geo &geo, int J, uint32_t g, uint32_t p, uint32_t colour, uint32_t t,
                                            const Thr &Tall, uint32_t k0, uint32_t k1, uint32_t q)
 {
+    constexpr int W = kWords<L>;
     uint32_t R0[4] = {0u, 0u, 0u, 0u};
     if (MODE == kUniform) philox4x32_10(g, (uint32_t)J, t, colour, k0, k1, R0);
-    auto P = [&](uint32_t q, uint32_t r) { return base + q * ps + (size_t)r * rs + 4u + 4u * lgrp; };
-    uint32_t O[4], Nn[4], Sn[4], E[4], W[4], NE[4], NW[4], SE[4], SW[4];
-    hld4(P(p, lrow), O);
-    hld4(P(p, lrow + 1), Nn);
-    hld4(P(p, lrow - 1), Sn);
+    auto P = [&](uint32_t pl, uint32_t r) { return base + pl * ps + (size_t)r * rs + 4u + 4u * lgrp; };
+    uint32_t O[W], Nn[W], Sn[W], E[W], Wn[W], NE[W], NW[W], SE[W], SW[W];
+    hldw<W>(P(p, lrow), q, O);
+    hldw<W>(P(p, lrow + 1), q, Nn);
+    hldw<W>(P(p, lrow - 1), q, Sn);
     if (p == 0) {
-        hld4(P(1, lrow), E);
-        hld4_minus1(P(1, lrow), W);
-        hld4(P(1, lrow + 1), NE);
-        hld4_minus1(P(1, lrow + 1), NW);
-        hld4(P(1, lrow - 1), SE);
-        hld4_minus1(P(1, lrow - 1), SW);
+        hldw<W>(P(1, lrow), q, E);
+        hldw_minus1<W>(P(1, lrow), q, Wn);
+        hldw<W>(P(1, lrow + 1), q, NE);
+        hldw_minus1<W>(P(1, lrow + 1), q, NW);
+        hldw<W>(P(1, lrow - 1), q, SE);
+        hldw_minus1<W>(P(1, lrow - 1), q, SW);
     } else {
-        hld4_plus1(P(0, lrow), E);
-        hld4(P(0, lrow), W);
-        hld4_plus1(P(0, lrow + 1), NE);
-        hld4(P(0, lrow + 1), NW);
-        hld4_plus1(P(0, lrow - 1), SE);
-        hld4(P(0, lrow - 1), SW);
+        hldw_plus1<W>(P(0, lrow), q, E);
+        hldw<W>(P(0, lrow), q, Wn);
+        hldw_plus1<W>(P(0, lrow + 1), q, NE);
+        hldw<W>(P(0, lrow + 1), q, NW);
+        hldw_plus1<W>(P(0, lrow - 1), q, SE);
+        hldw<W>(P(0, lrow - 1), q, SW);
     }
     // interior faces 1 <= I <= N-1 (and, in a masked domain, its sites)
     const int klo = p == 0 ? 1 : 0, khi = (geo.N - 1 - (int)p) >> 1;
-    uint32_t sm[4] = {~0u, ~0u, ~0u, ~0u}, fm[4] = {0u, 0u, 0u, 0u};
+    uint32_t sm[W], fm[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        sm[w] = ~0u;
+        fm[w] = 0u;
+    }
     int side = 0;
     if constexpr (MASKED) {
-        hld4(geo.site + p * geo.sPS + (size_t)J * geo.sRS + 4u + 4u * g, sm);
+        hldw<W>(geo.site + p * geo.sPS + (size_t)J * geo.sRS + 4u + 4u * g, q, sm);
         // points of the free side ignore their (absent) neighbour across it
         if (geo.freep) {
-            hld4(geo.freep + p * geo.sPS + (size_t)J * geo.sRS + 4u + 4u * g, fm);
+            hldw<W>(geo.freep + p * geo.sPS + (size_t)J * geo.sRS + 4u + 4u * g, q, fm);
             side = geo.free_side;
         }
     }
     const bool podd = ((p + (uint32_t)J) & 1u) != 0u;   // parity of I + J
-    uint32_t live[4], up[4], hNE[4], hNW[4], hSW[4], hSE[4], cur[4];
+    uint32_t live[W], up[W], hNE[W], hNW[W], hSW[W], hSE[W], cur[W];
     uint32_t any = 0u;
 #pragma unroll
-    for (int w = 0; w < 4; ++w) {
-        const uint32_t m = range_mask((int)(4 * g) + w, klo, khi) & sm[w];
-        const uint32_t eEW = ~(E[w] ^ W[w]), eEN = ~(E[w] ^ Nn[w]), eES = ~(E[w] ^ Sn[w]);
+    for (int w = 0; w < W; ++w) {
+        const int wi = W == 4 ? w : (int)q;   // the word's index in the group
+        const uint32_t m = range_mask((int)(4 * g) + wi, klo, khi) & sm[w];
+        const uint32_t eEW = ~(E[w] ^ Wn[w]), eEN = ~(E[w] ^ Nn[w]), eES = ~(E[w] ^ Sn[w]);
         // free points: the three neighbours off the free side share m
         const uint32_t lf = side == 1   ? eEW & eES
                             : side == 2 ? eEW & eEN
-                            : side == 3 ? ~(W[w] ^ Nn[w]) & ~(W[w] ^ Sn[w])
+                            : side == 3 ? ~(Wn[w] ^ Nn[w]) & ~(Wn[w] ^ Sn[w])
                             : side == 4 ? eEN & eES
                                         : 0u;
         live[w] = ((eEW & eEN & eES & ~fm[w]) | (lf & fm[w])) & m;
         // residual bit of m + 1 (m read off E, or W across a free east side)
-        const uint32_t ref = side == 3 ? (E[w] & ~fm[w]) | (W[w] & fm[w]) : E[w];
+        const uint32_t ref = side == 3 ? (E[w] & ~fm[w]) | (Wn[w] & fm[w]) : E[w];
         up[w] = podd ? ref : ~ref;
         hNE[w] = ~(NE[w] ^ up[w]);
         hNW[w] = ~(NW[w] ^ up[w]);
@@ -385,35 +451,35 @@ __device__ __forceinline__ void sixv_group(uint32_t *base, size_t ps, uint32_t r
         cur[w] = ~(O[w] ^ up[w]);
         any |= live[w];
     }
-    if (!any) return;
-    uint32_t D[4];
+    if (!group_any<L>(any)) return;
+    uint32_t D[W];
     if constexpr (MASKED) {
-        uint32_t li[4], lf[4], anyf = 0u;
+        uint32_t li[W], lf[W], anyf = 0u;
 #pragma unroll
-        for (int w = 0; w < 4; ++w) {
+        for (int w = 0; w < W; ++w) {
             li[w] = live[w] & ~fm[w];
             lf[w] = live[w] & fm[w];
             anyf |= lf[w];
         }
         sixv_decide<MODE, KIND, L>(k0, k1, g, (uint32_t)J, t, colour, Tall, R0, hNE, hNW, hSW, hSE, cur, li, q, D);
-        if (anyf) {
-            uint32_t Df[4];
+        if (group_any<L>(anyf)) {
+            uint32_t Df[W];
             // context diagonals beside the two cells the flip changes
-            const uint32_t (&c0)[4] = side == 2 ? hNW : side == 4 ? hSE : hSW;
-            const uint32_t (&c1)[4] = side == 1 ? hSE : side == 3 ? hNW : hNE;
+            const uint32_t (&c0)[W] = side == 2 ? hNW : side == 4 ? hSE : hSW;
+            const uint32_t (&c1)[W] = side == 1 ? hSE : side == 3 ? hNW : hNE;
             sixv_free_decide<MODE, L>(k0, k1, g, (uint32_t)J, t, colour, Tall, R0, c0, c1, cur, lf, q, Df);
 #pragma unroll
-            for (int w = 0; w < 4; ++w) D[w] = (D[w] & ~fm[w]) | (Df[w] & fm[w]);
+            for (int w = 0; w < W; ++w) D[w] = (D[w] & ~fm[w]) | (Df[w] & fm[w]);
         }
     } else {
         sixv_decide<MODE, KIND, L>(k0, k1, g, (uint32_t)J, t, colour, Tall, R0, hNE, hNW, hSW, hSE, cur, live, q, D);
     }
 #pragma unroll
-    for (int w = 0; w < 4; ++w) {
+    for (int w = 0; w < W; ++w) {
         const uint32_t nw = ~(D[w] ^ up[w]);
         O[w] = (O[w] & ~live[w]) | (nw & live[w]);
     }
-    if (q == 0u) hst4(P(p, lrow), O);
+    hstw<W>(P(p, lrow), q, O);
 }
 
 // Which plane of row y holds the sites of colour c (-1: none in this row).
