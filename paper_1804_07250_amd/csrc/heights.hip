@@ -52,10 +52,12 @@ namespace {
 enum { kHeatBath = 0, kMetropolis = 1, kUniform = 2 };
 static_assert(kHeatBath == kModeHeatBath && kMetropolis == kModeMetropolis && kUniform == kModeUniform,
               "kernel modes and TileJob modes agree");
-// Threads per work-group of the tiled and item kernels: 512 leaves 256 VGPRs
-// per lane for the weighted decisions (the largest plans use ~400).
+// Tasks per work-group of a tile, and lanes per work-group of the multi-job
+// kernels (512: room for the step kernels' registers when one-bit and
+// bit-serial jobs share a launch); the tiled kernels take up to 1024 lanes
+// (a quad of lanes per bit-serial task needs at most 69 registers per lane).
 constexpr uint32_t kHeightThreads = 512;
-constexpr uint32_t kLozThreads = 1024;
+constexpr uint32_t kTileThreads = 1024;
 // Layout of a six-vertex threshold table (each layout is its own kernel
 // instantiation, so its registers are allocated for it alone): 9 classes
 // (sA, sB) [x2 for Metropolis], or 5 classes by sA + sB (heat-bath).  Lozenge
@@ -618,17 +620,9 @@ __device__ __forceinline__ void height_tile(uint32_t *lds, const uint32_t *__res
     }
 }
 
-// Tiled multi-sweep kernels of one state: one work-group per tile.  Six-
-// vertex tiles with the nine-class tables, or Metropolis tables by sA + sB on
-// masked domains, run up to 512 lanes (their bit-serial context masks need up
-// to ~190 registers per lane), the others and lozenge tiles up to 1024.
-template <int MODE, int KIND, bool MASKED>
-constexpr uint32_t sixv_threads()
-{
-    return MODE == kUniform || (KIND == kKindSum && !(MASKED && MODE == kMetropolis)) ? kLozThreads : kHeightThreads;
-}
+// Tiled multi-sweep kernels of one state: one work-group per tile.
 template <int MODE, int KIND, bool RANDOM, bool MASKED>
-__global__ void __launch_bounds__((sixv_threads<MODE, KIND, MASKED>())) height_tiled_kernel(const uint32_t *__restrict__ in,
+__global__ void __launch_bounds__(kTileThreads) height_tiled_kernel(const uint32_t *__restrict__ in,
                                                             uint32_t *__restrict__ out, size_t PS, uint32_t RS,
                                                             uint32_t ng, uint32_t rows, uint32_t P, Geo geo,
                                                             uint32_t t0, uint32_t nsweeps, uint32_t TR, uint32_t TG,
@@ -642,7 +636,7 @@ __global__ void __launch_bounds__((sixv_threads<MODE, KIND, MASKED>())) height_t
                                                        HR, HG, blockIdx.x / tiles_x, blockIdx.x % tiles_x, T, k0, k1);
 }
 template <int MODE, int KIND, bool RANDOM, bool MASKED>
-__global__ void __launch_bounds__(kLozThreads) loz_tiled_kernel(const uint32_t *__restrict__ in,
+__global__ void __launch_bounds__(kTileThreads) loz_tiled_kernel(const uint32_t *__restrict__ in,
                                                         uint32_t *__restrict__ out, size_t PS, uint32_t RS,
                                                         uint32_t ng, uint32_t rows, uint32_t P, Geo geo, uint32_t t0,
                                                         uint32_t nsweeps, uint32_t TR, uint32_t TG, uint32_t HR,
@@ -986,7 +980,7 @@ bool height_plan(const HeightDev &d, const HeightTile &tile, uint32_t S_max, Til
     // a thread per task, a quad per task for bit-serial decisions (the
     // kernel loops over the tasks when the work-group has fewer lanes)
     const uint32_t lanes = (tasks * (tile.lanes ? tile.lanes : 1u) + 63) / 64 * 64;
-    const uint32_t cap = tile.items ? kHeightThreads : (tile.wide || d.model == TL_LOZENGE ? kLozThreads : kHeightThreads);
+    const uint32_t cap = tile.items ? kHeightThreads : kTileThreads;
     p->threads = lanes < cap ? lanes : cap;
     p->lds = lds;
     p->order = tile.order;

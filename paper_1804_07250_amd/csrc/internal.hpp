@@ -206,7 +206,6 @@ struct HeightTile {
     uint32_t order = 0;   // colour order: 0 fixed, 1 random per step
     uint32_t lanes = 1;   // lanes per task: 1 (one-bit decisions) or 4 (bit-serial, a quad per task)
     uint32_t items = 0;   // 1: a share of a multi-job launch (work-groups of at most 512 lanes)
-    uint32_t wide = 0;    // 1: six-vertex tables the 1024-lane kernels take (one-bit, or by sA + sB)
 };
 size_t height_words(HeightDev &d);
 hipError_t height_init(const HeightDev &d, int init_max, hipStream_t s);

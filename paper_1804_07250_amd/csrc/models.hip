@@ -559,7 +559,6 @@ public:
         if (opt.sweeps_per_launch) tile.S = opt.sweeps_per_launch;
         tile.order = order;
         tile.lanes = K.uniform() ? 1u : 4u;
-        tile.wide = K.uniform() || (table_kind(K) == kTableSum && !(metro && region_)) ? 1u : 0u;
         return height_tiled_sweeps(d_, tile, t0, n, K, metro ? 1 : 0, seed, s, &timing);
     }
     hipError_t observe(uint32_t B, uint32_t bins_x, unsigned long long *bins, hipStream_t s) override
