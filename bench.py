@@ -225,7 +225,7 @@ def run_served(tl, args, budget_mib):
             "peak_active": st["peak_active"], "peak_bytes": st["peak_bytes"],
             "workload": "served: six-vertex DWBC, N uniform over {64,128,256,512,1024}, weights (1,1,sqrt2) and "
                         "(1,1,1) alternating (lazy Metropolis), %d sweeps per request, Poisson %.0f/s, %d requests, budget %d MiB, "
-                        "%d slots, ticks of %d sweeps (x4 for one-bit jobs)"
+                        "%d slots, ticks of %d sweeps (x2 for one-bit jobs)"
                         % (args.served_sweeps, args.served_rate, len(res), budget_mib, args.served_slots,
                            args.served_quantum)}
 

@@ -392,9 +392,11 @@ tl_status tl_batch_destroy(tl_batch *b);
  * A request loop with continuous batching: jobs (any model and domain) are
  * queued by tl_server_submit and admitted in arrival order by a scheduler
  * thread while the device-memory budget and the slot count allow; admitted
- * chains stay resident on the device and advance in quanta of
- * tl_options.sweeps_per_launch sweeps (default 250) on their own streams, so
- * jobs that arrive while others run overlap with them on the GPU.  A finished
+ * chains stay resident on the device and advance together in ticks: each tick
+ * moves every resident job by tl_options.sweeps_per_launch sweeps (default 8;
+ * twice that for jobs with one-bit decisions) in one launch per kernel family,
+ * a work-group per tile of each job, so jobs that arrive while others run
+ * share the GPU with them.  A finished
  * job's result is its canonical hash and whole-domain observable; its memory
  * is released at once.  A job gives the same result alone and in a mix.
  * Domains given by masks are served too (their host pre-pass runs in

@@ -174,7 +174,7 @@ struct Finish {
 struct tl_server {
     size_t budget = 0;
     int32_t max_slots = 0;
-    uint32_t quantum = 8;   // sweeps per tick of a weighted job (4x for one-bit jobs)
+    uint32_t quantum = 8;   // sweeps per tick of a weighted job (2x for one-bit jobs)
     uint32_t order = 0;     // colour order of every job: 0 fixed, 1 random per step
     int device = 0;
     std::chrono::steady_clock::time_point t0;
@@ -378,7 +378,9 @@ bool tick(tl_server *sv)
     for (size_t i = 0; i < run.size(); ++i) {
         Job &j = *run[i];
         const uint64_t left = j.sweeps - j.enq;
-        const uint64_t want = (uint64_t)sv->quantum * (j.uniform ? 4u : 1u);
+        // one-bit jobs take twice the sweeps per tick (their launch then
+        // lasts about as long as the weighted one beside it)
+        const uint64_t want = (uint64_t)sv->quantum * (j.uniform ? 2u : 1u);
         const uint32_t smax = (uint32_t)std::min<uint64_t>(left, want);
         if (!j.model->tile_job((uint32_t)j.enq, smax, j.T, j.metro, j.seed, true, &jobs[i], &plans[i])) {
             j.status = TL_EINVAL;
