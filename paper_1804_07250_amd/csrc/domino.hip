@@ -413,8 +413,15 @@ __global__ void __launch_bounds__(1024) domino_reg_kernel(const uint32_t *__rest
                                                           uint32_t TG, uint32_t HR, uint32_t HG, uint32_t tiles_x,
                                                           Thr Tall, uint32_t key0, uint32_t key1)
 {
-    // first words of E and S published for the previous group, and carries
-    __shared__ uint32_t xE[kRegGroups][kRegRows], xS[kRegGroups][kRegRows], xC[kRegGroups][kRegRows];
+    // First words of E and S published for the previous group, and either the
+    // carries (bit-serial decisions: a second barrier) or, for one-bit
+    // decisions, the bits of the group's last site from which the next group
+    // computes that carry itself (one barrier per other-colour step; the
+    // arrays alternate between consecutive such steps, so a wavefront that
+    // runs ahead never overwrites what a slower one has still to read).
+    constexpr bool kOneBarrier = MODE == kUniform;
+    __shared__ uint32_t xE[2][kRegGroups][kRegRows], xS[2][kRegGroups][kRegRows], xC[2][kRegGroups][kRegRows];
+    uint32_t xb = 0;   // buffer of the next other-colour step
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const uint32_t tile_r = tile / tiles_x, tile_g = tile % tiles_x;
     const uint32_t LR = TR + 2 * HR, LG = TG + 2 * HG;
@@ -466,17 +473,33 @@ __global__ void __launch_bounds__(1024) domino_reg_kernel(const uint32_t *__rest
                     }
                 }
             } else {
-                xE[lg][lr] = E[0];
-                xS[lg][lr] = S[0];
                 uint32_t S1[4], W1[4];
 #pragma unroll
                 for (int w = 0; w < 4; ++w) {
                     S1[w] = lane_next(S[w]);
                     W1[w] = lane_next(W[w]);
                 }
+                xE[xb][lg][lr] = E[0];
+                xS[xb][lg][lr] = S[0];
+                if constexpr (kOneBarrier) {
+                    // the last site (127) of this group: its N bit, the W bit of
+                    // the row above, its decision, and whether it may flip
+                    const uint32_t may = act && lr + 1u < LR ? 8u : 0u;
+                    xC[xb][lg][lr] = (N[3] >> 31) | ((W1[3] >> 31) << 1) | ((~R0v[3] >> 31) << 2) | may;
+                }
                 __syncthreads();
-                const uint32_t eNext = has_next ? xE[lg + 1][lr] : 0u;
-                const uint32_t sNext = has_next && lr + 1u < kRegRows ? xS[lg + 1][lr + 1] : 0u;
+                const uint32_t eNext = has_next ? xE[xb][lg + 1][lr] : 0u;
+                const uint32_t sNext = has_next && lr + 1u < kRegRows ? xS[xb][lg + 1][lr + 1] : 0u;
+                // carry in from the previous group's last site, which flips with
+                // this group's first E bit of this row and S bit of the row above
+                uint32_t cin = 0u;
+                if constexpr (kOneBarrier) {
+                    if (lg > 0u) {
+                        const uint32_t P = xC[xb][lg - 1][lr];
+                        const uint32_t hz = S1[0] & P, vt = (P >> 1) & E[0], d = P >> 2;
+                        cin = ((hz & d) | (vt & ~d)) & (P >> 3) & 1u;
+                    }
+                }
                 uint32_t horiz[4], vert[4], live[4], any = 0u;
 #pragma unroll
                 for (int w = 0; w < 4; ++w) {
@@ -511,12 +534,18 @@ __global__ void __launch_bounds__(1024) domino_reg_kernel(const uint32_t *__rest
                     W[w] ^= Fd[w];
                     S[w] ^= (Fd[w] << 1) | (w > 0 ? Fd[w - 1] >> 31 : 0u);
                 }
-                xC[lg][lr] = F[3] >> 31;
-                __syncthreads();
-                if (lg > 0u) {
-                    E[0] ^= xC[lg - 1][lr];
-                    if (lr > 0u) S[0] ^= xC[lg - 1][lr - 1];
+                if constexpr (kOneBarrier) {
+                    E[0] ^= cin;
+                    S[0] ^= lane_prev(cin);   // the carry of the row below
+                } else {
+                    xC[0][lg][lr] = F[3] >> 31;
+                    __syncthreads();
+                    if (lg > 0u) {
+                        E[0] ^= xC[0][lg - 1][lr];
+                        if (lr > 0u) S[0] ^= xC[0][lg - 1][lr - 1];
+                    }
                 }
+                xb ^= 1u;
             }
         }
     }
