@@ -54,20 +54,26 @@ const ShaConst &consts()
 
 __host__ __device__ inline uint32_t rotr(uint32_t x, int s) { return (x >> s) | (x << (32 - s)); }
 
+// One compression: the message schedule kept as a rolling window of 16 words
+// (w[i & 15] holds W_i once round i needs it), fully unrolled, so that on the
+// device every word stays in a register.
 __host__ __device__ inline void compress(uint32_t st[8], const uint32_t m[16], const uint32_t *K)
 {
-    uint32_t w[64];
+    uint32_t w[16];
+#pragma unroll
     for (int i = 0; i < 16; ++i) w[i] = m[i];
-    for (int i = 16; i < 64; ++i) {
-        const uint32_t s0 = rotr(w[i - 15], 7) ^ rotr(w[i - 15], 18) ^ (w[i - 15] >> 3);
-        const uint32_t s1 = rotr(w[i - 2], 17) ^ rotr(w[i - 2], 19) ^ (w[i - 2] >> 10);
-        w[i] = w[i - 16] + s0 + w[i - 7] + s1;
-    }
     uint32_t a = st[0], b = st[1], c = st[2], d = st[3], e = st[4], f = st[5], g = st[6], h = st[7];
+#pragma unroll
     for (int i = 0; i < 64; ++i) {
+        if (i >= 16) {
+            const uint32_t x = w[(i - 15) & 15], y = w[(i - 2) & 15];
+            const uint32_t s0 = rotr(x, 7) ^ rotr(x, 18) ^ (x >> 3);
+            const uint32_t s1 = rotr(y, 17) ^ rotr(y, 19) ^ (y >> 10);
+            w[i & 15] += s0 + w[(i - 7) & 15] + s1;
+        }
         const uint32_t S1 = rotr(e, 6) ^ rotr(e, 11) ^ rotr(e, 25);
         const uint32_t ch = (e & f) ^ (~e & g);
-        const uint32_t t1 = h + S1 + ch + K[i] + w[i];
+        const uint32_t t1 = h + S1 + ch + K[i] + w[i & 15];
         const uint32_t S0 = rotr(a, 2) ^ rotr(a, 13) ^ rotr(a, 22);
         const uint32_t mj = (a & b) ^ (a & c) ^ (b & c);
         const uint32_t t2 = S0 + mj;
@@ -108,9 +114,18 @@ __host__ __device__ inline void sha256_any(const uint8_t *data, uint64_t len, co
     uint32_t st[8];
     for (int i = 0; i < 8; ++i) st[i] = H0[i];
     const uint64_t plen = ((len + 8) / 64 + 1) * 64;
+    // whole blocks of a 16-byte aligned message are read a word at a time
+    const bool aligned = ((uintptr_t)data & 15u) == 0u;
     for (uint64_t blk = 0; blk < plen; blk += 64) {
         uint32_t m[16];
-        if (blk + 64 <= len) {
+        if (blk + 64 <= len && aligned) {
+            const uint32_t *p = reinterpret_cast<const uint32_t *>(data + blk);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const uint32_t v = p[i];   // bytes of a little-endian word, read big-endian
+                m[i] = (v >> 24) | ((v >> 8) & 0xFF00u) | ((v << 8) & 0xFF0000u) | (v << 24);
+            }
+        } else if (blk + 64 <= len) {
             for (int i = 0; i < 16; ++i) {
                 const uint8_t *p = data + blk + 4 * i;
                 m[i] = ((uint32_t)p[0] << 24) | ((uint32_t)p[1] << 16) | ((uint32_t)p[2] << 8) | p[3];
