@@ -298,6 +298,27 @@ def test_streaming_kernel_parity(n):
     assert (s.export() == o.export()).all()
 
 
+@pytest.mark.parametrize("n,B,every", [(300, 1, 3), (300, 5, 20), (300, 16, 7), (257, 7, 40), (300, 64, 17)])
+def test_observables_of_register_tile_launches(n, B, every):
+    # samples taken between register-tile launches (bins in LDS when they
+    # fit, global ones otherwise; runs of a word for bins of 32 faces or more,
+    # single dominoes below): the same sums as the oracle and as the LDS tiles
+    tl = need_gpu()
+    say("register-tile observables n=%d B=%d every=%d" % (n, B, every))
+    s = gpu_sampler(tl, n, seed=29, obs_every=every, obs_bin=B)
+    l = gpu_sampler(tl, n, seed=29, obs_every=every, obs_bin=B, kernel=2)
+    o = oracle.DominoOracle(n, thr_uniform(), seed=29, obs_every=every, bin_=B)
+    for k in (every + 1, 2 * every):
+        s.sweep(k)
+        l.sweep(k)
+        o.sweep(k)
+    a, b = s.observables(), l.observables()
+    assert a["samples"] == b["samples"] == int(o.samples[0]) == (3 * every + 1) // every
+    assert (a["bin_sum"].reshape(-1) == o.bin_sum).all()
+    assert (b["bin_sum"] == a["bin_sum"]).all()
+    assert s.hash() == l.hash()
+
+
 def test_streaming_equals_tiled_order_2048():
     tl = need_gpu()
     say("domino order 2048 streaming vs tiled")
