@@ -763,7 +763,7 @@ __global__ void domino_export_kernel(const uint32_t *pl, size_t PS, uint32_t RS,
 // diamond); the run-counting path below assumes offset 0.
 constexpr uint32_t kLdsBins = 8192;
 
-__global__ void __launch_bounds__(256) domino_observe_kernel(const uint32_t *pl, size_t PS, uint32_t RS, int n,
+__global__ void __launch_bounds__(1024) domino_observe_kernel(const uint32_t *pl, size_t PS, uint32_t RS, int n,
                                                              uint32_t nw, uint32_t B, uint32_t bins_x,
                                                              uint32_t nbins, int ox, int oy,
                                                              unsigned long long *bins)
@@ -1036,7 +1036,11 @@ hipError_t domino_observe_box(const DominoDev &d, int ox, int oy, int h, uint32_
     const uint32_t bins_y = ((uint32_t)h + B - 1) / B;
     const uint32_t nbins = bins_x * bins_y;
     const uint32_t threads = nw * (uint32_t)d.n;
-    dim3 block(256), grid((threads + 255) / 256);
+    // counting runs of a word (bins of 32 faces or more, no offset): large
+    // work-groups, each clearing and flushing the LDS bins once; single
+    // dominoes: smaller ones, so that fewer lanes share a block's bins
+    const uint32_t bs = B >= 32u && ox == 0 && oy == 0 ? 1024u : 256u;
+    dim3 block(bs), grid((threads + bs - 1) / bs);
     const uint32_t shmem = nbins <= kLdsBins ? nbins * 4u : 0u;
     hipLaunchKernelGGL(domino_observe_kernel, grid, block, shmem, s, d.planes, d.PS, d.RS, d.n, nw, B, bins_x, nbins,
                        ox, oy, bins);
