@@ -394,9 +394,9 @@ tl_status tl_batch_destroy(tl_batch *b);
  * thread while the device-memory budget and the slot count allow; admitted
  * chains stay resident on the device and advance together in ticks: each tick
  * moves every resident job by tl_options.sweeps_per_launch sweeps (default 8;
- * twice that for jobs with one-bit decisions) in one launch per kernel family,
- * a work-group per tile of each job, so jobs that arrive while others run
- * share the GPU with them.  A finished
+ * twice that for jobs with one-bit decisions) in one launch for the height
+ * models and one for dominoes, a work-group per tile of each job, so jobs that
+ * arrive while others run share the GPU with them.  A finished
  * job's result is its canonical hash and whole-domain observable; its memory
  * is released at once.  A job gives the same result alone and in a mix.
  * Domains given by masks are served too (their host pre-pass runs in

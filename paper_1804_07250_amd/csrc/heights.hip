@@ -677,6 +677,27 @@ __global__ void __launch_bounds__(kHeightThreads) height_items_kernel(const Tile
     height_item<MODE, KIND, RANDOM, MASKED>(lds, j, it.tile);
 }
 
+// The same with every rule and table layout in one launch: work-group b takes
+// the kernel body of its job's rule and layout (the served ticks, where jobs of
+// several rules share one launch instead of a launch per rule on streams
+// joined by events).
+template <bool RANDOM, bool MASKED>
+__global__ void __launch_bounds__(kHeightThreads) height_items_mixed_kernel(const TileJob *__restrict__ jobs,
+                                                                            const TileItem *__restrict__ items)
+{
+    extern __shared__ uint32_t lds[];
+    const TileItem it = items[blockIdx.x];
+    const TileJob &j = jobs[it.job];
+    if (j.mode == kUniform)
+        height_item<kUniform, kKindClass, RANDOM, MASKED>(lds, j, it.tile);
+    else if (j.mode == kMetropolis)
+        j.kind == kKindSum ? height_item<kMetropolis, kKindSum, RANDOM, MASKED>(lds, j, it.tile)
+                           : height_item<kMetropolis, kKindClass, RANDOM, MASKED>(lds, j, it.tile);
+    else
+        j.kind == kKindSum ? height_item<kHeatBath, kKindSum, RANDOM, MASKED>(lds, j, it.tile)
+                           : height_item<kHeatBath, kKindClass, RANDOM, MASKED>(lds, j, it.tile);
+}
+
 __device__ __forceinline__ uint32_t hbit(const uint32_t *pl, size_t PS, uint32_t RS, uint32_t p, uint32_t y,
                                          uint32_t k)
 {
@@ -1062,6 +1083,17 @@ hipError_t height_items(const TileJob *jobs, const TileItem *items, uint32_t n_i
     if (threads == 0 || threads > kHeightThreads || lds > 160u * 1024u || mode > 2u || kind > 1u)
         return hipErrorInvalidConfiguration;
     auto k = TL_HEIGHT_PICK_ORDER_MASK(height_items_kernel, (int)mode, (int)kind, order, masked);
+    hipLaunchKernelGGL(k, dim3(n_items), dim3(threads), lds, s, jobs, items);
+    return hipGetLastError();
+}
+
+hipError_t height_items_mixed(const TileJob *jobs, const TileItem *items, uint32_t n_items, uint32_t threads,
+                              uint32_t lds, uint32_t order, uint32_t masked, hipStream_t s)
+{
+    if (n_items == 0) return hipSuccess;
+    if (threads == 0 || threads > kHeightThreads || lds > 160u * 1024u) return hipErrorInvalidConfiguration;
+    auto k = order ? (masked ? height_items_mixed_kernel<true, true> : height_items_mixed_kernel<true, false>)
+                   : (masked ? height_items_mixed_kernel<false, true> : height_items_mixed_kernel<false, false>);
     hipLaunchKernelGGL(k, dim3(n_items), dim3(threads), lds, s, jobs, items);
     return hipGetLastError();
 }

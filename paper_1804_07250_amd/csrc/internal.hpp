@@ -298,6 +298,9 @@ hipError_t domino_items(const TileJob *jobs, const TileItem *items, uint32_t n_i
 // Every job has colour order `order`, and site planes iff `masked`.
 hipError_t height_items(const TileJob *jobs, const TileItem *items, uint32_t n_items, uint32_t threads,
                         uint32_t lds, uint32_t mode, uint32_t kind, uint32_t order, uint32_t masked, hipStream_t s);
+// Height items of any rules and table kinds in one launch.
+hipError_t height_items_mixed(const TileJob *jobs, const TileItem *items, uint32_t n_items, uint32_t threads,
+                              uint32_t lds, uint32_t order, uint32_t masked, hipStream_t s);
 
 // ----------------------------------------------------------------- hashing
 // SHA-256 of each of `rows` rows of `row_bytes` bytes at `data` (device), into

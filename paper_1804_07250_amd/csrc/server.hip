@@ -405,14 +405,12 @@ bool tick(tl_server *sv)
     tl::TileItem *hi = reinterpret_cast<tl::TileItem *>(sv->h_buf[slot] + joff);
     tl::TileJob *dj = reinterpret_cast<tl::TileJob *>(sv->d_buf);
     tl::TileItem *di = reinterpret_cast<tl::TileItem *>(sv->d_buf + joff);
-    // one launch per kernel instantiation: height jobs grouped by masked
-    // domain, rule and table layout (one-bit jobs ride with the heat-bath ones
-    // of the 5-class layout), then the domino jobs
+    // one launch per kernel: the height jobs of every rule and table layout
+    // together (the work-groups take their job's kernel body), by whether the
+    // domain has site planes, then the domino jobs
     auto key = [&](size_t i) {
         if (!run[i]->model->height_family()) return 100u;
-        const uint32_t m = run[i]->model->masked() ? 10u : 0u;
-        if (jobs[i].mode == tl::kModeUniform) return m + (uint32_t)tl::kTableSum;
-        return m + (jobs[i].mode == tl::kModeMetropolis ? 3u : 0u) + jobs[i].kind;
+        return run[i]->model->masked() ? 10u : 0u;
     };
     std::vector<size_t> order(run.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = i;
@@ -449,9 +447,8 @@ bool tick(tl_server *sv)
             if (gr.key == 100u)
                 e = tl::domino_items(dj, di + gr.first, gr.count, gr.threads, gr.lds, sv->order, st);
             else
-                e = tl::height_items(dj, di + gr.first, gr.count, gr.threads, gr.lds,
-                                     gr.key % 10u >= 3u ? (uint32_t)tl::kModeMetropolis : (uint32_t)tl::kModeHeatBath,
-                                     gr.key % 10u % 3u, sv->order, gr.key >= 10u ? 1u : 0u, st);
+                e = tl::height_items_mixed(dj, di + gr.first, gr.count, gr.threads, gr.lds, sv->order,
+                                           gr.key >= 10u ? 1u : 0u, st);
         }
         if (split && e == hipSuccess) e = hipEventRecord(sv->ev_side, sv->side);
         if (split && e == hipSuccess) e = hipStreamWaitEvent(sv->stream, sv->ev_side, 0);
