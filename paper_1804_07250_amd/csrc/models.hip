@@ -15,6 +15,35 @@ namespace tl {
 
 namespace {
 
+// Copy a packed extremal state (host) into both state buffers.  With cache, a
+// model that owns its device memory keeps a device copy of it (made on the
+// first start from it), so that later starts (resets, the rounds of coupling
+// from the past) copy on the device.
+hipError_t load_state(uint32_t *planes, uint32_t *spare, const std::vector<uint32_t> &host, uint32_t **cache,
+                      hipStream_t s)
+{
+    const size_t bytes = host.size() * sizeof(uint32_t);
+    const void *src = host.data();
+    hipMemcpyKind kind = hipMemcpyHostToDevice;
+    if (cache) {
+        if (!*cache) {
+            uint32_t *d = nullptr;
+            hipError_t e = hipMalloc(&d, bytes);
+            if (e == hipSuccess) e = hipMemcpyAsync(d, src, bytes, hipMemcpyHostToDevice, s);
+            if (e != hipSuccess) {
+                if (d) (void)hipFree(d);
+                return e;
+            }
+            *cache = d;
+        }
+        src = *cache;
+        kind = hipMemcpyDeviceToDevice;
+    }
+    hipError_t e = hipMemcpyAsync(planes, src, bytes, kind, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(spare, src, bytes, kind, s);
+    return e;
+}
+
 // ------------------------------------------------------------------ domino
 // The Aztec diamond of order n, or a domain given by a mask, embedded in the
 // Aztec diamond of its region (faces outside the domain stay uncovered, so no
@@ -39,11 +68,13 @@ public:
         hipError_t e = hipMalloc(&d_.planes, words_ * sizeof(uint32_t));
         if (e == hipSuccess) e = hipMalloc(&d_.spare, words_ * sizeof(uint32_t));
         owned_ = true;
+        keep_ext_ = true;
         return e;
     }
     hipError_t allocate_into(uint32_t *state, uint32_t *spare) override
     {
         attach(state, spare);
+        keep_ext_ = true;   // a sampler's state: other tables stay library-allocated
         return hipSuccess;
     }
     void release() override
@@ -51,6 +82,12 @@ public:
         if (owned_ && d_.planes) (void)hipFree(d_.planes);
         if (owned_ && d_.spare) (void)hipFree(d_.spare);
         d_.planes = d_.spare = nullptr;
+        for (uint32_t *&p : ext_)
+            if (p) {
+                (void)hipFree(p);
+                p = nullptr;
+            }
+        keep_ext_ = false;
         timing.release();
     }
     size_t state_words() const override { return words_; }
@@ -60,6 +97,7 @@ public:
         d_.planes = state;
         d_.spare = spare;
         owned_ = false;
+        keep_ext_ = false;
     }
     bool tile_job(uint32_t t0, uint32_t S_max, const Thr &T, bool metro, uint64_t seed, bool, TileJob *j,
                   TilePlan *p) const override
@@ -86,11 +124,7 @@ public:
             if (!pack(init_max ? region_->tmax.data() : region_->tmin.data(), host, why))
                 return hipErrorInvalidValue;
         }
-        hipError_t e = hipMemcpyAsync(d_.planes, host.data(), host.size() * sizeof(uint32_t),
-                                      hipMemcpyHostToDevice, s);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(d_.spare, host.data(), host.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s);
-        return e;
+        return load_state(d_.planes, d_.spare, host, keep_ext_ ? &ext_[init_max ? 1 : 0] : nullptr, s);
     }
 
     hipError_t sweeps(uint32_t t0, uint32_t n, const Thr &T, bool metro, uint64_t seed, const tl_options &opt,
@@ -232,6 +266,8 @@ private:
     bool owned_ = false;
     std::shared_ptr<const Region> region_;
     std::vector<uint32_t> packed_max_, packed_min_;
+    bool keep_ext_ = false;                  // keep device copies of the extremal states
+    uint32_t *ext_[2] = {nullptr, nullptr};  // T_min, T_max on the device
 };
 
 // ------------------------------------------------------- lozenge / six-vertex
@@ -293,12 +329,14 @@ public:
         hipError_t e = hipMalloc(&d_.planes, words * sizeof(uint32_t));
         if (e == hipSuccess) e = hipMalloc(&d_.spare, words * sizeof(uint32_t));
         owned_ = true;
+        keep_ext_ = true;
         if (e != hipSuccess) return e;
         return allocate_region();
     }
     hipError_t allocate_into(uint32_t *state, uint32_t *spare) override
     {
         attach(state, spare);
+        keep_ext_ = true;   // a sampler's state: other tables stay library-allocated
         return allocate_region();
     }
     // Bytes of a masked domain's device tables, each 256-byte aligned: site
@@ -377,6 +415,12 @@ public:
         if (owned_ && d_.planes) (void)hipFree(d_.planes);
         if (owned_ && d_.spare) (void)hipFree(d_.spare);
         d_.planes = d_.spare = nullptr;
+        for (uint32_t *&p : ext_)
+            if (p) {
+                (void)hipFree(p);
+                p = nullptr;
+            }
+        keep_ext_ = false;
         if (region_owned_)
             for (void *p : {(void *)site_, (void *)anchor_, (void *)heights_, (void *)hmin_, (void *)cells_,
                             (void *)freep_})
@@ -417,6 +461,7 @@ public:
         d_.planes = state;
         d_.spare = spare;
         owned_ = false;
+        keep_ext_ = false;
     }
     // Multi-job tiles: a state whose (row, group) tasks fit one work-group (512)
     // and whose planes fit 64 KB of LDS is one tile (no halo, any sweep
@@ -472,11 +517,7 @@ public:
         if (host.empty())
             pack_points(init_max ? region_->hmax : region_->hmin, host,
                         [this](int32_t v) { return v != INT32_MIN && residual(v); });
-        hipError_t e = hipMemcpyAsync(d_.planes, host.data(), host.size() * sizeof(uint32_t),
-                                      hipMemcpyHostToDevice, s);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(d_.spare, host.data(), host.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s);
-        return e;
+        return load_state(d_.planes, d_.spare, host, keep_ext_ ? &ext_[init_max ? 1 : 0] : nullptr, s);
     }
 
     // Six-vertex kernels take one threshold per weight class (sA, sB) (and
@@ -751,6 +792,8 @@ private:
     tl_domain dom_;
     HeightDev d_;
     bool owned_ = false;
+    bool keep_ext_ = false;                  // keep device copies of the extremal states
+    uint32_t *ext_[2] = {nullptr, nullptr};  // minimal, maximal state on the device
     std::shared_ptr<const HeightRegion> region_;
     uint32_t *site_ = nullptr, *freep_ = nullptr;
     bool region_owned_ = true;   // false: the tables live in caller-owned memory (attach_region)
