@@ -704,40 +704,95 @@ __device__ __forceinline__ uint32_t hbit(const uint32_t *pl, size_t PS, uint32_t
     return (pl[p * PS + (size_t)y * RS + 4 + (k >> 5)] >> (k & 31u)) & 1u;
 }
 
-// Height of every site of row y, one thread per row, and the per-cell
-// observable (lozenge H - H_min per vertex; six-vertex: type-c vertices, done
-// separately below).
-__global__ void height_export_kernel(const uint32_t *pl, size_t PS, uint32_t RS, uint32_t rows, Geo geo,
-                                     int32_t *out)
+// Bits k of a row word whose bit k is the point X0 + s k + p (the s planes
+// of a row interleave their points) with u <= X0 + s k + p <= v.
+__device__ __forceinline__ uint32_t word_mask(int X0, int p, int u, int v, int s)
 {
-    const uint32_t y = blockIdx.x * blockDim.x + threadIdx.x;
-    if (y >= rows) return;
-    if (geo.model == TL_LOZENGE) {
-        const int W = geo.a + geo.c + 1, Y = (int)y;
-        const int xs = loz_xs(geo, Y), xe = loz_xe(geo, Y);
-        int H = loz_hmin(geo, xs, Y);
-        uint32_t prev = hbit(pl, PS, RS, (uint32_t)xs % 3u, y, (uint32_t)xs / 3u);
-        for (int X = 0; X < W; ++X) {
-            int32_t v = INT32_MIN;
-            if (X >= xs && X <= xe) {
-                if (X > xs) {
-                    const uint32_t bx = hbit(pl, PS, RS, (uint32_t)X % 3u, y, (uint32_t)X / 3u);
-                    H -= (int)(bx ^ prev);
-                    prev = bx;
-                }
-                v = H;
+    const int a = u - X0 - p, b = v - X0 - p;
+    const int klo = a <= 0 ? 0 : (a + s - 1) / s, khi = b < 0 ? -1 : imin(31, b / s);
+    if (klo > khi) return 0u;
+    const uint32_t upto = khi >= 31 ? ~0u : (2u << khi) - 1u;
+    return upto & ~((1u << klo) - 1u);
+}
+
+// Sum of the indices k of the set bits of x.
+__device__ __forceinline__ uint32_t bit_index_sum(uint32_t x)
+{
+    return (uint32_t)__popc(x & 0xAAAAAAAAu) + 2u * (uint32_t)__popc(x & 0xCCCCCCCCu) +
+           4u * (uint32_t)__popc(x & 0xF0F0F0F0u) + 8u * (uint32_t)__popc(x & 0xFF00FF00u) +
+           16u * (uint32_t)__popc(x & 0xFFFF0000u);
+}
+
+// Heights of every point of a row, one wavefront per row.  A chunk is word m
+// of each plane: lozenge vertices X in [96m, 96m + 96) (bit k of plane p is
+// X = 96m + 3k + p), six-vertex faces I in [64m, 64m + 64) (I = 64m + 2k + p).
+// Along a lozenge row H falls by one exactly where the residual bit differs
+// from the previous vertex's.  Along a six-vertex row h moves by one at every
+// face, and, the bit being bit 1 of h and h having the parity of I + J, it
+// goes up exactly where the bit, the previous face's bit and that parity XOR
+// to 1.  So each chunk's step words are XORs of its planes: phase one keeps
+// them in LDS with the count of steps before the chunk (a wavefront prefix
+// sum); phase two writes the row, consecutive lanes on consecutive points,
+// each height the row's first one moved by popcounts of the steps up to it.
+// LDS: nch words of counts, then 3 nch (lozenge) or 2 nch step words.
+__global__ void __launch_bounds__(64) height_export_kernel(const uint32_t *pl, size_t PS, uint32_t RS, Geo geo,
+                                                           uint32_t nch, int32_t *out)
+{
+    extern __shared__ uint32_t xl[];
+    const int y = (int)blockIdx.x, lane = (int)threadIdx.x;
+    const uint32_t *row = pl + (size_t)y * RS + 4;
+    uint32_t *pre = xl, *steps = xl + nch;
+    const bool loz = geo.model == TL_LOZENGE;
+    const int P = loz ? 3 : 2, span = loz ? 96 : 64;
+    // the row's points with a step, and (lozenge) its vertices
+    const int xs = loz ? loz_xs(geo, y) : 0, xe = loz ? loz_xe(geo, y) : geo.N;
+    int carry = 0;
+    for (int m0 = 0; m0 < (int)nch; m0 += 64) {
+        const int m = m0 + lane, X0 = span * m;
+        const int lo = imax(xs, X0), hi = imin(xe, X0 + span - 1), L = imax(lo, xs + 1);
+        uint32_t S[3] = {0u, 0u, 0u};
+        int cnt = 0;
+        if (m < (int)nch && lo <= hi) {
+            if (loz) {
+                const uint32_t W0 = row[m], W1 = row[PS + m], W2 = row[2 * PS + m];
+                const uint32_t cin = X0 > xs ? row[2 * PS + m - 1] >> 31 : 0u;   // the vertex before X0
+                S[0] = W0 ^ ((W2 << 1) | cin);
+                S[1] = W1 ^ W0;
+                S[2] = W2 ^ W1;
+            } else {
+                const uint32_t P0 = row[m], P1 = row[PS + m];
+                const uint32_t cin = m > 0 ? row[PS + m - 1] >> 31 : 0u;   // the face before I = 64m
+                const uint32_t par0 = (y & 1) ? ~0u : 0u;                  // parity of I + J, I even
+                S[0] = P0 ^ ((P1 << 1) | cin) ^ par0;
+                S[1] = P1 ^ P0 ^ ~par0;
             }
-            out[(size_t)y * W + X] = v;
+            for (int p = 0; p < P; ++p) cnt += __popc(S[p] & word_mask(X0, p, L, hi, P));
         }
-    } else {
-        const int N = geo.N;
-        int h = (int)y;    // h(0, J) = J
-        out[(size_t)y * (N + 1)] = h;
-        for (int I = 1; I <= N; ++I) {
-            const uint32_t bx = hbit(pl, PS, RS, (uint32_t)I & 1u, y, (uint32_t)I >> 1);
-            h = ((uint32_t)(((h + 1) >> 1) & 1) == bx) ? h + 1 : h - 1;
-            out[(size_t)y * (N + 1) + I] = h;
+        int incl = cnt;   // inclusive scan over the lanes
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int v = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += v;
         }
+        if (m < (int)nch) {
+            pre[m] = (uint32_t)(carry + incl - cnt);
+            for (int p = 0; p < P; ++p) steps[P * m + p] = S[p];
+        }
+        carry += __shfl(incl, 63, 64);
+    }
+    __syncthreads();
+    const int W = loz ? geo.a + geo.c + 1 : geo.N + 1;
+    const int h0 = loz ? loz_hmin(geo, xs, y) : y;   // lozenge H at xs, six-vertex h(0, J) = J
+    int32_t *o = out + (size_t)y * W;
+    for (int X = lane; X < W; X += 64) {
+        int32_t v = INT32_MIN;
+        if (X >= xs && X <= xe) {
+            const int m = X / span, X0 = span * m, L = imax(imax(xs, X0), xs + 1);
+            int c = (int)pre[m];
+            for (int p = 0; p < P; ++p) c += __popc(steps[P * m + p] & word_mask(X0, p, L, X, P));
+            v = loz ? h0 - c : h0 + 2 * c - X;
+        }
+        o[X] = v;
     }
 }
 
@@ -862,10 +917,15 @@ __global__ void sixv_region_count_kernel(const int32_t *H, const uint8_t *cells,
 }
 
 // Lozenge observable: H - H_min per vertex, summed into bins of B x B cells.
-// One wavefront per row Y: H falls by one across every change of the residual
-// bit along the row, so each lane counts the changes in its chunk of X, a
-// wavefront prefix sum gives every chunk its starting height, and the lanes
-// accumulate their chunk into per-row bins in LDS (flushed once per bin).
+// One wavefront per row Y, a lane per chunk X in [96m, 96m + 96): word m of
+// the three planes holds the residual bits of those vertices (bit k of plane
+// p is X = 96m + 3k + p).  H falls by one at every X > xs whose bit differs
+// from the bit of X - 1, so XORs of the planes (plane 0 against plane 2
+// shifted by one site) give the chunk's drops; a wavefront prefix sum of
+// their counts gives every chunk its starting height.  Within a bin the sum
+// of H over X in [u, v] is n H(u - 1) minus, for every drop d, the v - d + 1
+// vertices from d on, and the sum of H_min = max(c - X, max(0, c - Y)) is an
+// arithmetic series: popcounts and closed forms, no loop over vertices.
 __global__ void __launch_bounds__(64) loz_observe_kernel(const uint32_t *pl, size_t PS, uint32_t RS, Geo geo,
                                                          uint32_t B, uint32_t bins_x, unsigned long long *bins)
 {
@@ -874,36 +934,65 @@ __global__ void __launch_bounds__(64) loz_observe_kernel(const uint32_t *pl, siz
     for (uint32_t i = (uint32_t)lane; i < bins_x; i += 64u) rowbin[i] = 0ull;
     __syncthreads();
     const int xs = loz_xs(geo, Y), xe = loz_xe(geo, Y);
-    const int C = (xe - xs + 1 + 63) / 64;
-    const int x0 = xs + lane * C, x1 = x0 + C - 1 < xe ? x0 + C - 1 : xe;
-    auto bit = [&](int X) { return hbit(pl, PS, RS, (uint32_t)X % 3u, (uint32_t)Y, (uint32_t)X / 3u); };
-    int drops = 0;   // changes at X in [x0, x1], X > xs
-    for (int X = x0 > xs ? x0 : xs + 1; X <= x1; ++X) drops += (int)(bit(X) ^ bit(X - 1));
-    int before = drops;   // inclusive scan over the lanes
+    const int h0 = imax(0, geo.c - Y), tc = geo.c - h0;   // H_min(X) = c - X for X < tc, else h0
+    const uint32_t *row = pl + (size_t)Y * RS + 4;
+    int carry = 0;   // drops in the chunks of earlier passes
+    for (int m0 = xs / 96; m0 <= xe / 96; m0 += 64) {
+        const int m = m0 + lane, X0 = 96 * m;
+        const int lo = imax(xs, X0), hi = imin(xe, X0 + 95), L = imax(lo, xs + 1);
+        uint32_t D[3] = {0u, 0u, 0u};
+        int cnt = 0;
+        if (lo <= hi) {
+            const uint32_t W0 = row[m], W1 = row[PS + m], W2 = row[2 * PS + m];
+            // the bit of X0 - 1 (plane 2, last bit of word m - 1), needed when X0 > xs
+            const uint32_t cin = X0 > xs ? row[2 * PS + m - 1] >> 31 : 0u;
+            D[0] = W0 ^ ((W2 << 1) | cin);
+            D[1] = W1 ^ W0;
+            D[2] = W2 ^ W1;
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int v = __shfl_up(before, off, 64);
-        if (lane >= off) before += v;
-    }
-    before -= drops;
-    int H = loz_hmin(geo, xs, Y) - before;
-    unsigned long long acc = 0ull;
-    int cur = -1;
-    for (int X = x0; X <= x1; ++X) {
-        if (X > xs) H -= (int)(bit(X) ^ bit(X - 1));
-        const int b = X / (int)B;
-        if (b != cur) {
-            if (cur >= 0 && acc) atomicAdd(&rowbin[cur], acc);
-            cur = b;
-            acc = 0ull;
+            for (int p = 0; p < 3; ++p) cnt += __popc(D[p] & word_mask(X0, p, L, hi, 3));
         }
-        acc += (unsigned long long)(H - loz_hmin(geo, X, Y));
+        int incl = cnt;   // inclusive scan over the lanes
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int v = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += v;
+        }
+        const int total = __shfl(incl, 63, 64);
+        if (lo <= hi) {
+            int H = loz_hmin(geo, xs, Y) - carry - (incl - cnt);   // H before this chunk's drops
+            for (int u = lo; u <= hi;) {
+                const int j = u / (int)B, v = imin(hi, (j + 1) * (int)B - 1);
+                const int du = imax(u, L);
+                int c = 0;
+                long long sd = 0;   // drops in [du, v] and the sum of their X
+#pragma unroll
+                for (int p = 0; p < 3; ++p) {
+                    const uint32_t x = D[p] & word_mask(X0, p, du, v, 3);
+                    const int cp = __popc(x);
+                    c += cp;
+                    sd += (long long)cp * (X0 + p) + 3ll * (long long)bit_index_sum(x);
+                }
+                const long long n = v - u + 1;
+                const long long sumH = n * H - ((long long)c * (v + 1) - sd);
+                long long sumMin = 0;
+                const int aE = imin(v, tc - 1), bS = imax(u, tc);
+                if (aE >= u) {
+                    const long long na = aE - u + 1;
+                    sumMin += na * geo.c - (long long)(u + aE) * na / 2;
+                }
+                if (bS <= v) sumMin += (long long)(v - bS + 1) * h0;
+                if (sumH != sumMin) atomicAdd(&rowbin[j], (unsigned long long)(sumH - sumMin));
+                H -= c;
+                u = v + 1;
+            }
+        }
+        carry += total;
     }
-    if (cur >= 0 && acc) atomicAdd(&rowbin[cur], acc);
     __syncthreads();
-    const size_t row = (size_t)(Y / (int)B) * bins_x;
+    const size_t row_bins = (size_t)(Y / (int)B) * bins_x;
     for (uint32_t i = (uint32_t)lane; i < bins_x; i += 64u)
-        if (rowbin[i]) atomicAdd(&bins[row + i], rowbin[i]);
+        if (rowbin[i]) atomicAdd(&bins[row_bins + i], rowbin[i]);
 }
 
 Geo geo_of(const HeightDev &d)
@@ -946,14 +1035,14 @@ HeightTile height_auto_tile(const HeightDev &d, bool uniform, bool metropolis)
     // Rows up to 8 groups wide are one tile wide (no column halo).  Bit-serial
     // decisions favour short tiles and few sweeps per launch, one-bit
     // decisions longer launches; measured on MI355X for the 1024 hexagon
-    // (q = 1999/2000: 6 rows, 3 sweeps) and the N = 1024 squares (heat-bath
+    // (q = 1999/2000: 5 rows, 3 sweeps) and the N = 1024 squares (heat-bath
     // 4 rows and 6 sweeps, lazy Metropolis 8 and 8).
     t.TG = d.ng <= 8 ? d.ng : 4;
     if (uniform) {
         t.TR = 8;
         t.S = 16;
     } else if (d.model == TL_LOZENGE) {
-        t.TR = 6;
+        t.TR = 5;
         t.S = 3;
     } else {
         t.TR = metropolis ? 8 : 4;
@@ -1100,8 +1189,12 @@ hipError_t height_items_mixed(const TileJob *jobs, const TileItem *items, uint32
 
 hipError_t height_export(const HeightDev &d, int32_t *dev, hipStream_t s)
 {
-    dim3 block(64), grid((d.rows + 63) / 64);
-    hipLaunchKernelGGL(height_export_kernel, grid, block, 0, s, d.planes, d.PS, d.RS, d.rows, geo_of(d), dev);
+    // chunks of a row: 96 lozenge vertices or 64 six-vertex faces each
+    const uint32_t nch = d.model == TL_LOZENGE ? (uint32_t)(d.a + d.c) / 96u + 1u : (uint32_t)d.N / 64u + 1u;
+    const uint32_t shmem = 4u * nch * (d.model == TL_LOZENGE ? 4u : 3u);
+    if (shmem > 64u * 1024u) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(height_export_kernel, dim3(d.rows), dim3(64), shmem, s, d.planes, d.PS, d.RS, geo_of(d), nch,
+                       dev);
     return hipGetLastError();
 }
 

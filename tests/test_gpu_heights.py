@@ -251,6 +251,23 @@ def test_lozenge_volume_bins(B):
     assert obs["scalar_now"] == o.observe(1)[0]
 
 
+@pytest.mark.parametrize("abc,B", [((150, 40, 170), 1), ((150, 40, 170), 7), ((150, 40, 170), 64),
+                                   ((300, 64, 80), 100), ((6200, 3, 4), 64)])
+def test_lozenge_volume_bins_wide_rows(abc, B):
+    # rows of several 96-vertex words (the observable kernel's chunks), and a
+    # row of more than 64 of them (several passes of one wavefront)
+    tl = need_gpu()
+    say("lozenge volume bins %s B=%d" % (abc, B))
+    s = loz_sampler(tl, *abc, seed=31, q=Fraction(3, 2), obs_every=4, obs_bin=B)
+    o = loz_oracle(*abc, seed=31, q=Fraction(3, 2), obs_every=4, bin_=B)
+    s.sweep(12)
+    o.sweep(12)
+    obs = s.observables()
+    assert obs["samples"] == int(o.samples[0]) == 3
+    assert (obs["bin_sum"].reshape(-1) == o.bin_sum).all()
+    assert obs["scalar_now"] == o.observe(1)[0]
+
+
 @pytest.mark.parametrize("N,B", [(1, 1), (2, 1), (33, 5), (130, 32), (130, 64), (77, 200), (64, 3)])
 def test_sixvertex_c_vertex_bins(N, B):
     tl = need_gpu()
