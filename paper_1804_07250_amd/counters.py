@@ -11,10 +11,12 @@ measured on; bench.py ignores it once they change.
     python -m paper_1804_07250_amd.counters summary DIR
     python -m paper_1804_07250_amd.counters record NAME --kernel 'domino_tiled_kernel<2, false>' \\
         --fetch DIR --write DIR --copy-fetch DIR --copy-write DIR --copy-mib 256 \\
-        [--lds DIR] [--valu DIR] [--sources domino.hip device_common.hpp] [--largest N]
+        [--lds DIR] [--valu DIR] [--trace DIR] [--sources domino.hip device_common.hpp] [--largest N]
 
 Each DIR is the output folder of one rocprofv3 run (one counter block per run:
-FETCH_SIZE and WRITE_SIZE cannot share a pass).  The copy runs profile
+FETCH_SIZE and WRITE_SIZE cannot share a pass); --trace is a
+``--kernel-trace`` run of the same workload, whose mean dispatch duration of
+the kernel the record keeps (the launch time its figures are stated at).  The copy runs profile
 ``bench.py --copy-calibration MIB``, whose copies the runtime issues as
 ``__amd_rocclr_copyBuffer``.
 """
@@ -87,6 +89,22 @@ def mean_of(values, kernel, counter, largest=None):
     return statistics.fmean(v), len(v)
 
 
+def trace_durations(folder):
+    """{kernel label: [dispatch duration in us]} over every kernel_trace.csv
+    under folder."""
+    files = sorted(glob.glob(os.path.join(folder, "**", "*kernel_trace.csv"), recursive=True))
+    if not files:
+        raise FileNotFoundError("no kernel_trace.csv under %s" % folder)
+    out = defaultdict(list)
+    for f in files:
+        with open(f, newline="") as fh:
+            for r in csv.DictReader(fh):
+                start = int(_col(r, "Start_Timestamp", "START_TIMESTAMP"))
+                end = int(_col(r, "End_Timestamp", "END_TIMESTAMP"))
+                out[kernel_label(_col(r, "Kernel_Name", "KERNEL_NAME"))].append((end - start) / 1000.0)
+    return out
+
+
 def sources_sha256(sources):
     h = hashlib.sha256()
     for s in sources:
@@ -96,11 +114,14 @@ def sources_sha256(sources):
 
 
 def make_record(kernel, fetch, write, copy_fetch, copy_write, copy_mib, sources, lds=None, valu=None, base=None,
-                largest=None):
+                largest=None, trace=None):
     """The record as a dict.  fetch / write / copy_* / lds / valu are the
-    counter_values() of the corresponding runs; base supplies the fields kept
-    from an existing record (workload, commands)."""
+    counter_values() of the corresponding runs, trace the trace_durations()
+    of a kernel-trace run; base supplies the fields kept from an existing
+    record (workload, commands)."""
     rec = dict(base or {})
+    rec.pop("trace_avg_launch_us", None)   # a trace time belongs to the runs it came with
+    rec.pop("trace_launches", None)
     rec["kernel"] = kernel
     rec["sources"] = list(sources)
     rec["sources_sha256"] = sources_sha256(sources)
@@ -128,6 +149,16 @@ def make_record(kernel, fetch, write, copy_fetch, copy_write, copy_mib, sources,
         rec["valu_counters_raw"] = raw
         rec["valu_active_per_launch"] = raw["SQ_ACTIVE_INST_VALU"]
         rec["valu_lane_util"] = round(raw["SQ_THREAD_CYCLES_VALU"] / (64.0 * raw["SQ_ACTIVE_INST_VALU"]), 4)
+    if trace is not None:
+        d = trace.get(kernel)
+        if not d:
+            raise KeyError("no dispatches of kernel %s in the kernel trace" % kernel)
+        if largest:
+            if len(d) < largest:
+                raise KeyError("%d traced dispatches of %s, %d asked for" % (len(d), kernel, largest))
+            d = sorted(d, reverse=True)[:largest]
+        rec["trace_avg_launch_us"] = round(statistics.fmean(d), 3)
+        rec["trace_launches"] = len(d)
     return rec
 
 
@@ -144,6 +175,7 @@ def main(argv=None):
     r.add_argument("--copy-mib", type=float, required=True)
     r.add_argument("--lds")
     r.add_argument("--valu")
+    r.add_argument("--trace", help="rocprofv3 --kernel-trace folder of the same workload")
     r.add_argument("--sources", nargs="+")
     r.add_argument("--largest", type=int, help="use only the N dispatches with the largest value of each counter")
     r.add_argument("--out", help="record path (default profiles/<name>_traffic.json, whose workload, commands\n"
@@ -168,7 +200,7 @@ def main(argv=None):
     rec = make_record(a.kernel, counter_values(a.fetch), counter_values(a.write), counter_values(a.copy_fetch),
                       counter_values(a.copy_write), a.copy_mib, sources,
                       counter_values(a.lds) if a.lds else None, counter_values(a.valu) if a.valu else None, base,
-                      a.largest)
+                      a.largest, trace_durations(a.trace) if a.trace else None)
     with open(out, "w") as fh:
         json.dump(rec, fh, indent=1)
     print("%s: %d bytes per launch%s" % (out, rec["bytes_per_launch"],

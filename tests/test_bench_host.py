@@ -127,6 +127,17 @@ def test_committed_records_give_no_fraction_above_one(fname):
     assert rec["bytes_per_launch"] / t / 1e9 <= bench.HBM_PEAK_GBS
 
 
+def write_trace(folder, rows):
+    """A rocprofv3-style kernel_trace.csv: rows of (kernel, start ns, end ns)."""
+    d = folder / "host" / "123"
+    d.mkdir(parents=True)
+    with open(d / "123_kernel_trace.csv", "w") as fh:
+        fh.write("Kind,Agent_Id,Queue_Id,Kernel_Id,Kernel_Name,Correlation_Id,Start_Timestamp,End_Timestamp\n")
+        for i, (k, s, e) in enumerate(rows):
+            fh.write('KERNEL_DISPATCH,1,1,%d,"%s",%d,%d,%d\n' % (i, k, i, s, e))
+    return str(folder)
+
+
 def write_counters(folder, rows):
     """A rocprofv3-style counter_collection.csv: rows of (kernel, counter, value)."""
     d = folder / "host" / "123"
@@ -155,13 +166,15 @@ def test_counter_tool_builds_the_record(tmp_path):
         ("SQ_INSTS_LDS", 9.0))])
     valu = write_counters(tmp_path / "v", [(k, "SQ_INSTS_VALU", 10.0), (k, "SQ_ACTIVE_INST_VALU", 10.0),
                                            (k, "SQ_THREAD_CYCLES_VALU", 480.0)])
+    trace = write_trace(tmp_path / "t", [(k, 1000, 26000), (k, 30000, 54000), ("other_kernel", 0, 5)])
     out = tmp_path / "rec.json"
     rc = counters.main(["record", "x_aztec9", "--kernel", "domino_tiled_kernel<2, false>", "--fetch", fetch,
                         "--write", write, "--copy-fetch", cf, "--copy-write", cw, "--copy-mib", "256",
-                        "--lds", lds, "--valu", valu, "--sources", "domino.hip", "device_common.hpp",
-                        "--out", str(out)])
+                        "--lds", lds, "--valu", valu, "--trace", trace, "--sources", "domino.hip",
+                        "device_common.hpp", "--out", str(out)])
     assert rc == 0
     rec = json.load(open(out))
+    assert rec["trace_avg_launch_us"] == 24.5 and rec["trace_launches"] == 2
     assert rec["launches_profiled"] == 2 and rec["fetch_scale"] == 2.0 and rec["write_scale"] == 1.0
     assert rec["bytes_per_launch"] == (1001 * 2 + 500) * 1024
     assert rec["lds_bytes_per_launch"] == 124 * 64
