@@ -268,6 +268,25 @@ def test_lozenge_volume_bins_wide_rows(abc, B):
     assert obs["scalar_now"] == o.observe(1)[0]
 
 
+@pytest.mark.parametrize("model", ["lozenge", "sixvertex"])
+def test_height_exports_of_wide_rows(model):
+    # rows of more than 64 chunks (96 lozenge vertices or 64 six-vertex faces
+    # each): the export kernel's wavefront takes them in several passes
+    tl = need_gpu()
+    say("wide-row export %s" % model)
+    if model == "lozenge":
+        s = loz_sampler(tl, 6200, 3, 4, seed=37, q=Fraction(3, 2))
+        o = loz_oracle(6200, 3, 4, seed=37, q=Fraction(3, 2))
+        sweeps = 6
+    else:
+        s = sixv_sampler(tl, 4160, seed=37, w2=(1, 1, 2))
+        o = sixv_oracle(4160, seed=37, w2=(1, 1, 2))
+        sweeps = 2
+    s.sweep(sweeps)
+    o.sweep(sweeps)
+    assert (s.export() == o.export()).all()
+
+
 @pytest.mark.parametrize("N,B", [(1, 1), (2, 1), (33, 5), (130, 32), (130, 64), (77, 200), (64, 3)])
 def test_sixvertex_c_vertex_bins(N, B):
     tl = need_gpu()
