@@ -145,6 +145,19 @@ enum { kHeatBath = 0, kMetropolis = 1, kUniform = 2 };
 static_assert(kHeatBath == kModeHeatBath && kMetropolis == kModeMetropolis && kUniform == kModeUniform,
               "kernel modes and TileJob modes agree");
 
+// Are all thresholds of colour c 2^31 (ratio 1, as in the first colour of
+// two-periodic weights)?  Then the top bit of each site's uniform decides it
+// alone, and plane 0 settles every site of the group.
+template <int MODE>
+__device__ __forceinline__ bool one_bit_colour(const Thr &Tall, uint32_t c)
+{
+    constexpr uint32_t NC = MODE == kMetropolis ? 4u : 2u;
+    bool all = true;
+#pragma unroll
+    for (uint32_t i = 0; i < NC; ++i) all = all && Tall.v[NC * c + i] == 0x80000000u;
+    return all;
+}
+
 template <int MODE>
 __device__ __forceinline__ void decide_group(uint32_t key0, uint32_t key1, uint32_t g, uint32_t r, uint32_t t,
                                              uint32_t c, const Thr &Tall, const uint32_t (&R0)[4],
@@ -153,6 +166,12 @@ __device__ __forceinline__ void decide_group(uint32_t key0, uint32_t key1, uint3
     if (MODE == kUniform) {
 #pragma unroll
         for (int w = 0; w < 4; ++w) D[w] = ~R0[w];
+    } else if (one_bit_colour<MODE>(Tall, c)) {
+        // the draw of plane 0, as the bit-serial comparison makes it first
+        uint32_t R[4];
+        philox4x32_10(g, r, t, c, key0, key1, R);
+#pragma unroll
+        for (int w = 0; w < 4; ++w) D[w] = ~R[w];
     } else {
         constexpr int NC = DomCtx<MODE == kMetropolis>::NC;
         uint32_t T[NC], cm[NC][4];
@@ -604,19 +623,6 @@ __global__ void __launch_bounds__(1024) domino_batch_kernel(BatchChain *chains, 
     __shared__ uint32_t s_first[kBundleMax + 1];   // first task of each member (prefix of n * ng)
     __shared__ uint32_t s_off[kBundleMax];         // LDS word offset of each member
     const uint32_t tid = threadIdx.x, nt = blockDim.x;
-    // Under the fixed order, a colour whose thresholds are all 2^31 (ratio 1,
-    // as in the first colour of two-periodic weights) is decided by the top
-    // bit of each site's uniform alone: the one-bit update draws the same
-    // plane and makes the same flips without the bit-serial loop.
-    bool one_bit[2] = {false, false};
-    if constexpr (MODE != kUniform && !RANDOM) {
-        constexpr uint32_t NC = MODE == kMetropolis ? 4u : 2u;
-        for (uint32_t c = 0; c < 2; ++c) {
-            bool all = true;
-            for (uint32_t j = 0; j < NC; ++j) all = all && Tall.v[NC * c + j] == 0x80000000u;
-            one_bit[c] = all;
-        }
-    }
     for (;;) {
         if (tid == 0) s_next = atomicAdd(counter, 1u);
         __syncthreads();
@@ -665,21 +671,12 @@ __global__ void __launch_bounds__(1024) domino_batch_kernel(BatchChain *chains, 
                     for (uint32_t task = tid; task < tasks; task += nt) {
                         const uint32_t r = task / ng, gg = task % ng;
                         uint32_t *pN = lds + r * LRS + 4 * gg;
-                        if (c == omega) {
-                            if (one_bit[i])
-                                owner_group<kUniform>(pN, pN + LPS, pN + 2 * LPS, pN + 3 * LPS, r, gg, c, t, Tall,
-                                                      ch.key0, ch.key1);
-                            else
-                                owner_group<MODE>(pN, pN + LPS, pN + 2 * LPS, pN + 3 * LPS, r, gg, c, t, Tall,
-                                                  ch.key0, ch.key1);
-                        } else if (r + 1 < n) {
-                            if (one_bit[i])
-                                other_group<kUniform>(pN, pN + 2 * LPS, pN + LPS + LRS, pN + 3 * LPS + LRS, r, gg, c,
-                                                      t, Tall, ch.key0, ch.key1, gg + 1 < ng);
-                            else
-                                other_group<MODE>(pN, pN + 2 * LPS, pN + LPS + LRS, pN + 3 * LPS + LRS, r, gg, c, t,
-                                                  Tall, ch.key0, ch.key1, gg + 1 < ng);
-                        }
+                        if (c == omega)
+                            owner_group<MODE>(pN, pN + LPS, pN + 2 * LPS, pN + 3 * LPS, r, gg, c, t, Tall, ch.key0,
+                                              ch.key1);
+                        else if (r + 1 < n)
+                            other_group<MODE>(pN, pN + 2 * LPS, pN + LPS + LRS, pN + 3 * LPS + LRS, r, gg, c, t, Tall,
+                                              ch.key0, ch.key1, gg + 1 < ng);
                     }
                     __syncthreads();
                 }
@@ -701,21 +698,12 @@ __global__ void __launch_bounds__(1024) domino_batch_kernel(BatchChain *chains, 
                         c = step_colour(t, 2u, ch.key0, ch.key1);
                     }
                     if (has) {
-                        if (c == omega) {
-                            if (one_bit[i])
-                                owner_group<kUniform>(pN, pN + LPS, pN + 2 * LPS, pN + 3 * LPS, r, gg, c, t, Tall,
-                                                      ch.key0, ch.key1);
-                            else
-                                owner_group<MODE>(pN, pN + LPS, pN + 2 * LPS, pN + 3 * LPS, r, gg, c, t, Tall,
-                                                  ch.key0, ch.key1);
-                        } else if (r + 1 < n) {
-                            if (one_bit[i])
-                                other_group<kUniform>(pN, pN + 2 * LPS, pN + LPS + LRS, pN + 3 * LPS + LRS, r, gg, c,
-                                                      t, Tall, ch.key0, ch.key1, gg + 1 < ng);
-                            else
-                                other_group<MODE>(pN, pN + 2 * LPS, pN + LPS + LRS, pN + 3 * LPS + LRS, r, gg, c, t,
-                                                  Tall, ch.key0, ch.key1, gg + 1 < ng);
-                        }
+                        if (c == omega)
+                            owner_group<MODE>(pN, pN + LPS, pN + 2 * LPS, pN + 3 * LPS, r, gg, c, t, Tall, ch.key0,
+                                              ch.key1);
+                        else if (r + 1 < n)
+                            other_group<MODE>(pN, pN + 2 * LPS, pN + LPS + LRS, pN + 3 * LPS + LRS, r, gg, c, t, Tall,
+                                              ch.key0, ch.key1, gg + 1 < ng);
                     }
                     __syncthreads();
                 }
