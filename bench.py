@@ -238,8 +238,13 @@ def run_cftp(tl, args):
               (args.cftp_n - 1) ** 2),
              ("aztec", tl.domain(tl.TL_DOMINO, n=args.cftp_aztec), tl.weights(tl.TL_W_UNIFORM),
               2 * args.cftp_aztec ** 2 - 2 * args.cftp_aztec + 1)]
+    # the oracle's stored samples of these cases (R and canonical hash)
+    g = golden("cftp")
+    stored = {(c["model"], c["n"], c["seed"]): c for c in g["cases"]} if g else {}
+    checked = matched = 0
     for name, dom, w, sites in cases:
         secs, logs, total = [], [], 0
+        model = "sixvertex" if name == "sixv" else "domino"
         for seed in range(args.cftp_samples):
             s = tl.Sampler(dom, w, seed)
             s.sync()
@@ -248,9 +253,14 @@ def run_cftp(tl, args):
             secs.append(time.perf_counter() - t0)
             logs.append(info["log2_sweeps"])
             total += info["total_sweeps"]
+            c = stored.get((model, dom.n, seed))
+            if c:
+                checked += 1
+                matched += int(info["log2_sweeps"] == c["log2_sweeps"] and s.hash() == c["hash"])
             s.destroy()
         out[name] = {"seconds_per_sample": round(sum(secs) / len(secs), 4), "log2_sweeps": logs,
                      "site_updates_per_s": sites * total / sum(secs)}
+    out["oracle_match"] = "%d/%d" % (matched, checked) if checked else None
     out["workload"] = ("coupling from the past: six-vertex DWBC %dx%d with (a,b,c) = (1,1,1) and the uniform "
                        "Aztec diamond of order %d, seeds 0..%d, doubling from 2 sweeps"
                        % (args.cftp_n, args.cftp_n, args.cftp_aztec, args.cftp_samples - 1))

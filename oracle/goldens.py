@@ -26,6 +26,11 @@ step count in, a tiling out) over the full length of each workload and writes
   served       requests of the served six-vertex stream (2000 requests at
                200/s, lazy Metropolis, 2000 sweeps): the first ten requests of
                every size for each of the two weight sets
+  cftp         exact samples by coupling from the past (Section 1.1.4, the
+               CFTP host function of Section 2.2): the six-vertex domain-wall
+               square N = 128 with (a, b, c) = (1, 1, 1) and the uniform Aztec
+               diamond of order 64, seeds 0 and 1; the coalescence exponent R
+               and the canonical hash of each sample
 
 Usage: python -m oracle.goldens <name> [--jobs J] [--ckpt-dir DIR]
 
@@ -261,8 +266,39 @@ def served(args):
         "cpu_s": round(cpu, 2), "site_updates_per_s_per_core": upd / cpu})
 
 
+CFTP_CASES = [("sixvertex", 128, 0), ("sixvertex", 128, 1), ("domino", 64, 0), ("domino", 64, 1)]
+
+
+def _cftp_case(case):
+    model, n, seed = case
+    if model == "sixvertex":
+        thr = oracle.table_from_ratios(oracle.sixv_ratios(1, 1, 1), False)
+        make = lambda init: oracle.SixVertexOracle(n, thr, seed=seed, init=init)
+    else:
+        thr = oracle.table_from_ratios(oracle.domino_ratios(), False)
+        make = lambda init: oracle.DominoOracle(n, thr, seed=seed, init=init)
+    t0 = time.perf_counter()
+    R, sample = oracle.cftp(make, max_log2=30)
+    el = time.perf_counter() - t0
+    return {"model": model, "n": n, "seed": seed, "log2_sweeps": R, "hash": oracle.canonical_hash(sample),
+            "seconds": round(el, 3)}
+
+
+def cftp(args):
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=args.jobs) as ex:
+        cases = list(ex.map(_cftp_case, CFTP_CASES))
+    wall = time.perf_counter() - t0
+    write("cftp", {
+        "workload": "coupling from the past, uniform weights (every threshold 2^31), heat-bath, rounds "
+                    "doubling from 2 sweeps with the draws of each time step fixed for all rounds: the "
+                    "six-vertex domain-wall square N = 128 and the Aztec diamond of order 64, seeds 0 and 1",
+        "cases": cases, "processes": args.jobs, "wall_s": round(wall, 2),
+        "cpu_s": round(sum(c["seconds"] for c in cases), 2)})
+
+
 JOBS = {"aztec2048": aztec2048, "hexagon1024": hexagon1024, "sixv1024": sixv1024, "sixv1024u": sixv1024u,
-        "batch4096": batch4096, "served": served}
+        "batch4096": batch4096, "served": served, "cftp": cftp}
 
 
 def main():

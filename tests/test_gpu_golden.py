@@ -120,6 +120,23 @@ def test_batch4096_full_call():
     assert not bad, "chains differing from the oracle: %s" % bad
 
 
+def test_cftp_exact_samples_of_the_benchmark():
+    """The benchmark's exact samples by coupling from the past (uniform
+    weights, seeds 0 and 1, at most 2^30 sweeps): the six-vertex N = 128
+    square and the Aztec diamond of order 64 coalesce at the oracle's R and
+    give its sample."""
+    tl = need_gpu()
+    g = golden("cftp")
+    for c in g["cases"]:
+        say("cftp %s n=%d seed %d" % (c["model"], c["n"], c["seed"]))
+        model = tl.TL_SIXVERTEX if c["model"] == "sixvertex" else tl.TL_DOMINO
+        s = tl.Sampler(tl.domain(model, n=c["n"]), tl.weights(tl.TL_W_UNIFORM), c["seed"])
+        info = s.cftp(30)
+        digest = s.hash()
+        s.destroy()
+        assert info["log2_sweeps"] == c["log2_sweeps"] and digest == c["hash"], c
+
+
 def test_served_requests_in_a_budget_bound_mix():
     """The stored requests of the served stream (ten of each size and weight
     set), submitted together to a server whose memory budget, not its slots,
