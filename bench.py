@@ -299,6 +299,10 @@ def run_variants(tl, wl, args):
         out[name] = {"value": sites * wl["sweeps"] * args.steps / el, "unit": "site-updates/s",
                      "ms_per_step": el / args.steps * 1e3, "sites": sites, "hash": digest,
                      "create_s": round(t_make, 3)}
+        # the oracle's stored final tiling of the random-order job
+        g = golden("aztec2048r") if name == "random_order" else None
+        if g and (g["n"], g["seed"], g["sweeps"]) == (wl["n"], wl["seed"], wl["sweeps"]):
+            out[name]["oracle_match"] = digest == g["hash"]
     out["workload"] = ("the plain domino job (%d sweeps, density bins, row hash) with a random colour per step on "
                        "the order-%d Aztec diamond, and with the fixed order on the %dx%d square domain (mask, "
                        "T_min start; create_s includes the host tileability pre-pass)"

@@ -12,6 +12,8 @@ step count in, a tiling out) over the full length of each workload and writes
                bins of 64 x 64 faces sampled every 100 sweeps; the canonical
                hash after 2500, 5000, 7500 and 10^4 sweeps; oracle checkpoints
                (canonical exports) at the intermediate times
+  aztec2048r   the same chain under the random colour choice per step
+               (Section 2.2's RandomWalk draws the colour of every step)
   hexagon1024  lozenge tilings of the 1024^3 hexagon, q^volume with
                q = 1999/2000 (heat-bath), empty-box start, seed 11, 2 x 10^4
                sweeps; volume bins of 64 x 64 vertices every 200 sweeps; hashes
@@ -140,6 +142,24 @@ def aztec2048(args):
                     "all-horizontal brick start, Philox seed 7, 10^4 sweeps, fixed colour order",
         "model": "domino", "n": n, "seed": seed, "sweeps": sweeps, "obs_every": every, "bin": bin_,
         "sites": sites, "thresholds": [int(v) for v in thr],
+        "hash": marks[-1]["hash"], "marks": marks,
+        "samples": int(o.samples[0]), "scalar_sum": int(o.scalar_sum[0]),
+        "bin_sum": [int(v) for v in o.bin_sum],
+        "wall_s": round(wall, 2), "site_updates_per_s": sites * sweeps / wall})
+
+
+def aztec2048r(args):
+    """aztec2048 under the paper's random colour choice per step."""
+    n, seed, sweeps, every, bin_ = 2048, 7, 10000, 100, 64
+    thr = oracle.table_from_ratios(oracle.domino_ratios(), False)
+    o = oracle.DominoOracle(n, thr, seed=seed, obs_every=every, bin_=bin_, random_colours=True)
+    sites = 2 * n * n - 2 * n + 1
+    marks, wall = run_plain("aztec2048r", o, sweeps, (2500, 5000, 7500), "", sites)
+    write("aztec2048r", {
+        "workload": "domino tilings of the order-2048 Aztec diamond, uniform weights (T = 2^31), "
+                    "all-horizontal brick start, Philox seed 7, 10^4 sweeps, random colour per step",
+        "model": "domino", "n": n, "seed": seed, "sweeps": sweeps, "obs_every": every, "bin": bin_,
+        "colour_order": "random", "sites": sites, "thresholds": [int(v) for v in thr],
         "hash": marks[-1]["hash"], "marks": marks,
         "samples": int(o.samples[0]), "scalar_sum": int(o.scalar_sum[0]),
         "bin_sum": [int(v) for v in o.bin_sum],
@@ -297,7 +317,7 @@ def cftp(args):
         "cpu_s": round(sum(c["seconds"] for c in cases), 2)})
 
 
-JOBS = {"aztec2048": aztec2048, "hexagon1024": hexagon1024, "sixv1024": sixv1024, "sixv1024u": sixv1024u,
+JOBS = {"aztec2048": aztec2048, "aztec2048r": aztec2048r, "hexagon1024": hexagon1024, "sixv1024": sixv1024, "sixv1024u": sixv1024u,
         "batch4096": batch4096, "served": served, "cftp": cftp}
 
 

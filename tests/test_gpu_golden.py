@@ -41,9 +41,15 @@ def bench_sampler(tl, workload):
     return bench.make_sampler(tl, bench.WORKLOADS[workload], args), bench.WORKLOADS[workload]
 
 
-def check_plain(tl, name, in_domain):
-    g = golden(name)
+def check_plain(tl, name, in_domain, variant=None):
+    """variant: the stored result of the workload under the random colour
+    order, run with the sampler of the benchmark's variants leg."""
+    g = golden(variant or name)
     s, wl = bench_sampler(tl, name)
+    if variant:
+        s.destroy()
+        s = tl.Sampler(tl.domain(tl.TL_DOMINO, n=wl["n"]), tl.weights(tl.TL_W_UNIFORM), wl["seed"],
+                       tl.options(obs_every=wl["obs_every"], obs_bin=wl["obs_bin"], colour_order=1))
     assert (wl["seed"], wl["sweeps"], wl["obs_every"], wl["obs_bin"]) == (g["seed"], g["sweeps"], g["obs_every"],
                                                                           g["bin"])
     assert s.thresholds() == g["thresholds"]
@@ -79,6 +85,16 @@ def test_aztec2048_full_chain():
     Y, X = np.mgrid[0:2 * n, 0:2 * n]
     inside = np.abs(2 * X - 2 * n + 1) + np.abs(2 * Y - 2 * n + 1) <= 2 * n
     check_plain(tl, "aztec2048", inside)
+
+
+def test_aztec2048_random_order_full_chain():
+    """The same job under the random colour choice per step (the benchmark's
+    random-order variant: register tiles of 8 sweeps per launch)."""
+    tl = need_gpu()
+    n = 2048
+    Y, X = np.mgrid[0:2 * n, 0:2 * n]
+    inside = np.abs(2 * X - 2 * n + 1) + np.abs(2 * Y - 2 * n + 1) <= 2 * n
+    check_plain(tl, "aztec2048", inside, variant="aztec2048r")
 
 
 def test_hexagon1024_full_chain():
