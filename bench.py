@@ -299,9 +299,14 @@ def run_variants(tl, wl, args):
         out[name] = {"value": sites * wl["sweeps"] * args.steps / el, "unit": "site-updates/s",
                      "ms_per_step": el / args.steps * 1e3, "sites": sites, "hash": digest,
                      "create_s": round(t_make, 3)}
-        # the oracle's stored final tiling of the random-order job
-        g = golden("aztec2048r") if name == "random_order" else None
-        if g and (g["n"], g["seed"], g["sweeps"]) == (wl["n"], wl["seed"], wl["sweeps"]):
+        # the oracle's stored final tilings of the two variants
+        if name == "random_order":
+            g = golden("aztec2048r")
+            same = g and (g["n"], g["seed"], g["sweeps"]) == (wl["n"], wl["seed"], wl["sweeps"])
+        else:
+            g = golden("square2048")
+            same = g and (g["side"], g["seed"], g["sweeps"]) == (side, wl["seed"], wl["sweeps"])
+        if same:
             out[name]["oracle_match"] = digest == g["hash"]
     out["workload"] = ("the plain domino job (%d sweeps, density bins, row hash) with a random colour per step on "
                        "the order-%d Aztec diamond, and with the fixed order on the %dx%d square domain (mask, "

@@ -551,7 +551,7 @@ def bin_density(bin_sum, samples, in_domain, bin_):
 
 
 from .region import (DominoRegionOracle, Untileable, check_region, extremal_heights,  # noqa: E402
-                     extremal_tilings, region_embedding, region_heights, tiling_from_heights)
+                     extremal_tilings, region_embedding, region_heights, tiling_from_heights, square_tmin)
 from .sixv_region import (SixVertexRegionOracle, sixv_boundary_heights, sixv_c_vertices,  # noqa: E402
                           sixv_extremal_heights, sixv_free_points, sixv_points)
 from .loz_region import (LozengeRegionOracle, check_loz_region, hexagon_mask, loz_extremal_heights,  # noqa: E402

@@ -14,6 +14,8 @@ step count in, a tiling out) over the full length of each workload and writes
                (canonical exports) at the intermediate times
   aztec2048r   the same chain under the random colour choice per step
                (Section 2.2's RandomWalk draws the colour of every step)
+  square2048   the same chain on the 2048 x 2048 square given as a mask, from
+               its T_min (closed form, checked against the general algorithm)
   hexagon1024  lozenge tilings of the 1024^3 hexagon, q^volume with
                q = 1999/2000 (heat-bath), empty-box start, seed 11, 2 x 10^4
                sweeps; volume bins of 64 x 64 vertices every 200 sweeps; hashes
@@ -160,6 +162,28 @@ def aztec2048r(args):
                     "all-horizontal brick start, Philox seed 7, 10^4 sweeps, random colour per step",
         "model": "domino", "n": n, "seed": seed, "sweeps": sweeps, "obs_every": every, "bin": bin_,
         "colour_order": "random", "sites": sites, "thresholds": [int(v) for v in thr],
+        "hash": marks[-1]["hash"], "marks": marks,
+        "samples": int(o.samples[0]), "scalar_sum": int(o.scalar_sum[0]),
+        "bin_sum": [int(v) for v in o.bin_sum],
+        "wall_s": round(wall, 2), "site_updates_per_s": sites * sweeps / wall})
+
+
+def square2048(args):
+    """The plain domino job on the 2048 x 2048 square given as a mask, from
+    T_min (closed form, oracle.square_tmin), embedded in the Aztec diamond of
+    order 2048."""
+    side, seed, sweeps, every, bin_ = 2048, 7, 10000, 100, 64
+    thr = oracle.table_from_ratios(oracle.domino_ratios(), False)
+    o = oracle.DominoRegionOracle(np.ones((side, side), dtype=bool), thr, seed=seed, obs_every=every, bin_=bin_,
+                                  init=None)
+    o.load(oracle.square_tmin(side))
+    sites = (side - 1) ** 2
+    marks, wall = run_plain("square2048", o, sweeps, (2500, 5000, 7500), "", sites)
+    write("square2048", {
+        "workload": "domino tilings of the 2048 x 2048 square (a mask), uniform weights (T = 2^31), T_min start, "
+                    "embedded in the Aztec diamond of order 2048, Philox seed 7, 10^4 sweeps, fixed colour order",
+        "model": "domino", "side": side, "seed": seed, "sweeps": sweeps, "obs_every": every, "bin": bin_,
+        "sites": sites, "thresholds": [int(v) for v in thr],
         "hash": marks[-1]["hash"], "marks": marks,
         "samples": int(o.samples[0]), "scalar_sum": int(o.scalar_sum[0]),
         "bin_sum": [int(v) for v in o.bin_sum],
@@ -317,7 +341,7 @@ def cftp(args):
         "cpu_s": round(sum(c["seconds"] for c in cases), 2)})
 
 
-JOBS = {"aztec2048": aztec2048, "aztec2048r": aztec2048r, "hexagon1024": hexagon1024, "sixv1024": sixv1024, "sixv1024u": sixv1024u,
+JOBS = {"aztec2048": aztec2048, "aztec2048r": aztec2048r, "square2048": square2048, "hexagon1024": hexagon1024, "sixv1024": sixv1024, "sixv1024u": sixv1024u,
         "batch4096": batch4096, "served": served, "cftp": cftp}
 
 

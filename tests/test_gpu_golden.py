@@ -42,14 +42,21 @@ def bench_sampler(tl, workload):
 
 
 def check_plain(tl, name, in_domain, variant=None):
-    """variant: the stored result of the workload under the random colour
-    order, run with the sampler of the benchmark's variants leg."""
+    """variant: the stored result of a variant of the workload (aztec2048r:
+    the random colour order; square2048: the square domain given as a mask),
+    run with the sampler of the benchmark's variants leg."""
     g = golden(variant or name)
     s, wl = bench_sampler(tl, name)
     if variant:
         s.destroy()
-        s = tl.Sampler(tl.domain(tl.TL_DOMINO, n=wl["n"]), tl.weights(tl.TL_W_UNIFORM), wl["seed"],
-                       tl.options(obs_every=wl["obs_every"], obs_bin=wl["obs_bin"], colour_order=1))
+        if variant == "square2048":
+            dom = tl.domain(tl.TL_DOMINO, mask=np.ones((g["side"], g["side"]), dtype=np.uint8))
+            order = 0
+        else:
+            dom = tl.domain(tl.TL_DOMINO, n=wl["n"])
+            order = 1
+        s = tl.Sampler(dom, tl.weights(tl.TL_W_UNIFORM), wl["seed"],
+                       tl.options(obs_every=wl["obs_every"], obs_bin=wl["obs_bin"], colour_order=order))
     assert (wl["seed"], wl["sweeps"], wl["obs_every"], wl["obs_bin"]) == (g["seed"], g["sweeps"], g["obs_every"],
                                                                           g["bin"])
     assert s.thresholds() == g["thresholds"]
@@ -95,6 +102,13 @@ def test_aztec2048_random_order_full_chain():
     Y, X = np.mgrid[0:2 * n, 0:2 * n]
     inside = np.abs(2 * X - 2 * n + 1) + np.abs(2 * Y - 2 * n + 1) <= 2 * n
     check_plain(tl, "aztec2048", inside, variant="aztec2048r")
+
+
+def test_square2048_domain_full_chain():
+    """The same job on the 2048 x 2048 square given as a mask, from T_min (the
+    benchmark's square-domain variant)."""
+    tl = need_gpu()
+    check_plain(tl, "aztec2048", np.ones((2048, 2048), dtype=bool), variant="square2048")
 
 
 def test_hexagon1024_full_chain():

@@ -219,6 +219,18 @@ def test_rectangles_and_l_shapes_extremes():
         assert check_extremes(m, 0) == len(brute_tilings(m))
 
 
+def test_closed_form_tmin_of_squares():
+    # the closed form used for squares too large for the general algorithm
+    # equals its T_min on every even side up to 16; odd sides are refused
+    for side in range(2, 18, 2):
+        m = np.ones((side, side), dtype=bool)
+        n, ox, oy = oracle.region_embedding(side, side)
+        _, tmin = oracle.extremal_tilings(m, (ox + oy) % 2)
+        assert np.array_equal(oracle.square_tmin(side), tmin), side
+    with pytest.raises(ValueError):
+        oracle.square_tmin(7)
+
+
 @pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6, 9])
 def test_aztec_extremes_are_the_bricks(n):
     d = oracle.DominoOracle(n, [0] * 4)
